@@ -1,0 +1,136 @@
+"""Planted-mistake checks: each plausible slip in the oracle (a dropped term, a
+wrong sign or index, a transposed operand) must make at least one pin fail.
+Mistakes are planted in the oracle on the CPU via monkeypatch."""
+import math
+
+import numpy as np
+import pytest
+from scipy.special import wofz
+
+import oracle as O
+import oracle.xsec as X
+from tests import test_oracle_pins as pins
+
+
+def _patch(monkeypatch, name, fn):
+    monkeypatch.setattr(X, name, fn)
+    monkeypatch.setattr(O, name, fn)
+
+
+def _bad_intensity(variant):
+    def f(E, g, upper, lower, A, T, Q=None, index_base=0):
+        E = np.asarray(E, np.float64); gg = np.asarray(g, np.float64)
+        up = np.asarray(upper, np.int64) - index_base; lo = np.asarray(lower, np.int64) - index_base
+        nu = E[up] - E[lo]
+        if Q is None:
+            Q = X.partition_function(E, g, T)
+        A = np.asarray(A, np.float64)
+        stim = -np.expm1(-O.C2 * nu / T)
+        boltz = np.exp(-O.C2 * E[lo] / T)
+        pref = gg[up] * A / (8.0 * math.pi * O.C_LIGHT_CGS * nu * nu)
+        if variant == "no_stim":
+            stim = 1.0
+        elif variant == "naive_stim":
+            stim = 1.0 - np.exp(-O.C2 * nu / T)
+        elif variant == "upper_boltz":
+            boltz = np.exp(-O.C2 * E[up] / T)
+        elif variant == "lower_g":
+            pref = gg[lo] * A / (8.0 * math.pi * O.C_LIGHT_CGS * nu * nu)
+        elif variant == "no_8pi":
+            pref = gg[up] * A / (O.C_LIGHT_CGS * nu * nu)
+        return pref * boltz * stim / Q
+    return f
+
+
+@pytest.mark.parametrize("variant,pin", [
+    ("no_stim", pins.test_intensity_is_boltzmann_population_difference),
+    ("naive_stim", pins.test_intensity_small_nu_uses_expm1),
+    ("upper_boltz", pins.test_intensity_is_boltzmann_population_difference),
+    ("lower_g", pins.test_intensity_is_boltzmann_population_difference),
+    ("no_8pi", pins.test_intensity_is_boltzmann_population_difference),
+])
+def test_intensity_mistakes_are_caught(monkeypatch, variant, pin):
+    _patch(monkeypatch, "intensities", _bad_intensity(variant))
+    with pytest.raises(AssertionError):
+        pin()
+
+
+def test_doppler_without_ln2_is_caught(monkeypatch):
+    _patch(monkeypatch, "doppler_hwhm",
+           lambda nu, T, m: np.sqrt(2.0 * O.K_BOLTZMANN * T / (m * O.AMU_KG)) * np.asarray(nu) / O.C_LIGHT_SI)
+    with pytest.raises(AssertionError):
+        pins.test_doppler_width_from_maxwell_velocity_variance()
+
+
+def _bad_voigt(variant):
+    def f(delta, alpha_d, gamma):
+        delta = np.asarray(delta, np.float64)
+        s = (math.log(2) if variant == "ln2" else math.sqrt(math.log(2))) / np.asarray(alpha_d)
+        y = np.asarray(gamma) * (1.0 if variant == "unscaled_gamma" else s)
+        return math.sqrt(math.log(2) / math.pi) / np.asarray(alpha_d) * wofz(delta * s + 1j * y).real
+    return f
+
+
+@pytest.mark.parametrize("variant", ["ln2", "unscaled_gamma"])
+def test_voigt_mistakes_are_caught(monkeypatch, variant):
+    _patch(monkeypatch, "voigt_profile", _bad_voigt(variant))
+    with pytest.raises(AssertionError):
+        pins.test_voigt_equals_brute_force_convolution(0.01, 0.05, 0.3)
+
+
+def test_exclusive_window_is_caught(monkeypatch):
+    def bad(nu, nu_a, dnu, n_points, cutoff):
+        nu = np.asarray(nu, np.float64)
+        klo = np.floor((nu - cutoff - nu_a) / dnu) + 1
+        khi = np.ceil((nu + cutoff - nu_a) / dnu) - 1
+        return np.maximum(klo, 0).astype(np.int64), np.minimum(khi, n_points - 1).astype(np.int64)
+    _patch(monkeypatch, "window", bad)
+    with pytest.raises(AssertionError):
+        pins.test_window_is_inclusive_and_clipped()
+
+
+def test_reversed_centre_is_caught(monkeypatch, golden_dir):
+    _patch(monkeypatch, "line_centres",
+           lambda E, upper, lower, index_base=0: np.asarray(E)[np.asarray(lower)] - np.asarray(E)[np.asarray(upper)])
+    with pytest.raises(AssertionError):
+        pins.test_transition_wavenumber_is_upper_minus_lower(golden_dir)
+
+
+def test_partition_without_degeneracy_is_caught(monkeypatch):
+    _patch(monkeypatch, "partition_function",
+           lambda E, g, T: math.fsum(np.exp(-O.C2 * np.asarray(E, np.float64) / T)))
+    with pytest.raises(AssertionError):
+        pins.test_partition_single_and_two_level()
+
+
+def test_gh_without_node_shift_is_caught(monkeypatch):
+    def bad(delta, alpha_d, gamma, dnu, n_gh=30):
+        t, w = np.polynomial.hermite.hermgauss(n_gh)
+        delta = np.asarray(delta, np.float64)
+        out = 0.0
+        for tj, wj in zip(t, w):
+            out = out + wj * (np.arctan((delta + dnu / 2) / gamma) - np.arctan((delta - dnu / 2) / gamma))
+        return out / (math.pi ** 1.5 * dnu)
+    _patch(monkeypatch, "gh_binned_profile", bad)
+    with pytest.raises(AssertionError):
+        pins.test_gh_binned_area_telescopes()
+
+
+def test_inverted_temperature_exponent_is_caught(monkeypatch, golden_dir):
+    _patch(monkeypatch, "lorentz_hwhm",
+           lambda gref, n, T, P, T0=296.0, P0=1.0: np.asarray(gref) * (T / T0) ** np.asarray(n) * (P / P0))
+    with pytest.raises(AssertionError):
+        pins.test_a0_table_selects_by_lower_J(golden_dir)
+
+
+def test_wrong_adjoint_sign_is_caught(monkeypatch):
+    real = X.voigt_adjoint
+
+    def bad(*a, **k):
+        r = real(*a, **k)
+        r["dT"] = -r["dT"]
+        return r
+    _patch(monkeypatch, "voigt_adjoint", bad)
+    from tests import test_oracle_adjoint as adj
+    with pytest.raises(AssertionError):
+        adj.test_adjoint_matches_central_differences(1500.0, 0.1)
