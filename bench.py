@@ -1,0 +1,221 @@
+"""Benchmark: Voigt line-profiles/s at a 25 cm^-1 cut-off on one MI355X.
+
+Workload (default): 1e8 synthetic transitions among 1e6 states (34 Da), T = 296 K and
+2000 K at P = 1 bar, Voigt profile sampled on 0-10000 cm^-1 at 0.01 cm^-1
+(1,000,001 points), FP32 profile arithmetic with FP64 line setup.
+
+One step = the whole hot path on device-resident inputs: line preparation and sort
+(xs_set_lines), Q(T) on the device, and both cross sections from one batched call.
+The plain FP64 path is timed on the same workload for comparison, and the CPU oracle
+is timed on a bounded sample of the same list (before the GPU is touched).
+
+Prints one JSON line (rank 0, N = 1 only).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FLOPS_PER_EVAL = 12          # far-wing rational: j add, 4 fma, rcp, accumulate fma (FMA = 2)
+PEAK_FP32_TFLOPS = 157.3     # MI355X FP32 vector peak (published, packed)
+PEAK_FP32_UNPACKED = 78.6    # 256 CU x 64 lanes x 2 flop x 2.4 GHz without packed FP32
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline(cfg, n_sample_lines, temps, pressures):
+    """Time the FP64 oracle (as it stands) on the first n_sample_lines lines."""
+    import numpy as np
+    import oracle as O
+    import synth
+    d = synth.make_linelist(cfg, n_lines=n_sample_lines, device="cpu")
+    h = {k: v.numpy() for k, v in d.items()}
+    cores = len(os.sched_getaffinity(0))
+    t0 = time.perf_counter()
+    profiles = 0
+    for T, P in zip(temps, pressures):
+        ls = O.make_lineset(h["E"], h["g"], h["upper"], h["lower"], h["A"], T, P, cfg.mass_amu,
+                            gamma_ref=h["gamma_ref"], n_exp=h["n_exp"])
+        O.cross_section(ls, cfg.nu_a, cfg.nu_b, cfg.n_points, cfg.cutoff, workers=cores)
+        klo, khi = O.window(ls.nu, cfg.nu_a, cfg.dnu, cfg.n_points, cfg.cutoff)
+        profiles += int(np.count_nonzero(khi >= klo))
+    dt = time.perf_counter() - t0
+    cpu = "unknown"
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                cpu = ln.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return dict(value=profiles / dt, unit="line-profiles/s", cores=cores, kind="oracle",
+                sample=f"first {n_sample_lines} lines of the same list x {len(temps)} (T,P), full grid; "
+                       f"{dt:.1f} s wall on {cores} processes ({cpu})")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="C2")
+    ap.add_argument("--lines", type=int, default=0, help="truncate the line list (profiling runs)")
+    ap.add_argument("--slices-per-wave", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--cpu-lines-per-core", type=int, default=20000)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import synth
+    cfg = synth.CONFIGS[args.workload]
+    n_lines = args.lines or cfg.n_lines
+    temps, pressures = list(cfg.temperatures), list(cfg.pressures) * (len(cfg.temperatures) // len(cfg.pressures) or 1)
+    if len(pressures) != len(temps):
+        pressures = [cfg.pressures[0]] * len(temps)
+
+    base = None
+    if not args.no_cpu_baseline:
+        cores = len(os.sched_getaffinity(0))
+        n_s = min(n_lines, args.cpu_lines_per_core * cores)
+        log(f"cpu baseline: oracle on {n_s} lines, {cores} processes")
+        base = cpu_baseline(cfg, n_s, temps, pressures)
+        log(f"cpu baseline: {base['value']:.3e} line-profiles/s")
+
+    import torch
+    from paper_1801_09803_amd import Plan
+
+    dev = torch.device("cuda:0")
+    log(f"generating {n_lines} lines / {cfg.n_states} states on {torch.cuda.get_device_name(0)}")
+    d = synth.make_linelist(cfg, n_lines=n_lines, device=dev)
+    torch.cuda.synchronize()
+
+    # algorithmic units: grid points inside every kept line's window (same for each (T,P))
+    E = d["E"]
+    nu = E[d["upper"].long()] - E[d["lower"].long()]
+    klo = torch.clamp(torch.ceil(((nu - cfg.cutoff) - cfg.nu_a) / cfg.dnu), min=0)
+    khi = torch.clamp(torch.floor(((nu + cfg.cutoff) - cfg.nu_a) / cfg.dnu), max=cfg.n_points - 1)
+    evals_per_tp = int(torch.clamp(khi - klo + 1, min=0).sum().item())
+    del nu, klo, khi
+
+    def make(precision):
+        return Plan(cfg.nu_a, cfg.nu_b, cfg.n_points, cfg.mass_amu, cutoff=cfg.cutoff,
+                    profile="voigt", precision=precision, slices_per_wave=args.slices_per_wave)
+
+    plan = make("fp32")
+    plan.set_states(d["E"], d["g"], d["J"])
+    stream = torch.cuda.current_stream()
+    out = torch.empty((len(temps), cfg.n_points), dtype=torch.float32, device=dev)
+
+    def step():
+        plan.set_lines(d["upper"], d["lower"], d["A"], d["gamma_ref"], d["n_exp"])
+        ev0.record(stream)
+        plan.cross_section(temps, pressures, out=out)
+        ev1.record(stream)
+
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for i in range(args.warmup):
+        log(f"warmup step {i}")
+        step()
+    torch.cuda.synchronize()
+    kern_ms = []
+    log(f"timing {args.steps} steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step()
+        torch.cuda.synchronize()
+        kern_ms.append(ev0.elapsed_time(ev1))
+        log(f"step {i}: forward {kern_ms[-1]:.1f} ms")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    n_kept = plan.lines_kept()
+    n_tp = len(temps)
+    value = n_kept * n_tp * args.steps / elapsed
+    ms_step = 1e3 * elapsed / args.steps
+    avg_launch_s = (sum(kern_ms) / len(kern_ms)) / 1e3 / n_tp
+    achieved = FLOPS_PER_EVAL * evals_per_tp / avg_launch_s / 1e12
+
+    result = {
+        "metric": "Voigt line-profiles/s at 25 cm^-1 cutoff",
+        "value": value,
+        "unit": "line-profiles/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{cfg.name}: {n_lines} transitions, {cfg.n_states} states, {cfg.mass_amu} Da, "
+                        f"T={temps} K, P={pressures} bar, Voigt, {cfg.nu_a}-{cfg.nu_b} cm^-1 "
+                        f"({cfg.n_points} points, dnu={cfg.dnu}), cutoff {cfg.cutoff}",
+            "lines_kept": n_kept,
+            "n_tp": n_tp,
+            "point_evaluations_per_tp": evals_per_tp,
+            "precision": "fp32 profiles, fp64 line setup, compensated fp32 sums",
+            "step": "xs_set_lines (prep + sort) + Q(T) + batched forward",
+        },
+        "roofline": {
+            "bound": "alu",
+            "achieved": achieved,
+            "peak": PEAK_FP32_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP32_TFLOPS,
+            "traffic": None,
+            "kernel": "fwd_f32_kernel<Voigt>",
+            "avg_launch_ms": avg_launch_s * 1e3,
+            "flops_per_eval": FLOPS_PER_EVAL,
+            "frac_of_unpacked_fp32": achieved / PEAK_FP32_UNPACKED,
+        },
+        "forward_line_profiles_per_s": n_kept / avg_launch_s,
+        "point_evaluations_per_s": evals_per_tp / avg_launch_s,
+        "cpu_baseline": base,
+    }
+
+    if not args.no_fp64:
+        plan64 = make("fp64")
+        plan64.set_states(d["E"], d["g"], d["J"])
+        plan64.set_lines(d["upper"], d["lower"], d["A"], d["gamma_ref"], d["n_exp"])
+        out64 = torch.empty((1, cfg.n_points), dtype=torch.float64, device=dev)
+        torch.cuda.synchronize()
+        log("timing the plain FP64 path (one call per (T,P))")
+        ev2, ev3 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev2.record(stream)
+        for T, P in zip(temps, pressures):
+            plan64.cross_section([T], [P], out=out64)
+        ev3.record(stream)
+        torch.cuda.synchronize()
+        t64 = ev2.elapsed_time(ev3) / 1e3
+        result["fp64_plain_forward_line_profiles_per_s"] = n_kept * n_tp / t64
+        result["fp32_vs_fp64_forward_speedup"] = t64 / (avg_launch_s * n_tp)
+        # agreement of the two paths on the last (T, P)
+        ref = out64[0]
+        got = out[-1].double()
+        mask = ref > 1e-6 * ref.max()
+        result["fp32_vs_fp64_max_rel"] = float(((got - ref).abs()[mask] / ref[mask]).max().item())
+        result["fp32_vs_fp64_area_rel"] = float(abs(got.sum().item() - ref.sum().item()) / ref.sum().item())
+        del plan64, out64
+
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

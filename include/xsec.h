@@ -1,0 +1,166 @@
+/*
+ * xsec.h -- C ABI of the MI355X line-by-line cross-section library (libxsec.so).
+ *
+ * The library computes molecular absorption cross sections sigma(nu) from a line
+ * list, following the ExoCross paper (Yurchenko, Al-Refaie & Tennyson,
+ * arXiv:1801.09803):
+ *   - line intensity I (cm/molecule), Sec. "Intensities and partition function", Eq. 1,
+ *     with the partition function Q(T) summed over the states, Eq. 2;
+ *   - Doppler / Gaussian / Lorentzian / Voigt line profiles, Sec. "Line profiles",
+ *     Eq. 15-19, sampled on the grid (the "sampling method");
+ *   - sigma(nu_k) = sum over lines of I f(nu_k - nu_fi), Sec. "Cross sections", Eq. 6-8;
+ *   - an equidistant grid of N points including both ends, Eq. 9;
+ *   - line wings truncated at a cut-off (25 cm^-1 by default), Sec. "Off-set".
+ *
+ * Conventions
+ *   Units: wavenumbers and energies in cm^-1, T in K, P in the unit of P0 (bar by
+ *   default), gamma_ref in cm^-1 per P0, mass in Da, A in s^-1, sigma in
+ *   cm^2/molecule (the paper's table of units).
+ *   Transitions follow the ExoMol two-file format: upper and lower state indices
+ *   into the states arrays (index_base 0, or 1 for ExoMol running numbers).
+ *   nu = E[upper] - E[lower] must be > 0.
+ *
+ * Memory and streams
+ *   Arrays documented as "device" are device pointers owned by the caller; the
+ *   library never frees them and does not keep them past the call (it copies what
+ *   it needs into plan-owned workspace).  "host" arrays are read during the call.
+ *   `stream` is a hipStream_t passed as void* (NULL = the default stream).  Every
+ *   call enqueues its work on that stream and returns without waiting, except where
+ *   a call is documented as synchronous.
+ *
+ * Errors
+ *   Every call returns an xs_status; no exception crosses the ABI.  On failure
+ *   xs_last_error() returns a thread-local message describing the first problem.
+ *   A failed call leaves the plan usable (its previous line set stays valid unless
+ *   the failing call was xs_set_lines, which then leaves no line set).
+ *
+ * Thread safety: one plan must not be used from two host threads at once.
+ */
+#ifndef XSEC_H
+#define XSEC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define XS_ABI_VERSION 1
+
+typedef struct xs_plan xs_plan;
+
+typedef enum {
+    XS_OK = 0,
+    XS_ERR_ARG = 1,          /* invalid argument (sizes, ranges, null pointers)          */
+    XS_ERR_INDEX = 2,        /* a transition's state index is outside the states array  */
+    XS_ERR_NU_NONPOS = 3,    /* a transition has E[upper] - E[lower] <= 0               */
+    XS_ERR_HIP = 4,          /* the HIP runtime reported an error                        */
+    XS_ERR_OOM = 5,          /* device allocation failed                                 */
+    XS_ERR_STATE = 6,        /* call out of order (e.g. no states or lines set)          */
+    XS_ERR_UNSUPPORTED = 7   /* option combination not implemented                       */
+} xs_status;
+
+typedef enum {
+    XS_DOPPLER = 0,      /* Gaussian with the Doppler HWHM of Eq. 16                      */
+    XS_GAUSS_FIXED = 1,  /* Gaussian with a constant HWHM alpha_fixed (Eq. 15)            */
+    XS_LORENTZ = 2,      /* Lorentzian with HWHM gamma_L of Eq. 18 (Eq. 17)               */
+    XS_VOIGT = 3         /* Voigt: Doppler (x) Lorentz (Eq. 19, normalised convolution)   */
+} xs_profile;
+
+typedef enum {
+    XS_FP64 = 0,         /* profiles and sums in double precision                         */
+    XS_FP32 = 1          /* profiles in single precision with double-precision line
+                            setup (intensity exponents, Q(T), centre-to-grid offsets) and
+                            compensated single-precision accumulation; sigma is float    */
+} xs_precision;
+
+typedef enum {
+    XS_BROAD_CONST = 0,      /* gamma_const, n_const for every line                        */
+    XS_BROAD_PER_LINE = 1,   /* gamma_ref[i], n_exp[i] given per transition                */
+    XS_BROAD_A0_JLOWER = 2   /* ExoMol "a0" scheme: table indexed by the lower state's J   */
+} xs_broadening;
+
+typedef struct {
+    double nu_a, nu_b;     /* grid bounds, both included (Eq. 9), nu_b > nu_a              */
+    int64_t n_points;      /* grid points N >= 2; dnu = (nu_b - nu_a)/(N - 1)              */
+    double cutoff;         /* wing cut-off (cm^-1) > 0; window |nu_k - nu| <= cutoff       */
+    double mass_da;        /* molecular mass (Da) > 0, for Eq. 16                          */
+    double T0, P0;         /* reference temperature / pressure of gamma_ref (Eq. 18)      */
+    int32_t profile;       /* xs_profile                                                   */
+    int32_t precision;     /* xs_precision                                                 */
+    int32_t broadening;    /* xs_broadening                                                */
+    int32_t index_base;    /* 0, or 1 for ExoMol running numbers                           */
+    double alpha_fixed;    /* HWHM for XS_GAUSS_FIXED                                      */
+    double gamma_const;    /* gamma_ref for XS_BROAD_CONST                                 */
+    double n_const;        /* temperature exponent for XS_BROAD_CONST                      */
+    int32_t slices_per_wave; /* tile shape: 64-point slices per wavefront (1, 2 or 4);
+                                0 = library default                                      */
+    int32_t reserved[7];
+} xs_opts;
+
+/* Fill *opts with defaults: cutoff 25, T0 296 K, P0 1 bar, Voigt, FP32, per-line
+ * broadening, index_base 0.  Grid and mass must still be set.  */
+xs_status xs_opts_default(xs_opts* opts);
+
+/* Create a plan for a grid and profile.  *out receives the plan (owned by the
+ * caller until xs_plan_destroy).  Validates the options (XS_ERR_ARG). */
+xs_status xs_plan_create(const xs_opts* opts, xs_plan** out);
+
+/* Free the plan and all of its device workspace.  NULL is accepted. */
+xs_status xs_plan_destroy(xs_plan* plan);
+
+/* States (Eq. 2; the .states file's energy, total degeneracy and J columns).
+ * E: device double[n_states] (cm^-1); g: device int32[n_states] (g_tot > 0);
+ * J: device int32[n_states] or NULL (needed only for XS_BROAD_A0_JLOWER).
+ * The arrays are copied into the plan on `stream`.  Replaces any previous states
+ * and invalidates the line set. */
+xs_status xs_set_states(xs_plan* plan, int64_t n_states, const double* E, const int32_t* g,
+                        const int32_t* J, void* stream);
+
+/* a0 broadening table (Sec. "Broadening parameters"): host float arrays indexed by
+ * the lower state's J = 0..n_j-1; lower states with J >= n_j use the last row. */
+xs_status xs_set_broadening_table(xs_plan* plan, int32_t n_j, const float* gamma_ref,
+                                  const float* n_exp);
+
+/* Transitions (the .trans file: upper index, lower index, Einstein A).
+ * upper, lower: device int32[n_lines]; A: device float[n_lines] (s^-1);
+ * gamma_ref, n_exp: device float[n_lines] for XS_BROAD_PER_LINE, else NULL.
+ * Computes per-line wavenumbers nu = E[upper] - E[lower] and line constants,
+ * drops lines whose cut-off window misses the grid, and sorts the rest by centre
+ * into the plan's workspace (original indices are kept for gradients).
+ * SYNCHRONOUS: waits for `stream` to check indices and wavenumbers; returns
+ * XS_ERR_INDEX or XS_ERR_NU_NONPOS for invalid transitions (no line set then). */
+xs_status xs_set_lines(xs_plan* plan, int64_t n_lines, const int32_t* upper, const int32_t* lower,
+                       const float* A, const float* gamma_ref, const float* n_exp, void* stream);
+
+/* Number of lines kept by the last xs_set_lines (window overlaps the grid). */
+xs_status xs_lines_kept(const xs_plan* plan, int64_t* n_kept);
+
+/* Partition function Q(T) of Eq. 2 and its derivative dQ/dT, summed on the device
+ * in double precision, for n_T temperatures.  T: host double[n_T] (> 0);
+ * Q, dQdT: device double[n_T] or NULL. */
+xs_status xs_partition_function(xs_plan* plan, int32_t n_T, const double* T, double* Q,
+                                double* dQdT, void* stream);
+
+/* Cross sections for n_tp (T, P) pairs (Eq. 6-8 with the sampling method).
+ * T, P: host double[n_tp] (T > 0, P >= 0; P = 0 gives the pure Doppler limit).
+ * sigma: device array [n_tp][n_points], nu fastest; float for XS_FP32, double for
+ * XS_FP64.  The result overwrites sigma. */
+xs_status xs_cross_section(xs_plan* plan, int32_t n_tp, const double* T, const double* P,
+                           void* sigma, void* stream);
+
+/* Bytes of device memory the plan currently holds. */
+size_t xs_workspace_bytes(const xs_plan* plan);
+
+/* Thread-local description of the last error ("" if none). */
+const char* xs_last_error(void);
+
+/* XS_ABI_VERSION of the built library. */
+int xs_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* XSEC_H */

@@ -1,0 +1,212 @@
+"""ctypes binding of libxsec.so: argument marshalling only.
+
+Tensors passed in must already live on the GPU (torch is used for device memory
+and streams); every computation happens in the library's HIP kernels.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_NAME = "libxsec.so"
+
+PROFILES = {"doppler": 0, "gauss_fixed": 1, "lorentz": 2, "voigt": 3}
+PRECISIONS = {"fp64": 0, "fp32": 1}
+BROADENING = {"const": 0, "per_line": 1, "a0_jlower": 2}
+STATUS = {0: "XS_OK", 1: "XS_ERR_ARG", 2: "XS_ERR_INDEX", 3: "XS_ERR_NU_NONPOS", 4: "XS_ERR_HIP",
+          5: "XS_ERR_OOM", 6: "XS_ERR_STATE", 7: "XS_ERR_UNSUPPORTED"}
+
+
+class XsecError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+        self.name = STATUS.get(status, str(status))
+
+
+class XsOpts(ctypes.Structure):
+    _fields_ = [
+        ("nu_a", ctypes.c_double), ("nu_b", ctypes.c_double), ("n_points", ctypes.c_int64),
+        ("cutoff", ctypes.c_double), ("mass_da", ctypes.c_double), ("T0", ctypes.c_double),
+        ("P0", ctypes.c_double), ("profile", ctypes.c_int32), ("precision", ctypes.c_int32),
+        ("broadening", ctypes.c_int32), ("index_base", ctypes.c_int32),
+        ("alpha_fixed", ctypes.c_double), ("gamma_const", ctypes.c_double), ("n_const", ctypes.c_double),
+        ("slices_per_wave", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7),
+    ]
+
+
+_lib = None
+
+
+def lib_path() -> str:
+    return os.path.join(HERE, _LIB_NAME)
+
+
+def load_library() -> ctypes.CDLL:
+    """Load the in-tree libxsec.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = lib_path()
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_1801_09803_amd.build`")
+    lib = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    i32, i64, dbl = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    sig = {
+        "xs_opts_default": (i32, [ctypes.POINTER(XsOpts)]),
+        "xs_plan_create": (i32, [ctypes.POINTER(XsOpts), ctypes.POINTER(P)]),
+        "xs_plan_destroy": (i32, [P]),
+        "xs_set_states": (i32, [P, i64, P, P, P, P]),
+        "xs_set_broadening_table": (i32, [P, i32, P, P]),
+        "xs_set_lines": (i32, [P, i64, P, P, P, P, P, P]),
+        "xs_lines_kept": (i32, [P, ctypes.POINTER(i64)]),
+        "xs_partition_function": (i32, [P, i32, P, P, P, P]),
+        "xs_cross_section": (i32, [P, i32, P, P, P, P]),
+        "xs_workspace_bytes": (ctypes.c_size_t, [P]),
+        "xs_last_error": (ctypes.c_char_p, []),
+        "xs_version": (ctypes.c_int, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def abi_version() -> int:
+    return int(load_library().xs_version())
+
+
+def _check(status: int):
+    if status != 0:
+        msg = load_library().xs_last_error()
+        raise XsecError(status, msg.decode() if msg else "")
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def _host_doubles(vals: Sequence[float]):
+    arr = (ctypes.c_double * len(vals))(*[float(v) for v in vals])
+    return arr
+
+
+class Plan:
+    """One grid + profile configuration; owns the library plan and its workspace."""
+
+    def __init__(self, nu_a: float, nu_b: float, n_points: int, mass_da: float, *,
+                 cutoff: float = 25.0, profile: str = "voigt", precision: str = "fp32",
+                 broadening: str = "per_line", T0: float = 296.0, P0: float = 1.0,
+                 index_base: int = 0, alpha_fixed: float = 0.0, gamma_const: float = 0.0,
+                 n_const: float = 0.0, slices_per_wave: int = 0):
+        import torch
+        self._torch = torch
+        lib = load_library()
+        o = XsOpts()
+        _check(lib.xs_opts_default(ctypes.byref(o)))
+        o.nu_a, o.nu_b, o.n_points = float(nu_a), float(nu_b), int(n_points)
+        o.cutoff, o.mass_da, o.T0, o.P0 = float(cutoff), float(mass_da), float(T0), float(P0)
+        o.profile = PROFILES[profile]
+        o.precision = PRECISIONS[precision]
+        o.broadening = BROADENING[broadening]
+        o.index_base = int(index_base)
+        o.alpha_fixed, o.gamma_const, o.n_const = float(alpha_fixed), float(gamma_const), float(n_const)
+        o.slices_per_wave = int(slices_per_wave)
+        h = ctypes.c_void_p()
+        _check(lib.xs_plan_create(ctypes.byref(o), ctypes.byref(h)))
+        self._lib = lib
+        self._h = h
+        self.opts = o
+        self.n_points = int(n_points)
+        self.precision = precision
+        self.dtype = torch.float32 if precision == "fp32" else torch.float64
+
+    # -- helpers
+    def _stream(self):
+        return ctypes.c_void_p(self._torch.cuda.current_stream().cuda_stream)
+
+    def _dev(self, t, dtype, name):
+        if t is None:
+            return None
+        if not t.is_cuda:
+            raise ValueError(f"{name} must be a CUDA tensor")
+        if t.dtype != dtype:
+            raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+        return t
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.xs_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- ABI calls
+    def set_states(self, E, g, J=None):
+        torch = self._torch
+        E = self._dev(E, torch.float64, "E")
+        g = self._dev(g, torch.int32, "g")
+        J = self._dev(J, torch.int32, "J")
+        self._states = (E, g, J)
+        _check(self._lib.xs_set_states(self._h, E.numel(), _ptr(E), _ptr(g), _ptr(J), self._stream()))
+
+    def set_broadening_table(self, gamma_ref, n_exp):
+        import numpy as np
+        gr = np.ascontiguousarray(np.asarray(gamma_ref, dtype=np.float32))
+        ne = np.ascontiguousarray(np.asarray(n_exp, dtype=np.float32))
+        if gr.shape != ne.shape:
+            raise ValueError("table arrays differ in length")
+        _check(self._lib.xs_set_broadening_table(self._h, gr.size, gr.ctypes.data, ne.ctypes.data))
+
+    def set_lines(self, upper, lower, A, gamma_ref=None, n_exp=None):
+        torch = self._torch
+        upper = self._dev(upper, torch.int32, "upper")
+        lower = self._dev(lower, torch.int32, "lower")
+        A = self._dev(A, torch.float32, "A")
+        gamma_ref = self._dev(gamma_ref, torch.float32, "gamma_ref")
+        n_exp = self._dev(n_exp, torch.float32, "n_exp")
+        _check(self._lib.xs_set_lines(self._h, upper.numel(), _ptr(upper), _ptr(lower), _ptr(A),
+                                      _ptr(gamma_ref), _ptr(n_exp), self._stream()))
+
+    def lines_kept(self) -> int:
+        n = ctypes.c_int64()
+        _check(self._lib.xs_lines_kept(self._h, ctypes.byref(n)))
+        return int(n.value)
+
+    def partition_function(self, T: Sequence[float]):
+        torch = self._torch
+        T = list(T)
+        Q = torch.empty(len(T), dtype=torch.float64, device="cuda")
+        dQ = torch.empty(len(T), dtype=torch.float64, device="cuda")
+        _check(self._lib.xs_partition_function(self._h, len(T), _host_doubles(T), _ptr(Q), _ptr(dQ),
+                                               self._stream()))
+        return Q, dQ
+
+    def cross_section(self, T: Sequence[float], P: Sequence[float], out=None):
+        torch = self._torch
+        T, P = list(T), list(P)
+        if len(T) != len(P):
+            raise ValueError("T and P differ in length")
+        if out is None:
+            out = torch.empty((len(T), self.n_points), dtype=self.dtype, device="cuda")
+        else:
+            out = self._dev(out, self.dtype, "out")
+            if out.numel() != len(T) * self.n_points:
+                raise ValueError("out has the wrong size")
+        _check(self._lib.xs_cross_section(self._h, len(T), _host_doubles(T), _host_doubles(P), _ptr(out),
+                                          self._stream()))
+        return out
+
+    def workspace_bytes(self) -> int:
+        return int(self._lib.xs_workspace_bytes(self._h))

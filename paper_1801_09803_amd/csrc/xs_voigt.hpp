@@ -1,0 +1,99 @@
+// Device evaluation of Re w(z), w the Faddeeva function, for the Voigt profile
+//   f_V(D) = sqrt(ln2/pi)/alpha_D * Re w(x + i y),  x = sqrt(ln2) D/alpha_D,
+//   y = sqrt(ln2) gamma/alpha_D
+// (the normalised Doppler (x) Lorentz convolution the paper's Voigt equation
+// describes, Sec. "Line profiles").
+//
+// The plane is split by |z| (y is fixed per line, so the choice is per line and
+// per 64-point slice, never per lane):
+//  * wings: n-point Gauss-Hermite quadrature of the convolution,
+//        Re w(z) ~ (y/pi) sum_j w_j / ((x - t_j)^2 + y^2),
+//    summed over node pairs +-t_j as 2 w_j q_j / d_j with
+//        p_j = x^2 + y^2 - t_j^2,  d_j = p_j^2 + 4 t_j^2 y^2,  q_j = p_j + 2 t_j^2.
+//    (n = 2 is the single rational term of Humlicek's far region.)  The error falls
+//    like |z|^-(2n); the zone radii keep it below the precision's target.
+//  * core |z| < 8: Weideman's rational approximation (SIAM J. Numer. Anal. 1994) for
+//    y >= 0.2; for y < 0.2 a Taylor series in i*y about the real axis,
+//        w(x + iy) = sum_k w^(k)(x) (iy)^k / k!,
+//        w' = -2 z w + 2i/sqrt(pi),  w^(k+1) = -2 x w^(k) - 2k w^(k-1),
+//    started from w(x) = exp(-x^2) + i Im w(x) (Weideman on the real axis), which
+//    keeps relative accuracy in Re w where it is much smaller than |w|.
+#pragma once
+
+#include "xs_internal.hpp"
+
+namespace xs {
+
+struct cplx { double re, im; };
+
+__device__ __forceinline__ double rcp64(double d) {
+    double r = __builtin_amdgcn_rcp(d);
+    double e = __builtin_fma(-d, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    e = __builtin_fma(-d, r, 1.0);
+    return __builtin_fma(r, e, r);
+}
+
+// w(z) ~ 2 p(Z)/(L - iz)^2 + (1/sqrt(pi))/(L - iz),  Z = (L + iz)/(L - iz).
+template <int N>
+__device__ __forceinline__ cplx weideman_w(double x, double y, const WeidemanCoef& W) {
+    const double L = W.L;
+    const double dr = L + y, di = -x;      // L - iz
+    const double nr = L - y, ni = x;       // L + iz
+    const double inv = 1.0 / (dr * dr + di * di);
+    const double zr = (nr * dr + ni * di) * inv;
+    const double zi = (ni * dr - nr * di) * inv;
+    double pr = W.a[N - 1], pi = 0.0;
+#pragma unroll
+    for (int k = N - 2; k >= 0; --k) {
+        const double t = __builtin_fma(pr, zr, __builtin_fma(-pi, zi, W.a[k]));
+        pi = __builtin_fma(pr, zi, pi * zr);
+        pr = t;
+    }
+    const double ir = dr * inv, ii = -di * inv;            // 1/(L - iz)
+    const double i2r = ir * ir - ii * ii, i2i = 2.0 * ir * ii;
+    cplx w;
+    w.re = 2.0 * (pr * i2r - pi * i2i) + kINV_SQRT_PI * ir;
+    w.im = 2.0 * (pr * i2i + pi * i2r) + kINV_SQRT_PI * ii;
+    return w;
+}
+
+// Re w(x + iy) for |z| < 8 with relative accuracy (N Weideman terms, K Taylor terms).
+template <int N, int K>
+__device__ __forceinline__ double voigt_core_re(double x, double y, const WeidemanCoef& W) {
+    if (y >= 0.2) return weideman_w<N>(x, y, W).re;
+    // w^(0), w^(1) on the real axis
+    double w0r = exp(-x * x);
+    double w0i = weideman_w<N>(x, 0.0, W).im;
+    double w1r = -2.0 * x * w0r;
+    double w1i = -2.0 * x * w0i + 2.0 * kINV_SQRT_PI;
+    double sum = w0r - w1i * y;            // k = 0, 1:  Re(w0) + Re(i y w1)
+    double fac = y;                        // y^k / k!
+#pragma unroll
+    for (int k = 1; k < K; ++k) {
+        const double w2r = -2.0 * x * w1r - 2.0 * k * w0r;
+        const double w2i = -2.0 * x * w1i - 2.0 * k * w0i;
+        fac *= y / (k + 1);
+        // Re(w^(k+1) i^(k+1)):  (k+1) mod 4 = 0: re, 1: -im, 2: -re, 3: im
+        const int m = (k + 1) & 3;
+        const double term = (m == 0) ? w2r : (m == 1) ? -w2i : (m == 2) ? -w2r : w2i;
+        sum = __builtin_fma(term, fac, sum);
+        w0r = w1r; w0i = w1i; w1r = w2r; w1i = w2i;
+    }
+    return sum;
+}
+
+// Re w from the n-point Gauss-Hermite rule (pairs + optional zero node), double.
+__device__ __forceinline__ double gh_wing_re(double u, double y, const GHPairs& G) {
+    const double y2 = y * y;
+    double acc = G.has_zero ? G.w0 * rcp64(u + y2) : 0.0;
+    for (int j = 0; j < G.n_pairs; ++j) {
+        const double t2 = G.t[j] * G.t[j];
+        const double p = u + y2 - t2;
+        const double d = __builtin_fma(p, p, 4.0 * t2 * y2);
+        acc = __builtin_fma(2.0 * G.w[j] * (p + 2.0 * t2), rcp64(d), acc);
+    }
+    return acc * y * (1.0 / kPI);
+}
+
+}  // namespace xs

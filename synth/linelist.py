@@ -139,11 +139,11 @@ def make_states(n_states: int, seed: int, device="cpu"):
 
 
 def make_transitions(E: torch.Tensor, n_lines: int, nu_max: float, seed: int,
-                     first_line: int = 0, max_attempts: int = 64):
+                     first_line: int = 0, max_attempts: int = 1024):
     """Upper/lower state indices (0-based int32) for lines first_line..first_line+n_lines-1.
 
-    Attempt r of line i draws two state indices from counters 2*(64*i + r) and
-    2*(64*i + r) + 1; the first accepted attempt wins.
+    Attempt r of line i draws two state indices from counters 2*(1024*i + r) and
+    2*(1024*i + r) + 1; the first accepted attempt wins.
     """
     device = E.device
     n_states = E.numel()

@@ -1,0 +1,66 @@
+"""The C-ABI library loads and exports every entry point include/xsec.h declares
+(no compute calls: this runs without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from tests.conftest import ROOT
+
+HEADER = os.path.join(ROOT, "include", "xsec.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(xs_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_header_declares_the_entry_points():
+    names = _declared()
+    for n in ("xs_plan_create", "xs_plan_destroy", "xs_set_states", "xs_set_lines",
+              "xs_partition_function", "xs_cross_section", "xs_last_error"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1801_09803_amd import lib_path
+    if not os.path.exists(lib_path()):
+        pytest.fail("libxsec.so is not built (run python -m paper_1801_09803_amd.build)")
+    lib = ctypes.CDLL(lib_path())
+    missing = [n for n in _declared() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_version_and_defaults_without_gpu():
+    from paper_1801_09803_amd.binding import XsOpts, load_library
+    lib = load_library()
+    assert lib.xs_version() == 1
+    o = XsOpts()
+    assert lib.xs_opts_default(ctypes.byref(o)) == 0
+    assert o.cutoff == 25.0 and o.T0 == 296.0 and o.P0 == 1.0 and o.profile == 3
+
+
+@pytest.mark.parametrize("field,value", [("n_points", 1), ("cutoff", 0.0), ("mass_da", -1.0),
+                                         ("profile", 9), ("index_base", 2), ("slices_per_wave", 3)])
+def test_plan_create_rejects_bad_options_on_host(field, value):
+    # option validation happens before any device call
+    from paper_1801_09803_amd.binding import XsOpts, load_library
+    lib = load_library()
+    o = XsOpts()
+    lib.xs_opts_default(ctypes.byref(o))
+    o.nu_a, o.nu_b, o.n_points, o.mass_da = 0.0, 10.0, 101, 18.0
+    setattr(o, field, value)
+    h = ctypes.c_void_p()
+    st = lib.xs_plan_create(ctypes.byref(o), ctypes.byref(h))
+    assert st in (1, 7) and not h.value
+    assert lib.xs_last_error()
+
+
+def test_null_arguments_are_rejected_without_gpu():
+    from paper_1801_09803_amd.binding import load_library
+    lib = load_library()
+    assert lib.xs_plan_destroy(None) == 0
+    assert lib.xs_set_states(None, 10, None, None, None, None) == 1
+    assert lib.xs_cross_section(None, 1, None, None, None, None) == 1
