@@ -5,6 +5,7 @@
 #include "xs_forward.hpp"
 
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -54,6 +55,9 @@ struct xs_plan {
     DevBuf s_nu, s_elow, s_cA, s_gref, s_nexp, s_kc, s_klo, s_khi, s_orig;
     DevBuf k1, v1, k2, v2, hist, hoff, tsum;
     DevBuf off, flag;
+    // FP32 Voigt core pre-pass
+    DevBuf core_rc, core_cnt, core_bsum, core_off, core_val, core_tmp;
+    int xcd_contiguous = 0;
     uint32_t* sorted_keys = nullptr;
     // partition function
     int q_cap = 0;
@@ -87,7 +91,8 @@ struct xs_plan {
         DevBuf* all[] = {&E, &g, &J, &tab_g, &tab_n, &p_nu, &p_elow, &p_cA, &p_gref, &p_nexp, &p_kc,
                          &p_klo, &p_khi, &s_nu, &s_elow, &s_cA, &s_gref, &s_nexp, &s_kc, &s_klo,
                          &s_khi, &s_orig, &k1, &v1, &k2, &v2, &hist, &hoff, &tsum, &off, &flag,
-                         &T_dev, &Q, &dQ, &qpart, &tab_dev};
+                         &T_dev, &Q, &dQ, &qpart, &tab_dev, &core_rc, &core_cnt, &core_bsum,
+                         &core_off, &core_val, &core_tmp};
         for (DevBuf* b : all) release(*b);
     }
 };
@@ -151,6 +156,7 @@ xs_status xs_plan_create(const xs_opts* opts, xs_plan** out) {
     if (!p) return fail(XS_ERR_OOM, "host allocation failed");
     p->o = *opts;
     p->P = opts->slices_per_wave ? opts->slices_per_wave : 4;
+    if (const char* env = std::getenv("XSEC_XCD_CONTIGUOUS")) p->xcd_contiguous = std::atoi(env) ? 1 : 0;
     xs::Geometry& G = p->geo;
     G.nu_a = opts->nu_a;
     G.dnu = (opts->nu_b - opts->nu_a) / (double)(opts->n_points - 1);
@@ -351,6 +357,7 @@ xs_status xs_cross_section(xs_plan* p, int32_t n_tp, const double* T, const doub
     xs_status st = run_partition(p, n_tp, T, s);
     if (st != XS_OK) return st;
     const xs_opts& o = p->o;
+    // (the FP32 Voigt path waits on the stream once per (T, P) to size its core buffer)
     const bool fp64 = o.precision == XS_FP64;
     const size_t elem = fp64 ? sizeof(double) : sizeof(float);
     const int W = xs::tile_points(p->P);
@@ -361,9 +368,23 @@ xs_status xs_cross_section(xs_plan* p, int32_t n_tp, const double* T, const doub
     a.G = p->geo;
     a.Q = as<double>(p->Q);
     a.off = as<int>(p->off);
+    a.n_lines = (int)p->n_kept;
     a.n_tiles = (p->geo.n_points + W - 1) / W;
+    a.xcd_contiguous = p->xcd_contiguous;
     a.alpha_fixed = o.alpha_fixed;
     a.tab = as<xs::Tables>(p->tab_dev);
+    const bool core = !fp64 && o.profile == XS_VOIGT;
+    if (core) {
+        const size_t n = (size_t)std::max<int64_t>(p->n_kept, 1);
+        const size_t nb = (size_t)xs::core_blocks((int64_t)n);
+        if ((st = p->ensure(p->core_rc, n * sizeof(int), "core radii")) != XS_OK) return st;
+        if ((st = p->ensure(p->core_cnt, n * sizeof(int), "core counts")) != XS_OK) return st;
+        if ((st = p->ensure(p->core_off, n * sizeof(long long), "core offsets")) != XS_OK) return st;
+        if ((st = p->ensure(p->core_bsum, nb * sizeof(unsigned long long), "core block sums")) != XS_OK) return st;
+        if ((st = p->ensure(p->core_tmp, (4096 + 16) * sizeof(unsigned long long), "core scan")) != XS_OK) return st;
+        a.core_rc = as<int>(p->core_rc);
+        a.core_off = as<long long>(p->core_off);
+    }
     const double numax = std::max(std::fabs(o.nu_b), std::fabs(o.nu_a)) + o.cutoff;
     for (int i = 0; i < n_tp; ++i) {
         xs::TPParam& tp = a.tp;
@@ -382,8 +403,26 @@ xs_status xs_cross_section(xs_plan* p, int32_t n_tp, const double* T, const doub
         else if (o.profile == XS_GAUSS_FIXED) { xr = 10.5; alpha = o.alpha_fixed; }
         const double rmd = xr * alpha / (xs::kSQRT_LN2 * p->geo.dnu) + 2.0;
         tp.rm = rmd > 1.0e9 ? 1000000000 : (int)std::ceil(rmd);
-        a.fast_ok = (!fp64 && (double)W + rmd <= (double)p->geo.hmin) ? 1 : 0;
+        a.seg = (!fp64 && 64.0 * p->P + rmd + 1.0 <= (double)p->geo.hmin) ? 1 : 0;
         a.sigma = static_cast<char*>(sigma) + (size_t)i * (size_t)p->geo.n_points * elem;
+        if (core && p->n_kept > 0) {
+            xs::CoreArgs c{};
+            c.L = a.L; c.G = a.G; c.tp = tp; c.Q = a.Q; c.n_lines = a.n_lines; c.tab = a.tab;
+            c.rc = as<int>(p->core_rc); c.cnt = as<int>(p->core_cnt);
+            c.bsum = as<unsigned long long>(p->core_bsum); c.coff = as<long long>(p->core_off);
+            c.scan_tmp = as<unsigned long long>(p->core_tmp);
+            XS_HIP(xs::launch_core_count(c, s));
+            unsigned long long total = 0;
+            XS_HIP(hipMemcpyAsync(&total, as<unsigned long long>(p->core_tmp) + 4096, sizeof(total),
+                                  hipMemcpyDeviceToHost, s));
+            XS_HIP(hipStreamSynchronize(s));
+            if ((st = p->ensure(p->core_val, (size_t)std::max<unsigned long long>(total, 1) * sizeof(float),
+                                "core values")) != XS_OK)
+                return st;
+            c.val = as<float>(p->core_val);
+            XS_HIP(xs::launch_core_eval(c, s));
+            a.core_val = c.val;
+        }
         XS_HIP(xs::launch_forward(o.profile, fp64 ? 1 : 0, p->P, a, s));
     }
     return XS_OK;

@@ -1,0 +1,182 @@
+// Double-precision pre-pass of the FP32 Voigt path: every line's grid points with
+// |z| < 8 (where the single-precision wing formulas lose accuracy) are evaluated once
+// per (T, P), densely (one grid point per lane, points of consecutive lines packed
+// together), and stored as f32 values a * Re w(z) for the tile kernel to add.
+//
+// core_count: per sorted line, the core radius r (grid steps from kc, conservative)
+//   and the number of window points in [kc - r, kc + r]; per-256-line totals.
+// (exclusive scan of the totals)
+// core_eval: per 256 lines, block-local offsets, then the block's points in passes of
+//   256, each thread finding its line by binary search over the block prefix.
+#include "xs_forward_common.hpp"
+#include "xs_lineprep.hpp"
+
+namespace xs {
+
+namespace {
+
+template <class T>
+__device__ __forceinline__ T block_exclusive_scan_t(T v, T* lds4, T* total) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    T incl = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const T o = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += o;
+    }
+    __syncthreads();
+    if (lane == 63) lds4[wave] = incl;
+    __syncthreads();
+    T wbase = 0;
+    for (int w = 0; w < wave; ++w) wbase += lds4[w];
+    *total = lds4[0] + lds4[1] + lds4[2] + lds4[3];
+    return wbase + incl - v;
+}
+
+struct CoreLine {
+    double s, nu, y, a;
+    int lo, hi, r;
+};
+
+__device__ __forceinline__ CoreLine core_line(const CoreArgs& A, int g, double Q) {
+    const LineSetup ls = line_setup(A.L, A.tp, g, Q);
+    CoreLine c;
+    c.s = kSQRT_LN2 / ls.aD;
+    c.nu = ls.nu;
+    c.y = ls.gam * c.s;
+    c.a = ls.S * kSQRT_LN2_PI / ls.aD;
+    c.r = -1;
+    c.lo = 0;
+    c.hi = -1;
+    const double y2 = c.y * c.y;
+    if (y2 < kCoreR2) {
+        const double d = (A.G.nu_a + (double)ls.kc * A.G.dnu) - ls.nu;
+        c.r = radius_steps(sqrt(kCoreR2 - y2), c.s * A.G.dnu, c.s * d);
+        const int64_t lo = (int64_t)ls.kc - c.r, hi = (int64_t)ls.kc + c.r;
+        c.lo = (int)(lo > ls.klo ? lo : ls.klo);
+        c.hi = (int)(hi < ls.khi ? hi : ls.khi);
+    }
+    return c;
+}
+
+__global__ __launch_bounds__(256) void core_count_kernel(const CoreArgs A) {
+    __shared__ unsigned long long lds[4];
+    const int g = blockIdx.x * 256 + threadIdx.x;
+    unsigned long long c = 0;
+    if (g < A.n_lines) {
+        const CoreLine cl = core_line(A, g, A.Q[A.tp.iq]);
+        c = cl.hi >= cl.lo ? (unsigned long long)(cl.hi - cl.lo + 1) : 0ull;
+        A.rc[g] = cl.r;
+        A.cnt[g] = (int)c;
+    }
+    unsigned long long tot;
+    block_exclusive_scan_t<unsigned long long>(c, lds, &tot);
+    if (threadIdx.x == 0) A.bsum[blockIdx.x] = tot;
+}
+
+// exclusive scan of m u64 values in place (m <= 4096 * 4096); tmp[4096] gets the total
+constexpr int kScanTile = 4096;
+
+__global__ __launch_bounds__(256) void scan64_tiles_kernel(const unsigned long long* x, int64_t m,
+                                                           unsigned long long* tsum) {
+    __shared__ unsigned long long lds[4];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * 16;
+    unsigned long long s = 0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) if (base + k < m) s += x[base + k];
+    unsigned long long tot;
+    block_exclusive_scan_t<unsigned long long>(s, lds, &tot);
+    if (threadIdx.x == 0) tsum[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(256) void scan64_small_kernel(unsigned long long* tsum, int64_t nt) {
+    __shared__ unsigned long long lds[4];
+    const int64_t base = (int64_t)threadIdx.x * 16;
+    unsigned long long v[16], s = 0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) { v[k] = (base + k < nt) ? tsum[base + k] : 0ull; s += v[k]; }
+    unsigned long long tot;
+    unsigned long long pre = block_exclusive_scan_t<unsigned long long>(s, lds, &tot);
+#pragma unroll
+    for (int k = 0; k < 16; ++k) { if (base + k < nt) tsum[base + k] = pre; pre += v[k]; }
+    if (threadIdx.x == 0) tsum[kScanTile] = tot;
+}
+
+__global__ __launch_bounds__(256) void scan64_apply_kernel(unsigned long long* x, int64_t m,
+                                                           const unsigned long long* tsum) {
+    __shared__ unsigned long long lds[4];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * 16;
+    unsigned long long v[16], s = 0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) { v[k] = (base + k < m) ? x[base + k] : 0ull; s += v[k]; }
+    unsigned long long tot;
+    unsigned long long pre = block_exclusive_scan_t<unsigned long long>(s, lds, &tot) + tsum[blockIdx.x];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) { if (base + k < m) x[base + k] = pre; pre += v[k]; }
+}
+
+__global__ __launch_bounds__(256) void core_eval_kernel(const CoreArgs A) {
+    __shared__ unsigned long long lds4[4];
+    __shared__ unsigned long long pre[256];
+    __shared__ double ls_s[256], ls_nu[256], ls_y[256], ls_a[256];
+    __shared__ int ls_lo[256];
+    const int t = threadIdx.x;
+    const int g = blockIdx.x * 256 + t;
+    const double Q = A.Q[A.tp.iq];
+    unsigned long long c = 0;
+    if (g < A.n_lines) {
+        c = (unsigned long long)A.cnt[g];
+        if (c) {
+            const CoreLine cl = core_line(A, g, Q);
+            ls_s[t] = cl.s; ls_nu[t] = cl.nu; ls_y[t] = cl.y; ls_a[t] = cl.a; ls_lo[t] = cl.lo;
+        }
+    }
+    unsigned long long tot;
+    const unsigned long long ex = block_exclusive_scan_t<unsigned long long>(c, lds4, &tot);
+    const unsigned long long base = A.bsum[blockIdx.x];
+    pre[t] = ex;
+    if (g < A.n_lines) A.coff[g] = (long long)(base + ex);
+    __syncthreads();
+    for (unsigned long long it = t; it < tot; it += 256) {
+        int lo = 0, hi = 255;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (pre[mid] <= it) lo = mid; else hi = mid - 1;
+        }
+        const int j = lo;
+        const int k = ls_lo[j] + (int)(it - pre[j]);
+        const double x = ls_s[j] * ((A.G.nu_a + (double)k * A.G.dnu) - ls_nu[j]);
+        const double y = ls_y[j];
+        const double z2 = __builtin_fma(x, x, y * y);
+        double re;
+        if (z2 < kCoreR2) re = voigt_core_re<24, 8>(x, y, A.tab->w24);
+        else if (z2 < kMidR2) re = gh_wing_re(x * x, y, A.tab->gh4);
+        else re = gh_wing_re(x * x, y, A.tab->gh2);
+        A.val[base + it] = (float)(ls_a[j] * re);
+    }
+}
+
+}  // namespace
+
+int64_t core_blocks(int64_t n_lines) { return (n_lines + 255) / 256; }
+
+hipError_t launch_core_count(const CoreArgs& a, hipStream_t s) {
+    const int64_t nb = core_blocks(a.n_lines);
+    if (nb == 0) return hipSuccess;
+    hipLaunchKernelGGL(core_count_kernel, dim3((unsigned)nb), dim3(256), 0, s, a);
+    const int64_t nt = (nb + kScanTile - 1) / kScanTile;
+    if (nt > kScanTile) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(scan64_tiles_kernel, dim3((unsigned)nt), dim3(256), 0, s, a.bsum, nb, a.scan_tmp);
+    hipLaunchKernelGGL(scan64_small_kernel, dim3(1), dim3(256), 0, s, a.scan_tmp, nt);
+    hipLaunchKernelGGL(scan64_apply_kernel, dim3((unsigned)nt), dim3(256), 0, s, a.bsum, nb, a.scan_tmp);
+    return hipGetLastError();
+}
+
+hipError_t launch_core_eval(const CoreArgs& a, hipStream_t s) {
+    const int64_t nb = core_blocks(a.n_lines);
+    if (nb == 0) return hipSuccess;
+    hipLaunchKernelGGL(core_eval_kernel, dim3((unsigned)nb), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace xs
