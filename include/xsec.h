@@ -95,8 +95,10 @@ typedef struct {
     double gamma_const;    /* gamma_ref for XS_BROAD_CONST                                 */
     double n_const;        /* temperature exponent for XS_BROAD_CONST                      */
     int32_t slices_per_wave; /* tile shape: 64-point slices per wavefront (1, 2 or 4);
-                                0 = library default                                      */
-    int32_t reserved[7];
+                                0 = library default (2)                                  */
+    int32_t waves_per_block; /* tile shape: wavefronts per workgroup for XS_FP32 (4 or 8);
+                                0 = library default (4); XS_FP64 always uses 4           */
+    int32_t reserved[6];
 } xs_opts;
 
 /* Fill *opts with defaults: cutoff 25, T0 296 K, P0 1 bar, Voigt, FP32, per-line

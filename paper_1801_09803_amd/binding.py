@@ -33,7 +33,8 @@ class XsOpts(ctypes.Structure):
         ("P0", ctypes.c_double), ("profile", ctypes.c_int32), ("precision", ctypes.c_int32),
         ("broadening", ctypes.c_int32), ("index_base", ctypes.c_int32),
         ("alpha_fixed", ctypes.c_double), ("gamma_const", ctypes.c_double), ("n_const", ctypes.c_double),
-        ("slices_per_wave", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7),
+        ("slices_per_wave", ctypes.c_int32), ("waves_per_block", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 6),
     ]
 
 
@@ -103,7 +104,7 @@ class Plan:
                  cutoff: float = 25.0, profile: str = "voigt", precision: str = "fp32",
                  broadening: str = "per_line", T0: float = 296.0, P0: float = 1.0,
                  index_base: int = 0, alpha_fixed: float = 0.0, gamma_const: float = 0.0,
-                 n_const: float = 0.0, slices_per_wave: int = 0):
+                 n_const: float = 0.0, slices_per_wave: int = 0, waves_per_block: int = 0):
         import torch
         self._torch = torch
         lib = load_library()
@@ -117,6 +118,7 @@ class Plan:
         o.index_base = int(index_base)
         o.alpha_fixed, o.gamma_const, o.n_const = float(alpha_fixed), float(gamma_const), float(n_const)
         o.slices_per_wave = int(slices_per_wave)
+        o.waves_per_block = int(waves_per_block)
         h = ctypes.c_void_p()
         _check(lib.xs_plan_create(ctypes.byref(o), ctypes.byref(h)))
         self._lib = lib

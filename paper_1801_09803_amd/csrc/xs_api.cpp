@@ -8,6 +8,8 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <algorithm>
+#include <utility>
 #include <vector>
 
 namespace {
@@ -39,7 +41,8 @@ struct DevBuf {
 struct xs_plan {
     xs_opts o{};
     xs::Geometry geo{};
-    int P = 4;
+    int P = 2;
+    int waves = 4;
     size_t total_bytes = 0;
 
     // states
@@ -58,6 +61,9 @@ struct xs_plan {
     // FP32 Voigt core pre-pass
     DevBuf core_rc, core_cnt, core_bsum, core_off, core_val, core_tmp;
     int xcd_contiguous = 0;
+    int lpt_order = 1;
+    DevBuf tile_order;
+    int n_order = 0;
     uint32_t* sorted_keys = nullptr;
     // partition function
     int q_cap = 0;
@@ -92,7 +98,7 @@ struct xs_plan {
                          &p_klo, &p_khi, &s_nu, &s_elow, &s_cA, &s_gref, &s_nexp, &s_kc, &s_klo,
                          &s_khi, &s_orig, &k1, &v1, &k2, &v2, &hist, &hoff, &tsum, &off, &flag,
                          &T_dev, &Q, &dQ, &qpart, &tab_dev, &core_rc, &core_cnt, &core_bsum,
-                         &core_off, &core_val, &core_tmp};
+                         &core_off, &core_val, &core_tmp, &tile_order};
         for (DevBuf* b : all) release(*b);
     }
 };
@@ -122,6 +128,8 @@ xs_status validate_opts(const xs_opts* o) {
         return fail(XS_ERR_ARG, "gamma_const must be >= 0 and n_const finite");
     if (o->slices_per_wave != 0 && o->slices_per_wave != 1 && o->slices_per_wave != 2 && o->slices_per_wave != 4)
         return fail(XS_ERR_ARG, "slices_per_wave must be 0, 1, 2 or 4");
+    if (o->waves_per_block != 0 && o->waves_per_block != 4 && o->waves_per_block != 8)
+        return fail(XS_ERR_ARG, "waves_per_block must be 0, 4 or 8");
     const double dnu = (o->nu_b - o->nu_a) / (double)(o->n_points - 1);
     if (!(dnu > 0.0)) return fail(XS_ERR_ARG, "grid step underflows");
     const double hw = o->cutoff / dnu;
@@ -155,8 +163,10 @@ xs_status xs_plan_create(const xs_opts* opts, xs_plan** out) {
     xs_plan* p = new (std::nothrow) xs_plan();
     if (!p) return fail(XS_ERR_OOM, "host allocation failed");
     p->o = *opts;
-    p->P = opts->slices_per_wave ? opts->slices_per_wave : 4;
+    p->P = opts->slices_per_wave ? opts->slices_per_wave : 2;
+    p->waves = opts->precision == XS_FP64 ? 4 : (opts->waves_per_block ? opts->waves_per_block : 4);
     if (const char* env = std::getenv("XSEC_XCD_CONTIGUOUS")) p->xcd_contiguous = std::atoi(env) ? 1 : 0;
+    if (const char* env = std::getenv("XSEC_TILE_ORDER")) p->lpt_order = std::atoi(env) ? 1 : 0;
     xs::Geometry& G = p->geo;
     G.nu_a = opts->nu_a;
     G.dnu = (opts->nu_b - opts->nu_a) / (double)(opts->n_points - 1);
@@ -305,6 +315,28 @@ xs_status xs_set_lines(xs_plan* p, int64_t n, const int32_t* upper, const int32_
     if (flag & xs::kFlagKey) return fail(XS_ERR_ARG, "internal: window key out of range");
     p->n_lines = n;
     p->n_kept = kept;
+    p->n_order = 0;
+    if (p->lpt_order && kept > 0) {
+        // tiles by decreasing number of overlapping lines (host sort of the tile costs)
+        const xs::Geometry& G = p->geo;
+        const int W = xs::tile_points(p->P, p->waves);
+        const int nt = (G.n_points + W - 1) / W;
+        std::vector<int> off(G.nkeys + 1);
+        XS_HIP(hipMemcpy(off.data(), p->off.p, off.size() * sizeof(int), hipMemcpyDeviceToHost));
+        std::vector<std::pair<int, int>> cost(nt);
+        for (int t = 0; t < nt; ++t) {
+            const int64_t k0 = (int64_t)t * W;                       // key of kc = t0 - hmax
+            const int64_t k1 = std::min<int64_t>((int64_t)t * W + W + 2 * G.hmax, G.nkeys);
+            cost[t] = {off[k1] - off[std::min<int64_t>(k0, G.nkeys)], t};
+        }
+        std::stable_sort(cost.begin(), cost.end(),
+                         [](const std::pair<int, int>& a, const std::pair<int, int>& b) { return a.first > b.first; });
+        std::vector<int> order(nt);
+        for (int t = 0; t < nt; ++t) order[t] = cost[t].second;
+        if ((st = p->ensure(p->tile_order, nt * sizeof(int), "tile order")) != XS_OK) return st;
+        XS_HIP(hipMemcpy(p->tile_order.p, order.data(), nt * sizeof(int), hipMemcpyHostToDevice));
+        p->n_order = nt;
+    }
     p->have_lines = true;
     return XS_OK;
 }
@@ -360,7 +392,7 @@ xs_status xs_cross_section(xs_plan* p, int32_t n_tp, const double* T, const doub
     // (the FP32 Voigt path waits on the stream once per (T, P) to size its core buffer)
     const bool fp64 = o.precision == XS_FP64;
     const size_t elem = fp64 ? sizeof(double) : sizeof(float);
-    const int W = xs::tile_points(p->P);
+    const int W = xs::tile_points(p->P, p->waves);
     xs::FwdArgs a{};
     a.L.nu = as<double>(p->s_nu); a.L.elow = as<double>(p->s_elow); a.L.cA = as<double>(p->s_cA);
     a.L.gref = as<float>(p->s_gref); a.L.nexp = as<float>(p->s_nexp); a.L.kc = as<int>(p->s_kc);
@@ -371,6 +403,7 @@ xs_status xs_cross_section(xs_plan* p, int32_t n_tp, const double* T, const doub
     a.n_lines = (int)p->n_kept;
     a.n_tiles = (p->geo.n_points + W - 1) / W;
     a.xcd_contiguous = p->xcd_contiguous;
+    a.tile_order = (p->n_order == a.n_tiles) ? as<int>(p->tile_order) : nullptr;
     a.alpha_fixed = o.alpha_fixed;
     a.tab = as<xs::Tables>(p->tab_dev);
     const bool core = !fp64 && o.profile == XS_VOIGT;
@@ -423,7 +456,7 @@ xs_status xs_cross_section(xs_plan* p, int32_t n_tp, const double* T, const doub
             XS_HIP(xs::launch_core_eval(c, s));
             a.core_val = c.val;
         }
-        XS_HIP(xs::launch_forward(o.profile, fp64 ? 1 : 0, p->P, a, s));
+        XS_HIP(xs::launch_forward(o.profile, fp64 ? 1 : 0, p->waves, p->P, a, s));
     }
     return XS_OK;
 }

@@ -18,7 +18,8 @@ struct FwdArgs {
     int n_lines;            // kept (sorted) lines
     int n_tiles;
     int seg;                // FP32 path: per-wavefront line segments (needs 64P + rm < hmin)
-    int xcd_contiguous;     // map consecutive tiles to one XCD
+    int xcd_contiguous;     // map consecutive tiles to one XCD (when no order is given)
+    const int* tile_order;  // tiles by decreasing line count (heaviest dispatched first), or NULL
     double alpha_fixed;     // HWHM for the fixed Gaussian
     const Tables* tab;      // device quadrature tables
     // FP32 Voigt core pre-pass results (per sorted line)
@@ -27,10 +28,12 @@ struct FwdArgs {
     const float* core_val;          // a * Re w at the line's core points
 };
 
-// Points per block tile for a given number of 64-point slices per wavefront.
-inline int tile_points(int slices_per_wave) { return 256 * slices_per_wave; }
+// Points per block tile: 64-point slices per wavefront x wavefronts per block
+// (the FP64 kernel always uses 4 wavefronts).
+inline int tile_points(int slices_per_wave, int waves) { return 64 * waves * slices_per_wave; }
 
-hipError_t launch_forward(int profile, int fp64, int slices_per_wave, const FwdArgs& a, hipStream_t s);
+hipError_t launch_forward(int profile, int fp64, int waves, int slices_per_wave, const FwdArgs& a,
+                          hipStream_t s);
 
 // Core pre-pass (FP32 Voigt): radius/count per line, per-256-line block totals.
 struct CoreArgs {

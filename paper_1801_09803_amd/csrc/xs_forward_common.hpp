@@ -12,8 +12,11 @@ __device__ __forceinline__ int off_at(const int* off, int64_t kc, const Geometry
     return off[k];
 }
 
-// Tile index for a block; see launch_forward for the ordering policy.
-__device__ __forceinline__ int tile_of_block(int bid, int n, int xcd_contiguous) {
+// Tile index for a block.  With an order table the heaviest tiles are dispatched
+// first (longest-processing-time first), which balances the CUs when line density
+// varies along the grid; the lightest tiles fill the tail.
+__device__ __forceinline__ int tile_of_block(int bid, int n, int xcd_contiguous, const int* order) {
+    if (order) return order[bid];
     if (!xcd_contiguous) return bid;
     // consecutive tiles on the same XCD (blocks reach the 8 XCDs round-robin)
     const int x = bid & 7, q = n >> 3, r = n & 7;

@@ -35,33 +35,63 @@ namespace xs {
 
 namespace {
 
-constexpr int kRec = 32;     // record size in 4-byte words (128 B)
-constexpr int kBatch = 256;  // lines per LDS batch
+constexpr int kRec = 32;     // record size in 4-byte words (128 B); one line per thread
 
 enum : int {
     R_XC = 0, R_H = 1, R_C0 = 2, R_C1 = 3, R_AMP = 4, R_B = 5, R_SB0 = 6, R_CSC = 7,
-    R_CODE0 = 8, R_CODE1 = 9, R_JLO = 10, R_JHI = 11,
-    R_M = 12,        // 4-node mid zone: cp1, cd1, A1, B1, cp2, cd2, A2, B2
-    R_KCL = 20, R_KCH = 21, R_RAD = 22, R_SB0I = 23,
-    R_CBASE = 24     // int64 (words 24-25): core value index = cbase + k
+    R_JLO = 8, R_JHI = 9, R_KCL = 10, R_KCH = 11, R_RAD = 12, R_SB0I = 13,
+    R_CBASE = 14,    // int64 (words 14-15): core value index = cbase + k
+    R_M = 16,        // 4-node mid zone: cp1, cd1, A1, B1, cp2, cd2, A2, B2
+    R_ANC = 24,      // per-wavefront anchor x at the wave end nearest the centre (<= 8 waves)
+    R_CODE = 24      // coded sweep: 4-bit per-slice codes (<= 32 slices), shares the anchor words
+};
+
+// The caller's line data one thread needs to prepare a line record (prefetched a
+// batch ahead so the global loads overlap the sweep).
+struct RawLine {
+    double nu, elow, cA;
+    float gref, nexp;
+    int kc, klo, khi, rc;
+    long long coff;
 };
 
 template <int PROF>
-__device__ __forceinline__ void prepare_line(const FwdArgs& A, const Geometry& G, int g, double Q,
-                                             int t0, int NS, bool codes, float* r) {
-    const LineSetup ls = line_setup(A.L, A.tp, g, Q);
-    const double d = (G.nu_a + (double)ls.kc * G.dnu) - ls.nu;   // anchor offset nu_kc - nu
+__device__ __forceinline__ RawLine load_raw(const FwdArgs& A, int g) {
+    RawLine w;
+    w.nu = A.L.nu[g];
+    w.elow = A.L.elow[g];
+    w.cA = A.L.cA[g];
+    w.gref = A.L.gref[g];
+    w.nexp = A.L.nexp[g];
+    w.kc = A.L.kc[g];
+    w.klo = A.L.klo[g];
+    w.khi = A.L.khi[g];
+    if (PROF == kVoigt) { w.rc = A.core_rc[g]; w.coff = A.core_off[g]; }
+    else { w.rc = -1; w.coff = 0; }
+    return w;
+}
+
+template <int PROF, int WAVES, int P>
+__device__ __forceinline__ void prepare_line(const FwdArgs& A, const Geometry& G, const RawLine& w, double Q,
+                                             int t0, bool codes, float* r) {
+    constexpr int NS = WAVES * P;
+    const double T = A.tp.T;
+    // Eq. 1: I = [g_f A/(8 pi c nu^2)] exp(-c2 E_i/T) (1 - exp(-c2 nu/T)) / Q(T)
+    const double S = w.cA * exp(-(kC2 * w.elow) / T) * (-expm1(-(kC2 * w.nu) / T)) / Q;
+    const double aD = w.nu * A.tp.beta;                                              // Eq. 16
+    const double gam = (double)w.gref * exp((double)w.nexp * A.tp.ln_T0_T) * A.tp.p_over_p0;  // Eq. 18
+    const double d = (G.nu_a + (double)w.kc * G.dnu) - w.nu;   // anchor offset nu_kc - nu
     int* ri = reinterpret_cast<int*>(r);
-    r[R_SB0] = (float)(t0 - ls.kc);
-    ri[R_SB0I] = t0 - ls.kc;
-    r[R_JLO] = (float)(ls.klo - ls.kc);
-    r[R_JHI] = (float)(ls.khi - ls.kc);
+    r[R_SB0] = (float)(t0 - w.kc);
+    ri[R_SB0I] = t0 - w.kc;
+    r[R_JLO] = (float)(w.klo - w.kc);
+    r[R_JHI] = (float)(w.khi - w.kc);
     int kcl = 0, kch = -1, rad = -1;
-    double s = 1.0, y = 0.0;
+    double hd = 0.0, xd = 0.0;      // double-precision h and xc (scaled), for anchors
     if (PROF == kVoigt) {
-        s = kSQRT_LN2 / ls.aD;
-        y = ls.gam * s;
-        const double a = ls.S * kSQRT_LN2_PI / ls.aD;
+        const double s = kSQRT_LN2 / aD;
+        const double y = gam * s;
+        const double a = S * kSQRT_LN2_PI / aD;
         // power-of-two scaling keeps x^4 inside the float range for very narrow lines
         const double xmax = s * (G.cutoff + 2.0 * G.dnu) + 1.0;
         int e;
@@ -70,8 +100,10 @@ __device__ __forceinline__ void prepare_line(const FwdArgs& A, const Geometry& G
         const double sc = ldexp(1.0, -e), sc2 = sc * sc;
         const double y2 = y * y;
         const double ampf = a * y * kINV_SQRT_PI;
-        r[R_XC] = (float)(s * d * sc);
-        r[R_H] = (float)(s * G.dnu * sc);
+        hd = s * G.dnu * sc;
+        xd = s * d * sc;
+        r[R_XC] = (float)xd;
+        r[R_H] = (float)hd;
         r[R_C0] = (float)((y2 - 0.5) * sc2);
         r[R_C1] = (float)(2.0 * y2 * sc2 * sc2);
         r[R_AMP] = (float)(ampf * sc2);
@@ -87,54 +119,66 @@ __device__ __forceinline__ void prepare_line(const FwdArgs& A, const Geometry& G
             r[R_M + 4 * jp + 3] = (float)(Aj * 2.0 * t2);
         }
         rad = y2 < kMidR2 ? radius_steps(sqrt(kMidR2 - y2), s * G.dnu, s * d) : -1;
-        const int rc = A.core_rc[g];
-        if (rc >= 0) {
-            const int64_t lo = (int64_t)ls.kc - rc, hi = (int64_t)ls.kc + rc;
-            kcl = (int)(lo > ls.klo ? lo : ls.klo);
-            kch = (int)(hi < ls.khi ? hi : ls.khi);
+        if (w.rc >= 0) {
+            const int64_t lo = (int64_t)w.kc - w.rc, hi = (int64_t)w.kc + w.rc;
+            kcl = (int)(lo > w.klo ? lo : w.klo);
+            kch = (int)(hi < w.khi ? hi : w.khi);
         }
-        *reinterpret_cast<long long*>(r + R_CBASE) = A.core_off[g] - (long long)kcl;
+        *reinterpret_cast<long long*>(r + R_CBASE) = w.coff - (long long)kcl;
     } else if (PROF == kLorentz) {
-        const double ig = ls.gam > 0.0 ? 1.0 / ls.gam : 0.0;
-        s = ig;
-        r[R_XC] = (float)(d * ig);
-        r[R_H] = (float)(G.dnu * ig);
-        r[R_AMP] = (float)(ls.S * ig * (1.0 / kPI));
+        const double ig = gam > 0.0 ? 1.0 / gam : 0.0;
+        hd = G.dnu * ig;
+        xd = d * ig;
+        r[R_XC] = (float)xd;
+        r[R_H] = (float)hd;
+        r[R_AMP] = (float)(S * ig * (1.0 / kPI));
     } else {
         // Gaussian (Eq. 15); x scaled by sqrt(1/ln 2) so exp(-x^2) = exp2(-x'^2)
-        const double alpha = (PROF == kDoppler) ? ls.aD : A.alpha_fixed;
-        s = kSQRT_LN2 / alpha;
+        const double alpha = (PROF == kDoppler) ? aD : A.alpha_fixed;
+        const double s = kSQRT_LN2 / alpha;
         const double sl = s * 1.2011224087864498;
         r[R_XC] = (float)(sl * d);
         r[R_H] = (float)(sl * G.dnu);
-        r[R_AMP] = (float)(ls.S * kSQRT_LN2_PI / alpha);
+        r[R_AMP] = (float)(S * kSQRT_LN2_PI / alpha);
         rad = radius_steps(10.5, s * G.dnu, s * d);   // exp(-x^2) underflows beyond
     }
     ri[R_KCL] = kcl;
     ri[R_KCH] = kch;
     ri[R_RAD] = rad;
-    if (codes) {
-        unsigned c0 = 0, c1 = 0;
+    if (!codes) {
+        // x at the end of each wavefront's range nearest the centre: wing points are then
+        // x = anchor + (k - k_anchor) h with both terms of one sign
+#pragma unroll
+        for (int wv = 0; wv < WAVES; ++wv) {
+            const int wa = t0 + 64 * P * wv;
+            const int ka = wa > w.kc ? wa : wa + 64 * P - 1;
+            r[R_ANC + wv] = (float)__builtin_fma((double)(ka - w.kc), hd, xd);
+        }
+    } else {
+        unsigned cw[(NS + 7) / 8];
+#pragma unroll
+        for (int q = 0; q < (NS + 7) / 8; ++q) cw[q] = 0;
+#pragma unroll
         for (int sl = 0; sl < NS; ++sl) {
             const int kA = t0 + 64 * sl, kB = kA + 63;
             unsigned code = 0;
-            if (!(kB < ls.klo || kA > ls.khi)) {
-                const bool full = (kA >= ls.klo && kB <= ls.khi);
+            if (!(kB < w.klo || kA > w.khi)) {
+                const bool full = (kA >= w.klo && kB <= w.khi);
                 unsigned zone = 1;
                 if (PROF == kVoigt) {
                     if (kA <= kch && kB >= kcl) zone = 3;
-                    else if (rad >= 0 && (int64_t)kA <= (int64_t)ls.kc + rad && (int64_t)kB >= (int64_t)ls.kc - rad) zone = 2;
+                    else if (rad >= 0 && (int64_t)kA <= (int64_t)w.kc + rad && (int64_t)kB >= (int64_t)w.kc - rad) zone = 2;
                 } else if (PROF == kLorentz) {
-                    zone = ls.gam > 0.0 ? 1u : 0u;
+                    zone = gam > 0.0 ? 1u : 0u;
                 } else {
-                    zone = ((int64_t)kA <= (int64_t)ls.kc + rad && (int64_t)kB >= (int64_t)ls.kc - rad) ? 1u : 0u;
+                    zone = ((int64_t)kA <= (int64_t)w.kc + rad && (int64_t)kB >= (int64_t)w.kc - rad) ? 1u : 0u;
                 }
                 code = zone ? (zone | (full ? 0u : 4u)) : 0u;
             }
-            if (sl < 8) c0 |= code << (4 * sl); else c1 |= code << (4 * (sl - 8));
+            cw[sl / 8] |= code << (4 * (sl % 8));
         }
-        r[R_CODE0] = __uint_as_float(c0);
-        r[R_CODE1] = __uint_as_float(c1);
+#pragma unroll
+        for (int q = 0; q < (NS + 7) / 8; ++q) r[R_CODE + q] = __uint_as_float(cw[q]);
     }
 }
 
@@ -180,23 +224,25 @@ __device__ __forceinline__ float v_gauss(const float* r, float j) {
     return r[R_AMP] * __builtin_amdgcn_exp2f(-x * x);
 }
 
-template <int PROF, int P, bool SEG>
-__global__ __launch_bounds__(256) void fwd_f32_kernel(const FwdArgs A) {
-    constexpr int W = 256 * P;
-    constexpr int WW = 64 * P;
-    constexpr int NS = 4 * P;
-    __shared__ float rec[kBatch * kRec];
+template <int PROF, int WAVES, int P, bool SEG>
+__global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
+    constexpr int NT = 64 * WAVES;       // threads = lines per LDS batch
+    constexpr int W = NT * P;            // grid points per tile
+    constexpr int WW = 64 * P;           // grid points per wavefront
+    __shared__ float rec[NT * kRec];
 
     const Geometry G = A.G;
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int tile = tile_of_block(blockIdx.x, A.n_tiles, A.xcd_contiguous);
+    // the wavefront index is uniform within a wavefront: keep it (and everything derived
+    // from it: run bounds, loop counters, LDS record offsets) in scalar registers
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int tile = tile_of_block(blockIdx.x, A.n_tiles, A.xcd_contiguous, A.tile_order);
     const int t0 = tile * W, t1 = t0 + W - 1;
     const int w0 = t0 + wave * WW, w1 = w0 + WW - 1;
 
     const int b0 = off_at(A.off, (int64_t)t0 - G.hmax, G);
     const int b5 = off_at(A.off, (int64_t)t1 + G.hmax + 1, G);
     const int rm = A.tp.rm;
-    // per-wavefront runs (line indices), SEG mode
     int s0 = 0, s1 = 0, s2 = 0, s3 = 0, s4 = 0, s5 = 0;
     if (SEG) {
         s0 = off_at(A.off, (int64_t)w0 - G.hmax, G);
@@ -208,25 +254,31 @@ __global__ __launch_bounds__(256) void fwd_f32_kernel(const FwdArgs A) {
     }
     const double Q = A.Q[A.tp.iq];
 
-    float jl[P], part[P], sum[P], comp[P];
+    float jl[P], jlo_w[P], jhi_w[P], part[P], sum[P], comp[P];
 #pragma unroll
     for (int p = 0; p < P; ++p) {
-        jl[p] = (float)(64 * (wave * P + p) + lane);
+        jl[p] = (float)(64 * (wave * P + p) + lane);     // k - t0
+        jlo_w[p] = (float)(64 * p + lane);              // k - w0
+        jhi_w[p] = (float)(64 * p + lane - (WW - 1));   // k - w1
         part[p] = 0.f; sum[p] = 0.f; comp[p] = 0.f;
     }
-    const int cword = R_CODE0 + (wave * P) / 8;
+    const int cword = R_CODE + (wave * P) / 8;
     const int cshift = 4 * ((wave * P) % 8);
+    const int anc = R_ANC + wave;
 
-    for (int bs = b0; bs < b5; bs += kBatch) {
+    RawLine nxt;
+    if (b0 + tid < b5) nxt = load_raw<PROF>(A, b0 + tid);
+    for (int bs = b0; bs < b5; bs += NT) {
         const int g = bs + tid;
-        if (g < b5) prepare_line<PROF>(A, G, g, Q, t0, NS, !SEG, rec + tid * kRec);
+        if (g < b5) prepare_line<PROF, WAVES, P>(A, G, nxt, Q, t0, !SEG, rec + tid * kRec);
         __syncthreads();
-        const int be = bs + kBatch < b5 ? bs + kBatch : b5;
+        if (g + NT < b5) nxt = load_raw<PROF>(A, g + NT);   // overlaps the sweep below
+        const int be = bs + NT < b5 ? bs + NT : b5;
         for (int cs = bs; cs < be; cs += 64) {
             const int ce = cs + 64 < be ? cs + 64 : be;
             if (SEG) {
-                // ---- run 1: window ends inside the wave (upper mask)
                 if (PROF == kVoigt || PROF == kLorentz) {
+                    // ---- run 1: window ends inside the wave (upper mask)
                     const int lo = cs > s0 ? cs : s0, hi = ce < s1 ? ce : s1;
                     for (int l = lo; l < hi; ++l) {
                         const float* r = rec + (l - bs) * kRec;
@@ -250,21 +302,24 @@ __global__ __launch_bounds__(256) void fwd_f32_kernel(const FwdArgs A) {
                             part[p] += (j >= jlo) ? v : 0.0f;
                         }
                     }
-                    // ---- runs 2 and 4 (and 3 for Lorentz): wing formula, no branches
-                    for (int seg = 0; seg < 2; ++seg) {
-                        const int a0 = seg == 0 ? s1 : s3, a1 = seg == 0 ? s2 : s4;
+                    // ---- runs 2 and 4: wing formula from the anchor, no branches
+#pragma unroll
+                    for (int side = 0; side < 2; ++side) {
+                        const int a0 = side == 0 ? s1 : s3, a1 = side == 0 ? s2 : s4;
                         const int lo2 = cs > a0 ? cs : a0, hi2 = ce < a1 ? ce : a1;
+                        const float* jd = side == 0 ? jlo_w : jhi_w;
 #pragma unroll 2
                         for (int l = lo2; l < hi2; ++l) {
                             const float* r = rec + (l - bs) * kRec;
                             const float4 h0 = *reinterpret_cast<const float4*>(r);
-                            const float4 h1 = *reinterpret_cast<const float4*>(r + 4);
-                            const float xc = h0.x, h = h0.y, amp = h1.x, sb0 = h1.z;
+                            const float2 h1 = *reinterpret_cast<const float2*>(r + 4);
+                            const float xa = r[anc];
+                            const float h = h0.y, amp = h1.x;
                             if (PROF == kVoigt) {
                                 const float c0 = h0.z, c1 = h0.w, bb = h1.y;
 #pragma unroll
                                 for (int p = 0; p < P; ++p) {
-                                    const float x = __builtin_fmaf(jl[p] + sb0, h, xc);
+                                    const float x = __builtin_fmaf(jd[p], h, xa);
                                     const float pp = __builtin_fmaf(x, x, c0);
                                     const float den = __builtin_fmaf(pp, pp, c1);
                                     const float num = __builtin_fmaf(pp, amp, bb);
@@ -273,7 +328,7 @@ __global__ __launch_bounds__(256) void fwd_f32_kernel(const FwdArgs A) {
                             } else {
 #pragma unroll
                                 for (int p = 0; p < P; ++p) {
-                                    const float x = __builtin_fmaf(jl[p] + sb0, h, xc);
+                                    const float x = __builtin_fmaf(jd[p], h, xa);
                                     part[p] = __builtin_fmaf(amp, __builtin_amdgcn_rcpf(__builtin_fmaf(x, x, 1.0f)), part[p]);
                                 }
                             }
@@ -297,6 +352,16 @@ __global__ __launch_bounds__(256) void fwd_f32_kernel(const FwdArgs A) {
                         const int rad = __builtin_amdgcn_readfirstlane(ri[R_RAD]);
                         const int kcl = __builtin_amdgcn_readfirstlane(ri[R_KCL]);
                         const int kch = __builtin_amdgcn_readfirstlane(ri[R_KCH]);
+                        float vc[P];
+                        if (PROF == kVoigt) {
+                            // issue the stored core-value loads first
+                            const long long cb = *reinterpret_cast<const long long*>(r + R_CBASE);
+#pragma unroll
+                            for (int p = 0; p < P; ++p) {
+                                const int k = w0 + 64 * p + lane;
+                                vc[p] = (k >= kcl && k <= kch) ? A.core_val[cb + k] : 0.0f;
+                            }
+                        }
 #pragma unroll
                         for (int p = 0; p < P; ++p) {
                             const int kA = w0 + 64 * p, kB = kA + 63;
@@ -304,9 +369,15 @@ __global__ __launch_bounds__(256) void fwd_f32_kernel(const FwdArgs A) {
                             const bool near = rad >= 0 && (int64_t)kA <= (int64_t)kc + rad &&
                                               (int64_t)kB >= (int64_t)kc - rad;
                             if (PROF == kVoigt) {
-                                if (kA <= kch && kB >= kcl) part[p] += v_core(A, r, j, kA + lane);
-                                else if (near) part[p] += v_mid(r, j);
-                                else part[p] += v_far(r, j);
+                                if (kA <= kch && kB >= kcl) {
+                                    const int k = kA + lane;
+                                    const float vm = v_mid(r, j);
+                                    part[p] += (k >= kcl && k <= kch) ? vc[p] : vm;
+                                } else if (near) {
+                                    part[p] += v_mid(r, j);
+                                } else {
+                                    part[p] += v_far(r, j);
+                                }
                             } else {
                                 if (near) part[p] += v_gauss(r, j);
                             }
@@ -364,31 +435,39 @@ __global__ __launch_bounds__(256) void fwd_f32_kernel(const FwdArgs A) {
     }
 }
 
-template <int PROF, int P>
+template <int PROF, int WAVES, int P>
 void launch_one(const FwdArgs& a, hipStream_t s) {
-    const dim3 grid(a.n_tiles), block(256);
-    if (a.seg) hipLaunchKernelGGL((fwd_f32_kernel<PROF, P, true>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((fwd_f32_kernel<PROF, P, false>), grid, block, 0, s, a);
+    const dim3 grid(a.n_tiles), block(64 * WAVES);
+    if (a.seg) hipLaunchKernelGGL((fwd_f32_kernel<PROF, WAVES, P, true>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((fwd_f32_kernel<PROF, WAVES, P, false>), grid, block, 0, s, a);
 }
 
 template <int PROF>
-void launch_p(int P, const FwdArgs& a, hipStream_t s) {
-    switch (P) {
-        case 1: launch_one<PROF, 1>(a, s); break;
-        case 2: launch_one<PROF, 2>(a, s); break;
-        default: launch_one<PROF, 4>(a, s); break;
+void launch_p(int waves, int P, const FwdArgs& a, hipStream_t s) {
+    if (waves == 4) {
+        switch (P) {
+            case 1: launch_one<PROF, 4, 1>(a, s); break;
+            case 2: launch_one<PROF, 4, 2>(a, s); break;
+            default: launch_one<PROF, 4, 4>(a, s); break;
+        }
+    } else {
+        switch (P) {
+            case 1: launch_one<PROF, 8, 1>(a, s); break;
+            case 2: launch_one<PROF, 8, 2>(a, s); break;
+            default: launch_one<PROF, 8, 4>(a, s); break;
+        }
     }
 }
 
 }  // namespace
 
-hipError_t launch_forward_f32(int profile, int P, const FwdArgs& a, hipStream_t s) {
+hipError_t launch_forward_f32(int profile, int waves, int P, const FwdArgs& a, hipStream_t s) {
     if (a.n_tiles <= 0) return hipSuccess;
     switch (profile) {
-        case kDoppler: launch_p<kDoppler>(P, a, s); break;
-        case kGaussFixed: launch_p<kGaussFixed>(P, a, s); break;
-        case kLorentz: launch_p<kLorentz>(P, a, s); break;
-        default: launch_p<kVoigt>(P, a, s); break;
+        case kDoppler: launch_p<kDoppler>(waves, P, a, s); break;
+        case kGaussFixed: launch_p<kGaussFixed>(waves, P, a, s); break;
+        case kLorentz: launch_p<kLorentz>(waves, P, a, s); break;
+        default: launch_p<kVoigt>(waves, P, a, s); break;
     }
     return hipGetLastError();
 }

@@ -22,7 +22,7 @@ __global__ __launch_bounds__(256) void fwd_f64_kernel(const FwdArgs A) {
 
     const Geometry G = A.G;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int tile = tile_of_block(blockIdx.x, A.n_tiles, A.xcd_contiguous);
+    const int tile = tile_of_block(blockIdx.x, A.n_tiles, A.xcd_contiguous, A.tile_order);
     const int t0 = tile * W, t1 = t0 + W - 1;
     const int b0 = off_at(A.off, (int64_t)t0 - G.hmax, G);
     const int b5 = off_at(A.off, (int64_t)t1 + G.hmax + 1, G);
@@ -150,11 +150,11 @@ void launch_p64(int P, const FwdArgs& a, hipStream_t s) {
 
 }  // namespace
 
-hipError_t launch_forward_f32(int profile, int P, const FwdArgs& a, hipStream_t s);
+hipError_t launch_forward_f32(int profile, int waves, int P, const FwdArgs& a, hipStream_t s);
 
-hipError_t launch_forward(int profile, int fp64, int P, const FwdArgs& a, hipStream_t s) {
+hipError_t launch_forward(int profile, int fp64, int waves, int P, const FwdArgs& a, hipStream_t s) {
     if (a.n_tiles <= 0) return hipSuccess;
-    if (!fp64) return launch_forward_f32(profile, P, a, s);
+    if (!fp64) return launch_forward_f32(profile, waves, P, a, s);
     switch (profile) {
         case kDoppler: launch_p64<kDoppler>(P, a, s); break;
         case kGaussFixed: launch_p64<kGaussFixed>(P, a, s); break;
