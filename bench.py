@@ -74,7 +74,19 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--cpu-lines-per-core", type=int, default=20000)
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="only run a device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
+
+    if args.copy_probe:
+        import torch
+        x = torch.ones(args.copy_probe * 2**18, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_each_way": x.numel() * 4}), flush=True)
+        return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "

@@ -1,0 +1,115 @@
+"""Parity at the workloads' full sizes, in the launch configuration bench.py times,
+on sampled grid points the FP64 oracle computes one by one (every line whose window
+holds the point)."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import synth
+from tests.gpu_util import log, make_plan
+
+pytestmark = pytest.mark.gpu
+
+
+def _sample_points(sig, n_rand, seed, n_points):
+    rng = np.random.default_rng(seed)
+    pts = set(rng.integers(0, n_points, n_rand).tolist())
+    # points around the strongest features, where the core pre-pass values enter
+    top = np.argsort(sig)[-8:]
+    for k in top:
+        pts.update([int(k), max(int(k) - 1, 0), min(int(k) + 1, n_points - 1)])
+    return np.array(sorted(pts))
+
+
+def _oracle_at(cfg, d, ks, T, P, margin=25.5):
+    """Oracle sigma at grid indices ks: lines near each point are gathered on the
+    device (a generous distance filter) and evaluated on the host."""
+    E = d["E"]
+    nu = E[d["upper"].long()] - E[d["lower"].long()]
+    nu_k = torch.tensor(cfg.nu_a + ks.astype(np.float64) * cfg.dnu, device=nu.device)
+    sel = torch.zeros_like(nu, dtype=torch.bool)
+    for v in nu_k:
+        sel |= (nu - v).abs() <= margin
+    idx = torch.nonzero(sel).squeeze(1)
+    h = {k: d[k][idx].cpu().numpy() for k in ("upper", "lower", "A", "gamma_ref", "n_exp")}
+    Eh, gh = E.cpu().numpy(), d["g"].cpu().numpy()
+    Q = O.partition_function(Eh, gh, T)
+    ls = O.make_lineset(Eh, gh, h["upper"], h["lower"], h["A"], T, P, cfg.mass_amu,
+                        gamma_ref=h["gamma_ref"], n_exp=h["n_exp"], Q=Q)
+    log(f"  oracle: {idx.numel()} lines near {ks.size} points")
+    return O.cross_section_at(ls, ks, cfg.nu_a, cfg.nu_b, cfg.n_points, cfg.cutoff)
+
+
+def _check(got, ref, tol, what):
+    rel = np.abs(got - ref) / ref
+    log(f"  {what}: max rel {rel.max():.3e} over {ref.size} sampled points")
+    assert np.all(ref > 0)
+    assert rel.max() <= tol, (what, rel.max())
+
+
+@pytest.fixture(scope="module")
+def c2():
+    cfg = synth.CONFIGS["C2"]
+    log("generating C2 (1e8 transitions) on the device")
+    d = synth.make_linelist(cfg, device="cuda")
+    torch.cuda.synchronize()
+    return cfg, d
+
+
+@pytest.mark.parametrize("T", [296.0, 2000.0])
+def test_c2_full_size_fp32_sampled(c2, T):
+    cfg, d = c2
+    plan = make_plan(cfg, "fp32")
+    plan.set_states(d["E"], d["g"], d["J"])
+    plan.set_lines(d["upper"], d["lower"], d["A"], d["gamma_ref"], d["n_exp"])
+    assert plan.lines_kept() == cfg.n_lines
+    sig = plan.cross_section([T], [1.0])[0].double().cpu().numpy()
+    ks = _sample_points(sig, 24, int(T), cfg.n_points)
+    ref = _oracle_at(cfg, d, ks, T, 1.0)
+    _check(sig[ks], ref, 1e-5, f"C2 fp32 T={T}")
+
+
+def test_c2_full_size_fp64_sampled(c2):
+    cfg, d = c2
+    plan = make_plan(cfg, "fp64")
+    plan.set_states(d["E"], d["g"], d["J"])
+    plan.set_lines(d["upper"], d["lower"], d["A"], d["gamma_ref"], d["n_exp"])
+    sig = plan.cross_section([2000.0], [1.0])[0].cpu().numpy()
+    ks = _sample_points(sig, 12, 7, cfg.n_points)
+    ref = _oracle_at(cfg, d, ks, 2000.0, 1.0)
+    _check(sig[ks], ref, 1e-10, "C2 fp64 T=2000")
+
+
+def test_c3_subset_full_size(c2):
+    # C3 uses C2's list; three of its 270 (T, P) points, batched in one call
+    cfg3 = synth.CONFIGS["C3"]
+    cfg, d = c2
+    Ts = [cfg3.temperatures[0], cfg3.temperatures[13], cfg3.temperatures[26]]
+    Ps = [cfg3.pressures[0], cfg3.pressures[5], cfg3.pressures[9]]
+    plan = make_plan(cfg3, "fp32")
+    plan.set_states(d["E"], d["g"], d["J"])
+    plan.set_lines(d["upper"], d["lower"], d["A"], d["gamma_ref"], d["n_exp"])
+    out = plan.cross_section(Ts, Ps).double().cpu().numpy()
+    for i, (T, P) in enumerate(zip(Ts, Ps)):
+        ks = _sample_points(out[i], 8, 100 + i, cfg.n_points)
+        ref = _oracle_at(cfg3, d, ks, T, P)
+        keep = ref > 1e-6 * out[i].max()       # the parity floor of the full-grid metric
+        _check(out[i][ks][keep], ref[keep], 1e-5, f"C3 T={T:.1f} P={P:.2e}")
+
+
+def test_c4_full_size_sampled():
+    cfg = synth.CONFIGS["C4"]
+    d = synth.make_linelist(cfg, device="cuda")
+    plan = make_plan(cfg, "fp32")
+    plan.set_states(d["E"], d["g"], d["J"])
+    plan.set_lines(d["upper"], d["lower"], d["A"], d["gamma_ref"], d["n_exp"])
+    kept = plan.lines_kept()
+    log(f"  C4: {kept} of {cfg.n_lines} lines overlap the grid")
+    sig = plan.cross_section([1500.0], [0.1])[0].double().cpu().numpy()
+    ks = _sample_points(sig, 16, 4, cfg.n_points)
+    ref = _oracle_at(cfg, d, ks, 1500.0, 0.1)
+    keep = ref > 1e-6 * sig.max()
+    _check(sig[ks][keep], ref[keep], 1e-5, "C4 T=1500 P=0.1")
