@@ -25,6 +25,37 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FLOPS_PER_EVAL = 12          # far-wing rational: j add, 4 fma, rcp, accumulate fma (FMA = 2)
+
+# HBM traffic of the dominant kernel from two rocprofv3 --pmc runs of this script
+# (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch, T = 296 K and 2000 K), scaled by the
+# same counters on a 1 GiB device copy (FETCH_SIZE reads 0.5 GiB -> x2, WRITE_SIZE 1 GiB
+# -> x1).  Valid only for the kernel sources they were taken with (hash below).
+TRAFFIC = {
+    "kernel_sources": ["xs_forward_f32.hip", "xs_forward_common.hpp", "xs_voigt.hpp",
+                       "xs_forward.hpp", "xs_internal.hpp"],
+    "sha256": "116b2d4b3bd032ecbcbdf55c015ea9b181c7b3facb2cc02d90569496edb5555f",
+    "fetch_kib": [30174576.7, 33919933.7],
+    "write_kib": [3906.3, 3967.3],
+    "fetch_scale": 2.0,
+    "write_scale": 1.0,
+}
+
+
+def kernel_sources_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRAFFIC["kernel_sources"]:
+        with open(os.path.join(ROOT, "paper_1801_09803_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def traffic_bytes_per_launch():
+    if TRAFFIC["sha256"] is None or TRAFFIC["sha256"] != kernel_sources_sha():
+        return None
+    f = sum(TRAFFIC["fetch_kib"]) / len(TRAFFIC["fetch_kib"]) * TRAFFIC["fetch_scale"]
+    w = sum(TRAFFIC["write_kib"]) / len(TRAFFIC["write_kib"]) * TRAFFIC["write_scale"]
+    return (f + w) * 1024.0
 PEAK_FP32_TFLOPS = 157.3     # MI355X FP32 vector peak (published, packed)
 PEAK_FP32_UNPACKED = 78.6    # 256 CU x 64 lanes x 2 flop x 2.4 GHz without packed FP32
 
@@ -144,6 +175,7 @@ def main():
         log(f"warmup step {i}")
         step()
     torch.cuda.synchronize()
+    plan.set_timing(True)   # hipEvents around each library kernel launch, on this stream
     kern_ms = []
     log(f"timing {args.steps} steps")
     torch.cuda.synchronize()
@@ -155,11 +187,13 @@ def main():
         log(f"step {i}: forward {kern_ms[-1]:.1f} ms")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    kt = plan.kernel_times()
+    plan.set_timing(False)
     n_kept = plan.lines_kept()
     n_tp = len(temps)
     value = n_kept * n_tp * args.steps / elapsed
     ms_step = 1e3 * elapsed / args.steps
-    avg_launch_s = (sum(kern_ms) / len(kern_ms)) / 1e3 / n_tp
+    avg_launch_s = kt["forward_ms"] / kt["forward_launches"] / 1e3
     achieved = FLOPS_PER_EVAL * evals_per_tp / avg_launch_s / 1e12
 
     result = {
@@ -191,11 +225,16 @@ def main():
             "peak": PEAK_FP32_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_TFLOPS,
-            "traffic": None,
-            "kernel": "fwd_f32_kernel<Voigt>",
+            "traffic": traffic_bytes_per_launch(),
+            "kernel": "fwd_f32_kernel<Voigt> (tile kernel, one launch per (T,P))",
             "avg_launch_ms": avg_launch_s * 1e3,
             "flops_per_eval": FLOPS_PER_EVAL,
             "frac_of_unpacked_fp32": achieved / PEAK_FP32_UNPACKED,
+        },
+        "step_breakdown_ms": {
+            "line_prep_and_sort": kt["prep_ms"] / args.steps,
+            "voigt_core_prepass": kt["core_ms"] / args.steps,
+            "tile_kernel": kt["forward_ms"] / args.steps,
         },
         "forward_line_profiles_per_s": n_kept / avg_launch_s,
         "point_evaluations_per_s": evals_per_tp / avg_launch_s,

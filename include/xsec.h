@@ -152,6 +152,24 @@ xs_status xs_partition_function(xs_plan* plan, int32_t n_T, const double* T, dou
 xs_status xs_cross_section(xs_plan* plan, int32_t n_tp, const double* T, const double* P,
                            void* sigma, void* stream);
 
+/* Kernel timing (tracing).  While enabled, every launch of the forward tile kernel,
+ * of the double-precision Voigt core pre-pass and of the line preparation (prep,
+ * sort, gather) is bracketed by hipEvents recorded on the call's stream.
+ * xs_set_timing(plan, 1) clears the accumulated times and enables recording;
+ * xs_set_timing(plan, 0) stops it.  xs_kernel_times waits for the recorded events
+ * (synchronous) and returns the accumulated milliseconds and launch counts. */
+typedef struct {
+    double forward_ms;          /* tile kernels (one launch per (T, P))                    */
+    double core_ms;             /* Voigt core pre-pass (count + evaluation)                */
+    double prep_ms;             /* xs_set_lines device work                                */
+    int64_t forward_launches;
+    int64_t core_launches;
+    int64_t prep_launches;
+} xs_timings;
+
+xs_status xs_set_timing(xs_plan* plan, int enable);
+xs_status xs_kernel_times(xs_plan* plan, xs_timings* out);
+
 /* Bytes of device memory the plan currently holds. */
 size_t xs_workspace_bytes(const xs_plan* plan);
 

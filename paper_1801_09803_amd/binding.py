@@ -38,6 +38,12 @@ class XsOpts(ctypes.Structure):
     ]
 
 
+class XsKernelTimes(ctypes.Structure):
+    _fields_ = [("forward_ms", ctypes.c_double), ("core_ms", ctypes.c_double), ("prep_ms", ctypes.c_double),
+                ("forward_launches", ctypes.c_int64), ("core_launches", ctypes.c_int64),
+                ("prep_launches", ctypes.c_int64)]
+
+
 _lib = None
 
 
@@ -66,6 +72,8 @@ def load_library() -> ctypes.CDLL:
         "xs_lines_kept": (i32, [P, ctypes.POINTER(i64)]),
         "xs_partition_function": (i32, [P, i32, P, P, P, P]),
         "xs_cross_section": (i32, [P, i32, P, P, P, P]),
+        "xs_set_timing": (i32, [P, i32]),
+        "xs_kernel_times": (i32, [P, ctypes.POINTER(XsKernelTimes)]),
         "xs_workspace_bytes": (ctypes.c_size_t, [P]),
         "xs_last_error": (ctypes.c_char_p, []),
         "xs_version": (ctypes.c_int, []),
@@ -209,6 +217,14 @@ class Plan:
         _check(self._lib.xs_cross_section(self._h, len(T), _host_doubles(T), _host_doubles(P), _ptr(out),
                                           self._stream()))
         return out
+
+    def set_timing(self, enable: bool = True):
+        _check(self._lib.xs_set_timing(self._h, 1 if enable else 0))
+
+    def kernel_times(self) -> dict:
+        t = XsKernelTimes()
+        _check(self._lib.xs_kernel_times(self._h, ctypes.byref(t)))
+        return {f: getattr(t, f) for f, _ in XsKernelTimes._fields_}
 
     def workspace_bytes(self) -> int:
         return int(self._lib.xs_workspace_bytes(self._h))

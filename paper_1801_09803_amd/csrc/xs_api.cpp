@@ -38,8 +38,17 @@ struct DevBuf {
 
 }  // namespace
 
+struct TimedRange {
+    hipEvent_t a, b;
+    int kind;   // 0 forward, 1 core, 2 prep
+};
+
 struct xs_plan {
     xs_opts o{};
+    bool timing = false;
+    std::vector<TimedRange> timed;
+    double acc_ms[3] = {0, 0, 0};
+    int64_t acc_n[3] = {0, 0, 0};
     xs::Geometry geo{};
     int P = 2;
     int waves = 4;
@@ -93,7 +102,12 @@ struct xs_plan {
         total_bytes += bytes;
         return XS_OK;
     }
+    void drop_timed() {
+        for (auto& t : timed) { (void)hipEventDestroy(t.a); (void)hipEventDestroy(t.b); }
+        timed.clear();
+    }
     void release_all() {
+        drop_timed();
         DevBuf* all[] = {&E, &g, &J, &tab_g, &tab_n, &p_nu, &p_elow, &p_cA, &p_gref, &p_nexp, &p_kc,
                          &p_klo, &p_khi, &s_nu, &s_elow, &s_cA, &s_gref, &s_nexp, &s_kc, &s_klo,
                          &s_khi, &s_orig, &k1, &v1, &k2, &v2, &hist, &hoff, &tsum, &off, &flag,
@@ -107,6 +121,30 @@ namespace {
 
 template <class T>
 T* as(DevBuf& b) { return static_cast<T*>(b.p); }
+
+// Event pair around a launch sequence when timing is on.
+struct Timer {
+    xs_plan* p;
+    hipStream_t s;
+    int kind;
+    hipEvent_t a = nullptr, b = nullptr;
+    Timer(xs_plan* p_, hipStream_t s_, int k) : p(p_), s(s_), kind(k) {
+        if (p->timing && hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess)
+            (void)hipEventRecord(a, s);
+        else a = b = nullptr;
+    }
+    void stop() {
+        if (a && b) {
+            (void)hipEventRecord(b, s);
+            p->timed.push_back({a, b, kind});
+            a = b = nullptr;
+        }
+    }
+    ~Timer() {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    }
+};
 
 xs_status validate_opts(const xs_opts* o) {
     if (!o) return fail(XS_ERR_ARG, "opts is NULL");
@@ -271,6 +309,7 @@ xs_status xs_set_lines(xs_plan* p, int64_t n, const int32_t* upper, const int32_
     if ((st = p->ensure(p->off, (size_t)(p->geo.nkeys + 1) * sizeof(int), "offsets")) != XS_OK) return st;
     if ((st = p->ensure(p->flag, sizeof(int) * 4, "flags")) != XS_OK) return st;
     XS_HIP(hipMemsetAsync(p->flag.p, 0, sizeof(int), s));
+    Timer tprep(p, s, 2);
 
     xs::PrepArgs a{};
     a.n = n;
@@ -305,6 +344,7 @@ xs_status xs_set_lines(xs_plan* p, int64_t n, const int32_t* upper, const int32_
     ga.klo = as<int>(p->s_klo); ga.khi = as<int>(p->s_khi); ga.orig = as<int>(p->s_orig);
     XS_HIP(xs::launch_gather(ga, s));
     XS_HIP(xs::launch_offsets(sk, n, p->geo.nkeys, as<int>(p->off), s));
+    tprep.stop();
 
     int flag = 0, kept = 0;
     XS_HIP(hipMemcpyAsync(&flag, p->flag.p, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -444,7 +484,9 @@ xs_status xs_cross_section(xs_plan* p, int32_t n_tp, const double* T, const doub
             c.rc = as<int>(p->core_rc); c.cnt = as<int>(p->core_cnt);
             c.bsum = as<unsigned long long>(p->core_bsum); c.coff = as<long long>(p->core_off);
             c.scan_tmp = as<unsigned long long>(p->core_tmp);
+            Timer tc(p, s, 1);
             XS_HIP(xs::launch_core_count(c, s));
+            tc.stop();
             unsigned long long total = 0;
             XS_HIP(hipMemcpyAsync(&total, as<unsigned long long>(p->core_tmp) + 4096, sizeof(total),
                                   hipMemcpyDeviceToHost, s));
@@ -453,11 +495,44 @@ xs_status xs_cross_section(xs_plan* p, int32_t n_tp, const double* T, const doub
                                 "core values")) != XS_OK)
                 return st;
             c.val = as<float>(p->core_val);
+            Timer te(p, s, 1);
             XS_HIP(xs::launch_core_eval(c, s));
+            te.stop();
             a.core_val = c.val;
         }
+        Timer tf(p, s, 0);
         XS_HIP(xs::launch_forward(o.profile, fp64 ? 1 : 0, p->waves, p->P, a, s));
+        tf.stop();
     }
+    return XS_OK;
+}
+
+xs_status xs_set_timing(xs_plan* p, int enable) {
+    if (!p) return fail(XS_ERR_ARG, "plan is NULL");
+    if (enable) {
+        p->drop_timed();
+        for (int k = 0; k < 3; ++k) { p->acc_ms[k] = 0; p->acc_n[k] = 0; }
+    }
+    p->timing = enable != 0;
+    return XS_OK;
+}
+
+xs_status xs_kernel_times(xs_plan* p, xs_timings* out) {
+    if (!p || !out) return fail(XS_ERR_ARG, "NULL argument");
+    for (auto& t : p->timed) {
+        XS_HIP(hipEventSynchronize(t.b));
+        float ms = 0.0f;
+        XS_HIP(hipEventElapsedTime(&ms, t.a, t.b));
+        p->acc_ms[t.kind] += ms;
+        p->acc_n[t.kind] += 1;
+    }
+    p->drop_timed();
+    out->forward_ms = p->acc_ms[0];
+    out->core_ms = p->acc_ms[1];
+    out->prep_ms = p->acc_ms[2];
+    out->forward_launches = p->acc_n[0];
+    out->core_launches = p->acc_n[1];
+    out->prep_launches = p->acc_n[2];
     return XS_OK;
 }
 
