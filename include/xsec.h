@@ -98,7 +98,8 @@ typedef struct {
                                 0 = library default (2)                                  */
     int32_t waves_per_block; /* tile shape: wavefronts per workgroup for XS_FP32 (4 or 8);
                                 0 = library default (4); XS_FP64 always uses 4           */
-    int32_t reserved[6];
+    int32_t a_is_log;        /* 1: the A array given to xs_set_lines holds ln A (s^-1)    */
+    int32_t reserved[5];
 } xs_opts;
 
 /* Fill *opts with defaults: cutoff 25, T0 296 K, P0 1 bar, Voigt, FP32, per-line
@@ -151,6 +152,20 @@ xs_status xs_partition_function(xs_plan* plan, int32_t n_T, const double* T, dou
  * XS_FP64.  The result overwrites sigma. */
 xs_status xs_cross_section(xs_plan* plan, int32_t n_tp, const double* T, const double* P,
                            void* sigma, void* stream);
+
+/* Adjoint of xs_cross_section for one (T, P) with the Voigt profile (not in the paper:
+ * the derivative of Eq. 1, 2, 16, 18 and of the Voigt profile).  Given dL/dsigma on the
+ * grid it returns dL/dT, dL/dP and, per transition in the caller's order of the last
+ * xs_set_lines, dL/d(ln A), dL/d(gamma_ref) and dL/dn (lines whose window misses the grid
+ * get 0).  Profiles are recomputed; nothing is kept from the forward call.
+ * dL_dsigma: device float[n_points] (XS_FP32) or double[n_points] (XS_FP64);
+ * dL_dT, dL_dP: device double[1] or NULL; dL_dlogA, dL_dgamma_ref, dL_dn: device
+ * arrays of n_lines values, float (XS_FP32) or double (XS_FP64), or NULL
+ * (gamma_ref / n outputs need XS_BROAD_PER_LINE).
+ * Returns XS_ERR_UNSUPPORTED for other profiles. */
+xs_status xs_cross_section_adjoint(xs_plan* plan, double T, double P, const void* dL_dsigma,
+                                   double* dL_dT, double* dL_dP, void* dL_dlogA,
+                                   void* dL_dgamma_ref, void* dL_dn, void* stream);
 
 /* Kernel timing (tracing).  While enabled, every launch of the forward tile kernel,
  * of the double-precision Voigt core pre-pass and of the line preparation (prep,

@@ -34,7 +34,7 @@ class XsOpts(ctypes.Structure):
         ("broadening", ctypes.c_int32), ("index_base", ctypes.c_int32),
         ("alpha_fixed", ctypes.c_double), ("gamma_const", ctypes.c_double), ("n_const", ctypes.c_double),
         ("slices_per_wave", ctypes.c_int32), ("waves_per_block", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 6),
+        ("a_is_log", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5),
     ]
 
 
@@ -72,6 +72,7 @@ def load_library() -> ctypes.CDLL:
         "xs_lines_kept": (i32, [P, ctypes.POINTER(i64)]),
         "xs_partition_function": (i32, [P, i32, P, P, P, P]),
         "xs_cross_section": (i32, [P, i32, P, P, P, P]),
+        "xs_cross_section_adjoint": (i32, [P, dbl, dbl, P, P, P, P, P, P, P]),
         "xs_set_timing": (i32, [P, i32]),
         "xs_kernel_times": (i32, [P, ctypes.POINTER(XsKernelTimes)]),
         "xs_workspace_bytes": (ctypes.c_size_t, [P]),
@@ -112,7 +113,8 @@ class Plan:
                  cutoff: float = 25.0, profile: str = "voigt", precision: str = "fp32",
                  broadening: str = "per_line", T0: float = 296.0, P0: float = 1.0,
                  index_base: int = 0, alpha_fixed: float = 0.0, gamma_const: float = 0.0,
-                 n_const: float = 0.0, slices_per_wave: int = 0, waves_per_block: int = 0):
+                 n_const: float = 0.0, slices_per_wave: int = 0, waves_per_block: int = 0,
+                 a_is_log: bool = False):
         import torch
         self._torch = torch
         lib = load_library()
@@ -127,6 +129,7 @@ class Plan:
         o.alpha_fixed, o.gamma_const, o.n_const = float(alpha_fixed), float(gamma_const), float(n_const)
         o.slices_per_wave = int(slices_per_wave)
         o.waves_per_block = int(waves_per_block)
+        o.a_is_log = 1 if a_is_log else 0
         h = ctypes.c_void_p()
         _check(lib.xs_plan_create(ctypes.byref(o), ctypes.byref(h)))
         self._lib = lib
@@ -217,6 +220,22 @@ class Plan:
         _check(self._lib.xs_cross_section(self._h, len(T), _host_doubles(T), _host_doubles(P), _ptr(out),
                                           self._stream()))
         return out
+
+    def cross_section_adjoint(self, T: float, P: float, grad_sigma, n_lines: int,
+                              want_broadening: bool = True):
+        """Returns (dL/dT, dL/dP, dL/dlnA, dL/dgamma_ref, dL/dn) as device tensors."""
+        torch = self._torch
+        grad_sigma = self._dev(grad_sigma, self.dtype, "grad_sigma")
+        if grad_sigma.numel() != self.n_points:
+            raise ValueError("grad_sigma must have n_points values")
+        dT = torch.empty(1, dtype=torch.float64, device="cuda")
+        dP = torch.empty(1, dtype=torch.float64, device="cuda")
+        dlnA = torch.empty(n_lines, dtype=self.dtype, device="cuda")
+        dg = torch.empty(n_lines, dtype=self.dtype, device="cuda") if want_broadening else None
+        dn = torch.empty(n_lines, dtype=self.dtype, device="cuda") if want_broadening else None
+        _check(self._lib.xs_cross_section_adjoint(self._h, float(T), float(P), _ptr(grad_sigma), _ptr(dT),
+                                                  _ptr(dP), _ptr(dlnA), _ptr(dg), _ptr(dn), self._stream()))
+        return dT, dP, dlnA, dg, dn
 
     def set_timing(self, enable: bool = True):
         _check(self._lib.xs_set_timing(self._h, 1 if enable else 0))

@@ -1,0 +1,254 @@
+// Adjoint of the sampled Voigt cross section (extension of the paper's method: the
+// derivative of Eq. 1, 2, 16, 18 and the Voigt profile of Sec. "Line profiles").
+//
+// Given gbar_k = dL/dsigma_k on the grid, each line i needs three window sums
+// (phi = N Re w(z), N = sqrt(ln2/pi)/alpha_D, z = x + iy, x = s D, y = s gamma,
+// s = sqrt(ln2)/alpha_D, V = Re w):
+//   A0 = sum gbar V,   Ax = sum gbar x dV/dx,   Ay = sum gbar dV/dy
+// from which
+//   R0 = sum gbar phi            = N A0
+//   Rg = sum gbar dphi/dgamma    = N s Ay
+//   Ra = sum gbar dphi/dalpha_D  = -(N/alpha_D) (A0 + Ax + y Ay)
+//   dL/dln A_i     = S_i R0
+//   dL/dgamma_ref  = S_i Rg gamma_i / gamma_ref_i
+//   dL/dn_i        = S_i Rg gamma_i ln(T0/T)
+//   dL/dT = sum_i S_i (tau_i R0 + Ra alpha_D/(2T) - Rg n_i gamma_i / T),
+//           tau_i = c2 E''/T^2 - (c2 nu/T^2)/expm1(c2 nu/T) - (dQ/dT)/Q
+//   dL/dP = sum_i S_i Rg gamma_i / P   (gamma_ref (T0/T)^n / P0 at P = 0)
+// Profiles are recomputed, nothing is stored from the forward pass.  One wavefront
+// per line walks its window 64 points at a time; wing points use the analytic
+// derivatives of the Gauss-Hermite rules (single precision for the FP32 path, with
+// the forward kernel's power-of-two scaling), |z| < 8 points the double-precision core
+// with w' (Weideman / Taylor).  Window sums accumulate in double; per-line results go
+// to the caller's line order; dL/dT and dL/dP are reduced in a fixed order.
+#include "xs_adjoint.hpp"
+#include "xs_forward_common.hpp"
+
+namespace xs {
+
+namespace {
+
+__device__ __forceinline__ double wave_sum64(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+
+// single-precision Gauss-Hermite wing sums in scaled variables (see file header of
+// xs_forward_f32.hip for the scaling): per pair j, p = x_s^2 + a_j, q = p + b_j,
+// d = p^2 + e_j, r = 1/d; returns sum c q r, sum c u (r - 2 p q r^2), sum c (q r + 2 y_s^2 (r - 2 q^2 r^2))
+template <int NP>
+__device__ __forceinline__ void wing_dv_f32(float xs, const float* a, const float* b, const float* e,
+                                            const float* c, float ys2, float* sv, float* sx, float* sy) {
+    const float u = xs * xs;
+    float v0 = 0.f, v1 = 0.f, v2 = 0.f;
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+        const float p = u + a[j];
+        const float q = p + b[j];
+        const float r = __builtin_amdgcn_rcpf(__builtin_fmaf(p, p, e[j]));
+        const float qr = q * r;
+        v0 = __builtin_fmaf(c[j], qr, v0);
+        v1 = __builtin_fmaf(c[j], r * __builtin_fmaf(-2.0f * p, qr, 1.0f), v1);
+        v2 = __builtin_fmaf(c[j], __builtin_fmaf(2.0f * ys2, r * __builtin_fmaf(-2.0f * q, qr, 1.0f), qr), v2);
+    }
+    *sv = v0;
+    *sx = v1 * u;
+    *sy = v2;
+}
+
+template <bool FP64>
+__global__ __launch_bounds__(256) void adjoint_kernel(const AdjArgs A) {
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int nwaves = gridDim.x * 4;
+    const Geometry G = A.G;
+    const double T = A.tp.T;
+    const double Q = A.Q[0], dQ = A.dQ[0];
+    const Tables* tab = A.tab;
+
+    for (int g = blockIdx.x * 4 + wave; g < A.n_lines; g += nwaves) {
+        const LineSetup ls = line_setup(A.L, A.tp, g, Q);
+        const double s = kSQRT_LN2 / ls.aD;
+        const double y = ls.gam * s;
+        const double Nn = kSQRT_LN2_PI / ls.aD;
+        const double d = (G.nu_a + (double)ls.kc * G.dnu) - ls.nu;
+        const double y2 = y * y;
+        // scaled single-precision wing coefficients
+        double sc = 1.0;
+        float hs = 0.f, xcs = 0.f, ys2 = 0.f, z0s = 0.f, z1s = 0.f;
+        float a2[1], b2[1], e2[1], c2[1], a4[2], b4[2], e4[2], c4[2];
+        if (!FP64) {
+            const double xmax = s * (G.cutoff + 2.0 * G.dnu) + 1.0;
+            int ex;
+            frexp(xmax, &ex);
+            ex = ex > 31 ? ex - 31 : 0;
+            sc = ldexp(1.0, -ex);
+            const double sc2 = sc * sc;
+            hs = (float)(s * G.dnu * sc);
+            xcs = (float)(s * d * sc);
+            ys2 = (float)(y2 * sc2);
+            z0s = (float)(kCoreR2 * sc2);
+            z1s = (float)(kMidR2 * sc2);
+            {
+                const double t2 = tab->gh2.t[0] * tab->gh2.t[0];
+                a2[0] = (float)((y2 - t2) * sc2); b2[0] = (float)(2.0 * t2 * sc2);
+                e2[0] = (float)(4.0 * t2 * y2 * sc2 * sc2); c2[0] = (float)(2.0 * tab->gh2.w[0]);
+            }
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const double t2 = tab->gh4.t[j] * tab->gh4.t[j];
+                a4[j] = (float)((y2 - t2) * sc2); b4[j] = (float)(2.0 * t2 * sc2);
+                e4[j] = (float)(4.0 * t2 * y2 * sc2 * sc2); c4[j] = (float)(2.0 * tab->gh4.w[j]);
+            }
+        }
+        double s0 = 0.0, sxa = 0.0, sya = 0.0;   // scaled wing sums (FP32 path)
+        double c0 = 0.0, cx = 0.0, cy = 0.0;     // unscaled sums (core points; all points on FP64)
+        for (int k = ls.klo + lane; k <= ls.khi; k += 64) {
+            const double gb = FP64 ? static_cast<const double*>(A.gbar)[k]
+                                   : (double)static_cast<const float*>(A.gbar)[k];
+            const int j = k - ls.kc;
+            if (FP64) {
+                const double x = s * ((G.nu_a + (double)k * G.dnu) - ls.nu);
+                const double u = x * x;
+                const double z2 = u + y2;
+                double v, xvx, vy;
+                if (z2 < kCoreR2) {
+                    double rw, rdw, idw;
+                    voigt_core_dw<40, 14>(x, y, tab->w40, &rw, &rdw, &idw);
+                    v = rw; xvx = x * rdw; vy = -idw;
+                } else if (z2 < 400.0) {
+                    gh_wing_dv(u, y, tab->gh12, &v, &xvx, &vy);
+                } else if (z2 < 3600.0) {
+                    gh_wing_dv(u, y, tab->gh6, &v, &xvx, &vy);
+                } else if (z2 < 4.84e6) {
+                    gh_wing_dv(u, y, tab->gh4, &v, &xvx, &vy);
+                } else {
+                    gh_wing_dv(u, y, tab->gh2, &v, &xvx, &vy);
+                }
+                c0 = __builtin_fma(gb, v, c0);
+                cx = __builtin_fma(gb, xvx, cx);
+                cy = __builtin_fma(gb, vy, cy);
+            } else {
+                const float xsv = __builtin_fmaf((float)j, hs, xcs);
+                const float z2s = __builtin_fmaf(xsv, xsv, ys2);
+                if (z2s >= z0s) {
+                    float sv, sx, sy;
+                    if (z2s >= z1s) wing_dv_f32<1>(xsv, a2, b2, e2, c2, ys2, &sv, &sx, &sy);
+                    else wing_dv_f32<2>(xsv, a4, b4, e4, c4, ys2, &sv, &sx, &sy);
+                    s0 = __builtin_fma(gb, (double)sv, s0);
+                    sxa = __builtin_fma(gb, (double)sx, sxa);
+                    sya = __builtin_fma(gb, (double)sy, sya);
+                } else {
+                    const double x = s * __builtin_fma((double)j, G.dnu, d);
+                    double rw, rdw, idw;
+                    voigt_core_dw<24, 8>(x, y, tab->w24, &rw, &rdw, &idw);
+                    c0 = __builtin_fma(gb, rw, c0);
+                    cx = __builtin_fma(gb, x * rdw, cx);
+                    cy = __builtin_fma(gb, -idw, cy);
+                }
+            }
+        }
+        s0 = wave_sum64(s0); sxa = wave_sum64(sxa); sya = wave_sum64(sya);
+        c0 = wave_sum64(c0); cx = wave_sum64(cx); cy = wave_sum64(cy);
+        if (lane == 0) {
+            const double sc2 = sc * sc;
+            // scaled sums carry a factor c^2 = 1/sc^2 (x_s = x sc): V = (y sc^2/pi) sum c q_s r_s, ...
+            const double kv = y * sc2 / kPI, ky = sc2 / kPI;
+            const double A0 = kv * s0 + c0;
+            const double Ax = 2.0 * kv * sxa + cx;
+            const double Ay = ky * sya + cy;
+            const double R0 = Nn * A0;
+            const double Rg = Nn * s * Ay;
+            const double Ra = -(Nn / ls.aD) * (A0 + Ax + y * Ay);
+            const double S = ls.S;
+            const double gref = (double)A.L.gref[g];
+            const double nexp = (double)A.L.nexp[g];
+            const int o = A.L.orig[g];
+            const double v_lnA = S * R0;
+            const double v_gref = gref > 0.0 ? S * Rg * ls.gam / gref : 0.0;
+            const double v_n = S * Rg * ls.gam * A.tp.ln_T0_T;
+            if (FP64) {
+                if (A.dlnA) static_cast<double*>(A.dlnA)[o] = v_lnA;
+                if (A.dgref) static_cast<double*>(A.dgref)[o] = v_gref;
+                if (A.dn) static_cast<double*>(A.dn)[o] = v_n;
+            } else {
+                if (A.dlnA) static_cast<float*>(A.dlnA)[o] = (float)v_lnA;
+                if (A.dgref) static_cast<float*>(A.dgref)[o] = (float)v_gref;
+                if (A.dn) static_cast<float*>(A.dn)[o] = (float)v_n;
+            }
+            const double x2 = (kC2 * ls.nu) / T;
+            const double tau = (kC2 * A.L.elow[g]) / (T * T) - ((kC2 * ls.nu) / (T * T)) / expm1(x2) - dQ / Q;
+            A.pT[g] = S * (tau * R0 + Ra * ls.aD / (2.0 * T) - Rg * nexp * ls.gam / T);
+            const double dgam_dP = A.tp.P > 0.0 ? ls.gam / A.tp.P
+                                                : gref * exp(nexp * A.tp.ln_T0_T) / A.P0;
+            A.pP[g] = S * Rg * dgam_dP;
+        }
+    }
+}
+
+template <class R>
+__global__ __launch_bounds__(256) void fill_zero_kernel(void* a, void* b, void* c, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    if (a) static_cast<R*>(a)[i] = R(0);
+    if (b) static_cast<R*>(b)[i] = R(0);
+    if (c) static_cast<R*>(c)[i] = R(0);
+}
+
+// fixed-order sum of two double arrays: 256 blocks x 256 threads of strided partials,
+// then one block over the 256 partials
+__global__ __launch_bounds__(256) void sum2_partial_kernel(const double* a, const double* b, int64_t n,
+                                                           double* part) {
+    __shared__ double la[4], lb[4];
+    double sa = 0.0, sb = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        sa += a[i];
+        sb += b[i];
+    }
+    sa = wave_sum64(sa);
+    sb = wave_sum64(sb);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) { la[wave] = sa; lb[wave] = sb; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = (la[0] + la[1]) + (la[2] + la[3]);
+        part[gridDim.x + blockIdx.x] = (lb[0] + lb[1]) + (lb[2] + lb[3]);
+    }
+}
+
+__global__ __launch_bounds__(256) void sum2_final_kernel(const double* part, int nb, double* outa, double* outb) {
+    __shared__ double la[4], lb[4];
+    double sa = 0.0, sb = 0.0;
+    for (int i = threadIdx.x; i < nb; i += 256) { sa += part[i]; sb += part[nb + i]; }
+    sa = wave_sum64(sa);
+    sb = wave_sum64(sb);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) { la[wave] = sa; lb[wave] = sb; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (outa) *outa = (la[0] + la[1]) + (la[2] + la[3]);
+        if (outb) *outb = (lb[0] + lb[1]) + (lb[2] + lb[3]);
+    }
+}
+
+}  // namespace
+
+hipError_t launch_adjoint(const AdjArgs& a, int fp64, int64_t n_caller_lines, double* part, double* dT,
+                          double* dP, hipStream_t s) {
+    if (n_caller_lines > 0) {
+        const dim3 g((unsigned)((n_caller_lines + 255) / 256));
+        if (fp64) hipLaunchKernelGGL(fill_zero_kernel<double>, g, dim3(256), 0, s, a.dlnA, a.dgref, a.dn, n_caller_lines);
+        else hipLaunchKernelGGL(fill_zero_kernel<float>, g, dim3(256), 0, s, a.dlnA, a.dgref, a.dn, n_caller_lines);
+    }
+    if (a.n_lines > 0) {
+        const int blocks = 2048;
+        if (fp64) hipLaunchKernelGGL(adjoint_kernel<true>, dim3(blocks), dim3(256), 0, s, a);
+        else hipLaunchKernelGGL(adjoint_kernel<false>, dim3(blocks), dim3(256), 0, s, a);
+    }
+    hipLaunchKernelGGL(sum2_partial_kernel, dim3(256), dim3(256), 0, s, a.pT, a.pP, (int64_t)a.n_lines, part);
+    hipLaunchKernelGGL(sum2_final_kernel, dim3(1), dim3(256), 0, s, part, 256, dT, dP);
+    return hipGetLastError();
+}
+
+}  // namespace xs

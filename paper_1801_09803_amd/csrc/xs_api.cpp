@@ -3,6 +3,7 @@
 #include "xs_internal.hpp"
 #include "xs_lineprep.hpp"
 #include "xs_forward.hpp"
+#include "xs_adjoint.hpp"
 
 #include <cmath>
 #include <cstdlib>
@@ -69,6 +70,7 @@ struct xs_plan {
     DevBuf off, flag;
     // FP32 Voigt core pre-pass
     DevBuf core_rc, core_cnt, core_bsum, core_off, core_val, core_tmp;
+    DevBuf adj_pT, adj_pP, adj_part;
     int xcd_contiguous = 0;
     int lpt_order = 1;
     DevBuf tile_order;
@@ -112,7 +114,7 @@ struct xs_plan {
                          &p_klo, &p_khi, &s_nu, &s_elow, &s_cA, &s_gref, &s_nexp, &s_kc, &s_klo,
                          &s_khi, &s_orig, &k1, &v1, &k2, &v2, &hist, &hoff, &tsum, &off, &flag,
                          &T_dev, &Q, &dQ, &qpart, &tab_dev, &core_rc, &core_cnt, &core_bsum,
-                         &core_off, &core_val, &core_tmp, &tile_order};
+                         &core_off, &core_val, &core_tmp, &tile_order, &adj_pT, &adj_pP, &adj_part};
         for (DevBuf* b : all) release(*b);
     }
 };
@@ -166,6 +168,7 @@ xs_status validate_opts(const xs_opts* o) {
         return fail(XS_ERR_ARG, "gamma_const must be >= 0 and n_const finite");
     if (o->slices_per_wave != 0 && o->slices_per_wave != 1 && o->slices_per_wave != 2 && o->slices_per_wave != 4)
         return fail(XS_ERR_ARG, "slices_per_wave must be 0, 1, 2 or 4");
+    if (o->a_is_log != 0 && o->a_is_log != 1) return fail(XS_ERR_ARG, "a_is_log must be 0 or 1");
     if (o->waves_per_block != 0 && o->waves_per_block != 4 && o->waves_per_block != 8)
         return fail(XS_ERR_ARG, "waves_per_block must be 0, 4 or 8");
     const double dnu = (o->nu_b - o->nu_a) / (double)(o->n_points - 1);
@@ -319,6 +322,7 @@ xs_status xs_set_lines(xs_plan* p, int64_t n, const int32_t* upper, const int32_
     a.gamma_const = (float)p->o.gamma_const; a.n_const = (float)p->o.n_const;
     a.broad = broad;
     a.index_base = p->o.index_base;
+    a.a_is_log = p->o.a_is_log;
     a.E = as<double>(p->E); a.g = as<int>(p->g); a.J = as<int>(p->J);
     a.n_states = p->n_states;
     a.geo = p->geo;
@@ -504,6 +508,48 @@ xs_status xs_cross_section(xs_plan* p, int32_t n_tp, const double* T, const doub
         XS_HIP(xs::launch_forward(o.profile, fp64 ? 1 : 0, p->waves, p->P, a, s));
         tf.stop();
     }
+    return XS_OK;
+}
+
+xs_status xs_cross_section_adjoint(xs_plan* p, double T, double P, const void* gbar, double* dT, double* dP,
+                                   void* dlnA, void* dgref, void* dn, void* stream) {
+    if (!p || !gbar) return fail(XS_ERR_ARG, "NULL argument");
+    if (!p->have_lines) return fail(XS_ERR_STATE, "xs_set_lines must succeed first");
+    if (p->o.profile != XS_VOIGT) return fail(XS_ERR_UNSUPPORTED, "the adjoint is implemented for XS_VOIGT");
+    if ((dgref || dn) && p->o.broadening != XS_BROAD_PER_LINE)
+        return fail(XS_ERR_UNSUPPORTED, "gamma_ref / n gradients need per-line broadening");
+    if (!(P >= 0.0) || !std::isfinite(P)) return fail(XS_ERR_ARG, "pressure must be finite and >= 0");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    xs_status st = run_partition(p, 1, &T, s);
+    if (st != XS_OK) return st;
+    const size_t n = (size_t)std::max<int64_t>(p->n_kept, 1);
+    if ((st = p->ensure(p->adj_pT, n * sizeof(double), "adjoint partials")) != XS_OK) return st;
+    if ((st = p->ensure(p->adj_pP, n * sizeof(double), "adjoint partials")) != XS_OK) return st;
+    if ((st = p->ensure(p->adj_part, 512 * sizeof(double), "adjoint reduction")) != XS_OK) return st;
+    const xs_opts& o = p->o;
+    xs::AdjArgs a{};
+    a.L.nu = as<double>(p->s_nu); a.L.elow = as<double>(p->s_elow); a.L.cA = as<double>(p->s_cA);
+    a.L.gref = as<float>(p->s_gref); a.L.nexp = as<float>(p->s_nexp); a.L.kc = as<int>(p->s_kc);
+    a.L.klo = as<int>(p->s_klo); a.L.khi = as<int>(p->s_khi); a.L.orig = as<int>(p->s_orig);
+    a.G = p->geo;
+    a.tp.T = T;
+    a.tp.P = P;
+    a.tp.c2_over_T = xs::kC2 / T;
+    a.tp.beta = std::sqrt(2.0 * xs::kKB * T * xs::kLN2 / (o.mass_da * xs::kAMU)) / xs::kC_SI;
+    a.tp.ln_T0_T = std::log(o.T0 / T);
+    a.tp.p_over_p0 = P / o.P0;
+    a.P0 = o.P0;
+    a.Q = as<double>(p->Q);
+    a.dQ = as<double>(p->dQ);
+    a.gbar = gbar;
+    a.n_lines = (int)p->n_kept;
+    a.tab = as<xs::Tables>(p->tab_dev);
+    a.dlnA = dlnA; a.dgref = dgref; a.dn = dn;
+    a.pT = as<double>(p->adj_pT);
+    a.pP = as<double>(p->adj_pP);
+    Timer tf(p, s, 0);
+    XS_HIP(xs::launch_adjoint(a, o.precision == XS_FP64 ? 1 : 0, p->n_lines, as<double>(p->adj_part), dT, dP, s));
+    tf.stop();
     return XS_OK;
 }
 

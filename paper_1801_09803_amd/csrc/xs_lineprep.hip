@@ -110,7 +110,8 @@ __global__ __launch_bounds__(256) void prep_kernel(PrepArgs a) {
                     } else { gr = a.gamma_const; ne = a.n_const; }
                     a.p_nu[i] = nu;
                     a.p_elow[i] = El;
-                    a.p_cA[i] = (double)a.g[up] * (double)a.A[i] / (8.0 * kPI * kC_CGS * nu * nu);
+                    const double Aein = a.a_is_log ? exp((double)a.A[i]) : (double)a.A[i];
+                    a.p_cA[i] = (double)a.g[up] * Aein / (8.0 * kPI * kC_CGS * nu * nu);
                     a.p_gref[i] = gr;
                     a.p_nexp[i] = ne;
                     a.p_kc[i] = kc;

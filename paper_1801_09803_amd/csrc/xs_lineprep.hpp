@@ -18,6 +18,7 @@ struct PrepArgs {
     float gamma_const, n_const;  // broad == 0
     int broad;
     int index_base;
+    int a_is_log;              // A holds ln A
     const double* E;
     const int* g;
     const int* J;

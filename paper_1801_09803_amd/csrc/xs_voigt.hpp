@@ -97,3 +97,72 @@ __device__ __forceinline__ double gh_wing_re(double u, double y, const GHPairs& 
 }
 
 }  // namespace xs
+
+namespace xs {
+
+// Re w, Re w' and Im w' for |z| < 8 (same split as voigt_core_re).
+template <int N, int K>
+__device__ __forceinline__ void voigt_core_dw(double x, double y, const WeidemanCoef& W, double* re_w,
+                                              double* re_dw, double* im_dw) {
+    if (y >= 0.2) {
+        const cplx w = weideman_w<N>(x, y, W);
+        // w' = -2 z w + 2i/sqrt(pi)
+        *re_w = w.re;
+        *re_dw = -2.0 * (x * w.re - y * w.im);
+        *im_dw = -2.0 * (x * w.im + y * w.re) + 2.0 * kINV_SQRT_PI;
+        return;
+    }
+    // Taylor in iy about the real axis: w(z) = sum w^(k) (iy)^k/k!, w'(z) = sum w^(k+1) (iy)^k/k!
+    double w0r = exp(-x * x);
+    double w0i = weideman_w<N>(x, 0.0, W).im;
+    double w1r = -2.0 * x * w0r;
+    double w1i = -2.0 * x * w0i + 2.0 * kINV_SQRT_PI;
+    double sr = w0r, dr = w1r, di = w1i;   // k = 0 terms
+    double fac = 1.0;                      // y^k / k!
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        // w^(k+2) from w^(k+1), w^(k)
+        const double w2r = -2.0 * x * w1r - 2.0 * (k + 1) * w0r;
+        const double w2i = -2.0 * x * w1i - 2.0 * (k + 1) * w0i;
+        fac *= y / (k + 1);
+        const int m = (k + 1) & 3;   // i^(k+1)
+        // w term: w^(k+1) i^(k+1); w' term: w^(k+2) i^(k+1)
+        if (m == 0) { sr += w1r * fac; dr += w2r * fac; di += w2i * fac; }
+        else if (m == 1) { sr -= w1i * fac; dr -= w2i * fac; di += w2r * fac; }
+        else if (m == 2) { sr -= w1r * fac; dr -= w2r * fac; di -= w2i * fac; }
+        else { sr += w1i * fac; dr += w2i * fac; di -= w2r * fac; }
+        w0r = w1r; w0i = w1i; w1r = w2r; w1i = w2i;
+    }
+    *re_w = sr;
+    *re_dw = dr;
+    *im_dw = di;
+}
+
+// n-point Gauss-Hermite approximation V = Re w of the Voigt convolution and its
+// derivatives: returns V, x dV/dx and dV/dy (double).  With u = x^2 and, per node pair,
+// p = u + y^2 - t^2, q = p + 2 t^2, d = p^2 + 4 t^2 y^2 (V = (y/pi) sum c q/d):
+//   x dV/dx = (y/pi) sum c 2u (1/d - 2 p q/d^2)
+//   dV/dy   = (1/pi) sum c (q/d + 2 y^2 (1/d - 2 q^2/d^2))
+__device__ __forceinline__ void gh_wing_dv(double u, double y, const GHPairs& G, double* v, double* xvx,
+                                           double* vy) {
+    const double y2 = y * y;
+    double s0 = 0.0, sx = 0.0, sy = 0.0;
+    const int np = G.n_pairs + (G.has_zero ? 1 : 0);
+    for (int j = 0; j < np; ++j) {
+        const bool zero = j == G.n_pairs;
+        const double t2 = zero ? 0.0 : G.t[j] * G.t[j];
+        const double c = zero ? G.w0 : 2.0 * G.w[j];
+        const double p = u + y2 - t2;
+        const double q = p + 2.0 * t2;
+        const double r = rcp64(__builtin_fma(p, p, 4.0 * t2 * y2));
+        const double qr = q * r;
+        s0 = __builtin_fma(c, qr, s0);
+        sx = __builtin_fma(c, __builtin_fma(-2.0 * p * qr, r, r), sx);
+        sy = __builtin_fma(c, __builtin_fma(2.0 * y2, __builtin_fma(-2.0 * q * qr, r, r), qr), sy);
+    }
+    *v = s0 * y * (1.0 / kPI);
+    *xvx = sx * 2.0 * u * y * (1.0 / kPI);
+    *vy = sy * (1.0 / kPI);
+}
+
+}  // namespace xs

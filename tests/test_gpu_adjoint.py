@@ -1,0 +1,158 @@
+"""Adjoint (dL/dT, dL/dP, per-line dL/dlnA, dL/dgamma_ref, dL/dn) on the GPU against
+the FP64 oracle's analytic gradient (same seeded dL/dsigma as input) and against
+central finite differences of the GPU's own FP64 forward."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import synth
+from tests.gpu_util import log
+
+pytestmark = pytest.mark.gpu
+
+
+def _case(seed=21, n_states=400, n_lines=3000):
+    cfg = synth.WorkloadConfig("adj", seed, n_states, n_lines, 34.0, 300.0, 0.0, 200.0, 20001,
+                               (1500.0,), (0.1,), cutoff=25.0)
+    d = synth.make_linelist(cfg, device="cuda")
+    return cfg, d
+
+
+def _plan(cfg, precision):
+    from paper_1801_09803_amd import Plan
+    return Plan(cfg.nu_a, cfg.nu_b, cfg.n_points, cfg.mass_amu, cutoff=cfg.cutoff, profile="voigt",
+                precision=precision, a_is_log=True)
+
+
+def _gbar(cfg, n_points):
+    return synth.linelist.perturbation_normals(n_points, cfg.seed + 7).numpy() * 1e18
+
+
+def _oracle_adj(cfg, h, logA, T, P, gbar, lines=None):
+    up, lo, A, gr, ne = h["upper"], h["lower"], np.exp(logA.astype(np.float64)), h["gamma_ref"], h["n_exp"]
+    if lines is not None:
+        up, lo, A, gr, ne = up[lines], lo[lines], A[lines], gr[lines], ne[lines]
+    return O.voigt_adjoint(h["E"], h["g"], up, lo, A, gr, ne, T, P, cfg.mass_amu,
+                           cfg.nu_a, cfg.nu_b, cfg.n_points, gbar, cutoff=cfg.cutoff)
+
+
+def _cmp(name, got, ref, tol, floor=1e-6):
+    got, ref = np.asarray(got, np.float64), np.asarray(ref, np.float64)
+    m = np.abs(ref) > floor * np.abs(ref).max()
+    rel = np.abs(got[m] - ref[m]) / np.abs(ref[m])
+    log(f"  {name}: max rel {rel.max():.3e} over {m.sum()} values")
+    assert rel.max() <= tol, (name, rel.max())
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-8), ("fp32", 1e-4)])
+@pytest.mark.parametrize("T,P", [(1500.0, 0.1), (300.0, 1.0)])
+def test_adjoint_matches_oracle_gradient(precision, tol, T, P):
+    cfg, d = _case()
+    h = {k: v.cpu().numpy() for k, v in d.items()}
+    logA = np.log(h["A"].astype(np.float64)).astype(np.float32)
+    gbar = _gbar(cfg, cfg.n_points)
+    plan = _plan(cfg, precision)
+    plan.set_states(d["E"], d["g"], d["J"])
+    plan.set_lines(d["upper"], d["lower"], torch.from_numpy(logA).cuda(), d["gamma_ref"], d["n_exp"])
+    gdev = torch.from_numpy(gbar).to("cuda", plan.dtype)
+    dT, dP, dlnA, dg, dn = plan.cross_section_adjoint(T, P, gdev, cfg.n_lines)
+    torch.cuda.synchronize()
+    ref = _oracle_adj(cfg, h, logA, T, P, gdev.double().cpu().numpy())
+    log(f"{precision} T={T} P={P}")
+    _cmp("dlnA", dlnA.cpu().numpy(), ref["dlnA"], tol)
+    _cmp("dgamma_ref", dg.cpu().numpy(), ref["dgamma_ref"], tol)
+    _cmp("dn", dn.cpu().numpy(), ref["dn"], tol)
+    _cmp("dT", [dT.item()], [ref["dT"]], tol, floor=0)
+    _cmp("dP", [dP.item()], [ref["dP"]], tol, floor=0)
+
+
+def test_adjoint_matches_central_differences_fp64():
+    # L = sum (sigma - sigma*)^2 with the GPU FP64 forward; sigma* at a seeded perturbation
+    cfg, d = _case(seed=22, n_lines=1500)
+    logA = torch.log(d["A"].double()).float()
+    plan = _plan(cfg, "fp64")
+    plan.set_states(d["E"], d["g"], d["J"])
+    T, P = 1500.0, 0.1
+
+    def sigma(T_, P_, la, gr, ne):
+        plan.set_lines(d["upper"], d["lower"], la, gr, ne)
+        return plan.cross_section([T_], [P_])[0].clone()
+
+    pert = synth.linelist.perturbation_normals(cfg.n_lines, cfg.seed).to("cuda")
+    ref = sigma(1.05 * T, P, (logA.double() + 0.05 * pert).float(), d["gamma_ref"] * 1.1, d["n_exp"])
+    base = sigma(T, P, logA, d["gamma_ref"], d["n_exp"])
+
+    def L(*a):
+        return float(((sigma(*a) - ref) ** 2).sum().item())
+
+    g = 2.0 * (base - ref)
+    plan.set_lines(d["upper"], d["lower"], logA, d["gamma_ref"], d["n_exp"])
+    dT, dP, dlnA, dg, dn = plan.cross_section_adjoint(T, P, g, cfg.n_lines)
+    dT, dP = dT.item(), dP.item()
+    hT, hP = 1e-6 * T, 1e-6 * P
+    fT = (L(T + hT, P, logA, d["gamma_ref"], d["n_exp"]) - L(T - hT, P, logA, d["gamma_ref"], d["n_exp"])) / (2 * hT)
+    fP = (L(T, P + hP, logA, d["gamma_ref"], d["n_exp"]) - L(T, P - hP, logA, d["gamma_ref"], d["n_exp"])) / (2 * hP)
+    log(f"  dT adj {dT:.6e} fd {fT:.6e};  dP adj {dP:.6e} fd {fP:.6e}")
+    assert abs(dT - fT) <= 1e-5 * abs(fT)
+    assert abs(dP - fP) <= 1e-5 * abs(fP)
+    # per-line: the strongest few lines (float32 parameters: steps well above their ulp)
+    strength = dlnA.abs().cpu().numpy()
+    for i in np.argsort(strength)[-4:]:
+        e = torch.zeros(cfg.n_lines, device="cuda", dtype=torch.float64); e[int(i)] = 1.0
+        lp = (logA.double() + 1e-3 * e).float()
+        lm = (logA.double() - 1e-3 * e).float()
+        step = (lp[int(i)].double() - lm[int(i)].double()).item()   # the float32 step actually taken
+        fd = (L(T, P, lp, d["gamma_ref"], d["n_exp"]) - L(T, P, lm, d["gamma_ref"], d["n_exp"])) / step
+        log(f"  line {i}: dlnA adj {dlnA[int(i)].item():.6e} fd {fd:.6e}")
+        assert abs(dlnA[int(i)].item() - fd) <= 1e-3 * abs(fd)
+
+
+def test_autograd_function_wires_the_adjoint():
+    from paper_1801_09803_amd.autograd import XsecFn
+    cfg, d = _case(seed=23, n_lines=800)
+    plan = _plan(cfg, "fp32")
+    plan.set_states(d["E"], d["g"], d["J"])
+    T = torch.tensor(900.0, dtype=torch.float64, requires_grad=True)
+    P = torch.tensor(0.5, dtype=torch.float64, requires_grad=True)
+    logA = torch.log(d["A"]).clone().requires_grad_(True)
+    gr = d["gamma_ref"].clone().requires_grad_(True)
+    ne = d["n_exp"].clone().requires_grad_(True)
+    sig = XsecFn.apply(plan, d["upper"], d["lower"], T, P, logA, gr, ne)
+    w = torch.linspace(0.0, 1.0, sig.numel(), device="cuda")
+    (sig.double() * w).sum().backward()
+    dT, dP, dlnA, dg, dn = plan.cross_section_adjoint(900.0, 0.5, w.float().contiguous(), cfg.n_lines)
+    assert torch.allclose(T.grad, dT[0]) and torch.allclose(P.grad, dP[0])
+    assert torch.equal(logA.grad, dlnA) and torch.equal(gr.grad, dg) and torch.equal(ne.grad, dn)
+
+
+def test_c4_full_size_adjoint_sampled_lines():
+    cfg = synth.CONFIGS["C4"]
+    d = synth.make_linelist(cfg, device="cuda")
+    logA = torch.log(d["A"].double()).float()
+    gbar = _gbar(cfg, cfg.n_points)
+    out = {}
+    for precision in ("fp32",):
+        plan = _plan(cfg, precision)
+        plan.set_states(d["E"], d["g"], d["J"])
+        plan.set_lines(d["upper"], d["lower"], logA, d["gamma_ref"], d["n_exp"])
+        g = torch.from_numpy(gbar).to("cuda", plan.dtype)
+        out[precision] = plan.cross_section_adjoint(1500.0, 0.1, g, cfg.n_lines)
+    torch.cuda.synchronize()
+    dlnA = out["fp32"][2].cpu().numpy()
+    # 32 seeded lines among those whose window meets the grid
+    E = d["E"]
+    nu = (E[d["upper"].long()] - E[d["lower"].long()]).cpu().numpy()
+    inside = np.nonzero((nu > cfg.nu_a - 25) & (nu < cfg.nu_b + 25))[0]
+    rng = np.random.default_rng(4)
+    lines = np.sort(rng.choice(inside, 32, replace=False))
+    h = {k: d[k].cpu().numpy() for k in ("E", "g", "upper", "lower", "gamma_ref", "n_exp")}
+    h["A"] = np.exp(logA.cpu().numpy().astype(np.float64))
+    ref = _oracle_adj(cfg, h, logA.cpu().numpy(), 1500.0, 0.1,
+                      torch.from_numpy(gbar).float().double().numpy(), lines=lines)
+    got = dlnA[lines]
+    rel = np.abs(got - ref["dlnA"]) / np.maximum(np.abs(ref["dlnA"]), 1e-6 * np.abs(ref["dlnA"]).max())
+    log(f"  C4 fp32 dlnA on 32 lines: max rel {rel.max():.3e}")
+    assert rel.max() <= 1e-4
