@@ -65,7 +65,10 @@ typedef enum {
     XS_DOPPLER = 0,      /* Gaussian with the Doppler HWHM of Eq. 16                      */
     XS_GAUSS_FIXED = 1,  /* Gaussian with a constant HWHM alpha_fixed (Eq. 15)            */
     XS_LORENTZ = 2,      /* Lorentzian with HWHM gamma_L of Eq. 18 (Eq. 17)               */
-    XS_VOIGT = 3         /* Voigt: Doppler (x) Lorentz (Eq. 19, normalised convolution)   */
+    XS_VOIGT = 3,        /* Voigt: Doppler (x) Lorentz (Eq. 19, normalised convolution)   */
+    XS_GH_SAMPLED = 4,   /* Voigt as a Gauss-Hermite sum of shifted Lorentzians (Eq. 30),
+                            sampled at the grid points                                   */
+    XS_GH_BINNED = 5     /* bin-averaged Gauss-Hermite Voigt, area-conserving (Eq. 31)   */
 } xs_profile;
 
 typedef enum {

@@ -45,7 +45,8 @@ __all__ = [
     "grid", "partition_function", "partition_function_dT", "line_centres", "intensities",
     "doppler_hwhm", "lorentz_hwhm", "gauss_profile", "lorentz_profile", "voigt_profile",
     "gh_sampled_profile", "gh_binned_profile", "window", "LineSet", "make_lineset",
-    "cross_section", "cross_section_at", "error_metrics", "voigt_adjoint", "PROFILES",
+    "cross_section", "cross_section_at", "error_metrics", "voigt_adjoint", "faddeeva_derivative",
+    "PROFILES",
 ]
 
 PROFILES = ("doppler", "gauss_fixed", "lorentz", "voigt", "gh_binned", "gh_sampled")
@@ -157,7 +158,8 @@ def gh_binned_profile(delta, alpha_d, gamma, dnu: float, n_gh: int = 30):
     """Bin-averaged Gauss-Hermite Voigt (Eq. 31 as read): per unit intensity
     1/(pi^(3/2) dnu) sum_j w_j [atan(y_j+) - atan(y_j-)],
     y_j+- = (delta - delta_j +- dnu/2)/gamma  (Eq. 29 with the minus sign restored).
-    gamma == 0 takes the step-function limit (a 30-point histogram)."""
+    The difference of arctangents is evaluated as atan2(y+ - y-, 1 + y+ y-), equal to it
+    for y+ > y-.  gamma == 0 takes the step-function limit (a 30-point histogram)."""
     delta = np.asarray(delta, np.float64)
     t, w = _gh_nodes(n_gh)
     gamma = np.broadcast_to(np.asarray(gamma, np.float64), np.broadcast(delta, alpha_d, gamma).shape)
@@ -168,9 +170,11 @@ def gh_binned_profile(delta, alpha_d, gamma, dnu: float, n_gh: int = 30):
         dj = alpha_d * tj / math.sqrt(LN2)
         lo = delta - dj - 0.5 * dnu
         hi = delta - dj + 0.5 * dnu
-        term = np.empty(gamma.shape)
         g = np.where(pos, gamma, 1.0)
-        term[...] = np.arctan(hi / g) - np.arctan(lo / g)
+        a, b = hi / g, lo / g
+        # atan(a) - atan(b) for a > b, as atan2(a - b, 1 + a b) (an exact identity that
+        # avoids cancelling two arctangents near +-pi/2 in the far wings)
+        term = np.arctan2(dnu / g, 1.0 + a * b)
         # gamma -> 0: atan(+-inf) steps; half weight when an edge sits on the node
         step = (np.sign(hi) - np.sign(lo)) * (math.pi / 2.0)
         out = out + wj * np.where(pos, term, step)
@@ -352,6 +356,29 @@ def error_metrics(sig_hat, sig, rel_floor: float = 1e-6):
 
 
 # ------------------------------------------------------------------------ adjoint
+def faddeeva_derivative(z):
+    """w'(z) for Im z >= 0.  |z| < 30: the identity w' = -2 z w + 2i/sqrt(pi) (loses at
+    most ~3.3 digits to cancellation there); |z| >= 30: the asymptotic series
+    w'(z) = -(i/sqrt(pi)) sum_k (2k+1)!! / (2^k z^(2k+2)), k = 0..14 (Abramowitz & Stegun
+    7.1.23 differentiated; the omitted terms are below 1e-22 relative), where the identity
+    would cancel ~log10|z|^2 digits."""
+    z = np.asarray(z, complex)
+    out = np.empty(z.shape, complex)
+    big = np.abs(z) >= 30.0
+    zs = z[~big]
+    out[~big] = -2.0 * zs * wofz(zs) + 2j / math.sqrt(math.pi)
+    zb = z[big]
+    if zb.size:
+        inv2 = 1.0 / (zb * zb)
+        term = inv2.copy()          # k = 0: 1/z^2
+        acc = term.copy()
+        for k in range(1, 15):
+            term = term * (2 * k + 1) / 2.0 * inv2
+            acc = acc + term
+        out[big] = -1j / math.sqrt(math.pi) * acc
+    return out
+
+
 def voigt_adjoint(E, g, upper, lower, A, gamma_ref, n_exp, T: float, P: float, mass_amu: float,
                   nu_a: float, nu_b: float, n_points: int, gbar, cutoff: float = 25.0,
                   T0: float = T0_REF, P0: float = P0_REF, index_base: int = 0):
@@ -360,7 +387,7 @@ def voigt_adjoint(E, g, upper, lower, A, gamma_ref, n_exp, T: float, P: float, m
     from differentiating Eq. 1, 2, 16, 18 and the Voigt profile).
 
     With z = x + iy, x = sqrt(ln2) D/alpha_D, y = sqrt(ln2) gamma/alpha_D,
-    W = w(z), W' = -2 z W + 2i/sqrt(pi), N = sqrt(ln2/pi)/alpha_D, phi = N Re W:
+    W = w(z), W' = dw/dz (faddeeva_derivative), N = sqrt(ln2/pi)/alpha_D, phi = N Re W:
         dphi/dgamma   = -N (sqrt(ln2)/alpha_D) Im W'
         dphi/dalpha_D = -(N/alpha_D) (Re W + Re(z W'))
     Per line: R0 = sum gbar phi, Rg = sum gbar dphi/dgamma, Ra = sum gbar dphi/dalpha.
@@ -388,7 +415,7 @@ def voigt_adjoint(E, g, upper, lower, A, gamma_ref, n_exp, T: float, P: float, m
         s = sq / aD
         z = D * s + 1j * ls.gamma[i] * s
         W = wofz(z)
-        Wp = -2.0 * z * W + 2j / math.sqrt(math.pi)
+        Wp = faddeeva_derivative(z)
         Nrm = math.sqrt(LN2 / math.pi) / aD
         phi = Nrm * W.real
         dphi_dg = -Nrm * s * Wp.imag

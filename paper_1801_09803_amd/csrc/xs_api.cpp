@@ -157,7 +157,7 @@ xs_status validate_opts(const xs_opts* o) {
     if (!(o->cutoff > 0.0) || !std::isfinite(o->cutoff)) return fail(XS_ERR_ARG, "cutoff must be > 0");
     if (!(o->mass_da > 0.0)) return fail(XS_ERR_ARG, "mass_da must be > 0");
     if (!(o->T0 > 0.0) || !(o->P0 > 0.0)) return fail(XS_ERR_ARG, "T0 and P0 must be > 0");
-    if (o->profile < XS_DOPPLER || o->profile > XS_VOIGT) return fail(XS_ERR_UNSUPPORTED, "unknown profile");
+    if (o->profile < XS_DOPPLER || o->profile > XS_GH_BINNED) return fail(XS_ERR_UNSUPPORTED, "unknown profile");
     if (o->precision != XS_FP64 && o->precision != XS_FP32) return fail(XS_ERR_ARG, "unknown precision");
     if (o->broadening < XS_BROAD_CONST || o->broadening > XS_BROAD_A0_JLOWER)
         return fail(XS_ERR_ARG, "unknown broadening scheme");
@@ -223,6 +223,11 @@ xs_status xs_plan_create(const xs_opts* opts, xs_plan** out) {
     xs::make_gh_pairs(4, &p->tabs.gh4);
     xs::make_gh_pairs(6, &p->tabs.gh6);
     xs::make_gh_pairs(12, &p->tabs.gh12);
+    xs::gauss_hermite_rule(xs::kGHConv, p->tabs.tconv, p->tabs.wconv);
+    for (int j = 0; j < xs::kGHConv; ++j) {
+        p->tabs.tconvf[j] = (float)p->tabs.tconv[j];
+        p->tabs.wconvf[j] = (float)p->tabs.wconv[j];
+    }
     if ((st = p->ensure(p->tab_dev, sizeof(xs::Tables), "quadrature tables")) != XS_OK) { delete p; return st; }
     {
         hipError_t e = hipMemcpy(p->tab_dev.p, &p->tabs, sizeof(xs::Tables), hipMemcpyHostToDevice);
@@ -480,7 +485,7 @@ xs_status xs_cross_section(xs_plan* p, int32_t n_tp, const double* T, const doub
         else if (o.profile == XS_GAUSS_FIXED) { xr = 10.5; alpha = o.alpha_fixed; }
         const double rmd = xr * alpha / (xs::kSQRT_LN2 * p->geo.dnu) + 2.0;
         tp.rm = rmd > 1.0e9 ? 1000000000 : (int)std::ceil(rmd);
-        a.seg = (!fp64 && 64.0 * p->P + rmd + 1.0 <= (double)p->geo.hmin) ? 1 : 0;
+        a.seg = (!fp64 && o.profile <= XS_VOIGT && 64.0 * p->P + rmd + 1.0 <= (double)p->geo.hmin) ? 1 : 0;
         a.sigma = static_cast<char*>(sigma) + (size_t)i * (size_t)p->geo.n_points * elem;
         if (core && p->n_kept > 0) {
             xs::CoreArgs c{};

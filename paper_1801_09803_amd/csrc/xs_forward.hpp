@@ -6,7 +6,7 @@
 
 namespace xs {
 
-enum ProfileKind { kDoppler = 0, kGaussFixed = 1, kLorentz = 2, kVoigt = 3 };
+enum ProfileKind { kDoppler = 0, kGaussFixed = 1, kLorentz = 2, kVoigt = 3, kGHSampled = 4, kGHBinned = 5 };
 
 struct FwdArgs {
     SortedLines L;

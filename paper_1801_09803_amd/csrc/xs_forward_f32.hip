@@ -132,6 +132,21 @@ __device__ __forceinline__ void prepare_line(const FwdArgs& A, const Geometry& G
         r[R_XC] = (float)xd;
         r[R_H] = (float)hd;
         r[R_AMP] = (float)(S * ig * (1.0 / kPI));
+    } else if (PROF == kGHSampled || PROF == kGHBinned) {
+        // Gauss-Hermite convolution (Eq. 30-31 as read): nodes shift the Lorentzian by
+        // delta_j = alpha_D t_j / sqrt(ln 2); work in wavenumber units D = nu_k - nu
+        r[R_XC] = (float)d;
+        r[R_H] = (float)G.dnu;
+        r[R_M + 0] = (float)(gam * gam);
+        r[R_M + 1] = (float)(aD / kSQRT_LN2);
+        if (PROF == kGHSampled) {
+            r[R_AMP] = (float)(S * gam / (kPI * 1.7724538509055160273));   // S gamma / pi^(3/2)
+            r[R_M + 2] = (float)(4.0 * gam * gam);
+        } else {
+            r[R_AMP] = (float)(S / (kPI * 1.7724538509055160273 * G.dnu));   // S / (pi^(3/2) dnu)
+            r[R_M + 3] = (float)(G.dnu * gam);
+            r[R_M + 4] = (float)(gam * gam - 0.25 * G.dnu * G.dnu);
+        }
     } else {
         // Gaussian (Eq. 15); x scaled by sqrt(1/ln 2) so exp(-x^2) = exp2(-x'^2)
         const double alpha = (PROF == kDoppler) ? aD : A.alpha_fixed;
@@ -168,8 +183,10 @@ __device__ __forceinline__ void prepare_line(const FwdArgs& A, const Geometry& G
                 if (PROF == kVoigt) {
                     if (kA <= kch && kB >= kcl) zone = 3;
                     else if (rad >= 0 && (int64_t)kA <= (int64_t)w.kc + rad && (int64_t)kB >= (int64_t)w.kc - rad) zone = 2;
-                } else if (PROF == kLorentz) {
+                } else if (PROF == kLorentz || PROF == kGHSampled) {
                     zone = gam > 0.0 ? 1u : 0u;
+                } else if (PROF == kGHBinned) {
+                    zone = 1u;
                 } else {
                     zone = ((int64_t)kA <= (int64_t)w.kc + rad && (int64_t)kB >= (int64_t)w.kc - rad) ? 1u : 0u;
                 }
@@ -217,6 +234,37 @@ __device__ __forceinline__ float v_core(const FwdArgs& A, const float* r, float 
 __device__ __forceinline__ float v_lor(const float* r, float j) {
     const float x = __builtin_fmaf(j, r[R_H], r[R_XC]);
     return r[R_AMP] * __builtin_amdgcn_rcpf(__builtin_fmaf(x, x, 1.0f));
+}
+
+// Gauss-Hermite sum of shifted Lorentzians, node pairs +-t_j:
+// L(D - dj) + L(D + dj) = (gamma/pi) 2 (D^2 + g^2 + dj^2) / ((D^2 + g^2 - dj^2)^2 + 4 dj^2 g^2)
+__device__ __forceinline__ float v_ghs(const Tables* tab, const float* r, float j) {
+    const float D = __builtin_fmaf(j, r[R_H], r[R_XC]);
+    const float g2 = r[R_M + 0], ad = r[R_M + 1], g4 = r[R_M + 2];
+    const float D2 = __builtin_fmaf(D, D, g2);
+    float acc = 0.0f;
+#pragma unroll
+    for (int q = 0; q < kGHConv / 2; ++q) {
+        const float t = tab->tconvf[kGHConv / 2 + q];
+        const float dj = ad * t;
+        const float d2 = dj * dj;
+        const float p = D2 - d2;
+        const float den = __builtin_fmaf(p, p, g4 * d2);
+        acc = __builtin_fmaf(2.0f * tab->wconvf[kGHConv / 2 + q] * (D2 + d2), __builtin_amdgcn_rcpf(den), acc);
+    }
+    return r[R_AMP] * acc;
+}
+
+// bin-averaged Gauss-Hermite Voigt: atan(y+) - atan(y-) = atan2(dnu g, (D - dj)^2 + g^2 - dnu^2/4)
+__device__ __forceinline__ float v_ghb(const Tables* tab, const float* r, float j) {
+    const float D = __builtin_fmaf(j, r[R_H], r[R_XC]);
+    const float ad = r[R_M + 1], hg = r[R_M + 3], c = r[R_M + 4];
+    float acc = 0.0f;
+    for (int q = 0; q < kGHConv; ++q) {
+        const float e = D - ad * tab->tconvf[q];
+        acc = __builtin_fmaf(tab->wconvf[q], atan2f(hg, __builtin_fmaf(e, e, c)), acc);
+    }
+    return r[R_AMP] * acc;
 }
 
 __device__ __forceinline__ float v_gauss(const float* r, float j) {
@@ -405,6 +453,10 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
                             else v = v_core(A, r, j, w0 + 64 * p + lane);
                         } else if (PROF == kLorentz) {
                             v = v_lor(r, j);
+                        } else if (PROF == kGHSampled) {
+                            v = v_ghs(A.tab, r, j);
+                        } else if (PROF == kGHBinned) {
+                            v = v_ghb(A.tab, r, j);
                         } else {
                             v = v_gauss(r, j);
                         }
@@ -438,7 +490,7 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
 template <int PROF, int WAVES, int P>
 void launch_one(const FwdArgs& a, hipStream_t s) {
     const dim3 grid(a.n_tiles), block(64 * WAVES);
-    if (a.seg) hipLaunchKernelGGL((fwd_f32_kernel<PROF, WAVES, P, true>), grid, block, 0, s, a);
+    if (PROF <= kVoigt && a.seg) hipLaunchKernelGGL((fwd_f32_kernel<PROF, WAVES, P, PROF <= kVoigt>), grid, block, 0, s, a);
     else hipLaunchKernelGGL((fwd_f32_kernel<PROF, WAVES, P, false>), grid, block, 0, s, a);
 }
 
@@ -467,6 +519,8 @@ hipError_t launch_forward_f32(int profile, int waves, int P, const FwdArgs& a, h
         case kDoppler: launch_p<kDoppler>(waves, P, a, s); break;
         case kGaussFixed: launch_p<kGaussFixed>(waves, P, a, s); break;
         case kLorentz: launch_p<kLorentz>(waves, P, a, s); break;
+        case kGHSampled: launch_p<kGHSampled>(waves, P, a, s); break;
+        case kGHBinned: launch_p<kGHBinned>(waves, P, a, s); break;
         default: launch_p<kVoigt>(waves, P, a, s); break;
     }
     return hipGetLastError();

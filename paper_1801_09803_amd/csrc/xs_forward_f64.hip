@@ -11,7 +11,7 @@ namespace {
 
 constexpr int kRec = 32;
 constexpr int kBatch = 256;
-enum : int { D_NU = 0, D_S = 1, D_Y = 2, D_A = 3, D_CODE = 4, D_KLIM = 5 };
+enum : int { D_NU = 0, D_S = 1, D_Y = 2, D_A = 3, D_CODE = 4, D_KLIM = 5, D_AD = 6 };
 
 // ============================================================== FP64 path
 template <int PROF, int P>
@@ -52,6 +52,13 @@ __global__ __launch_bounds__(256) void fwd_f64_kernel(const FwdArgs A) {
             } else if (PROF == kLorentz) {
                 s = ls.gam > 0.0 ? 1.0 / ls.gam : 0.0;
                 r[D_A] = ls.S * s * (1.0 / kPI);
+            } else if (PROF == kGHSampled || PROF == kGHBinned) {
+                // Gauss-Hermite convolution in wavenumber units (x = D, y = gamma)
+                s = 1.0;
+                y = ls.gam;
+                r[D_AD] = ls.aD / kSQRT_LN2;
+                r[D_A] = (PROF == kGHSampled) ? ls.S * ls.gam / (kPI * 1.7724538509055160273)
+                                              : ls.S / (kPI * 1.7724538509055160273 * G.dnu);
             } else {
                 const double alpha = (PROF == kDoppler) ? ls.aD : A.alpha_fixed;
                 s = kSQRT_LN2 / alpha;
@@ -75,8 +82,10 @@ __global__ __launch_bounds__(256) void fwd_f64_kernel(const FwdArgs A) {
                         const double z2 = mx * mx + y * y;
                         zone = z2 < 64.0 * 1.0001 ? 5u : z2 < 400.0 * 1.0001 ? 4u
                              : z2 < 3600.0 * 1.0001 ? 3u : z2 < 4.84e6 * 1.0001 ? 2u : 1u;
-                    } else if (PROF == kLorentz) {
+                    } else if (PROF == kLorentz || PROF == kGHSampled) {
                         zone = ls.gam > 0.0 ? 1u : 0u;
+                    } else if (PROF == kGHBinned) {
+                        zone = 1u;
                     } else {
                         zone = (mx * mx < 745.0) ? 1u : 0u;   // exp(-x^2) underflows beyond
                     }
@@ -123,6 +132,29 @@ __global__ __launch_bounds__(256) void fwd_f64_kernel(const FwdArgs A) {
                     v *= a;
                 } else if (PROF == kLorentz) {
                     v = a * rcp64(__builtin_fma(x, x, 1.0));
+                } else if (PROF == kGHSampled) {
+                    // node pairs: L(D - dj) + L(D + dj) ~ 2 (D^2 + g^2 + dj^2) / ((D^2 + g^2 - dj^2)^2 + 4 dj^2 g^2)
+                    const double ad = r[D_AD], g2 = y * y;
+                    const double D2 = __builtin_fma(x, x, g2);
+                    double accg = 0.0;
+                    for (int q = 0; q < kGHConv / 2; ++q) {
+                        const double dj = ad * A.tab->tconv[kGHConv / 2 + q];
+                        const double d2 = dj * dj;
+                        const double pq = D2 - d2;
+                        accg = __builtin_fma(2.0 * A.tab->wconv[kGHConv / 2 + q] * (D2 + d2),
+                                             rcp64(__builtin_fma(pq, pq, 4.0 * g2 * d2)), accg);
+                    }
+                    v = a * accg;
+                } else if (PROF == kGHBinned) {
+                    // atan(y+) - atan(y-) = atan2(dnu g, (D - dj)^2 + g^2 - dnu^2/4)
+                    const double ad = r[D_AD];
+                    const double hg = G.dnu * y, c = y * y - 0.25 * G.dnu * G.dnu;
+                    double accg = 0.0;
+                    for (int q = 0; q < kGHConv; ++q) {
+                        const double e = x - ad * A.tab->tconv[q];
+                        accg = __builtin_fma(A.tab->wconv[q], atan2(hg, __builtin_fma(e, e, c)), accg);
+                    }
+                    v = a * accg;
                 } else {
                     v = a * exp(-x * x);
                 }
@@ -159,6 +191,8 @@ hipError_t launch_forward(int profile, int fp64, int waves, int P, const FwdArgs
         case kDoppler: launch_p64<kDoppler>(P, a, s); break;
         case kGaussFixed: launch_p64<kGaussFixed>(P, a, s); break;
         case kLorentz: launch_p64<kLorentz>(P, a, s); break;
+        case kGHSampled: launch_p64<kGHSampled>(P, a, s); break;
+        case kGHBinned: launch_p64<kGHBinned>(P, a, s); break;
         default: launch_p64<kVoigt>(P, a, s); break;
     }
     return hipGetLastError();

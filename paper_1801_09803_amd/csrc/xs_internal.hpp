@@ -79,10 +79,13 @@ struct WeidemanCoef {
 
 // All quadrature tables of a plan, kept in one device buffer and read by the kernels
 // through a uniform pointer (scalar loads).
+constexpr int kGHConv = 30;   // nodes of the Gauss-Hermite convolution profiles
 struct Tables {
     WeidemanCoef w24;   // FP32 path core
     WeidemanCoef w40;   // FP64 path core
     GHPairs gh2, gh4, gh6, gh12;
+    double tconv[kGHConv], wconv[kGHConv];   // full 30-node rule (nodes ascending)
+    float tconvf[kGHConv], wconvf[kGHConv];
 };
 
 // Host helpers implemented in xs_quadrature.cpp.

@@ -221,3 +221,29 @@ def test_invalid_transitions_report_errors():
     with pytest.raises(XsecError) as ei:
         plan.cross_section([-5.0], [1.0])
     assert ei.value.name == "XS_ERR_ARG"
+
+
+@pytest.mark.parametrize("profile", ["gh_sampled", "gh_binned"])
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("T,P", [(800.0, 0.5), (2500.0, 0.02)])
+def test_gauss_hermite_profiles(profile, precision, T, P):
+    cfg, d = _small_case(9, n_lines=1500)
+    h = host(d)
+    plan = make_plan(cfg, precision, profile=profile)
+    got = _run(plan, d, [T], [P])[0]
+    ls = oracle_lineset(h, cfg, T, P)
+    ref = O.cross_section(ls, cfg.nu_a, cfg.nu_b, cfg.n_points, cfg.cutoff, profile=profile, workers=1)
+    assert_parity(got, ref, TOL32 if precision == "fp32" else TOL64, what=f"{profile} {precision} T={T}")
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_gh_binned_pure_doppler_limit(precision):
+    # P = 0: each node becomes a delta function; the binned profile is a 30-point
+    # histogram of the Gaussian (the oracle's step-function limit)
+    cfg, d = _small_case(10, n_lines=1500)
+    h = host(d)
+    plan = make_plan(cfg, precision, profile="gh_binned")
+    got = _run(plan, d, [1000.0], [0.0])[0]
+    ls = oracle_lineset(h, cfg, 1000.0, 0.0)
+    ref = O.cross_section(ls, cfg.nu_a, cfg.nu_b, cfg.n_points, cfg.cutoff, profile="gh_binned", workers=1)
+    assert_parity(got, ref, TOL32 if precision == "fp32" else TOL64, what=f"gh_binned P=0 {precision}")

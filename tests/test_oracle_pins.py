@@ -300,3 +300,35 @@ def test_error_metrics():
     ref = np.array([1.0, 1e-3, 1e-8, 0.0])
     m = O.error_metrics(ref * (1 + np.array([1e-6, -2e-6, 0.5, 0.0])), ref)
     assert abs(m["max_rel"] - 2e-6) < 1e-12 and m["n_checked"] == 2
+
+
+def test_gh_binned_arctangent_difference_identity():
+    # the oracle's atan2 form equals atan(y+) - atan(y-) evaluated in 50-digit arithmetic,
+    # including far wings where the two arctangents nearly cancel
+    mpmath.mp.dps = 50
+    t, w = np.polynomial.hermite.hermgauss(30)
+    for delta, aD, gam, dnu in ((3e-4, 0.02, 0.03, 0.01), (24.9, 0.03, 0.002, 0.01), (-7.3, 0.5, 0.1, 1.0),
+                                (0.0, 1e-4, 1e-5, 0.01)):
+        ref = mpmath.mpf(0)
+        for tj, wj in zip(t, w):
+            dj = mpmath.mpf(aD) * tj / mpmath.sqrt(mpmath.log(2))
+            hi = (mpmath.mpf(delta) - dj + mpmath.mpf(dnu) / 2) / gam
+            lo = (mpmath.mpf(delta) - dj - mpmath.mpf(dnu) / 2) / gam
+            ref += wj * (mpmath.atan(hi) - mpmath.atan(lo))
+        ref = ref / (mpmath.pi ** 1.5 * dnu)
+        got = O.gh_binned_profile(np.array([delta]), aD, gam, dnu)[0]
+        assert abs(got - float(ref)) <= 1e-12 * abs(float(ref))
+    mpmath.mp.dps = 15
+
+
+def test_faddeeva_derivative_against_mpmath():
+    # w'(z) = -2 z w(z) + 2i/sqrt(pi) evaluated in 60-digit arithmetic
+    mpmath.mp.dps = 60
+    for z in (0.5 + 0.1j, 5.0 + 1e-6j, 29.0 + 3.0j, 31.0 + 0.01j, 800.0 + 2.0j, 3e5 + 10.0j, 1e-3 + 45.0j,
+              -40.0 + 1e-3j):
+        zm = mpmath.mpc(z)
+        w = mpmath.exp(-zm * zm) * mpmath.erfc(-1j * zm)
+        ref = complex(-2 * zm * w + 2j / mpmath.sqrt(mpmath.pi))
+        got = O.faddeeva_derivative(np.array([z]))[0]
+        assert abs(got - ref) <= 1e-12 * abs(ref), (z, got, ref)
+    mpmath.mp.dps = 15
