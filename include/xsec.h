@@ -46,9 +46,10 @@
 extern "C" {
 #endif
 
-#define XS_ABI_VERSION 1
+#define XS_ABI_VERSION 2
 
 typedef struct xs_plan xs_plan;
+typedef struct xs_graph xs_graph;
 
 typedef enum {
     XS_OK = 0,
@@ -102,7 +103,14 @@ typedef struct {
     int32_t waves_per_block; /* tile shape: wavefronts per workgroup for XS_FP32 (4 or 8);
                                 0 = library default (4); XS_FP64 always uses 4           */
     int32_t a_is_log;        /* 1: the A array given to xs_set_lines holds ln A (s^-1)    */
-    int32_t reserved[5];
+    int32_t n_split;         /* workgroups sharing one tile (each sums an equal share of the
+                                tile's lines; a fixed-order compensated pass adds the shares):
+                                1..64, or 0 = chosen per call from the grid and line counts */
+    int32_t tp_block;        /* (T, P) points per forward launch (workgroups of one tile for
+                                consecutive (T, P) run back to back): 1..256, or 0 = chosen
+                                per call (8, fewer when the FP32 Voigt core rows of
+                                16 B per line and (T, P) would exceed 16 GiB)            */
+    int32_t reserved[3];
 } xs_opts;
 
 /* Fill *opts with defaults: cutoff 25, T0 296 K, P0 1 bar, Voigt, FP32, per-line
@@ -152,9 +160,54 @@ xs_status xs_partition_function(xs_plan* plan, int32_t n_T, const double* T, dou
 /* Cross sections for n_tp (T, P) pairs (Eq. 6-8 with the sampling method).
  * T, P: host double[n_tp] (T > 0, P >= 0; P = 0 gives the pure Doppler limit).
  * sigma: device array [n_tp][n_points], nu fastest; float for XS_FP32, double for
- * XS_FP64.  The result overwrites sigma. */
+ * XS_FP64.  The result overwrites sigma.  The (T, P) points are processed in blocks
+ * of tp_block, each block in one forward launch that makes one pass over the sorted
+ * lines per tile.  XS_FP32 with XS_VOIGT waits on `stream` once per block (to size the
+ * buffer of its double-precision core values); otherwise the call does not wait.
+ * The result of a (T, P) point does not depend on the other points of the call. */
 xs_status xs_cross_section(xs_plan* plan, int32_t n_tp, const double* T, const double* P,
                            void* sigma, void* stream);
+
+/* Graph capture of xs_cross_section (the batching extension: a whole (T, P) grid from
+ * one recorded launch sequence, replayed without host work or waits).
+ * xs_graph_create records the sequence for n_tp (T, P) points (host arrays, as for
+ * xs_cross_section) writing into the device array sigma [n_tp][n_points] (kept by
+ * the graph: it must stay allocated while the graph is used).  The graph owns its
+ * own workspace (xs_graph_workspace_bytes), sized from a bound that holds for every
+ * temperature up to the captured one, so the recording involves waits and allocation
+ * but a replay involves neither.  SYNCHRONOUS.  *out receives the graph.
+ * xs_graph_launch replays it on `stream`; it returns XS_ERR_STATE once the plan's
+ * states, lines or tile configuration have changed since the capture.
+ * xs_graph_set_tp replaces the (T, P) values used by later replays (enqueued on
+ * `stream`, ordered with replays on the same stream); each new T must be > 0 and
+ * <= the T captured at its position (XS_ERR_ARG otherwise), P >= 0.
+ * xs_graph_destroy waits for the device and frees the graph (NULL accepted); destroy
+ * graphs before their plan. */
+xs_status xs_graph_create(xs_plan* plan, int32_t n_tp, const double* T, const double* P,
+                          void* sigma, xs_graph** out);
+xs_status xs_graph_set_tp(xs_graph* graph, const double* T, const double* P, void* stream);
+xs_status xs_graph_launch(xs_graph* graph, void* stream);
+xs_status xs_graph_destroy(xs_graph* graph);
+size_t xs_graph_workspace_bytes(const xs_graph* graph);
+
+/* Tile configuration of the forward launches: wavefronts per workgroup (4, or 8 for
+ * XS_FP32), 64-point slices per wavefront (1, 2, 4), n_split and tp_block as in
+ * xs_opts; 0 selects the default.  SYNCHRONOUS (waits for the device, then rebuilds
+ * the tile dispatch order).  Invalidates captured graphs.
+ * xs_get_tile_config writes {waves, slices, n_split, tp_block, n_split and tp_block
+ * used by the last xs_cross_section}. */
+xs_status xs_set_tile_config(xs_plan* plan, int32_t waves, int32_t slices, int32_t n_split,
+                             int32_t tp_block);
+xs_status xs_get_tile_config(const xs_plan* plan, int32_t out[6]);
+
+/* Autotuner of the tile configuration (the batching extension).  Times the forward
+ * launches (and the split combine) over the first min(n_tp, 16) (T, P) points for
+ * every (waves, slices, n_split) candidate, then tp_block for the best of them, each
+ * twice, until budget_ms of wall time is spent (the first candidate always runs), and
+ * keeps the fastest per (T, P).  out (host int32[4] or NULL) receives {waves, slices,
+ * n_split, tp_block}.  SYNCHRONOUS; uses plan workspace; invalidates captured graphs. */
+xs_status xs_autotune(xs_plan* plan, int32_t n_tp, const double* T, const double* P,
+                      double budget_ms, void* stream, int32_t out[4]);
 
 /* Adjoint of xs_cross_section for one (T, P) with the Voigt profile (not in the paper:
  * the derivative of Eq. 1, 2, 16, 18 and of the Voigt profile).  Given dL/dsigma on the
@@ -171,18 +224,23 @@ xs_status xs_cross_section_adjoint(xs_plan* plan, double T, double P, const void
                                    void* dL_dgamma_ref, void* dL_dn, void* stream);
 
 /* Kernel timing (tracing).  While enabled, every launch of the forward tile kernel,
- * of the double-precision Voigt core pre-pass and of the line preparation (prep,
- * sort, gather) is bracketed by hipEvents recorded on the call's stream.
+ * of the split combine, of the double-precision Voigt core pre-pass and of the line
+ * preparation (prep, sort, gather) is bracketed by hipEvents recorded on the call's
+ * stream (graph replays are not recorded).
  * xs_set_timing(plan, 1) clears the accumulated times and enables recording;
  * xs_set_timing(plan, 0) stops it.  xs_kernel_times waits for the recorded events
  * (synchronous) and returns the accumulated milliseconds and launch counts. */
 typedef struct {
-    double forward_ms;          /* tile kernels (one launch per (T, P))                    */
+    double forward_ms;          /* tile kernels (one launch per block of (T, P)), and the
+                                   adjoint kernel                                          */
     double core_ms;             /* Voigt core pre-pass (count + evaluation)                */
     double prep_ms;             /* xs_set_lines device work                                */
     int64_t forward_launches;
     int64_t core_launches;
     int64_t prep_launches;
+    double combine_ms;          /* sums of split tiles (n_split > 1)                       */
+    int64_t combine_launches;
+    int64_t forward_tp;         /* (T, P) results computed by the forward launches         */
 } xs_timings;
 
 xs_status xs_set_timing(xs_plan* plan, int enable);

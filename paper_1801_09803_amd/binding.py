@@ -34,14 +34,16 @@ class XsOpts(ctypes.Structure):
         ("broadening", ctypes.c_int32), ("index_base", ctypes.c_int32),
         ("alpha_fixed", ctypes.c_double), ("gamma_const", ctypes.c_double), ("n_const", ctypes.c_double),
         ("slices_per_wave", ctypes.c_int32), ("waves_per_block", ctypes.c_int32),
-        ("a_is_log", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5),
+        ("a_is_log", ctypes.c_int32), ("n_split", ctypes.c_int32), ("tp_block", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 3),
     ]
 
 
 class XsKernelTimes(ctypes.Structure):
     _fields_ = [("forward_ms", ctypes.c_double), ("core_ms", ctypes.c_double), ("prep_ms", ctypes.c_double),
                 ("forward_launches", ctypes.c_int64), ("core_launches", ctypes.c_int64),
-                ("prep_launches", ctypes.c_int64)]
+                ("prep_launches", ctypes.c_int64), ("combine_ms", ctypes.c_double),
+                ("combine_launches", ctypes.c_int64), ("forward_tp", ctypes.c_int64)]
 
 
 _lib = None
@@ -73,6 +75,14 @@ def load_library() -> ctypes.CDLL:
         "xs_partition_function": (i32, [P, i32, P, P, P, P]),
         "xs_cross_section": (i32, [P, i32, P, P, P, P]),
         "xs_cross_section_adjoint": (i32, [P, dbl, dbl, P, P, P, P, P, P, P]),
+        "xs_graph_create": (i32, [P, i32, P, P, P, ctypes.POINTER(P)]),
+        "xs_graph_set_tp": (i32, [P, P, P, P]),
+        "xs_graph_launch": (i32, [P, P]),
+        "xs_graph_destroy": (i32, [P]),
+        "xs_graph_workspace_bytes": (ctypes.c_size_t, [P]),
+        "xs_set_tile_config": (i32, [P, i32, i32, i32, i32]),
+        "xs_get_tile_config": (i32, [P, ctypes.POINTER(i32)]),
+        "xs_autotune": (i32, [P, i32, P, P, dbl, P, ctypes.POINTER(i32)]),
         "xs_set_timing": (i32, [P, i32]),
         "xs_kernel_times": (i32, [P, ctypes.POINTER(XsKernelTimes)]),
         "xs_workspace_bytes": (ctypes.c_size_t, [P]),
@@ -114,7 +124,7 @@ class Plan:
                  broadening: str = "per_line", T0: float = 296.0, P0: float = 1.0,
                  index_base: int = 0, alpha_fixed: float = 0.0, gamma_const: float = 0.0,
                  n_const: float = 0.0, slices_per_wave: int = 0, waves_per_block: int = 0,
-                 a_is_log: bool = False):
+                 a_is_log: bool = False, n_split: int = 0, tp_block: int = 0):
         import torch
         self._torch = torch
         lib = load_library()
@@ -130,6 +140,8 @@ class Plan:
         o.slices_per_wave = int(slices_per_wave)
         o.waves_per_block = int(waves_per_block)
         o.a_is_log = 1 if a_is_log else 0
+        o.n_split = int(n_split)
+        o.tp_block = int(tp_block)
         h = ctypes.c_void_p()
         _check(lib.xs_plan_create(ctypes.byref(o), ctypes.byref(h)))
         self._lib = lib
@@ -237,6 +249,28 @@ class Plan:
                                                   _ptr(dP), _ptr(dlnA), _ptr(dg), _ptr(dn), self._stream()))
         return dT, dP, dlnA, dg, dn
 
+    def set_tile_config(self, waves: int = 0, slices: int = 0, n_split: int = 0, tp_block: int = 0):
+        _check(self._lib.xs_set_tile_config(self._h, int(waves), int(slices), int(n_split), int(tp_block)))
+
+    def tile_config(self) -> dict:
+        out = (ctypes.c_int32 * 6)()
+        _check(self._lib.xs_get_tile_config(self._h, out))
+        return dict(waves=out[0], slices=out[1], n_split=out[2], tp_block=out[3], last_split=out[4],
+                    last_block=out[5])
+
+    def autotune(self, T: Sequence[float], P: Sequence[float], budget_ms: float = 2000.0) -> dict:
+        T, P = list(T), list(P)
+        if len(T) != len(P):
+            raise ValueError("T and P differ in length")
+        out = (ctypes.c_int32 * 4)()
+        _check(self._lib.xs_autotune(self._h, len(T), _host_doubles(T), _host_doubles(P), float(budget_ms),
+                                     self._stream(), out))
+        return dict(waves=out[0], slices=out[1], n_split=out[2], tp_block=out[3])
+
+    def graph(self, T: Sequence[float], P: Sequence[float], out=None) -> "Graph":
+        """Capture the cross-section launch sequence for these (T, P) into `out`."""
+        return Graph(self, T, P, out)
+
     def set_timing(self, enable: bool = True):
         _check(self._lib.xs_set_timing(self._h, 1 if enable else 0))
 
@@ -247,3 +281,52 @@ class Plan:
 
     def workspace_bytes(self) -> int:
         return int(self._lib.xs_workspace_bytes(self._h))
+
+
+class Graph:
+    """A captured xs_cross_section sequence; `sigma` is the output it writes on replay."""
+
+    def __init__(self, plan: Plan, T: Sequence[float], P: Sequence[float], out=None):
+        torch = plan._torch
+        T, P = list(T), list(P)
+        if len(T) != len(P):
+            raise ValueError("T and P differ in length")
+        if out is None:
+            out = torch.empty((len(T), plan.n_points), dtype=plan.dtype, device="cuda")
+        else:
+            out = plan._dev(out, plan.dtype, "out")
+            if out.numel() != len(T) * plan.n_points:
+                raise ValueError("out has the wrong size")
+        torch.cuda.synchronize()
+        h = ctypes.c_void_p()
+        _check(plan._lib.xs_graph_create(plan._h, len(T), _host_doubles(T), _host_doubles(P), _ptr(out),
+                                         ctypes.byref(h)))
+        self._plan = plan
+        self._lib = plan._lib
+        self._h = h
+        self.n_tp = len(T)
+        self.sigma = out
+
+    def set_tp(self, T: Sequence[float], P: Sequence[float]):
+        T, P = list(T), list(P)
+        if len(T) != self.n_tp or len(P) != self.n_tp:
+            raise ValueError("T and P must keep the captured length")
+        _check(self._lib.xs_graph_set_tp(self._h, _host_doubles(T), _host_doubles(P), self._plan._stream()))
+
+    def launch(self):
+        _check(self._lib.xs_graph_launch(self._h, self._plan._stream()))
+        return self.sigma
+
+    def workspace_bytes(self) -> int:
+        return int(self._lib.xs_graph_workspace_bytes(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.xs_graph_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

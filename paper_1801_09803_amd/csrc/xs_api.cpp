@@ -1,15 +1,18 @@
-// C ABI of libxsec: plan object, argument validation, workspace, launch sequencing.
+// C ABI of libxsec: plan object, argument validation, workspace, launch sequencing of
+// the batched cross-section pipeline, its graph capture, and the tile-shape autotuner.
 #include "../../include/xsec.h"
 #include "xs_internal.hpp"
 #include "xs_lineprep.hpp"
 #include "xs_forward.hpp"
 #include "xs_adjoint.hpp"
 
+#include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <new>
 #include <string>
-#include <algorithm>
 #include <utility>
 #include <vector>
 
@@ -32,27 +35,130 @@ xs_status hip_fail(hipError_t e, const char* where) {
         if (e_ != hipSuccess) return hip_fail(e_, #call);     \
     } while (0)
 
+#define XS_TRY(call)                                          \
+    do {                                                      \
+        xs_status s_ = (call);                                \
+        if (s_ != XS_OK) return s_;                           \
+    } while (0)
+
 struct DevBuf {
     void* p = nullptr;
     size_t bytes = 0;
 };
 
+void dev_release(DevBuf& b, size_t* total) {
+    if (b.p) { (void)hipFree(b.p); *total -= b.bytes; }
+    b.p = nullptr;
+    b.bytes = 0;
+}
+
+// Device allocation with accounting; a buffer is only replaced when it must grow.
+xs_status dev_ensure(DevBuf& b, size_t bytes, const char* what, size_t* total) {
+    if (bytes == 0) bytes = 16;
+    if (b.p && b.bytes >= bytes) return XS_OK;
+    dev_release(b, total);
+    hipError_t e = hipMalloc(&b.p, bytes);
+    if (e != hipSuccess) {
+        b.p = nullptr;
+        (void)hipGetLastError();
+        return fail(XS_ERR_OOM, std::string("device allocation failed for ") + what + " (" +
+                                    std::to_string(bytes) + " bytes)");
+    }
+    b.bytes = bytes;
+    *total += bytes;
+    return XS_OK;
+}
+
+// Pinned host staging buffer for the small per-call copies (temperatures, per-(T, P)
+// parameters, count read-back).  Copies from it are asynchronous, so it is rewritten
+// only after the event recorded behind the last copy has completed.
+struct Stage {
+    void* h = nullptr;
+    size_t cap = 0;
+    hipEvent_t ev = nullptr;
+    bool pending = false;
+
+    xs_status get(size_t bytes, void** out) {
+        if (pending) {
+            XS_HIP(hipEventSynchronize(ev));
+            pending = false;
+        }
+        if (bytes > cap) {
+            if (h) (void)hipHostFree(h);
+            h = nullptr;
+            cap = 0;
+            XS_HIP(hipHostMalloc(&h, bytes, hipHostMallocDefault));
+            cap = bytes;
+        }
+        if (!ev) XS_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        *out = h;
+        return XS_OK;
+    }
+    xs_status record(hipStream_t s) {
+        XS_HIP(hipEventRecord(ev, s));
+        pending = true;
+        return XS_OK;
+    }
+    void release() {
+        if (pending) (void)hipEventSynchronize(ev);
+        pending = false;
+        if (h) (void)hipHostFree(h);
+        if (ev) (void)hipEventDestroy(ev);
+        h = nullptr;
+        ev = nullptr;
+        cap = 0;
+    }
+};
+
+// Device buffers of the batched cross-section pipeline: one set per plan for direct
+// calls and one per captured graph (a graph replays against its own buffers).
+struct Workset {
+    DevBuf T, Q, dQ, qpart;   // temperatures of the call, Q(T), dQ/dT, partial sums
+    DevBuf tps;               // xs::TPParam per (T, P) of the call
+    DevBuf rc, cnt, coff;     // core pre-pass rows [tp_block][n_kept]
+    DevBuf bsum, tmp;         // per row: core count block sums, scan scratch
+    DevBuf val;               // core values of one block of (T, P)
+    DevBuf part;              // per-part sums [tp_block][n_split][n_points] when n_split > 1
+    DevBuf out;               // autotuner output scratch
+    size_t bytes = 0;
+    Stage stage;
+    int rows = 0;             // core rows allocated
+    int64_t row_stride = 0;
+
+    xs_status ensure(DevBuf& b, size_t n, const char* what) { return dev_ensure(b, n, what, &bytes); }
+    void release() {
+        DevBuf* all[] = {&T, &Q, &dQ, &qpart, &tps, &rc, &cnt, &coff, &bsum, &tmp, &val, &part, &out};
+        for (DevBuf* b : all) dev_release(*b, &bytes);
+        stage.release();
+        rows = 0;
+        row_stride = 0;
+    }
+};
+
+constexpr int kScanTmp = 4096 + 16;   // u64 scan scratch per core row (total at [4096])
+
 }  // namespace
 
 struct TimedRange {
     hipEvent_t a, b;
-    int kind;   // 0 forward, 1 core, 2 prep
+    int kind;   // 0 forward, 1 core, 2 prep, 3 combine
+    int ntp;    // (T, P) results covered (forward launches)
 };
 
 struct xs_plan {
     xs_opts o{};
     bool timing = false;
     std::vector<TimedRange> timed;
-    double acc_ms[3] = {0, 0, 0};
-    int64_t acc_n[3] = {0, 0, 0};
+    double acc_ms[4] = {0, 0, 0, 0};
+    int64_t acc_n[4] = {0, 0, 0, 0};
+    int64_t acc_tp = 0;
     xs::Geometry geo{};
     int P = 2;
     int waves = 4;
+    int n_split = 0;        // 0: chosen per call
+    int tp_block = 0;       // 0: chosen per call
+    int last_split = 0, last_block = 0;
+    uint64_t generation = 1;   // bumped whenever captured graphs become invalid
     size_t total_bytes = 0;
 
     // states
@@ -68,42 +174,25 @@ struct xs_plan {
     DevBuf s_nu, s_elow, s_cA, s_gref, s_nexp, s_kc, s_klo, s_khi, s_orig;
     DevBuf k1, v1, k2, v2, hist, hoff, tsum;
     DevBuf off, flag;
-    // FP32 Voigt core pre-pass
-    DevBuf core_rc, core_cnt, core_bsum, core_off, core_val, core_tmp;
     DevBuf adj_pT, adj_pP, adj_part;
     int xcd_contiguous = 0;
     int lpt_order = 1;
     DevBuf tile_order;
-    int n_order = 0;
+    int n_order = 0, order_W = 0;
+    std::vector<int> off_host;     // offsets table (host copy) for tile costs
     uint32_t* sorted_keys = nullptr;
-    // partition function
+    // partition function (xs_partition_function and the adjoint)
     int q_cap = 0;
     DevBuf T_dev, Q, dQ, qpart;
     static constexpr int kQBlocks = 256;
+    // batched cross-section pipeline of direct calls
+    Workset ws;
     // tables
     xs::Tables tabs{};
     DevBuf tab_dev;
 
-    void release(DevBuf& b) {
-        if (b.p) { (void)hipFree(b.p); total_bytes -= b.bytes; }
-        b.p = nullptr;
-        b.bytes = 0;
-    }
-    xs_status ensure(DevBuf& b, size_t bytes, const char* what) {
-        if (bytes == 0) bytes = 16;
-        if (b.p && b.bytes >= bytes) return XS_OK;
-        release(b);
-        hipError_t e = hipMalloc(&b.p, bytes);
-        if (e != hipSuccess) {
-            b.p = nullptr;
-            (void)hipGetLastError();
-            return fail(XS_ERR_OOM, std::string("device allocation failed for ") + what + " (" +
-                                        std::to_string(bytes) + " bytes)");
-        }
-        b.bytes = bytes;
-        total_bytes += bytes;
-        return XS_OK;
-    }
+    void release(DevBuf& b) { dev_release(b, &total_bytes); }
+    xs_status ensure(DevBuf& b, size_t bytes, const char* what) { return dev_ensure(b, bytes, what, &total_bytes); }
     void drop_timed() {
         for (auto& t : timed) { (void)hipEventDestroy(t.a); (void)hipEventDestroy(t.b); }
         timed.clear();
@@ -113,10 +202,22 @@ struct xs_plan {
         DevBuf* all[] = {&E, &g, &J, &tab_g, &tab_n, &p_nu, &p_elow, &p_cA, &p_gref, &p_nexp, &p_kc,
                          &p_klo, &p_khi, &s_nu, &s_elow, &s_cA, &s_gref, &s_nexp, &s_kc, &s_klo,
                          &s_khi, &s_orig, &k1, &v1, &k2, &v2, &hist, &hoff, &tsum, &off, &flag,
-                         &T_dev, &Q, &dQ, &qpart, &tab_dev, &core_rc, &core_cnt, &core_bsum,
-                         &core_off, &core_val, &core_tmp, &tile_order, &adj_pT, &adj_pP, &adj_part};
+                         &T_dev, &Q, &dQ, &qpart, &tab_dev, &tile_order, &adj_pT, &adj_pP, &adj_part};
         for (DevBuf* b : all) release(*b);
+        ws.release();
     }
+};
+
+// A captured launch sequence of xs_cross_section for fixed (T, P) capacities.
+struct xs_graph {
+    xs_plan* p = nullptr;
+    uint64_t generation = 0;
+    int n_tp = 0;
+    std::vector<double> T_cap;
+    std::vector<xs::TPParam> tps;
+    Workset ws;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
 };
 
 namespace {
@@ -128,17 +229,20 @@ T* as(DevBuf& b) { return static_cast<T*>(b.p); }
 struct Timer {
     xs_plan* p;
     hipStream_t s;
-    int kind;
+    int kind, ntp;
     hipEvent_t a = nullptr, b = nullptr;
-    Timer(xs_plan* p_, hipStream_t s_, int k) : p(p_), s(s_), kind(k) {
-        if (p->timing && hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess)
+    Timer(xs_plan* p_, hipStream_t s_, int k, int ntp_ = 0, bool on = true) : p(p_), s(s_), kind(k), ntp(ntp_) {
+        if (on && p->timing && hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess)
             (void)hipEventRecord(a, s);
-        else a = b = nullptr;
+        else {
+            if (a) (void)hipEventDestroy(a);
+            a = b = nullptr;
+        }
     }
     void stop() {
         if (a && b) {
             (void)hipEventRecord(b, s);
-            p->timed.push_back({a, b, kind});
+            p->timed.push_back({a, b, kind, ntp});
             a = b = nullptr;
         }
     }
@@ -171,11 +275,299 @@ xs_status validate_opts(const xs_opts* o) {
     if (o->a_is_log != 0 && o->a_is_log != 1) return fail(XS_ERR_ARG, "a_is_log must be 0 or 1");
     if (o->waves_per_block != 0 && o->waves_per_block != 4 && o->waves_per_block != 8)
         return fail(XS_ERR_ARG, "waves_per_block must be 0, 4 or 8");
+    if (o->n_split < 0 || o->n_split > 64) return fail(XS_ERR_ARG, "n_split must be in [0, 64]");
+    if (o->tp_block < 0 || o->tp_block > 256) return fail(XS_ERR_ARG, "tp_block must be in [0, 256]");
     const double dnu = (o->nu_b - o->nu_a) / (double)(o->n_points - 1);
     if (!(dnu > 0.0)) return fail(XS_ERR_ARG, "grid step underflows");
     const double hw = o->cutoff / dnu;
     if (hw > 4.0e8) return fail(XS_ERR_ARG, "cutoff spans more than 4e8 grid steps");
     if ((double)o->n_points + 2.0 * (hw + 3.0) > 2.0e9) return fail(XS_ERR_ARG, "grid plus cut-off halo too large");
+    return XS_OK;
+}
+
+// ------------------------------------------------------------ batched pipeline
+int tile_width(const xs_plan* p) { return xs::tile_points(p->P, p->o.precision == XS_FP64 ? 4 : p->waves); }
+
+int n_tiles(const xs_plan* p) {
+    const int W = tile_width(p);
+    return (p->geo.n_points + W - 1) / W;
+}
+
+// Dispatch order of the tiles of the current width: decreasing number of overlapping
+// lines (longest processing time first).  Synchronous (the table is small).
+xs_status build_tile_order(xs_plan* p) {
+    const int W = tile_width(p);
+    const int nt = n_tiles(p);
+    if (p->order_W == W && p->n_order == nt) return XS_OK;
+    p->n_order = 0;
+    p->order_W = 0;
+    if (!p->lpt_order || p->n_kept <= 0 || (int64_t)p->off_host.size() != (int64_t)p->geo.nkeys + 1) return XS_OK;
+    const xs::Geometry& G = p->geo;
+    std::vector<std::pair<int, int>> cost(nt);
+    for (int t = 0; t < nt; ++t) {
+        const int64_t k0 = std::min<int64_t>((int64_t)t * W, G.nkeys);           // key of kc = t0 - hmax
+        const int64_t k1 = std::min<int64_t>((int64_t)t * W + W + 2 * G.hmax, G.nkeys);
+        cost[t] = {p->off_host[k1] - p->off_host[k0], t};
+    }
+    std::stable_sort(cost.begin(), cost.end(),
+                     [](const std::pair<int, int>& a, const std::pair<int, int>& b) { return a.first > b.first; });
+    std::vector<int> order(nt);
+    for (int t = 0; t < nt; ++t) order[t] = cost[t].second;
+    XS_TRY(p->ensure(p->tile_order, nt * sizeof(int), "tile order"));
+    XS_HIP(hipMemcpy(p->tile_order.p, order.data(), nt * sizeof(int), hipMemcpyHostToDevice));
+    p->n_order = nt;
+    p->order_W = W;
+    return XS_OK;
+}
+
+double beta_of(const xs_opts& o, double T) {
+    // Eq. 16: alpha_D = nu sqrt(2 k T ln2 / m) / c
+    return std::sqrt(2.0 * xs::kKB * T * xs::kLN2 / (o.mass_da * xs::kAMU)) / xs::kC_SI;
+}
+
+// Radius in grid steps beyond which every point of a line is in the FP32 path's far
+// zone (Voigt: |x| >= 40) or a Gaussian has underflowed (x^2 >= 110), for every
+// temperature up to T_rm (the Doppler width grows with T).  Lorentz lines need none.
+double rm_steps(const xs_plan* p, double T_rm) {
+    const xs_opts& o = p->o;
+    const double numax = std::max(std::fabs(o.nu_b), std::fabs(o.nu_a)) + o.cutoff;
+    double xr = 0.0, alpha = 0.0;
+    if (o.profile == XS_VOIGT) { xr = 40.0; alpha = numax * beta_of(o, T_rm); }
+    else if (o.profile == XS_DOPPLER) { xr = 10.5; alpha = numax * beta_of(o, T_rm); }
+    else if (o.profile == XS_GAUSS_FIXED) { xr = 10.5; alpha = o.alpha_fixed; }
+    return xr * alpha / (xs::kSQRT_LN2 * p->geo.dnu) + 2.0;
+}
+
+xs::TPParam make_tp(const xs_plan* p, double T, double P, int iq, double T_rm) {
+    const xs_opts& o = p->o;
+    xs::TPParam tp{};
+    tp.T = T;
+    tp.P = P;
+    tp.c2_over_T = xs::kC2 / T;
+    tp.beta = beta_of(o, T);
+    tp.ln_T0_T = std::log(o.T0 / T);
+    tp.p_over_p0 = P / o.P0;
+    tp.iq = iq;
+    const double rmd = rm_steps(p, T_rm);
+    tp.rm = rmd > 1.0e9 ? 1000000000 : (int)std::ceil(rmd);
+    return tp;
+}
+
+bool core_path(const xs_plan* p) { return p->o.precision == XS_FP32 && p->o.profile == XS_VOIGT; }
+
+int pick_block(const xs_plan* p, int n_tp) {
+    int B = p->tp_block > 0 ? p->tp_block : 8;
+    if (core_path(p) && p->tp_block <= 0) {
+        // core rows take 16 B per line and (T, P): keep them within 16 GiB
+        const int64_t cap = ((int64_t)16 << 30) / std::max<int64_t>(16 * p->n_kept, 1);
+        B = (int)std::max<int64_t>(1, std::min<int64_t>(B, cap));
+    }
+    return std::max(1, std::min(B, n_tp));
+}
+
+// Workgroups per tile: enough work items for ~5000 workgroups per (T, P) (the chip
+// holds ~1300 resident at once), without shares below 4096 lines.  It depends on the
+// plan only, so a (T, P) result does not depend on the other points of its call.
+int pick_split(const xs_plan* p) {
+    if (p->n_split > 0) return p->n_split;
+    const int nt = n_tiles(p);
+    const xs::Geometry& G = p->geo;
+    const double per_tile = (double)p->n_kept * (double)(tile_width(p) + 2 * G.hmax) / std::max(1, G.nkeys);
+    int S = 1;
+    while (S < 32 && (int64_t)nt * S < 5120 && per_tile / (2.0 * S) >= 4096.0) S *= 2;
+    return S;
+}
+
+// FP32 sweep mode of a (T, P): per-wavefront line segments when the fast-path radius
+// leaves room inside the half window, per-slice codes otherwise.
+bool seg_mode(const xs_plan* p, const xs::TPParam& tp) {
+    return p->o.precision == XS_FP32 && p->o.profile <= XS_VOIGT &&
+           64.0 * p->P + (double)tp.rm + 1.0 <= (double)p->geo.hmin;
+}
+
+// Core rows and per-part buffers for blocks of B (T, P) split S ways.
+xs_status ensure_rows(xs_plan* p, Workset& ws, int B, int S) {
+    const int64_t n = std::max<int64_t>(p->n_kept, 1);
+    if (core_path(p)) {
+        const int64_t nb = xs::core_blocks(n);
+        XS_TRY(ws.ensure(ws.rc, (size_t)B * n * sizeof(int), "core radii"));
+        XS_TRY(ws.ensure(ws.cnt, (size_t)B * n * sizeof(int), "core counts"));
+        XS_TRY(ws.ensure(ws.coff, (size_t)B * n * sizeof(long long), "core offsets"));
+        XS_TRY(ws.ensure(ws.bsum, (size_t)B * nb * sizeof(unsigned long long), "core block sums"));
+        XS_TRY(ws.ensure(ws.tmp, (size_t)B * kScanTmp * sizeof(unsigned long long), "core scan"));
+        ws.rows = B;
+        ws.row_stride = n;
+    }
+    if (S > 1) {
+        const size_t elem = p->o.precision == XS_FP64 ? sizeof(double) : 2 * sizeof(float);
+        XS_TRY(ws.ensure(ws.part, (size_t)B * S * (size_t)p->geo.n_points * elem, "split partial sums"));
+    }
+    return XS_OK;
+}
+
+xs::SortedLines sorted_lines(xs_plan* p) {
+    xs::SortedLines L{};
+    L.nu = as<double>(p->s_nu); L.elow = as<double>(p->s_elow); L.cA = as<double>(p->s_cA);
+    L.gref = as<float>(p->s_gref); L.nexp = as<float>(p->s_nexp); L.kc = as<int>(p->s_kc);
+    L.klo = as<int>(p->s_klo); L.khi = as<int>(p->s_khi); L.orig = as<int>(p->s_orig);
+    return L;
+}
+
+// Core pre-pass arguments of the call's (T, P) point `it` in core row `row`.
+xs::CoreArgs core_args(xs_plan* p, Workset& ws, int it, int row) {
+    xs::CoreArgs c{};
+    const int64_t n = ws.row_stride, nb = xs::core_blocks(n);
+    c.L = sorted_lines(p);
+    c.G = p->geo;
+    c.tp = as<xs::TPParam>(ws.tps) + it;
+    c.Q = as<double>(ws.Q);
+    c.n_lines = (int)p->n_kept;
+    c.tab = as<xs::Tables>(p->tab_dev);
+    c.rc = as<int>(ws.rc) + row * n;
+    c.cnt = as<int>(ws.cnt) + row * n;
+    c.coff = as<long long>(ws.coff) + row * n;
+    c.bsum = as<unsigned long long>(ws.bsum) + row * nb;
+    c.scan_tmp = as<unsigned long long>(ws.tmp) + (int64_t)row * kScanTmp;
+    c.val = as<float>(ws.val);
+    return c;
+}
+
+// Forward launch arguments for the (T, P) points [f, f + nb) of the call, whose core
+// rows start at row0, writing sigma rows f.. of the call's output.
+xs::FwdArgs fwd_args(xs_plan* p, Workset& ws, const std::vector<xs::TPParam>& tps, int f, int nb, int row0,
+                     int S, void* sigma) {
+    const xs_opts& o = p->o;
+    const bool fp64 = o.precision == XS_FP64;
+    const size_t elem = fp64 ? sizeof(double) : sizeof(float);
+    xs::FwdArgs a{};
+    a.L = sorted_lines(p);
+    a.G = p->geo;
+    a.tps = as<xs::TPParam>(ws.tps) + f;
+    a.Q = as<double>(ws.Q);
+    a.off = as<int>(p->off);
+    a.sigma = static_cast<char*>(sigma) + (size_t)f * (size_t)p->geo.n_points * elem;
+    a.part = ws.part.p;
+    a.n_lines = (int)p->n_kept;
+    a.n_tiles = n_tiles(p);
+    a.n_tp = nb;
+    a.n_split = S;
+    a.seg = 1;
+    for (int t = f; t < f + nb; ++t) a.seg = a.seg && seg_mode(p, tps[t]);
+    a.xcd_contiguous = p->xcd_contiguous;
+    a.tile_order = (p->n_order == a.n_tiles && p->order_W == tile_width(p)) ? as<int>(p->tile_order) : nullptr;
+    a.alpha_fixed = o.alpha_fixed;
+    a.tab = as<xs::Tables>(p->tab_dev);
+    if (core_path(p)) {
+        a.core_rc = as<int>(ws.rc) + (int64_t)row0 * ws.row_stride;
+        a.core_off = as<long long>(ws.coff) + (int64_t)row0 * ws.row_stride;
+        a.core_val = as<float>(ws.val);
+        a.core_stride = ws.row_stride;
+    }
+    return a;
+}
+
+// Per-(T, P) parameters and temperatures to the device (through pinned staging), then
+// Q(T) for every temperature of the call.  With enqueue_q false the partition sum is
+// left to the caller (graph capture records it).
+xs_status upload_tps(xs_plan* p, Workset& ws, const std::vector<xs::TPParam>& tps, hipStream_t s, bool enqueue_q) {
+    const int n = (int)tps.size();
+    XS_TRY(ws.ensure(ws.T, n * sizeof(double), "temperatures"));
+    XS_TRY(ws.ensure(ws.Q, n * sizeof(double), "Q(T)"));
+    XS_TRY(ws.ensure(ws.dQ, n * sizeof(double), "dQ/dT"));
+    XS_TRY(ws.ensure(ws.qpart, (size_t)2 * n * xs_plan::kQBlocks * sizeof(double), "Q partials"));
+    XS_TRY(ws.ensure(ws.tps, n * sizeof(xs::TPParam), "(T, P) parameters"));
+    void* h = nullptr;
+    XS_TRY(ws.stage.get(n * (sizeof(double) + sizeof(xs::TPParam)), &h));
+    double* hT = static_cast<double*>(h);
+    xs::TPParam* hp = reinterpret_cast<xs::TPParam*>(hT + n);
+    for (int i = 0; i < n; ++i) { hT[i] = tps[i].T; hp[i] = tps[i]; }
+    XS_HIP(hipMemcpyAsync(ws.T.p, hT, n * sizeof(double), hipMemcpyHostToDevice, s));
+    XS_HIP(hipMemcpyAsync(ws.tps.p, hp, n * sizeof(xs::TPParam), hipMemcpyHostToDevice, s));
+    XS_TRY(ws.stage.record(s));
+    if (enqueue_q)
+        XS_HIP(xs::launch_partition(as<double>(p->E), as<int>(p->g), p->n_states, as<double>(ws.T), n,
+                                    as<double>(ws.qpart), xs_plan::kQBlocks, as<double>(ws.Q), as<double>(ws.dQ), s));
+    return XS_OK;
+}
+
+// Read back the u64 totals at scan_tmp[4096] of core rows [0, nb) (synchronous).
+xs_status read_totals(Workset& ws, int nb, hipStream_t s, std::vector<unsigned long long>& out) {
+    void* h = nullptr;
+    XS_TRY(ws.stage.get(nb * sizeof(unsigned long long), &h));
+    unsigned long long* ht = static_cast<unsigned long long*>(h);
+    for (int t = 0; t < nb; ++t)
+        XS_HIP(hipMemcpyAsync(ht + t, as<unsigned long long>(ws.tmp) + (int64_t)t * kScanTmp + 4096,
+                              sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    XS_HIP(hipStreamSynchronize(s));
+    out.assign(ht, ht + nb);
+    return XS_OK;
+}
+
+// Core evaluation (optionally preceded by the count) of rows [0, nb) for the (T, P)
+// points [f, f + nb), then the block's forward launch and, when split, the combine.
+// Enqueue only: no allocation and no synchronisation (graph-capturable).
+xs_status enqueue_block(xs_plan* p, Workset& ws, const std::vector<xs::TPParam>& tps, int f, int nb, int S,
+                        bool count, const std::vector<long long>& vbase, const std::vector<long long>& vend,
+                        void* sigma, hipStream_t s, bool timed) {
+    const bool fp64 = p->o.precision == XS_FP64;
+    if (core_path(p) && p->n_kept > 0) {
+        for (int t = 0; t < nb; ++t) {
+            xs::CoreArgs c = core_args(p, ws, f + t, t);
+            c.val_base = vbase[f + t];
+            c.val_end = vend[f + t];
+            Timer tc(p, s, 1, 0, timed);
+            if (count) XS_HIP(xs::launch_core_count(c, s));
+            XS_HIP(xs::launch_core_eval(c, s));
+            tc.stop();
+        }
+    }
+    // one launch per run of consecutive (T, P) sharing the sweep mode
+    for (int r0 = f; r0 < f + nb;) {
+        int r1 = r0 + 1;
+        while (r1 < f + nb && seg_mode(p, tps[r1]) == seg_mode(p, tps[r0])) ++r1;
+        const xs::FwdArgs a = fwd_args(p, ws, tps, r0, r1 - r0, r0 - f, S, sigma);
+        {
+            Timer tf(p, s, 0, r1 - r0, timed);
+            XS_HIP(xs::launch_forward(p->o.profile, fp64 ? 1 : 0, p->waves, p->P, a, s));
+            tf.stop();
+        }
+        if (S > 1) {
+            Timer tm(p, s, 3, r1 - r0, timed);
+            XS_HIP(xs::launch_combine(fp64 ? 1 : 0, a, s));
+            tm.stop();
+        }
+        r0 = r1;
+    }
+    return XS_OK;
+}
+
+// Exact core counts of the block [f, f + nb) (one wait), value offsets, capacity.
+xs_status count_block(xs_plan* p, Workset& ws, const std::vector<xs::TPParam>& tps, int f, int nb, hipStream_t s,
+                      std::vector<long long>& vbase, std::vector<long long>& vend) {
+    for (int t = 0; t < nb; ++t) {
+        xs::CoreArgs c = core_args(p, ws, f + t, t);
+        Timer tc(p, s, 1);
+        XS_HIP(xs::launch_core_count(c, s));
+        tc.stop();
+    }
+    std::vector<unsigned long long> tot;
+    XS_TRY(read_totals(ws, nb, s, tot));
+    long long base = 0;
+    for (int t = 0; t < nb; ++t) {
+        vbase[f + t] = base;
+        base += (long long)tot[t];
+        vend[f + t] = base;
+    }
+    return ws.ensure(ws.val, (size_t)std::max<long long>(base, 1) * sizeof(float), "core values");
+}
+
+xs_status validate_tp(int n_tp, const double* T, const double* P) {
+    if (!T || !P) return fail(XS_ERR_ARG, "NULL argument");
+    if (n_tp <= 0) return fail(XS_ERR_ARG, "n_tp must be > 0");
+    for (int i = 0; i < n_tp; ++i) {
+        if (!(T[i] > 0.0) || !std::isfinite(T[i])) return fail(XS_ERR_ARG, "temperatures must be finite and > 0");
+        if (!(P[i] >= 0.0) || !std::isfinite(P[i])) return fail(XS_ERR_ARG, "pressures must be finite and >= 0");
+    }
     return XS_OK;
 }
 
@@ -206,6 +598,8 @@ xs_status xs_plan_create(const xs_opts* opts, xs_plan** out) {
     p->o = *opts;
     p->P = opts->slices_per_wave ? opts->slices_per_wave : 2;
     p->waves = opts->precision == XS_FP64 ? 4 : (opts->waves_per_block ? opts->waves_per_block : 4);
+    p->n_split = opts->n_split;
+    p->tp_block = opts->tp_block;
     if (const char* env = std::getenv("XSEC_XCD_CONTIGUOUS")) p->xcd_contiguous = std::atoi(env) ? 1 : 0;
     if (const char* env = std::getenv("XSEC_TILE_ORDER")) p->lpt_order = std::atoi(env) ? 1 : 0;
     xs::Geometry& G = p->geo;
@@ -254,6 +648,7 @@ xs_status xs_set_states(xs_plan* p, int64_t n, const double* E, const int32_t* g
     if (p->o.broadening == XS_BROAD_A0_JLOWER && !J) return fail(XS_ERR_ARG, "J is required for a0 broadening");
     hipStream_t s = static_cast<hipStream_t>(stream);
     p->have_lines = false;
+    p->generation++;
     xs_status st;
     if ((st = p->ensure(p->E, n * sizeof(double), "states E")) != XS_OK) return st;
     if ((st = p->ensure(p->g, n * sizeof(int), "states g")) != XS_OK) return st;
@@ -295,6 +690,7 @@ xs_status xs_set_lines(xs_plan* p, int64_t n, const int32_t* upper, const int32_
         return fail(XS_ERR_STATE, "a0 broadening needs xs_set_broadening_table and states J");
     hipStream_t s = static_cast<hipStream_t>(stream);
     p->have_lines = false;
+    p->generation++;
     xs_status st;
     if (n > p->cap) {
         const size_t d = n * sizeof(double), f = n * sizeof(float), i4 = n * sizeof(int);
@@ -365,26 +761,11 @@ xs_status xs_set_lines(xs_plan* p, int64_t n, const int32_t* upper, const int32_
     p->n_lines = n;
     p->n_kept = kept;
     p->n_order = 0;
-    if (p->lpt_order && kept > 0) {
-        // tiles by decreasing number of overlapping lines (host sort of the tile costs)
-        const xs::Geometry& G = p->geo;
-        const int W = xs::tile_points(p->P, p->waves);
-        const int nt = (G.n_points + W - 1) / W;
-        std::vector<int> off(G.nkeys + 1);
-        XS_HIP(hipMemcpy(off.data(), p->off.p, off.size() * sizeof(int), hipMemcpyDeviceToHost));
-        std::vector<std::pair<int, int>> cost(nt);
-        for (int t = 0; t < nt; ++t) {
-            const int64_t k0 = (int64_t)t * W;                       // key of kc = t0 - hmax
-            const int64_t k1 = std::min<int64_t>((int64_t)t * W + W + 2 * G.hmax, G.nkeys);
-            cost[t] = {off[k1] - off[std::min<int64_t>(k0, G.nkeys)], t};
-        }
-        std::stable_sort(cost.begin(), cost.end(),
-                         [](const std::pair<int, int>& a, const std::pair<int, int>& b) { return a.first > b.first; });
-        std::vector<int> order(nt);
-        for (int t = 0; t < nt; ++t) order[t] = cost[t].second;
-        if ((st = p->ensure(p->tile_order, nt * sizeof(int), "tile order")) != XS_OK) return st;
-        XS_HIP(hipMemcpy(p->tile_order.p, order.data(), nt * sizeof(int), hipMemcpyHostToDevice));
-        p->n_order = nt;
+    p->order_W = 0;
+    p->off_host.assign(p->geo.nkeys + 1, 0);
+    if (kept > 0) {
+        XS_HIP(hipMemcpy(p->off_host.data(), p->off.p, p->off_host.size() * sizeof(int), hipMemcpyDeviceToHost));
+        if ((st = build_tile_order(p)) != XS_OK) return st;
     }
     p->have_lines = true;
     return XS_OK;
@@ -429,90 +810,274 @@ xs_status xs_partition_function(xs_plan* p, int32_t nT, const double* T, double*
 
 xs_status xs_cross_section(xs_plan* p, int32_t n_tp, const double* T, const double* P, void* sigma,
                            void* stream) {
-    if (!p || !T || !P || !sigma) return fail(XS_ERR_ARG, "NULL argument");
-    if (n_tp <= 0) return fail(XS_ERR_ARG, "n_tp must be > 0");
+    if (!p || !sigma) return fail(XS_ERR_ARG, "NULL argument");
+    XS_TRY(validate_tp(n_tp, T, P));
     if (!p->have_lines) return fail(XS_ERR_STATE, "xs_set_lines must succeed first");
-    for (int i = 0; i < n_tp; ++i)
-        if (!(P[i] >= 0.0) || !std::isfinite(P[i])) return fail(XS_ERR_ARG, "pressures must be finite and >= 0");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    xs_status st = run_partition(p, n_tp, T, s);
-    if (st != XS_OK) return st;
-    const xs_opts& o = p->o;
-    // (the FP32 Voigt path waits on the stream once per (T, P) to size its core buffer)
-    const bool fp64 = o.precision == XS_FP64;
-    const size_t elem = fp64 ? sizeof(double) : sizeof(float);
-    const int W = xs::tile_points(p->P, p->waves);
-    xs::FwdArgs a{};
-    a.L.nu = as<double>(p->s_nu); a.L.elow = as<double>(p->s_elow); a.L.cA = as<double>(p->s_cA);
-    a.L.gref = as<float>(p->s_gref); a.L.nexp = as<float>(p->s_nexp); a.L.kc = as<int>(p->s_kc);
-    a.L.klo = as<int>(p->s_klo); a.L.khi = as<int>(p->s_khi); a.L.orig = as<int>(p->s_orig);
-    a.G = p->geo;
-    a.Q = as<double>(p->Q);
-    a.off = as<int>(p->off);
-    a.n_lines = (int)p->n_kept;
-    a.n_tiles = (p->geo.n_points + W - 1) / W;
-    a.xcd_contiguous = p->xcd_contiguous;
-    a.tile_order = (p->n_order == a.n_tiles) ? as<int>(p->tile_order) : nullptr;
-    a.alpha_fixed = o.alpha_fixed;
-    a.tab = as<xs::Tables>(p->tab_dev);
-    const bool core = !fp64 && o.profile == XS_VOIGT;
-    if (core) {
-        const size_t n = (size_t)std::max<int64_t>(p->n_kept, 1);
-        const size_t nb = (size_t)xs::core_blocks((int64_t)n);
-        if ((st = p->ensure(p->core_rc, n * sizeof(int), "core radii")) != XS_OK) return st;
-        if ((st = p->ensure(p->core_cnt, n * sizeof(int), "core counts")) != XS_OK) return st;
-        if ((st = p->ensure(p->core_off, n * sizeof(long long), "core offsets")) != XS_OK) return st;
-        if ((st = p->ensure(p->core_bsum, nb * sizeof(unsigned long long), "core block sums")) != XS_OK) return st;
-        if ((st = p->ensure(p->core_tmp, (4096 + 16) * sizeof(unsigned long long), "core scan")) != XS_OK) return st;
-        a.core_rc = as<int>(p->core_rc);
-        a.core_off = as<long long>(p->core_off);
+    Workset& ws = p->ws;
+    std::vector<xs::TPParam> tps(n_tp);
+    for (int i = 0; i < n_tp; ++i) tps[i] = make_tp(p, T[i], P[i], i, T[i]);
+    XS_TRY(build_tile_order(p));
+    XS_TRY(upload_tps(p, ws, tps, s, true));
+    const int B = pick_block(p, n_tp), S = pick_split(p);
+    p->last_block = B;
+    p->last_split = S;
+    XS_TRY(ensure_rows(p, ws, B, S));
+    std::vector<long long> vbase(n_tp, 0), vend(n_tp, 0);
+    // (the FP32 Voigt path waits once per block of (T, P) to size its core values)
+    for (int f = 0; f < n_tp; f += B) {
+        const int nb = std::min(B, n_tp - f);
+        if (core_path(p) && p->n_kept > 0) XS_TRY(count_block(p, ws, tps, f, nb, s, vbase, vend));
+        XS_TRY(enqueue_block(p, ws, tps, f, nb, S, false, vbase, vend, sigma, s, true));
     }
-    const double numax = std::max(std::fabs(o.nu_b), std::fabs(o.nu_a)) + o.cutoff;
-    for (int i = 0; i < n_tp; ++i) {
-        xs::TPParam& tp = a.tp;
-        tp.T = T[i];
-        tp.P = P[i];
-        tp.c2_over_T = xs::kC2 / T[i];
-        tp.beta = std::sqrt(2.0 * xs::kKB * T[i] * xs::kLN2 / (o.mass_da * xs::kAMU)) / xs::kC_SI;
-        tp.ln_T0_T = std::log(o.T0 / T[i]);
-        tp.p_over_p0 = P[i] / o.P0;
-        tp.iq = i;
-        // radius (grid steps) beyond which the wing formula holds (Voigt, |x| >= 40) or a
-        // Gaussian has underflowed (x^2 >= 110); Lorentz lines need no radius
-        double xr = 0.0, alpha = 0.0;
-        if (o.profile == XS_VOIGT) { xr = 40.0; alpha = numax * tp.beta; }
-        else if (o.profile == XS_DOPPLER) { xr = 10.5; alpha = numax * tp.beta; }
-        else if (o.profile == XS_GAUSS_FIXED) { xr = 10.5; alpha = o.alpha_fixed; }
-        const double rmd = xr * alpha / (xs::kSQRT_LN2 * p->geo.dnu) + 2.0;
-        tp.rm = rmd > 1.0e9 ? 1000000000 : (int)std::ceil(rmd);
-        a.seg = (!fp64 && o.profile <= XS_VOIGT && 64.0 * p->P + rmd + 1.0 <= (double)p->geo.hmin) ? 1 : 0;
-        a.sigma = static_cast<char*>(sigma) + (size_t)i * (size_t)p->geo.n_points * elem;
-        if (core && p->n_kept > 0) {
-            xs::CoreArgs c{};
-            c.L = a.L; c.G = a.G; c.tp = tp; c.Q = a.Q; c.n_lines = a.n_lines; c.tab = a.tab;
-            c.rc = as<int>(p->core_rc); c.cnt = as<int>(p->core_cnt);
-            c.bsum = as<unsigned long long>(p->core_bsum); c.coff = as<long long>(p->core_off);
-            c.scan_tmp = as<unsigned long long>(p->core_tmp);
-            Timer tc(p, s, 1);
-            XS_HIP(xs::launch_core_count(c, s));
-            tc.stop();
-            unsigned long long total = 0;
-            XS_HIP(hipMemcpyAsync(&total, as<unsigned long long>(p->core_tmp) + 4096, sizeof(total),
-                                  hipMemcpyDeviceToHost, s));
-            XS_HIP(hipStreamSynchronize(s));
-            if ((st = p->ensure(p->core_val, (size_t)std::max<unsigned long long>(total, 1) * sizeof(float),
-                                "core values")) != XS_OK)
-                return st;
-            c.val = as<float>(p->core_val);
-            Timer te(p, s, 1);
-            XS_HIP(xs::launch_core_eval(c, s));
-            te.stop();
-            a.core_val = c.val;
+    return XS_OK;
+}
+
+// ------------------------------------------------------------------ graphs
+xs_status xs_graph_create(xs_plan* p, int32_t n_tp, const double* T, const double* P, void* sigma,
+                          xs_graph** out) {
+    if (!out) return fail(XS_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (!p || !sigma) return fail(XS_ERR_ARG, "NULL argument");
+    XS_TRY(validate_tp(n_tp, T, P));
+    if (!p->have_lines) return fail(XS_ERR_STATE, "xs_set_lines must succeed first");
+    XS_TRY(build_tile_order(p));
+    xs_graph* g = new (std::nothrow) xs_graph();
+    if (!g) return fail(XS_ERR_OOM, "host allocation failed");
+    g->p = p;
+    g->n_tp = n_tp;
+    g->T_cap.assign(T, T + n_tp);
+    g->tps.resize(n_tp);
+    for (int i = 0; i < n_tp; ++i) g->tps[i] = make_tp(p, T[i], P[i], i, T[i]);
+    hipStream_t cs = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e != hipSuccess) { delete g; return hip_fail(e, "hipStreamCreateWithFlags"); }
+    auto cleanup = [&](xs_status st) {
+        if (cs) (void)hipStreamSynchronize(cs);
+        if (g->exec) (void)hipGraphExecDestroy(g->exec);
+        if (g->graph) (void)hipGraphDestroy(g->graph);
+        g->ws.release();
+        delete g;
+        if (cs) (void)hipStreamDestroy(cs);
+        return st;
+    };
+    Workset& ws = g->ws;
+    const int B = pick_block(p, n_tp), S = pick_split(p);
+    xs_status st = upload_tps(p, ws, g->tps, cs, true);
+    if (st == XS_OK) st = ensure_rows(p, ws, B, S);
+    std::vector<long long> vbase(n_tp, 0), vend(n_tp, 0);
+    if (st == XS_OK && core_path(p) && p->n_kept > 0) {
+        // capacities from the width-independent bound (valid for any T up to T_cap)
+        long long cap = 1;
+        for (int f = 0; f < n_tp && st == XS_OK; f += B) {
+            const int nb = std::min(B, n_tp - f);
+            for (int t = 0; t < nb && st == XS_OK; ++t) {
+                xs::CoreArgs c = core_args(p, ws, f + t, t);
+                e = xs::launch_core_bound(c, cs);
+                if (e != hipSuccess) st = hip_fail(e, "core bound");
+            }
+            std::vector<unsigned long long> tot;
+            if (st == XS_OK) st = read_totals(ws, nb, cs, tot);
+            long long base = 0;
+            for (int t = 0; t < nb && st == XS_OK; ++t) {
+                vbase[f + t] = base;
+                base += (long long)tot[t];
+                vend[f + t] = base;
+            }
+            cap = std::max(cap, base);
         }
-        Timer tf(p, s, 0);
-        XS_HIP(xs::launch_forward(o.profile, fp64 ? 1 : 0, p->waves, p->P, a, s));
-        tf.stop();
+        if (st == XS_OK) st = ws.ensure(ws.val, (size_t)cap * sizeof(float), "core values");
     }
+    if (st == XS_OK && (e = hipStreamSynchronize(cs)) != hipSuccess) st = hip_fail(e, "hipStreamSynchronize");
+    if (st != XS_OK) return cleanup(st);
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return cleanup(hip_fail(e, "hipStreamBeginCapture"));
+    e = xs::launch_partition(as<double>(p->E), as<int>(p->g), p->n_states, as<double>(ws.T), n_tp,
+                             as<double>(ws.qpart), xs_plan::kQBlocks, as<double>(ws.Q), as<double>(ws.dQ), cs);
+    if (e != hipSuccess) st = hip_fail(e, "partition function");
+    for (int f = 0; f < n_tp && st == XS_OK; f += B) {
+        const int nb = std::min(B, n_tp - f);
+        st = enqueue_block(p, ws, g->tps, f, nb, S, true, vbase, vend, sigma, cs, false);
+    }
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(cs, &graph);
+    g->graph = graph;
+    if (st != XS_OK) return cleanup(st);
+    if (e != hipSuccess) return cleanup(hip_fail(e, "hipStreamEndCapture"));
+    e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) { g->exec = nullptr; return cleanup(hip_fail(e, "hipGraphInstantiate")); }
+    (void)hipStreamDestroy(cs);
+    g->generation = p->generation;
+    *out = g;
+    return XS_OK;
+}
+
+xs_status xs_graph_set_tp(xs_graph* g, const double* T, const double* P, void* stream) {
+    if (!g) return fail(XS_ERR_ARG, "graph is NULL");
+    XS_TRY(validate_tp(g->n_tp, T, P));
+    for (int i = 0; i < g->n_tp; ++i)
+        if (T[i] > g->T_cap[i])
+            return fail(XS_ERR_ARG, "a temperature exceeds the one the graph was captured with");
+    for (int i = 0; i < g->n_tp; ++i) g->tps[i] = make_tp(g->p, T[i], P[i], i, g->T_cap[i]);
+    const int n = g->n_tp;
+    Workset& ws = g->ws;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    void* h = nullptr;
+    XS_TRY(ws.stage.get(n * (sizeof(double) + sizeof(xs::TPParam)), &h));
+    double* hT = static_cast<double*>(h);
+    xs::TPParam* hp = reinterpret_cast<xs::TPParam*>(hT + n);
+    for (int i = 0; i < n; ++i) { hT[i] = g->tps[i].T; hp[i] = g->tps[i]; }
+    XS_HIP(hipMemcpyAsync(ws.T.p, hT, n * sizeof(double), hipMemcpyHostToDevice, s));
+    XS_HIP(hipMemcpyAsync(ws.tps.p, hp, n * sizeof(xs::TPParam), hipMemcpyHostToDevice, s));
+    return ws.stage.record(s);
+}
+
+xs_status xs_graph_launch(xs_graph* g, void* stream) {
+    if (!g) return fail(XS_ERR_ARG, "graph is NULL");
+    if (g->generation != g->p->generation)
+        return fail(XS_ERR_STATE, "the plan's states, lines or tile configuration changed since the capture");
+    XS_HIP(hipGraphLaunch(g->exec, static_cast<hipStream_t>(stream)));
+    return XS_OK;
+}
+
+xs_status xs_graph_destroy(xs_graph* g) {
+    if (!g) return XS_OK;
+    (void)hipDeviceSynchronize();
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    g->ws.release();
+    delete g;
+    return XS_OK;
+}
+
+size_t xs_graph_workspace_bytes(const xs_graph* g) { return g ? g->ws.bytes : 0; }
+
+// ------------------------------------------------------------------ tile shape
+xs_status xs_set_tile_config(xs_plan* p, int32_t waves, int32_t slices, int32_t n_split, int32_t tp_block) {
+    if (!p) return fail(XS_ERR_ARG, "plan is NULL");
+    const bool fp64 = p->o.precision == XS_FP64;
+    if (!(waves == 0 || waves == 4 || (waves == 8 && !fp64)))
+        return fail(XS_ERR_ARG, "waves must be 0 or 4 (or 8 for XS_FP32)");
+    if (!(slices == 0 || slices == 1 || slices == 2 || slices == 4)) return fail(XS_ERR_ARG, "slices must be 0, 1, 2 or 4");
+    if (n_split < 0 || n_split > 64) return fail(XS_ERR_ARG, "n_split must be in [0, 64]");
+    if (tp_block < 0 || tp_block > 256) return fail(XS_ERR_ARG, "tp_block must be in [0, 256]");
+    XS_HIP(hipDeviceSynchronize());
+    p->waves = fp64 ? 4 : (waves ? waves : 4);
+    p->P = slices ? slices : 2;
+    p->n_split = n_split;
+    p->tp_block = tp_block;
+    p->generation++;
+    if (p->have_lines) XS_TRY(build_tile_order(p));
+    return XS_OK;
+}
+
+xs_status xs_get_tile_config(const xs_plan* p, int32_t out[6]) {
+    if (!p || !out) return fail(XS_ERR_ARG, "NULL argument");
+    out[0] = p->waves;
+    out[1] = p->P;
+    out[2] = p->n_split;
+    out[3] = p->tp_block;
+    out[4] = p->last_split;
+    out[5] = p->last_block;
+    return XS_OK;
+}
+
+xs_status xs_autotune(xs_plan* p, int32_t n_tp, const double* T, const double* P, double budget_ms, void* stream,
+                      int32_t out[4]) {
+    if (!p) return fail(XS_ERR_ARG, "plan is NULL");
+    XS_TRY(validate_tp(n_tp, T, P));
+    if (!p->have_lines) return fail(XS_ERR_STATE, "xs_set_lines must succeed first");
+    if (!(budget_ms > 0.0)) return fail(XS_ERR_ARG, "budget_ms must be > 0");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const auto t_start = std::chrono::steady_clock::now();
+    auto elapsed = [&]() {
+        return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+    };
+    const bool fp64 = p->o.precision == XS_FP64;
+    const int save_w = p->waves, save_p = p->P, save_s = p->n_split, save_b = p->tp_block;
+    // sample: the first (T, P) points, at most one default block
+    const int ns = pick_block(p, std::min<int>(n_tp, 16));
+    std::vector<xs::TPParam> tps(ns);
+    for (int i = 0; i < ns; ++i) tps[i] = make_tp(p, T[i], P[i], i, T[i]);
+    Workset& ws = p->ws;
+    XS_TRY(upload_tps(p, ws, tps, s, true));
+    XS_TRY(ensure_rows(p, ws, ns, 1));
+    std::vector<long long> vbase(ns, 0), vend(ns, 0);
+    if (core_path(p) && p->n_kept > 0) {
+        XS_TRY(count_block(p, ws, tps, 0, ns, s, vbase, vend));
+        for (int t = 0; t < ns; ++t) {
+            xs::CoreArgs c = core_args(p, ws, t, t);
+            c.val_base = vbase[t];
+            c.val_end = vend[t];
+            XS_HIP(xs::launch_core_eval(c, s));
+        }
+    }
+    const size_t elem = fp64 ? sizeof(double) : sizeof(float);
+    XS_TRY(ws.ensure(ws.out, (size_t)ns * p->geo.n_points * elem, "autotune output"));
+    hipEvent_t e0, e1;
+    XS_HIP(hipEventCreate(&e0));
+    XS_HIP(hipEventCreate(&e1));
+    // time of the forward (+ combine) launches over the sample in blocks of B, per (T, P)
+    auto run = [&](int w, int sl, int S, int B, double* ms) -> xs_status {
+        p->waves = w;
+        p->P = sl;
+        XS_TRY(build_tile_order(p));
+        XS_TRY(ensure_rows(p, ws, ns, S));
+        XS_HIP(hipEventRecord(e0, s));
+        for (int f = 0; f < ns; f += B) {
+            const int nb = std::min(B, ns - f);
+            const xs::FwdArgs a = fwd_args(p, ws, tps, f, nb, f, S, ws.out.p);
+            XS_HIP(xs::launch_forward(p->o.profile, fp64 ? 1 : 0, w, sl, a, s));
+            if (S > 1) XS_HIP(xs::launch_combine(fp64 ? 1 : 0, a, s));
+        }
+        XS_HIP(hipEventRecord(e1, s));
+        XS_HIP(hipEventSynchronize(e1));
+        float t = 0.0f;
+        XS_HIP(hipEventElapsedTime(&t, e0, e1));
+        *ms = (double)t / ns;
+        return XS_OK;
+    };
+    struct Cand { int w, sl, S, B; double ms; };
+    std::vector<Cand> shapes;
+    const int wlist[2] = {4, 8}, slist[3] = {2, 1, 4}, splits[6] = {1, 2, 4, 8, 16, 32};
+    for (int w : wlist) {
+        if (fp64 && w != 4) continue;
+        for (int sl : slist)
+            for (int S : splits) shapes.push_back({w, sl, S, ns, 0.0});
+    }
+    Cand best{save_w, save_p, 0, ns, 1e300};
+    xs_status st = XS_OK;
+    // a warm-up launch of every shape's kernel is part of the first timing; time twice
+    for (size_t i = 0; i < shapes.size() && st == XS_OK; ++i) {
+        if (i > 0 && elapsed() > budget_ms) break;
+        double a = 0.0, b = 0.0;
+        st = run(shapes[i].w, shapes[i].sl, shapes[i].S, shapes[i].B, &a);
+        if (st == XS_OK) st = run(shapes[i].w, shapes[i].sl, shapes[i].S, shapes[i].B, &b);
+        if (st == XS_OK && std::min(a, b) < best.ms) { best = shapes[i]; best.ms = std::min(a, b); }
+    }
+    // (T, P) block size with the best shape
+    for (int B = 1; B <= ns && st == XS_OK; B *= 2) {
+        if (B == ns || elapsed() > budget_ms) continue;
+        double a = 0.0, b = 0.0;
+        st = run(best.w, best.sl, best.S, B, &a);
+        if (st == XS_OK) st = run(best.w, best.sl, best.S, B, &b);
+        if (st == XS_OK && std::min(a, b) < best.ms) { best.B = B; best.ms = std::min(a, b); }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    dev_release(ws.out, &ws.bytes);
+    if (st != XS_OK || best.ms >= 1e300) {
+        p->waves = save_w; p->P = save_p; p->n_split = save_s; p->tp_block = save_b;
+        (void)build_tile_order(p);
+        return st != XS_OK ? st : fail(XS_ERR_STATE, "autotune timed no configuration");
+    }
+    p->waves = best.w;
+    p->P = best.sl;
+    p->n_split = best.S;
+    p->tp_block = best.B;
+    p->generation++;
+    XS_TRY(build_tile_order(p));
+    if (out) { out[0] = best.w; out[1] = best.sl; out[2] = best.S; out[3] = best.B; }
     return XS_OK;
 }
 
@@ -552,7 +1117,7 @@ xs_status xs_cross_section_adjoint(xs_plan* p, double T, double P, const void* g
     a.dlnA = dlnA; a.dgref = dgref; a.dn = dn;
     a.pT = as<double>(p->adj_pT);
     a.pP = as<double>(p->adj_pP);
-    Timer tf(p, s, 0);
+    Timer tf(p, s, 0, 1);
     XS_HIP(xs::launch_adjoint(a, o.precision == XS_FP64 ? 1 : 0, p->n_lines, as<double>(p->adj_part), dT, dP, s));
     tf.stop();
     return XS_OK;
@@ -562,7 +1127,8 @@ xs_status xs_set_timing(xs_plan* p, int enable) {
     if (!p) return fail(XS_ERR_ARG, "plan is NULL");
     if (enable) {
         p->drop_timed();
-        for (int k = 0; k < 3; ++k) { p->acc_ms[k] = 0; p->acc_n[k] = 0; }
+        for (int k = 0; k < 4; ++k) { p->acc_ms[k] = 0; p->acc_n[k] = 0; }
+        p->acc_tp = 0;
     }
     p->timing = enable != 0;
     return XS_OK;
@@ -576,6 +1142,7 @@ xs_status xs_kernel_times(xs_plan* p, xs_timings* out) {
         XS_HIP(hipEventElapsedTime(&ms, t.a, t.b));
         p->acc_ms[t.kind] += ms;
         p->acc_n[t.kind] += 1;
+        if (t.kind == 0) p->acc_tp += t.ntp;
     }
     p->drop_timed();
     out->forward_ms = p->acc_ms[0];
@@ -584,10 +1151,13 @@ xs_status xs_kernel_times(xs_plan* p, xs_timings* out) {
     out->forward_launches = p->acc_n[0];
     out->core_launches = p->acc_n[1];
     out->prep_launches = p->acc_n[2];
+    out->combine_ms = p->acc_ms[3];
+    out->combine_launches = p->acc_n[3];
+    out->forward_tp = p->acc_tp;
     return XS_OK;
 }
 
-size_t xs_workspace_bytes(const xs_plan* p) { return p ? p->total_bytes : 0; }
+size_t xs_workspace_bytes(const xs_plan* p) { return p ? p->total_bytes + p->ws.bytes : 0; }
 
 const char* xs_last_error(void) { return g_err.c_str(); }
 

@@ -38,8 +38,8 @@ struct CoreLine {
     int lo, hi, r;
 };
 
-__device__ __forceinline__ CoreLine core_line(const CoreArgs& A, int g, double Q) {
-    const LineSetup ls = line_setup(A.L, A.tp, g, Q);
+__device__ __forceinline__ CoreLine core_line(const CoreArgs& A, const TPParam& tp, int g, double Q) {
+    const LineSetup ls = line_setup(A.L, tp, g, Q);
     CoreLine c;
     c.s = kSQRT_LN2 / ls.aD;
     c.nu = ls.nu;
@@ -62,9 +62,10 @@ __device__ __forceinline__ CoreLine core_line(const CoreArgs& A, int g, double Q
 __global__ __launch_bounds__(256) void core_count_kernel(const CoreArgs A) {
     __shared__ unsigned long long lds[4];
     const int g = blockIdx.x * 256 + threadIdx.x;
+    const TPParam tp = *A.tp;
     unsigned long long c = 0;
     if (g < A.n_lines) {
-        const CoreLine cl = core_line(A, g, A.Q[A.tp.iq]);
+        const CoreLine cl = core_line(A, tp, g, A.Q[tp.iq]);
         c = cl.hi >= cl.lo ? (unsigned long long)(cl.hi - cl.lo + 1) : 0ull;
         A.rc[g] = cl.r;
         A.cnt[g] = (int)c;
@@ -122,20 +123,21 @@ __global__ __launch_bounds__(256) void core_eval_kernel(const CoreArgs A) {
     __shared__ int ls_lo[256];
     const int t = threadIdx.x;
     const int g = blockIdx.x * 256 + t;
-    const double Q = A.Q[A.tp.iq];
+    const TPParam tp = *A.tp;
+    const double Q = A.Q[tp.iq];
     unsigned long long c = 0;
     if (g < A.n_lines) {
         c = (unsigned long long)A.cnt[g];
         if (c) {
-            const CoreLine cl = core_line(A, g, Q);
+            const CoreLine cl = core_line(A, tp, g, Q);
             ls_s[t] = cl.s; ls_nu[t] = cl.nu; ls_y[t] = cl.y; ls_a[t] = cl.a; ls_lo[t] = cl.lo;
         }
     }
     unsigned long long tot;
     const unsigned long long ex = block_exclusive_scan_t<unsigned long long>(c, lds4, &tot);
-    const unsigned long long base = A.bsum[blockIdx.x];
+    const long long base = A.val_base + (long long)A.bsum[blockIdx.x];
     pre[t] = ex;
-    if (g < A.n_lines) A.coff[g] = (long long)(base + ex);
+    if (g < A.n_lines) A.coff[g] = base + (long long)ex;
     __syncthreads();
     for (unsigned long long it = t; it < tot; it += 256) {
         int lo = 0, hi = 255;
@@ -152,24 +154,58 @@ __global__ __launch_bounds__(256) void core_eval_kernel(const CoreArgs A) {
         if (z2 < kCoreR2) re = voigt_core_re<24, 8>(x, y, A.tab->w24);
         else if (z2 < kMidR2) re = gh_wing_re(x * x, y, A.tab->gh4);
         else re = gh_wing_re(x * x, y, A.tab->gh2);
-        A.val[base + it] = (float)(ls_a[j] * re);
+        const long long at = base + (long long)it;
+        if (at < A.val_end) A.val[at] = (float)(ls_a[j] * re);
     }
+}
+
+// Core points of a line: 2r + 1 with r = floor((X + |xc|)/h) + 1, X <= 8, |xc| <= h/2
+// (kc is the nearest grid index), so at most 16/h + 4, h = sqrt(ln2) dnu / alpha_D;
+// alpha_D grows with T, so the bound also holds at every lower temperature.
+__global__ __launch_bounds__(256) void core_bound_kernel(const CoreArgs A) {
+    __shared__ unsigned long long lds[4];
+    const int g = blockIdx.x * 256 + threadIdx.x;
+    unsigned long long c = 0;
+    if (g < A.n_lines) {
+        const int klo = A.L.klo[g], khi = A.L.khi[g];
+        if (khi >= klo) {
+            const double aD = A.L.nu[g] * A.tp->beta;
+            const double inv_h = aD / (kSQRT_LN2 * A.G.dnu);
+            const double b = floor(16.0 * inv_h) + 6.0;
+            const double win = (double)(khi - klo + 1);
+            c = (unsigned long long)(b < win ? b : win);
+        }
+    }
+    unsigned long long tot;
+    block_exclusive_scan_t<unsigned long long>(c, lds, &tot);
+    if (threadIdx.x == 0) A.bsum[blockIdx.x] = tot;
 }
 
 }  // namespace
 
 int64_t core_blocks(int64_t n_lines) { return (n_lines + 255) / 256; }
 
-hipError_t launch_core_count(const CoreArgs& a, hipStream_t s) {
-    const int64_t nb = core_blocks(a.n_lines);
-    if (nb == 0) return hipSuccess;
-    hipLaunchKernelGGL(core_count_kernel, dim3((unsigned)nb), dim3(256), 0, s, a);
+static hipError_t scan_block_sums(const CoreArgs& a, int64_t nb, hipStream_t s) {
     const int64_t nt = (nb + kScanTile - 1) / kScanTile;
     if (nt > kScanTile) return hipErrorInvalidValue;
     hipLaunchKernelGGL(scan64_tiles_kernel, dim3((unsigned)nt), dim3(256), 0, s, a.bsum, nb, a.scan_tmp);
     hipLaunchKernelGGL(scan64_small_kernel, dim3(1), dim3(256), 0, s, a.scan_tmp, nt);
     hipLaunchKernelGGL(scan64_apply_kernel, dim3((unsigned)nt), dim3(256), 0, s, a.bsum, nb, a.scan_tmp);
     return hipGetLastError();
+}
+
+hipError_t launch_core_count(const CoreArgs& a, hipStream_t s) {
+    const int64_t nb = core_blocks(a.n_lines);
+    if (nb == 0) return hipSuccess;
+    hipLaunchKernelGGL(core_count_kernel, dim3((unsigned)nb), dim3(256), 0, s, a);
+    return scan_block_sums(a, nb, s);
+}
+
+hipError_t launch_core_bound(const CoreArgs& a, hipStream_t s) {
+    const int64_t nb = core_blocks(a.n_lines);
+    if (nb == 0) return hipSuccess;
+    hipLaunchKernelGGL(core_bound_kernel, dim3((unsigned)nb), dim3(256), 0, s, a);
+    return scan_block_sums(a, nb, s);
 }
 
 hipError_t launch_core_eval(const CoreArgs& a, hipStream_t s) {

@@ -11,21 +11,32 @@ enum ProfileKind { kDoppler = 0, kGaussFixed = 1, kLorentz = 2, kVoigt = 3, kGHS
 struct FwdArgs {
     SortedLines L;
     Geometry G;
-    TPParam tp;
-    const double* Q;        // device Q(T) array, indexed by tp.iq
+    const TPParam* tps;     // device array: the launch's block of (T, P) points
+    const double* Q;        // device Q(T) array, indexed by TPParam::iq
     const int* off;         // offsets table, nkeys + 1 entries
-    void* sigma;            // float* (FP32 path) or double* (FP64 path), n_points values
+    void* sigma;            // output of the first (T, P) of the block: float* (FP32) or double*
+    void* part;             // n_split > 1: per-part sums, [n_tp][n_split][n_points] float2
+                            // (FP32: sum, compensation) or double (FP64)
     int n_lines;            // kept (sorted) lines
     int n_tiles;
+    int n_tp;               // (T, P) points in this launch (sigma has n_tp rows of n_points)
+    int n_split;            // workgroups sharing one tile's line range (1: write sigma directly)
     int seg;                // FP32 path: per-wavefront line segments (needs 64P + rm < hmin)
     int xcd_contiguous;     // map consecutive tiles to one XCD (when no order is given)
     const int* tile_order;  // tiles by decreasing line count (heaviest dispatched first), or NULL
     double alpha_fixed;     // HWHM for the fixed Gaussian
     const Tables* tab;      // device quadrature tables
-    // FP32 Voigt core pre-pass results (per sorted line)
+    // FP32 Voigt core pre-pass results, one row of n_lines per (T, P) of the block
     const int* core_rc;             // core radius in grid steps (-1: none)
-    const long long* core_off;      // first value of the line in core_val
+    const long long* core_off;      // index in core_val of the value at the first core point
     const float* core_val;          // a * Re w at the line's core points
+    int64_t core_stride;            // row stride of core_rc / core_off (>= n_lines)
+};
+
+// Work item of one workgroup: tiles in dispatch order, each tile's n_tp * n_split
+// workgroups consecutive (the same lines are read back to back from the caches).
+struct WorkItem {
+    int tile, tp, part;
 };
 
 // Points per block tile: 64-point slices per wavefront x wavefronts per block
@@ -34,25 +45,33 @@ inline int tile_points(int slices_per_wave, int waves) { return 64 * waves * sli
 
 hipError_t launch_forward(int profile, int fp64, int waves, int slices_per_wave, const FwdArgs& a,
                           hipStream_t s);
+// n_split > 1: sigma[t][k] = compensated sum over parts of part[t][*][k]
+hipError_t launch_combine(int fp64, const FwdArgs& a, hipStream_t s);
 
 // Core pre-pass (FP32 Voigt): radius/count per line, per-256-line block totals.
 struct CoreArgs {
     SortedLines L;
     Geometry G;
-    TPParam tp;
+    const TPParam* tp;               // device: this (T, P)
     const double* Q;
     int n_lines;
     const Tables* tab;
     int* rc;                         // [n_lines]
     int* cnt;                        // [n_lines]
     unsigned long long* bsum;        // [ceil(n_lines/256)] block totals, then exclusive prefix
-    long long* coff;                 // [n_lines]
-    float* val;                      // [total]
-    unsigned long long* scan_tmp;    // scratch for the block-total scan (>= 4096 + 16 entries)
+    long long* coff;                 // [n_lines] (absolute indices into val)
+    float* val;                      // values of every (T, P) of the block
+    long long val_base;              // first index of this (T, P) in val
+    long long val_end;               // end of this (T, P)'s capacity in val (no write at or beyond)
+    unsigned long long* scan_tmp;    // scratch for the block-total scan (>= 4096 + 16 entries);
+                                     // scan_tmp[4096] receives the total count
 };
 
 hipError_t launch_core_count(const CoreArgs& a, hipStream_t s);
 hipError_t launch_core_eval(const CoreArgs& a, hipStream_t s);
 int64_t core_blocks(int64_t n_lines);
+// Upper bound of the total core point count at temperature parameters tp, valid for
+// any Lorentz widths and any temperature not above tp.T; the total goes to scan_tmp[4096].
+hipError_t launch_core_bound(const CoreArgs& a, hipStream_t s);
 
 }  // namespace xs

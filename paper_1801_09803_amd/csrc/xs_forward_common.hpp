@@ -23,6 +23,25 @@ __device__ __forceinline__ int tile_of_block(int bid, int n, int xcd_contiguous,
     return x * q + (x < r ? x : r) + (bid >> 3);
 }
 
+// Work item of workgroup blockIdx.x (uniform: scalar registers).
+__device__ __forceinline__ WorkItem work_item(const FwdArgs& A) {
+    const int per = A.n_tp * A.n_split;
+    const int rank = (int)blockIdx.x / per;
+    const int rem = (int)blockIdx.x - rank * per;
+    WorkItem w;
+    w.tile = tile_of_block(rank, A.n_tiles, A.xcd_contiguous, A.tile_order);
+    w.tp = rem / A.n_split;
+    w.part = rem - w.tp * A.n_split;
+    return w;
+}
+
+// Part `part` of n equal shares of the sorted line range [b0, b5).
+__device__ __forceinline__ void part_range(int b0, int b5, int part, int n, int* p0, int* p1) {
+    const int64_t len = (int64_t)b5 - b0;
+    *p0 = b0 + (int)(len * part / n);
+    *p1 = b0 + (int)(len * (part + 1) / n);
+}
+
 // Per-line, per-(T,P) double-precision setup.
 struct LineSetup {
     double nu, S, aD, gam;

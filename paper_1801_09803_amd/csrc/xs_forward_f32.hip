@@ -56,7 +56,7 @@ struct RawLine {
 };
 
 template <int PROF>
-__device__ __forceinline__ RawLine load_raw(const FwdArgs& A, int g) {
+__device__ __forceinline__ RawLine load_raw(const FwdArgs& A, const int* crc, const long long* coff, int g) {
     RawLine w;
     w.nu = A.L.nu[g];
     w.elow = A.L.elow[g];
@@ -66,20 +66,20 @@ __device__ __forceinline__ RawLine load_raw(const FwdArgs& A, int g) {
     w.kc = A.L.kc[g];
     w.klo = A.L.klo[g];
     w.khi = A.L.khi[g];
-    if (PROF == kVoigt) { w.rc = A.core_rc[g]; w.coff = A.core_off[g]; }
+    if (PROF == kVoigt) { w.rc = crc[g]; w.coff = coff[g]; }
     else { w.rc = -1; w.coff = 0; }
     return w;
 }
 
 template <int PROF, int WAVES, int P>
-__device__ __forceinline__ void prepare_line(const FwdArgs& A, const Geometry& G, const RawLine& w, double Q,
-                                             int t0, bool codes, float* r) {
+__device__ __forceinline__ void prepare_line(const FwdArgs& A, const TPParam& tp, const Geometry& G,
+                                             const RawLine& w, double Q, int t0, bool codes, float* r) {
     constexpr int NS = WAVES * P;
-    const double T = A.tp.T;
+    const double T = tp.T;
     // Eq. 1: I = [g_f A/(8 pi c nu^2)] exp(-c2 E_i/T) (1 - exp(-c2 nu/T)) / Q(T)
     const double S = w.cA * exp(-(kC2 * w.elow) / T) * (-expm1(-(kC2 * w.nu) / T)) / Q;
-    const double aD = w.nu * A.tp.beta;                                              // Eq. 16
-    const double gam = (double)w.gref * exp((double)w.nexp * A.tp.ln_T0_T) * A.tp.p_over_p0;  // Eq. 18
+    const double aD = w.nu * tp.beta;                                              // Eq. 16
+    const double gam = (double)w.gref * exp((double)w.nexp * tp.ln_T0_T) * tp.p_over_p0;  // Eq. 18
     const double d = (G.nu_a + (double)w.kc * G.dnu) - w.nu;   // anchor offset nu_kc - nu
     int* ri = reinterpret_cast<int*>(r);
     r[R_SB0] = (float)(t0 - w.kc);
@@ -284,13 +284,18 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
     // from it: run bounds, loop counters, LDS record offsets) in scalar registers
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int tile = tile_of_block(blockIdx.x, A.n_tiles, A.xcd_contiguous, A.tile_order);
-    const int t0 = tile * W, t1 = t0 + W - 1;
+    const WorkItem wi = work_item(A);
+    const TPParam tp = A.tps[wi.tp];
+    const int* crc = PROF == kVoigt ? A.core_rc + (int64_t)wi.tp * A.core_stride : nullptr;
+    const long long* coff = PROF == kVoigt ? A.core_off + (int64_t)wi.tp * A.core_stride : nullptr;
+    const int t0 = wi.tile * W, t1 = t0 + W - 1;
     const int w0 = t0 + wave * WW, w1 = w0 + WW - 1;
 
-    const int b0 = off_at(A.off, (int64_t)t0 - G.hmax, G);
-    const int b5 = off_at(A.off, (int64_t)t1 + G.hmax + 1, G);
-    const int rm = A.tp.rm;
+    // this workgroup's share of the lines overlapping the tile
+    int b0, b5;
+    part_range(off_at(A.off, (int64_t)t0 - G.hmax, G), off_at(A.off, (int64_t)t1 + G.hmax + 1, G), wi.part,
+               A.n_split, &b0, &b5);
+    const int rm = tp.rm;
     int s0 = 0, s1 = 0, s2 = 0, s3 = 0, s4 = 0, s5 = 0;
     if (SEG) {
         s0 = off_at(A.off, (int64_t)w0 - G.hmax, G);
@@ -300,7 +305,7 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
         s4 = off_at(A.off, (int64_t)w0 + G.hmin + 1, G);
         s5 = off_at(A.off, (int64_t)w1 + G.hmax + 1, G);
     }
-    const double Q = A.Q[A.tp.iq];
+    const double Q = A.Q[tp.iq];
 
     float jl[P], jlo_w[P], jhi_w[P], part[P], sum[P], comp[P];
 #pragma unroll
@@ -315,12 +320,12 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
     const int anc = R_ANC + wave;
 
     RawLine nxt;
-    if (b0 + tid < b5) nxt = load_raw<PROF>(A, b0 + tid);
+    if (b0 + tid < b5) nxt = load_raw<PROF>(A, crc, coff, b0 + tid);
     for (int bs = b0; bs < b5; bs += NT) {
         const int g = bs + tid;
-        if (g < b5) prepare_line<PROF, WAVES, P>(A, G, nxt, Q, t0, !SEG, rec + tid * kRec);
+        if (g < b5) prepare_line<PROF, WAVES, P>(A, tp, G, nxt, Q, t0, !SEG, rec + tid * kRec);
         __syncthreads();
-        if (g + NT < b5) nxt = load_raw<PROF>(A, g + NT);   // overlaps the sweep below
+        if (g + NT < b5) nxt = load_raw<PROF>(A, crc, coff, g + NT);   // overlaps the sweep below
         const int be = bs + NT < b5 ? bs + NT : b5;
         for (int cs = bs; cs < be; cs += 64) {
             const int ce = cs + 64 < be ? cs + 64 : be;
@@ -479,17 +484,26 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
         __syncthreads();
     }
 
-    float* out = static_cast<float*>(A.sigma);
+    if (A.n_split == 1) {
+        float* out = static_cast<float*>(A.sigma) + (int64_t)wi.tp * G.n_points;
 #pragma unroll
-    for (int p = 0; p < P; ++p) {
-        const int k = w0 + 64 * p + lane;
-        if (k < G.n_points) out[k] = sum[p] + comp[p];
+        for (int p = 0; p < P; ++p) {
+            const int k = w0 + 64 * p + lane;
+            if (k < G.n_points) out[k] = sum[p] + comp[p];
+        }
+    } else {
+        float2* out = static_cast<float2*>(A.part) + ((int64_t)wi.tp * A.n_split + wi.part) * G.n_points;
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            const int k = w0 + 64 * p + lane;
+            if (k < G.n_points) out[k] = make_float2(sum[p], comp[p]);
+        }
     }
 }
 
 template <int PROF, int WAVES, int P>
 void launch_one(const FwdArgs& a, hipStream_t s) {
-    const dim3 grid(a.n_tiles), block(64 * WAVES);
+    const dim3 grid((unsigned)((int64_t)a.n_tiles * a.n_tp * a.n_split)), block(64 * WAVES);
     if (PROF <= kVoigt && a.seg) hipLaunchKernelGGL((fwd_f32_kernel<PROF, WAVES, P, PROF <= kVoigt>), grid, block, 0, s, a);
     else hipLaunchKernelGGL((fwd_f32_kernel<PROF, WAVES, P, false>), grid, block, 0, s, a);
 }

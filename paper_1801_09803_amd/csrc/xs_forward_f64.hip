@@ -22,11 +22,13 @@ __global__ __launch_bounds__(256) void fwd_f64_kernel(const FwdArgs A) {
 
     const Geometry G = A.G;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int tile = tile_of_block(blockIdx.x, A.n_tiles, A.xcd_contiguous, A.tile_order);
-    const int t0 = tile * W, t1 = t0 + W - 1;
-    const int b0 = off_at(A.off, (int64_t)t0 - G.hmax, G);
-    const int b5 = off_at(A.off, (int64_t)t1 + G.hmax + 1, G);
-    const double Q = A.Q[A.tp.iq];
+    const WorkItem wi = work_item(A);
+    const TPParam tp = A.tps[wi.tp];
+    const int t0 = wi.tile * W, t1 = t0 + W - 1;
+    int b0, b5;
+    part_range(off_at(A.off, (int64_t)t0 - G.hmax, G), off_at(A.off, (int64_t)t1 + G.hmax + 1, G), wi.part,
+               A.n_split, &b0, &b5);
+    const double Q = A.Q[tp.iq];
 
     int kk[P];
     double nuk[P], acc[P];
@@ -42,7 +44,7 @@ __global__ __launch_bounds__(256) void fwd_f64_kernel(const FwdArgs A) {
         const int g = bs + tid;
         if (g < b5) {
             double* r = rec + tid * (kRec / 2);
-            const LineSetup ls = line_setup(A.L, A.tp, g, Q);
+            const LineSetup ls = line_setup(A.L, tp, g, Q);
             double s, y = 0.0;
             r[D_NU] = ls.nu;
             if (PROF == kVoigt) {
@@ -164,7 +166,9 @@ __global__ __launch_bounds__(256) void fwd_f64_kernel(const FwdArgs A) {
         }
         __syncthreads();
     }
-    double* out = static_cast<double*>(A.sigma);
+    double* out = A.n_split == 1
+                      ? static_cast<double*>(A.sigma) + (int64_t)wi.tp * G.n_points
+                      : static_cast<double*>(A.part) + ((int64_t)wi.tp * A.n_split + wi.part) * G.n_points;
 #pragma unroll
     for (int p = 0; p < P; ++p)
         if (kk[p] < G.n_points) out[kk[p]] = acc[p];
@@ -172,7 +176,7 @@ __global__ __launch_bounds__(256) void fwd_f64_kernel(const FwdArgs A) {
 
 template <int PROF>
 void launch_p64(int P, const FwdArgs& a, hipStream_t s) {
-    const dim3 grid(a.n_tiles), block(256);
+    const dim3 grid((unsigned)((int64_t)a.n_tiles * a.n_tp * a.n_split)), block(256);
     switch (P) {
         case 1: hipLaunchKernelGGL((fwd_f64_kernel<PROF, 1>), grid, block, 0, s, a); break;
         case 2: hipLaunchKernelGGL((fwd_f64_kernel<PROF, 2>), grid, block, 0, s, a); break;
@@ -183,6 +187,55 @@ void launch_p64(int P, const FwdArgs& a, hipStream_t s) {
 }  // namespace
 
 hipError_t launch_forward_f32(int profile, int waves, int P, const FwdArgs& a, hipStream_t s);
+
+namespace {
+
+// Sum of the n_split partial results of every (T, P) and grid point, in part order.
+// FP32: TwoSum of the parts' sums, plus their compensations.
+__global__ __launch_bounds__(256) void combine_f32_kernel(const float2* part, float* sigma, int n_split,
+                                                          int n_points, int64_t total) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= total) return;
+    const int64_t t = i / n_points, k = i - t * n_points;
+    const float2* p = part + t * n_split * (int64_t)n_points + k;
+    float s = 0.0f, c = 0.0f;
+    for (int q = 0; q < n_split; ++q) {
+        const float2 v = p[(int64_t)q * n_points];
+        const float u = s + v.x;
+        const float bp = u - s;
+        c += (s - (u - bp)) + (v.x - bp);
+        c += v.y;
+        s = u;
+    }
+    sigma[i] = s + c;
+}
+
+__global__ __launch_bounds__(256) void combine_f64_kernel(const double* part, double* sigma, int n_split,
+                                                          int n_points, int64_t total) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= total) return;
+    const int64_t t = i / n_points, k = i - t * n_points;
+    const double* p = part + t * n_split * (int64_t)n_points + k;
+    double s = 0.0;
+    for (int q = 0; q < n_split; ++q) s += p[(int64_t)q * n_points];
+    sigma[i] = s;
+}
+
+}  // namespace
+
+hipError_t launch_combine(int fp64, const FwdArgs& a, hipStream_t s) {
+    if (a.n_split <= 1) return hipSuccess;
+    const int64_t total = (int64_t)a.n_tp * a.G.n_points;
+    if (total == 0) return hipSuccess;
+    const dim3 grid((unsigned)((total + 255) / 256)), block(256);
+    if (fp64)
+        hipLaunchKernelGGL(combine_f64_kernel, grid, block, 0, s, static_cast<const double*>(a.part),
+                           static_cast<double*>(a.sigma), a.n_split, a.G.n_points, total);
+    else
+        hipLaunchKernelGGL(combine_f32_kernel, grid, block, 0, s, static_cast<const float2*>(a.part),
+                           static_cast<float*>(a.sigma), a.n_split, a.G.n_points, total);
+    return hipGetLastError();
+}
 
 hipError_t launch_forward(int profile, int fp64, int waves, int P, const FwdArgs& a, hipStream_t s) {
     if (a.n_tiles <= 0) return hipSuccess;

@@ -36,14 +36,15 @@ def test_library_exports_every_declared_symbol():
 def test_version_and_defaults_without_gpu():
     from paper_1801_09803_amd.binding import XsOpts, load_library
     lib = load_library()
-    assert lib.xs_version() == 1
+    assert lib.xs_version() == 2
     o = XsOpts()
     assert lib.xs_opts_default(ctypes.byref(o)) == 0
     assert o.cutoff == 25.0 and o.T0 == 296.0 and o.P0 == 1.0 and o.profile == 3
 
 
 @pytest.mark.parametrize("field,value", [("n_points", 1), ("cutoff", 0.0), ("mass_da", -1.0),
-                                         ("profile", 9), ("index_base", 2), ("slices_per_wave", 3)])
+                                         ("profile", 9), ("index_base", 2), ("slices_per_wave", 3),
+                                         ("n_split", 65), ("n_split", -1), ("tp_block", 257)])
 def test_plan_create_rejects_bad_options_on_host(field, value):
     # option validation happens before any device call
     from paper_1801_09803_amd.binding import XsOpts, load_library
@@ -64,3 +65,25 @@ def test_null_arguments_are_rejected_without_gpu():
     assert lib.xs_plan_destroy(None) == 0
     assert lib.xs_set_states(None, 10, None, None, None, None) == 1
     assert lib.xs_cross_section(None, 1, None, None, None, None) == 1
+
+
+def test_struct_layouts_match_the_header():
+    # the binding's ctypes mirrors must keep the C sizes (xs_opts keeps its size: the
+    # tile-configuration fields took reserved slots)
+    from paper_1801_09803_amd.binding import XsKernelTimes, XsOpts
+    assert ctypes.sizeof(XsOpts) == 8 * 7 + 4 * 4 + 8 * 3 + 4 * 8
+    assert ctypes.sizeof(XsKernelTimes) == 8 * 9
+
+
+def test_graph_and_tuning_calls_reject_null_plans_on_host():
+    from paper_1801_09803_amd.binding import load_library
+    lib = load_library()
+    h = ctypes.c_void_p()
+    T = (ctypes.c_double * 1)(296.0)
+    P = (ctypes.c_double * 1)(1.0)
+    assert lib.xs_graph_create(None, 1, T, P, None, ctypes.byref(h)) == 1 and not h.value
+    assert lib.xs_graph_launch(None, None) == 1
+    assert lib.xs_graph_set_tp(None, T, P, None) == 1
+    assert lib.xs_graph_destroy(None) == 0
+    assert lib.xs_set_tile_config(None, 4, 2, 0, 0) == 1
+    assert lib.xs_autotune(None, 1, T, P, 10.0, None, None) == 1

@@ -1,0 +1,198 @@
+"""Batching extension on the GPU, through the C ABI: blocks of (T, P) per forward launch,
+tiles split between workgroups, graph capture and replay of the whole launch sequence,
+and the tile-shape autotuner.  Checked against the FP64 oracle at sampled grid points
+and against direct (uncaptured, unsplit) calls.
+
+The grid is 0-1000 cm^-1 at 0.01 (100001 points: 196 tiles of 512 points, the last one
+ragged); 2e5 lines with centres up to 1000 cm^-1 and a 25 cm^-1 cut-off."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import synth
+from tests.gpu_util import host, log, make_plan, oracle_lineset
+
+pytestmark = pytest.mark.gpu
+
+TOL32 = 1e-5
+TOL64 = 1e-10
+TS = [150.0, 296.0, 900.0, 2000.0, 3000.0]
+PS = [1e-4, 1.0, 0.05, 10.0, 0.3]
+
+
+@pytest.fixture(scope="module")
+def case():
+    cfg = synth.WorkloadConfig("batch", 4321, 2000, 200000, 34.0, 1000.0, 0.0, 1000.0, 100001,
+                               (296.0,), (1.0,), cutoff=25.0)
+    d = synth.make_linelist(cfg, device="cuda")
+    return cfg, d, host(d)
+
+
+def _points(cfg):
+    ks = np.linspace(0, cfg.n_points - 1, 1001).astype(np.int64)
+    return np.unique(np.concatenate([ks, [1, 511, 512, cfg.n_points - 2]]))
+
+
+@pytest.fixture(scope="module")
+def oracle_at(case):
+    """(grid indices, oracle sigma there) per (T, P): 1001 evenly spread points plus
+    the points nearest the centres of the 40 strongest lines."""
+    cfg, d, h = case
+    base = _points(cfg)
+    cache = {}
+
+    def get(T, P):
+        if (T, P) not in cache:
+            ls = oracle_lineset(h, cfg, T, P)
+            _, dnu = O.grid(cfg.nu_a, cfg.nu_b, cfg.n_points)
+            top = np.argsort(-ls.I)[:40]
+            kc = np.rint((ls.nu[top] - cfg.nu_a) / dnu).astype(np.int64)
+            kc = kc[(kc >= 0) & (kc < cfg.n_points)]
+            ks = np.unique(np.concatenate([base, kc, np.clip(kc + 3, 0, cfg.n_points - 1)]))
+            cache[(T, P)] = ks, O.cross_section_at(ls, ks, cfg.nu_a, cfg.nu_b, cfg.n_points, cfg.cutoff)
+        return cache[(T, P)]
+    return get
+
+
+def _plan(cfg, d, precision="fp32", **kw):
+    plan = make_plan(cfg, precision, **kw)
+    plan.set_states(d["E"], d["g"], d["J"])
+    plan.set_lines(d["upper"], d["lower"], d["A"], d["gamma_ref"], d["n_exp"])
+    return plan
+
+
+def _check_at(row, ks, ref, tol, what):
+    got = np.asarray(row, np.float64)[ks]
+    m = ref > 1e-6 * ref.max()
+    rel = np.abs(got[m] - ref[m]) / ref[m]
+    log(f"  {what}: max rel {rel.max():.3e} over {m.sum()} sampled points")
+    # at 150 K and 1e-4 bar (or P = 0) Doppler widths are ~4% of the grid step: the
+    # sampled spectrum is a few spikes and only ~10 sampled points exceed 1e-6 of its max
+    assert m.sum() >= 8
+    assert rel.max() <= tol, (what, rel.max())
+
+
+def _np(t):
+    torch.cuda.synchronize()
+    return t.double().cpu().numpy()
+
+
+@pytest.mark.parametrize("precision,split", [("fp32", 1), ("fp32", 4), ("fp32", 16), ("fp64", 1), ("fp64", 4)])
+def test_split_tiles_match_oracle(case, oracle_at, precision, split):
+    cfg, d, h = case
+    log(f"split tiles {precision} n_split={split}")
+    plan = _plan(cfg, d, precision, n_split=split)
+    out = _np(plan.cross_section(TS, PS))
+    assert plan.tile_config()["last_split"] == split
+    for i, (T, P) in enumerate(zip(TS, PS)):
+        _check_at(out[i], *oracle_at(T, P), TOL32 if precision == "fp32" else TOL64, f"T={T} P={P}")
+
+
+def test_split_changes_only_rounding(case):
+    cfg, d, h = case
+    a = _np(_plan(cfg, d, "fp32", n_split=1).cross_section(TS, PS))
+    b = _np(_plan(cfg, d, "fp32", n_split=8).cross_section(TS, PS))
+    for i in range(len(TS)):
+        m = O.error_metrics(b[i], a[i])
+        log(f"  n_split 8 vs 1, T={TS[i]}: max rel {m['max_rel']:.2e}")
+        assert m["max_rel"] < 2e-6
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_tp_blocks_are_bitwise_independent(case, precision):
+    # a (T, P) result does not depend on the other points of the call or the block size
+    cfg, d, h = case
+    ref = _np(_plan(cfg, d, precision, tp_block=1).cross_section(TS, PS))
+    for B in (2, 3, 8):
+        plan = _plan(cfg, d, precision, tp_block=B)
+        out = _np(plan.cross_section(TS, PS))
+        assert plan.tile_config()["last_block"] == min(B, len(TS))
+        assert np.array_equal(out, ref), B
+    plan = _plan(cfg, d, precision)
+    for i in (0, 3):
+        one = _np(plan.cross_section([TS[i]], [PS[i]]))[0]
+        assert np.array_equal(one, ref[i])
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_graph_replays_match_direct_calls(case, precision):
+    cfg, d, h = case
+    plan = _plan(cfg, d, precision, tp_block=2)
+    direct = _np(plan.cross_section(TS, PS))
+    graph = plan.graph(TS, PS)
+    log(f"graph {precision}: workspace {graph.workspace_bytes() / 2**20:.1f} MiB")
+    for rep in range(3):
+        graph.sigma.fill_(-1.0)
+        out = _np(graph.launch())
+        assert np.array_equal(out, direct), rep
+        # eager work of the program between replays: another call on the same plan
+        other = _np(plan.cross_section([500.0], [2.0]))
+        assert np.isfinite(other).all()
+    graph.close()
+
+
+def test_graph_new_temperatures_and_pressures(case, oracle_at):
+    cfg, d, h = case
+    plan = _plan(cfg, d, "fp32")
+    graph = plan.graph(TS, PS)
+    T2 = [100.0, 296.0, 600.0, 2000.0, 1200.0]
+    P2 = [3.0, 0.0, 0.05, 1e-3, 30.0]
+    graph.set_tp(T2, P2)
+    out = _np(graph.launch())
+    direct = _np(plan.cross_section(T2, P2))
+    for i, (T, P) in enumerate(zip(T2, P2)):
+        _check_at(out[i], *oracle_at(T, P), TOL32, f"graph T={T} P={P}")
+        assert O.error_metrics(out[i], direct[i])["max_rel"] < 2e-6
+    with pytest.raises(Exception) as e:
+        graph.set_tp([160.0] + T2[1:], P2)      # above the captured 150 K
+    assert "XS_ERR_ARG" in str(e.value)
+    graph.set_tp(TS, PS)
+    assert np.array_equal(_np(graph.launch()), _np(plan.cross_section(TS, PS)))
+    graph.close()
+
+
+def test_graph_invalidated_by_plan_changes(case):
+    cfg, d, h = case
+    plan = _plan(cfg, d, "fp32")
+    g1 = plan.graph(TS[:2], PS[:2])
+    g1.launch()
+    plan.set_tile_config(4, 4, 2, 1)
+    with pytest.raises(Exception) as e:
+        g1.launch()
+    assert "XS_ERR_STATE" in str(e.value)
+    g2 = plan.graph(TS[:2], PS[:2])
+    assert np.array_equal(_np(g2.launch()), _np(plan.cross_section(TS[:2], PS[:2])))
+    plan.set_lines(d["upper"], d["lower"], d["A"], d["gamma_ref"], d["n_exp"])
+    with pytest.raises(Exception) as e:
+        g2.launch()
+    assert "XS_ERR_STATE" in str(e.value)
+    g1.close()
+    g2.close()
+
+
+def test_autotune_picks_a_valid_configuration(case, oracle_at):
+    cfg, d, h = case
+    plan = _plan(cfg, d, "fp32")
+    best = plan.autotune(TS, PS, budget_ms=4000.0)
+    log(f"autotune: {best}")
+    assert best["waves"] in (4, 8) and best["slices"] in (1, 2, 4)
+    assert 1 <= best["n_split"] <= 32 and 1 <= best["tp_block"] <= len(TS)
+    cfgd = plan.tile_config()
+    assert (cfgd["waves"], cfgd["slices"], cfgd["n_split"], cfgd["tp_block"]) == \
+        (best["waves"], best["slices"], best["n_split"], best["tp_block"])
+    out = _np(plan.cross_section(TS, PS))
+    for i, (T, P) in enumerate(zip(TS, PS)):
+        _check_at(out[i], *oracle_at(T, P), TOL32, f"tuned T={T} P={P}")
+
+
+def test_timing_counts_blocks(case):
+    cfg, d, h = case
+    plan = _plan(cfg, d, "fp32", tp_block=2, n_split=4)
+    plan.set_timing(True)
+    plan.cross_section(TS, PS)
+    t = plan.kernel_times()
+    log(f"  timings {t}")
+    assert t["forward_tp"] == len(TS)
+    assert t["forward_launches"] == 3 and t["combine_launches"] == 3
+    assert t["forward_ms"] > 0 and t["core_launches"] == 2 * len(TS)
