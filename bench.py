@@ -5,9 +5,13 @@ Workload (default): 1e8 synthetic transitions among 1e6 states (34 Da), T = 296 
 (1,000,001 points), FP32 profile arithmetic with FP64 line setup.
 
 One step = the whole hot path on device-resident inputs: line preparation and sort
-(xs_set_lines), Q(T) on the device, and both cross sections from one batched call.
-The plain FP64 path is timed on the same workload for comparison, and the CPU oracle
-is timed on a bounded sample of the same list (before the GPU is touched).
+(xs_set_lines), Q(T) on the device, and both cross sections from one batched call
+(tile shape chosen by the library's autotuner before the timed steps).  The plain
+FP64 path is timed on the same workload for comparison, a captured graph of the
+batched call is replayed, the retrieval workload (1e7 lines, 1000-6000 cm^-1,
+1500 K, 0.1 bar) is timed as batched FP32 forward + adjoint against the plain FP64
+forward + adjoint, and the CPU oracle is timed on a bounded sample of the same list
+(before the GPU is touched).
 
 Prints one JSON line (rank 0, N = 1 only).
 """
@@ -104,6 +108,11 @@ def main():
     ap.add_argument("--slices-per-wave", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--autotune-ms", type=float, default=20000.0,
+                    help="autotuner budget (0: keep the library's default tile shape)")
+    ap.add_argument("--tile", default="", help="fixed tile config waves,slices,n_split,tp_block")
     ap.add_argument("--cpu-lines-per-core", type=int, default=20000)
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run a device copy of this many MiB (HBM counter calibration)")
@@ -162,6 +171,17 @@ def main():
     plan = make("fp32")
     plan.set_states(d["E"], d["g"], d["J"])
     stream = torch.cuda.current_stream()
+    tune = None
+    if args.tile:
+        w, sl, sp, tb = (int(v) for v in args.tile.split(","))
+        plan.set_lines(d["upper"], d["lower"], d["A"], d["gamma_ref"], d["n_exp"])
+        plan.set_tile_config(w, sl, sp, tb)
+    elif args.autotune_ms > 0:
+        plan.set_lines(d["upper"], d["lower"], d["A"], d["gamma_ref"], d["n_exp"])
+        t_tune = time.perf_counter()
+        chosen = plan.autotune(temps, pressures, budget_ms=args.autotune_ms)
+        tune = dict(chosen=chosen, wall_s=time.perf_counter() - t_tune, budget_ms=args.autotune_ms)
+        log(f"autotune: {chosen} in {tune['wall_s']:.1f} s")
     out = torch.empty((len(temps), cfg.n_points), dtype=torch.float32, device=dev)
 
     def step():
@@ -194,7 +214,10 @@ def main():
     value = n_kept * n_tp * args.steps / elapsed
     ms_step = 1e3 * elapsed / args.steps
     avg_launch_s = kt["forward_ms"] / kt["forward_launches"] / 1e3
-    achieved = FLOPS_PER_EVAL * evals_per_tp / avg_launch_s / 1e12
+    tp_per_launch = kt["forward_tp"] / kt["forward_launches"]
+    fwd_s_per_tp = kt["forward_ms"] / kt["forward_tp"] / 1e3
+    achieved = FLOPS_PER_EVAL * evals_per_tp * tp_per_launch / avg_launch_s / 1e12
+    tile = plan.tile_config()
 
     result = {
         "metric": "Voigt line-profiles/s at 25 cm^-1 cutoff",
@@ -218,6 +241,9 @@ def main():
             "point_evaluations_per_tp": evals_per_tp,
             "precision": "fp32 profiles, fp64 line setup, compensated fp32 sums",
             "step": "xs_set_lines (prep + sort) + Q(T) + batched forward",
+            "tile": {"waves": tile["waves"], "slices_per_wave": tile["slices"],
+                     "n_split": tile["last_split"], "tp_block": tile["last_block"]},
+            "autotune": tune,
         },
         "roofline": {
             "bound": "alu",
@@ -226,8 +252,10 @@ def main():
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_TFLOPS,
             "traffic": traffic_bytes_per_launch(),
-            "kernel": "fwd_f32_kernel<Voigt> (tile kernel, one launch per (T,P))",
+            "kernel": "fwd_f32_kernel<Voigt> (tile kernel, one launch per block of (T,P))",
             "avg_launch_ms": avg_launch_s * 1e3,
+            "tp_per_launch": tp_per_launch,
+            "algorithmic_flops_per_launch": FLOPS_PER_EVAL * evals_per_tp * tp_per_launch,
             "flops_per_eval": FLOPS_PER_EVAL,
             "frac_of_unpacked_fp32": achieved / PEAK_FP32_UNPACKED,
         },
@@ -235,9 +263,10 @@ def main():
             "line_prep_and_sort": kt["prep_ms"] / args.steps,
             "voigt_core_prepass": kt["core_ms"] / args.steps,
             "tile_kernel": kt["forward_ms"] / args.steps,
+            "split_combine": kt["combine_ms"] / args.steps,
         },
-        "forward_line_profiles_per_s": n_kept / avg_launch_s,
-        "point_evaluations_per_s": evals_per_tp / avg_launch_s,
+        "forward_line_profiles_per_s": n_kept / fwd_s_per_tp,
+        "point_evaluations_per_s": evals_per_tp / fwd_s_per_tp,
         "cpu_baseline": base,
     }
 
@@ -256,7 +285,7 @@ def main():
         torch.cuda.synchronize()
         t64 = ev2.elapsed_time(ev3) / 1e3
         result["fp64_plain_forward_line_profiles_per_s"] = n_kept * n_tp / t64
-        result["fp32_vs_fp64_forward_speedup"] = t64 / (avg_launch_s * n_tp)
+        result["fp32_vs_fp64_forward_speedup"] = t64 / (fwd_s_per_tp * n_tp)
         # agreement of the two paths on the last (T, P)
         ref = out64[0]
         got = out[-1].double()
@@ -265,7 +294,87 @@ def main():
         result["fp32_vs_fp64_area_rel"] = float(abs(got.sum().item() - ref.sum().item()) / ref.sum().item())
         del plan64, out64
 
+    if not args.no_graph:
+        # the batched call captured once and replayed (no host work, no waits)
+        graph = plan.graph(temps, pressures)
+        graph.launch()
+        torch.cuda.synchronize()
+        ev4, ev5 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 3
+        ev4.record(stream)
+        for _ in range(reps):
+            graph.launch()
+        ev5.record(stream)
+        torch.cuda.synchronize()
+        tg = ev4.elapsed_time(ev5) / 1e3 / reps
+        result["graph_replay"] = {"ms": tg * 1e3, "line_profiles_per_s": n_kept * n_tp / tg,
+                                  "equal_to_direct_call": bool(torch.equal(graph.sigma, out))}
+        log(f"graph replay {tg * 1e3:.1f} ms")
+        graph.close()
+
+    del plan, out, d
+    torch.cuda.empty_cache()
+    if not args.no_adjoint:
+        result["fwd_adj"] = fwd_adj(synth.CONFIGS["C4"], dev, stream, log)
+
     print(json.dumps(result), flush=True)
+
+
+def fwd_adj(cfg, dev, stream, log):
+    """Retrieval step (forward + adjoint) on the retrieval workload: batched FP32 path
+    against the plain FP64 path; dL/dsigma = 2 (sigma - sigma*) with sigma* from the
+    seeded perturbation (T x 1.05, gamma_ref x 1.1, ln A + N(0, 0.05))."""
+    import torch
+    import synth
+    from paper_1801_09803_amd import Plan
+    d = synth.make_linelist(cfg, device=dev)
+    T, P = cfg.temperatures[0], cfg.pressures[0]
+    logA = torch.log(d["A"].double()).float()
+    pert = synth.linelist.perturbation_normals(cfg.n_lines, cfg.seed).to(dev)
+    res = {"workload": f"{cfg.name}: {cfg.n_lines} transitions, {cfg.n_states} states, T={T} K, P={P} bar, "
+                       f"{cfg.nu_a}-{cfg.nu_b} cm^-1 ({cfg.n_points} points), Voigt"}
+    grads = {}
+    for prec in ("fp32", "fp64"):
+        plan = Plan(cfg.nu_a, cfg.nu_b, cfg.n_points, cfg.mass_amu, cutoff=cfg.cutoff, profile="voigt",
+                    precision=prec, a_is_log=True)
+        plan.set_states(d["E"], d["g"], d["J"])
+        plan.set_lines(d["upper"], d["lower"], (logA.double() + 0.05 * pert).float(), d["gamma_ref"] * 1.1,
+                       d["n_exp"])
+        target = plan.cross_section([1.05 * T], [P]).clone()
+        plan.set_lines(d["upper"], d["lower"], logA, d["gamma_ref"], d["n_exp"])
+        kept = plan.lines_kept()
+
+        def once():
+            sig = plan.cross_section([T], [P])[0]
+            g = 2.0 * (sig - target[0])
+            return plan.cross_section_adjoint(T, P, g, cfg.n_lines)
+
+        once()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 3 if prec == "fp32" else 1
+        e0.record(stream)
+        for _ in range(reps):
+            out = once()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        res[f"{prec}_fwd_adj_ms"] = ms
+        res[f"{prec}_line_profiles_per_s"] = 2 * kept / (ms / 1e3)
+        grads[prec] = [t.double() if t.numel() > 1 else t.item() for t in out]
+        log(f"fwd+adj {prec}: {ms:.1f} ms")
+        del plan
+    res["lines_kept"] = kept
+    res["fp32_vs_fp64_speedup"] = res["fp64_fwd_adj_ms"] / res["fp32_fwd_adj_ms"]
+    g32, g64 = grads["fp32"], grads["fp64"]
+    res["fp32_vs_fp64_dT_rel"] = abs(g32[0] - g64[0]) / abs(g64[0])
+    res["fp32_vs_fp64_dP_rel"] = abs(g32[1] - g64[1]) / abs(g64[1])
+    for name, i in (("dlnA", 2), ("dgamma_ref", 3)):
+        a, b = g32[i], g64[i]
+        m = b.abs() > 1e-6 * b.abs().max()
+        res[f"fp32_vs_fp64_{name}_max_rel"] = float(((a - b).abs()[m] / b.abs()[m]).max().item())
+    res["note"] = "one line-profile = one (line, T, P) forward evaluation or its adjoint; the step counts both"
+    return res
 
 
 if __name__ == "__main__":

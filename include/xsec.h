@@ -103,9 +103,11 @@ typedef struct {
     int32_t waves_per_block; /* tile shape: wavefronts per workgroup for XS_FP32 (4 or 8);
                                 0 = library default (4); XS_FP64 always uses 4           */
     int32_t a_is_log;        /* 1: the A array given to xs_set_lines holds ln A (s^-1)    */
-    int32_t n_split;         /* workgroups sharing one tile (each sums an equal share of the
-                                tile's lines; a fixed-order compensated pass adds the shares):
-                                1..64, or 0 = chosen per call from the grid and line counts */
+    int32_t n_split;         /* workgroups sharing one tile: workgroup q sums the LDS batches
+                                q, q + n_split, ... of the tile's sorted lines (every share
+                                gets the same mix of centre and wing lines) and a fixed-order
+                                compensated pass adds the shares: 1..64, or 0 = chosen from
+                                the plan's grid and line counts                          */
     int32_t tp_block;        /* (T, P) points per forward launch (workgroups of one tile for
                                 consecutive (T, P) run back to back): 1..256, or 0 = chosen
                                 per call (8, fewer when the FP32 Voigt core rows of
@@ -201,10 +203,12 @@ xs_status xs_set_tile_config(xs_plan* plan, int32_t waves, int32_t slices, int32
 xs_status xs_get_tile_config(const xs_plan* plan, int32_t out[6]);
 
 /* Autotuner of the tile configuration (the batching extension).  Times the forward
- * launches (and the split combine) over the first min(n_tp, 16) (T, P) points for
- * every (waves, slices, n_split) candidate, then tp_block for the best of them, each
- * twice, until budget_ms of wall time is spent (the first candidate always runs), and
- * keeps the fastest per (T, P).  out (host int32[4] or NULL) receives {waves, slices,
+ * launches (and the split combine) over the first min(n_tp, 16) (T, P) points (at
+ * most one default block) in a coordinate search: the six (waves, slices) shapes at
+ * their default n_split, then every n_split in 1..32 for the best shape, then smaller
+ * tp_block values; a candidate is timed twice when one run is under 20 ms.  It stops
+ * once budget_ms of wall time is spent (the first candidate always runs) and keeps the
+ * fastest per (T, P).  out (host int32[4] or NULL) receives {waves, slices,
  * n_split, tp_block}.  SYNCHRONOUS; uses plan workspace; invalidates captured graphs. */
 xs_status xs_autotune(xs_plan* plan, int32_t n_tp, const double* T, const double* P,
                       double budget_ms, void* stream, int32_t out[4]);

@@ -365,16 +365,18 @@ int pick_block(const xs_plan* p, int n_tp) {
     return std::max(1, std::min(B, n_tp));
 }
 
-// Workgroups per tile: enough work items for ~5000 workgroups per (T, P) (the chip
-// holds ~1300 resident at once), without shares below 4096 lines.  It depends on the
-// plan only, so a (T, P) result does not depend on the other points of its call.
+// Workgroups per tile: ~24000 workgroups per (T, P) (the chip holds ~1300 at once, so
+// the heavy-first order ends with a short tail), each share keeping at least four LDS
+// batches of lines.  It depends on the plan only, so a (T, P) result does not depend
+// on the other points of its call.
 int pick_split(const xs_plan* p) {
     if (p->n_split > 0) return p->n_split;
     const int nt = n_tiles(p);
     const xs::Geometry& G = p->geo;
     const double per_tile = (double)p->n_kept * (double)(tile_width(p) + 2 * G.hmax) / std::max(1, G.nkeys);
+    const double batch = 64.0 * (p->o.precision == XS_FP64 ? 4 : p->waves);
     int S = 1;
-    while (S < 32 && (int64_t)nt * S < 5120 && per_tile / (2.0 * S) >= 4096.0) S *= 2;
+    while (S < 32 && (int64_t)nt * S < 24000 && per_tile / (2.0 * S) >= 4.0 * batch) S *= 2;
     return S;
 }
 
@@ -1038,31 +1040,37 @@ xs_status xs_autotune(xs_plan* p, int32_t n_tp, const double* T, const double* P
         return XS_OK;
     };
     struct Cand { int w, sl, S, B; double ms; };
-    std::vector<Cand> shapes;
-    const int wlist[2] = {4, 8}, slist[3] = {2, 1, 4}, splits[6] = {1, 2, 4, 8, 16, 32};
-    for (int w : wlist) {
-        if (fp64 && w != 4) continue;
-        for (int sl : slist)
-            for (int S : splits) shapes.push_back({w, sl, S, ns, 0.0});
-    }
-    Cand best{save_w, save_p, 0, ns, 1e300};
+    Cand best{save_w, save_p, 1, ns, 1e300};
     xs_status st = XS_OK;
-    // a warm-up launch of every shape's kernel is part of the first timing; time twice
-    for (size_t i = 0; i < shapes.size() && st == XS_OK; ++i) {
-        if (i > 0 && elapsed() > budget_ms) break;
-        double a = 0.0, b = 0.0;
-        st = run(shapes[i].w, shapes[i].sl, shapes[i].S, shapes[i].B, &a);
-        if (st == XS_OK) st = run(shapes[i].w, shapes[i].sl, shapes[i].S, shapes[i].B, &b);
-        if (st == XS_OK && std::min(a, b) < best.ms) { best = shapes[i]; best.ms = std::min(a, b); }
+    int tried = 0;
+    // one timing, repeated when short (the first launch of a kernel includes its load)
+    auto consider = [&](int w, int sl, int S, int B) {
+        if (st != XS_OK || (tried > 0 && elapsed() > budget_ms)) return;
+        ++tried;
+        double a = 0.0;
+        st = run(w, sl, S, B, &a);
+        if (st == XS_OK && a * ns < 20.0) {
+            double b = 0.0;
+            st = run(w, sl, S, B, &b);
+            a = std::min(a, b);
+        }
+        if (st == XS_OK && a < best.ms) best = Cand{w, sl, S, B, a};
+    };
+    // coordinate search: tile shapes at their default split, then the split of the best
+    // shape, then the (T, P) block size
+    const int shapes[6][2] = {{4, 2}, {4, 4}, {8, 2}, {4, 1}, {8, 4}, {8, 1}};
+    for (const auto& sh : shapes) {
+        if (fp64 && sh[0] != 4) continue;
+        p->waves = sh[0];
+        p->P = sh[1];
+        p->n_split = 0;
+        consider(sh[0], sh[1], pick_split(p), ns);
     }
-    // (T, P) block size with the best shape
-    for (int B = 1; B <= ns && st == XS_OK; B *= 2) {
-        if (B == ns || elapsed() > budget_ms) continue;
-        double a = 0.0, b = 0.0;
-        st = run(best.w, best.sl, best.S, B, &a);
-        if (st == XS_OK) st = run(best.w, best.sl, best.S, B, &b);
-        if (st == XS_OK && std::min(a, b) < best.ms) { best.B = B; best.ms = std::min(a, b); }
-    }
+    const int splits[6] = {1, 2, 4, 8, 16, 32};
+    const int s0 = best.S;
+    for (int S : splits)
+        if (S != s0) consider(best.w, best.sl, S, ns);
+    for (int B = 1; B < ns; B *= 2) consider(best.w, best.sl, best.S, B);
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     dev_release(ws.out, &ws.bytes);

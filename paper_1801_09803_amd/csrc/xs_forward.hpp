@@ -20,7 +20,8 @@ struct FwdArgs {
     int n_lines;            // kept (sorted) lines
     int n_tiles;
     int n_tp;               // (T, P) points in this launch (sigma has n_tp rows of n_points)
-    int n_split;            // workgroups sharing one tile's line range (1: write sigma directly)
+    int n_split;            // workgroups sharing one tile: workgroup q of a tile takes the LDS
+                            // batches q, q + n_split, ... of its sorted lines (1: write sigma)
     int seg;                // FP32 path: per-wavefront line segments (needs 64P + rm < hmin)
     int xcd_contiguous;     // map consecutive tiles to one XCD (when no order is given)
     const int* tile_order;  // tiles by decreasing line count (heaviest dispatched first), or NULL

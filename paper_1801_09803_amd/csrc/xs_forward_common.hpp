@@ -35,13 +35,6 @@ __device__ __forceinline__ WorkItem work_item(const FwdArgs& A) {
     return w;
 }
 
-// Part `part` of n equal shares of the sorted line range [b0, b5).
-__device__ __forceinline__ void part_range(int b0, int b5, int part, int n, int* p0, int* p1) {
-    const int64_t len = (int64_t)b5 - b0;
-    *p0 = b0 + (int)(len * part / n);
-    *p1 = b0 + (int)(len * (part + 1) / n);
-}
-
 // Per-line, per-(T,P) double-precision setup.
 struct LineSetup {
     double nu, S, aD, gam;

@@ -291,10 +291,11 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
     const int t0 = wi.tile * W, t1 = t0 + W - 1;
     const int w0 = t0 + wave * WW, w1 = w0 + WW - 1;
 
-    // this workgroup's share of the lines overlapping the tile
-    int b0, b5;
-    part_range(off_at(A.off, (int64_t)t0 - G.hmax, G), off_at(A.off, (int64_t)t1 + G.hmax + 1, G), wi.part,
-               A.n_split, &b0, &b5);
+    // lines overlapping the tile; this workgroup takes every n_split-th batch of them
+    const int b0 = off_at(A.off, (int64_t)t0 - G.hmax, G);
+    const int b5 = off_at(A.off, (int64_t)t1 + G.hmax + 1, G);
+    const int bstride = NT * A.n_split;
+    const int bfirst = b0 + NT * wi.part;
     const int rm = tp.rm;
     int s0 = 0, s1 = 0, s2 = 0, s3 = 0, s4 = 0, s5 = 0;
     if (SEG) {
@@ -320,12 +321,12 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
     const int anc = R_ANC + wave;
 
     RawLine nxt;
-    if (b0 + tid < b5) nxt = load_raw<PROF>(A, crc, coff, b0 + tid);
-    for (int bs = b0; bs < b5; bs += NT) {
+    if (bfirst + tid < b5) nxt = load_raw<PROF>(A, crc, coff, bfirst + tid);
+    for (int bs = bfirst; bs < b5; bs += bstride) {
         const int g = bs + tid;
         if (g < b5) prepare_line<PROF, WAVES, P>(A, tp, G, nxt, Q, t0, !SEG, rec + tid * kRec);
         __syncthreads();
-        if (g + NT < b5) nxt = load_raw<PROF>(A, crc, coff, g + NT);   // overlaps the sweep below
+        if (g + bstride < b5) nxt = load_raw<PROF>(A, crc, coff, g + bstride);   // overlaps the sweep below
         const int be = bs + NT < b5 ? bs + NT : b5;
         for (int cs = bs; cs < be; cs += 64) {
             const int ce = cs + 64 < be ? cs + 64 : be;

@@ -25,9 +25,9 @@ __global__ __launch_bounds__(256) void fwd_f64_kernel(const FwdArgs A) {
     const WorkItem wi = work_item(A);
     const TPParam tp = A.tps[wi.tp];
     const int t0 = wi.tile * W, t1 = t0 + W - 1;
-    int b0, b5;
-    part_range(off_at(A.off, (int64_t)t0 - G.hmax, G), off_at(A.off, (int64_t)t1 + G.hmax + 1, G), wi.part,
-               A.n_split, &b0, &b5);
+    // lines overlapping the tile; this workgroup takes every n_split-th batch of them
+    const int b0 = off_at(A.off, (int64_t)t0 - G.hmax, G);
+    const int b5 = off_at(A.off, (int64_t)t1 + G.hmax + 1, G);
     const double Q = A.Q[tp.iq];
 
     int kk[P];
@@ -40,7 +40,7 @@ __global__ __launch_bounds__(256) void fwd_f64_kernel(const FwdArgs A) {
     }
     const int cshift = 4 * (wave * P);   // NS <= 16 slices, 64-bit code
 
-    for (int bs = b0; bs < b5; bs += kBatch) {
+    for (int bs = b0 + kBatch * wi.part; bs < b5; bs += kBatch * A.n_split) {
         const int g = bs + tid;
         if (g < b5) {
             double* r = rec + tid * (kRec / 2);
