@@ -50,6 +50,7 @@ extern "C" {
 
 typedef struct xs_plan xs_plan;
 typedef struct xs_graph xs_graph;
+typedef struct xs_stream xs_stream;
 
 typedef enum {
     XS_OK = 0,
@@ -212,6 +213,41 @@ xs_status xs_get_tile_config(const xs_plan* plan, int32_t out[6]);
  * n_split, tp_block}.  SYNCHRONOUS; uses plan workspace; invalidates captured graphs. */
 xs_status xs_autotune(xs_plan* plan, int32_t n_tp, const double* T, const double* P,
                       double budget_ms, void* stream, int32_t out[4]);
+
+/* Line-list streaming (chunked reading of a line list too large for one call, as the
+ * paper's program reads its transition files in chunks; here the chunks come from
+ * host memory and the sums stay on the device).
+ * xs_stream_begin starts accumulating the cross sections of n_tp (T, P) points
+ * (host arrays, as for xs_cross_section) over the chunks passed to xs_stream_chunk;
+ * sigma (device [n_tp][n_points], float for XS_FP32, double for XS_FP64) receives
+ * the result at xs_stream_end.  The stream owns device accumulators (a sum and a
+ * compensation per value), a chunk result and two chunk buffers, and an internal copy
+ * stream of default priority; its work runs on `stream`.  *out receives the stream.
+ * xs_stream_chunk takes the next chunk: n transitions as host arrays (upper, lower,
+ * A as for xs_set_lines; gamma_ref and n_exp for XS_BROAD_PER_LINE, else NULL).  Use
+ * pinned host memory: the chunk is copied asynchronously on the copy stream while the
+ * previous chunk is prepared and computed on `stream`, and the host arrays must stay
+ * unchanged until the next xs_stream_chunk (or xs_stream_end) call has returned.
+ * Each chunk replaces the plan's line set (as xs_set_lines: synchronous, and invalid
+ * transitions return XS_ERR_INDEX / XS_ERR_NU_NONPOS, reported one call later).
+ * xs_stream_end computes the last chunk, writes sigma = sum + compensation, waits for
+ * it (SYNCHRONOUS) and frees the stream (also after an error); lines_kept (host, or
+ * NULL) receives the number of transitions whose window overlapped the grid.
+ * xs_stream_checkpoint computes any pending chunk and writes the accumulators, the
+ * (T, P) points and the chunk counts to the file `path` (SYNCHRONOUS; written to
+ * path.tmp, then renamed).  xs_stream_resume creates a stream from such a file for a
+ * plan with the same grid and precision (states, broadening table and lines are not
+ * in the file: set the states before resuming); chunks then continue the sums.
+ * xs_stream_stats writes {chunks passed, transitions passed, transitions kept}. */
+xs_status xs_stream_begin(xs_plan* plan, int32_t n_tp, const double* T, const double* P,
+                          void* sigma, void* stream, xs_stream** out);
+xs_status xs_stream_chunk(xs_stream* st, int64_t n, const int32_t* upper, const int32_t* lower,
+                          const float* A, const float* gamma_ref, const float* n_exp);
+xs_status xs_stream_end(xs_stream* st, int64_t* lines_kept);
+xs_status xs_stream_checkpoint(xs_stream* st, const char* path);
+xs_status xs_stream_resume(xs_plan* plan, const char* path, void* sigma, void* stream,
+                           xs_stream** out);
+xs_status xs_stream_stats(const xs_stream* st, int64_t out[3]);
 
 /* Adjoint of xs_cross_section for one (T, P) with the Voigt profile (not in the paper:
  * the derivative of Eq. 1, 2, 16, 18 and of the Voigt profile).  Given dL/dsigma on the

@@ -5,5 +5,5 @@ include/xsec.h); this package only marshals arguments to it.  There is no CPU
 fallback: importing the binding fails loudly if the library is missing.
 """
 from .binding import (  # noqa: F401
-    Plan, Graph, XsecError, lib_path, load_library, PROFILES, PRECISIONS, BROADENING, abi_version,
+    Plan, Graph, Stream, XsecError, lib_path, load_library, PROFILES, PRECISIONS, BROADENING, abi_version,
 )

@@ -80,6 +80,12 @@ def load_library() -> ctypes.CDLL:
         "xs_graph_launch": (i32, [P, P]),
         "xs_graph_destroy": (i32, [P]),
         "xs_graph_workspace_bytes": (ctypes.c_size_t, [P]),
+        "xs_stream_begin": (i32, [P, i32, P, P, P, P, ctypes.POINTER(P)]),
+        "xs_stream_chunk": (i32, [P, i64, P, P, P, P, P]),
+        "xs_stream_end": (i32, [P, ctypes.POINTER(i64)]),
+        "xs_stream_checkpoint": (i32, [P, ctypes.c_char_p]),
+        "xs_stream_resume": (i32, [P, ctypes.c_char_p, P, P, ctypes.POINTER(P)]),
+        "xs_stream_stats": (i32, [P, ctypes.POINTER(i64)]),
         "xs_set_tile_config": (i32, [P, i32, i32, i32, i32]),
         "xs_get_tile_config": (i32, [P, ctypes.POINTER(i32)]),
         "xs_autotune": (i32, [P, i32, P, P, dbl, P, ctypes.POINTER(i32)]),
@@ -271,6 +277,10 @@ class Plan:
         """Capture the cross-section launch sequence for these (T, P) into `out`."""
         return Graph(self, T, P, out)
 
+    def stream(self, T: Sequence[float], P: Sequence[float], out=None) -> "Stream":
+        """Start accumulating cross sections over chunks of transitions from host memory."""
+        return Stream(self, T, P, out)
+
     def set_timing(self, enable: bool = True):
         _check(self._lib.xs_set_timing(self._h, 1 if enable else 0))
 
@@ -328,5 +338,84 @@ class Graph:
     def __del__(self):
         try:
             self.close()
+        except Exception:
+            pass
+
+
+class Stream:
+    """Line-list streaming: chunks of transitions (host tensors, preferably pinned) are
+    copied to the device while the previous chunk is computed; sums stay on the device."""
+
+    def __init__(self, plan: Plan, T: Sequence[float] = (), P: Sequence[float] = (), out=None, *,
+                 resume_from: Optional[str] = None, n_tp: Optional[int] = None):
+        torch = plan._torch
+        self._plan, self._lib = plan, plan._lib
+        self._held = []
+        h = ctypes.c_void_p()
+        if resume_from is None:
+            T, P = list(T), list(P)
+            if len(T) != len(P):
+                raise ValueError("T and P differ in length")
+            n_tp = len(T)
+        elif n_tp is None:
+            raise ValueError("resuming needs n_tp (the checkpoint's number of (T, P) points)")
+        if out is None:
+            out = torch.empty((n_tp, plan.n_points), dtype=plan.dtype, device="cuda")
+        else:
+            out = plan._dev(out, plan.dtype, "out")
+            if out.numel() != n_tp * plan.n_points:
+                raise ValueError("out has the wrong size")
+        if resume_from is None:
+            _check(self._lib.xs_stream_begin(plan._h, n_tp, _host_doubles(T), _host_doubles(P), _ptr(out),
+                                             plan._stream(), ctypes.byref(h)))
+        else:
+            _check(self._lib.xs_stream_resume(plan._h, os.fsencode(resume_from), _ptr(out), plan._stream(),
+                                              ctypes.byref(h)))
+        self._h = h
+        self.sigma = out
+
+    @classmethod
+    def resume(cls, plan: Plan, path: str, n_tp: int, out=None) -> "Stream":
+        return cls(plan, out=out, resume_from=path, n_tp=n_tp)
+
+    def _host(self, t, dtype, name):
+        if t is None:
+            return None
+        if t.is_cuda or t.dtype != dtype or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous host tensor of {dtype}")
+        return t
+
+    def chunk(self, upper, lower, A, gamma_ref=None, n_exp=None):
+        torch = self._plan._torch
+        upper = self._host(upper, torch.int32, "upper")
+        lower = self._host(lower, torch.int32, "lower")
+        A = self._host(A, torch.float32, "A")
+        gamma_ref = self._host(gamma_ref, torch.float32, "gamma_ref")
+        n_exp = self._host(n_exp, torch.float32, "n_exp")
+        _check(self._lib.xs_stream_chunk(self._h, upper.numel(), _ptr(upper), _ptr(lower), _ptr(A),
+                                         _ptr(gamma_ref), _ptr(n_exp)))
+        # the host arrays must outlive their asynchronous copy (until the next call returns)
+        self._held = [upper, lower, A, gamma_ref, n_exp]
+
+    def checkpoint(self, path: str):
+        _check(self._lib.xs_stream_checkpoint(self._h, os.fsencode(path)))
+
+    def stats(self) -> dict:
+        out = (ctypes.c_int64 * 3)()
+        _check(self._lib.xs_stream_stats(self._h, out))
+        return dict(chunks=out[0], lines=out[1], kept=out[2])
+
+    def end(self):
+        """Finish: returns (sigma, lines kept); the stream is released."""
+        kept = ctypes.c_int64()
+        h, self._h = self._h, ctypes.c_void_p()
+        _check(self._lib.xs_stream_end(h, ctypes.byref(kept)))
+        self._held = []
+        return self.sigma, int(kept.value)
+
+    def __del__(self):
+        try:
+            if getattr(self, "_h", None) is not None and self._h.value:
+                self._lib.xs_stream_end(self._h, None)
         except Exception:
             pass

@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <new>
@@ -218,6 +219,26 @@ struct xs_graph {
     Workset ws;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+};
+
+// Line-list streaming: chunks of transitions from host memory, accumulated on device.
+struct xs_stream {
+    xs_plan* p = nullptr;
+    int n_tp = 0;
+    std::vector<double> T, P;
+    void* sigma = nullptr;        // caller's output [n_tp][n_points]
+    hipStream_t compute = nullptr;
+    hipStream_t copy = nullptr;   // host-to-device copies of chunks
+    hipEvent_t copied[2] = {nullptr, nullptr};
+    DevBuf acc, tmp;              // (sum, compensation) per value; last chunk's cross sections
+    DevBuf raw[2][5];             // per slot: upper, lower, A, gamma_ref, n_exp
+    int64_t raw_cap[2] = {0, 0};
+    bool have_pending = false;    // a copied chunk awaiting its computation
+    int pending_slot = 0;
+    int64_t pending_n = 0;
+    bool pending_broad = false;
+    int64_t chunks = 0, lines = 0, kept = 0;
+    size_t bytes = 0;
 };
 
 namespace {
@@ -1086,6 +1107,214 @@ xs_status xs_autotune(xs_plan* p, int32_t n_tp, const double* T, const double* P
     p->generation++;
     XS_TRY(build_tile_order(p));
     if (out) { out[0] = best.w; out[1] = best.sl; out[2] = best.S; out[3] = best.B; }
+    return XS_OK;
+}
+
+// ------------------------------------------------------------------ streaming
+namespace {
+
+size_t stream_elem(const xs_plan* p) { return p->o.precision == XS_FP64 ? sizeof(double) : sizeof(float); }
+
+void stream_free(xs_stream* st) {
+    if (st->compute) (void)hipStreamSynchronize(st->compute);
+    if (st->copy) (void)hipStreamSynchronize(st->copy);
+    dev_release(st->acc, &st->bytes);
+    dev_release(st->tmp, &st->bytes);
+    for (auto& slot : st->raw)
+        for (auto& b : slot) dev_release(b, &st->bytes);
+    for (auto& e : st->copied)
+        if (e) (void)hipEventDestroy(e);
+    if (st->copy) (void)hipStreamDestroy(st->copy);
+    delete st;
+}
+
+xs_status stream_create(xs_plan* p, int n_tp, const double* T, const double* P, void* sigma, void* stream,
+                        xs_stream** out) {
+    xs_stream* st = new (std::nothrow) xs_stream();
+    if (!st) return fail(XS_ERR_OOM, "host allocation failed");
+    st->p = p;
+    st->n_tp = n_tp;
+    st->T.assign(T, T + n_tp);
+    st->P.assign(P, P + n_tp);
+    st->sigma = sigma;
+    st->compute = static_cast<hipStream_t>(stream);
+    hipError_t e = hipStreamCreateWithFlags(&st->copy, hipStreamNonBlocking);
+    if (e != hipSuccess) { st->copy = nullptr; stream_free(st); return hip_fail(e, "hipStreamCreateWithFlags"); }
+    for (auto& ev : st->copied) {
+        e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (e != hipSuccess) { ev = nullptr; stream_free(st); return hip_fail(e, "hipEventCreate"); }
+    }
+    const int64_t n = (int64_t)n_tp * p->geo.n_points;
+    xs_status r = dev_ensure(st->acc, (size_t)n * 2 * stream_elem(p), "stream accumulators", &st->bytes);
+    if (r == XS_OK) r = dev_ensure(st->tmp, (size_t)n * stream_elem(p), "stream chunk result", &st->bytes);
+    if (r != XS_OK) { stream_free(st); return r; }
+    *out = st;
+    return XS_OK;
+}
+
+// Line preparation and cross sections of the copied chunk, added into the accumulators.
+xs_status stream_process(xs_stream* st) {
+    if (!st->have_pending) return XS_OK;
+    st->have_pending = false;
+    xs_plan* p = st->p;
+    const int k = st->pending_slot;
+    XS_HIP(hipStreamWaitEvent(st->compute, st->copied[k], 0));
+    DevBuf* r = st->raw[k];
+    XS_TRY(xs_set_lines(p, st->pending_n, as<int32_t>(r[0]), as<int32_t>(r[1]), as<float>(r[2]),
+                        st->pending_broad ? as<float>(r[3]) : nullptr, st->pending_broad ? as<float>(r[4]) : nullptr,
+                        st->compute));
+    st->lines += st->pending_n;
+    st->kept += p->n_kept;
+    if (p->n_kept == 0) return XS_OK;
+    XS_TRY(xs_cross_section(p, st->n_tp, st->T.data(), st->P.data(), st->tmp.p, st->compute));
+    XS_HIP(xs::launch_acc_add(p->o.precision == XS_FP64 ? 1 : 0, st->tmp.p, st->acc.p,
+                              (int64_t)st->n_tp * p->geo.n_points, st->compute));
+    return XS_OK;
+}
+
+constexpr uint64_t kCkptMagic = 0x31544b4343455358ull;   // "XSECCKT1"
+
+}  // namespace
+
+xs_status xs_stream_begin(xs_plan* p, int32_t n_tp, const double* T, const double* P, void* sigma, void* stream,
+                          xs_stream** out) {
+    if (!out) return fail(XS_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (!p || !sigma) return fail(XS_ERR_ARG, "NULL argument");
+    XS_TRY(validate_tp(n_tp, T, P));
+    if (p->n_states <= 0) return fail(XS_ERR_STATE, "xs_set_states must come first");
+    if (p->o.broadening == XS_BROAD_A0_JLOWER && (p->n_j <= 0 || !p->J.p))
+        return fail(XS_ERR_STATE, "a0 broadening needs xs_set_broadening_table and states J");
+    xs_stream* st = nullptr;
+    XS_TRY(stream_create(p, n_tp, T, P, sigma, stream, &st));
+    hipError_t e = xs::launch_acc_zero(p->o.precision == XS_FP64 ? 1 : 0, st->acc.p,
+                                       (int64_t)n_tp * p->geo.n_points, st->compute);
+    if (e != hipSuccess) { stream_free(st); return hip_fail(e, "accumulator clear"); }
+    *out = st;
+    return XS_OK;
+}
+
+xs_status xs_stream_chunk(xs_stream* st, int64_t n, const int32_t* upper, const int32_t* lower, const float* A,
+                          const float* gamma_ref, const float* n_exp) {
+    if (!st) return fail(XS_ERR_ARG, "stream is NULL");
+    xs_plan* p = st->p;
+    if (n < 0 || n > ((int64_t)1 << 31) - 1) return fail(XS_ERR_ARG, "chunk size must be in [0, 2^31-1]");
+    if (n > 0 && (!upper || !lower || !A)) return fail(XS_ERR_ARG, "upper, lower and A must be non-NULL");
+    const bool broad = p->o.broadening == XS_BROAD_PER_LINE;
+    if (broad && n > 0 && (!gamma_ref || !n_exp)) return fail(XS_ERR_ARG, "per-line broadening needs gamma_ref and n_exp");
+    const int k = (int)(st->chunks & 1);
+    // the slot's previous chunk was prepared (synchronously) two calls ago
+    if (n > st->raw_cap[k]) {
+        const size_t sz[5] = {n * sizeof(int32_t), n * sizeof(int32_t), n * sizeof(float), n * sizeof(float),
+                              n * sizeof(float)};
+        for (int a = 0; a < 5; ++a) {
+            if (a >= 3 && !broad) continue;
+            XS_TRY(dev_ensure(st->raw[k][a], sz[a], "stream chunk buffers", &st->bytes));
+        }
+        st->raw_cap[k] = n;
+    }
+    if (n > 0) {
+        XS_HIP(hipMemcpyAsync(st->raw[k][0].p, upper, n * sizeof(int32_t), hipMemcpyHostToDevice, st->copy));
+        XS_HIP(hipMemcpyAsync(st->raw[k][1].p, lower, n * sizeof(int32_t), hipMemcpyHostToDevice, st->copy));
+        XS_HIP(hipMemcpyAsync(st->raw[k][2].p, A, n * sizeof(float), hipMemcpyHostToDevice, st->copy));
+        if (broad) {
+            XS_HIP(hipMemcpyAsync(st->raw[k][3].p, gamma_ref, n * sizeof(float), hipMemcpyHostToDevice, st->copy));
+            XS_HIP(hipMemcpyAsync(st->raw[k][4].p, n_exp, n * sizeof(float), hipMemcpyHostToDevice, st->copy));
+        }
+    }
+    XS_HIP(hipEventRecord(st->copied[k], st->copy));
+    // the previous chunk computes while this one is copied
+    XS_TRY(stream_process(st));
+    st->have_pending = true;
+    st->pending_slot = k;
+    st->pending_n = n;
+    st->pending_broad = broad;
+    st->chunks++;
+    return XS_OK;
+}
+
+xs_status xs_stream_end(xs_stream* st, int64_t* lines_kept) {
+    if (!st) return fail(XS_ERR_ARG, "stream is NULL");
+    xs_status r = stream_process(st);
+    if (r == XS_OK) {
+        hipError_t e = xs::launch_acc_finish(st->p->o.precision == XS_FP64 ? 1 : 0, st->acc.p, st->sigma,
+                                             (int64_t)st->n_tp * st->p->geo.n_points, st->compute);
+        if (e != hipSuccess) r = hip_fail(e, "accumulator read-out");
+    }
+    if (r == XS_OK && lines_kept) *lines_kept = st->kept;
+    stream_free(st);
+    return r;
+}
+
+xs_status xs_stream_checkpoint(xs_stream* st, const char* path) {
+    if (!st || !path) return fail(XS_ERR_ARG, "NULL argument");
+    XS_TRY(stream_process(st));
+    xs_plan* p = st->p;
+    const int64_t n = (int64_t)st->n_tp * p->geo.n_points;
+    const size_t bytes = (size_t)n * 2 * stream_elem(p);
+    std::vector<char> host(bytes);
+    XS_HIP(hipMemcpyAsync(host.data(), st->acc.p, bytes, hipMemcpyDeviceToHost, st->compute));
+    XS_HIP(hipStreamSynchronize(st->compute));
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE* f = std::fopen(tmp.c_str(), "wb");
+    if (!f) return fail(XS_ERR_ARG, std::string("cannot write ") + tmp);
+    const int64_t hdr[8] = {(int64_t)kCkptMagic, XS_ABI_VERSION, st->n_tp, p->geo.n_points, p->o.precision,
+                            st->chunks, st->lines, st->kept};
+    bool ok = std::fwrite(hdr, sizeof(hdr), 1, f) == 1;
+    ok = ok && std::fwrite(st->T.data(), sizeof(double), st->n_tp, f) == (size_t)st->n_tp;
+    ok = ok && std::fwrite(st->P.data(), sizeof(double), st->n_tp, f) == (size_t)st->n_tp;
+    ok = ok && std::fwrite(host.data(), 1, bytes, f) == bytes;
+    ok = (std::fclose(f) == 0) && ok;
+    if (!ok || std::rename(tmp.c_str(), path) != 0) {
+        std::remove(tmp.c_str());
+        return fail(XS_ERR_ARG, std::string("writing the checkpoint failed: ") + path);
+    }
+    return XS_OK;
+}
+
+xs_status xs_stream_resume(xs_plan* p, const char* path, void* sigma, void* stream, xs_stream** out) {
+    if (!out) return fail(XS_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (!p || !path || !sigma) return fail(XS_ERR_ARG, "NULL argument");
+    if (p->n_states <= 0) return fail(XS_ERR_STATE, "xs_set_states must come first");
+    FILE* f = std::fopen(path, "rb");
+    if (!f) return fail(XS_ERR_ARG, std::string("cannot read ") + path);
+    int64_t hdr[8];
+    if (std::fread(hdr, sizeof(hdr), 1, f) != 1 || hdr[0] != (int64_t)kCkptMagic || hdr[1] != XS_ABI_VERSION) {
+        std::fclose(f);
+        return fail(XS_ERR_ARG, "not a checkpoint of this library version");
+    }
+    const int n_tp = (int)hdr[2];
+    if (n_tp <= 0 || hdr[3] != p->geo.n_points || hdr[4] != p->o.precision) {
+        std::fclose(f);
+        return fail(XS_ERR_ARG, "the checkpoint's grid or precision differs from the plan's");
+    }
+    std::vector<double> T(n_tp), P(n_tp);
+    const size_t bytes = (size_t)n_tp * p->geo.n_points * 2 * stream_elem(p);
+    std::vector<char> host(bytes);
+    bool ok = std::fread(T.data(), sizeof(double), n_tp, f) == (size_t)n_tp &&
+              std::fread(P.data(), sizeof(double), n_tp, f) == (size_t)n_tp &&
+              std::fread(host.data(), 1, bytes, f) == bytes;
+    std::fclose(f);
+    if (!ok) return fail(XS_ERR_ARG, "truncated checkpoint");
+    XS_TRY(validate_tp(n_tp, T.data(), P.data()));
+    xs_stream* st = nullptr;
+    XS_TRY(stream_create(p, n_tp, T.data(), P.data(), sigma, stream, &st));
+    hipError_t e = hipMemcpyAsync(st->acc.p, host.data(), bytes, hipMemcpyHostToDevice, st->compute);
+    if (e == hipSuccess) e = hipStreamSynchronize(st->compute);
+    if (e != hipSuccess) { stream_free(st); return hip_fail(e, "checkpoint upload"); }
+    st->chunks = hdr[5];
+    st->lines = hdr[6];
+    st->kept = hdr[7];
+    *out = st;
+    return XS_OK;
+}
+
+xs_status xs_stream_stats(const xs_stream* st, int64_t out[3]) {
+    if (!st || !out) return fail(XS_ERR_ARG, "NULL argument");
+    out[0] = st->chunks;
+    out[1] = st->lines;
+    out[2] = st->kept;
     return XS_OK;
 }
 

@@ -49,6 +49,12 @@ hipError_t launch_forward(int profile, int fp64, int waves, int slices_per_wave,
 // n_split > 1: sigma[t][k] = compensated sum over parts of part[t][*][k]
 hipError_t launch_combine(int fp64, const FwdArgs& a, hipStream_t s);
 
+// Streaming accumulators: acc holds n (sum, compensation) pairs, float2 (FP32) or
+// double2 (FP64); add TwoSums x[i] into acc[i]; finish writes sum + compensation.
+hipError_t launch_acc_zero(int fp64, void* acc, int64_t n, hipStream_t s);
+hipError_t launch_acc_add(int fp64, const void* x, void* acc, int64_t n, hipStream_t s);
+hipError_t launch_acc_finish(int fp64, const void* acc, void* out, int64_t n, hipStream_t s);
+
 // Core pre-pass (FP32 Voigt): radius/count per line, per-256-line block totals.
 struct CoreArgs {
     SortedLines L;

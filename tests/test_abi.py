@@ -87,3 +87,17 @@ def test_graph_and_tuning_calls_reject_null_plans_on_host():
     assert lib.xs_graph_destroy(None) == 0
     assert lib.xs_set_tile_config(None, 4, 2, 0, 0) == 1
     assert lib.xs_autotune(None, 1, T, P, 10.0, None, None) == 1
+
+
+def test_stream_calls_reject_null_arguments_on_host():
+    from paper_1801_09803_amd.binding import load_library
+    lib = load_library()
+    h = ctypes.c_void_p()
+    T = (ctypes.c_double * 1)(296.0)
+    P = (ctypes.c_double * 1)(1.0)
+    assert lib.xs_stream_begin(None, 1, T, P, None, None, ctypes.byref(h)) == 1 and not h.value
+    assert lib.xs_stream_chunk(None, 0, None, None, None, None, None) == 1
+    assert lib.xs_stream_end(None, None) == 1
+    assert lib.xs_stream_checkpoint(None, b"x") == 1
+    assert lib.xs_stream_resume(None, b"x", None, None, ctypes.byref(h)) == 1 and not h.value
+    assert lib.xs_stream_stats(None, None) == 1
