@@ -371,6 +371,9 @@ xs::TPParam make_tp(const xs_plan* p, double T, double P, int iq, double T_rm) {
     tp.iq = iq;
     const double rmd = rm_steps(p, T_rm);
     tp.rm = rmd > 1.0e9 ? 1000000000 : (int)std::ceil(rmd);
+    // the same radius for a line of wavenumber nu: xr alpha_D(nu) / (sqrt(ln2) dnu)
+    const double xr = p->o.profile == XS_VOIGT ? 40.0 : p->o.profile == XS_DOPPLER ? 10.5 : 0.0;
+    tp.rm_scale = xr * beta_of(p->o, T_rm) / (xs::kSQRT_LN2 * p->geo.dnu);
     return tp;
 }
 

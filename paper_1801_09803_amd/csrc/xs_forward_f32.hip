@@ -19,6 +19,8 @@
 //   [w0 - hmax, w1 - hmin)  window ends inside the wave:   wing formula + upper mask
 //   [w1 - hmin, w0 - rm)    covers the wave, wings only:   wing formula, no branches
 //   [w0 - rm,   w1 + rm]    centre near the wave:          per-slice zone (scalar branch)
+// (rm: radius beyond which every point of the wave is in the far zone, from the largest
+// Doppler width a line of the centre-near run can have, so it shrinks at low wavenumber)
 //   (w1 + rm,  w0 + hmin]   covers the wave, wings only:   wing formula, no branches
 //   (w0 + hmin, w1 + hmax]  window starts inside the wave: wing formula + lower mask
 // Coarse grids use per-slice codes (skip / zone / mask) for every line instead.
@@ -296,7 +298,15 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
     const int b5 = off_at(A.off, (int64_t)t1 + G.hmax + 1, G);
     const int bstride = NT * A.n_split;
     const int bfirst = b0 + NT * wi.part;
-    const int rm = tp.rm;
+    int rm = tp.rm;
+    if (SEG && tp.rm_scale > 0.0) {
+        // the centre-near run holds lines with kc within rm of the wave, i.e. wavenumbers
+        // inside [nlo, nhi]; their Doppler widths, hence the radius, are bounded there
+        const double nlo = G.nu_a + ((double)w0 - rm - 1) * G.dnu;
+        const double nhi = G.nu_a + ((double)w1 + rm + 1) * G.dnu;
+        const double rw = ceil(tp.rm_scale * fmax(fabs(nlo), fabs(nhi))) + 2.0;
+        if (rw < (double)rm) rm = __builtin_amdgcn_readfirstlane((int)rw);
+    }
     int s0 = 0, s1 = 0, s2 = 0, s3 = 0, s4 = 0, s5 = 0;
     if (SEG) {
         s0 = off_at(A.off, (int64_t)w0 - G.hmax, G);

@@ -55,6 +55,8 @@ struct TPParam {
     double beta;          // alpha_D / nu  (Eq. 16)
     double ln_T0_T;       // ln(T0 / T), for (T0/T)^n in Eq. 18
     double p_over_p0;     // P / P0
+    double rm_scale;      // radius per cm^-1 of line wavenumber (grid steps, Doppler-width
+                          // profiles; 0 when the radius does not grow with the wavenumber)
     int iq;               // index of T in the plan's device Q array
     int rm;               // bound on the mid/core radius in grid steps (FP32 Voigt fast path)
 };
