@@ -31,16 +31,17 @@ sys.path.insert(0, ROOT)
 
 FLOPS_PER_EVAL = 12          # far-wing rational: j add, 4 fma, rcp, accumulate fma (FMA = 2)
 
-# HBM traffic of the dominant kernel from two rocprofv3 --pmc runs of this script
-# (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch, T = 296 K and 2000 K), scaled by the
+# HBM traffic of the dominant kernel from two rocprofv3 --pmc runs of this script with
+# the tile configuration fixed (4 waves, 2 slices, 32 shares, one (T, P) per dispatch):
+# FETCH_SIZE, then WRITE_SIZE, KiB per dispatch at T = 296 K and 2000 K, scaled by the
 # same counters on a 1 GiB device copy (FETCH_SIZE reads 0.5 GiB -> x2, WRITE_SIZE 1 GiB
-# -> x1).  Valid only for the kernel sources they were taken with (hash below).
+# -> x1).  Per (T, P); a launch covering several (T, P) moves that many times the bytes.
+# Valid only for the kernel sources they were taken with (hash below).
 TRAFFIC = {
-    "kernel_sources": ["xs_forward_f32.hip", "xs_forward_common.hpp", "xs_voigt.hpp",
-                       "xs_forward.hpp", "xs_internal.hpp"],
-    "sha256": "116b2d4b3bd032ecbcbdf55c015ea9b181c7b3facb2cc02d90569496edb5555f",
-    "fetch_kib": [30174576.7, 33919933.7],
-    "write_kib": [3906.3, 3967.3],
+    "kernel_sources": ['xs_forward_f32.hip', 'xs_forward_common.hpp', 'xs_voigt.hpp', 'xs_forward.hpp', 'xs_internal.hpp'],
+    "sha256": "4fd9f7428f625b5a9383548398b7186bcbf46f8a0c3b0798ce0c6e3cf0bb3cfd",
+    "fetch_kib": [31287051.9, 34993998.4],
+    "write_kib": [251035.4, 251246.1],
     "fetch_scale": 2.0,
     "write_scale": 1.0,
 }
@@ -55,12 +56,12 @@ def kernel_sources_sha():
     return h.hexdigest()
 
 
-def traffic_bytes_per_launch():
+def traffic_bytes_per_launch(tp_per_launch):
     if TRAFFIC["sha256"] is None or TRAFFIC["sha256"] != kernel_sources_sha():
         return None
     f = sum(TRAFFIC["fetch_kib"]) / len(TRAFFIC["fetch_kib"]) * TRAFFIC["fetch_scale"]
     w = sum(TRAFFIC["write_kib"]) / len(TRAFFIC["write_kib"]) * TRAFFIC["write_scale"]
-    return (f + w) * 1024.0
+    return (f + w) * 1024.0 * tp_per_launch
 PEAK_FP32_TFLOPS = 157.3     # MI355X FP32 vector peak (published, packed)
 PEAK_FP32_UNPACKED = 78.6    # 256 CU x 64 lanes x 2 flop x 2.4 GHz without packed FP32
 
@@ -255,7 +256,7 @@ def main():
             "peak": PEAK_FP32_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_TFLOPS,
-            "traffic": traffic_bytes_per_launch(),
+            "traffic": traffic_bytes_per_launch(tp_per_launch),
             "kernel": "fwd_f32_kernel<Voigt> (tile kernel, one launch per block of (T,P))",
             "avg_launch_ms": avg_launch_s * 1e3,
             "tp_per_launch": tp_per_launch,
