@@ -273,7 +273,8 @@ xs_status xs_cross_section_adjoint(xs_plan* plan, double T, double P, const void
 typedef struct {
     double forward_ms;          /* tile kernels (one launch per block of (T, P)), and the
                                    adjoint kernel                                          */
-    double core_ms;             /* Voigt core pre-pass (count + evaluation)                */
+    double core_ms;             /* FP32 per-(line, T, P) pre-passes: Voigt core values
+                                   (count + evaluation) and line records                   */
     double prep_ms;             /* xs_set_lines device work                                */
     int64_t forward_launches;
     int64_t core_launches;

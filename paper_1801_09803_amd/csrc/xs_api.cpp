@@ -119,6 +119,7 @@ struct Workset {
     DevBuf rc, cnt, coff;     // core pre-pass rows [tp_block][n_kept]
     DevBuf bsum, tmp;         // per row: core count block sums, scan scratch
     DevBuf val;               // core values of one block of (T, P)
+    DevBuf hot, cold, xscale; // FP32 line records [tp_block][n_kept] (32 + 64 + 8 B per line)
     DevBuf part;              // per-part sums [tp_block][n_split][n_points] when n_split > 1
     DevBuf out;               // autotuner output scratch
     size_t bytes = 0;
@@ -128,7 +129,8 @@ struct Workset {
 
     xs_status ensure(DevBuf& b, size_t n, const char* what) { return dev_ensure(b, n, what, &bytes); }
     void release() {
-        DevBuf* all[] = {&T, &Q, &dQ, &qpart, &tps, &rc, &cnt, &coff, &bsum, &tmp, &val, &part, &out};
+        DevBuf* all[] = {&T, &Q, &dQ, &qpart, &tps, &rc, &cnt, &coff, &bsum, &tmp, &val, &hot, &cold, &xscale,
+                         &part, &out};
         for (DevBuf* b : all) dev_release(*b, &bytes);
         stage.release();
         rows = 0;
@@ -379,11 +381,18 @@ xs::TPParam make_tp(const xs_plan* p, double T, double P, int iq, double T_rm) {
 
 bool core_path(const xs_plan* p) { return p->o.precision == XS_FP32 && p->o.profile == XS_VOIGT; }
 
+bool fp32_path(const xs_plan* p) { return p->o.precision == XS_FP32; }
+
+// Bytes of per-(line, T, P) workspace: FP32 line records (104 B) and Voigt core rows (16 B).
+int64_t row_bytes_per_line(const xs_plan* p) {
+    return (fp32_path(p) ? 104 : 0) + (core_path(p) ? 16 : 0);
+}
+
 int pick_block(const xs_plan* p, int n_tp) {
     int B = p->tp_block > 0 ? p->tp_block : 8;
-    if (core_path(p) && p->tp_block <= 0) {
-        // core rows take 16 B per line and (T, P): keep them within 16 GiB
-        const int64_t cap = ((int64_t)16 << 30) / std::max<int64_t>(16 * p->n_kept, 1);
+    if (p->tp_block <= 0 && row_bytes_per_line(p) > 0) {
+        // keep the per-(T, P) rows of a block within 24 GiB
+        const int64_t cap = ((int64_t)24 << 30) / std::max<int64_t>(row_bytes_per_line(p) * p->n_kept, 1);
         B = (int)std::max<int64_t>(1, std::min<int64_t>(B, cap));
     }
     return std::max(1, std::min(B, n_tp));
@@ -414,6 +423,13 @@ bool seg_mode(const xs_plan* p, const xs::TPParam& tp) {
 // Core rows and per-part buffers for blocks of B (T, P) split S ways.
 xs_status ensure_rows(xs_plan* p, Workset& ws, int B, int S) {
     const int64_t n = std::max<int64_t>(p->n_kept, 1);
+    if (fp32_path(p)) {
+        XS_TRY(ws.ensure(ws.hot, (size_t)B * n * 8 * sizeof(float), "line records"));
+        XS_TRY(ws.ensure(ws.cold, (size_t)B * n * 16 * sizeof(int), "line records"));
+        XS_TRY(ws.ensure(ws.xscale, (size_t)B * n * sizeof(double), "line records"));
+        ws.rows = B;
+        ws.row_stride = n;
+    }
     if (core_path(p)) {
         const int64_t nb = xs::core_blocks(n);
         XS_TRY(ws.ensure(ws.rc, (size_t)B * n * sizeof(int), "core radii"));
@@ -483,13 +499,35 @@ xs::FwdArgs fwd_args(xs_plan* p, Workset& ws, const std::vector<xs::TPParam>& tp
     a.tile_order = (p->n_order == a.n_tiles && p->order_W == tile_width(p)) ? as<int>(p->tile_order) : nullptr;
     a.alpha_fixed = o.alpha_fixed;
     a.tab = as<xs::Tables>(p->tab_dev);
-    if (core_path(p)) {
-        a.core_rc = as<int>(ws.rc) + (int64_t)row0 * ws.row_stride;
-        a.core_off = as<long long>(ws.coff) + (int64_t)row0 * ws.row_stride;
+    if (fp32_path(p)) {
+        a.hot = as<float>(ws.hot) + (int64_t)row0 * ws.row_stride * 8;
+        a.cold = as<int>(ws.cold) + (int64_t)row0 * ws.row_stride * 16;
+        a.xscale = as<double>(ws.xscale) + (int64_t)row0 * ws.row_stride;
+        a.rec_stride = ws.row_stride;
         a.core_val = as<float>(ws.val);
-        a.core_stride = ws.row_stride;
     }
     return a;
+}
+
+// Line records of the call's (T, P) point `it` into row `row` (after its core values).
+xs::RecArgs rec_args(xs_plan* p, Workset& ws, int it, int row) {
+    xs::RecArgs r{};
+    const int64_t n = ws.row_stride;
+    r.L = sorted_lines(p);
+    r.G = p->geo;
+    r.tp = as<xs::TPParam>(ws.tps) + it;
+    r.Q = as<double>(ws.Q);
+    r.n_lines = (int)p->n_kept;
+    r.tab = as<xs::Tables>(p->tab_dev);
+    r.alpha_fixed = p->o.alpha_fixed;
+    if (core_path(p)) {
+        r.core_rc = as<int>(ws.rc) + row * n;
+        r.core_off = as<long long>(ws.coff) + row * n;
+    }
+    r.hot = as<float>(ws.hot) + row * n * 8;
+    r.cold = as<int>(ws.cold) + row * n * 16;
+    r.xscale = as<double>(ws.xscale) + row * n;
+    return r;
 }
 
 // Per-(T, P) parameters and temperatures to the device (through pinned staging), then
@@ -536,14 +574,17 @@ xs_status enqueue_block(xs_plan* p, Workset& ws, const std::vector<xs::TPParam>&
                         bool count, const std::vector<long long>& vbase, const std::vector<long long>& vend,
                         void* sigma, hipStream_t s, bool timed) {
     const bool fp64 = p->o.precision == XS_FP64;
-    if (core_path(p) && p->n_kept > 0) {
+    if (fp32_path(p) && p->n_kept > 0) {
         for (int t = 0; t < nb; ++t) {
-            xs::CoreArgs c = core_args(p, ws, f + t, t);
-            c.val_base = vbase[f + t];
-            c.val_end = vend[f + t];
             Timer tc(p, s, 1, 0, timed);
-            if (count) XS_HIP(xs::launch_core_count(c, s));
-            XS_HIP(xs::launch_core_eval(c, s));
+            if (core_path(p)) {
+                xs::CoreArgs c = core_args(p, ws, f + t, t);
+                c.val_base = vbase[f + t];
+                c.val_end = vend[f + t];
+                if (count) XS_HIP(xs::launch_core_count(c, s));
+                XS_HIP(xs::launch_core_eval(c, s));
+            }
+            XS_HIP(xs::launch_records(p->o.profile, rec_args(p, ws, f + t, t), s));
             tc.stop();
         }
     }
@@ -1029,13 +1070,16 @@ xs_status xs_autotune(xs_plan* p, int32_t n_tp, const double* T, const double* P
     XS_TRY(upload_tps(p, ws, tps, s, true));
     XS_TRY(ensure_rows(p, ws, ns, 1));
     std::vector<long long> vbase(ns, 0), vend(ns, 0);
-    if (core_path(p) && p->n_kept > 0) {
-        XS_TRY(count_block(p, ws, tps, 0, ns, s, vbase, vend));
+    if (core_path(p) && p->n_kept > 0) XS_TRY(count_block(p, ws, tps, 0, ns, s, vbase, vend));
+    if (fp32_path(p) && p->n_kept > 0) {
         for (int t = 0; t < ns; ++t) {
-            xs::CoreArgs c = core_args(p, ws, t, t);
-            c.val_base = vbase[t];
-            c.val_end = vend[t];
-            XS_HIP(xs::launch_core_eval(c, s));
+            if (core_path(p)) {
+                xs::CoreArgs c = core_args(p, ws, t, t);
+                c.val_base = vbase[t];
+                c.val_end = vend[t];
+                XS_HIP(xs::launch_core_eval(c, s));
+            }
+            XS_HIP(xs::launch_records(p->o.profile, rec_args(p, ws, t, t), s));
         }
     }
     const size_t elem = fp64 ? sizeof(double) : sizeof(float);

@@ -27,12 +27,32 @@ struct FwdArgs {
     const int* tile_order;  // tiles by decreasing line count (heaviest dispatched first), or NULL
     double alpha_fixed;     // HWHM for the fixed Gaussian
     const Tables* tab;      // device quadrature tables
-    // FP32 Voigt core pre-pass results, one row of n_lines per (T, P) of the block
-    const int* core_rc;             // core radius in grid steps (-1: none)
-    const long long* core_off;      // index in core_val of the value at the first core point
-    const float* core_val;          // a * Re w at the line's core points
-    int64_t core_stride;            // row stride of core_rc / core_off (>= n_lines)
+    // FP32 path: line records of record_kernel, one row of rec_stride lines per (T, P) of
+    // the launch (8 floats hot, 16 words cold, 1 double scale per line)
+    const float* hot;
+    const int* cold;
+    const double* xscale;
+    int64_t rec_stride;
+    const float* core_val;          // FP32 Voigt: a * Re w at the lines' core points
 };
+
+// Per-(line, T, P) records of the FP32 path (record_kernel).
+struct RecArgs {
+    SortedLines L;
+    Geometry G;
+    const TPParam* tp;              // device: this (T, P)
+    const double* Q;
+    int n_lines;
+    const Tables* tab;
+    double alpha_fixed;
+    const int* core_rc;             // Voigt: core radius per line (-1: none)
+    const long long* core_off;      // Voigt: index in core_val of the line's first core value
+    float* hot;                     // [n_lines][8]
+    int* cold;                      // [n_lines][16]
+    double* xscale;                 // [n_lines]
+};
+
+hipError_t launch_records(int profile, const RecArgs& a, hipStream_t s);
 
 // Work item of one workgroup: tiles in dispatch order, each tile's n_tp * n_split
 // workgroups consecutive (the same lines are read back to back from the caches).

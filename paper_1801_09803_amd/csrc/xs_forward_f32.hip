@@ -1,17 +1,25 @@
-// FP32 forward tile kernel (the hot loop of the sampling method: sigma_k = sum over
-// lines of I f(nu_k - nu_fi) within the cut-off; Sec. "Cross sections" Eq. 6-8,
-// Sec. "Standard line profiles and sampling method", Sec. "Off-set").
+// FP32 forward path: sigma_k = sum over lines of I f(nu_k - nu_fi) within the cut-off
+// (the sampling method; Sec. "Cross sections" Eq. 6-8, Sec. "Standard line profiles and
+// sampling method", Sec. "Off-set").
 //
-// One workgroup (4 wavefronts) owns a tile of 256*P consecutive grid points; each
-// wavefront owns P slices of 64 points (one point per lane per slice) with its sums
-// in registers, so no atomics touch the output.  Lines are sorted by their nearest
-// grid index kc; the lines overlapping a range of grid points are a contiguous index
-// range read from the offsets table.  The workgroup walks its tile's line range in
-// batches of 256:
-//   1. each thread prepares one line in double precision (intensity Eq. 1 with Q(T)
-//      from the device, Doppler width Eq. 16, Lorentz width Eq. 18, offset of the
-//      centre from its anchor grid point) into an LDS record of f32 coefficients;
-//   2. each wavefront sweeps the batch, reading records by broadcast.
+// record_kernel, once per (line, T, P): the double-precision line setup (intensity Eq. 1
+// with Q(T) from the device, Doppler width Eq. 16, Lorentz width Eq. 18, offset of the
+// centre from its nearest grid point) reduced to single-precision coefficients:
+//   hot record (8 words) -- what the wing loops read for every line;
+//   cold record (16 words) -- zone radii, core-value range and offset, 4-node
+//     coefficients, the Gauss-Hermite profile parameters: read for lines whose centre is
+//     near the tile;
+//   scale (double) -- x per cm^-1 of offset, for the per-tile anchors.
+//
+// fwd_f32_kernel: a workgroup (WAVES wavefronts) owns a tile of 64*WAVES*P consecutive
+// grid points; each wavefront owns P slices of 64 points (one point per lane per slice)
+// with its sums in registers, so no atomics touch the output.  Lines are sorted by their
+// nearest grid index kc; the lines overlapping a tile are a contiguous range of the sorted
+// list, and workgroup q of the n_split sharing a tile takes its LDS batches q, q+n_split,..
+// Per batch of 64*WAVES lines: the hot records are copied to LDS (coalesced), each thread
+// adds its line's tile fields (grid offset, per-wavefront anchors or per-slice codes) and,
+// for lines centred near the tile, the cold record; the wavefronts then sweep the batch
+// reading records by broadcast.
 //
 // Segmented sweep (grids fine enough that 64P + r_mid < the half window): every
 // wavefront splits the sorted lines by kc into five contiguous runs relative to its
@@ -19,77 +27,60 @@
 //   [w0 - hmax, w1 - hmin)  window ends inside the wave:   wing formula + upper mask
 //   [w1 - hmin, w0 - rm)    covers the wave, wings only:   wing formula, no branches
 //   [w0 - rm,   w1 + rm]    centre near the wave:          per-slice zone (scalar branch)
-// (rm: radius beyond which every point of the wave is in the far zone, from the largest
-// Doppler width a line of the centre-near run can have, so it shrinks at low wavenumber)
 //   (w1 + rm,  w0 + hmin]   covers the wave, wings only:   wing formula, no branches
 //   (w0 + hmin, w1 + hmax]  window starts inside the wave: wing formula + lower mask
+// (rm: radius beyond which every point of the wave is in the far zone, from the largest
+// Doppler width a line of the centre-near run can have, so it shrinks at low wavenumber)
 // Coarse grids use per-slice codes (skip / zone / mask) for every line instead.
 //
 // Voigt zones (|z| = |x + iy|): wings |z| >= 40 use the 2-node Gauss-Hermite rational
 // (6 FMA + 1 reciprocal per point); 8 <= |z| < 40 the 4-node rule; points with |z| < 8
 // take the value the double-precision core pre-pass stored for them.
-// x is formed as fma(j, h, xc) from the exact integer offset j = k - kc, so its relative
-// error stays ~1e-7 however far the point is from the centre.  Partial sums are
-// flushed every 64 lines into a compensated (TwoSum) pair.
+// x is formed as fma(j, h, xc) from the exact integer offset j = k - kc, or in the wing
+// runs as fma(k - k_anchor, h, x_anchor) from an anchor at the wavefront end nearest the
+// centre (computed in double), so its relative error stays ~1e-7 however far the point is
+// from the centre.  Partial sums are flushed every 64 lines into a compensated (TwoSum) pair.
 #include "xs_forward_common.hpp"
 
 namespace xs {
 
 namespace {
 
-constexpr int kRec = 32;     // record size in 4-byte words (128 B); one line per thread
+// hot record words
+enum : int { H_H = 0, H_C0 = 1, H_C1 = 2, H_AMP = 3, H_B = 4, H_XC = 5, H_JLO = 6, H_JHI = 7 };
+// cold record words (ints unless noted; C_CBASE is int64, C_M 8 floats)
+enum : int { C_CSC = 0, C_KC = 1, C_RAD = 2, C_KCL = 3, C_KCH = 4, C_FLAG = 5, C_CBASE = 6, C_M = 8 };
+constexpr int kHot = 8;
+constexpr int kCold = 16;
 
-enum : int {
-    R_XC = 0, R_H = 1, R_C0 = 2, R_C1 = 3, R_AMP = 4, R_B = 5, R_SB0 = 6, R_CSC = 7,
-    R_JLO = 8, R_JHI = 9, R_KCL = 10, R_KCH = 11, R_RAD = 12, R_SB0I = 13,
-    R_CBASE = 14,    // int64 (words 14-15): core value index = cbase + k
-    R_M = 16,        // 4-node mid zone: cp1, cd1, A1, B1, cp2, cd2, A2, B2
-    R_ANC = 24,      // per-wavefront anchor x at the wave end nearest the centre (<= 8 waves)
-    R_CODE = 24      // coded sweep: 4-bit per-slice codes (<= 32 slices), shares the anchor words
-};
-
-// The caller's line data one thread needs to prepare a line record (prefetched a
-// batch ahead so the global loads overlap the sweep).
-struct RawLine {
-    double nu, elow, cA;
-    float gref, nexp;
-    int kc, klo, khi, rc;
-    long long coff;
-};
-
+// ------------------------------------------------------------------ record kernel
 template <int PROF>
-__device__ __forceinline__ RawLine load_raw(const FwdArgs& A, const int* crc, const long long* coff, int g) {
-    RawLine w;
-    w.nu = A.L.nu[g];
-    w.elow = A.L.elow[g];
-    w.cA = A.L.cA[g];
-    w.gref = A.L.gref[g];
-    w.nexp = A.L.nexp[g];
-    w.kc = A.L.kc[g];
-    w.klo = A.L.klo[g];
-    w.khi = A.L.khi[g];
-    if (PROF == kVoigt) { w.rc = crc[g]; w.coff = coff[g]; }
-    else { w.rc = -1; w.coff = 0; }
-    return w;
-}
-
-template <int PROF, int WAVES, int P>
-__device__ __forceinline__ void prepare_line(const FwdArgs& A, const TPParam& tp, const Geometry& G,
-                                             const RawLine& w, double Q, int t0, bool codes, float* r) {
-    constexpr int NS = WAVES * P;
-    const double T = tp.T;
+__global__ __launch_bounds__(256) void record_kernel(const RecArgs A) {
+    const int g = blockIdx.x * 256 + threadIdx.x;
+    if (g >= A.n_lines) return;
+    const TPParam tp = *A.tp;
+    const Geometry G = A.G;
+    const double Q = A.Q[tp.iq];
+    const double nu = A.L.nu[g];
+    const int kc = A.L.kc[g], klo = A.L.klo[g], khi = A.L.khi[g];
     // Eq. 1: I = [g_f A/(8 pi c nu^2)] exp(-c2 E_i/T) (1 - exp(-c2 nu/T)) / Q(T)
-    const double S = w.cA * exp(-(kC2 * w.elow) / T) * (-expm1(-(kC2 * w.nu) / T)) / Q;
-    const double aD = w.nu * tp.beta;                                              // Eq. 16
-    const double gam = (double)w.gref * exp((double)w.nexp * tp.ln_T0_T) * tp.p_over_p0;  // Eq. 18
-    const double d = (G.nu_a + (double)w.kc * G.dnu) - w.nu;   // anchor offset nu_kc - nu
-    int* ri = reinterpret_cast<int*>(r);
-    r[R_SB0] = (float)(t0 - w.kc);
-    ri[R_SB0I] = t0 - w.kc;
-    r[R_JLO] = (float)(w.klo - w.kc);
-    r[R_JHI] = (float)(w.khi - w.kc);
-    int kcl = 0, kch = -1, rad = -1;
-    double hd = 0.0, xd = 0.0;      // double-precision h and xc (scaled), for anchors
+    const double S = A.L.cA[g] * exp(-(kC2 * A.L.elow[g]) / tp.T) * (-expm1(-(kC2 * nu) / tp.T)) / Q;
+    const double aD = nu * tp.beta;                                                               // Eq. 16
+    const double gam = (double)A.L.gref[g] * exp((double)A.L.nexp[g] * tp.ln_T0_T) * tp.p_over_p0;  // Eq. 18
+    const double d = (G.nu_a + (double)kc * G.dnu) - nu;   // centre offset nu_kc - nu
+    float h[kHot];
+    int c[kCold];
+    float* cf = reinterpret_cast<float*>(c);
+#pragma unroll
+    for (int i = 0; i < kHot; ++i) h[i] = 0.0f;
+#pragma unroll
+    for (int i = 0; i < kCold; ++i) c[i] = 0;
+    h[H_JLO] = (float)(klo - kc);
+    h[H_JHI] = (float)(khi - kc);
+    c[C_KC] = kc;
+    c[C_RAD] = -1;
+    c[C_KCH] = -1;
+    double scale;
     if (PROF == kVoigt) {
         const double s = kSQRT_LN2 / aD;
         const double y = gam * s;
@@ -102,147 +93,126 @@ __device__ __forceinline__ void prepare_line(const FwdArgs& A, const TPParam& tp
         const double sc = ldexp(1.0, -e), sc2 = sc * sc;
         const double y2 = y * y;
         const double ampf = a * y * kINV_SQRT_PI;
-        hd = s * G.dnu * sc;
-        xd = s * d * sc;
-        r[R_XC] = (float)xd;
-        r[R_H] = (float)hd;
-        r[R_C0] = (float)((y2 - 0.5) * sc2);
-        r[R_C1] = (float)(2.0 * y2 * sc2 * sc2);
-        r[R_AMP] = (float)(ampf * sc2);
-        r[R_B] = (float)(ampf * sc2 * sc2);
-        r[R_CSC] = (float)ldexp(1.0, e);
+        scale = s * sc;
+        h[H_XC] = (float)(scale * d);
+        h[H_H] = (float)(scale * G.dnu);
+        h[H_C0] = (float)((y2 - 0.5) * sc2);
+        h[H_C1] = (float)(2.0 * y2 * sc2 * sc2);
+        h[H_AMP] = (float)(ampf * sc2);
+        h[H_B] = (float)(ampf * sc2 * sc2);
+        cf[C_CSC] = (float)ldexp(1.0, e);
 #pragma unroll
         for (int jp = 0; jp < 2; ++jp) {
             const double t2 = A.tab->gh4.t[jp] * A.tab->gh4.t[jp];
             const double Aj = a * (y / kPI) * 2.0 * A.tab->gh4.w[jp];
-            r[R_M + 4 * jp + 0] = (float)(y2 - t2);
-            r[R_M + 4 * jp + 1] = (float)(4.0 * t2 * y2);
-            r[R_M + 4 * jp + 2] = (float)Aj;
-            r[R_M + 4 * jp + 3] = (float)(Aj * 2.0 * t2);
+            cf[C_M + 4 * jp + 0] = (float)(y2 - t2);
+            cf[C_M + 4 * jp + 1] = (float)(4.0 * t2 * y2);
+            cf[C_M + 4 * jp + 2] = (float)Aj;
+            cf[C_M + 4 * jp + 3] = (float)(Aj * 2.0 * t2);
         }
-        rad = y2 < kMidR2 ? radius_steps(sqrt(kMidR2 - y2), s * G.dnu, s * d) : -1;
-        if (w.rc >= 0) {
-            const int64_t lo = (int64_t)w.kc - w.rc, hi = (int64_t)w.kc + w.rc;
-            kcl = (int)(lo > w.klo ? lo : w.klo);
-            kch = (int)(hi < w.khi ? hi : w.khi);
+        c[C_RAD] = y2 < kMidR2 ? radius_steps(sqrt(kMidR2 - y2), s * G.dnu, s * d) : -1;
+        const int rc = A.core_rc[g];
+        int kcl = 0, kch = -1;
+        if (rc >= 0) {
+            const int64_t lo = (int64_t)kc - rc, hi = (int64_t)kc + rc;
+            kcl = (int)(lo > klo ? lo : klo);
+            kch = (int)(hi < khi ? hi : khi);
         }
-        *reinterpret_cast<long long*>(r + R_CBASE) = w.coff - (long long)kcl;
+        c[C_KCL] = kcl;
+        c[C_KCH] = kch;
+        const long long cb = A.core_off[g] - (long long)kcl;
+        c[C_CBASE] = (int)(unsigned)(cb & 0xffffffffll);
+        c[C_CBASE + 1] = (int)(cb >> 32);
     } else if (PROF == kLorentz) {
         const double ig = gam > 0.0 ? 1.0 / gam : 0.0;
-        hd = G.dnu * ig;
-        xd = d * ig;
-        r[R_XC] = (float)xd;
-        r[R_H] = (float)hd;
-        r[R_AMP] = (float)(S * ig * (1.0 / kPI));
+        scale = ig;
+        h[H_XC] = (float)(d * ig);
+        h[H_H] = (float)(G.dnu * ig);
+        h[H_AMP] = (float)(S * ig * (1.0 / kPI));
+        c[C_FLAG] = gam > 0.0 ? 1 : 0;
     } else if (PROF == kGHSampled || PROF == kGHBinned) {
         // Gauss-Hermite convolution (Eq. 30-31 as read): nodes shift the Lorentzian by
         // delta_j = alpha_D t_j / sqrt(ln 2); work in wavenumber units D = nu_k - nu
-        r[R_XC] = (float)d;
-        r[R_H] = (float)G.dnu;
-        r[R_M + 0] = (float)(gam * gam);
-        r[R_M + 1] = (float)(aD / kSQRT_LN2);
+        scale = 1.0;
+        h[H_XC] = (float)d;
+        h[H_H] = (float)G.dnu;
+        cf[C_M + 0] = (float)(gam * gam);
+        cf[C_M + 1] = (float)(aD / kSQRT_LN2);
         if (PROF == kGHSampled) {
-            r[R_AMP] = (float)(S * gam / (kPI * 1.7724538509055160273));   // S gamma / pi^(3/2)
-            r[R_M + 2] = (float)(4.0 * gam * gam);
+            h[H_AMP] = (float)(S * gam / (kPI * 1.7724538509055160273));   // S gamma / pi^(3/2)
+            cf[C_M + 2] = (float)(4.0 * gam * gam);
         } else {
-            r[R_AMP] = (float)(S / (kPI * 1.7724538509055160273 * G.dnu));   // S / (pi^(3/2) dnu)
-            r[R_M + 3] = (float)(G.dnu * gam);
-            r[R_M + 4] = (float)(gam * gam - 0.25 * G.dnu * G.dnu);
+            h[H_AMP] = (float)(S / (kPI * 1.7724538509055160273 * G.dnu));   // S / (pi^(3/2) dnu)
+            cf[C_M + 3] = (float)(G.dnu * gam);
+            cf[C_M + 4] = (float)(gam * gam - 0.25 * G.dnu * G.dnu);
         }
+        c[C_FLAG] = gam > 0.0 ? 1 : 0;
     } else {
         // Gaussian (Eq. 15); x scaled by sqrt(1/ln 2) so exp(-x^2) = exp2(-x'^2)
         const double alpha = (PROF == kDoppler) ? aD : A.alpha_fixed;
         const double s = kSQRT_LN2 / alpha;
-        const double sl = s * 1.2011224087864498;
-        r[R_XC] = (float)(sl * d);
-        r[R_H] = (float)(sl * G.dnu);
-        r[R_AMP] = (float)(S * kSQRT_LN2_PI / alpha);
-        rad = radius_steps(10.5, s * G.dnu, s * d);   // exp(-x^2) underflows beyond
+        scale = s * 1.2011224087864498;
+        h[H_XC] = (float)(scale * d);
+        h[H_H] = (float)(scale * G.dnu);
+        h[H_AMP] = (float)(S * kSQRT_LN2_PI / alpha);
+        c[C_RAD] = radius_steps(10.5, s * G.dnu, s * d);   // exp(-x^2) underflows beyond
     }
-    ri[R_KCL] = kcl;
-    ri[R_KCH] = kch;
-    ri[R_RAD] = rad;
-    if (!codes) {
-        // x at the end of each wavefront's range nearest the centre: wing points are then
-        // x = anchor + (k - k_anchor) h with both terms of one sign
+    float4* ho = reinterpret_cast<float4*>(A.hot + (int64_t)g * kHot);
+    ho[0] = make_float4(h[0], h[1], h[2], h[3]);
+    ho[1] = make_float4(h[4], h[5], h[6], h[7]);
+    int4* co = reinterpret_cast<int4*>(A.cold + (int64_t)g * kCold);
 #pragma unroll
-        for (int wv = 0; wv < WAVES; ++wv) {
-            const int wa = t0 + 64 * P * wv;
-            const int ka = wa > w.kc ? wa : wa + 64 * P - 1;
-            r[R_ANC + wv] = (float)__builtin_fma((double)(ka - w.kc), hd, xd);
-        }
-    } else {
-        unsigned cw[(NS + 7) / 8];
-#pragma unroll
-        for (int q = 0; q < (NS + 7) / 8; ++q) cw[q] = 0;
-#pragma unroll
-        for (int sl = 0; sl < NS; ++sl) {
-            const int kA = t0 + 64 * sl, kB = kA + 63;
-            unsigned code = 0;
-            if (!(kB < w.klo || kA > w.khi)) {
-                const bool full = (kA >= w.klo && kB <= w.khi);
-                unsigned zone = 1;
-                if (PROF == kVoigt) {
-                    if (kA <= kch && kB >= kcl) zone = 3;
-                    else if (rad >= 0 && (int64_t)kA <= (int64_t)w.kc + rad && (int64_t)kB >= (int64_t)w.kc - rad) zone = 2;
-                } else if (PROF == kLorentz || PROF == kGHSampled) {
-                    zone = gam > 0.0 ? 1u : 0u;
-                } else if (PROF == kGHBinned) {
-                    zone = 1u;
-                } else {
-                    zone = ((int64_t)kA <= (int64_t)w.kc + rad && (int64_t)kB >= (int64_t)w.kc - rad) ? 1u : 0u;
-                }
-                code = zone ? (zone | (full ? 0u : 4u)) : 0u;
-            }
-            cw[sl / 8] |= code << (4 * (sl % 8));
-        }
-#pragma unroll
-        for (int q = 0; q < (NS + 7) / 8; ++q) r[R_CODE + q] = __uint_as_float(cw[q]);
-    }
+    for (int q = 0; q < 4; ++q) co[q] = make_int4(c[4 * q], c[4 * q + 1], c[4 * q + 2], c[4 * q + 3]);
+    A.xscale[g] = scale;
 }
+
+// ------------------------------------------------------------------ tile kernel
+// LDS image of one batch: hot records (AoS, copied as float4), per-line tile fields and
+// cold fields (one array per field, indexed by the line's place in the batch).
+template <int NT, int NTF>
+struct Lds {
+    float4 hot[2 * NT];
+    float sb0[NT];          // t0 - kc
+    float tf[NTF * NT];     // anchors per wavefront (segmented sweep) or slice-code words
+    float csc[NT];
+    int kc[NT], rad[NT], kcl[NT], kch[NT];
+    long long cb[NT];
+    float m[8 * NT];
+};
 
 // wing formula (2-node rule, scaled variables)
 __device__ __forceinline__ float v_far(const float* r, float j) {
-    const float x = __builtin_fmaf(j, r[R_H], r[R_XC]);
-    const float pp = __builtin_fmaf(x, x, r[R_C0]);
-    const float den = __builtin_fmaf(pp, pp, r[R_C1]);
-    const float num = __builtin_fmaf(pp, r[R_AMP], r[R_B]);
+    const float x = __builtin_fmaf(j, r[H_H], r[H_XC]);
+    const float pp = __builtin_fmaf(x, x, r[H_C0]);
+    const float den = __builtin_fmaf(pp, pp, r[H_C1]);
+    const float num = __builtin_fmaf(pp, r[H_AMP], r[H_B]);
     return num * __builtin_amdgcn_rcpf(den);
 }
 
-// 4-node rule (unscaled x)
-__device__ __forceinline__ float v_mid(const float* r, float j) {
-    const float x = __builtin_fmaf(j, r[R_H], r[R_XC]) * r[R_CSC];
-    const float p1 = __builtin_fmaf(x, x, r[R_M + 0]);
-    const float p2 = __builtin_fmaf(x, x, r[R_M + 4]);
-    const float d1 = __builtin_fmaf(p1, p1, r[R_M + 1]);
-    const float d2 = __builtin_fmaf(p2, p2, r[R_M + 5]);
-    const float n1 = __builtin_fmaf(p1, r[R_M + 2], r[R_M + 3]);
-    const float n2 = __builtin_fmaf(p2, r[R_M + 6], r[R_M + 7]);
+// 4-node rule (unscaled x); m points at the line's first coefficient, stride NT
+template <int NT>
+__device__ __forceinline__ float v_mid(const float* r, const float* m, float csc, float j) {
+    const float x = __builtin_fmaf(j, r[H_H], r[H_XC]) * csc;
+    const float p1 = __builtin_fmaf(x, x, m[0 * NT]);
+    const float p2 = __builtin_fmaf(x, x, m[4 * NT]);
+    const float d1 = __builtin_fmaf(p1, p1, m[1 * NT]);
+    const float d2 = __builtin_fmaf(p2, p2, m[5 * NT]);
+    const float n1 = __builtin_fmaf(p1, m[2 * NT], m[3 * NT]);
+    const float n2 = __builtin_fmaf(p2, m[6 * NT], m[7 * NT]);
     return __builtin_fmaf(n1, __builtin_amdgcn_rcpf(d1), n2 * __builtin_amdgcn_rcpf(d2));
 }
 
-// core slice: stored value inside [kcl, kch], 4-node rule elsewhere
-__device__ __forceinline__ float v_core(const FwdArgs& A, const float* r, float j, int k) {
-    const int* ri = reinterpret_cast<const int*>(r);
-    const float vm = v_mid(r, j);
-    const long long cb = *reinterpret_cast<const long long*>(r + R_CBASE);
-    const bool in = (k >= ri[R_KCL]) && (k <= ri[R_KCH]);
-    float vc = 0.0f;
-    if (in) vc = A.core_val[cb + k];
-    return in ? vc : vm;
-}
-
 __device__ __forceinline__ float v_lor(const float* r, float j) {
-    const float x = __builtin_fmaf(j, r[R_H], r[R_XC]);
-    return r[R_AMP] * __builtin_amdgcn_rcpf(__builtin_fmaf(x, x, 1.0f));
+    const float x = __builtin_fmaf(j, r[H_H], r[H_XC]);
+    return r[H_AMP] * __builtin_amdgcn_rcpf(__builtin_fmaf(x, x, 1.0f));
 }
 
 // Gauss-Hermite sum of shifted Lorentzians, node pairs +-t_j:
 // L(D - dj) + L(D + dj) = (gamma/pi) 2 (D^2 + g^2 + dj^2) / ((D^2 + g^2 - dj^2)^2 + 4 dj^2 g^2)
-__device__ __forceinline__ float v_ghs(const Tables* tab, const float* r, float j) {
-    const float D = __builtin_fmaf(j, r[R_H], r[R_XC]);
-    const float g2 = r[R_M + 0], ad = r[R_M + 1], g4 = r[R_M + 2];
+template <int NT>
+__device__ __forceinline__ float v_ghs(const Tables* tab, const float* r, const float* m, float j) {
+    const float D = __builtin_fmaf(j, r[H_H], r[H_XC]);
+    const float g2 = m[0], ad = m[NT], g4 = m[2 * NT];
     const float D2 = __builtin_fmaf(D, D, g2);
     float acc = 0.0f;
 #pragma unroll
@@ -254,24 +224,86 @@ __device__ __forceinline__ float v_ghs(const Tables* tab, const float* r, float 
         const float den = __builtin_fmaf(p, p, g4 * d2);
         acc = __builtin_fmaf(2.0f * tab->wconvf[kGHConv / 2 + q] * (D2 + d2), __builtin_amdgcn_rcpf(den), acc);
     }
-    return r[R_AMP] * acc;
+    return r[H_AMP] * acc;
 }
 
 // bin-averaged Gauss-Hermite Voigt: atan(y+) - atan(y-) = atan2(dnu g, (D - dj)^2 + g^2 - dnu^2/4)
-__device__ __forceinline__ float v_ghb(const Tables* tab, const float* r, float j) {
-    const float D = __builtin_fmaf(j, r[R_H], r[R_XC]);
-    const float ad = r[R_M + 1], hg = r[R_M + 3], c = r[R_M + 4];
+template <int NT>
+__device__ __forceinline__ float v_ghb(const Tables* tab, const float* r, const float* m, float j) {
+    const float D = __builtin_fmaf(j, r[H_H], r[H_XC]);
+    const float ad = m[NT], hg = m[3 * NT], c = m[4 * NT];
     float acc = 0.0f;
     for (int q = 0; q < kGHConv; ++q) {
         const float e = D - ad * tab->tconvf[q];
         acc = __builtin_fmaf(tab->wconvf[q], atan2f(hg, __builtin_fmaf(e, e, c)), acc);
     }
-    return r[R_AMP] * acc;
+    return r[H_AMP] * acc;
 }
 
 __device__ __forceinline__ float v_gauss(const float* r, float j) {
-    const float x = __builtin_fmaf(j, r[R_H], r[R_XC]);
-    return r[R_AMP] * __builtin_amdgcn_exp2f(-x * x);
+    const float x = __builtin_fmaf(j, r[H_H], r[H_XC]);
+    return r[H_AMP] * __builtin_amdgcn_exp2f(-x * x);
+}
+
+// Branch-free wing loop over sorted lines [lo, hi) of the batch starting at bs:
+// x = anchor + (k - k_anchor) h, with jd[p] = k - k_anchor of this lane's points.
+template <int PROF, int P>
+__device__ __forceinline__ void wing_run(const float* hot, const float* anc, int bs, int lo, int hi,
+                                         const float (&jd)[P], float (&part)[P]) {
+#pragma unroll 2
+    for (int l = lo; l < hi; ++l) {
+        const float* r = hot + (l - bs) * kHot;
+        const float4 h0 = *reinterpret_cast<const float4*>(r);
+        const float xa = anc[l - bs];
+        const float h = h0.x;
+        if (PROF == kVoigt) {
+            const float c0 = h0.y, c1 = h0.z, amp = h0.w, bb = r[H_B];
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                const float x = __builtin_fmaf(jd[p], h, xa);
+                const float pp = __builtin_fmaf(x, x, c0);
+                const float den = __builtin_fmaf(pp, pp, c1);
+                const float num = __builtin_fmaf(pp, amp, bb);
+                part[p] = __builtin_fmaf(num, __builtin_amdgcn_rcpf(den), part[p]);
+            }
+        } else {
+            const float amp = h0.w;
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                const float x = __builtin_fmaf(jd[p], h, xa);
+                part[p] = __builtin_fmaf(amp, __builtin_amdgcn_rcpf(__builtin_fmaf(x, x, 1.0f)), part[p]);
+            }
+        }
+    }
+}
+
+// The next batch's global data of one thread: two float4 of the hot records (chunks
+// tid and NT + tid of the batch) and its own line's offset data.
+struct Prefetch {
+    float4 h0, h1;
+    int kc;
+    double nu, scale;
+};
+
+template <int NT>
+__device__ __forceinline__ Prefetch load_batch(const FwdArgs& A, const float4* ghot, const double* gscale, int bs,
+                                               int b5, int tid) {
+    Prefetch f;
+    f.h0 = make_float4(0.f, 0.f, 0.f, 0.f);
+    f.h1 = f.h0;
+    f.kc = 0;
+    f.nu = 0.0;
+    f.scale = 0.0;
+    const int64_t c0 = 2 * (int64_t)bs + tid, c1 = c0 + NT, cend = 2 * (int64_t)b5;
+    if (c0 < cend) f.h0 = ghot[c0];
+    if (c1 < cend) f.h1 = ghot[c1];
+    const int g = bs + tid;
+    if (g < b5) {
+        f.kc = A.L.kc[g];
+        f.nu = A.L.nu[g];
+        f.scale = gscale[g];
+    }
+    return f;
 }
 
 template <int PROF, int WAVES, int P, bool SEG>
@@ -279,17 +311,22 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
     constexpr int NT = 64 * WAVES;       // threads = lines per LDS batch
     constexpr int W = NT * P;            // grid points per tile
     constexpr int WW = 64 * P;           // grid points per wavefront
-    __shared__ float rec[NT * kRec];
+    constexpr int NS = WAVES * P;        // slices per tile
+    constexpr int NCW = (NS + 7) / 8;    // code words (4 bits per slice)
+    constexpr int NTF = SEG ? WAVES : NCW;
+    __shared__ Lds<NT, NTF> S;
 
     const Geometry G = A.G;
     // the wavefront index is uniform within a wavefront: keep it (and everything derived
-    // from it: run bounds, loop counters, LDS record offsets) in scalar registers
+    // from it: run bounds, loop counters, LDS offsets) in scalar registers
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const WorkItem wi = work_item(A);
     const TPParam tp = A.tps[wi.tp];
-    const int* crc = PROF == kVoigt ? A.core_rc + (int64_t)wi.tp * A.core_stride : nullptr;
-    const long long* coff = PROF == kVoigt ? A.core_off + (int64_t)wi.tp * A.core_stride : nullptr;
+    const int64_t row = (int64_t)wi.tp * A.rec_stride;
+    const float4* ghot = reinterpret_cast<const float4*>(A.hot + row * kHot);
+    const int4* gcold = reinterpret_cast<const int4*>(A.cold + row * kCold);
+    const double* gscale = A.xscale + row;
     const int t0 = wi.tile * W, t1 = t0 + W - 1;
     const int w0 = t0 + wave * WW, w1 = w0 + WW - 1;
 
@@ -298,6 +335,7 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
     const int b5 = off_at(A.off, (int64_t)t1 + G.hmax + 1, G);
     const int bstride = NT * A.n_split;
     const int bfirst = b0 + NT * wi.part;
+    const int rm_tile = tp.rm;
     int rm = tp.rm;
     if (SEG && tp.rm_scale > 0.0) {
         // the centre-near run holds lines with kc within rm of the wave, i.e. wavenumbers
@@ -316,7 +354,6 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
         s4 = off_at(A.off, (int64_t)w0 + G.hmin + 1, G);
         s5 = off_at(A.off, (int64_t)w1 + G.hmax + 1, G);
     }
-    const double Q = A.Q[tp.iq];
 
     float jl[P], jlo_w[P], jhi_w[P], part[P], sum[P], comp[P];
 #pragma unroll
@@ -326,17 +363,89 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
         jhi_w[p] = (float)(64 * p + lane - (WW - 1));   // k - w1
         part[p] = 0.f; sum[p] = 0.f; comp[p] = 0.f;
     }
-    const int cword = R_CODE + (wave * P) / 8;
+    const int cword = (wave * P) / 8;
     const int cshift = 4 * ((wave * P) % 8);
-    const int anc = R_ANC + wave;
+    const float* anc = S.tf + wave * NT;
 
-    RawLine nxt;
-    if (bfirst + tid < b5) nxt = load_raw<PROF>(A, crc, coff, bfirst + tid);
+    Prefetch nxt = load_batch<NT>(A, ghot, gscale, bfirst, b5, tid);
     for (int bs = bfirst; bs < b5; bs += bstride) {
         const int g = bs + tid;
-        if (g < b5) prepare_line<PROF, WAVES, P>(A, tp, G, nxt, Q, t0, !SEG, rec + tid * kRec);
+        // ---- batch set-up: hot records (coalesced copy), then this thread's line
+        if (2 * (int64_t)bs + tid < 2 * (int64_t)b5) S.hot[tid] = nxt.h0;
+        if (2 * (int64_t)bs + NT + tid < 2 * (int64_t)b5) S.hot[NT + tid] = nxt.h1;
+        if (g < b5) {
+            const int kc = nxt.kc;
+            S.sb0[tid] = (float)(t0 - kc);
+            if (SEG) {
+                // x at the end of each wavefront's range nearest the centre: wing points are
+                // then x = anchor + (k - k_anchor) h with both terms of one sign
+                const double d = (G.nu_a + (double)kc * G.dnu) - nxt.nu;
+                const double hd = nxt.scale * G.dnu, xd = nxt.scale * d;
+#pragma unroll
+                for (int wv = 0; wv < WAVES; ++wv) {
+                    const int wa = t0 + WW * wv;
+                    const int ka = wa > kc ? wa : wa + WW - 1;
+                    S.tf[wv * NT + tid] = (float)__builtin_fma((double)(ka - kc), hd, xd);
+                }
+            }
+            // cold fields for lines whose centre can be near the tile (every line for
+            // the coded sweep)
+            const bool near = !SEG || (PROF != kLorentz && (int64_t)kc >= (int64_t)t0 - rm_tile &&
+                                       (int64_t)kc <= (int64_t)t1 + rm_tile);
+            if (near) {
+                const int4* cg = gcold + (int64_t)g * (kCold / 4);
+                const int4 q0 = cg[0], q1 = cg[1], q2 = cg[2], q3 = cg[3];
+                S.csc[tid] = __int_as_float(q0.x);
+                S.kc[tid] = q0.y;
+                S.rad[tid] = q0.z;
+                S.kcl[tid] = q0.w;
+                S.kch[tid] = q1.x;
+                S.cb[tid] = (long long)(((unsigned long long)(unsigned)q1.w << 32) | (unsigned)q1.z);
+                S.m[0 * NT + tid] = __int_as_float(q2.x);
+                S.m[1 * NT + tid] = __int_as_float(q2.y);
+                S.m[2 * NT + tid] = __int_as_float(q2.z);
+                S.m[3 * NT + tid] = __int_as_float(q2.w);
+                S.m[4 * NT + tid] = __int_as_float(q3.x);
+                S.m[5 * NT + tid] = __int_as_float(q3.y);
+                S.m[6 * NT + tid] = __int_as_float(q3.z);
+                S.m[7 * NT + tid] = __int_as_float(q3.w);
+                if (!SEG) {
+                    // 4-bit code per slice: zone (0 skip, 1 far, 2 mid, 3 core) | 4 (mask)
+                    const int klo = A.L.klo[g], khi = A.L.khi[g];
+                    const int rad = q0.z, kcl = q0.w, kch = q1.x, flag = q1.y;
+                    unsigned cw[NCW];
+#pragma unroll
+                    for (int q = 0; q < NCW; ++q) cw[q] = 0;
+#pragma unroll
+                    for (int sl = 0; sl < NS; ++sl) {
+                        const int kA = t0 + 64 * sl, kB = kA + 63;
+                        unsigned code = 0;
+                        if (!(kB < klo || kA > khi)) {
+                            const bool full = (kA >= klo && kB <= khi);
+                            unsigned zone = 1;
+                            if (PROF == kVoigt) {
+                                if (kA <= kch && kB >= kcl) zone = 3;
+                                else if (rad >= 0 && (int64_t)kA <= (int64_t)kc + rad &&
+                                         (int64_t)kB >= (int64_t)kc - rad) zone = 2;
+                            } else if (PROF == kLorentz || PROF == kGHSampled) {
+                                zone = flag ? 1u : 0u;
+                            } else if (PROF == kGHBinned) {
+                                zone = 1u;
+                            } else {
+                                zone = ((int64_t)kA <= (int64_t)kc + rad && (int64_t)kB >= (int64_t)kc - rad) ? 1u : 0u;
+                            }
+                            code = zone ? (zone | (full ? 0u : 4u)) : 0u;
+                        }
+                        cw[sl / 8] |= code << (4 * (sl % 8));
+                    }
+#pragma unroll
+                    for (int q = 0; q < NCW; ++q) S.tf[q * NT + tid] = __uint_as_float(cw[q]);
+                }
+            }
+        }
         __syncthreads();
-        if (g + bstride < b5) nxt = load_raw<PROF>(A, crc, coff, g + bstride);   // overlaps the sweep below
+        if (bs + bstride < b5) nxt = load_batch<NT>(A, ghot, gscale, bs + bstride, b5, tid);   // overlaps the sweep
+        const float* hot = reinterpret_cast<const float*>(S.hot);
         const int be = bs + NT < b5 ? bs + NT : b5;
         for (int cs = bs; cs < be; cs += 64) {
             const int ce = cs + 64 < be ? cs + 64 : be;
@@ -345,8 +454,8 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
                     // ---- run 1: window ends inside the wave (upper mask)
                     const int lo = cs > s0 ? cs : s0, hi = ce < s1 ? ce : s1;
                     for (int l = lo; l < hi; ++l) {
-                        const float* r = rec + (l - bs) * kRec;
-                        const float sb0 = r[R_SB0], jhi = r[R_JHI];
+                        const float* r = hot + (l - bs) * kHot;
+                        const float sb0 = S.sb0[l - bs], jhi = r[H_JHI];
 #pragma unroll
                         for (int p = 0; p < P; ++p) {
                             const float j = jl[p] + sb0;
@@ -357,8 +466,8 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
                     // ---- run 5: window starts inside the wave (lower mask)
                     const int lo5 = cs > s4 ? cs : s4, hi5 = ce < s5 ? ce : s5;
                     for (int l = lo5; l < hi5; ++l) {
-                        const float* r = rec + (l - bs) * kRec;
-                        const float sb0 = r[R_SB0], jlo = r[R_JLO];
+                        const float* r = hot + (l - bs) * kHot;
+                        const float sb0 = S.sb0[l - bs], jlo = r[H_JLO];
 #pragma unroll
                         for (int p = 0; p < P; ++p) {
                             const float j = jl[p] + sb0;
@@ -367,83 +476,55 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
                         }
                     }
                     // ---- runs 2 and 4: wing formula from the anchor, no branches
-#pragma unroll
-                    for (int side = 0; side < 2; ++side) {
-                        const int a0 = side == 0 ? s1 : s3, a1 = side == 0 ? s2 : s4;
-                        const int lo2 = cs > a0 ? cs : a0, hi2 = ce < a1 ? ce : a1;
-                        const float* jd = side == 0 ? jlo_w : jhi_w;
-#pragma unroll 2
-                        for (int l = lo2; l < hi2; ++l) {
-                            const float* r = rec + (l - bs) * kRec;
-                            const float4 h0 = *reinterpret_cast<const float4*>(r);
-                            const float2 h1 = *reinterpret_cast<const float2*>(r + 4);
-                            const float xa = r[anc];
-                            const float h = h0.y, amp = h1.x;
-                            if (PROF == kVoigt) {
-                                const float c0 = h0.z, c1 = h0.w, bb = h1.y;
-#pragma unroll
-                                for (int p = 0; p < P; ++p) {
-                                    const float x = __builtin_fmaf(jd[p], h, xa);
-                                    const float pp = __builtin_fmaf(x, x, c0);
-                                    const float den = __builtin_fmaf(pp, pp, c1);
-                                    const float num = __builtin_fmaf(pp, amp, bb);
-                                    part[p] = __builtin_fmaf(num, __builtin_amdgcn_rcpf(den), part[p]);
-                                }
-                            } else {
-#pragma unroll
-                                for (int p = 0; p < P; ++p) {
-                                    const float x = __builtin_fmaf(jd[p], h, xa);
-                                    part[p] = __builtin_fmaf(amp, __builtin_amdgcn_rcpf(__builtin_fmaf(x, x, 1.0f)), part[p]);
-                                }
-                            }
-                        }
-                    }
+                    wing_run<PROF, P>(hot, anc, bs, cs > s1 ? cs : s1, ce < s2 ? ce : s2, jlo_w, part);
+                    wing_run<PROF, P>(hot, anc, bs, cs > s3 ? cs : s3, ce < s4 ? ce : s4, jhi_w, part);
                 }
                 // ---- run 3: centre near the wave
                 {
                     const int lo3 = cs > s2 ? cs : s2, hi3 = ce < s3 ? ce : s3;
                     for (int l = lo3; l < hi3; ++l) {
-                        const float* r = rec + (l - bs) * kRec;
-                        const int* ri = reinterpret_cast<const int*>(r);
-                        const float sb0 = r[R_SB0];
+                        const int i = l - bs;
+                        const float* r = hot + i * kHot;
+                        const float sb0 = S.sb0[i];
                         if (PROF == kLorentz) {
 #pragma unroll
                             for (int p = 0; p < P; ++p) part[p] += v_lor(r, jl[p] + sb0);
                             continue;
                         }
                         // scalar copies of the line's integer geometry
-                        const int kc = t0 - __builtin_amdgcn_readfirstlane(ri[R_SB0I]);
-                        const int rad = __builtin_amdgcn_readfirstlane(ri[R_RAD]);
-                        const int kcl = __builtin_amdgcn_readfirstlane(ri[R_KCL]);
-                        const int kch = __builtin_amdgcn_readfirstlane(ri[R_KCH]);
+                        const int kc = __builtin_amdgcn_readfirstlane(S.kc[i]);
+                        const int rad = __builtin_amdgcn_readfirstlane(S.rad[i]);
+                        const int kcl = __builtin_amdgcn_readfirstlane(S.kcl[i]);
+                        const int kch = __builtin_amdgcn_readfirstlane(S.kch[i]);
                         float vc[P];
                         if (PROF == kVoigt) {
                             // issue the stored core-value loads first
-                            const long long cb = *reinterpret_cast<const long long*>(r + R_CBASE);
+                            const long long cb = S.cb[i];
 #pragma unroll
                             for (int p = 0; p < P; ++p) {
                                 const int k = w0 + 64 * p + lane;
                                 vc[p] = (k >= kcl && k <= kch) ? A.core_val[cb + k] : 0.0f;
                             }
                         }
+                        const float csc = S.csc[i];
 #pragma unroll
                         for (int p = 0; p < P; ++p) {
                             const int kA = w0 + 64 * p, kB = kA + 63;
                             const float j = jl[p] + sb0;
-                            const bool near = rad >= 0 && (int64_t)kA <= (int64_t)kc + rad &&
-                                              (int64_t)kB >= (int64_t)kc - rad;
+                            const bool nearz = rad >= 0 && (int64_t)kA <= (int64_t)kc + rad &&
+                                               (int64_t)kB >= (int64_t)kc - rad;
                             if (PROF == kVoigt) {
                                 if (kA <= kch && kB >= kcl) {
                                     const int k = kA + lane;
-                                    const float vm = v_mid(r, j);
+                                    const float vm = v_mid<NT>(r, S.m + i, csc, j);
                                     part[p] += (k >= kcl && k <= kch) ? vc[p] : vm;
-                                } else if (near) {
-                                    part[p] += v_mid(r, j);
+                                } else if (nearz) {
+                                    part[p] += v_mid<NT>(r, S.m + i, csc, j);
                                 } else {
                                     part[p] += v_far(r, j);
                                 }
                             } else {
-                                if (near) part[p] += v_gauss(r, j);
+                                if (nearz) part[p] += v_gauss(r, j);
                             }
                         }
                     }
@@ -451,11 +532,12 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
             } else {
                 // ---- coded sweep: every line carries per-slice codes
                 for (int l = cs; l < ce; ++l) {
-                    const float* r = rec + (l - bs) * kRec;
+                    const int i = l - bs;
+                    const float* r = hot + i * kHot;
                     const unsigned cw =
-                        __builtin_amdgcn_readfirstlane(__float_as_uint(r[cword])) >> cshift;
+                        __builtin_amdgcn_readfirstlane(__float_as_uint(S.tf[cword * NT + i])) >> cshift;
                     if ((cw & ((1u << (4 * P)) - 1u)) == 0u) continue;
-                    const float sb0 = r[R_SB0], jlo = r[R_JLO], jhi = r[R_JHI];
+                    const float sb0 = S.sb0[i], jlo = r[H_JLO], jhi = r[H_JHI];
 #pragma unroll
                     for (int p = 0; p < P; ++p) {
                         const unsigned z = (cw >> (4 * p)) & 15u;
@@ -464,15 +546,28 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
                         const float j = jl[p] + sb0;
                         float v;
                         if (PROF == kVoigt) {
-                            if (zone == 1u) v = v_far(r, j);
-                            else if (zone == 2u) v = v_mid(r, j);
-                            else v = v_core(A, r, j, w0 + 64 * p + lane);
+                            if (zone == 1u) {
+                                v = v_far(r, j);
+                            } else {
+                                const float vm = v_mid<NT>(r, S.m + i, S.csc[i], j);
+                                if (zone == 2u) {
+                                    v = vm;
+                                } else {
+                                    // core slice: stored value inside [kcl, kch], 4-node rule elsewhere
+                                    const int k = w0 + 64 * p + lane;
+                                    const int kcl = S.kcl[i], kch = S.kch[i];
+                                    const bool in = (k >= kcl) && (k <= kch);
+                                    float vcore = 0.0f;
+                                    if (in) vcore = A.core_val[S.cb[i] + k];
+                                    v = in ? vcore : vm;
+                                }
+                            }
                         } else if (PROF == kLorentz) {
                             v = v_lor(r, j);
                         } else if (PROF == kGHSampled) {
-                            v = v_ghs(A.tab, r, j);
+                            v = v_ghs<NT>(A.tab, r, S.m + i, j);
                         } else if (PROF == kGHBinned) {
-                            v = v_ghb(A.tab, r, j);
+                            v = v_ghb<NT>(A.tab, r, S.m + i, j);
                         } else {
                             v = v_gauss(r, j);
                         }
@@ -537,6 +632,20 @@ void launch_p(int waves, int P, const FwdArgs& a, hipStream_t s) {
 }
 
 }  // namespace
+
+hipError_t launch_records(int profile, const RecArgs& a, hipStream_t s) {
+    if (a.n_lines <= 0) return hipSuccess;
+    const dim3 grid((unsigned)((a.n_lines + 255) / 256)), block(256);
+    switch (profile) {
+        case kDoppler: hipLaunchKernelGGL(record_kernel<kDoppler>, grid, block, 0, s, a); break;
+        case kGaussFixed: hipLaunchKernelGGL(record_kernel<kGaussFixed>, grid, block, 0, s, a); break;
+        case kLorentz: hipLaunchKernelGGL(record_kernel<kLorentz>, grid, block, 0, s, a); break;
+        case kGHSampled: hipLaunchKernelGGL(record_kernel<kGHSampled>, grid, block, 0, s, a); break;
+        case kGHBinned: hipLaunchKernelGGL(record_kernel<kGHBinned>, grid, block, 0, s, a); break;
+        default: hipLaunchKernelGGL(record_kernel<kVoigt>, grid, block, 0, s, a); break;
+    }
+    return hipGetLastError();
+}
 
 hipError_t launch_forward_f32(int profile, int waves, int P, const FwdArgs& a, hipStream_t s) {
     if (a.n_tiles <= 0) return hipSuccess;
