@@ -167,13 +167,15 @@ __global__ __launch_bounds__(256) void record_kernel(const RecArgs A) {
 }
 
 // ------------------------------------------------------------------ tile kernel
-// LDS image of one batch: hot records (AoS, copied as float4), per-line tile fields and
-// cold fields (one array per field, indexed by the line's place in the batch).
-template <int NT, int NTF>
+// LDS image of one batch: line records of RS words (the 8 hot words, then for the
+// segmented sweep one anchor per wavefront, so a wing-loop line is read from one base
+// address), the grid offset, slice codes (coded sweep) and the cold fields (one array
+// per field, indexed by the line's place in the batch).
+template <int NT, int RS, int NTF>
 struct Lds {
-    float4 hot[2 * NT];
+    float4 rec[NT * RS / 4];
     float sb0[NT];          // t0 - kc
-    float tf[NTF * NT];     // anchors per wavefront (segmented sweep) or slice-code words
+    float tf[NTF * NT];     // slice-code words (coded sweep)
     float csc[NT];
     int kc[NT], rad[NT], kcl[NT], kch[NT];
     long long cb[NT];
@@ -246,15 +248,16 @@ __device__ __forceinline__ float v_gauss(const float* r, float j) {
 }
 
 // Branch-free wing loop over sorted lines [lo, hi) of the batch starting at bs:
-// x = anchor + (k - k_anchor) h, with jd[p] = k - k_anchor of this lane's points.
-template <int PROF, int P>
-__device__ __forceinline__ void wing_run(const float* hot, const float* anc, int bs, int lo, int hi,
-                                         const float (&jd)[P], float (&part)[P]) {
+// x = anchor + (k - k_anchor) h, with jd[p] = k - k_anchor of this lane's points; the
+// anchor of this wavefront is word ia of the line record.
+template <int PROF, int P, int RS, int IA>
+__device__ __forceinline__ void wing_run(const float* rec, int bs, int lo, int hi, const float (&jd)[P],
+                                         float (&part)[P]) {
 #pragma unroll 2
     for (int l = lo; l < hi; ++l) {
-        const float* r = hot + (l - bs) * kHot;
+        const float* r = rec + (l - bs) * RS;
         const float4 h0 = *reinterpret_cast<const float4*>(r);
-        const float xa = anc[l - bs];
+        const float xa = r[IA];
         const float h = h0.x;
         if (PROF == kVoigt) {
             const float c0 = h0.y, c1 = h0.z, amp = h0.w, bb = r[H_B];
@@ -275,6 +278,14 @@ __device__ __forceinline__ void wing_run(const float* hot, const float* anc, int
             }
         }
     }
+}
+
+// Both wing-only runs of wavefront WV (its anchor word is a compile-time offset).
+template <int PROF, int P, int RS, int WV>
+__device__ __forceinline__ void wing_runs(const float* rec, int bs, int lo2, int hi2, int lo4, int hi4,
+                                          const float (&jlo_w)[P], const float (&jhi_w)[P], float (&part)[P]) {
+    wing_run<PROF, P, RS, kHot + WV>(rec, bs, lo2, hi2, jlo_w, part);
+    wing_run<PROF, P, RS, kHot + WV>(rec, bs, lo4, hi4, jhi_w, part);
 }
 
 // The next batch's global data of one thread: two float4 of the hot records (chunks
@@ -313,8 +324,9 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
     constexpr int WW = 64 * P;           // grid points per wavefront
     constexpr int NS = WAVES * P;        // slices per tile
     constexpr int NCW = (NS + 7) / 8;    // code words (4 bits per slice)
-    constexpr int NTF = SEG ? WAVES : NCW;
-    __shared__ Lds<NT, NTF> S;
+    constexpr int RS = SEG ? kHot + WAVES : kHot;   // LDS record words
+    constexpr int NTF = SEG ? 1 : NCW;
+    __shared__ Lds<NT, RS, NTF> S;
 
     const Geometry G = A.G;
     // the wavefront index is uniform within a wavefront: keep it (and everything derived
@@ -365,14 +377,15 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
     }
     const int cword = (wave * P) / 8;
     const int cshift = 4 * ((wave * P) % 8);
-    const float* anc = S.tf + wave * NT;
 
     Prefetch nxt = load_batch<NT>(A, ghot, gscale, bfirst, b5, tid);
     for (int bs = bfirst; bs < b5; bs += bstride) {
         const int g = bs + tid;
-        // ---- batch set-up: hot records (coalesced copy), then this thread's line
-        if (2 * (int64_t)bs + tid < 2 * (int64_t)b5) S.hot[tid] = nxt.h0;
-        if (2 * (int64_t)bs + NT + tid < 2 * (int64_t)b5) S.hot[NT + tid] = nxt.h1;
+        // ---- batch set-up: hot records (coalesced loads; chunk c is half c%2 of line
+        // c/2), then this thread's line
+        if (2 * (int64_t)bs + tid < 2 * (int64_t)b5) S.rec[(tid >> 1) * (RS / 4) + (tid & 1)] = nxt.h0;
+        if (2 * (int64_t)bs + NT + tid < 2 * (int64_t)b5)
+            S.rec[(NT / 2 + (tid >> 1)) * (RS / 4) + (tid & 1)] = nxt.h1;
         if (g < b5) {
             const int kc = nxt.kc;
             S.sb0[tid] = (float)(t0 - kc);
@@ -385,7 +398,8 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
                 for (int wv = 0; wv < WAVES; ++wv) {
                     const int wa = t0 + WW * wv;
                     const int ka = wa > kc ? wa : wa + WW - 1;
-                    S.tf[wv * NT + tid] = (float)__builtin_fma((double)(ka - kc), hd, xd);
+                    reinterpret_cast<float*>(S.rec)[tid * RS + kHot + wv] =
+                        (float)__builtin_fma((double)(ka - kc), hd, xd);
                 }
             }
             // cold fields for lines whose centre can be near the tile (every line for
@@ -445,7 +459,7 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
         }
         __syncthreads();
         if (bs + bstride < b5) nxt = load_batch<NT>(A, ghot, gscale, bs + bstride, b5, tid);   // overlaps the sweep
-        const float* hot = reinterpret_cast<const float*>(S.hot);
+        const float* rec = reinterpret_cast<const float*>(S.rec);
         const int be = bs + NT < b5 ? bs + NT : b5;
         for (int cs = bs; cs < be; cs += 64) {
             const int ce = cs + 64 < be ? cs + 64 : be;
@@ -454,7 +468,7 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
                     // ---- run 1: window ends inside the wave (upper mask)
                     const int lo = cs > s0 ? cs : s0, hi = ce < s1 ? ce : s1;
                     for (int l = lo; l < hi; ++l) {
-                        const float* r = hot + (l - bs) * kHot;
+                        const float* r = rec + (l - bs) * RS;
                         const float sb0 = S.sb0[l - bs], jhi = r[H_JHI];
 #pragma unroll
                         for (int p = 0; p < P; ++p) {
@@ -466,7 +480,7 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
                     // ---- run 5: window starts inside the wave (lower mask)
                     const int lo5 = cs > s4 ? cs : s4, hi5 = ce < s5 ? ce : s5;
                     for (int l = lo5; l < hi5; ++l) {
-                        const float* r = hot + (l - bs) * kHot;
+                        const float* r = rec + (l - bs) * RS;
                         const float sb0 = S.sb0[l - bs], jlo = r[H_JLO];
 #pragma unroll
                         for (int p = 0; p < P; ++p) {
@@ -476,15 +490,27 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
                         }
                     }
                     // ---- runs 2 and 4: wing formula from the anchor, no branches
-                    wing_run<PROF, P>(hot, anc, bs, cs > s1 ? cs : s1, ce < s2 ? ce : s2, jlo_w, part);
-                    wing_run<PROF, P>(hot, anc, bs, cs > s3 ? cs : s3, ce < s4 ? ce : s4, jhi_w, part);
+                    {
+                        const int lo2 = cs > s1 ? cs : s1, hi2 = ce < s2 ? ce : s2;
+                        const int lo4 = cs > s3 ? cs : s3, hi4 = ce < s4 ? ce : s4;
+                        switch (wave) {
+                            case 0: wing_runs<PROF, P, RS, 0>(rec, bs, lo2, hi2, lo4, hi4, jlo_w, jhi_w, part); break;
+                            case 1: wing_runs<PROF, P, RS, 1>(rec, bs, lo2, hi2, lo4, hi4, jlo_w, jhi_w, part); break;
+                            case 2: wing_runs<PROF, P, RS, 2>(rec, bs, lo2, hi2, lo4, hi4, jlo_w, jhi_w, part); break;
+                            case 3: wing_runs<PROF, P, RS, 3>(rec, bs, lo2, hi2, lo4, hi4, jlo_w, jhi_w, part); break;
+                            case 4: wing_runs<PROF, P, RS, (WAVES > 4 ? 4 : 0)>(rec, bs, lo2, hi2, lo4, hi4, jlo_w, jhi_w, part); break;
+                            case 5: wing_runs<PROF, P, RS, (WAVES > 5 ? 5 : 0)>(rec, bs, lo2, hi2, lo4, hi4, jlo_w, jhi_w, part); break;
+                            case 6: wing_runs<PROF, P, RS, (WAVES > 6 ? 6 : 0)>(rec, bs, lo2, hi2, lo4, hi4, jlo_w, jhi_w, part); break;
+                            default: wing_runs<PROF, P, RS, (WAVES > 7 ? 7 : 0)>(rec, bs, lo2, hi2, lo4, hi4, jlo_w, jhi_w, part); break;
+                        }
+                    }
                 }
                 // ---- run 3: centre near the wave
                 {
                     const int lo3 = cs > s2 ? cs : s2, hi3 = ce < s3 ? ce : s3;
                     for (int l = lo3; l < hi3; ++l) {
                         const int i = l - bs;
-                        const float* r = hot + i * kHot;
+                        const float* r = rec + i * RS;
                         const float sb0 = S.sb0[i];
                         if (PROF == kLorentz) {
 #pragma unroll
@@ -496,16 +522,6 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
                         const int rad = __builtin_amdgcn_readfirstlane(S.rad[i]);
                         const int kcl = __builtin_amdgcn_readfirstlane(S.kcl[i]);
                         const int kch = __builtin_amdgcn_readfirstlane(S.kch[i]);
-                        float vc[P];
-                        if (PROF == kVoigt) {
-                            // issue the stored core-value loads first
-                            const long long cb = S.cb[i];
-#pragma unroll
-                            for (int p = 0; p < P; ++p) {
-                                const int k = w0 + 64 * p + lane;
-                                vc[p] = (k >= kcl && k <= kch) ? A.core_val[cb + k] : 0.0f;
-                            }
-                        }
                         const float csc = S.csc[i];
 #pragma unroll
                         for (int p = 0; p < P; ++p) {
@@ -515,9 +531,15 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
                                                (int64_t)kB >= (int64_t)kc - rad;
                             if (PROF == kVoigt) {
                                 if (kA <= kch && kB >= kcl) {
+                                    // stored core values: loaded and consumed inside this branch
+                                    // (a load left in flight past it would make the next wing
+                                    // loop wait for every outstanding load, the prefetch too)
                                     const int k = kA + lane;
+                                    const bool in = (k >= kcl && k <= kch);
+                                    float vcv = 0.0f;
+                                    if (in) vcv = A.core_val[S.cb[i] + k];
                                     const float vm = v_mid<NT>(r, S.m + i, csc, j);
-                                    part[p] += (k >= kcl && k <= kch) ? vc[p] : vm;
+                                    part[p] += in ? vcv : vm;
                                 } else if (nearz) {
                                     part[p] += v_mid<NT>(r, S.m + i, csc, j);
                                 } else {
@@ -533,7 +555,7 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
                 // ---- coded sweep: every line carries per-slice codes
                 for (int l = cs; l < ce; ++l) {
                     const int i = l - bs;
-                    const float* r = hot + i * kHot;
+                    const float* r = rec + i * RS;
                     const unsigned cw =
                         __builtin_amdgcn_readfirstlane(__float_as_uint(S.tf[cword * NT + i])) >> cshift;
                     if ((cw & ((1u << (4 * P)) - 1u)) == 0u) continue;
