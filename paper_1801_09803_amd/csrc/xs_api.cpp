@@ -173,7 +173,7 @@ struct xs_plan {
     // lines
     int64_t cap = 0, n_lines = 0, n_kept = 0;
     bool have_lines = false;
-    DevBuf p_nu, p_elow, p_cA, p_gref, p_nexp, p_kc, p_klo, p_khi;
+    DevBuf p_rec;              // prepared lines in the caller's order (xs::PrepRec)
     DevBuf s_nu, s_elow, s_cA, s_gref, s_nexp, s_kc, s_klo, s_khi, s_orig;
     DevBuf k1, v1, k2, v2, hist, hoff, tsum;
     DevBuf off, flag;
@@ -202,8 +202,7 @@ struct xs_plan {
     }
     void release_all() {
         drop_timed();
-        DevBuf* all[] = {&E, &g, &J, &tab_g, &tab_n, &p_nu, &p_elow, &p_cA, &p_gref, &p_nexp, &p_kc,
-                         &p_klo, &p_khi, &s_nu, &s_elow, &s_cA, &s_gref, &s_nexp, &s_kc, &s_klo,
+        DevBuf* all[] = {&E, &g, &J, &tab_g, &tab_n, &p_rec, &s_nu, &s_elow, &s_cA, &s_gref, &s_nexp, &s_kc, &s_klo,
                          &s_khi, &s_orig, &k1, &v1, &k2, &v2, &hist, &hoff, &tsum, &off, &flag,
                          &T_dev, &Q, &dQ, &qpart, &tab_dev, &tile_order, &adj_pT, &adj_pP, &adj_part};
         for (DevBuf* b : all) release(*b);
@@ -762,8 +761,7 @@ xs_status xs_set_lines(xs_plan* p, int64_t n, const int32_t* upper, const int32_
     if (n > p->cap) {
         const size_t d = n * sizeof(double), f = n * sizeof(float), i4 = n * sizeof(int);
         struct { DevBuf* b; size_t sz; } req[] = {
-            {&p->p_nu, d}, {&p->p_elow, d}, {&p->p_cA, d}, {&p->p_gref, f}, {&p->p_nexp, f},
-            {&p->p_kc, i4}, {&p->p_klo, i4}, {&p->p_khi, i4},
+            {&p->p_rec, n * sizeof(xs::PrepRec)},
             {&p->s_nu, d}, {&p->s_elow, d}, {&p->s_cA, d}, {&p->s_gref, f}, {&p->s_nexp, f},
             {&p->s_kc, i4}, {&p->s_klo, i4}, {&p->s_khi, i4}, {&p->s_orig, i4},
             {&p->k1, i4}, {&p->v1, i4}, {&p->k2, i4}, {&p->v2, i4},
@@ -795,9 +793,7 @@ xs_status xs_set_lines(xs_plan* p, int64_t n, const int32_t* upper, const int32_
     a.n_states = p->n_states;
     a.geo = p->geo;
     a.flag = as<int>(p->flag);
-    a.p_nu = as<double>(p->p_nu); a.p_elow = as<double>(p->p_elow); a.p_cA = as<double>(p->p_cA);
-    a.p_gref = as<float>(p->p_gref); a.p_nexp = as<float>(p->p_nexp);
-    a.p_kc = as<int>(p->p_kc); a.p_klo = as<int>(p->p_klo); a.p_khi = as<int>(p->p_khi);
+    a.p_rec = as<xs::PrepRec>(p->p_rec);
     a.keys = as<uint32_t>(p->k1); a.vals = as<uint32_t>(p->v1);
     XS_HIP(xs::launch_prep(a, s));
 
@@ -809,8 +805,7 @@ xs_status xs_set_lines(xs_plan* p, int64_t n, const int32_t* upper, const int32_
     p->sorted_keys = sk;
     xs::GatherArgs ga{};
     ga.n = n; ga.nkeys = p->geo.nkeys; ga.keys = sk; ga.vals = sv;
-    ga.p_nu = a.p_nu; ga.p_elow = a.p_elow; ga.p_cA = a.p_cA; ga.p_gref = a.p_gref; ga.p_nexp = a.p_nexp;
-    ga.p_kc = a.p_kc; ga.p_klo = a.p_klo; ga.p_khi = a.p_khi;
+    ga.p_rec = a.p_rec;
     ga.nu = as<double>(p->s_nu); ga.elow = as<double>(p->s_elow); ga.cA = as<double>(p->s_cA);
     ga.gref = as<float>(p->s_gref); ga.nexp = as<float>(p->s_nexp); ga.kc = as<int>(p->s_kc);
     ga.klo = as<int>(p->s_klo); ga.khi = as<int>(p->s_khi); ga.orig = as<int>(p->s_orig);

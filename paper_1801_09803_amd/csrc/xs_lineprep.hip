@@ -108,15 +108,18 @@ __global__ __launch_bounds__(256) void prep_kernel(PrepArgs a) {
                         j = j < 0 ? 0 : (j >= a.n_j ? a.n_j - 1 : j);
                         gr = a.gref_tab[j]; ne = a.nexp_tab[j];
                     } else { gr = a.gamma_const; ne = a.n_const; }
-                    a.p_nu[i] = nu;
-                    a.p_elow[i] = El;
                     const double Aein = a.a_is_log ? exp((double)a.A[i]) : (double)a.A[i];
-                    a.p_cA[i] = (double)a.g[up] * Aein / (8.0 * kPI * kC_CGS * nu * nu);
-                    a.p_gref[i] = gr;
-                    a.p_nexp[i] = ne;
-                    a.p_kc[i] = kc;
-                    a.p_klo[i] = klo;
-                    a.p_khi[i] = khi;
+                    PrepRec r;
+                    r.nu = nu;
+                    r.elow = El;
+                    r.cA = (double)a.g[up] * Aein / (8.0 * kPI * kC_CGS * nu * nu);
+                    r.gref = gr;
+                    r.nexp = ne;
+                    r.kc = kc;
+                    r.klo = klo;
+                    r.khi = khi;
+                    r.pad = 0;
+                    a.p_rec[i] = r;
                 }
             }
         }
@@ -308,14 +311,15 @@ __global__ __launch_bounds__(256) void gather_kernel(GatherArgs a) {
     if (p >= a.n) return;
     const uint32_t i = a.vals[p];
     if (a.keys[p] >= (uint32_t)a.nkeys || (int64_t)i >= a.n) return;   // dropped lines sit at the end
-    a.nu[p] = a.p_nu[i];
-    a.elow[p] = a.p_elow[i];
-    a.cA[p] = a.p_cA[i];
-    a.gref[p] = a.p_gref[i];
-    a.nexp[p] = a.p_nexp[i];
-    a.kc[p] = a.p_kc[i];
-    a.klo[p] = a.p_klo[i];
-    a.khi[p] = a.p_khi[i];
+    const PrepRec r = a.p_rec[i];
+    a.nu[p] = r.nu;
+    a.elow[p] = r.elow;
+    a.cA[p] = r.cA;
+    a.gref[p] = r.gref;
+    a.nexp[p] = r.nexp;
+    a.kc[p] = r.kc;
+    a.klo[p] = r.klo;
+    a.khi[p] = r.khi;
     a.orig[p] = (int)i;
 }
 

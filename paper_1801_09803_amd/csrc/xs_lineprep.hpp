@@ -5,6 +5,16 @@
 
 namespace xs {
 
+// One prepared line in the caller's order (48 B, so the gather into sorted order reads
+// one record per line instead of eight scattered arrays).
+struct PrepRec {
+    double nu;       // E_up - E_low
+    double elow;     // lower-state energy
+    double cA;       // g_up A / (8 pi c nu^2)
+    float gref, nexp;
+    int kc, klo, khi, pad;
+};
+
 struct PrepArgs {
     int64_t n;                 // transitions
     const int* upper;
@@ -26,14 +36,7 @@ struct PrepArgs {
     Geometry geo;
     int* flag;
     // outputs, indexed by the caller's line index
-    double* p_nu;
-    double* p_elow;
-    double* p_cA;
-    float* p_gref;
-    float* p_nexp;
-    int* p_kc;
-    int* p_klo;
-    int* p_khi;
+    PrepRec* p_rec;
     uint32_t* keys;
     uint32_t* vals;
 };
@@ -43,14 +46,7 @@ struct GatherArgs {
     int nkeys;
     const uint32_t* keys;
     const uint32_t* vals;
-    const double* p_nu;
-    const double* p_elow;
-    const double* p_cA;
-    const float* p_gref;
-    const float* p_nexp;
-    const int* p_kc;
-    const int* p_klo;
-    const int* p_khi;
+    const PrepRec* p_rec;
     double* nu;
     double* elow;
     double* cA;
