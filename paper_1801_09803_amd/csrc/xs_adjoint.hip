@@ -15,12 +15,13 @@
 //   dL/dT = sum_i S_i (tau_i R0 + Ra alpha_D/(2T) - Rg n_i gamma_i / T),
 //           tau_i = c2 E''/T^2 - (c2 nu/T^2)/expm1(c2 nu/T) - (dQ/dT)/Q
 //   dL/dP = sum_i S_i Rg gamma_i / P   (gamma_ref (T0/T)^n / P0 at P = 0)
-// Profiles are recomputed, nothing is stored from the forward pass.  One wavefront
-// per line walks its window 64 points at a time; wing points use the analytic
-// derivatives of the Gauss-Hermite rules (single precision for the FP32 path, with
-// the forward kernel's power-of-two scaling), |z| < 8 points the double-precision core
-// with w' (Weideman / Taylor).  Window sums accumulate in double; per-line results go
-// to the caller's line order; dL/dT and dL/dP are reduced in a fixed order.
+// Profiles are recomputed, nothing is stored from the forward pass.  Wing points use
+// the analytic derivatives of the Gauss-Hermite rules, |z| < 8 points the core with w'
+// (Weideman / Taylor).  FP64 path: one wavefront per line walks its window 64 points at
+// a time, all in double.  FP32 path: three passes (below) with single-precision wings
+// (the forward kernel's power-of-two scaling) and double-precision core points and sums.
+// Per-line results go to the caller's line order; dL/dT and dL/dP are reduced in a fixed
+// order.
 #include "xs_adjoint.hpp"
 #include "xs_forward_common.hpp"
 
@@ -57,8 +58,8 @@ __device__ __forceinline__ void wing_dv_f32(float xs, const float* a, const floa
     *sy = v2;
 }
 
-template <bool FP64>
-__global__ __launch_bounds__(256) void adjoint_kernel(const AdjArgs A) {
+// FP64 path: one wavefront per line, every window point in double precision.
+__global__ __launch_bounds__(256) void adjoint64_kernel(const AdjArgs A) {
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int nwaves = gridDim.x * 4;
@@ -66,117 +67,50 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const AdjArgs A) {
     const double T = A.tp.T;
     const double Q = A.Q[0], dQ = A.dQ[0];
     const Tables* tab = A.tab;
+    const double* gbar = static_cast<const double*>(A.gbar);
 
     for (int g = blockIdx.x * 4 + wave; g < A.n_lines; g += nwaves) {
         const LineSetup ls = line_setup(A.L, A.tp, g, Q);
         const double s = kSQRT_LN2 / ls.aD;
         const double y = ls.gam * s;
         const double Nn = kSQRT_LN2_PI / ls.aD;
-        const double d = (G.nu_a + (double)ls.kc * G.dnu) - ls.nu;
         const double y2 = y * y;
-        // scaled single-precision wing coefficients
-        double sc = 1.0;
-        float hs = 0.f, xcs = 0.f, ys2 = 0.f, z0s = 0.f, z1s = 0.f;
-        float a2[1], b2[1], e2[1], c2[1], a4[2], b4[2], e4[2], c4[2];
-        if (!FP64) {
-            const double xmax = s * (G.cutoff + 2.0 * G.dnu) + 1.0;
-            int ex;
-            frexp(xmax, &ex);
-            ex = ex > 31 ? ex - 31 : 0;
-            sc = ldexp(1.0, -ex);
-            const double sc2 = sc * sc;
-            hs = (float)(s * G.dnu * sc);
-            xcs = (float)(s * d * sc);
-            ys2 = (float)(y2 * sc2);
-            z0s = (float)(kCoreR2 * sc2);
-            z1s = (float)(kMidR2 * sc2);
-            {
-                const double t2 = tab->gh2.t[0] * tab->gh2.t[0];
-                a2[0] = (float)((y2 - t2) * sc2); b2[0] = (float)(2.0 * t2 * sc2);
-                e2[0] = (float)(4.0 * t2 * y2 * sc2 * sc2); c2[0] = (float)(2.0 * tab->gh2.w[0]);
-            }
-#pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                const double t2 = tab->gh4.t[j] * tab->gh4.t[j];
-                a4[j] = (float)((y2 - t2) * sc2); b4[j] = (float)(2.0 * t2 * sc2);
-                e4[j] = (float)(4.0 * t2 * y2 * sc2 * sc2); c4[j] = (float)(2.0 * tab->gh4.w[j]);
-            }
-        }
-        double s0 = 0.0, sxa = 0.0, sya = 0.0;   // scaled wing sums (FP32 path)
-        double c0 = 0.0, cx = 0.0, cy = 0.0;     // unscaled sums (core points; all points on FP64)
+        double c0 = 0.0, cx = 0.0, cy = 0.0;
         for (int k = ls.klo + lane; k <= ls.khi; k += 64) {
-            const double gb = FP64 ? static_cast<const double*>(A.gbar)[k]
-                                   : (double)static_cast<const float*>(A.gbar)[k];
-            const int j = k - ls.kc;
-            if (FP64) {
-                const double x = s * ((G.nu_a + (double)k * G.dnu) - ls.nu);
-                const double u = x * x;
-                const double z2 = u + y2;
-                double v, xvx, vy;
-                if (z2 < kCoreR2) {
-                    double rw, rdw, idw;
-                    voigt_core_dw<40, 14>(x, y, tab->w40, &rw, &rdw, &idw);
-                    v = rw; xvx = x * rdw; vy = -idw;
-                } else if (z2 < 400.0) {
-                    gh_wing_dv(u, y, tab->gh12, &v, &xvx, &vy);
-                } else if (z2 < 3600.0) {
-                    gh_wing_dv(u, y, tab->gh6, &v, &xvx, &vy);
-                } else if (z2 < 4.84e6) {
-                    gh_wing_dv(u, y, tab->gh4, &v, &xvx, &vy);
-                } else {
-                    gh_wing_dv(u, y, tab->gh2, &v, &xvx, &vy);
-                }
-                c0 = __builtin_fma(gb, v, c0);
-                cx = __builtin_fma(gb, xvx, cx);
-                cy = __builtin_fma(gb, vy, cy);
+            const double gb = gbar[k];
+            const double x = s * ((G.nu_a + (double)k * G.dnu) - ls.nu);
+            const double u = x * x;
+            const double z2 = u + y2;
+            double v, xvx, vy;
+            if (z2 < kCoreR2) {
+                double rw, rdw, idw;
+                voigt_core_dw<40, 14>(x, y, tab->w40, &rw, &rdw, &idw);
+                v = rw; xvx = x * rdw; vy = -idw;
+            } else if (z2 < 400.0) {
+                gh_wing_dv(u, y, tab->gh12, &v, &xvx, &vy);
+            } else if (z2 < 3600.0) {
+                gh_wing_dv(u, y, tab->gh6, &v, &xvx, &vy);
+            } else if (z2 < 4.84e6) {
+                gh_wing_dv(u, y, tab->gh4, &v, &xvx, &vy);
             } else {
-                const float xsv = __builtin_fmaf((float)j, hs, xcs);
-                const float z2s = __builtin_fmaf(xsv, xsv, ys2);
-                if (z2s >= z0s) {
-                    float sv, sx, sy;
-                    if (z2s >= z1s) wing_dv_f32<1>(xsv, a2, b2, e2, c2, ys2, &sv, &sx, &sy);
-                    else wing_dv_f32<2>(xsv, a4, b4, e4, c4, ys2, &sv, &sx, &sy);
-                    s0 = __builtin_fma(gb, (double)sv, s0);
-                    sxa = __builtin_fma(gb, (double)sx, sxa);
-                    sya = __builtin_fma(gb, (double)sy, sya);
-                } else {
-                    const double x = s * __builtin_fma((double)j, G.dnu, d);
-                    double rw, rdw, idw;
-                    voigt_core_dw<24, 8>(x, y, tab->w24, &rw, &rdw, &idw);
-                    c0 = __builtin_fma(gb, rw, c0);
-                    cx = __builtin_fma(gb, x * rdw, cx);
-                    cy = __builtin_fma(gb, -idw, cy);
-                }
+                gh_wing_dv(u, y, tab->gh2, &v, &xvx, &vy);
             }
+            c0 = __builtin_fma(gb, v, c0);
+            cx = __builtin_fma(gb, xvx, cx);
+            cy = __builtin_fma(gb, vy, cy);
         }
-        s0 = wave_sum64(s0); sxa = wave_sum64(sxa); sya = wave_sum64(sya);
         c0 = wave_sum64(c0); cx = wave_sum64(cx); cy = wave_sum64(cy);
         if (lane == 0) {
-            const double sc2 = sc * sc;
-            // scaled sums carry a factor c^2 = 1/sc^2 (x_s = x sc): V = (y sc^2/pi) sum c q_s r_s, ...
-            const double kv = y * sc2 / kPI, ky = sc2 / kPI;
-            const double A0 = kv * s0 + c0;
-            const double Ax = 2.0 * kv * sxa + cx;
-            const double Ay = ky * sya + cy;
-            const double R0 = Nn * A0;
-            const double Rg = Nn * s * Ay;
-            const double Ra = -(Nn / ls.aD) * (A0 + Ax + y * Ay);
+            const double R0 = Nn * c0;
+            const double Rg = Nn * s * cy;
+            const double Ra = -(Nn / ls.aD) * (c0 + cx + y * cy);
             const double S = ls.S;
             const double gref = (double)A.L.gref[g];
             const double nexp = (double)A.L.nexp[g];
             const int o = A.L.orig[g];
-            const double v_lnA = S * R0;
-            const double v_gref = gref > 0.0 ? S * Rg * ls.gam / gref : 0.0;
-            const double v_n = S * Rg * ls.gam * A.tp.ln_T0_T;
-            if (FP64) {
-                if (A.dlnA) static_cast<double*>(A.dlnA)[o] = v_lnA;
-                if (A.dgref) static_cast<double*>(A.dgref)[o] = v_gref;
-                if (A.dn) static_cast<double*>(A.dn)[o] = v_n;
-            } else {
-                if (A.dlnA) static_cast<float*>(A.dlnA)[o] = (float)v_lnA;
-                if (A.dgref) static_cast<float*>(A.dgref)[o] = (float)v_gref;
-                if (A.dn) static_cast<float*>(A.dn)[o] = (float)v_n;
-            }
+            if (A.dlnA) static_cast<double*>(A.dlnA)[o] = S * R0;
+            if (A.dgref) static_cast<double*>(A.dgref)[o] = gref > 0.0 ? S * Rg * ls.gam / gref : 0.0;
+            if (A.dn) static_cast<double*>(A.dn)[o] = S * Rg * ls.gam * A.tp.ln_T0_T;
             const double x2 = (kC2 * ls.nu) / T;
             const double tau = (kC2 * A.L.elow[g]) / (T * T) - ((kC2 * ls.nu) / (T * T)) / expm1(x2) - dQ / Q;
             A.pT[g] = S * (tau * R0 + Ra * ls.aD / (2.0 * T) - Rg * nexp * ls.gam / T);
@@ -185,6 +119,187 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const AdjArgs A) {
             A.pP[g] = S * Rg * dgam_dP;
         }
     }
+}
+
+// ------------------------------------------------------------ FP32 path, three passes
+// 1. adj32_prep: one thread per line: the double-precision setup reduced to a record of
+//    scaled single-precision wing coefficients and index ranges, and the window sums over
+//    the line's core points [kcl, kch] (the forward core pre-pass's range: every point with
+//    |z| < 8 lies inside it) in double precision (core with w', or the 4- / 2-node rule).
+// 2. adj32_wing: one wavefront per line: the window sums over the other points with the
+//    single-precision Gauss-Hermite derivatives (2-node for |z| >= 40, 4-node inside),
+//    8-point single-precision partials folded into double.
+// 3. adj32_final: one thread per line: R0, R_gamma, R_alpha and the gradients.
+enum : int { J_HS = 0, J_XCS = 1, J_YS2 = 2, J_Z1S = 3, J_A2 = 4, J_B2 = 5, J_E2 = 6, J_C2 = 7,
+             J_A4 = 8, J_B4 = 10, J_E4 = 12, J_C4 = 14, J_KLO = 16, J_KHI = 17, J_KC = 18, J_KCL = 19,
+             J_KCH = 20 };
+
+// scaling of the single-precision wing variables: x_s = x sc keeps x_s^4 in range
+__device__ __forceinline__ double wing_scale(double s, const Geometry& G) {
+    const double xmax = s * (G.cutoff + 2.0 * G.dnu) + 1.0;
+    int ex;
+    frexp(xmax, &ex);
+    ex = ex > 31 ? ex - 31 : 0;
+    return ldexp(1.0, -ex);
+}
+
+__global__ __launch_bounds__(256) void adj32_prep_kernel(const AdjArgs A) {
+    const int g = blockIdx.x * 256 + threadIdx.x;
+    if (g >= A.n_lines) return;
+    const Geometry G = A.G;
+    const Tables* tab = A.tab;
+    const LineSetup ls = line_setup(A.L, A.tp, g, A.Q[0]);
+    const double s = kSQRT_LN2 / ls.aD;
+    const double y = ls.gam * s, y2 = y * y;
+    const double d = (G.nu_a + (double)ls.kc * G.dnu) - ls.nu;
+    const double sc = wing_scale(s, G), sc2 = sc * sc;
+    float f[kAdjRec];
+    int* fi = reinterpret_cast<int*>(f);
+#pragma unroll
+    for (int i = 0; i < kAdjRec; ++i) f[i] = 0.0f;
+    f[J_HS] = (float)(s * G.dnu * sc);
+    f[J_XCS] = (float)(s * d * sc);
+    f[J_YS2] = (float)(y2 * sc2);
+    f[J_Z1S] = (float)(kMidR2 * sc2);
+    {
+        const double t2 = tab->gh2.t[0] * tab->gh2.t[0];
+        f[J_A2] = (float)((y2 - t2) * sc2);
+        f[J_B2] = (float)(2.0 * t2 * sc2);
+        f[J_E2] = (float)(4.0 * t2 * y2 * sc2 * sc2);
+        f[J_C2] = (float)(2.0 * tab->gh2.w[0]);
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const double t2 = tab->gh4.t[j] * tab->gh4.t[j];
+        f[J_A4 + j] = (float)((y2 - t2) * sc2);
+        f[J_B4 + j] = (float)(2.0 * t2 * sc2);
+        f[J_E4 + j] = (float)(4.0 * t2 * y2 * sc2 * sc2);
+        f[J_C4 + j] = (float)(2.0 * tab->gh4.w[j]);
+    }
+    int kcl = 0, kch = -1;
+    if (y2 < kCoreR2) {
+        const int r = radius_steps(sqrt(kCoreR2 - y2), s * G.dnu, s * d);
+        const int64_t lo = (int64_t)ls.kc - r, hi = (int64_t)ls.kc + r;
+        kcl = (int)(lo > ls.klo ? lo : ls.klo);
+        kch = (int)(hi < ls.khi ? hi : ls.khi);
+    }
+    fi[J_KLO] = ls.klo;
+    fi[J_KHI] = ls.khi;
+    fi[J_KC] = ls.kc;
+    fi[J_KCL] = kcl;
+    fi[J_KCH] = kch;
+    float4* ro = reinterpret_cast<float4*>(A.rec + (int64_t)g * kAdjRec);
+#pragma unroll
+    for (int q = 0; q < kAdjRec / 4; ++q) ro[q] = make_float4(f[4 * q], f[4 * q + 1], f[4 * q + 2], f[4 * q + 3]);
+    // core points in double precision
+    const float* gbar = static_cast<const float*>(A.gbar);
+    double c0 = 0.0, cx = 0.0, cy = 0.0;
+    for (int k = kcl; k <= kch; ++k) {
+        const double x = s * ((G.nu_a + (double)k * G.dnu) - ls.nu);
+        const double u = x * x, z2 = u + y2;
+        double v, xvx, vy;
+        if (z2 < kCoreR2) {
+            double rw, rdw, idw;
+            voigt_core_dw<24, 8>(x, y, tab->w24, &rw, &rdw, &idw);
+            v = rw; xvx = x * rdw; vy = -idw;
+        } else if (z2 < kMidR2) {
+            gh_wing_dv(u, y, tab->gh4, &v, &xvx, &vy);
+        } else {
+            gh_wing_dv(u, y, tab->gh2, &v, &xvx, &vy);
+        }
+        const double gb = (double)gbar[k];
+        c0 = __builtin_fma(gb, v, c0);
+        cx = __builtin_fma(gb, xvx, cx);
+        cy = __builtin_fma(gb, vy, cy);
+    }
+    double* sm = A.sums + (int64_t)g * 6;
+    sm[0] = c0;
+    sm[1] = cx;
+    sm[2] = cy;
+}
+
+__global__ __launch_bounds__(256) void adj32_wing_kernel(const AdjArgs A) {
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int nwaves = gridDim.x * 4;
+    const float* gbar = static_cast<const float*>(A.gbar);
+    for (int g = blockIdx.x * 4 + wave; g < A.n_lines; g += nwaves) {
+        const float* r = A.rec + (int64_t)g * kAdjRec;
+        const int* ri = reinterpret_cast<const int*>(r);
+        const float hs = r[J_HS], xcs = r[J_XCS], ys2 = r[J_YS2], z1s = r[J_Z1S];
+        const float a2[1] = {r[J_A2]}, b2[1] = {r[J_B2]}, e2[1] = {r[J_E2]}, c2[1] = {r[J_C2]};
+        const float a4[2] = {r[J_A4], r[J_A4 + 1]}, b4[2] = {r[J_B4], r[J_B4 + 1]};
+        const float e4[2] = {r[J_E4], r[J_E4 + 1]}, c4[2] = {r[J_C4], r[J_C4 + 1]};
+        const int klo = __builtin_amdgcn_readfirstlane(ri[J_KLO]);
+        const int khi = __builtin_amdgcn_readfirstlane(ri[J_KHI]);
+        const int kc = __builtin_amdgcn_readfirstlane(ri[J_KC]);
+        const int kcl = __builtin_amdgcn_readfirstlane(ri[J_KCL]);
+        const int kch = __builtin_amdgcn_readfirstlane(ri[J_KCH]);
+        const int niter = khi >= klo ? (khi - klo + 64) / 64 : 0;
+        double s0 = 0.0, sxa = 0.0, sya = 0.0;
+        for (int it0 = 0; it0 < niter; it0 += 8) {
+            const int ite = it0 + 8 < niter ? it0 + 8 : niter;
+            float p0 = 0.0f, px = 0.0f, py = 0.0f;
+            for (int it = it0; it < ite; ++it) {
+                const int k = klo + 64 * it + lane;
+                const bool use = k <= khi && (k < kcl || k > kch);
+                const float gb = use ? gbar[k] : 0.0f;
+                const float xsv = __builtin_fmaf((float)(k - kc), hs, xcs);
+                const float z2s = __builtin_fmaf(xsv, xsv, ys2);
+                float sv, sx, sy;
+                if (z2s >= z1s) wing_dv_f32<1>(xsv, a2, b2, e2, c2, ys2, &sv, &sx, &sy);
+                else wing_dv_f32<2>(xsv, a4, b4, e4, c4, ys2, &sv, &sx, &sy);
+                p0 = __builtin_fmaf(gb, sv, p0);
+                px = __builtin_fmaf(gb, sx, px);
+                py = __builtin_fmaf(gb, sy, py);
+            }
+            s0 += (double)p0;
+            sxa += (double)px;
+            sya += (double)py;
+        }
+        s0 = wave_sum64(s0);
+        sxa = wave_sum64(sxa);
+        sya = wave_sum64(sya);
+        if (lane == 0) {
+            double* sm = A.sums + (int64_t)g * 6;
+            sm[3] = s0;
+            sm[4] = sxa;
+            sm[5] = sya;
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void adj32_final_kernel(const AdjArgs A) {
+    const int g = blockIdx.x * 256 + threadIdx.x;
+    if (g >= A.n_lines) return;
+    const double T = A.tp.T;
+    const double Q = A.Q[0], dQ = A.dQ[0];
+    const LineSetup ls = line_setup(A.L, A.tp, g, Q);
+    const double s = kSQRT_LN2 / ls.aD;
+    const double y = ls.gam * s;
+    const double Nn = kSQRT_LN2_PI / ls.aD;
+    const double sc = wing_scale(s, A.G), sc2 = sc * sc;
+    const double* sm = A.sums + (int64_t)g * 6;
+    // scaled sums carry a factor c^2 = 1/sc^2 (x_s = x sc): V = (y sc^2/pi) sum c q_s r_s, ...
+    const double kv = y * sc2 / kPI, ky = sc2 / kPI;
+    const double A0 = kv * sm[3] + sm[0];
+    const double Ax = 2.0 * kv * sm[4] + sm[1];
+    const double Ay = ky * sm[5] + sm[2];
+    const double R0 = Nn * A0;
+    const double Rg = Nn * s * Ay;
+    const double Ra = -(Nn / ls.aD) * (A0 + Ax + y * Ay);
+    const double S = ls.S;
+    const double gref = (double)A.L.gref[g];
+    const double nexp = (double)A.L.nexp[g];
+    const int o = A.L.orig[g];
+    if (A.dlnA) static_cast<float*>(A.dlnA)[o] = (float)(S * R0);
+    if (A.dgref) static_cast<float*>(A.dgref)[o] = (float)(gref > 0.0 ? S * Rg * ls.gam / gref : 0.0);
+    if (A.dn) static_cast<float*>(A.dn)[o] = (float)(S * Rg * ls.gam * A.tp.ln_T0_T);
+    const double x2 = (kC2 * ls.nu) / T;
+    const double tau = (kC2 * A.L.elow[g]) / (T * T) - ((kC2 * ls.nu) / (T * T)) / expm1(x2) - dQ / Q;
+    A.pT[g] = S * (tau * R0 + Ra * ls.aD / (2.0 * T) - Rg * nexp * ls.gam / T);
+    const double dgam_dP = A.tp.P > 0.0 ? ls.gam / A.tp.P : gref * exp(nexp * A.tp.ln_T0_T) / A.P0;
+    A.pP[g] = S * Rg * dgam_dP;
 }
 
 template <class R>
@@ -243,8 +358,14 @@ hipError_t launch_adjoint(const AdjArgs& a, int fp64, int64_t n_caller_lines, do
     }
     if (a.n_lines > 0) {
         const int blocks = 2048;
-        if (fp64) hipLaunchKernelGGL(adjoint_kernel<true>, dim3(blocks), dim3(256), 0, s, a);
-        else hipLaunchKernelGGL(adjoint_kernel<false>, dim3(blocks), dim3(256), 0, s, a);
+        if (fp64) {
+            hipLaunchKernelGGL(adjoint64_kernel, dim3(blocks), dim3(256), 0, s, a);
+        } else {
+            const dim3 gl((unsigned)((a.n_lines + 255) / 256));
+            hipLaunchKernelGGL(adj32_prep_kernel, gl, dim3(256), 0, s, a);
+            hipLaunchKernelGGL(adj32_wing_kernel, dim3(4096), dim3(256), 0, s, a);
+            hipLaunchKernelGGL(adj32_final_kernel, gl, dim3(256), 0, s, a);
+        }
     }
     hipLaunchKernelGGL(sum2_partial_kernel, dim3(256), dim3(256), 0, s, a.pT, a.pP, (int64_t)a.n_lines, part);
     hipLaunchKernelGGL(sum2_final_kernel, dim3(1), dim3(256), 0, s, part, 256, dT, dP);

@@ -20,7 +20,11 @@ struct AdjArgs {
     void* dn;
     double* pT;            // [n_lines] per-line dL/dT terms
     double* pP;            // [n_lines] per-line dL/dP terms
+    float* rec;            // FP32 path: [n_lines][kAdjRec] per-line wing records
+    double* sums;          // FP32 path: [n_lines][6] core and wing window sums
 };
+
+constexpr int kAdjRec = 24;
 
 // part: >= 512 doubles of scratch
 hipError_t launch_adjoint(const AdjArgs& a, int fp64, int64_t n_caller_lines, double* part, double* dT,

@@ -177,7 +177,7 @@ struct xs_plan {
     DevBuf s_nu, s_elow, s_cA, s_gref, s_nexp, s_kc, s_klo, s_khi, s_orig;
     DevBuf k1, v1, k2, v2, hist, hoff, tsum;
     DevBuf off, flag;
-    DevBuf adj_pT, adj_pP, adj_part;
+    DevBuf adj_pT, adj_pP, adj_part, adj_rec, adj_sums;
     int xcd_contiguous = 0;
     int lpt_order = 1;
     DevBuf tile_order;
@@ -204,7 +204,8 @@ struct xs_plan {
         drop_timed();
         DevBuf* all[] = {&E, &g, &J, &tab_g, &tab_n, &p_rec, &s_nu, &s_elow, &s_cA, &s_gref, &s_nexp, &s_kc, &s_klo,
                          &s_khi, &s_orig, &k1, &v1, &k2, &v2, &hist, &hoff, &tsum, &off, &flag,
-                         &T_dev, &Q, &dQ, &qpart, &tab_dev, &tile_order, &adj_pT, &adj_pP, &adj_part};
+                         &T_dev, &Q, &dQ, &qpart, &tab_dev, &tile_order, &adj_pT, &adj_pP, &adj_part, &adj_rec,
+                         &adj_sums};
         for (DevBuf* b : all) release(*b);
         ws.release();
     }
@@ -1375,6 +1376,10 @@ xs_status xs_cross_section_adjoint(xs_plan* p, double T, double P, const void* g
     if ((st = p->ensure(p->adj_pT, n * sizeof(double), "adjoint partials")) != XS_OK) return st;
     if ((st = p->ensure(p->adj_pP, n * sizeof(double), "adjoint partials")) != XS_OK) return st;
     if ((st = p->ensure(p->adj_part, 512 * sizeof(double), "adjoint reduction")) != XS_OK) return st;
+    if (p->o.precision == XS_FP32) {
+        if ((st = p->ensure(p->adj_rec, n * xs::kAdjRec * sizeof(float), "adjoint records")) != XS_OK) return st;
+        if ((st = p->ensure(p->adj_sums, n * 6 * sizeof(double), "adjoint sums")) != XS_OK) return st;
+    }
     const xs_opts& o = p->o;
     xs::AdjArgs a{};
     a.L.nu = as<double>(p->s_nu); a.L.elow = as<double>(p->s_elow); a.L.cA = as<double>(p->s_cA);
@@ -1396,6 +1401,8 @@ xs_status xs_cross_section_adjoint(xs_plan* p, double T, double P, const void* g
     a.dlnA = dlnA; a.dgref = dgref; a.dn = dn;
     a.pT = as<double>(p->adj_pT);
     a.pP = as<double>(p->adj_pP);
+    a.rec = as<float>(p->adj_rec);
+    a.sums = as<double>(p->adj_sums);
     Timer tf(p, s, 0, 1);
     XS_HIP(xs::launch_adjoint(a, o.precision == XS_FP64 ? 1 : 0, p->n_lines, as<double>(p->adj_part), dT, dP, s));
     tf.stop();
