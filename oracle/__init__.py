@@ -12,3 +12,4 @@ states use ``math.fsum`` (correctly rounded).
 """
 from .constants import *  # noqa: F401,F403
 from .xsec import *  # noqa: F401,F403
+from .vvoigt import *  # noqa: F401,F403

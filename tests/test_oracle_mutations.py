@@ -134,3 +134,56 @@ def test_wrong_adjoint_sign_is_caught(monkeypatch):
     from tests import test_oracle_adjoint as adj
     with pytest.raises(AssertionError):
         adj.test_adjoint_matches_central_differences(1500.0, 0.1)
+
+
+# ------------------------------------------------------------ Vectorized Voigt
+import oracle.vvoigt as VV  # noqa: E402
+from tests import test_oracle_vvoigt as vpins  # noqa: E402
+
+
+def test_vv_wrong_reference_width_is_caught(monkeypatch):
+    monkeypatch.setattr(VV, "vv_reference_hwhm", lambda T, m: float(O.doppler_hwhm(1.0, T, m)) * 10.0)
+    with pytest.raises(AssertionError):
+        vpins.test_reference_width_is_doppler_width_of_a_line_at_one_wavenumber()
+
+
+def test_vv_inverted_beta_is_caught(monkeypatch):
+    good = VV.vv_beta
+
+    def bad(alpha_d, gamma, alpha_ref, radius, use_beta):
+        b = good(alpha_d, gamma, alpha_ref, radius, use_beta)
+        return 1.0 / b
+    monkeypatch.setattr(VV, "vv_beta", bad)
+    with pytest.raises(AssertionError):
+        vpins.test_beta_makes_the_profile_continuous_at_the_radius()
+
+
+def test_vv_core_bound_off_by_one_is_caught(monkeypatch):
+    def bad(nu, nu_a, dnu, radius):
+        nu = np.asarray(nu, np.float64)
+        return (np.floor((nu - radius - nu_a) / dnu).astype(np.int64),
+                np.floor((nu + radius - nu_a) / dnu).astype(np.int64))
+    monkeypatch.setattr(VV, "vv_core_bounds", bad)
+    with pytest.raises(AssertionError):
+        vpins.test_vv_equals_brute_force_double_loop(False, False)
+
+
+@pytest.mark.parametrize("variant", ["no_dnu", "clipped"])
+def test_vvn_normalisation_mistakes_are_caught(monkeypatch, variant):
+    good = VV._vv_lines
+
+    def bad(ls, i0, i1, nu_a, dnu, cutoff, radius, alpha_ref, use_beta, normalise, k_clip):
+        if variant == "clipped" and normalise:
+            # sum over the on-grid part of the window only
+            owner, k, f, _ = good(ls, i0, i1, nu_a, dnu, cutoff, radius, alpha_ref, use_beta, False, None)
+            n = ls.nu[i0:i1].size
+            on = (k >= 0) & (k <= (k_clip[1] if k_clip else 10 ** 9))
+            tot = np.bincount(owner[on], weights=f[on], minlength=n)
+            return owner, k, f, np.where(tot > 0, 1.0 / (dnu * np.where(tot > 0, tot, 1.0)), 0.0)
+        owner, k, f, scale = good(ls, i0, i1, nu_a, dnu, cutoff, radius, alpha_ref, use_beta, normalise, k_clip)
+        if variant == "no_dnu" and normalise:
+            scale = scale * dnu
+        return owner, k, f, scale
+    monkeypatch.setattr(VV, "_vv_lines", bad)
+    with pytest.raises(AssertionError):
+        vpins.test_vvn_preserves_the_line_area()
