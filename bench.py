@@ -113,6 +113,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-stream", action="store_true")
+    ap.add_argument("--no-vv", action="store_true", help="skip the Vectorized Voigt leg")
     ap.add_argument("--stream-chunks", type=int, default=4)
     ap.add_argument("--stream-chunk-lines", type=int, default=1 << 24)
     ap.add_argument("--autotune-ms", type=float, default=20000.0,
@@ -317,6 +318,9 @@ def main():
         log(f"graph replay {tg * 1e3:.1f} ms")
         graph.close()
 
+    if not args.no_vv:
+        result["vectorized_voigt"] = vv_leg(cfg, d, temps, pressures, tile, out, n_kept, stream, log)
+
     del plan, out, d
     torch.cuda.empty_cache()
     if not args.no_adjoint:
@@ -326,6 +330,51 @@ def main():
                                          args.stream_chunk_lines)
 
     print(json.dumps(result), flush=True)
+
+
+def vv_leg(cfg, d, temps, pressures, tile, voigt_out, n_kept, stream, log):
+    """The Vectorized Voigt (beta = 1) and its area-normalised form (with beta) on the same
+    list and tile shape: one call over all (T, P), pre-passes included, and how far each
+    departs from the Voigt result of the timed steps (an approximation, not an error)."""
+    from paper_1801_09803_amd import Plan
+    legs = {}
+    for prof, beta in (("vvoigt", False), ("vvoigt_norm", True)):
+        plan = Plan(cfg.nu_a, cfg.nu_b, cfg.n_points, cfg.mass_amu, cutoff=cfg.cutoff, profile=prof,
+                    precision="fp32", vv_beta=beta)
+        plan.set_states(d["E"], d["g"], d["J"])
+        plan.set_lines(d["upper"], d["lower"], d["A"], d["gamma_ref"], d["n_exp"])
+        plan.set_tile_config(tile["waves"], tile["slices"], tile["last_split"], 1)
+        out = torch.empty((len(temps), cfg.n_points), dtype=torch.float32, device="cuda")
+        plan.cross_section(temps, pressures, out=out)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 2
+        plan.set_timing(True)
+        e0.record(stream)
+        for _ in range(reps):
+            plan.cross_section(temps, pressures, out=out)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        kt = plan.kernel_times()
+        plan.set_timing(False)
+        t_call = e0.elapsed_time(e1) / 1e3 / reps
+        ntp = len(temps)
+        ref, got = voigt_out.double(), out.double()
+        mask = ref > 1e-6 * ref.max()
+        legs[prof] = {
+            "vv_beta": beta,
+            "line_profiles_per_s": n_kept * ntp / t_call,
+            "call_ms": t_call * 1e3,
+            "tile_kernel_ms_per_tp": kt["forward_ms"] / kt["forward_tp"],
+            "pre_passes_ms_per_tp": kt["core_ms"] / (reps * ntp),
+            "max_rel_vs_voigt": float(((got - ref).abs()[mask] / ref[mask]).max().item()),
+            "area_rel_vs_voigt": float(((got.sum(dim=1) - ref.sum(dim=1)) / ref.sum(dim=1)).abs().max().item()),
+        }
+        log(f"{prof}: {t_call * 1e3:.1f} ms per call ({legs[prof]['tile_kernel_ms_per_tp']:.1f} ms tile kernel per (T,P))")
+        del plan, out
+    legs["note"] = ("same list, grid and tile shape as the headline; radius 4 cm^-1; call = Q(T) + "
+                    "pre-passes + tile kernel for all (T,P), line preparation excluded")
+    return legs
 
 
 def stream_run(cfg, dev, log, n_chunks, chunk):

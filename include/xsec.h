@@ -10,7 +10,10 @@
  *     Eq. 15-19, sampled on the grid (the "sampling method");
  *   - sigma(nu_k) = sum over lines of I f(nu_k - nu_fi), Sec. "Cross sections", Eq. 6-8;
  *   - an equidistant grid of N points including both ends, Eq. 9;
- *   - line wings truncated at a cut-off (25 cm^-1 by default), Sec. "Off-set".
+ *   - line wings truncated at a cut-off (25 cm^-1 by default), Sec. "Off-set";
+ *   - the Vectorized Voigt approximation and its area-normalised form, Sec.
+ *     "Vectorized Voigt approximation" and "Binned Vectorized Voigt with the line area
+ *     preserved".
  *
  * Conventions
  *   Units: wavenumbers and energies in cm^-1, T in K, P in the unit of P0 (bar by
@@ -46,7 +49,7 @@
 extern "C" {
 #endif
 
-#define XS_ABI_VERSION 2
+#define XS_ABI_VERSION 3
 
 typedef struct xs_plan xs_plan;
 typedef struct xs_graph xs_graph;
@@ -70,7 +73,24 @@ typedef enum {
     XS_VOIGT = 3,        /* Voigt: Doppler (x) Lorentz (Eq. 19, normalised convolution)   */
     XS_GH_SAMPLED = 4,   /* Voigt as a Gauss-Hermite sum of shifted Lorentzians (Eq. 30),
                             sampled at the grid points                                   */
-    XS_GH_BINNED = 5     /* bin-averaged Gauss-Hermite Voigt, area-conserving (Eq. 31)   */
+    XS_GH_BINNED = 5,    /* bin-averaged Gauss-Hermite Voigt, area-conserving (Eq. 31)   */
+    XS_VVOIGT = 6,       /* Vectorized Voigt (Sec. "Vectorized Voigt approximation"): the
+                            Voigt profile within vv_radius of the centre; beyond it the
+                            Voigt profile of a line at 1 cm^-1 (Doppler width of Eq. 16 at
+                            nu = 1, the line's own Lorentz width), at the same offset from
+                            the centre, times beta (1, or with vv_beta the ratio of the two
+                            profiles at vv_radius, which makes the profile continuous).
+                            The radius region is the grid points with
+                            ceil((nu - R - nu_a)/dnu) <= k <= floor((nu + R - nu_a)/dnu).
+                            Calls return XS_ERR_ARG when sqrt(ln2) R / alpha_ref < 2e4 at a
+                            requested T (alpha_ref the reference's Doppler HWHM), where the
+                            reference wing would lose its closed form.                   */
+    XS_VVOIGT_NORM = 7   /* XS_VVOIGT with each line's intensity divided by dnu times the
+                            sum of its profile values over its whole cut-off window (the
+                            window on the grid extended past its ends), so that a line whose
+                            window lies on the grid adds exactly I to dnu sum_k sigma_k
+                            (Sec. "Binned Vectorized Voigt with the line area preserved"); a
+                            line whose profile sums to zero adds nothing                  */
 } xs_profile;
 
 typedef enum {
@@ -113,7 +133,10 @@ typedef struct {
                                 consecutive (T, P) run back to back): 1..256, or 0 = chosen
                                 per call (8, fewer when the FP32 Voigt core rows of
                                 16 B per line and (T, P) would exceed 16 GiB)            */
-    int32_t reserved[3];
+    int32_t vv_beta;         /* XS_VVOIGT(_NORM): 1 = continuity factor beta, 0 = beta = 1
+                                (the paper's usual choice)                               */
+    double vv_radius;        /* XS_VVOIGT(_NORM): radius R (cm^-1) of the Voigt region, > 0;
+                                0 = 4 cm^-1 (the paper's value)                          */
 } xs_opts;
 
 /* Fill *opts with defaults: cutoff 25, T0 296 K, P0 1 bar, Voigt, FP32, per-line

@@ -12,7 +12,8 @@ from typing import Optional, Sequence
 HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_NAME = "libxsec.so"
 
-PROFILES = {"doppler": 0, "gauss_fixed": 1, "lorentz": 2, "voigt": 3, "gh_sampled": 4, "gh_binned": 5}
+PROFILES = {"doppler": 0, "gauss_fixed": 1, "lorentz": 2, "voigt": 3, "gh_sampled": 4, "gh_binned": 5,
+            "vvoigt": 6, "vvoigt_norm": 7}
 PRECISIONS = {"fp64": 0, "fp32": 1}
 BROADENING = {"const": 0, "per_line": 1, "a0_jlower": 2}
 STATUS = {0: "XS_OK", 1: "XS_ERR_ARG", 2: "XS_ERR_INDEX", 3: "XS_ERR_NU_NONPOS", 4: "XS_ERR_HIP",
@@ -35,7 +36,7 @@ class XsOpts(ctypes.Structure):
         ("alpha_fixed", ctypes.c_double), ("gamma_const", ctypes.c_double), ("n_const", ctypes.c_double),
         ("slices_per_wave", ctypes.c_int32), ("waves_per_block", ctypes.c_int32),
         ("a_is_log", ctypes.c_int32), ("n_split", ctypes.c_int32), ("tp_block", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 3),
+        ("vv_beta", ctypes.c_int32), ("vv_radius", ctypes.c_double),
     ]
 
 
@@ -130,7 +131,8 @@ class Plan:
                  broadening: str = "per_line", T0: float = 296.0, P0: float = 1.0,
                  index_base: int = 0, alpha_fixed: float = 0.0, gamma_const: float = 0.0,
                  n_const: float = 0.0, slices_per_wave: int = 0, waves_per_block: int = 0,
-                 a_is_log: bool = False, n_split: int = 0, tp_block: int = 0):
+                 a_is_log: bool = False, n_split: int = 0, tp_block: int = 0,
+                 vv_radius: float = 0.0, vv_beta: bool = False):
         import torch
         self._torch = torch
         lib = load_library()
@@ -148,6 +150,8 @@ class Plan:
         o.a_is_log = 1 if a_is_log else 0
         o.n_split = int(n_split)
         o.tp_block = int(tp_block)
+        o.vv_radius = float(vv_radius)
+        o.vv_beta = 1 if vv_beta else 0
         h = ctypes.c_void_p()
         _check(lib.xs_plan_create(ctypes.byref(o), ctypes.byref(h)))
         self._lib = lib

@@ -119,7 +119,8 @@ struct Workset {
     DevBuf rc, cnt, coff;     // core pre-pass rows [tp_block][n_kept]
     DevBuf bsum, tmp;         // per row: core count block sums, scan scratch
     DevBuf val;               // core values of one block of (T, P)
-    DevBuf hot, cold, xscale; // FP32 line records [tp_block][n_kept] (32 + 64 + 8 B per line)
+    DevBuf hot, cold, xscale; // FP32 line records [tp_block][n_kept] (32 or 48 + 64 + 8 B per line)
+    DevBuf vv;                // Vectorized Voigt {beta, intensity factor} [tp_block][n_kept]
     DevBuf part;              // per-part sums [tp_block][n_split][n_points] when n_split > 1
     DevBuf out;               // autotuner output scratch
     size_t bytes = 0;
@@ -130,7 +131,7 @@ struct Workset {
     xs_status ensure(DevBuf& b, size_t n, const char* what) { return dev_ensure(b, n, what, &bytes); }
     void release() {
         DevBuf* all[] = {&T, &Q, &dQ, &qpart, &tps, &rc, &cnt, &coff, &bsum, &tmp, &val, &hot, &cold, &xscale,
-                         &part, &out};
+                         &vv, &part, &out};
         for (DevBuf* b : all) dev_release(*b, &bytes);
         stage.release();
         rows = 0;
@@ -284,7 +285,9 @@ xs_status validate_opts(const xs_opts* o) {
     if (!(o->cutoff > 0.0) || !std::isfinite(o->cutoff)) return fail(XS_ERR_ARG, "cutoff must be > 0");
     if (!(o->mass_da > 0.0)) return fail(XS_ERR_ARG, "mass_da must be > 0");
     if (!(o->T0 > 0.0) || !(o->P0 > 0.0)) return fail(XS_ERR_ARG, "T0 and P0 must be > 0");
-    if (o->profile < XS_DOPPLER || o->profile > XS_GH_BINNED) return fail(XS_ERR_UNSUPPORTED, "unknown profile");
+    if (o->profile < XS_DOPPLER || o->profile > XS_VVOIGT_NORM) return fail(XS_ERR_UNSUPPORTED, "unknown profile");
+    if (o->vv_beta != 0 && o->vv_beta != 1) return fail(XS_ERR_ARG, "vv_beta must be 0 or 1");
+    if (!(o->vv_radius >= 0.0) || !std::isfinite(o->vv_radius)) return fail(XS_ERR_ARG, "vv_radius must be >= 0");
     if (o->precision != XS_FP64 && o->precision != XS_FP32) return fail(XS_ERR_ARG, "unknown precision");
     if (o->broadening < XS_BROAD_CONST || o->broadening > XS_BROAD_A0_JLOWER)
         return fail(XS_ERR_ARG, "unknown broadening scheme");
@@ -343,6 +346,11 @@ xs_status build_tile_order(xs_plan* p) {
     return XS_OK;
 }
 
+bool is_vv(const xs_plan* p) { return p->o.profile == XS_VVOIGT || p->o.profile == XS_VVOIGT_NORM; }
+
+// Voigt-like profiles: the Voigt zones (and, on the FP32 path, its core pre-pass) apply
+bool voigt_like(const xs_plan* p) { return p->o.profile == XS_VOIGT || is_vv(p); }
+
 double beta_of(const xs_opts& o, double T) {
     // Eq. 16: alpha_D = nu sqrt(2 k T ln2 / m) / c
     return std::sqrt(2.0 * xs::kKB * T * xs::kLN2 / (o.mass_da * xs::kAMU)) / xs::kC_SI;
@@ -355,7 +363,10 @@ double rm_steps(const xs_plan* p, double T_rm) {
     const xs_opts& o = p->o;
     const double numax = std::max(std::fabs(o.nu_b), std::fabs(o.nu_a)) + o.cutoff;
     double xr = 0.0, alpha = 0.0;
-    if (o.profile == XS_VOIGT) { xr = 40.0; alpha = numax * beta_of(o, T_rm); }
+    if (o.profile == XS_VOIGT || o.profile == XS_VVOIGT || o.profile == XS_VVOIGT_NORM) {
+        xr = 40.0;
+        alpha = numax * beta_of(o, T_rm);
+    }
     else if (o.profile == XS_DOPPLER) { xr = 10.5; alpha = numax * beta_of(o, T_rm); }
     else if (o.profile == XS_GAUSS_FIXED) { xr = 10.5; alpha = o.alpha_fixed; }
     return xr * alpha / (xs::kSQRT_LN2 * p->geo.dnu) + 2.0;
@@ -374,18 +385,40 @@ xs::TPParam make_tp(const xs_plan* p, double T, double P, int iq, double T_rm) {
     const double rmd = rm_steps(p, T_rm);
     tp.rm = rmd > 1.0e9 ? 1000000000 : (int)std::ceil(rmd);
     // the same radius for a line of wavenumber nu: xr alpha_D(nu) / (sqrt(ln2) dnu)
-    const double xr = p->o.profile == XS_VOIGT ? 40.0 : p->o.profile == XS_DOPPLER ? 10.5 : 0.0;
+    const double xr = voigt_like(p) ? 40.0 : p->o.profile == XS_DOPPLER ? 10.5 : 0.0;
     tp.rm_scale = xr * beta_of(p->o, T_rm) / (xs::kSQRT_LN2 * p->geo.dnu);
     return tp;
 }
 
-bool core_path(const xs_plan* p) { return p->o.precision == XS_FP32 && p->o.profile == XS_VOIGT; }
+// Vectorized Voigt pre-pass needed: continuity factors or area normalisation
+bool vv_needed(const xs_plan* p) { return is_vv(p) && (p->o.vv_beta || p->o.profile == XS_VVOIGT_NORM); }
+
+// Profile index of the kernels (the area-normalised form differs in its intensities only)
+int kernel_profile(const xs_plan* p) { return is_vv(p) ? (int)xs::kVVoigt : p->o.profile; }
+
+int hot_words(const xs_plan* p) { return is_vv(p) ? 12 : 8; }
+
+bool core_path(const xs_plan* p) { return p->o.precision == XS_FP32 && voigt_like(p); }
 
 bool fp32_path(const xs_plan* p) { return p->o.precision == XS_FP32; }
 
-// Bytes of per-(line, T, P) workspace: FP32 line records (104 B) and Voigt core rows (16 B).
+// The Vectorized Voigt wing uses the Lorentzian (FP32) or the 2-node rule (FP64) for the
+// reference profile: both need x_ref = sqrt(ln2) R / alpha_ref >= 2e4 at every temperature.
+xs_status check_vv(const xs_plan* p, int n, const double* T) {
+    if (!is_vv(p) || !(p->geo.vv_radius < p->o.cutoff)) return XS_OK;
+    for (int i = 0; i < n; ++i) {
+        const double xr = xs::kSQRT_LN2 * p->geo.vv_radius / beta_of(p->o, T[i]);
+        if (!(xr >= 2.0e4))
+            return fail(XS_ERR_ARG, "vv_radius too small for the reference profile at T = " + std::to_string(T[i]) +
+                                        " K (needs sqrt(ln2) R / alpha_ref >= 2e4)");
+    }
+    return XS_OK;
+}
+
+// Bytes of per-(line, T, P) workspace: FP32 line records (104 or 120 B), Voigt core rows
+// (16 B) and Vectorized Voigt factors (16 B).
 int64_t row_bytes_per_line(const xs_plan* p) {
-    return (fp32_path(p) ? 104 : 0) + (core_path(p) ? 16 : 0);
+    return (fp32_path(p) ? 72 + 4 * hot_words(p) : 0) + (core_path(p) ? 16 : 0) + (vv_needed(p) ? 16 : 0);
 }
 
 int pick_block(const xs_plan* p, int n_tp) {
@@ -416,15 +449,22 @@ int pick_split(const xs_plan* p) {
 // FP32 sweep mode of a (T, P): per-wavefront line segments when the fast-path radius
 // leaves room inside the half window, per-slice codes otherwise.
 bool seg_mode(const xs_plan* p, const xs::TPParam& tp) {
-    return p->o.precision == XS_FP32 && p->o.profile <= XS_VOIGT &&
-           64.0 * p->P + (double)tp.rm + 1.0 <= (double)p->geo.hmin;
+    // (Vectorized Voigt: the windows' outer ends must also lie beyond R)
+    return p->o.precision == XS_FP32 && (p->o.profile <= XS_VOIGT || is_vv(p)) &&
+           64.0 * p->P + (double)tp.rm + 1.0 <= (double)p->geo.hmin &&
+           (!is_vv(p) || 64.0 * p->P + (double)p->geo.rvmax + 1.0 <= (double)p->geo.hmin);
 }
 
 // Core rows and per-part buffers for blocks of B (T, P) split S ways.
 xs_status ensure_rows(xs_plan* p, Workset& ws, int B, int S) {
     const int64_t n = std::max<int64_t>(p->n_kept, 1);
+    if (vv_needed(p)) {
+        XS_TRY(ws.ensure(ws.vv, (size_t)B * n * 2 * sizeof(double), "Vectorized Voigt factors"));
+        ws.rows = B;
+        ws.row_stride = n;
+    }
     if (fp32_path(p)) {
-        XS_TRY(ws.ensure(ws.hot, (size_t)B * n * 8 * sizeof(float), "line records"));
+        XS_TRY(ws.ensure(ws.hot, (size_t)B * n * hot_words(p) * sizeof(float), "line records"));
         XS_TRY(ws.ensure(ws.cold, (size_t)B * n * 16 * sizeof(int), "line records"));
         XS_TRY(ws.ensure(ws.xscale, (size_t)B * n * sizeof(double), "line records"));
         ws.rows = B;
@@ -471,6 +511,7 @@ xs::CoreArgs core_args(xs_plan* p, Workset& ws, int it, int row) {
     c.bsum = as<unsigned long long>(ws.bsum) + row * nb;
     c.scan_tmp = as<unsigned long long>(ws.tmp) + (int64_t)row * kScanTmp;
     c.val = as<float>(ws.val);
+    c.vv = vv_needed(p) ? as<double2>(ws.vv) + row * n : nullptr;
     return c;
 }
 
@@ -499,8 +540,12 @@ xs::FwdArgs fwd_args(xs_plan* p, Workset& ws, const std::vector<xs::TPParam>& tp
     a.tile_order = (p->n_order == a.n_tiles && p->order_W == tile_width(p)) ? as<int>(p->tile_order) : nullptr;
     a.alpha_fixed = o.alpha_fixed;
     a.tab = as<xs::Tables>(p->tab_dev);
+    if (vv_needed(p) && fp64) {
+        a.vv = as<double2>(ws.vv) + (int64_t)row0 * ws.row_stride;
+        a.vv_stride = ws.row_stride;
+    }
     if (fp32_path(p)) {
-        a.hot = as<float>(ws.hot) + (int64_t)row0 * ws.row_stride * 8;
+        a.hot = as<float>(ws.hot) + (int64_t)row0 * ws.row_stride * hot_words(p);
         a.cold = as<int>(ws.cold) + (int64_t)row0 * ws.row_stride * 16;
         a.xscale = as<double>(ws.xscale) + (int64_t)row0 * ws.row_stride;
         a.rec_stride = ws.row_stride;
@@ -524,7 +569,8 @@ xs::RecArgs rec_args(xs_plan* p, Workset& ws, int it, int row) {
         r.core_rc = as<int>(ws.rc) + row * n;
         r.core_off = as<long long>(ws.coff) + row * n;
     }
-    r.hot = as<float>(ws.hot) + row * n * 8;
+    r.vv = vv_needed(p) ? as<double2>(ws.vv) + row * n : nullptr;
+    r.hot = as<float>(ws.hot) + row * n * hot_words(p);
     r.cold = as<int>(ws.cold) + row * n * 16;
     r.xscale = as<double>(ws.xscale) + row * n;
     return r;
@@ -570,21 +616,44 @@ xs_status read_totals(Workset& ws, int nb, hipStream_t s, std::vector<unsigned l
 // Core evaluation (optionally preceded by the count) of rows [0, nb) for the (T, P)
 // points [f, f + nb), then the block's forward launch and, when split, the combine.
 // Enqueue only: no allocation and no synchronisation (graph-capturable).
+// Per-(T, P) pre-passes of the call's point `it` into row `row`: Vectorized Voigt factors,
+// then (FP32) the Voigt core values and the line records.  Enqueue only.
+xs_status enqueue_prepass(xs_plan* p, Workset& ws, int it, int row, bool count, const std::vector<long long>& vbase,
+                          const std::vector<long long>& vend, hipStream_t s) {
+    if (p->n_kept <= 0) return XS_OK;
+    if (vv_needed(p)) {
+        xs::VVArgs v{};
+        v.L = sorted_lines(p);
+        v.G = p->geo;
+        v.tp = as<xs::TPParam>(ws.tps) + it;
+        v.tab = as<xs::Tables>(p->tab_dev);
+        v.n_lines = (int)p->n_kept;
+        v.use_beta = p->o.vv_beta;
+        v.normalise = p->o.profile == XS_VVOIGT_NORM ? 1 : 0;
+        v.fp64 = p->o.precision == XS_FP64 ? 1 : 0;
+        v.out = as<double2>(ws.vv) + (int64_t)row * ws.row_stride;
+        XS_HIP(xs::launch_vv_prep(v, s));
+    }
+    if (!fp32_path(p)) return XS_OK;
+    if (core_path(p)) {
+        xs::CoreArgs c = core_args(p, ws, it, row);
+        c.val_base = vbase[it];
+        c.val_end = vend[it];
+        if (count) XS_HIP(xs::launch_core_count(c, s));
+        XS_HIP(xs::launch_core_eval(c, s));
+    }
+    XS_HIP(xs::launch_records(kernel_profile(p), rec_args(p, ws, it, row), s));
+    return XS_OK;
+}
+
 xs_status enqueue_block(xs_plan* p, Workset& ws, const std::vector<xs::TPParam>& tps, int f, int nb, int S,
                         bool count, const std::vector<long long>& vbase, const std::vector<long long>& vend,
                         void* sigma, hipStream_t s, bool timed) {
     const bool fp64 = p->o.precision == XS_FP64;
-    if (fp32_path(p) && p->n_kept > 0) {
+    if ((fp32_path(p) || vv_needed(p)) && p->n_kept > 0) {
         for (int t = 0; t < nb; ++t) {
             Timer tc(p, s, 1, 0, timed);
-            if (core_path(p)) {
-                xs::CoreArgs c = core_args(p, ws, f + t, t);
-                c.val_base = vbase[f + t];
-                c.val_end = vend[f + t];
-                if (count) XS_HIP(xs::launch_core_count(c, s));
-                XS_HIP(xs::launch_core_eval(c, s));
-            }
-            XS_HIP(xs::launch_records(p->o.profile, rec_args(p, ws, f + t, t), s));
+            XS_TRY(enqueue_prepass(p, ws, f + t, t, count, vbase, vend, s));
             tc.stop();
         }
     }
@@ -595,7 +664,7 @@ xs_status enqueue_block(xs_plan* p, Workset& ws, const std::vector<xs::TPParam>&
         const xs::FwdArgs a = fwd_args(p, ws, tps, r0, r1 - r0, r0 - f, S, sigma);
         {
             Timer tf(p, s, 0, r1 - r0, timed);
-            XS_HIP(xs::launch_forward(p->o.profile, fp64 ? 1 : 0, p->waves, p->P, a, s));
+            XS_HIP(xs::launch_forward(kernel_profile(p), fp64 ? 1 : 0, p->waves, p->P, a, s));
             tf.stop();
         }
         if (S > 1) {
@@ -678,6 +747,13 @@ xs_status xs_plan_create(const xs_opts* opts, xs_plan** out) {
     G.hmax = (int)std::ceil(hw) + 2;
     G.hmin = (int)std::floor(hw) - 2;
     G.nkeys = G.n_points + 2 * G.hmax;
+    G.vv_radius = opts->vv_radius > 0.0 ? opts->vv_radius : 4.0;
+    {
+        // R beyond the cut-off covers every window point: bounds past the half window suffice
+        const double rv = std::min(G.vv_radius, opts->cutoff + 2.0 * G.dnu) / G.dnu;
+        G.rvmax = (int)std::ceil(rv) + 2;
+        G.rvmin = (int)std::floor(rv) - 2;
+    }
     xs::weideman_coefficients(24, &p->tabs.w24);
     xs::weideman_coefficients(40, &p->tabs.w40);
     xs::make_gh_pairs(2, &p->tabs.gh2);
@@ -875,6 +951,7 @@ xs_status xs_cross_section(xs_plan* p, int32_t n_tp, const double* T, const doub
                            void* stream) {
     if (!p || !sigma) return fail(XS_ERR_ARG, "NULL argument");
     XS_TRY(validate_tp(n_tp, T, P));
+    XS_TRY(check_vv(p, n_tp, T));
     if (!p->have_lines) return fail(XS_ERR_STATE, "xs_set_lines must succeed first");
     hipStream_t s = static_cast<hipStream_t>(stream);
     Workset& ws = p->ws;
@@ -903,6 +980,7 @@ xs_status xs_graph_create(xs_plan* p, int32_t n_tp, const double* T, const doubl
     *out = nullptr;
     if (!p || !sigma) return fail(XS_ERR_ARG, "NULL argument");
     XS_TRY(validate_tp(n_tp, T, P));
+    XS_TRY(check_vv(p, n_tp, T));
     if (!p->have_lines) return fail(XS_ERR_STATE, "xs_set_lines must succeed first");
     XS_TRY(build_tile_order(p));
     xs_graph* g = new (std::nothrow) xs_graph();
@@ -978,6 +1056,7 @@ xs_status xs_graph_create(xs_plan* p, int32_t n_tp, const double* T, const doubl
 xs_status xs_graph_set_tp(xs_graph* g, const double* T, const double* P, void* stream) {
     if (!g) return fail(XS_ERR_ARG, "graph is NULL");
     XS_TRY(validate_tp(g->n_tp, T, P));
+    XS_TRY(check_vv(g->p, g->n_tp, T));
     for (int i = 0; i < g->n_tp; ++i)
         if (T[i] > g->T_cap[i])
             return fail(XS_ERR_ARG, "a temperature exceeds the one the graph was captured with");
@@ -1049,6 +1128,7 @@ xs_status xs_autotune(xs_plan* p, int32_t n_tp, const double* T, const double* P
                       int32_t out[4]) {
     if (!p) return fail(XS_ERR_ARG, "plan is NULL");
     XS_TRY(validate_tp(n_tp, T, P));
+    XS_TRY(check_vv(p, n_tp, T));
     if (!p->have_lines) return fail(XS_ERR_STATE, "xs_set_lines must succeed first");
     if (!(budget_ms > 0.0)) return fail(XS_ERR_ARG, "budget_ms must be > 0");
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -1067,17 +1147,7 @@ xs_status xs_autotune(xs_plan* p, int32_t n_tp, const double* T, const double* P
     XS_TRY(ensure_rows(p, ws, ns, 1));
     std::vector<long long> vbase(ns, 0), vend(ns, 0);
     if (core_path(p) && p->n_kept > 0) XS_TRY(count_block(p, ws, tps, 0, ns, s, vbase, vend));
-    if (fp32_path(p) && p->n_kept > 0) {
-        for (int t = 0; t < ns; ++t) {
-            if (core_path(p)) {
-                xs::CoreArgs c = core_args(p, ws, t, t);
-                c.val_base = vbase[t];
-                c.val_end = vend[t];
-                XS_HIP(xs::launch_core_eval(c, s));
-            }
-            XS_HIP(xs::launch_records(p->o.profile, rec_args(p, ws, t, t), s));
-        }
-    }
+    for (int t = 0; t < ns; ++t) XS_TRY(enqueue_prepass(p, ws, t, t, false, vbase, vend, s));
     const size_t elem = fp64 ? sizeof(double) : sizeof(float);
     XS_TRY(ws.ensure(ws.out, (size_t)ns * p->geo.n_points * elem, "autotune output"));
     hipEvent_t e0, e1;
@@ -1093,7 +1163,7 @@ xs_status xs_autotune(xs_plan* p, int32_t n_tp, const double* T, const double* P
         for (int f = 0; f < ns; f += B) {
             const int nb = std::min(B, ns - f);
             const xs::FwdArgs a = fwd_args(p, ws, tps, f, nb, f, S, ws.out.p);
-            XS_HIP(xs::launch_forward(p->o.profile, fp64 ? 1 : 0, w, sl, a, s));
+            XS_HIP(xs::launch_forward(kernel_profile(p), fp64 ? 1 : 0, w, sl, a, s));
             if (S > 1) XS_HIP(xs::launch_combine(fp64 ? 1 : 0, a, s));
         }
         XS_HIP(hipEventRecord(e1, s));
@@ -1225,6 +1295,7 @@ xs_status xs_stream_begin(xs_plan* p, int32_t n_tp, const double* T, const doubl
     *out = nullptr;
     if (!p || !sigma) return fail(XS_ERR_ARG, "NULL argument");
     XS_TRY(validate_tp(n_tp, T, P));
+    XS_TRY(check_vv(p, n_tp, T));
     if (p->n_states <= 0) return fail(XS_ERR_STATE, "xs_set_states must come first");
     if (p->o.broadening == XS_BROAD_A0_JLOWER && (p->n_j <= 0 || !p->J.p))
         return fail(XS_ERR_STATE, "a0 broadening needs xs_set_broadening_table and states J");

@@ -130,7 +130,8 @@ __global__ __launch_bounds__(256) void core_eval_kernel(const CoreArgs A) {
         c = (unsigned long long)A.cnt[g];
         if (c) {
             const CoreLine cl = core_line(A, tp, g, Q);
-            ls_s[t] = cl.s; ls_nu[t] = cl.nu; ls_y[t] = cl.y; ls_a[t] = cl.a; ls_lo[t] = cl.lo;
+            ls_s[t] = cl.s; ls_nu[t] = cl.nu; ls_y[t] = cl.y; ls_lo[t] = cl.lo;
+            ls_a[t] = A.vv ? cl.a * A.vv[g].y : cl.a;   // area-normalised Vectorized Voigt: I' = I x factor
         }
     }
     unsigned long long tot;

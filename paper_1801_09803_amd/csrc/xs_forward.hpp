@@ -6,7 +6,10 @@
 
 namespace xs {
 
-enum ProfileKind { kDoppler = 0, kGaussFixed = 1, kLorentz = 2, kVoigt = 3, kGHSampled = 4, kGHBinned = 5 };
+enum ProfileKind {
+    kDoppler = 0, kGaussFixed = 1, kLorentz = 2, kVoigt = 3, kGHSampled = 4, kGHBinned = 5,
+    kVVoigt = 6   // Vectorized Voigt (the area-normalised form differs only in its intensities)
+};
 
 struct FwdArgs {
     SortedLines L;
@@ -34,6 +37,10 @@ struct FwdArgs {
     const double* xscale;
     int64_t rec_stride;
     const float* core_val;          // FP32 Voigt: a * Re w at the lines' core points
+    // FP64 Vectorized Voigt: per (line, T, P) {beta, intensity factor} rows of vv_stride
+    // lines per (T, P) of the launch, or NULL (beta = 1, factor 1)
+    const double2* vv;
+    int64_t vv_stride;
 };
 
 // Per-(line, T, P) records of the FP32 path (record_kernel).
@@ -47,10 +54,28 @@ struct RecArgs {
     double alpha_fixed;
     const int* core_rc;             // Voigt: core radius per line (-1: none)
     const long long* core_off;      // Voigt: index in core_val of the line's first core value
-    float* hot;                     // [n_lines][8]
+    const double2* vv;              // Vectorized Voigt: {beta, intensity factor} per line, or NULL
+    float* hot;                     // [n_lines][8] ([n_lines][12] for the Vectorized Voigt)
     int* cold;                      // [n_lines][16]
     double* xscale;                 // [n_lines]
 };
+
+// Vectorized Voigt pre-pass: per sorted line and (T, P), the continuity factor beta
+// (1 unless requested) and the intensity factor (1, or for the area-normalised form
+// 1 / (dnu x the sum of the line's profile values over its whole cut-off window)).
+struct VVArgs {
+    SortedLines L;
+    Geometry G;
+    const TPParam* tp;              // device: this (T, P)
+    const Tables* tab;
+    int n_lines;
+    int use_beta;
+    int normalise;
+    int fp64;                       // sum the profile as the FP64 path evaluates it
+    double2* out;                   // [n_lines]
+};
+
+hipError_t launch_vv_prep(const VVArgs& a, hipStream_t s);
 
 hipError_t launch_records(int profile, const RecArgs& a, hipStream_t s);
 
@@ -92,6 +117,7 @@ struct CoreArgs {
     long long val_end;               // end of this (T, P)'s capacity in val (no write at or beyond)
     unsigned long long* scan_tmp;    // scratch for the block-total scan (>= 4096 + 16 entries);
                                      // scan_tmp[4096] receives the total count
+    const double2* vv;               // Vectorized Voigt intensity factors (.y), or NULL
 };
 
 hipError_t launch_core_count(const CoreArgs& a, hipStream_t s);

@@ -33,6 +33,15 @@
 // Doppler width a line of the centre-near run can have, so it shrinks at low wavenumber)
 // Coarse grids use per-slice codes (skip / zone / mask) for every line instead.
 //
+// Vectorized Voigt (Sec. "Vectorized Voigt approximation"): within R of the centre the
+// Voigt zones below; beyond R the reference profile times beta, which for the reference's
+// Doppler width (that of a line at 1 cm^-1; the host requires sqrt(ln2) R / alpha_ref >=
+// 2e4) is the Lorentzian to a relative 3/(2 x_ref^2) <= 4e-9:
+//     beta I' (gamma/pi) / (D^2 + gamma^2) = B / (x^2 + Y),  x the line's scaled offset,
+// two FMA and a reciprocal per point.  Four more hot words carry Y, B and the index
+// bounds of the R region; the segmented sweep splits each wing run in three (outside R,
+// crossing R: per-lane select, inside R), and the centre-near run selects per lane.
+//
 // Voigt zones (|z| = |x + iy|): wings |z| >= 40 use the 2-node Gauss-Hermite rational
 // (6 FMA + 1 reciprocal per point); 8 <= |z| < 40 the 4-node rule; points with |z| < 8
 // take the value the double-precision core pre-pass stored for them.
@@ -47,15 +56,35 @@ namespace xs {
 namespace {
 
 // hot record words
-enum : int { H_H = 0, H_C0 = 1, H_C1 = 2, H_AMP = 3, H_B = 4, H_XC = 5, H_JLO = 6, H_JHI = 7 };
-// cold record words (ints unless noted; C_CBASE is int64, C_M 8 floats)
+// hot record words: scale h, 2-node coefficients C0 C1 AMP B, centre offset XC, window
+// bounds JLO JHI relative to kc; the Vectorized Voigt adds its wing term Y and amplitude VB
+// and the R-region bounds JVLO JVHI, and puts {h, Y, VB, XC} first so that its wing loop
+// reads one float4 per line
+template <int PROF>
+struct HotOf {
+    static constexpr int H = 0, C0 = 1, C1 = 2, AMP = 3, B = 4, XC = 5, JLO = 6, JHI = 7;
+    static constexpr int VY = -1, VB = -1, JVLO = -1, JVHI = -1;
+};
+template <>
+struct HotOf<kVVoigt> {
+    static constexpr int H = 0, VY = 1, VB = 2, XC = 3, C0 = 4, C1 = 5, AMP = 6, B = 7;
+    static constexpr int JLO = 8, JHI = 9, JVLO = 10, JVHI = 11;
+};
+// cold record words (ints unless noted; C_CBASE is int64, C_M up to 8 floats: the Voigt
+// zones use two, y^2 and the 4-node amplitude; the Gauss-Hermite profiles five)
 enum : int { C_CSC = 0, C_KC = 1, C_RAD = 2, C_KCL = 3, C_KCH = 4, C_FLAG = 5, C_CBASE = 6, C_M = 8 };
 constexpr int kHot = 8;
 constexpr int kCold = 16;
+constexpr bool is_voigt(int prof) { return prof == kVoigt || prof == kVVoigt; }
+constexpr int hot_words(int prof) { return prof == kVVoigt ? 12 : kHot; }
+// segmented sweep: keep per-wavefront anchors in the LDS record (saves two operations per
+// line and wavefront) or rebuild them (a smaller LDS image)
+constexpr bool anchors_in_lds(int prof) { return prof != kVVoigt; }
 
 // ------------------------------------------------------------------ record kernel
 template <int PROF>
 __global__ __launch_bounds__(256) void record_kernel(const RecArgs A) {
+    using L = HotOf<PROF>;
     const int g = blockIdx.x * 256 + threadIdx.x;
     if (g >= A.n_lines) return;
     const TPParam tp = *A.tp;
@@ -68,23 +97,25 @@ __global__ __launch_bounds__(256) void record_kernel(const RecArgs A) {
     const double aD = nu * tp.beta;                                                               // Eq. 16
     const double gam = (double)A.L.gref[g] * exp((double)A.L.nexp[g] * tp.ln_T0_T) * tp.p_over_p0;  // Eq. 18
     const double d = (G.nu_a + (double)kc * G.dnu) - nu;   // centre offset nu_kc - nu
-    float h[kHot];
+    constexpr int NH = hot_words(PROF);
+    float h[NH];
     int c[kCold];
     float* cf = reinterpret_cast<float*>(c);
 #pragma unroll
-    for (int i = 0; i < kHot; ++i) h[i] = 0.0f;
+    for (int i = 0; i < NH; ++i) h[i] = 0.0f;
 #pragma unroll
     for (int i = 0; i < kCold; ++i) c[i] = 0;
-    h[H_JLO] = (float)(klo - kc);
-    h[H_JHI] = (float)(khi - kc);
+    h[L::JLO] = (float)(klo - kc);
+    h[L::JHI] = (float)(khi - kc);
     c[C_KC] = kc;
     c[C_RAD] = -1;
     c[C_KCH] = -1;
     double scale;
-    if (PROF == kVoigt) {
+    if (is_voigt(PROF)) {
+        const double2 vv = (PROF == kVVoigt && A.vv) ? A.vv[g] : make_double2(1.0, 1.0);
         const double s = kSQRT_LN2 / aD;
         const double y = gam * s;
-        const double a = S * kSQRT_LN2_PI / aD;
+        const double a = S * vv.y * kSQRT_LN2_PI / aD;
         // power-of-two scaling keeps x^4 inside the float range for very narrow lines
         const double xmax = s * (G.cutoff + 2.0 * G.dnu) + 1.0;
         int e;
@@ -94,22 +125,26 @@ __global__ __launch_bounds__(256) void record_kernel(const RecArgs A) {
         const double y2 = y * y;
         const double ampf = a * y * kINV_SQRT_PI;
         scale = s * sc;
-        h[H_XC] = (float)(scale * d);
-        h[H_H] = (float)(scale * G.dnu);
-        h[H_C0] = (float)((y2 - 0.5) * sc2);
-        h[H_C1] = (float)(2.0 * y2 * sc2 * sc2);
-        h[H_AMP] = (float)(ampf * sc2);
-        h[H_B] = (float)(ampf * sc2 * sc2);
-        cf[C_CSC] = (float)ldexp(1.0, e);
-#pragma unroll
-        for (int jp = 0; jp < 2; ++jp) {
-            const double t2 = A.tab->gh4.t[jp] * A.tab->gh4.t[jp];
-            const double Aj = a * (y / kPI) * 2.0 * A.tab->gh4.w[jp];
-            cf[C_M + 4 * jp + 0] = (float)(y2 - t2);
-            cf[C_M + 4 * jp + 1] = (float)(4.0 * t2 * y2);
-            cf[C_M + 4 * jp + 2] = (float)Aj;
-            cf[C_M + 4 * jp + 3] = (float)(Aj * 2.0 * t2);
+        h[L::XC] = (float)(scale * d);
+        h[L::H] = (float)(scale * G.dnu);
+        h[L::C0] = (float)((y2 - 0.5) * sc2);
+        h[L::C1] = (float)(2.0 * y2 * sc2 * sc2);
+        h[L::AMP] = (float)(ampf * sc2);
+        h[L::B] = (float)(ampf * sc2 * sc2);
+        if (PROF == kVVoigt) {
+            // wing: beta I' (gamma/pi) / (D^2 + gamma^2) = B / (x^2 + Y), x = scale D
+            h[L::VY] = (float)(y2 * sc2);
+            h[L::VB] = (float)(vv.x * S * vv.y * (gam / kPI) * scale * scale);
+            const double kvl = ceil((nu - G.vv_radius - G.nu_a) / G.dnu);
+            const double kvh = floor((nu + G.vv_radius - G.nu_a) / G.dnu);
+            const double lim = 16777216.0;   // keep the float offsets exact
+            h[L::JVLO] = (float)fmax(kvl - (double)kc, -lim);
+            h[L::JVHI] = (float)fmin(kvh - (double)kc, lim);
         }
+        cf[C_CSC] = (float)ldexp(1.0, e);
+        // 4-node rule: node pair j has p_j = x^2 + y^2 - t_j^2 and amplitude amp w_j
+        cf[C_M + 0] = (float)y2;
+        cf[C_M + 1] = (float)(a * (y / kPI) * 2.0);
         c[C_RAD] = y2 < kMidR2 ? radius_steps(sqrt(kMidR2 - y2), s * G.dnu, s * d) : -1;
         const int rc = A.core_rc[g];
         int kcl = 0, kch = -1;
@@ -126,23 +161,23 @@ __global__ __launch_bounds__(256) void record_kernel(const RecArgs A) {
     } else if (PROF == kLorentz) {
         const double ig = gam > 0.0 ? 1.0 / gam : 0.0;
         scale = ig;
-        h[H_XC] = (float)(d * ig);
-        h[H_H] = (float)(G.dnu * ig);
-        h[H_AMP] = (float)(S * ig * (1.0 / kPI));
+        h[L::XC] = (float)(d * ig);
+        h[L::H] = (float)(G.dnu * ig);
+        h[L::AMP] = (float)(S * ig * (1.0 / kPI));
         c[C_FLAG] = gam > 0.0 ? 1 : 0;
     } else if (PROF == kGHSampled || PROF == kGHBinned) {
         // Gauss-Hermite convolution (Eq. 30-31 as read): nodes shift the Lorentzian by
         // delta_j = alpha_D t_j / sqrt(ln 2); work in wavenumber units D = nu_k - nu
         scale = 1.0;
-        h[H_XC] = (float)d;
-        h[H_H] = (float)G.dnu;
+        h[L::XC] = (float)d;
+        h[L::H] = (float)G.dnu;
         cf[C_M + 0] = (float)(gam * gam);
         cf[C_M + 1] = (float)(aD / kSQRT_LN2);
         if (PROF == kGHSampled) {
-            h[H_AMP] = (float)(S * gam / (kPI * 1.7724538509055160273));   // S gamma / pi^(3/2)
+            h[L::AMP] = (float)(S * gam / (kPI * 1.7724538509055160273));   // S gamma / pi^(3/2)
             cf[C_M + 2] = (float)(4.0 * gam * gam);
         } else {
-            h[H_AMP] = (float)(S / (kPI * 1.7724538509055160273 * G.dnu));   // S / (pi^(3/2) dnu)
+            h[L::AMP] = (float)(S / (kPI * 1.7724538509055160273 * G.dnu));   // S / (pi^(3/2) dnu)
             cf[C_M + 3] = (float)(G.dnu * gam);
             cf[C_M + 4] = (float)(gam * gam - 0.25 * G.dnu * G.dnu);
         }
@@ -152,14 +187,14 @@ __global__ __launch_bounds__(256) void record_kernel(const RecArgs A) {
         const double alpha = (PROF == kDoppler) ? aD : A.alpha_fixed;
         const double s = kSQRT_LN2 / alpha;
         scale = s * 1.2011224087864498;
-        h[H_XC] = (float)(scale * d);
-        h[H_H] = (float)(scale * G.dnu);
-        h[H_AMP] = (float)(S * kSQRT_LN2_PI / alpha);
+        h[L::XC] = (float)(scale * d);
+        h[L::H] = (float)(scale * G.dnu);
+        h[L::AMP] = (float)(S * kSQRT_LN2_PI / alpha);
         c[C_RAD] = radius_steps(10.5, s * G.dnu, s * d);   // exp(-x^2) underflows beyond
     }
-    float4* ho = reinterpret_cast<float4*>(A.hot + (int64_t)g * kHot);
-    ho[0] = make_float4(h[0], h[1], h[2], h[3]);
-    ho[1] = make_float4(h[4], h[5], h[6], h[7]);
+    float4* ho = reinterpret_cast<float4*>(A.hot + (int64_t)g * NH);
+#pragma unroll
+    for (int q = 0; q < NH / 4; ++q) ho[q] = make_float4(h[4 * q], h[4 * q + 1], h[4 * q + 2], h[4 * q + 3]);
     int4* co = reinterpret_cast<int4*>(A.cold + (int64_t)g * kCold);
 #pragma unroll
     for (int q = 0; q < 4; ++q) co[q] = make_int4(c[4 * q], c[4 * q + 1], c[4 * q + 2], c[4 * q + 3]);
@@ -171,49 +206,97 @@ __global__ __launch_bounds__(256) void record_kernel(const RecArgs A) {
 // segmented sweep one anchor per wavefront, so a wing-loop line is read from one base
 // address), the grid offset, slice codes (coded sweep) and the cold fields (one array
 // per field, indexed by the line's place in the batch).
-template <int NT, int RS, int NTF>
+template <int NT, int RS, int NTF, int NM>
 struct Lds {
     float4 rec[NT * RS / 4];
     float sb0[NT];          // t0 - kc
-    float tf[NTF * NT];     // slice-code words (coded sweep)
+    float tf[NTF];          // slice-code words (coded sweep: NCW per line, stride NT)
     float csc[NT];
     int kc[NT], rad[NT], kcl[NT], kch[NT];
     long long cb[NT];
-    float m[8 * NT];
+    float m[NM * NT];       // cold profile words (stride NT)
+};
+// segmented sweep: no slice codes (keeps the Vectorized Voigt image at 32 KiB, five
+// workgroups per CU)
+template <int NT, int RS, int NM>
+struct Lds<NT, RS, 0, NM> {
+    float4 rec[NT * RS / 4];
+    float sb0[NT];
+    float csc[NT];
+    int kc[NT], rad[NT], kcl[NT], kch[NT];
+    long long cb[NT];
+    float m[NM * NT];
 };
 
 // wing formula (2-node rule, scaled variables)
+template <int PROF>
 __device__ __forceinline__ float v_far(const float* r, float j) {
-    const float x = __builtin_fmaf(j, r[H_H], r[H_XC]);
-    const float pp = __builtin_fmaf(x, x, r[H_C0]);
-    const float den = __builtin_fmaf(pp, pp, r[H_C1]);
-    const float num = __builtin_fmaf(pp, r[H_AMP], r[H_B]);
+    using L = HotOf<PROF>;
+    const float x = __builtin_fmaf(j, r[L::H], r[L::XC]);
+    const float pp = __builtin_fmaf(x, x, r[L::C0]);
+    const float den = __builtin_fmaf(pp, pp, r[L::C1]);
+    const float num = __builtin_fmaf(pp, r[L::AMP], r[L::B]);
     return num * __builtin_amdgcn_rcpf(den);
 }
 
-// 4-node rule (unscaled x); m points at the line's first coefficient, stride NT
-template <int NT>
-__device__ __forceinline__ float v_mid(const float* r, const float* m, float csc, float j) {
-    const float x = __builtin_fmaf(j, r[H_H], r[H_XC]) * csc;
-    const float p1 = __builtin_fmaf(x, x, m[0 * NT]);
-    const float p2 = __builtin_fmaf(x, x, m[4 * NT]);
-    const float d1 = __builtin_fmaf(p1, p1, m[1 * NT]);
-    const float d2 = __builtin_fmaf(p2, p2, m[5 * NT]);
-    const float n1 = __builtin_fmaf(p1, m[2 * NT], m[3 * NT]);
-    const float n2 = __builtin_fmaf(p2, m[6 * NT], m[7 * NT]);
+// 4-node rule coefficients of one line, from y^2 and the amplitude (node pairs t_j, w_j):
+// p_j = x^2 + y^2 - t_j^2, d_j = p_j^2 + 4 t_j^2 y^2, n_j = amp w_j (p_j + 2 t_j^2)
+struct Mid {
+    float m0, m1, m2, m3, m4, m5, m6, m7;
+};
+
+struct Gh4f {
+    float t2a, t2b, wa, wb;
+};
+
+__device__ __forceinline__ Gh4f gh4f(const Tables* tab) {
+    Gh4f g;
+    g.t2a = (float)(tab->gh4.t[0] * tab->gh4.t[0]);
+    g.t2b = (float)(tab->gh4.t[1] * tab->gh4.t[1]);
+    g.wa = (float)tab->gh4.w[0];
+    g.wb = (float)tab->gh4.w[1];
+    return g;
+}
+
+__device__ __forceinline__ Mid mid_coef(float y2, float amp, const Gh4f& g) {
+    Mid c;
+    c.m0 = y2 - g.t2a;
+    c.m1 = 4.0f * g.t2a * y2;
+    c.m2 = amp * g.wa;
+    c.m3 = c.m2 * (2.0f * g.t2a);
+    c.m4 = y2 - g.t2b;
+    c.m5 = 4.0f * g.t2b * y2;
+    c.m6 = amp * g.wb;
+    c.m7 = c.m6 * (2.0f * g.t2b);
+    return c;
+}
+
+// 4-node rule (unscaled x)
+template <int PROF>
+__device__ __forceinline__ float v_mid(const float* r, const Mid& c, float csc, float j) {
+    using L = HotOf<PROF>;
+    const float x = __builtin_fmaf(j, r[L::H], r[L::XC]) * csc;
+    const float p1 = __builtin_fmaf(x, x, c.m0);
+    const float p2 = __builtin_fmaf(x, x, c.m4);
+    const float d1 = __builtin_fmaf(p1, p1, c.m1);
+    const float d2 = __builtin_fmaf(p2, p2, c.m5);
+    const float n1 = __builtin_fmaf(p1, c.m2, c.m3);
+    const float n2 = __builtin_fmaf(p2, c.m6, c.m7);
     return __builtin_fmaf(n1, __builtin_amdgcn_rcpf(d1), n2 * __builtin_amdgcn_rcpf(d2));
 }
 
+using LD = HotOf<kVoigt>;   // layout of the other profiles
+
 __device__ __forceinline__ float v_lor(const float* r, float j) {
-    const float x = __builtin_fmaf(j, r[H_H], r[H_XC]);
-    return r[H_AMP] * __builtin_amdgcn_rcpf(__builtin_fmaf(x, x, 1.0f));
+    const float x = __builtin_fmaf(j, r[LD::H], r[LD::XC]);
+    return r[LD::AMP] * __builtin_amdgcn_rcpf(__builtin_fmaf(x, x, 1.0f));
 }
 
 // Gauss-Hermite sum of shifted Lorentzians, node pairs +-t_j:
 // L(D - dj) + L(D + dj) = (gamma/pi) 2 (D^2 + g^2 + dj^2) / ((D^2 + g^2 - dj^2)^2 + 4 dj^2 g^2)
 template <int NT>
 __device__ __forceinline__ float v_ghs(const Tables* tab, const float* r, const float* m, float j) {
-    const float D = __builtin_fmaf(j, r[H_H], r[H_XC]);
+    const float D = __builtin_fmaf(j, r[LD::H], r[LD::XC]);
     const float g2 = m[0], ad = m[NT], g4 = m[2 * NT];
     const float D2 = __builtin_fmaf(D, D, g2);
     float acc = 0.0f;
@@ -226,41 +309,64 @@ __device__ __forceinline__ float v_ghs(const Tables* tab, const float* r, const 
         const float den = __builtin_fmaf(p, p, g4 * d2);
         acc = __builtin_fmaf(2.0f * tab->wconvf[kGHConv / 2 + q] * (D2 + d2), __builtin_amdgcn_rcpf(den), acc);
     }
-    return r[H_AMP] * acc;
+    return r[LD::AMP] * acc;
 }
 
 // bin-averaged Gauss-Hermite Voigt: atan(y+) - atan(y-) = atan2(dnu g, (D - dj)^2 + g^2 - dnu^2/4)
 template <int NT>
 __device__ __forceinline__ float v_ghb(const Tables* tab, const float* r, const float* m, float j) {
-    const float D = __builtin_fmaf(j, r[H_H], r[H_XC]);
+    const float D = __builtin_fmaf(j, r[LD::H], r[LD::XC]);
     const float ad = m[NT], hg = m[3 * NT], c = m[4 * NT];
     float acc = 0.0f;
     for (int q = 0; q < kGHConv; ++q) {
         const float e = D - ad * tab->tconvf[q];
         acc = __builtin_fmaf(tab->wconvf[q], atan2f(hg, __builtin_fmaf(e, e, c)), acc);
     }
-    return r[H_AMP] * acc;
+    return r[LD::AMP] * acc;
 }
 
 __device__ __forceinline__ float v_gauss(const float* r, float j) {
-    const float x = __builtin_fmaf(j, r[H_H], r[H_XC]);
-    return r[H_AMP] * __builtin_amdgcn_exp2f(-x * x);
+    const float x = __builtin_fmaf(j, r[LD::H], r[LD::XC]);
+    return r[LD::AMP] * __builtin_amdgcn_exp2f(-x * x);
+}
+
+// Vectorized Voigt wing beyond R: B / (x^2 + Y)
+__device__ __forceinline__ float v_vvw(const float* r, float j) {
+    using L = HotOf<kVVoigt>;
+    static_assert(L::H == 0 && L::VY == 1 && L::VB == 2 && L::XC == 3, "wing words");
+    const float4 q = *reinterpret_cast<const float4*>(r);   // h, Y, B, xc
+    const float x = __builtin_fmaf(j, q.x, q.w);
+    return q.z * __builtin_amdgcn_rcpf(__builtin_fmaf(x, x, q.y));
 }
 
 // Branch-free wing loop over sorted lines [lo, hi) of the batch starting at bs:
-// x = anchor + (k - k_anchor) h, with jd[p] = k - k_anchor of this lane's points; the
-// anchor of this wavefront is word ia of the line record.
-template <int PROF, int P, int RS, int IA>
-__device__ __forceinline__ void wing_run(const float* rec, int bs, int lo, int hi, const float (&jd)[P],
-                                         float (&part)[P]) {
+// x = anchor + (k - k_anchor) h, with jd[p] = k - k_anchor of this lane's points.  The
+// anchor of this wavefront is word IA of the line record or, with IA < 0, rebuilt per
+// line as (k_anchor - kc) h + xc, k_anchor - kc = (t0 - kc) + koff (two operations per
+// line instead of WAVES record words).  KIND: 0 the Voigt 2-node rule, 1 the Lorentzian,
+// 2 the Vectorized Voigt wing beyond R.
+template <int PROF, int KIND, int P, int RS, int IA>
+__device__ __forceinline__ void wing_run(const float* rec, const float* sb0, float koff, int bs, int lo, int hi,
+                                         const float (&jd)[P], float (&part)[P]) {
+    using L = HotOf<PROF>;
 #pragma unroll 2
     for (int l = lo; l < hi; ++l) {
         const float* r = rec + (l - bs) * RS;
-        const float4 h0 = *reinterpret_cast<const float4*>(r);
-        const float xa = r[IA];
-        const float h = h0.x;
-        if (PROF == kVoigt) {
-            const float c0 = h0.y, c1 = h0.z, amp = h0.w, bb = r[H_B];
+        float xa;
+        if constexpr (IA >= 0) xa = r[IA];
+        else xa = __builtin_fmaf(sb0[l - bs] + koff, r[L::H], r[L::XC]);
+        if constexpr (KIND == 0) {
+            // h, C0, C1, AMP, B: one float4 and one word in either layout
+            float h, c0, c1, amp, bb;
+            if constexpr (PROF == kVVoigt) {
+                const float4 q = *reinterpret_cast<const float4*>(r + L::C0);
+                h = r[L::H]; c0 = q.x; c1 = q.y; amp = q.z; bb = q.w;
+                static_assert(L::C1 == L::C0 + 1 && L::AMP == L::C0 + 2 && L::B == L::C0 + 3, "layout");
+            } else {
+                const float4 q = *reinterpret_cast<const float4*>(r);
+                h = q.x; c0 = q.y; c1 = q.z; amp = q.w; bb = r[L::B];
+                static_assert(L::H == 0 && L::C0 == 1 && L::C1 == 2 && L::AMP == 3, "layout");
+            }
 #pragma unroll
             for (int p = 0; p < P; ++p) {
                 const float x = __builtin_fmaf(jd[p], h, xa);
@@ -269,45 +375,74 @@ __device__ __forceinline__ void wing_run(const float* rec, int bs, int lo, int h
                 const float num = __builtin_fmaf(pp, amp, bb);
                 part[p] = __builtin_fmaf(num, __builtin_amdgcn_rcpf(den), part[p]);
             }
-        } else {
-            const float amp = h0.w;
+        } else if constexpr (KIND == 1) {
+            const float4 q = *reinterpret_cast<const float4*>(r);
+            const float h = q.x, amp = q.w;
+            static_assert(L::H == 0 && L::AMP == 3, "layout");
 #pragma unroll
             for (int p = 0; p < P; ++p) {
                 const float x = __builtin_fmaf(jd[p], h, xa);
                 part[p] = __builtin_fmaf(amp, __builtin_amdgcn_rcpf(__builtin_fmaf(x, x, 1.0f)), part[p]);
             }
+        } else {
+            const float4 q = *reinterpret_cast<const float4*>(r);   // h, Y, B, xc
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                const float x = __builtin_fmaf(jd[p], q.x, xa);
+                part[p] = __builtin_fmaf(q.z, __builtin_amdgcn_rcpf(__builtin_fmaf(x, x, q.y)), part[p]);
+            }
         }
     }
 }
 
-// Both wing-only runs of wavefront WV (its anchor word is a compile-time offset).
-template <int PROF, int P, int RS, int WV>
-__device__ __forceinline__ void wing_runs(const float* rec, int bs, int lo2, int hi2, int lo4, int hi4,
+// Wing-only runs of wavefront WV (its anchor word is a compile-time offset): for the
+// Voigt and Lorentz profiles one run on each side, [lo2, hi2) and [lo4, hi4); for the
+// Vectorized Voigt the runs outside R ([lo2, ha) left, [hd, hi4) right) take the
+// reference wing and the runs inside R ([hb, hi2) left, [lo4, hc) right) the 2-node rule.
+// Wing-only runs of one wavefront.  Voigt and Lorentz: [lo2, hi2) left of the wave and
+// [lo4, hi4) right of it; Vectorized Voigt: [lo2, ha) beyond R and [hb, hi2) inside R on
+// the left, [lo4, hc) inside R and [hd, hi4) beyond R on the right.  IA: anchor word of
+// this wavefront, or -1 to rebuild anchors from (t0 - kc) + kl (left, kl = w0 - t0) or
+// + kr (right, kr = w1 - t0).
+template <int PROF, int P, int RS, int IA>
+__device__ __forceinline__ void wing_runs(const float* rec, const float* sb0, float kl, float kr, int bs, int lo2,
+                                          int hi2, int lo4, int hi4, int ha, int hb, int hc, int hd,
                                           const float (&jlo_w)[P], const float (&jhi_w)[P], float (&part)[P]) {
-    wing_run<PROF, P, RS, kHot + WV>(rec, bs, lo2, hi2, jlo_w, part);
-    wing_run<PROF, P, RS, kHot + WV>(rec, bs, lo4, hi4, jhi_w, part);
+    if constexpr (PROF == kVVoigt) {
+        wing_run<PROF, 2, P, RS, IA>(rec, sb0, kl, bs, lo2, ha, jlo_w, part);
+        wing_run<PROF, 0, P, RS, IA>(rec, sb0, kl, bs, hb, hi2, jlo_w, part);
+        wing_run<PROF, 0, P, RS, IA>(rec, sb0, kr, bs, lo4, hc, jhi_w, part);
+        wing_run<PROF, 2, P, RS, IA>(rec, sb0, kr, bs, hd, hi4, jhi_w, part);
+    } else {
+        wing_run<PROF, PROF == kVoigt ? 0 : 1, P, RS, IA>(rec, sb0, kl, bs, lo2, hi2, jlo_w, part);
+        wing_run<PROF, PROF == kVoigt ? 0 : 1, P, RS, IA>(rec, sb0, kr, bs, lo4, hi4, jhi_w, part);
+    }
 }
 
-// The next batch's global data of one thread: two float4 of the hot records (chunks
-// tid and NT + tid of the batch) and its own line's offset data.
+// The next batch's global data of one thread: NQ float4 chunks of the hot records
+// (chunks tid, NT + tid, ... of the batch; chunk c is quarter c % NQ of line c / NQ)
+// and its own line's offset data.
+template <int NQ>
 struct Prefetch {
-    float4 h0, h1;
+    float4 h[NQ];
     int kc;
     double nu, scale;
 };
 
-template <int NT>
-__device__ __forceinline__ Prefetch load_batch(const FwdArgs& A, const float4* ghot, const double* gscale, int bs,
-                                               int b5, int tid) {
-    Prefetch f;
-    f.h0 = make_float4(0.f, 0.f, 0.f, 0.f);
-    f.h1 = f.h0;
+template <int NT, int NQ>
+__device__ __forceinline__ Prefetch<NQ> load_batch(const FwdArgs& A, const float4* ghot, const double* gscale,
+                                                   int bs, int b5, int tid) {
+    Prefetch<NQ> f;
+    const int64_t cend = NQ * (int64_t)b5;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const int64_t c = NQ * (int64_t)bs + q * NT + tid;
+        f.h[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (c < cend) f.h[q] = ghot[c];
+    }
     f.kc = 0;
     f.nu = 0.0;
     f.scale = 0.0;
-    const int64_t c0 = 2 * (int64_t)bs + tid, c1 = c0 + NT, cend = 2 * (int64_t)b5;
-    if (c0 < cend) f.h0 = ghot[c0];
-    if (c1 < cend) f.h1 = ghot[c1];
     const int g = bs + tid;
     if (g < b5) {
         f.kc = A.L.kc[g];
@@ -324,11 +459,19 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
     constexpr int WW = 64 * P;           // grid points per wavefront
     constexpr int NS = WAVES * P;        // slices per tile
     constexpr int NCW = (NS + 7) / 8;    // code words (4 bits per slice)
-    constexpr int RS = SEG ? kHot + WAVES : kHot;   // LDS record words
-    constexpr int NTF = SEG ? 1 : NCW;
-    __shared__ Lds<NT, RS, NTF> S;
+    using L = HotOf<PROF>;
+    constexpr int RH = hot_words(PROF);   // hot record words
+    constexpr int NQ = RH / 4;            // float4 chunks per hot record
+    // per-wavefront anchor words in the LDS record (segmented sweep), or anchors rebuilt
+    // per line (a smaller LDS image, more resident workgroups)
+    constexpr bool ANCH = SEG && anchors_in_lds(PROF);
+    constexpr int RS = ANCH ? RH + WAVES : RH;   // LDS record words
+    constexpr int NTF = SEG ? 0 : NCW * NT;
+    constexpr int NM = (PROF == kGHSampled || PROF == kGHBinned) ? 5 : 2;   // cold profile words in LDS
+    __shared__ Lds<NT, RS, NTF, NM> S;
 
     const Geometry G = A.G;
+    const Gh4f g4 = gh4f(A.tab);
     // the wavefront index is uniform within a wavefront: keep it (and everything derived
     // from it: run bounds, loop counters, LDS offsets) in scalar registers
     const int tid = threadIdx.x, lane = tid & 63;
@@ -336,7 +479,7 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
     const WorkItem wi = work_item(A);
     const TPParam tp = A.tps[wi.tp];
     const int64_t row = (int64_t)wi.tp * A.rec_stride;
-    const float4* ghot = reinterpret_cast<const float4*>(A.hot + row * kHot);
+    const float4* ghot = reinterpret_cast<const float4*>(A.hot + row * RH);
     const int4* gcold = reinterpret_cast<const int4*>(A.cold + row * kCold);
     const double* gscale = A.xscale + row;
     const int t0 = wi.tile * W, t1 = t0 + W - 1;
@@ -358,6 +501,7 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
         if (rw < (double)rm) rm = __builtin_amdgcn_readfirstlane((int)rw);
     }
     int s0 = 0, s1 = 0, s2 = 0, s3 = 0, s4 = 0, s5 = 0;
+    int ha = 0, hb = 0, hc = 0, hd = 0;
     if (SEG) {
         s0 = off_at(A.off, (int64_t)w0 - G.hmax, G);
         s1 = off_at(A.off, (int64_t)w1 - G.hmin, G);
@@ -365,6 +509,18 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
         s3 = off_at(A.off, (int64_t)w1 + rm + 1, G);
         s4 = off_at(A.off, (int64_t)w0 + G.hmin + 1, G);
         s5 = off_at(A.off, (int64_t)w1 + G.hmax + 1, G);
+        if (PROF == kVVoigt) {
+            // wing-only runs split where R can cross the wave: left lines with kc < w0 - rvmax
+            // see only points beyond R, those with kc >= w1 - rvmin only points inside R
+            // (bounds clamped into the runs, so the pieces stay ordered)
+            const int64_t l0 = (int64_t)w1 - G.hmin, l1 = (int64_t)w0 - rm;
+            const int64_t r0 = (int64_t)w1 + rm + 1, r1 = (int64_t)w0 + G.hmin + 1;
+            auto cl = [](int64_t v, int64_t lo, int64_t hi) { return v < lo ? lo : (v > hi ? hi : v); };
+            ha = off_at(A.off, cl((int64_t)w0 - G.rvmax, l0, l1), G);
+            hb = off_at(A.off, cl((int64_t)w1 - G.rvmin, l0, l1), G);
+            hc = off_at(A.off, cl((int64_t)w0 + G.rvmin + 1, r0, r1), G);
+            hd = off_at(A.off, cl((int64_t)w1 + G.rvmax + 1, r0, r1), G);
+        }
     }
 
     float jl[P], jlo_w[P], jhi_w[P], part[P], sum[P], comp[P];
@@ -378,18 +534,20 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
     const int cword = (wave * P) / 8;
     const int cshift = 4 * ((wave * P) % 8);
 
-    Prefetch nxt = load_batch<NT>(A, ghot, gscale, bfirst, b5, tid);
+    Prefetch<NQ> nxt = load_batch<NT, NQ>(A, ghot, gscale, bfirst, b5, tid);
     for (int bs = bfirst; bs < b5; bs += bstride) {
         const int g = bs + tid;
-        // ---- batch set-up: hot records (coalesced loads; chunk c is half c%2 of line
-        // c/2), then this thread's line
-        if (2 * (int64_t)bs + tid < 2 * (int64_t)b5) S.rec[(tid >> 1) * (RS / 4) + (tid & 1)] = nxt.h0;
-        if (2 * (int64_t)bs + NT + tid < 2 * (int64_t)b5)
-            S.rec[(NT / 2 + (tid >> 1)) * (RS / 4) + (tid & 1)] = nxt.h1;
+        // ---- batch set-up: hot records (coalesced loads; chunk c is quarter c % NQ of
+        // line c / NQ), then this thread's line
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const int c = q * NT + tid;
+            if (NQ * (int64_t)bs + c < NQ * (int64_t)b5) S.rec[(c / NQ) * (RS / 4) + (c % NQ)] = nxt.h[q];
+        }
         if (g < b5) {
             const int kc = nxt.kc;
             S.sb0[tid] = (float)(t0 - kc);
-            if (SEG) {
+            if constexpr (ANCH) {
                 // x at the end of each wavefront's range nearest the centre: wing points are
                 // then x = anchor + (k - k_anchor) h with both terms of one sign
                 const double d = (G.nu_a + (double)kc * G.dnu) - nxt.nu;
@@ -398,7 +556,7 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
                 for (int wv = 0; wv < WAVES; ++wv) {
                     const int wa = t0 + WW * wv;
                     const int ka = wa > kc ? wa : wa + WW - 1;
-                    reinterpret_cast<float*>(S.rec)[tid * RS + kHot + wv] =
+                    reinterpret_cast<float*>(S.rec)[tid * RS + RH + wv] =
                         (float)__builtin_fma((double)(ka - kc), hd, xd);
                 }
             }
@@ -417,14 +575,14 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
                 S.cb[tid] = (long long)(((unsigned long long)(unsigned)q1.w << 32) | (unsigned)q1.z);
                 S.m[0 * NT + tid] = __int_as_float(q2.x);
                 S.m[1 * NT + tid] = __int_as_float(q2.y);
-                S.m[2 * NT + tid] = __int_as_float(q2.z);
-                S.m[3 * NT + tid] = __int_as_float(q2.w);
-                S.m[4 * NT + tid] = __int_as_float(q3.x);
-                S.m[5 * NT + tid] = __int_as_float(q3.y);
-                S.m[6 * NT + tid] = __int_as_float(q3.z);
-                S.m[7 * NT + tid] = __int_as_float(q3.w);
-                if (!SEG) {
+                if constexpr (NM > 2) {
+                    S.m[2 * NT + tid] = __int_as_float(q2.z);
+                    S.m[3 * NT + tid] = __int_as_float(q2.w);
+                    S.m[4 * NT + tid] = __int_as_float(q3.x);
+                }
+                if constexpr (!SEG) {
                     // 4-bit code per slice: zone (0 skip, 1 far, 2 mid, 3 core) | 4 (mask)
+                    // | 8 (Vectorized Voigt: points beyond R)
                     const int klo = A.L.klo[g], khi = A.L.khi[g];
                     const int rad = q0.z, kcl = q0.w, kch = q1.x, flag = q1.y;
                     unsigned cw[NCW];
@@ -436,11 +594,21 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
                         unsigned code = 0;
                         if (!(kB < klo || kA > khi)) {
                             const bool full = (kA >= klo && kB <= khi);
-                            unsigned zone = 1;
-                            if (PROF == kVoigt) {
+                            unsigned zone = 1, vvb = 0;
+                            if (is_voigt(PROF)) {
                                 if (kA <= kch && kB >= kcl) zone = 3;
                                 else if (rad >= 0 && (int64_t)kA <= (int64_t)kc + rad &&
                                          (int64_t)kB >= (int64_t)kc - rad) zone = 2;
+                                if (PROF == kVVoigt) {
+                                    // 8: the slice may hold points beyond R (per-lane select);
+                                    // zone 0 with 8: every point is beyond R
+                                    const bool inside = (int64_t)kA >= (int64_t)kc - G.rvmin &&
+                                                        (int64_t)kB <= (int64_t)kc + G.rvmin;
+                                    const bool outside = (int64_t)kB < (int64_t)kc - G.rvmax ||
+                                                         (int64_t)kA > (int64_t)kc + G.rvmax;
+                                    if (!inside) vvb = 8u;
+                                    if (outside) zone = 0u;
+                                }
                             } else if (PROF == kLorentz || PROF == kGHSampled) {
                                 zone = flag ? 1u : 0u;
                             } else if (PROF == kGHBinned) {
@@ -448,7 +616,7 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
                             } else {
                                 zone = ((int64_t)kA <= (int64_t)kc + rad && (int64_t)kB >= (int64_t)kc - rad) ? 1u : 0u;
                             }
-                            code = zone ? (zone | (full ? 0u : 4u)) : 0u;
+                            code = (zone | vvb) ? (zone | vvb | (full ? 0u : 4u)) : 0u;
                         }
                         cw[sl / 8] |= code << (4 * (sl % 8));
                     }
@@ -458,22 +626,22 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
             }
         }
         __syncthreads();
-        if (bs + bstride < b5) nxt = load_batch<NT>(A, ghot, gscale, bs + bstride, b5, tid);   // overlaps the sweep
+        if (bs + bstride < b5) nxt = load_batch<NT, NQ>(A, ghot, gscale, bs + bstride, b5, tid);   // overlaps the sweep
         const float* rec = reinterpret_cast<const float*>(S.rec);
         const int be = bs + NT < b5 ? bs + NT : b5;
         for (int cs = bs; cs < be; cs += 64) {
             const int ce = cs + 64 < be ? cs + 64 : be;
-            if (SEG) {
-                if (PROF == kVoigt || PROF == kLorentz) {
+            if constexpr (SEG) {
+                if (is_voigt(PROF) || PROF == kLorentz) {
                     // ---- run 1: window ends inside the wave (upper mask)
                     const int lo = cs > s0 ? cs : s0, hi = ce < s1 ? ce : s1;
                     for (int l = lo; l < hi; ++l) {
                         const float* r = rec + (l - bs) * RS;
-                        const float sb0 = S.sb0[l - bs], jhi = r[H_JHI];
+                        const float sb0 = S.sb0[l - bs], jhi = r[L::JHI];
 #pragma unroll
                         for (int p = 0; p < P; ++p) {
                             const float j = jl[p] + sb0;
-                            const float v = (PROF == kVoigt) ? v_far(r, j) : v_lor(r, j);
+                            const float v = (PROF == kVoigt) ? v_far<PROF>(r, j) : (PROF == kVVoigt) ? v_vvw(r, j) : v_lor(r, j);
                             part[p] += (j <= jhi) ? v : 0.0f;
                         }
                     }
@@ -481,27 +649,61 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
                     const int lo5 = cs > s4 ? cs : s4, hi5 = ce < s5 ? ce : s5;
                     for (int l = lo5; l < hi5; ++l) {
                         const float* r = rec + (l - bs) * RS;
-                        const float sb0 = S.sb0[l - bs], jlo = r[H_JLO];
+                        const float sb0 = S.sb0[l - bs], jlo = r[L::JLO];
 #pragma unroll
                         for (int p = 0; p < P; ++p) {
                             const float j = jl[p] + sb0;
-                            const float v = (PROF == kVoigt) ? v_far(r, j) : v_lor(r, j);
+                            const float v = (PROF == kVoigt) ? v_far<PROF>(r, j) : (PROF == kVVoigt) ? v_vvw(r, j) : v_lor(r, j);
                             part[p] += (j >= jlo) ? v : 0.0f;
                         }
                     }
-                    // ---- runs 2 and 4: wing formula from the anchor, no branches
+                    // ---- Vectorized Voigt: wing-only lines whose R boundary may fall on the
+                    // wave (per-lane select between the 2-node rule and the reference wing)
+                    if (PROF == kVVoigt) {
+                        const int la = cs > ha ? cs : ha, lb = ce < hb ? ce : hb;
+                        const int lc = cs > hc ? cs : hc, ld = ce < hd ? ce : hd;
+                        for (int l = la; l < lb; ++l) {
+                            const float* r = rec + (l - bs) * RS;
+                            const float sb0 = S.sb0[l - bs], jvh = r[L::JVHI];
+#pragma unroll
+                            for (int p = 0; p < P; ++p) {
+                                const float j = jl[p] + sb0;
+                                part[p] += (j <= jvh) ? v_far<PROF>(r, j) : v_vvw(r, j);
+                            }
+                        }
+                        for (int l = lc; l < ld; ++l) {
+                            const float* r = rec + (l - bs) * RS;
+                            const float sb0 = S.sb0[l - bs], jvl = r[L::JVLO];
+#pragma unroll
+                            for (int p = 0; p < P; ++p) {
+                                const float j = jl[p] + sb0;
+                                part[p] += (j >= jvl) ? v_far<PROF>(r, j) : v_vvw(r, j);
+                            }
+                        }
+                    }
+                    // ---- wing-only runs from the anchor, no branches
                     {
                         const int lo2 = cs > s1 ? cs : s1, hi2 = ce < s2 ? ce : s2;
                         const int lo4 = cs > s3 ? cs : s3, hi4 = ce < s4 ? ce : s4;
-                        switch (wave) {
-                            case 0: wing_runs<PROF, P, RS, 0>(rec, bs, lo2, hi2, lo4, hi4, jlo_w, jhi_w, part); break;
-                            case 1: wing_runs<PROF, P, RS, 1>(rec, bs, lo2, hi2, lo4, hi4, jlo_w, jhi_w, part); break;
-                            case 2: wing_runs<PROF, P, RS, 2>(rec, bs, lo2, hi2, lo4, hi4, jlo_w, jhi_w, part); break;
-                            case 3: wing_runs<PROF, P, RS, 3>(rec, bs, lo2, hi2, lo4, hi4, jlo_w, jhi_w, part); break;
-                            case 4: wing_runs<PROF, P, RS, (WAVES > 4 ? 4 : 0)>(rec, bs, lo2, hi2, lo4, hi4, jlo_w, jhi_w, part); break;
-                            case 5: wing_runs<PROF, P, RS, (WAVES > 5 ? 5 : 0)>(rec, bs, lo2, hi2, lo4, hi4, jlo_w, jhi_w, part); break;
-                            case 6: wing_runs<PROF, P, RS, (WAVES > 6 ? 6 : 0)>(rec, bs, lo2, hi2, lo4, hi4, jlo_w, jhi_w, part); break;
-                            default: wing_runs<PROF, P, RS, (WAVES > 7 ? 7 : 0)>(rec, bs, lo2, hi2, lo4, hi4, jlo_w, jhi_w, part); break;
+                        // Vectorized Voigt pieces: [lo2, xa) beyond R, [xb, hi2) inside R (left);
+                        // [lo4, xc) inside R, [xd, hi4) beyond R (right)
+                        const int xa = ce < ha ? ce : ha, xb = cs > hb ? cs : hb;
+                        const int xc = ce < hc ? ce : hc, xd = cs > hd ? cs : hd;
+                        const float kl = (float)(wave * WW), kr = (float)(wave * WW + WW - 1);
+                        if constexpr (!ANCH) {
+                            wing_runs<PROF, P, RS, -1>(rec, S.sb0, kl, kr, bs, lo2, hi2, lo4, hi4, xa, xb, xc, xd, jlo_w,
+                                                       jhi_w, part);
+                        } else {
+                            switch (wave) {
+                                case 0: wing_runs<PROF, P, RS, RH + 0>(rec, S.sb0, kl, kr, bs, lo2, hi2, lo4, hi4, xa, xb, xc, xd, jlo_w, jhi_w, part); break;
+                                case 1: wing_runs<PROF, P, RS, RH + 1>(rec, S.sb0, kl, kr, bs, lo2, hi2, lo4, hi4, xa, xb, xc, xd, jlo_w, jhi_w, part); break;
+                                case 2: wing_runs<PROF, P, RS, RH + 2>(rec, S.sb0, kl, kr, bs, lo2, hi2, lo4, hi4, xa, xb, xc, xd, jlo_w, jhi_w, part); break;
+                                case 3: wing_runs<PROF, P, RS, RH + 3>(rec, S.sb0, kl, kr, bs, lo2, hi2, lo4, hi4, xa, xb, xc, xd, jlo_w, jhi_w, part); break;
+                                case 4: wing_runs<PROF, P, RS, RH + (WAVES > 4 ? 4 : 0)>(rec, S.sb0, kl, kr, bs, lo2, hi2, lo4, hi4, xa, xb, xc, xd, jlo_w, jhi_w, part); break;
+                                case 5: wing_runs<PROF, P, RS, RH + (WAVES > 5 ? 5 : 0)>(rec, S.sb0, kl, kr, bs, lo2, hi2, lo4, hi4, xa, xb, xc, xd, jlo_w, jhi_w, part); break;
+                                case 6: wing_runs<PROF, P, RS, RH + (WAVES > 6 ? 6 : 0)>(rec, S.sb0, kl, kr, bs, lo2, hi2, lo4, hi4, xa, xb, xc, xd, jlo_w, jhi_w, part); break;
+                                default: wing_runs<PROF, P, RS, RH + (WAVES > 7 ? 7 : 0)>(rec, S.sb0, kl, kr, bs, lo2, hi2, lo4, hi4, xa, xb, xc, xd, jlo_w, jhi_w, part); break;
+                            }
                         }
                     }
                 }
@@ -523,13 +725,15 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
                         const int kcl = __builtin_amdgcn_readfirstlane(S.kcl[i]);
                         const int kch = __builtin_amdgcn_readfirstlane(S.kch[i]);
                         const float csc = S.csc[i];
+                        const Mid mc = mid_coef(S.m[i], S.m[NT + i], g4);
 #pragma unroll
                         for (int p = 0; p < P; ++p) {
                             const int kA = w0 + 64 * p, kB = kA + 63;
                             const float j = jl[p] + sb0;
                             const bool nearz = rad >= 0 && (int64_t)kA <= (int64_t)kc + rad &&
                                                (int64_t)kB >= (int64_t)kc - rad;
-                            if (PROF == kVoigt) {
+                            if (is_voigt(PROF)) {
+                                float v;
                                 if (kA <= kch && kB >= kcl) {
                                     // stored core values: loaded and consumed inside this branch
                                     // (a load left in flight past it would make the next wing
@@ -538,13 +742,19 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
                                     const bool in = (k >= kcl && k <= kch);
                                     float vcv = 0.0f;
                                     if (in) vcv = A.core_val[S.cb[i] + k];
-                                    const float vm = v_mid<NT>(r, S.m + i, csc, j);
-                                    part[p] += in ? vcv : vm;
+                                    const float vm = v_mid<PROF>(r, mc, csc, j);
+                                    v = in ? vcv : vm;
                                 } else if (nearz) {
-                                    part[p] += v_mid<NT>(r, S.m + i, csc, j);
+                                    v = v_mid<PROF>(r, mc, csc, j);
                                 } else {
-                                    part[p] += v_far(r, j);
+                                    v = v_far<PROF>(r, j);
                                 }
+                                if (PROF == kVVoigt) {
+                                    const bool inr = (j >= r[L::JVLO]) && (j <= r[L::JVHI]);
+                                    const float w = v_vvw(r, j);
+                                    v = inr ? v : w;
+                                }
+                                part[p] += v;
                             } else {
                                 if (nearz) part[p] += v_gauss(r, j);
                             }
@@ -559,19 +769,19 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
                     const unsigned cw =
                         __builtin_amdgcn_readfirstlane(__float_as_uint(S.tf[cword * NT + i])) >> cshift;
                     if ((cw & ((1u << (4 * P)) - 1u)) == 0u) continue;
-                    const float sb0 = S.sb0[i], jlo = r[H_JLO], jhi = r[H_JHI];
+                    const float sb0 = S.sb0[i], jlo = r[L::JLO], jhi = r[L::JHI];
 #pragma unroll
                     for (int p = 0; p < P; ++p) {
                         const unsigned z = (cw >> (4 * p)) & 15u;
                         const unsigned zone = z & 3u;
-                        if (zone == 0u) continue;
+                        if (z == 0u) continue;
                         const float j = jl[p] + sb0;
-                        float v;
-                        if (PROF == kVoigt) {
+                        float v = 0.0f;
+                        if (is_voigt(PROF)) {
                             if (zone == 1u) {
-                                v = v_far(r, j);
-                            } else {
-                                const float vm = v_mid<NT>(r, S.m + i, S.csc[i], j);
+                                v = v_far<PROF>(r, j);
+                            } else if (zone != 0u) {
+                                const float vm = v_mid<PROF>(r, mid_coef(S.m[i], S.m[NT + i], g4), S.csc[i], j);
                                 if (zone == 2u) {
                                     v = vm;
                                 } else {
@@ -583,6 +793,11 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
                                     if (in) vcore = A.core_val[S.cb[i] + k];
                                     v = in ? vcore : vm;
                                 }
+                            }
+                            if (PROF == kVVoigt && (z & 8u)) {
+                                const bool inr = (j >= r[L::JVLO]) && (j <= r[L::JVHI]);
+                                const float w = v_vvw(r, j);
+                                v = inr ? v : w;
                             }
                         } else if (PROF == kLorentz) {
                             v = v_lor(r, j);
@@ -632,7 +847,8 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
 template <int PROF, int WAVES, int P>
 void launch_one(const FwdArgs& a, hipStream_t s) {
     const dim3 grid((unsigned)((int64_t)a.n_tiles * a.n_tp * a.n_split)), block(64 * WAVES);
-    if (PROF <= kVoigt && a.seg) hipLaunchKernelGGL((fwd_f32_kernel<PROF, WAVES, P, PROF <= kVoigt>), grid, block, 0, s, a);
+    constexpr bool CAN_SEG = PROF <= kVoigt || PROF == kVVoigt;
+    if (CAN_SEG && a.seg) hipLaunchKernelGGL((fwd_f32_kernel<PROF, WAVES, P, CAN_SEG>), grid, block, 0, s, a);
     else hipLaunchKernelGGL((fwd_f32_kernel<PROF, WAVES, P, false>), grid, block, 0, s, a);
 }
 
@@ -664,6 +880,7 @@ hipError_t launch_records(int profile, const RecArgs& a, hipStream_t s) {
         case kLorentz: hipLaunchKernelGGL(record_kernel<kLorentz>, grid, block, 0, s, a); break;
         case kGHSampled: hipLaunchKernelGGL(record_kernel<kGHSampled>, grid, block, 0, s, a); break;
         case kGHBinned: hipLaunchKernelGGL(record_kernel<kGHBinned>, grid, block, 0, s, a); break;
+        case kVVoigt: hipLaunchKernelGGL(record_kernel<kVVoigt>, grid, block, 0, s, a); break;
         default: hipLaunchKernelGGL(record_kernel<kVoigt>, grid, block, 0, s, a); break;
     }
     return hipGetLastError();
@@ -677,6 +894,7 @@ hipError_t launch_forward_f32(int profile, int waves, int P, const FwdArgs& a, h
         case kLorentz: launch_p<kLorentz>(waves, P, a, s); break;
         case kGHSampled: launch_p<kGHSampled>(waves, P, a, s); break;
         case kGHBinned: launch_p<kGHBinned>(waves, P, a, s); break;
+        case kVVoigt: launch_p<kVVoigt>(waves, P, a, s); break;
         default: launch_p<kVoigt>(waves, P, a, s); break;
     }
     return hipGetLastError();

@@ -3,6 +3,9 @@
 // kernel; every line carries per-slice codes (skip / zone / window mask), and the
 // Voigt zones use Gauss-Hermite rules of 2, 4, 6 and 12 nodes for |z| >= 2200, 60,
 // 20 and 8, and the Weideman/Taylor core (40 terms / 14 terms) inside |z| < 8.
+// Vectorized Voigt: the same Voigt inside the radius R; beyond it beta times the reference
+// profile (Doppler width of a line at 1 cm^-1), evaluated with the 2-node rule in the
+// reference's own variables (relative error 1/(2 |z_ref|^4), |z_ref| >= 2e4).
 #include "xs_forward_common.hpp"
 
 namespace xs {
@@ -11,7 +14,18 @@ namespace {
 
 constexpr int kRec = 32;
 constexpr int kBatch = 256;
-enum : int { D_NU = 0, D_S = 1, D_Y = 2, D_A = 3, D_CODE = 4, D_KLIM = 5, D_AD = 6 };
+enum : int { D_NU = 0, D_S = 1, D_Y = 2, D_A = 3, D_CODE = 4, D_KLIM = 5, D_AD = 6, D_W = 7, D_SR = 8, D_KV = 9 };
+
+// Re w from the plain path's zones, chosen per lane (slices that touch |z| < 8).
+__device__ __forceinline__ double re_w_zones(double x, double y, const Tables* tab) {
+    const double u = x * x;
+    const double z2 = u + y * y;
+    if (z2 < 64.0) return voigt_core_re<40, 14>(x, y, tab->w40);
+    if (z2 < 400.0) return gh_wing_re(u, y, tab->gh12);
+    if (z2 < 3600.0) return gh_wing_re(u, y, tab->gh6);
+    if (z2 < 4.84e6) return gh_wing_re(u, y, tab->gh4);
+    return gh_wing_re(u, y, tab->gh2);
+}
 
 // ============================================================== FP64 path
 template <int PROF, int P>
@@ -47,10 +61,23 @@ __global__ __launch_bounds__(256) void fwd_f64_kernel(const FwdArgs A) {
             const LineSetup ls = line_setup(A.L, tp, g, Q);
             double s, y = 0.0;
             r[D_NU] = ls.nu;
-            if (PROF == kVoigt) {
+            if (PROF == kVoigt || PROF == kVVoigt) {
                 s = kSQRT_LN2 / ls.aD;
                 y = ls.gam * s;
                 r[D_A] = ls.S * kSQRT_LN2_PI / ls.aD;
+                if (PROF == kVVoigt) {
+                    const double2 vv = A.vv ? A.vv[(int64_t)wi.tp * A.vv_stride + g] : make_double2(1.0, 1.0);
+                    const double sr = kSQRT_LN2 / tp.beta;   // reference: alpha_D of a line at 1 cm^-1
+                    r[D_A] *= vv.y;
+                    r[D_W] = vv.x * vv.y * ls.S * kSQRT_LN2_PI / tp.beta;
+                    r[D_SR] = sr;
+                    r[D_AD] = sr * ls.gam;
+                    const double kvl = ceil((ls.nu - G.vv_radius - G.nu_a) / G.dnu);
+                    const double kvh = floor((ls.nu + G.vv_radius - G.nu_a) / G.dnu);
+                    int* kv = reinterpret_cast<int*>(r + D_KV);
+                    kv[0] = (int)fmin(fmax(kvl, -1.0), (double)G.n_points);
+                    kv[1] = (int)fmin(fmax(kvh, -1.0), (double)G.n_points);
+                }
             } else if (PROF == kLorentz) {
                 s = ls.gam > 0.0 ? 1.0 / ls.gam : 0.0;
                 r[D_A] = ls.S * s * (1.0 / kPI);
@@ -80,10 +107,16 @@ __global__ __launch_bounds__(256) void fwd_f64_kernel(const FwdArgs A) {
                     const bool full = (kA >= ls.klo && kB <= ls.khi);
                     const double mx = min_abs_delta(G, kA, kB, ls.nu) * s;
                     unsigned zone = 1;
-                    if (PROF == kVoigt) {
+                    if (PROF == kVoigt || PROF == kVVoigt) {
                         const double z2 = mx * mx + y * y;
                         zone = z2 < 64.0 * 1.0001 ? 5u : z2 < 400.0 * 1.0001 ? 4u
                              : z2 < 3600.0 * 1.0001 ? 3u : z2 < 4.84e6 * 1.0001 ? 2u : 1u;
+                        if (PROF == kVVoigt) {
+                            // 7: every point beyond R; 6: R falls inside the slice
+                            const int* kv = reinterpret_cast<const int*>(r + D_KV);
+                            if (kB < kv[0] || kA > kv[1]) zone = 7u;
+                            else if (!(kA >= kv[0] && kB <= kv[1])) zone = 6u;
+                        }
                     } else if (PROF == kLorentz || PROF == kGHSampled) {
                         zone = ls.gam > 0.0 ? 1u : 0u;
                     } else if (PROF == kGHBinned) {
@@ -109,6 +142,7 @@ __global__ __launch_bounds__(256) void fwd_f64_kernel(const FwdArgs A) {
             const double nu = r[D_NU], s = r[D_S], y = r[D_Y], a = r[D_A];
             const int* kl = reinterpret_cast<const int*>(r + D_KLIM);
             const int klo = kl[0], khi = kl[1];
+            const int* kv = reinterpret_cast<const int*>(r + D_KV);
 #pragma unroll
             for (int p = 0; p < P; ++p) {
                 const unsigned z = (unsigned)(cw >> (4 * p)) & 15u;
@@ -116,7 +150,19 @@ __global__ __launch_bounds__(256) void fwd_f64_kernel(const FwdArgs A) {
                 if (zone == 0u) continue;
                 const double x = s * (nuk[p] - nu);
                 double v;
-                if (PROF == kVoigt) {
+                if (PROF == kVVoigt && zone >= 6u) {
+                    // beta f_ref beyond R (2-node rule in the reference's variables)
+                    const double xr = r[D_SR] * (nuk[p] - nu);
+                    const double vw = r[D_W] * gh_wing_re(xr * xr, r[D_AD], A.tab->gh2);
+                    if (zone == 7u) {
+                        v = vw;
+                    } else {
+                        const bool inr = kk[p] >= kv[0] && kk[p] <= kv[1];
+                        double vc = 0.0;
+                        if (inr) vc = a * re_w_zones(x, y, A.tab);
+                        v = inr ? vc : vw;
+                    }
+                } else if (PROF == kVoigt || PROF == kVVoigt) {
                     const double u = x * x;
                     if (zone == 1u) v = gh_wing_re(u, y, A.tab->gh2);
                     else if (zone == 2u) v = gh_wing_re(u, y, A.tab->gh4);
@@ -246,6 +292,7 @@ hipError_t launch_forward(int profile, int fp64, int waves, int P, const FwdArgs
         case kLorentz: launch_p64<kLorentz>(P, a, s); break;
         case kGHSampled: launch_p64<kGHSampled>(P, a, s); break;
         case kGHBinned: launch_p64<kGHBinned>(P, a, s); break;
+        case kVVoigt: launch_p64<kVVoigt>(P, a, s); break;
         default: launch_p64<kVoigt>(P, a, s); break;
     }
     return hipGetLastError();

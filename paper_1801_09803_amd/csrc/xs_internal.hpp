@@ -46,6 +46,11 @@ struct Geometry {
     int hmax;    // upper bound of |window edge - kc| in grid steps (key offset)
     int hmin;    // lower bound of the same (lines with |kc - k| <= hmin cover k)
     int nkeys;   // number of sort keys for kept lines; key == nkeys marks a dropped line
+    // Vectorized Voigt: radius R (cm^-1) of the region where the line's own Voigt profile
+    // is used, and bounds of |k - kc| at the region's edges in grid steps (every point
+    // with |k - kc| <= rvmin is inside, every point with |k - kc| > rvmax outside)
+    double vv_radius;
+    int rvmin, rvmax;
 };
 
 // Per (T, P) scalars computed on the host (everything but Q(T), which stays on the device).

@@ -36,15 +36,16 @@ def test_library_exports_every_declared_symbol():
 def test_version_and_defaults_without_gpu():
     from paper_1801_09803_amd.binding import XsOpts, load_library
     lib = load_library()
-    assert lib.xs_version() == 2
+    assert lib.xs_version() == 3
     o = XsOpts()
     assert lib.xs_opts_default(ctypes.byref(o)) == 0
     assert o.cutoff == 25.0 and o.T0 == 296.0 and o.P0 == 1.0 and o.profile == 3
 
 
 @pytest.mark.parametrize("field,value", [("n_points", 1), ("cutoff", 0.0), ("mass_da", -1.0),
-                                         ("profile", 9), ("index_base", 2), ("slices_per_wave", 3),
-                                         ("n_split", 65), ("n_split", -1), ("tp_block", 257)])
+                                         ("profile", 8), ("index_base", 2), ("slices_per_wave", 3),
+                                         ("n_split", 65), ("n_split", -1), ("tp_block", 257),
+                                         ("vv_beta", 2), ("vv_radius", -1.0), ("vv_radius", float("nan"))])
 def test_plan_create_rejects_bad_options_on_host(field, value):
     # option validation happens before any device call
     from paper_1801_09803_amd.binding import XsOpts, load_library
@@ -68,10 +69,11 @@ def test_null_arguments_are_rejected_without_gpu():
 
 
 def test_struct_layouts_match_the_header():
-    # the binding's ctypes mirrors must keep the C sizes (xs_opts keeps its size: the
-    # tile-configuration fields took reserved slots)
+    # the binding's ctypes mirrors must keep the C sizes and offsets (xs_opts keeps its
+    # size: the tile-configuration and Vectorized Voigt fields took reserved slots)
     from paper_1801_09803_amd.binding import XsKernelTimes, XsOpts
-    assert ctypes.sizeof(XsOpts) == 8 * 7 + 4 * 4 + 8 * 3 + 4 * 8
+    assert ctypes.sizeof(XsOpts) == 8 * 7 + 4 * 4 + 8 * 3 + 4 * 6 + 8
+    assert XsOpts.vv_beta.offset == 116 and XsOpts.vv_radius.offset == 120
     assert ctypes.sizeof(XsKernelTimes) == 8 * 9
 
 

@@ -24,7 +24,7 @@ def _sample_points(sig, n_rand, seed, n_points):
     return np.array(sorted(pts))
 
 
-def _oracle_at(cfg, d, ks, T, P, margin=25.5):
+def _oracle_at(cfg, d, ks, T, P, margin=25.5, vv_beta=None):
     """Oracle sigma at grid indices ks: lines near each point are gathered on the
     device (a generous distance filter) and evaluated on the host."""
     E = d["E"]
@@ -40,6 +40,9 @@ def _oracle_at(cfg, d, ks, T, P, margin=25.5):
     ls = O.make_lineset(Eh, gh, h["upper"], h["lower"], h["A"], T, P, cfg.mass_amu,
                         gamma_ref=h["gamma_ref"], n_exp=h["n_exp"], Q=Q)
     log(f"  oracle: {idx.numel()} lines near {ks.size} points")
+    if vv_beta is not None:
+        return O.cross_section_vv_at(ls, ks, cfg.nu_a, cfg.nu_b, cfg.n_points, T, cfg.mass_amu, cutoff=cfg.cutoff,
+                                     radius=4.0, use_beta=vv_beta)
     return O.cross_section_at(ls, ks, cfg.nu_a, cfg.nu_b, cfg.n_points, cfg.cutoff)
 
 
@@ -81,6 +84,19 @@ def test_c2_full_size_fp64_sampled(c2):
     ks = _sample_points(sig, 12, 7, cfg.n_points)
     ref = _oracle_at(cfg, d, ks, 2000.0, 1.0)
     _check(sig[ks], ref, 1e-10, "C2 fp64 T=2000")
+
+
+@pytest.mark.parametrize("T,beta", [(296.0, False), (2000.0, True)])
+def test_c2_full_size_vvoigt_sampled(c2, T, beta):
+    # the Vectorized Voigt at the full C2 list, in the tile shape bench.py times
+    cfg, d = c2
+    plan = make_plan(cfg, "fp32", profile="vvoigt", vv_beta=beta)
+    plan.set_states(d["E"], d["g"], d["J"])
+    plan.set_lines(d["upper"], d["lower"], d["A"], d["gamma_ref"], d["n_exp"])
+    sig = plan.cross_section([T], [1.0])[0].double().cpu().numpy()
+    ks = _sample_points(sig, 16, 11 + int(T), cfg.n_points)
+    ref = _oracle_at(cfg, d, ks, T, 1.0, vv_beta=beta)
+    _check(sig[ks], ref, 1e-5, f"C2 V-V fp32 T={T} beta={beta}")
 
 
 def test_c3_subset_full_size(c2):
