@@ -39,9 +39,9 @@ FLOPS_PER_EVAL = 12          # far-wing rational: j add, 4 fma, rcp, accumulate 
 # Valid only for the kernel sources they were taken with (hash below).
 TRAFFIC = {
     "kernel_sources": ['xs_forward_f32.hip', 'xs_forward_common.hpp', 'xs_voigt.hpp', 'xs_forward.hpp', 'xs_internal.hpp'],
-    "sha256": "c4005d6070e6d95a88b57103bf0e5b7de1934b847556c0c69c51291ee2a8ab28",
-    "fetch_kib": [31847958.3, 36475372.5],
-    "write_kib": [251199.2, 251556.9],
+    "sha256": "e240f86a8ce9f04fe7f775e2e1a50325f71b289bb8ad39abd40a411e2c093038",
+    "fetch_kib": [32131259.6, 36808961.8],
+    "write_kib": [251283.2, 251602.2],
     "fetch_scale": 2.0,
     "write_scale": 1.0,
 }
@@ -336,6 +336,7 @@ def vv_leg(cfg, d, temps, pressures, tile, voigt_out, n_kept, stream, log):
     """The Vectorized Voigt (beta = 1) and its area-normalised form (with beta) on the same
     list and tile shape: one call over all (T, P), pre-passes included, and how far each
     departs from the Voigt result of the timed steps (an approximation, not an error)."""
+    import torch
     from paper_1801_09803_amd import Plan
     legs = {}
     for prof, beta in (("vvoigt", False), ("vvoigt_norm", True)):
