@@ -13,3 +13,4 @@ states use ``math.fsum`` (correctly rounded).
 from .constants import *  # noqa: F401,F403
 from .xsec import *  # noqa: F401,F403
 from .vvoigt import *  # noqa: F401,F403
+from .binned import *  # noqa: F401,F403

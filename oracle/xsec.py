@@ -49,7 +49,8 @@ __all__ = [
     "PROFILES",
 ]
 
-PROFILES = ("doppler", "gauss_fixed", "lorentz", "voigt", "gh_binned", "gh_sampled")
+PROFILES = ("doppler", "gauss_fixed", "lorentz", "voigt", "gh_binned", "gh_sampled", "doppler_binned",
+            "lorentz_binned")
 
 
 # ----------------------------------------------------------------------------- grid
@@ -253,6 +254,12 @@ def _profile_values(kind, delta, aD, gam, dnu, alpha_fixed, n_gh):
         return gh_sampled_profile(delta, aD, gam, n_gh)
     if kind == "gh_binned":
         return gh_binned_profile(delta, aD, gam, dnu, n_gh)
+    if kind == "doppler_binned":
+        from .binned import gauss_binned_profile
+        return gauss_binned_profile(delta, aD, dnu)
+    if kind == "lorentz_binned":
+        from .binned import lorentz_binned_profile
+        return lorentz_binned_profile(delta, gam, dnu)
     raise ValueError(kind)
 
 

@@ -187,3 +187,30 @@ def test_vvn_normalisation_mistakes_are_caught(monkeypatch, variant):
     monkeypatch.setattr(VV, "_vv_lines", bad)
     with pytest.raises(AssertionError):
         vpins.test_vvn_preserves_the_line_area()
+
+
+# ------------------------------------------------------------ binned profiles, super-lines
+import oracle.binned as BN  # noqa: E402
+from tests import test_oracle_binned as bpins  # noqa: E402
+
+
+def test_gauss_binned_without_the_half_is_caught(monkeypatch):
+    good = BN.gauss_binned_profile
+    monkeypatch.setattr(BN, "gauss_binned_profile", lambda d, a, dnu: 2.0 * good(d, a, dnu))
+    monkeypatch.setattr(O, "gauss_binned_profile", lambda d, a, dnu: 2.0 * good(d, a, dnu))
+    with pytest.raises(AssertionError):
+        bpins.test_binned_areas_telescope_to_the_closed_forms()
+
+
+def test_lorentz_binned_with_full_width_edges_is_caught(monkeypatch):
+    good = BN.lorentz_binned_profile
+    monkeypatch.setattr(O, "lorentz_binned_profile", lambda d, g, dnu: good(d, g, 2.0 * dnu) * 2.0)
+    with pytest.raises(AssertionError):
+        bpins.test_lorentz_binned_is_the_bin_average(0.05, 0.01)
+
+
+def test_super_line_bins_by_truncation_are_caught(monkeypatch):
+    monkeypatch.setattr(BN, "stick_bins",
+                        lambda nu, nu_a, dnu: np.floor((np.asarray(nu) - nu_a) / dnu).astype(np.int64))
+    with pytest.raises(AssertionError):
+        bpins.test_super_line_histogram_equals_brute_force_bins()
