@@ -114,6 +114,7 @@ def main():
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-stream", action="store_true")
     ap.add_argument("--no-vv", action="store_true", help="skip the Vectorized Voigt leg")
+    ap.add_argument("--no-binned", action="store_true", help="skip the binned-profile / super-line leg")
     ap.add_argument("--stream-chunks", type=int, default=4)
     ap.add_argument("--stream-chunk-lines", type=int, default=1 << 24)
     ap.add_argument("--autotune-ms", type=float, default=20000.0,
@@ -320,6 +321,8 @@ def main():
 
     if not args.no_vv:
         result["vectorized_voigt"] = vv_leg(cfg, d, temps, pressures, tile, out, n_kept, stream, log)
+    if not args.no_binned:
+        result["binned_profiles"] = binned_leg(cfg, d, temps, pressures, n_kept, stream, log)
 
     del plan, out, d
     torch.cuda.empty_cache()
@@ -376,6 +379,51 @@ def vv_leg(cfg, d, temps, pressures, tile, voigt_out, n_kept, stream, log):
     legs["note"] = ("same list, grid and tile shape as the headline; radius 4 cm^-1; call = Q(T) + "
                     "pre-passes + tile kernel for all (T,P), line preparation excluded")
     return legs
+
+
+def binned_leg(cfg2, d2, temps, pressures, n_kept2, stream, log):
+    """Bin-averaged profiles on the coarse C1 grid they are meant for (0.1 cm^-1; the
+    sampled Voigt profile timed alongside), and super-line histograms of the C2 list."""
+    import torch
+    import synth
+    from paper_1801_09803_amd import Plan
+
+    def timed(plan, Ts, Ps, out, reps=5):
+        plan.cross_section(Ts, Ps, out=out)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            plan.cross_section(Ts, Ps, out=out)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / 1e3 / reps
+
+    res = {}
+    cfg1 = synth.CONFIGS["C1"]
+    d1 = synth.make_linelist(cfg1, device="cuda")
+    out1 = torch.empty((1, cfg1.n_points), dtype=torch.float32, device="cuda")
+    T1, P1 = [cfg1.temperatures[0]], [cfg1.pressures[0]]
+    for prof in ("voigt", "doppler_binned", "lorentz_binned"):
+        plan = Plan(cfg1.nu_a, cfg1.nu_b, cfg1.n_points, cfg1.mass_amu, cutoff=cfg1.cutoff, profile=prof)
+        plan.set_states(d1["E"], d1["g"], d1["J"])
+        plan.set_lines(d1["upper"], d1["lower"], d1["A"], d1["gamma_ref"], d1["n_exp"])
+        t = timed(plan, T1, P1, out1)
+        res[f"C1_{prof}"] = {"call_ms": t * 1e3, "line_profiles_per_s": plan.lines_kept() / t}
+        log(f"C1 {prof}: {t * 1e3:.2f} ms per call")
+        del plan
+    plan = Plan(cfg2.nu_a, cfg2.nu_b, cfg2.n_points, cfg2.mass_amu, cutoff=cfg2.cutoff, profile="superlines")
+    plan.set_states(d2["E"], d2["g"], d2["J"])
+    plan.set_lines(d2["upper"], d2["lower"], d2["A"], d2["gamma_ref"], d2["n_exp"])
+    out2 = torch.empty((len(temps), cfg2.n_points), dtype=torch.float32, device="cuda")
+    t = timed(plan, temps, pressures, out2, reps=3)
+    res["C2_superlines"] = {"call_ms": t * 1e3, "lines_per_s": n_kept2 * len(temps) / t,
+                            "note": "per-bin intensity sums of the 1e8 sorted lines for both (T,P); "
+                                    "line preparation excluded"}
+    log(f"C2 super-lines: {t * 1e3:.2f} ms per call")
+    res["note"] = ("C1: 1e5 lines, 0-5000 cm^-1 at 0.1, 1000 K, 1 bar, FP32; call = Q(T) + pre-passes + "
+                   "tile kernel, line preparation excluded")
+    return res
 
 
 def stream_run(cfg, dev, log, n_chunks, chunk):

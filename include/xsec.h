@@ -85,12 +85,26 @@ typedef enum {
                             Calls return XS_ERR_ARG when sqrt(ln2) R / alpha_ref < 2e4 at a
                             requested T (alpha_ref the reference's Doppler HWHM), where the
                             reference wing would lose its closed form.                   */
-    XS_VVOIGT_NORM = 7   /* XS_VVOIGT with each line's intensity divided by dnu times the
+    XS_VVOIGT_NORM = 7,  /* XS_VVOIGT with each line's intensity divided by dnu times the
                             sum of its profile values over its whole cut-off window (the
                             window on the grid extended past its ends), so that a line whose
                             window lies on the grid adds exactly I to dnu sum_k sigma_k
                             (Sec. "Binned Vectorized Voigt with the line area preserved"); a
                             line whose profile sums to zero adds nothing                  */
+    XS_DOPPLER_BINNED = 8,  /* bin-averaged Doppler Gaussian (Sec. "Binned Gaussian profile
+                            with analytical integrals"): sigma_k = I/(2 dnu) [erf(x+) -
+                            erf(x-)], x+- = sqrt(ln2)(nu_k +- dnu/2 - nu)/alpha_D, evaluated
+                            in double (erfc differences in the tails); same windows as the
+                            sampled profiles                                                */
+    XS_LORENTZ_BINNED = 9,  /* bin-averaged Lorentzian (Sec. "Binned Lorentzian profile with
+                            analytical integrals", Eq. 27-28 with the minus sign between nu_k
+                            and nu restored): sigma_k = I/(pi dnu) [atan(y+) - atan(y-)],
+                            y+- = (nu_k +- dnu/2 - nu)/gamma_L; gamma_L = 0 gives the step
+                            limit (I/dnu in the line's bin)                                  */
+    XS_SUPERLINES = 10      /* super-line histogram (Sec. "Super-lines", the Bin option):
+                            sigma_k = (sum of I over the lines with floor((nu - nu_a)/dnu +
+                            0.5) = k) / dnu, half-open bins; the super-line intensity of
+                            grid point k is dnu sigma_k.  No profile, no cut-off            */
 } xs_profile;
 
 typedef enum {

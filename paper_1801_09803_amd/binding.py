@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_NAME = "libxsec.so"
 
 PROFILES = {"doppler": 0, "gauss_fixed": 1, "lorentz": 2, "voigt": 3, "gh_sampled": 4, "gh_binned": 5,
-            "vvoigt": 6, "vvoigt_norm": 7}
+            "vvoigt": 6, "vvoigt_norm": 7, "doppler_binned": 8, "lorentz_binned": 9, "superlines": 10}
 PRECISIONS = {"fp64": 0, "fp32": 1}
 BROADENING = {"const": 0, "per_line": 1, "a0_jlower": 2}
 STATUS = {0: "XS_OK", 1: "XS_ERR_ARG", 2: "XS_ERR_INDEX", 3: "XS_ERR_NU_NONPOS", 4: "XS_ERR_HIP",

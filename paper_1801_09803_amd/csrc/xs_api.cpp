@@ -285,7 +285,7 @@ xs_status validate_opts(const xs_opts* o) {
     if (!(o->cutoff > 0.0) || !std::isfinite(o->cutoff)) return fail(XS_ERR_ARG, "cutoff must be > 0");
     if (!(o->mass_da > 0.0)) return fail(XS_ERR_ARG, "mass_da must be > 0");
     if (!(o->T0 > 0.0) || !(o->P0 > 0.0)) return fail(XS_ERR_ARG, "T0 and P0 must be > 0");
-    if (o->profile < XS_DOPPLER || o->profile > XS_VVOIGT_NORM) return fail(XS_ERR_UNSUPPORTED, "unknown profile");
+    if (o->profile < XS_DOPPLER || o->profile > XS_SUPERLINES) return fail(XS_ERR_UNSUPPORTED, "unknown profile");
     if (o->vv_beta != 0 && o->vv_beta != 1) return fail(XS_ERR_ARG, "vv_beta must be 0 or 1");
     if (!(o->vv_radius >= 0.0) || !std::isfinite(o->vv_radius)) return fail(XS_ERR_ARG, "vv_radius must be >= 0");
     if (o->precision != XS_FP64 && o->precision != XS_FP32) return fail(XS_ERR_ARG, "unknown precision");
@@ -394,13 +394,27 @@ xs::TPParam make_tp(const xs_plan* p, double T, double P, int iq, double T_rm) {
 bool vv_needed(const xs_plan* p) { return is_vv(p) && (p->o.vv_beta || p->o.profile == XS_VVOIGT_NORM); }
 
 // Profile index of the kernels (the area-normalised form differs in its intensities only)
-int kernel_profile(const xs_plan* p) { return is_vv(p) ? (int)xs::kVVoigt : p->o.profile; }
+int kernel_profile(const xs_plan* p) {
+    switch (p->o.profile) {
+        case XS_VVOIGT:
+        case XS_VVOIGT_NORM: return xs::kVVoigt;
+        case XS_DOPPLER_BINNED: return xs::kDopplerBinned;
+        case XS_LORENTZ_BINNED: return xs::kLorentzBinned;
+        case XS_SUPERLINES: return xs::kSuperLines;
+        default: return p->o.profile;
+    }
+}
+
+bool superlines(const xs_plan* p) { return p->o.profile == XS_SUPERLINES; }
 
 int hot_words(const xs_plan* p) { return is_vv(p) ? 12 : 8; }
 
 bool core_path(const xs_plan* p) { return p->o.precision == XS_FP32 && voigt_like(p); }
 
 bool fp32_path(const xs_plan* p) { return p->o.precision == XS_FP32; }
+
+// FP32 line records (every profile of the FP32 tile kernel; super-lines read the lines)
+bool records_path(const xs_plan* p) { return fp32_path(p) && !superlines(p); }
 
 // The Vectorized Voigt wing uses the Lorentzian (FP32) or the 2-node rule (FP64) for the
 // reference profile: both need x_ref = sqrt(ln2) R / alpha_ref >= 2e4 at every temperature.
@@ -418,7 +432,7 @@ xs_status check_vv(const xs_plan* p, int n, const double* T) {
 // Bytes of per-(line, T, P) workspace: FP32 line records (104 or 120 B), Voigt core rows
 // (16 B) and Vectorized Voigt factors (16 B).
 int64_t row_bytes_per_line(const xs_plan* p) {
-    return (fp32_path(p) ? 72 + 4 * hot_words(p) : 0) + (core_path(p) ? 16 : 0) + (vv_needed(p) ? 16 : 0);
+    return (records_path(p) ? 72 + 4 * hot_words(p) : 0) + (core_path(p) ? 16 : 0) + (vv_needed(p) ? 16 : 0);
 }
 
 int pick_block(const xs_plan* p, int n_tp) {
@@ -436,6 +450,7 @@ int pick_block(const xs_plan* p, int n_tp) {
 // batches of lines.  It depends on the plan only, so a (T, P) result does not depend
 // on the other points of its call.
 int pick_split(const xs_plan* p) {
+    if (superlines(p)) return 1;   // one thread per grid point, no shares
     if (p->n_split > 0) return p->n_split;
     const int nt = n_tiles(p);
     const xs::Geometry& G = p->geo;
@@ -463,7 +478,7 @@ xs_status ensure_rows(xs_plan* p, Workset& ws, int B, int S) {
         ws.rows = B;
         ws.row_stride = n;
     }
-    if (fp32_path(p)) {
+    if (records_path(p)) {
         XS_TRY(ws.ensure(ws.hot, (size_t)B * n * hot_words(p) * sizeof(float), "line records"));
         XS_TRY(ws.ensure(ws.cold, (size_t)B * n * 16 * sizeof(int), "line records"));
         XS_TRY(ws.ensure(ws.xscale, (size_t)B * n * sizeof(double), "line records"));
@@ -544,7 +559,7 @@ xs::FwdArgs fwd_args(xs_plan* p, Workset& ws, const std::vector<xs::TPParam>& tp
         a.vv = as<double2>(ws.vv) + (int64_t)row0 * ws.row_stride;
         a.vv_stride = ws.row_stride;
     }
-    if (fp32_path(p)) {
+    if (records_path(p)) {
         a.hot = as<float>(ws.hot) + (int64_t)row0 * ws.row_stride * hot_words(p);
         a.cold = as<int>(ws.cold) + (int64_t)row0 * ws.row_stride * 16;
         a.xscale = as<double>(ws.xscale) + (int64_t)row0 * ws.row_stride;
@@ -634,7 +649,7 @@ xs_status enqueue_prepass(xs_plan* p, Workset& ws, int it, int row, bool count, 
         v.out = as<double2>(ws.vv) + (int64_t)row * ws.row_stride;
         XS_HIP(xs::launch_vv_prep(v, s));
     }
-    if (!fp32_path(p)) return XS_OK;
+    if (!records_path(p)) return XS_OK;
     if (core_path(p)) {
         xs::CoreArgs c = core_args(p, ws, it, row);
         c.val_base = vbase[it];
@@ -650,7 +665,7 @@ xs_status enqueue_block(xs_plan* p, Workset& ws, const std::vector<xs::TPParam>&
                         bool count, const std::vector<long long>& vbase, const std::vector<long long>& vend,
                         void* sigma, hipStream_t s, bool timed) {
     const bool fp64 = p->o.precision == XS_FP64;
-    if ((fp32_path(p) || vv_needed(p)) && p->n_kept > 0) {
+    if ((records_path(p) || vv_needed(p)) && p->n_kept > 0) {
         for (int t = 0; t < nb; ++t) {
             Timer tc(p, s, 1, 0, timed);
             XS_TRY(enqueue_prepass(p, ws, f + t, t, count, vbase, vend, s));

@@ -8,7 +8,10 @@ namespace xs {
 
 enum ProfileKind {
     kDoppler = 0, kGaussFixed = 1, kLorentz = 2, kVoigt = 3, kGHSampled = 4, kGHBinned = 5,
-    kVVoigt = 6   // Vectorized Voigt (the area-normalised form differs only in its intensities)
+    kVVoigt = 6,          // Vectorized Voigt (the area-normalised form differs only in its intensities)
+    kDopplerBinned = 7,   // bin-averaged Doppler Gaussian (difference of error functions)
+    kLorentzBinned = 8,   // bin-averaged Lorentzian (difference of arctangents)
+    kSuperLines = 9       // per-bin intensity sums (no profile)
 };
 
 struct FwdArgs {
@@ -91,6 +94,9 @@ inline int tile_points(int slices_per_wave, int waves) { return 64 * waves * sli
 
 hipError_t launch_forward(int profile, int fp64, int waves, int slices_per_wave, const FwdArgs& a,
                           hipStream_t s);
+// Super-line histograms: sigma[t][k] = (sum of the intensities of the lines with kc == k) / dnu
+// for the launch's (T, P) block (one thread per grid point; lines of a bin in sorted order).
+hipError_t launch_superlines(int fp64, const FwdArgs& a, hipStream_t s);
 // n_split > 1: sigma[t][k] = compensated sum over parts of part[t][*][k]
 hipError_t launch_combine(int fp64, const FwdArgs& a, hipStream_t s);
 

@@ -72,6 +72,14 @@ __device__ __forceinline__ int radius_steps(double X, double h, double xc) {
     return r > 1.0e9 ? 1000000000 : (int)r;
 }
 
+// erf(b) - erf(a) for a <= b without cancellation in the tails: a difference of
+// complementary error functions of same-signed arguments there.
+__device__ __forceinline__ double erf_diff64(double a, double b) {
+    if (a >= 0.0) return erfc(a) - erfc(b);
+    if (b <= 0.0) return erfc(-b) - erfc(-a);
+    return erf(b) - erf(a);
+}
+
 // Core radius of the FP32 Voigt path: points with |z| < 8 are evaluated by the
 // double-precision core pre-pass.
 constexpr double kCoreR2 = 64.0;

@@ -182,6 +182,35 @@ __global__ __launch_bounds__(256) void record_kernel(const RecArgs A) {
             cf[C_M + 4] = (float)(gam * gam - 0.25 * G.dnu * G.dnu);
         }
         c[C_FLAG] = gam > 0.0 ? 1 : 0;
+    } else if (PROF == kLorentzBinned) {
+        // bin average of Eq. 17: S/(pi dnu) atan2(dnu gamma, D^2 + gamma^2 - dnu^2/4)
+        scale = 1.0;
+        h[L::XC] = (float)d;
+        h[L::H] = (float)G.dnu;
+        h[L::AMP] = (float)(S / (kPI * G.dnu));
+        cf[C_M + 0] = (float)(G.dnu * gam);
+        cf[C_M + 1] = (float)(gam * gam - 0.25 * G.dnu * G.dnu);
+        // the three bins nearest the centre are evaluated in double (D^2 - dnu^2/4 cancels
+        // there): centre offset d and gamma
+        const long long bd = __double_as_longlong(d), bg = __double_as_longlong(gam);
+        c[C_M + 2] = (int)(unsigned)(bd & 0xffffffffll);
+        c[C_M + 3] = (int)(bd >> 32);
+        c[C_M + 4] = (int)(unsigned)(bg & 0xffffffffll);
+        c[C_M + 5] = (int)(bg >> 32);
+    } else if (PROF == kDopplerBinned) {
+        // bin average of Eq. 15 (Doppler HWHM): S/(2 dnu) [erf(x+) - erf(x-)], evaluated in
+        // double from the centre offset d and s = sqrt(ln2)/alpha_D (cold words)
+        const double s = kSQRT_LN2 / aD;
+        scale = 1.0;
+        h[L::XC] = (float)d;
+        h[L::H] = (float)G.dnu;
+        h[L::AMP] = (float)(S / (2.0 * G.dnu));
+        const long long bd = __double_as_longlong(d), bs = __double_as_longlong(s);
+        c[C_M + 0] = (int)(unsigned)(bd & 0xffffffffll);
+        c[C_M + 1] = (int)(bd >> 32);
+        c[C_M + 2] = (int)(unsigned)(bs & 0xffffffffll);
+        c[C_M + 3] = (int)(bs >> 32);
+        c[C_RAD] = radius_steps(10.5 + 0.5 * s * G.dnu, s * G.dnu, s * d);   // both edges beyond x = 10.5
     } else {
         // Gaussian (Eq. 15); x scaled by sqrt(1/ln 2) so exp(-x^2) = exp2(-x'^2)
         const double alpha = (PROF == kDoppler) ? aD : A.alpha_fixed;
@@ -467,7 +496,9 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
     constexpr bool ANCH = SEG && anchors_in_lds(PROF);
     constexpr int RS = ANCH ? RH + WAVES : RH;   // LDS record words
     constexpr int NTF = SEG ? 0 : NCW * NT;
-    constexpr int NM = (PROF == kGHSampled || PROF == kGHBinned) ? 5 : 2;   // cold profile words in LDS
+    // cold profile words in LDS
+    constexpr int NM = (PROF == kGHSampled || PROF == kGHBinned) ? 5
+                       : PROF == kDopplerBinned ? 4 : PROF == kLorentzBinned ? 6 : 2;
     __shared__ Lds<NT, RS, NTF, NM> S;
 
     const Geometry G = A.G;
@@ -575,11 +606,10 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
                 S.cb[tid] = (long long)(((unsigned long long)(unsigned)q1.w << 32) | (unsigned)q1.z);
                 S.m[0 * NT + tid] = __int_as_float(q2.x);
                 S.m[1 * NT + tid] = __int_as_float(q2.y);
-                if constexpr (NM > 2) {
-                    S.m[2 * NT + tid] = __int_as_float(q2.z);
-                    S.m[3 * NT + tid] = __int_as_float(q2.w);
-                    S.m[4 * NT + tid] = __int_as_float(q3.x);
-                }
+                if constexpr (NM > 2) S.m[2 * NT + tid] = __int_as_float(q2.z);
+                if constexpr (NM > 3) S.m[3 * NT + tid] = __int_as_float(q2.w);
+                if constexpr (NM > 4) S.m[4 * NT + tid] = __int_as_float(q3.x);
+                if constexpr (NM > 5) S.m[5 * NT + tid] = __int_as_float(q3.y);
                 if constexpr (!SEG) {
                     // 4-bit code per slice: zone (0 skip, 1 far, 2 mid, 3 core) | 4 (mask)
                     // | 8 (Vectorized Voigt: points beyond R)
@@ -611,7 +641,7 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
                                 }
                             } else if (PROF == kLorentz || PROF == kGHSampled) {
                                 zone = flag ? 1u : 0u;
-                            } else if (PROF == kGHBinned) {
+                            } else if (PROF == kGHBinned || PROF == kLorentzBinned) {
                                 zone = 1u;
                             } else {
                                 zone = ((int64_t)kA <= (int64_t)kc + rad && (int64_t)kB >= (int64_t)kc - rad) ? 1u : 0u;
@@ -805,6 +835,26 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
                             v = v_ghs<NT>(A.tab, r, S.m + i, j);
                         } else if (PROF == kGHBinned) {
                             v = v_ghb<NT>(A.tab, r, S.m + i, j);
+                        } else if (PROF == kLorentzBinned) {
+                            if (fabsf(j) > 1.0f) {
+                                const float D = __builtin_fmaf(j, r[LD::H], r[LD::XC]);
+                                v = r[LD::AMP] * atan2f(S.m[i], __builtin_fmaf(D, D, S.m[NT + i]));
+                            } else {
+                                // bins next to the centre: (D - dnu/2)(D + dnu/2) + gamma^2 in double
+                                const double dd =
+                                    __hiloint2double(__float_as_int(S.m[3 * NT + i]), __float_as_int(S.m[2 * NT + i]));
+                                const double gg =
+                                    __hiloint2double(__float_as_int(S.m[5 * NT + i]), __float_as_int(S.m[4 * NT + i]));
+                                const double lo = __builtin_fma((double)j - 0.5, G.dnu, dd);
+                                const double hi = __builtin_fma((double)j + 0.5, G.dnu, dd);
+                                v = r[LD::AMP] * (float)atan2(G.dnu * gg, __builtin_fma(lo, hi, gg * gg));
+                            }
+                        } else if (PROF == kDopplerBinned) {
+                            const double dd = __hiloint2double(__float_as_int(S.m[NT + i]), __float_as_int(S.m[i]));
+                            const double ss =
+                                __hiloint2double(__float_as_int(S.m[3 * NT + i]), __float_as_int(S.m[2 * NT + i]));
+                            const double D = __builtin_fma((double)j, G.dnu, dd);
+                            v = r[LD::AMP] * (float)erf_diff64(ss * (D - 0.5 * G.dnu), ss * (D + 0.5 * G.dnu));
                         } else {
                             v = v_gauss(r, j);
                         }
@@ -881,6 +931,8 @@ hipError_t launch_records(int profile, const RecArgs& a, hipStream_t s) {
         case kGHSampled: hipLaunchKernelGGL(record_kernel<kGHSampled>, grid, block, 0, s, a); break;
         case kGHBinned: hipLaunchKernelGGL(record_kernel<kGHBinned>, grid, block, 0, s, a); break;
         case kVVoigt: hipLaunchKernelGGL(record_kernel<kVVoigt>, grid, block, 0, s, a); break;
+        case kDopplerBinned: hipLaunchKernelGGL(record_kernel<kDopplerBinned>, grid, block, 0, s, a); break;
+        case kLorentzBinned: hipLaunchKernelGGL(record_kernel<kLorentzBinned>, grid, block, 0, s, a); break;
         default: hipLaunchKernelGGL(record_kernel<kVoigt>, grid, block, 0, s, a); break;
     }
     return hipGetLastError();
@@ -895,6 +947,8 @@ hipError_t launch_forward_f32(int profile, int waves, int P, const FwdArgs& a, h
         case kGHSampled: launch_p<kGHSampled>(waves, P, a, s); break;
         case kGHBinned: launch_p<kGHBinned>(waves, P, a, s); break;
         case kVVoigt: launch_p<kVVoigt>(waves, P, a, s); break;
+        case kDopplerBinned: launch_p<kDopplerBinned>(waves, P, a, s); break;
+        case kLorentzBinned: launch_p<kLorentzBinned>(waves, P, a, s); break;
         default: launch_p<kVoigt>(waves, P, a, s); break;
     }
     return hipGetLastError();

@@ -81,6 +81,15 @@ __global__ __launch_bounds__(256) void fwd_f64_kernel(const FwdArgs A) {
             } else if (PROF == kLorentz) {
                 s = ls.gam > 0.0 ? 1.0 / ls.gam : 0.0;
                 r[D_A] = ls.S * s * (1.0 / kPI);
+            } else if (PROF == kLorentzBinned) {
+                // bin average of Eq. 17 in wavenumber units (x = D, y = gamma)
+                s = 1.0;
+                y = ls.gam;
+                r[D_A] = ls.S / (kPI * G.dnu);
+            } else if (PROF == kDopplerBinned) {
+                // bin average of Eq. 15 with the Doppler HWHM
+                s = kSQRT_LN2 / ls.aD;
+                r[D_A] = ls.S / (2.0 * G.dnu);
             } else if (PROF == kGHSampled || PROF == kGHBinned) {
                 // Gauss-Hermite convolution in wavenumber units (x = D, y = gamma)
                 s = 1.0;
@@ -119,8 +128,11 @@ __global__ __launch_bounds__(256) void fwd_f64_kernel(const FwdArgs A) {
                         }
                     } else if (PROF == kLorentz || PROF == kGHSampled) {
                         zone = ls.gam > 0.0 ? 1u : 0u;
-                    } else if (PROF == kGHBinned) {
+                    } else if (PROF == kGHBinned || PROF == kLorentzBinned) {
                         zone = 1u;
+                    } else if (PROF == kDopplerBinned) {
+                        const double e = mx - 0.5 * s * G.dnu;   // nearest bin edge, scaled
+                        zone = (e < 0.0 || e * e < 745.0) ? 1u : 0u;
                     } else {
                         zone = (mx * mx < 745.0) ? 1u : 0u;   // exp(-x^2) underflows beyond
                     }
@@ -203,6 +215,12 @@ __global__ __launch_bounds__(256) void fwd_f64_kernel(const FwdArgs A) {
                         accg = __builtin_fma(A.tab->wconv[q], atan2(hg, __builtin_fma(e, e, c)), accg);
                     }
                     v = a * accg;
+                } else if (PROF == kLorentzBinned) {
+                    // atan(y+) - atan(y-) = atan2(dnu gamma, (D - dnu/2)(D + dnu/2) + gamma^2)
+                    v = a * atan2(G.dnu * y, __builtin_fma(x - 0.5 * G.dnu, x + 0.5 * G.dnu, y * y));
+                } else if (PROF == kDopplerBinned) {
+                    const double hs = 0.5 * s * G.dnu;
+                    v = a * erf_diff64(x - hs, x + hs);
                 } else {
                     v = a * exp(-x * x);
                 }
@@ -285,6 +303,7 @@ hipError_t launch_combine(int fp64, const FwdArgs& a, hipStream_t s) {
 
 hipError_t launch_forward(int profile, int fp64, int waves, int P, const FwdArgs& a, hipStream_t s) {
     if (a.n_tiles <= 0) return hipSuccess;
+    if (profile == kSuperLines) return launch_superlines(fp64, a, s);
     if (!fp64) return launch_forward_f32(profile, waves, P, a, s);
     switch (profile) {
         case kDoppler: launch_p64<kDoppler>(P, a, s); break;
@@ -293,8 +312,45 @@ hipError_t launch_forward(int profile, int fp64, int waves, int P, const FwdArgs
         case kGHSampled: launch_p64<kGHSampled>(P, a, s); break;
         case kGHBinned: launch_p64<kGHBinned>(P, a, s); break;
         case kVVoigt: launch_p64<kVVoigt>(P, a, s); break;
+        case kDopplerBinned: launch_p64<kDopplerBinned>(P, a, s); break;
+        case kLorentzBinned: launch_p64<kLorentzBinned>(P, a, s); break;
         default: launch_p64<kVoigt>(P, a, s); break;
     }
+    return hipGetLastError();
+}
+
+namespace {
+
+// Sec. "Super-lines": per grid point k, the intensities (Eq. 1) of the lines whose nearest
+// grid index is k (the sorted lines of key k, in their sorted order) summed in double,
+// divided by dnu.
+__global__ __launch_bounds__(256) void superline_kernel(const FwdArgs A, int fp64) {
+    const Geometry G = A.G;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t total = (int64_t)A.n_tp * G.n_points;
+    if (i >= total) return;
+    const int t = (int)(i / G.n_points);
+    const int k = (int)(i - (int64_t)t * G.n_points);
+    const TPParam tp = A.tps[t];
+    const double Q = A.Q[tp.iq];
+    const int l0 = off_at(A.off, k, G), l1 = off_at(A.off, (int64_t)k + 1, G);
+    double acc = 0.0;
+    for (int l = l0; l < l1; ++l) {
+        // Eq. 1: I = [g_f A/(8 pi c nu^2)] exp(-c2 E_i/T) (1 - exp(-c2 nu/T)) / Q(T)
+        const double nu = A.L.nu[l];
+        acc += A.L.cA[l] * exp(-(kC2 * A.L.elow[l]) / tp.T) * (-expm1(-(kC2 * nu) / tp.T)) / Q;
+    }
+    const double v = acc / G.dnu;
+    if (fp64) static_cast<double*>(A.sigma)[i] = v;
+    else static_cast<float*>(A.sigma)[i] = (float)v;
+}
+
+}  // namespace
+
+hipError_t launch_superlines(int fp64, const FwdArgs& a, hipStream_t s) {
+    const int64_t total = (int64_t)a.n_tp * a.G.n_points;
+    if (total == 0) return hipSuccess;
+    hipLaunchKernelGGL(superline_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, a, fp64);
     return hipGetLastError();
 }
 

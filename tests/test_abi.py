@@ -43,7 +43,7 @@ def test_version_and_defaults_without_gpu():
 
 
 @pytest.mark.parametrize("field,value", [("n_points", 1), ("cutoff", 0.0), ("mass_da", -1.0),
-                                         ("profile", 8), ("index_base", 2), ("slices_per_wave", 3),
+                                         ("profile", 11), ("index_base", 2), ("slices_per_wave", 3),
                                          ("n_split", 65), ("n_split", -1), ("tp_block", 257),
                                          ("vv_beta", 2), ("vv_radius", -1.0), ("vv_radius", float("nan"))])
 def test_plan_create_rejects_bad_options_on_host(field, value):
