@@ -14,3 +14,4 @@ from .constants import *  # noqa: F401,F403
 from .xsec import *  # noqa: F401,F403
 from .vvoigt import *  # noqa: F401,F403
 from .binned import *  # noqa: F401,F403
+from .threshold import *  # noqa: F401,F403

@@ -214,3 +214,30 @@ def test_super_line_bins_by_truncation_are_caught(monkeypatch):
                         lambda nu, nu_a, dnu: np.floor((np.asarray(nu) - nu_a) / dnu).astype(np.int64))
     with pytest.raises(AssertionError):
         bpins.test_super_line_histogram_equals_brute_force_bins()
+
+
+# ------------------------------------------------------------ intensity thresholds
+import oracle.threshold as TH  # noqa: E402
+from tests import test_oracle_threshold as tpins  # noqa: E402
+
+
+def test_threshold_without_the_half_in_tanh_is_caught(monkeypatch):
+    def bad(nu, T, mode, i_crit=1e-29, nu_crit=2000.0):
+        nu = np.asarray(nu, np.float64)
+        if mode == "constant":
+            return np.full(nu.shape, float(i_crit))
+        return np.where(nu <= nu_crit, i_crit * (nu / nu_crit) * np.tanh(O.C2 * nu / T), i_crit)
+    monkeypatch.setattr(TH, "intensity_cutoff", bad)
+    monkeypatch.setattr(O, "intensity_cutoff", bad)
+    with pytest.raises(AssertionError):
+        tpins.test_hitran_cutoff_limits()
+
+
+def test_strict_threshold_is_caught(monkeypatch):
+    def bad(ls, T, mode, i_crit=1e-29, nu_crit=2000.0):
+        keep = ls.I > TH.intensity_cutoff(ls.nu, T, mode, i_crit, nu_crit)
+        return O.LineSet(ls.nu[keep], ls.I[keep], ls.alpha_d[keep], ls.gamma[keep])
+    monkeypatch.setattr(TH, "apply_threshold", bad)
+    monkeypatch.setattr(O, "apply_threshold", bad)
+    with pytest.raises(AssertionError):
+        tpins.test_threshold_keeps_exactly_the_lines_at_or_above_it()
