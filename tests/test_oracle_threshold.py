@@ -15,7 +15,7 @@ def test_hitran_cutoff_limits():
     small = np.array([0.01, 0.02, 0.04])
     c = O.intensity_cutoff(small, T, "hitran")
     assert np.allclose(c[1:] / c[:-1], 4.0, rtol=1e-8)
-    k = 1.438776877 / (2 * T)   # c2 / (2T), c2 = hc/k_B in cm K
+    k = O.C2 / (2 * T)   # c2 / (2T), c2 = hc/k_B in cm K
     x = 0.01 * k
     assert abs(c[0] - 1e-29 * (0.01 / 2000.0) * x * (1 - x * x / 3)) < 1e-12 * c[0]   # tanh x = x - x^3/3 + ...
     big = O.intensity_cutoff(np.array([1000.0, 1500.0]), 100.0, "hitran")
@@ -38,7 +38,7 @@ def test_threshold_keeps_exactly_the_lines_at_or_above_it():
             if mode == "constant":
                 cut = ic
             elif nu[i] <= 2000.0:
-                cut = ic * (nu[i] / 2000.0) * math.tanh(1.438776877 * nu[i] / (2 * 500.0))
+                cut = ic * (nu[i] / 2000.0) * math.tanh(O.C2 * nu[i] / (2 * 500.0))
             else:
                 cut = ic
             if I[i] >= cut:
