@@ -191,6 +191,23 @@ xs_status xs_set_lines(xs_plan* plan, int64_t n_lines, const int32_t* upper, con
 /* Number of lines kept by the last xs_set_lines (window overlaps the grid). */
 xs_status xs_lines_kept(const xs_plan* plan, int64_t* n_kept);
 
+/* Intensity thresholds (Sec. "Intensity thresholds"). */
+typedef enum {
+    XS_THRESHOLD_NONE = 0,     /* every line                                                  */
+    XS_THRESHOLD_CONSTANT = 1, /* keep lines with I >= i_crit (cm/molecule)                    */
+    XS_THRESHOLD_HITRAN = 2    /* HITRAN's dynamic cut-off: keep lines with I >= i_crit (nu/
+                                  nu_crit) tanh(c2 nu/(2T)) for nu <= nu_crit, I >= i_crit above;
+                                  the paper's defaults are nu_crit = 2000 cm^-1, i_crit = 1e-29 */
+} xs_threshold;
+
+/* Set the plan's intensity threshold for the following cross sections (and graphs
+ * created afterwards; existing graphs refuse to launch).  I is Eq. 1 at each call's T
+ * (in double); dropped lines contribute nothing, and the tile kernels sweep only the kept
+ * lines of each (T, P) (a per-(T, P) compaction in sorted order).  mode: xs_threshold;
+ * i_crit >= 0; nu_crit > 0 for XS_THRESHOLD_HITRAN.  Host-only, no device work.
+ * xs_cross_section_adjoint returns XS_ERR_UNSUPPORTED while a threshold is set. */
+xs_status xs_set_intensity_threshold(xs_plan* plan, int32_t mode, double i_crit, double nu_crit);
+
 /* Partition function Q(T) of Eq. 2 and its derivative dQ/dT, summed on the device
  * in double precision, for n_T temperatures.  T: host double[n_T] (> 0);
  * Q, dQdT: device double[n_T] or NULL. */

@@ -72,6 +72,7 @@ def load_library() -> ctypes.CDLL:
         "xs_set_states": (i32, [P, i64, P, P, P, P]),
         "xs_set_broadening_table": (i32, [P, i32, P, P]),
         "xs_set_lines": (i32, [P, i64, P, P, P, P, P, P]),
+        "xs_set_intensity_threshold": (i32, [P, i32, dbl, dbl]),
         "xs_lines_kept": (i32, [P, ctypes.POINTER(i64)]),
         "xs_partition_function": (i32, [P, i32, P, P, P, P]),
         "xs_cross_section": (i32, [P, i32, P, P, P, P]),
@@ -118,6 +119,11 @@ def _ptr(t) -> Optional[int]:
     return None if t is None else t.data_ptr()
 
 
+def _owner(obj) -> bool:
+    """True in the process that created obj's library handle."""
+    return getattr(obj, "_pid", None) == os.getpid()
+
+
 def _host_doubles(vals: Sequence[float]):
     arr = (ctypes.c_double * len(vals))(*[float(v) for v in vals])
     return arr
@@ -156,6 +162,7 @@ class Plan:
         _check(lib.xs_plan_create(ctypes.byref(o), ctypes.byref(h)))
         self._lib = lib
         self._h = h
+        self._pid = os.getpid()
         self.opts = o
         self.n_points = int(n_points)
         self.precision = precision
@@ -177,7 +184,9 @@ class Plan:
         return t
 
     def close(self):
-        if getattr(self, "_h", None) is not None and self._h.value:
+        # a process forked after the GPU was initialised (e.g. a multiprocessing worker)
+        # inherits this object but must not call into the HIP runtime
+        if getattr(self, "_h", None) is not None and self._h.value and _owner(self):
             self._lib.xs_plan_destroy(self._h)
             self._h = ctypes.c_void_p()
 
@@ -259,6 +268,11 @@ class Plan:
                                                   _ptr(dP), _ptr(dlnA), _ptr(dg), _ptr(dn), self._stream()))
         return dT, dP, dlnA, dg, dn
 
+    def set_intensity_threshold(self, mode: str = "none", i_crit: float = 1e-29, nu_crit: float = 2000.0):
+        """Intensity threshold: "none", "constant" (I >= i_crit) or "hitran" (dynamic cut-off)."""
+        modes = {"none": 0, "constant": 1, "hitran": 2}
+        _check(self._lib.xs_set_intensity_threshold(self._h, modes[mode], float(i_crit), float(nu_crit)))
+
     def set_tile_config(self, waves: int = 0, slices: int = 0, n_split: int = 0, tp_block: int = 0):
         _check(self._lib.xs_set_tile_config(self._h, int(waves), int(slices), int(n_split), int(tp_block)))
 
@@ -318,6 +332,7 @@ class Graph:
         self._plan = plan
         self._lib = plan._lib
         self._h = h
+        self._pid = os.getpid()
         self.n_tp = len(T)
         self.sigma = out
 
@@ -335,7 +350,7 @@ class Graph:
         return int(self._lib.xs_graph_workspace_bytes(self._h))
 
     def close(self):
-        if getattr(self, "_h", None) is not None and self._h.value:
+        if getattr(self, "_h", None) is not None and self._h.value and _owner(self):
             self._lib.xs_graph_destroy(self._h)
             self._h = ctypes.c_void_p()
 
@@ -376,6 +391,7 @@ class Stream:
             _check(self._lib.xs_stream_resume(plan._h, os.fsencode(resume_from), _ptr(out), plan._stream(),
                                               ctypes.byref(h)))
         self._h = h
+        self._pid = os.getpid()
         self.sigma = out
 
     @classmethod
@@ -419,7 +435,7 @@ class Stream:
 
     def __del__(self):
         try:
-            if getattr(self, "_h", None) is not None and self._h.value:
+            if getattr(self, "_h", None) is not None and self._h.value and _owner(self):
                 self._lib.xs_stream_end(self._h, None)
         except Exception:
             pass

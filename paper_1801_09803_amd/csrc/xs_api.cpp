@@ -121,6 +121,8 @@ struct Workset {
     DevBuf val;               // core values of one block of (T, P)
     DevBuf hot, cold, xscale; // FP32 line records [tp_block][n_kept] (32 or 48 + 64 + 8 B per line)
     DevBuf vv;                // Vectorized Voigt {beta, intensity factor} [tp_block][n_kept]
+    DevBuf th_bsum, th_tmp;   // intensity threshold: block counts, scan scratch per row
+    DevBuf th_pos, th_map, th_offs;   // per row: positions [n+1], kept lines [n], offsets [nkeys+1]
     DevBuf part;              // per-part sums [tp_block][n_split][n_points] when n_split > 1
     DevBuf out;               // autotuner output scratch
     size_t bytes = 0;
@@ -131,7 +133,7 @@ struct Workset {
     xs_status ensure(DevBuf& b, size_t n, const char* what) { return dev_ensure(b, n, what, &bytes); }
     void release() {
         DevBuf* all[] = {&T, &Q, &dQ, &qpart, &tps, &rc, &cnt, &coff, &bsum, &tmp, &val, &hot, &cold, &xscale,
-                         &vv, &part, &out};
+                         &vv, &th_bsum, &th_tmp, &th_pos, &th_map, &th_offs, &part, &out};
         for (DevBuf* b : all) dev_release(*b, &bytes);
         stage.release();
         rows = 0;
@@ -161,6 +163,8 @@ struct xs_plan {
     int waves = 4;
     int n_split = 0;        // 0: chosen per call
     int tp_block = 0;       // 0: chosen per call
+    int th_mode = 0;        // intensity threshold: 0 none, 1 constant, 2 HITRAN
+    double th_icrit = 0.0, th_nucrit = 0.0;
     int last_split = 0, last_block = 0;
     uint64_t generation = 1;   // bumped whenever captured graphs become invalid
     size_t total_bytes = 0;
@@ -416,6 +420,8 @@ bool fp32_path(const xs_plan* p) { return p->o.precision == XS_FP32; }
 // FP32 line records (every profile of the FP32 tile kernel; super-lines read the lines)
 bool records_path(const xs_plan* p) { return fp32_path(p) && !superlines(p); }
 
+bool threshold_on(const xs_plan* p) { return p->th_mode != 0; }
+
 // The Vectorized Voigt wing uses the Lorentzian (FP32) or the 2-node rule (FP64) for the
 // reference profile: both need x_ref = sqrt(ln2) R / alpha_ref >= 2e4 at every temperature.
 xs_status check_vv(const xs_plan* p, int n, const double* T) {
@@ -432,7 +438,8 @@ xs_status check_vv(const xs_plan* p, int n, const double* T) {
 // Bytes of per-(line, T, P) workspace: FP32 line records (104 or 120 B), Voigt core rows
 // (16 B) and Vectorized Voigt factors (16 B).
 int64_t row_bytes_per_line(const xs_plan* p) {
-    return (records_path(p) ? 72 + 4 * hot_words(p) : 0) + (core_path(p) ? 16 : 0) + (vv_needed(p) ? 16 : 0);
+    return (records_path(p) ? 72 + 4 * hot_words(p) : 0) + (core_path(p) ? 16 : 0) + (vv_needed(p) ? 16 : 0) +
+           (threshold_on(p) ? 8 : 0);
 }
 
 int pick_block(const xs_plan* p, int n_tp) {
@@ -475,6 +482,16 @@ xs_status ensure_rows(xs_plan* p, Workset& ws, int B, int S) {
     const int64_t n = std::max<int64_t>(p->n_kept, 1);
     if (vv_needed(p)) {
         XS_TRY(ws.ensure(ws.vv, (size_t)B * n * 2 * sizeof(double), "Vectorized Voigt factors"));
+        ws.rows = B;
+        ws.row_stride = n;
+    }
+    if (threshold_on(p)) {
+        const int64_t nb = xs::core_blocks(n);
+        XS_TRY(ws.ensure(ws.th_bsum, (size_t)B * nb * sizeof(unsigned long long), "threshold block counts"));
+        XS_TRY(ws.ensure(ws.th_tmp, (size_t)B * kScanTmp * sizeof(unsigned long long), "threshold scan"));
+        XS_TRY(ws.ensure(ws.th_pos, (size_t)B * (n + 1) * sizeof(unsigned), "threshold positions"));
+        XS_TRY(ws.ensure(ws.th_map, (size_t)B * n * sizeof(int), "threshold map"));
+        XS_TRY(ws.ensure(ws.th_offs, (size_t)B * ((size_t)p->geo.nkeys + 1) * sizeof(int), "threshold offsets"));
         ws.rows = B;
         ws.row_stride = n;
     }
@@ -559,6 +576,12 @@ xs::FwdArgs fwd_args(xs_plan* p, Workset& ws, const std::vector<xs::TPParam>& tp
         a.vv = as<double2>(ws.vv) + (int64_t)row0 * ws.row_stride;
         a.vv_stride = ws.row_stride;
     }
+    if (threshold_on(p)) {
+        a.map = as<int>(ws.th_map) + (int64_t)row0 * ws.row_stride;
+        a.map_stride = ws.row_stride;
+        a.offs = as<int>(ws.th_offs) + (int64_t)row0 * ((int64_t)p->geo.nkeys + 1);
+        a.offs_stride = (int64_t)p->geo.nkeys + 1;
+    }
     if (records_path(p)) {
         a.hot = as<float>(ws.hot) + (int64_t)row0 * ws.row_stride * hot_words(p);
         a.cold = as<int>(ws.cold) + (int64_t)row0 * ws.row_stride * 16;
@@ -585,6 +608,10 @@ xs::RecArgs rec_args(xs_plan* p, Workset& ws, int it, int row) {
         r.core_off = as<long long>(ws.coff) + row * n;
     }
     r.vv = vv_needed(p) ? as<double2>(ws.vv) + row * n : nullptr;
+    if (threshold_on(p)) {
+        r.map = as<int>(ws.th_map) + row * n;
+        r.count = as<unsigned long long>(ws.th_tmp) + (int64_t)row * kScanTmp + 4096;
+    }
     r.hot = as<float>(ws.hot) + row * n * hot_words(p);
     r.cold = as<int>(ws.cold) + row * n * 16;
     r.xscale = as<double>(ws.xscale) + row * n;
@@ -636,6 +663,25 @@ xs_status read_totals(Workset& ws, int nb, hipStream_t s, std::vector<unsigned l
 xs_status enqueue_prepass(xs_plan* p, Workset& ws, int it, int row, bool count, const std::vector<long long>& vbase,
                           const std::vector<long long>& vend, hipStream_t s) {
     if (p->n_kept <= 0) return XS_OK;
+    if (threshold_on(p)) {
+        xs::CullArgs c{};
+        const int64_t n = ws.row_stride;
+        c.L = sorted_lines(p);
+        c.G = p->geo;
+        c.tp = as<xs::TPParam>(ws.tps) + it;
+        c.Q = as<double>(ws.Q);
+        c.n_lines = (int)p->n_kept;
+        c.mode = p->th_mode;
+        c.i_crit = p->th_icrit;
+        c.nu_crit = p->th_nucrit;
+        c.bsum = as<unsigned long long>(ws.th_bsum) + (int64_t)row * xs::core_blocks(n);
+        c.scan_tmp = as<unsigned long long>(ws.th_tmp) + (int64_t)row * kScanTmp;
+        c.pos = as<unsigned>(ws.th_pos) + (int64_t)row * (n + 1);
+        c.map = as<int>(ws.th_map) + (int64_t)row * n;
+        c.off = as<int>(p->off);
+        c.offs = as<int>(ws.th_offs) + (int64_t)row * ((int64_t)p->geo.nkeys + 1);
+        XS_HIP(xs::launch_cull(c, s));
+    }
     if (vv_needed(p)) {
         xs::VVArgs v{};
         v.L = sorted_lines(p);
@@ -665,7 +711,7 @@ xs_status enqueue_block(xs_plan* p, Workset& ws, const std::vector<xs::TPParam>&
                         bool count, const std::vector<long long>& vbase, const std::vector<long long>& vend,
                         void* sigma, hipStream_t s, bool timed) {
     const bool fp64 = p->o.precision == XS_FP64;
-    if ((records_path(p) || vv_needed(p)) && p->n_kept > 0) {
+    if ((records_path(p) || vv_needed(p) || threshold_on(p)) && p->n_kept > 0) {
         for (int t = 0; t < nb; ++t) {
             Timer tc(p, s, 1, 0, timed);
             XS_TRY(enqueue_prepass(p, ws, f + t, t, count, vbase, vend, s));
@@ -922,6 +968,20 @@ xs_status xs_set_lines(xs_plan* p, int64_t n, const int32_t* upper, const int32_
         if ((st = build_tile_order(p)) != XS_OK) return st;
     }
     p->have_lines = true;
+    return XS_OK;
+}
+
+xs_status xs_set_intensity_threshold(xs_plan* p, int32_t mode, double i_crit, double nu_crit) {
+    if (!p) return fail(XS_ERR_ARG, "plan is NULL");
+    if (mode < XS_THRESHOLD_NONE || mode > XS_THRESHOLD_HITRAN) return fail(XS_ERR_ARG, "unknown threshold mode");
+    if (mode != XS_THRESHOLD_NONE && !(i_crit >= 0.0 && std::isfinite(i_crit)))
+        return fail(XS_ERR_ARG, "i_crit must be finite and >= 0");
+    if (mode == XS_THRESHOLD_HITRAN && !(nu_crit > 0.0 && std::isfinite(nu_crit)))
+        return fail(XS_ERR_ARG, "nu_crit must be finite and > 0");
+    p->th_mode = mode;
+    p->th_icrit = i_crit;
+    p->th_nucrit = nu_crit;
+    p->generation++;   // captured graphs were recorded without (or with another) threshold
     return XS_OK;
 }
 
@@ -1452,6 +1512,7 @@ xs_status xs_cross_section_adjoint(xs_plan* p, double T, double P, const void* g
     if (!p || !gbar) return fail(XS_ERR_ARG, "NULL argument");
     if (!p->have_lines) return fail(XS_ERR_STATE, "xs_set_lines must succeed first");
     if (p->o.profile != XS_VOIGT) return fail(XS_ERR_UNSUPPORTED, "the adjoint is implemented for XS_VOIGT");
+    if (threshold_on(p)) return fail(XS_ERR_UNSUPPORTED, "the adjoint does not apply an intensity threshold");
     if ((dgref || dn) && p->o.broadening != XS_BROAD_PER_LINE)
         return fail(XS_ERR_UNSUPPORTED, "gamma_ref / n gradients need per-line broadening");
     if (!(P >= 0.0) || !std::isfinite(P)) return fail(XS_ERR_ARG, "pressure must be finite and >= 0");

@@ -195,6 +195,13 @@ static hipError_t scan_block_sums(const CoreArgs& a, int64_t nb, hipStream_t s) 
     return hipGetLastError();
 }
 
+hipError_t launch_scan64(unsigned long long* bsum, int64_t nb, unsigned long long* scan_tmp, hipStream_t s) {
+    CoreArgs a{};
+    a.bsum = bsum;
+    a.scan_tmp = scan_tmp;
+    return scan_block_sums(a, nb, s);
+}
+
 hipError_t launch_core_count(const CoreArgs& a, hipStream_t s) {
     const int64_t nb = core_blocks(a.n_lines);
     if (nb == 0) return hipSuccess;

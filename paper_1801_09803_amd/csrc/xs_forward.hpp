@@ -44,7 +44,17 @@ struct FwdArgs {
     // lines per (T, P) of the launch, or NULL (beta = 1, factor 1)
     const double2* vv;
     int64_t vv_stride;
+    // intensity threshold: per (T, P) of the launch, the kept lines' sorted indices in
+    // order (map, rows of map_stride) and their offsets table (offs, rows of offs_stride);
+    // NULL: every sorted line, the plan's offsets table
+    const int* map;
+    int64_t map_stride;
+    const int* offs;
+    int64_t offs_stride;
 };
+
+// Sorted line index of the launch's line g (through the threshold map when there is one).
+__device__ __forceinline__ int line_of(const int* map, int g) { return map ? map[g] : g; }
 
 // Per-(line, T, P) records of the FP32 path (record_kernel).
 struct RecArgs {
@@ -58,7 +68,10 @@ struct RecArgs {
     const int* core_rc;             // Voigt: core radius per line (-1: none)
     const long long* core_off;      // Voigt: index in core_val of the line's first core value
     const double2* vv;              // Vectorized Voigt: {beta, intensity factor} per line, or NULL
-    float* hot;                     // [n_lines][8] ([n_lines][12] for the Vectorized Voigt)
+    const int* map;                 // intensity threshold: kept lines' sorted indices, or NULL
+    const unsigned long long* count;   // number of kept lines (device), with map
+    float* hot;                     // [n_lines][8] ([n_lines][12] for the Vectorized Voigt), in
+                                    // the order of map when there is one
     int* cold;                      // [n_lines][16]
     double* xscale;                 // [n_lines]
 };
@@ -79,6 +92,28 @@ struct VVArgs {
 };
 
 hipError_t launch_vv_prep(const VVArgs& a, hipStream_t s);
+
+// Intensity threshold (Sec. "Intensity thresholds") of one (T, P): lines with I >= I_cut(nu)
+// are kept, compacted in sorted order (map), with their own offsets table (offs).
+struct CullArgs {
+    SortedLines L;
+    Geometry G;
+    const TPParam* tp;               // device: this (T, P)
+    const double* Q;
+    int n_lines;
+    int mode;                        // 1 constant, 2 HITRAN's dynamic cut-off
+    double i_crit, nu_crit;
+    unsigned long long* bsum;        // [ceil(n_lines/256)] block counts, then exclusive prefix
+    unsigned long long* scan_tmp;    // >= 4096 + 16 entries; scan_tmp[4096] = kept lines
+    unsigned* pos;                   // [n_lines + 1] kept lines before each sorted line
+    int* map;                        // [n_lines] compacted -> sorted index
+    const int* off;                  // the plan's offsets table [nkeys + 1]
+    int* offs;                       // this (T, P)'s offsets table [nkeys + 1]
+};
+
+hipError_t launch_cull(const CullArgs& a, hipStream_t s);
+// exclusive scan of nb block totals in place; scan_tmp[4096] receives the total
+hipError_t launch_scan64(unsigned long long* bsum, int64_t nb, unsigned long long* scan_tmp, hipStream_t s);
 
 hipError_t launch_records(int profile, const RecArgs& a, hipStream_t s);
 

@@ -85,8 +85,10 @@ constexpr bool anchors_in_lds(int prof) { return prof != kVVoigt; }
 template <int PROF>
 __global__ __launch_bounds__(256) void record_kernel(const RecArgs A) {
     using L = HotOf<PROF>;
-    const int g = blockIdx.x * 256 + threadIdx.x;
-    if (g >= A.n_lines) return;
+    // ci: position of the record (the compacted index under an intensity threshold)
+    const int ci = blockIdx.x * 256 + threadIdx.x;
+    if (ci >= A.n_lines || (A.map && (unsigned long long)ci >= *A.count)) return;
+    const int g = line_of(A.map, ci);
     const TPParam tp = *A.tp;
     const Geometry G = A.G;
     const double Q = A.Q[tp.iq];
@@ -221,13 +223,13 @@ __global__ __launch_bounds__(256) void record_kernel(const RecArgs A) {
         h[L::AMP] = (float)(S * kSQRT_LN2_PI / alpha);
         c[C_RAD] = radius_steps(10.5, s * G.dnu, s * d);   // exp(-x^2) underflows beyond
     }
-    float4* ho = reinterpret_cast<float4*>(A.hot + (int64_t)g * NH);
+    float4* ho = reinterpret_cast<float4*>(A.hot + (int64_t)ci * NH);
 #pragma unroll
     for (int q = 0; q < NH / 4; ++q) ho[q] = make_float4(h[4 * q], h[4 * q + 1], h[4 * q + 2], h[4 * q + 3]);
-    int4* co = reinterpret_cast<int4*>(A.cold + (int64_t)g * kCold);
+    int4* co = reinterpret_cast<int4*>(A.cold + (int64_t)ci * kCold);
 #pragma unroll
     for (int q = 0; q < 4; ++q) co[q] = make_int4(c[4 * q], c[4 * q + 1], c[4 * q + 2], c[4 * q + 3]);
-    A.xscale[g] = scale;
+    A.xscale[ci] = scale;
 }
 
 // ------------------------------------------------------------------ tile kernel
@@ -459,8 +461,8 @@ struct Prefetch {
 };
 
 template <int NT, int NQ>
-__device__ __forceinline__ Prefetch<NQ> load_batch(const FwdArgs& A, const float4* ghot, const double* gscale,
-                                                   int bs, int b5, int tid) {
+__device__ __forceinline__ Prefetch<NQ> load_batch(const FwdArgs& A, const int* map, const float4* ghot,
+                                                   const double* gscale, int bs, int b5, int tid) {
     Prefetch<NQ> f;
     const int64_t cend = NQ * (int64_t)b5;
 #pragma unroll
@@ -474,8 +476,9 @@ __device__ __forceinline__ Prefetch<NQ> load_batch(const FwdArgs& A, const float
     f.scale = 0.0;
     const int g = bs + tid;
     if (g < b5) {
-        f.kc = A.L.kc[g];
-        f.nu = A.L.nu[g];
+        const int gs = line_of(map, g);
+        f.kc = A.L.kc[gs];
+        f.nu = A.L.nu[gs];
         f.scale = gscale[g];
     }
     return f;
@@ -513,12 +516,15 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
     const float4* ghot = reinterpret_cast<const float4*>(A.hot + row * RH);
     const int4* gcold = reinterpret_cast<const int4*>(A.cold + row * kCold);
     const double* gscale = A.xscale + row;
+    // intensity threshold: this (T, P)'s kept lines and offsets table
+    const int* map = A.map ? A.map + (int64_t)wi.tp * A.map_stride : nullptr;
+    const int* off = A.offs ? A.offs + (int64_t)wi.tp * A.offs_stride : A.off;
     const int t0 = wi.tile * W, t1 = t0 + W - 1;
     const int w0 = t0 + wave * WW, w1 = w0 + WW - 1;
 
     // lines overlapping the tile; this workgroup takes every n_split-th batch of them
-    const int b0 = off_at(A.off, (int64_t)t0 - G.hmax, G);
-    const int b5 = off_at(A.off, (int64_t)t1 + G.hmax + 1, G);
+    const int b0 = off_at(off, (int64_t)t0 - G.hmax, G);
+    const int b5 = off_at(off, (int64_t)t1 + G.hmax + 1, G);
     const int bstride = NT * A.n_split;
     const int bfirst = b0 + NT * wi.part;
     const int rm_tile = tp.rm;
@@ -534,12 +540,12 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
     int s0 = 0, s1 = 0, s2 = 0, s3 = 0, s4 = 0, s5 = 0;
     int ha = 0, hb = 0, hc = 0, hd = 0;
     if (SEG) {
-        s0 = off_at(A.off, (int64_t)w0 - G.hmax, G);
-        s1 = off_at(A.off, (int64_t)w1 - G.hmin, G);
-        s2 = off_at(A.off, (int64_t)w0 - rm, G);
-        s3 = off_at(A.off, (int64_t)w1 + rm + 1, G);
-        s4 = off_at(A.off, (int64_t)w0 + G.hmin + 1, G);
-        s5 = off_at(A.off, (int64_t)w1 + G.hmax + 1, G);
+        s0 = off_at(off, (int64_t)w0 - G.hmax, G);
+        s1 = off_at(off, (int64_t)w1 - G.hmin, G);
+        s2 = off_at(off, (int64_t)w0 - rm, G);
+        s3 = off_at(off, (int64_t)w1 + rm + 1, G);
+        s4 = off_at(off, (int64_t)w0 + G.hmin + 1, G);
+        s5 = off_at(off, (int64_t)w1 + G.hmax + 1, G);
         if (PROF == kVVoigt) {
             // wing-only runs split where R can cross the wave: left lines with kc < w0 - rvmax
             // see only points beyond R, those with kc >= w1 - rvmin only points inside R
@@ -547,10 +553,10 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
             const int64_t l0 = (int64_t)w1 - G.hmin, l1 = (int64_t)w0 - rm;
             const int64_t r0 = (int64_t)w1 + rm + 1, r1 = (int64_t)w0 + G.hmin + 1;
             auto cl = [](int64_t v, int64_t lo, int64_t hi) { return v < lo ? lo : (v > hi ? hi : v); };
-            ha = off_at(A.off, cl((int64_t)w0 - G.rvmax, l0, l1), G);
-            hb = off_at(A.off, cl((int64_t)w1 - G.rvmin, l0, l1), G);
-            hc = off_at(A.off, cl((int64_t)w0 + G.rvmin + 1, r0, r1), G);
-            hd = off_at(A.off, cl((int64_t)w1 + G.rvmax + 1, r0, r1), G);
+            ha = off_at(off, cl((int64_t)w0 - G.rvmax, l0, l1), G);
+            hb = off_at(off, cl((int64_t)w1 - G.rvmin, l0, l1), G);
+            hc = off_at(off, cl((int64_t)w0 + G.rvmin + 1, r0, r1), G);
+            hd = off_at(off, cl((int64_t)w1 + G.rvmax + 1, r0, r1), G);
         }
     }
 
@@ -565,7 +571,7 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
     const int cword = (wave * P) / 8;
     const int cshift = 4 * ((wave * P) % 8);
 
-    Prefetch<NQ> nxt = load_batch<NT, NQ>(A, ghot, gscale, bfirst, b5, tid);
+    Prefetch<NQ> nxt = load_batch<NT, NQ>(A, map, ghot, gscale, bfirst, b5, tid);
     for (int bs = bfirst; bs < b5; bs += bstride) {
         const int g = bs + tid;
         // ---- batch set-up: hot records (coalesced loads; chunk c is quarter c % NQ of
@@ -613,7 +619,8 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
                 if constexpr (!SEG) {
                     // 4-bit code per slice: zone (0 skip, 1 far, 2 mid, 3 core) | 4 (mask)
                     // | 8 (Vectorized Voigt: points beyond R)
-                    const int klo = A.L.klo[g], khi = A.L.khi[g];
+                    const int gs = line_of(map, g);
+                    const int klo = A.L.klo[gs], khi = A.L.khi[gs];
                     const int rad = q0.z, kcl = q0.w, kch = q1.x, flag = q1.y;
                     unsigned cw[NCW];
 #pragma unroll
@@ -656,7 +663,7 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
             }
         }
         __syncthreads();
-        if (bs + bstride < b5) nxt = load_batch<NT, NQ>(A, ghot, gscale, bs + bstride, b5, tid);   // overlaps the sweep
+        if (bs + bstride < b5) nxt = load_batch<NT, NQ>(A, map, ghot, gscale, bs + bstride, b5, tid);   // overlaps the sweep
         const float* rec = reinterpret_cast<const float*>(S.rec);
         const int be = bs + NT < b5 ? bs + NT : b5;
         for (int cs = bs; cs < be; cs += 64) {

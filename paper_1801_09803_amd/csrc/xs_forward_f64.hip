@@ -39,9 +39,12 @@ __global__ __launch_bounds__(256) void fwd_f64_kernel(const FwdArgs A) {
     const WorkItem wi = work_item(A);
     const TPParam tp = A.tps[wi.tp];
     const int t0 = wi.tile * W, t1 = t0 + W - 1;
+    // intensity threshold: this (T, P)'s kept lines and offsets table
+    const int* map = A.map ? A.map + (int64_t)wi.tp * A.map_stride : nullptr;
+    const int* off = A.offs ? A.offs + (int64_t)wi.tp * A.offs_stride : A.off;
     // lines overlapping the tile; this workgroup takes every n_split-th batch of them
-    const int b0 = off_at(A.off, (int64_t)t0 - G.hmax, G);
-    const int b5 = off_at(A.off, (int64_t)t1 + G.hmax + 1, G);
+    const int b0 = off_at(off, (int64_t)t0 - G.hmax, G);
+    const int b5 = off_at(off, (int64_t)t1 + G.hmax + 1, G);
     const double Q = A.Q[tp.iq];
 
     int kk[P];
@@ -58,7 +61,8 @@ __global__ __launch_bounds__(256) void fwd_f64_kernel(const FwdArgs A) {
         const int g = bs + tid;
         if (g < b5) {
             double* r = rec + tid * (kRec / 2);
-            const LineSetup ls = line_setup(A.L, tp, g, Q);
+            const int gs = line_of(map, g);
+            const LineSetup ls = line_setup(A.L, tp, gs, Q);
             double s, y = 0.0;
             r[D_NU] = ls.nu;
             if (PROF == kVoigt || PROF == kVVoigt) {
@@ -66,7 +70,7 @@ __global__ __launch_bounds__(256) void fwd_f64_kernel(const FwdArgs A) {
                 y = ls.gam * s;
                 r[D_A] = ls.S * kSQRT_LN2_PI / ls.aD;
                 if (PROF == kVVoigt) {
-                    const double2 vv = A.vv ? A.vv[(int64_t)wi.tp * A.vv_stride + g] : make_double2(1.0, 1.0);
+                    const double2 vv = A.vv ? A.vv[(int64_t)wi.tp * A.vv_stride + gs] : make_double2(1.0, 1.0);
                     const double sr = kSQRT_LN2 / tp.beta;   // reference: alpha_D of a line at 1 cm^-1
                     r[D_A] *= vv.y;
                     r[D_W] = vv.x * vv.y * ls.S * kSQRT_LN2_PI / tp.beta;
@@ -333,12 +337,15 @@ __global__ __launch_bounds__(256) void superline_kernel(const FwdArgs A, int fp6
     const int k = (int)(i - (int64_t)t * G.n_points);
     const TPParam tp = A.tps[t];
     const double Q = A.Q[tp.iq];
-    const int l0 = off_at(A.off, k, G), l1 = off_at(A.off, (int64_t)k + 1, G);
+    const int* map = A.map ? A.map + (int64_t)t * A.map_stride : nullptr;
+    const int* off = A.offs ? A.offs + (int64_t)t * A.offs_stride : A.off;
+    const int l0 = off_at(off, k, G), l1 = off_at(off, (int64_t)k + 1, G);
     double acc = 0.0;
     for (int l = l0; l < l1; ++l) {
+        const int gs = line_of(map, l);
         // Eq. 1: I = [g_f A/(8 pi c nu^2)] exp(-c2 E_i/T) (1 - exp(-c2 nu/T)) / Q(T)
-        const double nu = A.L.nu[l];
-        acc += A.L.cA[l] * exp(-(kC2 * A.L.elow[l]) / tp.T) * (-expm1(-(kC2 * nu) / tp.T)) / Q;
+        const double nu = A.L.nu[gs];
+        acc += A.L.cA[gs] * exp(-(kC2 * A.L.elow[gs]) / tp.T) * (-expm1(-(kC2 * nu) / tp.T)) / Q;
     }
     const double v = acc / G.dnu;
     if (fp64) static_cast<double*>(A.sigma)[i] = v;

@@ -103,3 +103,19 @@ def test_stream_calls_reject_null_arguments_on_host():
     assert lib.xs_stream_checkpoint(None, b"x") == 1
     assert lib.xs_stream_resume(None, b"x", None, None, ctypes.byref(h)) == 1 and not h.value
     assert lib.xs_stream_stats(None, None) == 1
+
+
+def test_binding_handles_skip_the_library_in_forked_processes():
+    # objects inherited by a forked worker (the oracle's process pool) must not call into
+    # the HIP runtime from their destructors
+    import os
+    from paper_1801_09803_amd import binding as B
+
+    class Fake:
+        pass
+    f = Fake()
+    f._pid = os.getpid()
+    assert B._owner(f)
+    f._pid = os.getpid() + 1
+    assert not B._owner(f)
+    assert not B._owner(Fake())
