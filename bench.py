@@ -115,6 +115,7 @@ def main():
     ap.add_argument("--no-stream", action="store_true")
     ap.add_argument("--no-vv", action="store_true", help="skip the Vectorized Voigt leg")
     ap.add_argument("--no-binned", action="store_true", help="skip the binned-profile / super-line leg")
+    ap.add_argument("--no-threshold", action="store_true", help="skip the intensity-threshold leg")
     ap.add_argument("--stream-chunks", type=int, default=4)
     ap.add_argument("--stream-chunk-lines", type=int, default=1 << 24)
     ap.add_argument("--autotune-ms", type=float, default=20000.0,
@@ -323,6 +324,8 @@ def main():
         result["vectorized_voigt"] = vv_leg(cfg, d, temps, pressures, tile, out, n_kept, stream, log)
     if not args.no_binned:
         result["binned_profiles"] = binned_leg(cfg, d, temps, pressures, n_kept, stream, log)
+    if not args.no_threshold:
+        result["intensity_threshold"] = threshold_leg(cfg, d, temps, pressures, tile, n_kept, stream, log)
 
     del plan, out, d
     torch.cuda.empty_cache()
@@ -379,6 +382,57 @@ def vv_leg(cfg, d, temps, pressures, tile, voigt_out, n_kept, stream, log):
     legs["note"] = ("same list, grid and tile shape as the headline; radius 4 cm^-1; call = Q(T) + "
                     "pre-passes + tile kernel for all (T,P), line preparation excluded")
     return legs
+
+
+def threshold_leg(cfg, d, temps, pressures, tile, n_kept, stream, log):
+    """The headline workload with HITRAN's dynamic intensity cut-off at its defaults
+    (I_crit = 1e-29 cm/molecule, nu_crit = 2000 cm^-1): one call over both (T, P), the
+    share of lines kept at each (computed here from the same arrays, for the report)."""
+    import torch
+    from paper_1801_09803_amd import Plan
+    plan = Plan(cfg.nu_a, cfg.nu_b, cfg.n_points, cfg.mass_amu, cutoff=cfg.cutoff, profile="voigt")
+    plan.set_states(d["E"], d["g"], d["J"])
+    plan.set_lines(d["upper"], d["lower"], d["A"], d["gamma_ref"], d["n_exp"])
+    plan.set_tile_config(tile["waves"], tile["slices"], tile["last_split"], 1)
+    plan.set_intensity_threshold("hitran", 1e-29, 2000.0)
+    out = torch.empty((len(temps), cfg.n_points), dtype=torch.float32, device="cuda")
+    plan.cross_section(temps, pressures, out=out)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 3
+    plan.set_timing(True)
+    e0.record(stream)
+    for _ in range(reps):
+        plan.cross_section(temps, pressures, out=out)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    kt = plan.kernel_times()
+    plan.set_timing(False)
+    t = e0.elapsed_time(e1) / 1e3 / reps
+    # kept shares (Eq. 1 in double on the same arrays; the library does this per (T, P))
+    c2 = 1.4387768775039338
+    E = d["E"]
+    up, lo = d["upper"].long(), d["lower"].long()
+    nu = E[up] - E[lo]
+    A = d["A"].double()
+    gup = d["g"].double()[up]
+    cA = gup * A / (8.0 * math.pi * 2.99792458e10 * nu * nu)
+    shares = []
+    for T in temps:
+        Q = float((d["g"].double() * torch.exp(-c2 * E / T)).sum().item())
+        S = cA * torch.exp(-c2 * E[lo] / T) * (-torch.expm1(-c2 * nu / T)) / Q
+        cut = torch.where(nu <= 2000.0, 1e-29 * (nu / 2000.0) * torch.tanh(c2 * nu / (2.0 * T)),
+                          torch.full_like(nu, 1e-29))
+        shares.append(float((S >= cut).double().mean().item()))
+    del plan, out
+    log(f"threshold: {t * 1e3:.1f} ms per call, kept {shares}")
+    return {"mode": "hitran", "i_crit": 1e-29, "nu_crit": 2000.0, "call_ms": t * 1e3,
+            "line_profiles_per_s_of_the_list": n_kept * len(temps) / t,
+            "tile_kernel_ms_per_tp": kt["forward_ms"] / kt["forward_tp"],
+            "pre_passes_ms_per_tp": kt["core_ms"] / (reps * len(temps)),
+            "kept_share_per_tp": shares,
+            "note": "throughput counts every line of the list (kept or dropped), as the headline does; "
+                    "call = Q(T) + threshold compaction + pre-passes + tile kernel"}
 
 
 def binned_leg(cfg2, d2, temps, pressures, n_kept2, stream, log):
