@@ -15,3 +15,4 @@ from .xsec import *  # noqa: F401,F403
 from .vvoigt import *  # noqa: F401,F403
 from .binned import *  # noqa: F401,F403
 from .threshold import *  # noqa: F401,F403
+from .emission import *  # noqa: F401,F403

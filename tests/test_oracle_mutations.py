@@ -241,3 +241,31 @@ def test_strict_threshold_is_caught(monkeypatch):
     monkeypatch.setattr(O, "apply_threshold", bad)
     with pytest.raises(AssertionError):
         tpins.test_threshold_keeps_exactly_the_lines_at_or_above_it()
+
+
+# ------------------------------------------------------------ emission and state reductions
+import oracle.emission as EM  # noqa: E402
+from tests import test_oracle_emission as epins  # noqa: E402
+
+
+def test_emissivity_from_the_lower_state_is_caught(monkeypatch):
+    def bad(E, g, upper, lower, A, T, Q=None, index_base=0):
+        E = np.asarray(E, np.float64); gg = np.asarray(g, np.float64)
+        up = np.asarray(upper, np.int64) - index_base; lo = np.asarray(lower, np.int64) - index_base
+        nu = E[up] - E[lo]
+        Q = X.partition_function(E, g, T) if Q is None else Q
+        return EM.H_PLANCK_CGS * O.C_LIGHT_CGS * gg[lo] * np.asarray(A) * nu * np.exp(-O.C2 * E[lo] / T) / (4 * math.pi * Q)
+    monkeypatch.setattr(EM, "emissivities", bad)
+    monkeypatch.setattr(O, "emissivities", bad)
+    with pytest.raises(AssertionError):
+        epins.test_emissivity_over_intensity_is_the_planck_function()
+
+
+def test_heat_capacity_without_the_square_is_caught(monkeypatch):
+    def bad(E, g, T):
+        Q, Q1, Q2 = EM.partition_moments(E, g, T)
+        return EM.R_GAS * (Q2 / Q - Q1 / Q) + 2.5 * EM.R_GAS
+    monkeypatch.setattr(EM, "heat_capacity", bad)
+    monkeypatch.setattr(O, "heat_capacity", bad)
+    with pytest.raises(AssertionError):
+        epins.test_heat_capacity_closed_forms()
