@@ -116,6 +116,8 @@ def main():
     ap.add_argument("--no-vv", action="store_true", help="skip the Vectorized Voigt leg")
     ap.add_argument("--no-binned", action="store_true", help="skip the binned-profile / super-line leg")
     ap.add_argument("--no-threshold", action="store_true", help="skip the intensity-threshold leg")
+    ap.add_argument("--no-emission", action="store_true",
+                    help="skip the emission cross-section and state-reduction leg")
     ap.add_argument("--stream-chunks", type=int, default=4)
     ap.add_argument("--stream-chunk-lines", type=int, default=1 << 24)
     ap.add_argument("--autotune-ms", type=float, default=20000.0,
@@ -326,6 +328,9 @@ def main():
         result["binned_profiles"] = binned_leg(cfg, d, temps, pressures, n_kept, stream, log)
     if not args.no_threshold:
         result["intensity_threshold"] = threshold_leg(cfg, d, temps, pressures, tile, n_kept, stream, log)
+    if not args.no_emission:
+        result["emission_and_state_reductions"] = emission_leg(cfg, d, temps, pressures, tile, n_kept, stream,
+                                                                log)
 
     del plan, out, d
     torch.cuda.empty_cache()
@@ -433,6 +438,65 @@ def threshold_leg(cfg, d, temps, pressures, tile, n_kept, stream, log):
             "kept_share_per_tp": shares,
             "note": "throughput counts every line of the list (kept or dropped), as the headline does; "
                     "call = Q(T) + threshold compaction + pre-passes + tile kernel"}
+
+
+def emission_leg(cfg, d, temps, pressures, tile, n_kept, stream, log):
+    """Emission cross sections of the headline workload (same list, grid and tile shape),
+    and the state reductions over the same list: radiative lifetimes, the cooling function
+    at 27 temperatures (100-3000 K, log-spaced) and the partition-function moments with C_p
+    at the same temperatures."""
+    import time
+    import torch
+    from paper_1801_09803_amd import Plan
+    plan = Plan(cfg.nu_a, cfg.nu_b, cfg.n_points, cfg.mass_amu, cutoff=cfg.cutoff, profile="voigt")
+    plan.set_states(d["E"], d["g"], d["J"])
+    plan.set_lines(d["upper"], d["lower"], d["A"], d["gamma_ref"], d["n_exp"])
+    plan.set_tile_config(tile["waves"], tile["slices"], tile["last_split"], 1)
+    plan.set_intensity_kind("emission")
+    out = torch.empty((len(temps), cfg.n_points), dtype=torch.float32, device="cuda")
+    plan.cross_section(temps, pressures, out=out)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 2
+    plan.set_timing(True)
+    e0.record(stream)
+    for _ in range(reps):
+        plan.cross_section(temps, pressures, out=out)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    kt = plan.kernel_times()
+    plan.set_timing(False)
+    t_em = e0.elapsed_time(e1) / 1e3 / reps
+    n_lines, n_states = d["upper"].numel(), d["E"].numel()
+    Ts = [100.0 * 30.0 ** (j / 26.0) for j in range(27)]
+
+    def wall(fn, reps=3):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    t_tau = wall(lambda: plan.lifetimes(d["upper"], d["A"]))
+    t_w = wall(lambda: plan.cooling_function(d["upper"], d["lower"], d["A"], Ts))
+    t_m = wall(lambda: plan.partition_moments(Ts))
+    # algorithmic bytes: lifetimes read upper + A (8 B per transition) and read-modify-write
+    # 8 B per state twice (sum, tau); the cooling function reads upper, lower, A and two
+    # energies (24 B per transition, the energies mostly from cache)
+    tau_bytes = 8.0 * n_lines + 24.0 * n_states
+    del plan, out
+    log(f"emission: {t_em * 1e3:.1f} ms per call; lifetimes {t_tau * 1e3:.2f} ms, cooling (27 T) "
+        f"{t_w * 1e3:.2f} ms, moments (27 T) {t_m * 1e3:.3f} ms")
+    return {"emission_call_ms": t_em * 1e3, "emission_line_profiles_per_s": n_kept * len(temps) / t_em,
+            "emission_tile_kernel_ms_per_tp": kt["forward_ms"] / kt["forward_tp"],
+            "lifetimes_ms": t_tau * 1e3, "lifetimes_transitions_per_s": n_lines / t_tau,
+            "lifetimes_algorithmic_GBps": tau_bytes / t_tau / 1e9,
+            "cooling_27T_ms": t_w * 1e3, "cooling_transitions_per_s": n_lines / t_w,
+            "moments_cp_27T_ms": t_m * 1e3, "moments_state_temperatures_per_s": n_states * len(Ts) / t_m,
+            "note": "state reductions: whole synchronous calls (argument checks, device work, the wait for "
+                    "the index flags), wall clock; emission call = Q(T) + pre-passes + tile kernel"}
 
 
 def binned_leg(cfg2, d2, temps, pressures, n_kept2, stream, log):

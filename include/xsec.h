@@ -13,7 +13,10 @@
  *   - line wings truncated at a cut-off (25 cm^-1 by default), Sec. "Off-set";
  *   - the Vectorized Voigt approximation and its area-normalised form, Sec.
  *     "Vectorized Voigt approximation" and "Binned Vectorized Voigt with the line area
- *     preserved".
+ *     preserved";
+ *   - emission cross sections from the emissivity (Eq. for the emissivity), radiative
+ *     lifetimes, the cooling function, and the moments of the partition function with
+ *     the specific heat.
  *
  * Conventions
  *   Units: wavenumbers and energies in cm^-1, T in K, P in the unit of P0 (bar by
@@ -49,7 +52,7 @@
 extern "C" {
 #endif
 
-#define XS_ABI_VERSION 3
+#define XS_ABI_VERSION 4
 
 typedef struct xs_plan xs_plan;
 typedef struct xs_graph xs_graph;
@@ -208,11 +211,62 @@ typedef enum {
  * xs_cross_section_adjoint returns XS_ERR_UNSUPPORTED while a threshold is set. */
 xs_status xs_set_intensity_threshold(xs_plan* plan, int32_t mode, double i_crit, double nu_crit);
 
+/* Intensity kind of the cross sections (Sec. "Intensities and partition function"). */
+typedef enum {
+    XS_ABSORPTION = 0,   /* Eq. 1: I = g_up A/(8 pi c nu^2) exp(-c2 E_low/T)(1 - exp(-c2 nu/T))/Q;
+                            sigma in cm^2/molecule                                          */
+    XS_EMISSION = 1      /* the emissivity of the transition's upper state,
+                            eps = h c g_up A nu exp(-c2 E_up/T)/(4 pi Q) (erg/s/sr/molecule;
+                            the printed formula's unit needs the factor h c); sigma in
+                            erg/s/sr/molecule per cm^-1                                     */
+} xs_intensity_kind;
+
+/* Set the intensity kind of the following cross sections (default XS_ABSORPTION), with
+ * the same profiles, grid and cut-off.  Graphs captured before a change refuse to launch
+ * (XS_ERR_STATE); an open line-list stream fails its next chunk, and a checkpoint resumes
+ * only under the kind it was written with.  An intensity threshold compares the quantity
+ * summed (the emissivity for XS_EMISSION).  xs_cross_section_adjoint returns
+ * XS_ERR_UNSUPPORTED for XS_EMISSION.  Host-only, no device work. */
+xs_status xs_set_intensity_kind(xs_plan* plan, int32_t kind);
+
 /* Partition function Q(T) of Eq. 2 and its derivative dQ/dT, summed on the device
  * in double precision, for n_T temperatures.  T: host double[n_T] (> 0);
  * Q, dQdT: device double[n_T] or NULL. */
 xs_status xs_partition_function(xs_plan* plan, int32_t n_T, const double* T, double* Q,
                                 double* dQdT, void* stream);
+
+/* Moments of the partition function and the specific heat (Sec. "Partition function",
+ * the equation for C_p), summed on the device in double precision in a fixed order over
+ * the plan's states, for n_T temperatures, with x = c2 E/T:
+ *   Q = sum g e^-x,  Q' = T dQ/dT = sum g x e^-x,  Q'' = sum g x^2 e^-x,
+ *   C_p = R [Q''/Q - (Q'/Q)^2] + 5R/2  (J/K/mol; the internal states' heat capacity plus
+ *   the ideal gas's 5R/2; the printed formula lacks the square, and its T^2 d^2Q/dT^2 is
+ *   Q'' - 2Q').
+ * T: host double[n_T] (> 0); Q, Q1, Q2, Cp: device double[n_T] or NULL. */
+xs_status xs_partition_moments(xs_plan* plan, int32_t n_T, const double* T, double* Q, double* Q1,
+                               double* Q2, double* Cp, void* stream);
+
+/* Radiative lifetimes (Sec. "Radiative lifetime"): tau_i = 1 / sum of A over the given
+ * transitions whose upper state is i (s), +inf for a state that no transition leaves.
+ * upper: device int32[n_lines] (the plan's index_base); A: device float[n_lines] (ln A with
+ * a_is_log); tau: device double[n_states of the plan].  The transitions are independent of
+ * the plan's line set (every transition counts, whether or not its window meets the grid).
+ * The sums are FP64 atomic additions: their order, and so the last bits, may vary between
+ * runs.  SYNCHRONOUS (waits for `stream` to check the indices): XS_ERR_INDEX for an upper
+ * index out of range. */
+xs_status xs_lifetimes(xs_plan* plan, int64_t n_lines, const int32_t* upper, const float* A, double* tau,
+                       void* stream);
+
+/* Cooling function (Sec. "Cooling function"): the total power emitted per molecule and
+ * steradian, the sum of the emissivities of the given transitions,
+ *   W(T) = h c / (4 pi Q(T)) sum g_up A nu exp(-c2 E_up/T)  (erg/s/sr/molecule),
+ * for n_T temperatures.  Computed as one pass over the transitions that sums A nu per
+ * upper state (FP64 atomic additions, order not fixed) and, per temperature, a fixed-order
+ * pass over the states.  upper, lower: device int32[n_lines]; A: device float[n_lines];
+ * T: host double[n_T] (> 0); W: device double[n_T].  SYNCHRONOUS (waits to check the
+ * transitions): XS_ERR_INDEX, XS_ERR_NU_NONPOS as for xs_set_lines. */
+xs_status xs_cooling_function(xs_plan* plan, int64_t n_lines, const int32_t* upper, const int32_t* lower,
+                              const float* A, int32_t n_T, const double* T, double* W, void* stream);
 
 /* Cross sections for n_tp (T, P) pairs (Eq. 6-8 with the sampling method).
  * T, P: host double[n_tp] (T > 0, P >= 0; P = 0 gives the pure Doppler limit).

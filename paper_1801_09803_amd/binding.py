@@ -75,6 +75,10 @@ def load_library() -> ctypes.CDLL:
         "xs_set_intensity_threshold": (i32, [P, i32, dbl, dbl]),
         "xs_lines_kept": (i32, [P, ctypes.POINTER(i64)]),
         "xs_partition_function": (i32, [P, i32, P, P, P, P]),
+        "xs_set_intensity_kind": (i32, [P, i32]),
+        "xs_partition_moments": (i32, [P, i32, P, P, P, P, P, P]),
+        "xs_lifetimes": (i32, [P, i64, P, P, P, P]),
+        "xs_cooling_function": (i32, [P, i64, P, P, P, i32, P, P, P]),
         "xs_cross_section": (i32, [P, i32, P, P, P, P]),
         "xs_cross_section_adjoint": (i32, [P, dbl, dbl, P, P, P, P, P, P, P]),
         "xs_graph_create": (i32, [P, i32, P, P, P, ctypes.POINTER(P)]),
@@ -236,6 +240,44 @@ class Plan:
         _check(self._lib.xs_partition_function(self._h, len(T), _host_doubles(T), _ptr(Q), _ptr(dQ),
                                                self._stream()))
         return Q, dQ
+
+    def partition_moments(self, T: Sequence[float]):
+        """(Q, Q' = T dQ/dT, Q'' = sum g x^2 e^-x, C_p in J/K/mol) per temperature."""
+        torch = self._torch
+        T = list(T)
+        out = [torch.empty(len(T), dtype=torch.float64, device="cuda") for _ in range(4)]
+        _check(self._lib.xs_partition_moments(self._h, len(T), _host_doubles(T), *[_ptr(x) for x in out],
+                                              self._stream()))
+        return tuple(out)
+
+    def lifetimes(self, upper, A):
+        """Radiative lifetime (s) of every state of the plan: 1 / sum of A leaving it."""
+        torch = self._torch
+        upper = self._dev(upper, torch.int32, "upper")
+        A = self._dev(A, torch.float32, "A")
+        states = getattr(self, "_states", None)
+        if states is None:
+            raise ValueError("set_states must come first")
+        tau = torch.empty(states[0].numel(), dtype=torch.float64, device="cuda")
+        _check(self._lib.xs_lifetimes(self._h, upper.numel(), _ptr(upper), _ptr(A), _ptr(tau), self._stream()))
+        return tau
+
+    def cooling_function(self, upper, lower, A, T: Sequence[float]):
+        """W(T) (erg/s/sr/molecule) of the given transitions at each temperature."""
+        torch = self._torch
+        upper = self._dev(upper, torch.int32, "upper")
+        lower = self._dev(lower, torch.int32, "lower")
+        A = self._dev(A, torch.float32, "A")
+        T = list(T)
+        W = torch.empty(len(T), dtype=torch.float64, device="cuda")
+        _check(self._lib.xs_cooling_function(self._h, upper.numel(), _ptr(upper), _ptr(lower), _ptr(A), len(T),
+                                             _host_doubles(T), _ptr(W), self._stream()))
+        return W
+
+    def set_intensity_kind(self, kind: str = "absorption"):
+        """Cross sections of absorption intensities (Eq. 1) or of emissivities ("emission")."""
+        kinds = {"absorption": 0, "emission": 1}
+        _check(self._lib.xs_set_intensity_kind(self._h, kinds[kind]))
 
     def cross_section(self, T: Sequence[float], P: Sequence[float], out=None):
         torch = self._torch

@@ -5,6 +5,7 @@
 #include "xs_lineprep.hpp"
 #include "xs_forward.hpp"
 #include "xs_adjoint.hpp"
+#include "xs_states.hpp"
 
 #include <algorithm>
 #include <chrono>
@@ -165,6 +166,7 @@ struct xs_plan {
     int tp_block = 0;       // 0: chosen per call
     int th_mode = 0;        // intensity threshold: 0 none, 1 constant, 2 HITRAN
     double th_icrit = 0.0, th_nucrit = 0.0;
+    int emission = 0;       // 1: cross sections sum emissivities instead of Eq. 1 intensities
     int last_split = 0, last_block = 0;
     uint64_t generation = 1;   // bumped whenever captured graphs become invalid
     size_t total_bytes = 0;
@@ -193,6 +195,9 @@ struct xs_plan {
     int q_cap = 0;
     DevBuf T_dev, Q, dQ, qpart;
     static constexpr int kQBlocks = 256;
+    // state reductions (moments, lifetimes, cooling function)
+    int st_cap = 0;
+    DevBuf st_T, st_part, st_sumA, st_power;
     // batched cross-section pipeline of direct calls
     Workset ws;
     // tables
@@ -210,7 +215,7 @@ struct xs_plan {
         DevBuf* all[] = {&E, &g, &J, &tab_g, &tab_n, &p_rec, &s_nu, &s_elow, &s_cA, &s_gref, &s_nexp, &s_kc, &s_klo,
                          &s_khi, &s_orig, &k1, &v1, &k2, &v2, &hist, &hoff, &tsum, &off, &flag,
                          &T_dev, &Q, &dQ, &qpart, &tab_dev, &tile_order, &adj_pT, &adj_pP, &adj_part, &adj_rec,
-                         &adj_sums};
+                         &adj_sums, &st_T, &st_part, &st_sumA, &st_power};
         for (DevBuf* b : all) release(*b);
         ws.release();
     }
@@ -245,6 +250,7 @@ struct xs_stream {
     int64_t pending_n = 0;
     bool pending_broad = false;
     int64_t chunks = 0, lines = 0, kept = 0;
+    int emission = 0;             // the plan's intensity kind when the stream began
     size_t bytes = 0;
 };
 
@@ -386,6 +392,7 @@ xs::TPParam make_tp(const xs_plan* p, double T, double P, int iq, double T_rm) {
     tp.ln_T0_T = std::log(o.T0 / T);
     tp.p_over_p0 = P / o.P0;
     tp.iq = iq;
+    tp.emission = p->emission;
     const double rmd = rm_steps(p, T_rm);
     tp.rm = rmd > 1.0e9 ? 1000000000 : (int)std::ceil(rmd);
     // the same radius for a line of wavenumber nu: xr alpha_D(nu) / (sqrt(ln2) dnu)
@@ -985,6 +992,14 @@ xs_status xs_set_intensity_threshold(xs_plan* p, int32_t mode, double i_crit, do
     return XS_OK;
 }
 
+xs_status xs_set_intensity_kind(xs_plan* p, int32_t kind) {
+    if (!p) return fail(XS_ERR_ARG, "plan is NULL");
+    if (kind != XS_ABSORPTION && kind != XS_EMISSION) return fail(XS_ERR_ARG, "unknown intensity kind");
+    if (p->emission != kind) p->generation++;   // captured graphs hold the other kind
+    p->emission = kind;
+    return XS_OK;
+}
+
 xs_status xs_lines_kept(const xs_plan* p, int64_t* n_kept) {
     if (!p || !n_kept) return fail(XS_ERR_ARG, "NULL argument");
     if (!p->have_lines) return fail(XS_ERR_STATE, "no line set");
@@ -1019,6 +1034,87 @@ xs_status xs_partition_function(xs_plan* p, int32_t nT, const double* T, double*
     if (st != XS_OK) return st;
     if (Q) XS_HIP(hipMemcpyAsync(Q, p->Q.p, nT * sizeof(double), hipMemcpyDeviceToDevice, s));
     if (dQdT) XS_HIP(hipMemcpyAsync(dQdT, p->dQ.p, nT * sizeof(double), hipMemcpyDeviceToDevice, s));
+    return XS_OK;
+}
+
+// Temperatures of a state reduction on the device, and its partial-sum buffer.
+static xs_status stage_temperatures(xs_plan* p, int nT, const double* T, hipStream_t s) {
+    if (!T) return fail(XS_ERR_ARG, "NULL argument");
+    if (nT <= 0) return fail(XS_ERR_ARG, "n_T must be > 0");
+    for (int i = 0; i < nT; ++i)
+        if (!(T[i] > 0.0) || !std::isfinite(T[i])) return fail(XS_ERR_ARG, "temperatures must be finite and > 0");
+    if (nT > p->st_cap) {
+        XS_TRY(p->ensure(p->st_T, nT * sizeof(double), "state-reduction temperatures"));
+        XS_TRY(p->ensure(p->st_part, (size_t)3 * nT * xs_plan::kQBlocks * sizeof(double), "state partial sums"));
+        p->st_cap = nT;
+    }
+    XS_HIP(hipMemcpyAsync(p->st_T.p, T, nT * sizeof(double), hipMemcpyHostToDevice, s));
+    return XS_OK;
+}
+
+// Per-state sums over the caller's transitions (sum of A and/or of A nu), then a wait for
+// the validation flags.
+static xs_status state_rates(xs_plan* p, int64_t n, const int32_t* upper, const int32_t* lower, const float* A,
+                             bool sum_A, bool power, hipStream_t s) {
+    if (n < 0) return fail(XS_ERR_ARG, "n_lines must be >= 0");
+    if (n > 0 && (!upper || !A || (power && !lower))) return fail(XS_ERR_ARG, "NULL transition array");
+    if (sum_A) XS_TRY(p->ensure(p->st_sumA, (size_t)p->n_states * sizeof(double), "per-state A sums"));
+    if (power) XS_TRY(p->ensure(p->st_power, (size_t)p->n_states * sizeof(double), "per-state A nu sums"));
+    XS_TRY(p->ensure(p->flag, sizeof(int) * 4, "flags"));
+    if (sum_A) XS_HIP(xs::launch_fill(as<double>(p->st_sumA), p->n_states, 0.0, s));
+    if (power) XS_HIP(xs::launch_fill(as<double>(p->st_power), p->n_states, 0.0, s));
+    XS_HIP(hipMemsetAsync(p->flag.p, 0, sizeof(int), s));
+    xs::RateArgs a{};
+    a.n = n;
+    a.upper = upper;
+    a.lower = lower;
+    a.A = A;
+    a.index_base = p->o.index_base;
+    a.a_is_log = p->o.a_is_log;
+    a.E = as<double>(p->E);
+    a.n_states = p->n_states;
+    a.flag = as<int>(p->flag);
+    a.sum_A = sum_A ? as<double>(p->st_sumA) : nullptr;
+    a.power = power ? as<double>(p->st_power) : nullptr;
+    XS_HIP(xs::launch_rates(a, s));
+    int flag = 0;
+    XS_HIP(hipMemcpyAsync(&flag, p->flag.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    XS_HIP(hipStreamSynchronize(s));
+    if (flag & xs::kFlagIndex) return fail(XS_ERR_INDEX, "a transition's state index is out of range");
+    if (flag & xs::kFlagNu) return fail(XS_ERR_NU_NONPOS, "a transition has E[upper] - E[lower] <= 0");
+    return XS_OK;
+}
+
+xs_status xs_partition_moments(xs_plan* p, int32_t nT, const double* T, double* Q, double* Q1, double* Q2,
+                               double* Cp, void* stream) {
+    if (!p) return fail(XS_ERR_ARG, "plan is NULL");
+    if (p->n_states <= 0) return fail(XS_ERR_STATE, "xs_set_states must come first");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    XS_TRY(stage_temperatures(p, nT, T, s));
+    XS_HIP(xs::launch_moments(as<double>(p->E), as<int>(p->g), p->n_states, as<double>(p->st_T), nT,
+                              as<double>(p->st_part), xs_plan::kQBlocks, Q, Q1, Q2, Cp, s));
+    return XS_OK;
+}
+
+xs_status xs_lifetimes(xs_plan* p, int64_t n_lines, const int32_t* upper, const float* A, double* tau,
+                       void* stream) {
+    if (!p || !tau) return fail(XS_ERR_ARG, "NULL argument");
+    if (p->n_states <= 0) return fail(XS_ERR_STATE, "xs_set_states must come first");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    XS_TRY(state_rates(p, n_lines, upper, nullptr, A, true, false, s));
+    XS_HIP(xs::launch_lifetimes(as<double>(p->st_sumA), p->n_states, tau, s));
+    return XS_OK;
+}
+
+xs_status xs_cooling_function(xs_plan* p, int64_t n_lines, const int32_t* upper, const int32_t* lower,
+                              const float* A, int32_t nT, const double* T, double* W, void* stream) {
+    if (!p || !W) return fail(XS_ERR_ARG, "NULL argument");
+    if (p->n_states <= 0) return fail(XS_ERR_STATE, "xs_set_states must come first");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    XS_TRY(stage_temperatures(p, nT, T, s));
+    XS_TRY(state_rates(p, n_lines, upper, lower, A, false, true, s));
+    XS_HIP(xs::launch_cooling(as<double>(p->E), as<int>(p->g), as<double>(p->st_power), p->n_states,
+                              as<double>(p->st_T), nT, as<double>(p->st_part), xs_plan::kQBlocks, W, s));
     return XS_OK;
 }
 
@@ -1325,6 +1421,7 @@ xs_status stream_create(xs_plan* p, int n_tp, const double* T, const double* P, 
     st->T.assign(T, T + n_tp);
     st->P.assign(P, P + n_tp);
     st->sigma = sigma;
+    st->emission = p->emission;
     st->compute = static_cast<hipStream_t>(stream);
     hipError_t e = hipStreamCreateWithFlags(&st->copy, hipStreamNonBlocking);
     if (e != hipSuccess) { st->copy = nullptr; stream_free(st); return hip_fail(e, "hipStreamCreateWithFlags"); }
@@ -1345,6 +1442,8 @@ xs_status stream_process(xs_stream* st) {
     if (!st->have_pending) return XS_OK;
     st->have_pending = false;
     xs_plan* p = st->p;
+    if (p->emission != st->emission)
+        return fail(XS_ERR_STATE, "the plan's intensity kind changed while the stream was open");
     const int k = st->pending_slot;
     XS_HIP(hipStreamWaitEvent(st->compute, st->copied[k], 0));
     DevBuf* r = st->raw[k];
@@ -1435,6 +1534,9 @@ xs_status xs_stream_end(xs_stream* st, int64_t* lines_kept) {
     return r;
 }
 
+// precision and intensity kind of a stream's cross sections, as one checkpoint field
+int64_t ckpt_kind(const xs_stream* st) { return st->p->o.precision | (st->emission << 8); }
+
 xs_status xs_stream_checkpoint(xs_stream* st, const char* path) {
     if (!st || !path) return fail(XS_ERR_ARG, "NULL argument");
     XS_TRY(stream_process(st));
@@ -1447,7 +1549,7 @@ xs_status xs_stream_checkpoint(xs_stream* st, const char* path) {
     const std::string tmp = std::string(path) + ".tmp";
     FILE* f = std::fopen(tmp.c_str(), "wb");
     if (!f) return fail(XS_ERR_ARG, std::string("cannot write ") + tmp);
-    const int64_t hdr[8] = {(int64_t)kCkptMagic, XS_ABI_VERSION, st->n_tp, p->geo.n_points, p->o.precision,
+    const int64_t hdr[8] = {(int64_t)kCkptMagic, XS_ABI_VERSION, st->n_tp, p->geo.n_points, ckpt_kind(st),
                             st->chunks, st->lines, st->kept};
     bool ok = std::fwrite(hdr, sizeof(hdr), 1, f) == 1;
     ok = ok && std::fwrite(st->T.data(), sizeof(double), st->n_tp, f) == (size_t)st->n_tp;
@@ -1474,9 +1576,9 @@ xs_status xs_stream_resume(xs_plan* p, const char* path, void* sigma, void* stre
         return fail(XS_ERR_ARG, "not a checkpoint of this library version");
     }
     const int n_tp = (int)hdr[2];
-    if (n_tp <= 0 || hdr[3] != p->geo.n_points || hdr[4] != p->o.precision) {
+    if (n_tp <= 0 || hdr[3] != p->geo.n_points || hdr[4] != (p->o.precision | (p->emission << 8))) {
         std::fclose(f);
-        return fail(XS_ERR_ARG, "the checkpoint's grid or precision differs from the plan's");
+        return fail(XS_ERR_ARG, "the checkpoint's grid, precision or intensity kind differs from the plan's");
     }
     std::vector<double> T(n_tp), P(n_tp);
     const size_t bytes = (size_t)n_tp * p->geo.n_points * 2 * stream_elem(p);
@@ -1513,6 +1615,7 @@ xs_status xs_cross_section_adjoint(xs_plan* p, double T, double P, const void* g
     if (!p->have_lines) return fail(XS_ERR_STATE, "xs_set_lines must succeed first");
     if (p->o.profile != XS_VOIGT) return fail(XS_ERR_UNSUPPORTED, "the adjoint is implemented for XS_VOIGT");
     if (threshold_on(p)) return fail(XS_ERR_UNSUPPORTED, "the adjoint does not apply an intensity threshold");
+    if (p->emission) return fail(XS_ERR_UNSUPPORTED, "the adjoint differentiates absorption intensities (Eq. 1)");
     if ((dgref || dn) && p->o.broadening != XS_BROAD_PER_LINE)
         return fail(XS_ERR_UNSUPPORTED, "gamma_ref / n gradients need per-line broadening");
     if (!(P >= 0.0) || !std::isfinite(P)) return fail(XS_ERR_ARG, "pressure must be finite and >= 0");

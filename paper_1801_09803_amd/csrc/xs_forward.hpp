@@ -14,6 +14,18 @@ enum ProfileKind {
     kSuperLines = 9       // per-bin intensity sums (no profile)
 };
 
+// Line intensity at a (T, P) point from the stored T-independent factor
+// cA = g_up A / (8 pi c nu^2) and the lower-state energy:
+//   absorption (Eq. 1, cm/molecule): cA exp(-c2 E_low/T) (1 - exp(-c2 nu/T)) / Q;
+//   emission (the emissivity, erg/s/sr/molecule): h c g_up A nu exp(-c2 E_up/T) / (4 pi Q),
+//   which is 2 h c^2 nu^3 cA exp(-c2 E_up/T) / Q with E_up = E_low + nu.
+__device__ __forceinline__ double line_intensity(double cA, double elow, double nu, const TPParam& tp,
+                                                 double Q) {
+    if (tp.emission)
+        return cA * ((2.0 * kH_CGS * kC_CGS * kC_CGS) * (nu * nu * nu)) * exp(-(kC2 * (elow + nu)) / tp.T) / Q;
+    return cA * exp(-(kC2 * elow) / tp.T) * (-expm1(-(kC2 * nu) / tp.T)) / Q;
+}
+
 struct FwdArgs {
     SortedLines L;
     Geometry G;

@@ -45,9 +45,7 @@ __device__ __forceinline__ LineSetup line_setup(const SortedLines& L, const TPPa
     LineSetup o;
     o.nu = L.nu[g];
     const double el = L.elow[g];
-    const double T = tp.T;
-    // Eq. 1: I = [g_f A/(8 pi c nu^2)] exp(-c2 E_i/T) (1 - exp(-c2 nu/T)) / Q(T)
-    o.S = L.cA[g] * exp(-(kC2 * el) / T) * (-expm1(-(kC2 * o.nu) / T)) / Q;
+    o.S = line_intensity(L.cA[g], el, o.nu, tp, Q);   // Eq. 1, or the emissivity for emission
     o.aD = o.nu * tp.beta;                                                        // Eq. 16
     o.gam = (double)L.gref[g] * exp((double)L.nexp[g] * tp.ln_T0_T) * tp.p_over_p0;  // Eq. 18
     o.kc = L.kc[g];

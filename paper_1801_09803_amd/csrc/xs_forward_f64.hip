@@ -343,9 +343,7 @@ __global__ __launch_bounds__(256) void superline_kernel(const FwdArgs A, int fp6
     double acc = 0.0;
     for (int l = l0; l < l1; ++l) {
         const int gs = line_of(map, l);
-        // Eq. 1: I = [g_f A/(8 pi c nu^2)] exp(-c2 E_i/T) (1 - exp(-c2 nu/T)) / Q(T)
-        const double nu = A.L.nu[gs];
-        acc += A.L.cA[gs] * exp(-(kC2 * A.L.elow[gs]) / tp.T) * (-expm1(-(kC2 * nu) / tp.T)) / Q;
+        acc += line_intensity(A.L.cA[gs], A.L.elow[gs], A.L.nu[gs], tp, Q);   // Eq. 1 (or emissivity)
     }
     const double v = acc / G.dnu;
     if (fp64) static_cast<double*>(A.sigma)[i] = v;

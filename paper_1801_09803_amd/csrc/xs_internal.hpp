@@ -15,6 +15,7 @@ constexpr double kKB = 1.380649e-23;         // J / K
 constexpr double kAMU = 1.66053906660e-27;   // kg
 constexpr double kC_CGS = kC_SI * 100.0;     // cm / s
 constexpr double kC2 = kH * kC_SI / kKB * 100.0;   // cm K
+constexpr double kH_CGS = kH * 1.0e7;        // erg s
 constexpr double kPI = 3.14159265358979323846;
 constexpr double kLN2 = 0.69314718055994530942;
 constexpr double kSQRT_LN2 = 0.83255461115769775635;        // sqrt(ln 2)
@@ -64,6 +65,7 @@ struct TPParam {
                           // profiles; 0 when the radius does not grow with the wavenumber)
     int iq;               // index of T in the plan's device Q array
     int rm;               // bound on the mid/core radius in grid steps (FP32 Voigt fast path)
+    int emission;         // 1: line intensities are emissivities (upper-state population)
 };
 
 // Gauss-Hermite pairs used by the wing formulas (positive nodes only).

@@ -5,27 +5,9 @@
 // contiguous index range found through an offsets table.
 #include "xs_internal.hpp"
 #include "xs_lineprep.hpp"
+#include "xs_reduce.hpp"
 
 namespace xs {
-
-// ---------------------------------------------------------------- reductions
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-    return v;
-}
-
-// Block sum in a fixed order (wave shuffles, then wave 0 over the 4 wave sums).
-__device__ __forceinline__ double block_sum256(double v, double* lds4) {
-    v = wave_sum(v);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    __syncthreads();
-    if (lane == 0) lds4[wave] = v;
-    __syncthreads();
-    double r = 0.0;
-    if (threadIdx.x == 0) r = (lds4[0] + lds4[1]) + (lds4[2] + lds4[3]);
-    return r;   // valid in thread 0
-}
 
 // Q(T) and dQ/dT partial sums: block b of temperature blockIdx.y sums states
 // b, b + nb, ... (per thread: i = b*256 + t + k*nb*256).

@@ -1,0 +1,156 @@
+// State reductions (Sec. "Radiative lifetime", Sec. "Cooling function", and the specific
+// heat from the moments of the partition function, Sec. "Partition function").
+//
+// The cooling function is a sum over transitions of the emissivity; every transition
+// leaving state i carries the same population factor g_i exp(-c2 E_i/T)/Q, so
+//     W(T) = h c / (4 pi Q(T)) sum_i g_i exp(-c2 E_i/T) P_i,   P_i = sum_f A_fi nu_fi.
+// One pass over the transitions accumulates P_i (and sum_f A_fi, the inverse lifetime)
+// per state; each temperature then costs a pass over the states only, not the lines.
+#include "xs_states.hpp"
+#include "xs_reduce.hpp"
+
+#include <cmath>
+
+namespace xs {
+
+namespace {
+
+constexpr double kR_GAS = kKB * 6.02214076e23;   // J / (K mol), the exact SI value
+
+__global__ __launch_bounds__(256) void fill_kernel(double* x, int64_t n, double v) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) x[i] = v;
+}
+
+__global__ __launch_bounds__(256) void rates_kernel(const RateArgs a) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= a.n) return;
+    const int up = a.upper[i] - a.index_base;
+    if (up < 0 || up >= a.n_states) { atomicOr(a.flag, kFlagIndex); return; }
+    const double Aein = a.a_is_log ? exp((double)a.A[i]) : (double)a.A[i];
+    if (a.power) {
+        const int lo = a.lower[i] - a.index_base;
+        if (lo < 0 || lo >= a.n_states) { atomicOr(a.flag, kFlagIndex); return; }
+        const double nu = a.E[up] - a.E[lo];
+        if (!(nu > 0.0)) { atomicOr(a.flag, kFlagNu); return; }
+        unsafeAtomicAdd(a.power + up, Aein * nu);
+    }
+    if (a.sum_A) unsafeAtomicAdd(a.sum_A + up, Aein);
+}
+
+__global__ __launch_bounds__(256) void lifetime_kernel(const double* __restrict__ sum_A, int64_t n,
+                                                       double* __restrict__ tau) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const double s = sum_A[i];
+    tau[i] = s > 0.0 ? 1.0 / s : HUGE_VAL;
+}
+
+// Partial sums over the states for temperature blockIdx.y: block b sums the states
+// b*256 + t + k*nb*256.  MOM: (w, w x, w x^2) with w = g exp(-x), x = c2 E/T; otherwise
+// (w, w P).
+template <bool MOM>
+__global__ __launch_bounds__(256) void state_partial_kernel(const double* __restrict__ E, const int* __restrict__ g,
+                                                            const double* __restrict__ power, int64_t n,
+                                                            const double* __restrict__ T, int nb,
+                                                            double* __restrict__ part) {
+    __shared__ double lds[4];
+    const double t = T[blockIdx.y];
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    const int64_t stride = (int64_t)nb * 256;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) {
+        const double x = (kC2 * E[i]) / t;
+        const double w = (double)g[i] * exp(-x);
+        s0 += w;
+        if constexpr (MOM) {
+            s1 += w * x;
+            s2 += (w * x) * x;
+        } else {
+            s1 += w * power[i];
+        }
+    }
+    constexpr int NS = MOM ? 3 : 2;
+    const double r0 = block_sum256(s0, lds);
+    const double r1 = block_sum256(s1, lds);
+    const double r2 = MOM ? block_sum256(s2, lds) : 0.0;
+    if (threadIdx.x == 0) {
+        double* p = part + (int64_t)NS * blockIdx.y * nb + blockIdx.x;
+        p[0] = r0;
+        p[nb] = r1;
+        if (MOM) p[2 * nb] = r2;
+    }
+}
+
+// Per temperature blockIdx.x: the nb partials of each sum, added in a fixed order.
+template <bool MOM>
+__global__ __launch_bounds__(256) void state_final_kernel(const double* __restrict__ part, int nb, double* Q,
+                                                          double* Q1, double* Q2, double* Cp, double* W) {
+    __shared__ double lds[4];
+    constexpr int NS = MOM ? 3 : 2;
+    const double* p = part + (int64_t)NS * blockIdx.x * nb;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    for (int i = threadIdx.x; i < nb; i += 256) {
+        s0 += p[i];
+        s1 += p[nb + i];
+        if (MOM) s2 += p[2 * nb + i];
+    }
+    const double q = block_sum256(s0, lds);
+    const double q1 = block_sum256(s1, lds);
+    const double q2 = MOM ? block_sum256(s2, lds) : 0.0;
+    if (threadIdx.x != 0) return;
+    const int t = blockIdx.x;
+    if (MOM) {
+        if (Q) Q[t] = q;
+        if (Q1) Q1[t] = q1;
+        if (Q2) Q2[t] = q2;
+        // C_p = R [Q''/Q - (Q'/Q)^2] + 5R/2: the internal states' heat capacity (the variance
+        // of x under the Boltzmann populations) plus the ideal gas's translation and pV
+        if (Cp) {
+            const double m1 = q1 / q;
+            Cp[t] = kR_GAS * (q2 / q - m1 * m1) + 2.5 * kR_GAS;
+        }
+    } else {
+        W[t] = (kH_CGS * kC_CGS) * q1 / (4.0 * kPI * q);
+    }
+}
+
+dim3 grid_of(int64_t n) { return dim3((unsigned)((n + 255) / 256)); }
+
+}  // namespace
+
+hipError_t launch_fill(double* x, int64_t n, double v, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_kernel, grid_of(n), dim3(256), 0, s, x, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_rates(const RateArgs& a, hipStream_t s) {
+    if (a.n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(rates_kernel, grid_of(a.n), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_lifetimes(const double* sum_A, int64_t n, double* tau, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(lifetime_kernel, grid_of(n), dim3(256), 0, s, sum_A, n, tau);
+    return hipGetLastError();
+}
+
+hipError_t launch_moments(const double* E, const int* g, int64_t n, const double* T_dev, int nT, double* part,
+                          int nb, double* Q, double* Q1, double* Q2, double* Cp, hipStream_t s) {
+    hipLaunchKernelGGL(state_partial_kernel<true>, dim3(nb, nT), dim3(256), 0, s, E, g, (const double*)nullptr, n,
+                       T_dev, nb, part);
+    hipLaunchKernelGGL(state_final_kernel<true>, dim3(nT), dim3(256), 0, s, part, nb, Q, Q1, Q2, Cp,
+                       (double*)nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_cooling(const double* E, const int* g, const double* power, int64_t n, const double* T_dev,
+                          int nT, double* part, int nb, double* W, hipStream_t s) {
+    hipLaunchKernelGGL(state_partial_kernel<false>, dim3(nb, nT), dim3(256), 0, s, E, g, power, n, T_dev, nb, part);
+    hipLaunchKernelGGL(state_final_kernel<false>, dim3(nT), dim3(256), 0, s, part, nb, (double*)nullptr,
+                       (double*)nullptr, (double*)nullptr, (double*)nullptr, W);
+    return hipGetLastError();
+}
+
+}  // namespace xs

@@ -1,0 +1,39 @@
+// Launch interfaces of the state reductions: partition-function moments and the specific
+// heat, per-state sums over the transitions (radiative lifetimes), and the cooling function.
+#pragma once
+
+#include "xs_internal.hpp"
+
+namespace xs {
+
+// One pass over the transitions in the caller's order.  Per transition: the state
+// indices are checked (kFlagIndex) and, when nu is needed, nu = E_up - E_low > 0
+// (kFlagNu); then, per upper state, sum_A += A and power += A nu (FP64 atomics, each
+// output optional).  Invalid transitions contribute nothing.
+struct RateArgs {
+    int64_t n;
+    const int* upper;
+    const int* lower;       // needed only for power
+    const float* A;
+    int index_base;
+    int a_is_log;           // A holds ln A
+    const double* E;
+    int64_t n_states;
+    int* flag;
+    double* sum_A;          // [n_states] or NULL
+    double* power;          // [n_states] or NULL
+};
+
+hipError_t launch_fill(double* x, int64_t n, double v, hipStream_t s);
+hipError_t launch_rates(const RateArgs& a, hipStream_t s);
+// tau_i = 1 / sum_A_i, +inf where no transition leaves state i
+hipError_t launch_lifetimes(const double* sum_A, int64_t n, double* tau, hipStream_t s);
+// Q, Q' = sum g x e^-x, Q'' = sum g x^2 e^-x (x = c2 E/T) and C_p per temperature; part:
+// 3 nT nb doubles; every output optional.
+hipError_t launch_moments(const double* E, const int* g, int64_t n, const double* T_dev, int nT, double* part,
+                          int nb, double* Q, double* Q1, double* Q2, double* Cp, hipStream_t s);
+// W(T) = h c sum_i g_i power_i exp(-c2 E_i/T) / (4 pi Q(T)); part: 2 nT nb doubles.
+hipError_t launch_cooling(const double* E, const int* g, const double* power, int64_t n, const double* T_dev,
+                          int nT, double* part, int nb, double* W, hipStream_t s);
+
+}  // namespace xs

@@ -15,8 +15,8 @@ namespace {
 
 __device__ __forceinline__ bool keep_line(const CullArgs& A, const TPParam& tp, double Q, int g) {
     const double nu = A.L.nu[g];
-    // Eq. 1: I = [g_f A/(8 pi c nu^2)] exp(-c2 E_i/T) (1 - exp(-c2 nu/T)) / Q(T)
-    const double S = A.L.cA[g] * exp(-(kC2 * A.L.elow[g]) / tp.T) * (-expm1(-(kC2 * nu) / tp.T)) / Q;
+    // the intensity the cross section sums: Eq. 1, or the emissivity for emission
+    const double S = line_intensity(A.L.cA[g], A.L.elow[g], nu, tp, Q);
     double cut = A.i_crit;
     if (A.mode == 2 && nu <= A.nu_crit) cut = A.i_crit * (nu / A.nu_crit) * tanh(kC2 * nu / (2.0 * tp.T));
     return S >= cut;

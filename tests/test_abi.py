@@ -36,7 +36,7 @@ def test_library_exports_every_declared_symbol():
 def test_version_and_defaults_without_gpu():
     from paper_1801_09803_amd.binding import XsOpts, load_library
     lib = load_library()
-    assert lib.xs_version() == 3
+    assert lib.xs_version() == 4
     o = XsOpts()
     assert lib.xs_opts_default(ctypes.byref(o)) == 0
     assert o.cutoff == 25.0 and o.T0 == 296.0 and o.P0 == 1.0 and o.profile == 3
@@ -103,6 +103,16 @@ def test_stream_calls_reject_null_arguments_on_host():
     assert lib.xs_stream_checkpoint(None, b"x") == 1
     assert lib.xs_stream_resume(None, b"x", None, None, ctypes.byref(h)) == 1 and not h.value
     assert lib.xs_stream_stats(None, None) == 1
+
+
+def test_state_reduction_and_emission_calls_reject_null_plans_on_host():
+    from paper_1801_09803_amd.binding import load_library
+    lib = load_library()
+    T = (ctypes.c_double * 1)(296.0)
+    assert lib.xs_set_intensity_kind(None, 1) == 1
+    assert lib.xs_partition_moments(None, 1, T, None, None, None, None, None) == 1
+    assert lib.xs_lifetimes(None, 0, None, None, None, None) == 1
+    assert lib.xs_cooling_function(None, 0, None, None, None, 1, T, None, None) == 1
 
 
 def test_binding_handles_skip_the_library_in_forked_processes():

@@ -24,7 +24,7 @@ def _sample_points(sig, n_rand, seed, n_points):
     return np.array(sorted(pts))
 
 
-def _oracle_at(cfg, d, ks, T, P, margin=25.5, vv_beta=None):
+def _oracle_at(cfg, d, ks, T, P, margin=25.5, vv_beta=None, emission=False):
     """Oracle sigma at grid indices ks: lines near each point are gathered on the
     device (a generous distance filter) and evaluated on the host."""
     E = d["E"]
@@ -39,6 +39,8 @@ def _oracle_at(cfg, d, ks, T, P, margin=25.5, vv_beta=None):
     Q = O.partition_function(Eh, gh, T)
     ls = O.make_lineset(Eh, gh, h["upper"], h["lower"], h["A"], T, P, cfg.mass_amu,
                         gamma_ref=h["gamma_ref"], n_exp=h["n_exp"], Q=Q)
+    if emission:
+        ls.I = O.emissivities(Eh, gh, h["upper"], h["lower"], h["A"], T, Q=Q)
     log(f"  oracle: {idx.numel()} lines near {ks.size} points")
     if vv_beta is not None:
         return O.cross_section_vv_at(ls, ks, cfg.nu_a, cfg.nu_b, cfg.n_points, T, cfg.mass_amu, cutoff=cfg.cutoff,
@@ -97,6 +99,41 @@ def test_c2_full_size_vvoigt_sampled(c2, T, beta):
     ks = _sample_points(sig, 16, 11 + int(T), cfg.n_points)
     ref = _oracle_at(cfg, d, ks, T, 1.0, vv_beta=beta)
     _check(sig[ks], ref, 1e-5, f"C2 V-V fp32 T={T} beta={beta}")
+
+
+def test_c2_full_size_emission_sampled(c2):
+    # emission cross sections at the full C2 list, in the tile shape bench.py times
+    cfg, d = c2
+    plan = make_plan(cfg, "fp32")
+    plan.set_states(d["E"], d["g"], d["J"])
+    plan.set_lines(d["upper"], d["lower"], d["A"], d["gamma_ref"], d["n_exp"])
+    plan.set_intensity_kind("emission")
+    sig = plan.cross_section([2000.0], [1.0])[0].double().cpu().numpy()
+    ks = _sample_points(sig, 16, 2017, cfg.n_points)
+    ref = _oracle_at(cfg, d, ks, 2000.0, 1.0, emission=True)
+    _check(sig[ks], ref, 1e-5, "C2 emission fp32 T=2000")
+
+
+def test_c2_full_size_state_reductions(c2):
+    # lifetimes over the full C2 list (per state) and the cooling function over it,
+    # against the oracle at sampled states / at one temperature
+    cfg, d = c2
+    plan = make_plan(cfg, "fp32")
+    plan.set_states(d["E"], d["g"], d["J"])
+    tau = plan.lifetimes(d["upper"], d["A"])
+    W = plan.cooling_function(d["upper"], d["lower"], d["A"], [1000.0]).item()
+    rng = np.random.default_rng(5)
+    states = torch.tensor(np.unique(rng.integers(0, cfg.n_states, 40)), device="cuda")
+    up = d["upper"].long()
+    for s in states.tolist():
+        sel = torch.nonzero(up == s).squeeze(1)
+        ref = O.lifetimes(1, np.zeros(sel.numel(), np.int64), d["A"][sel].cpu().numpy())[0]
+        got = tau[s].item()
+        assert (math.isinf(ref) and math.isinf(got)) or abs(got / ref - 1) <= 1e-12, (s, got, ref)
+    h = {k: d[k].cpu().numpy() for k in ("E", "g", "upper", "lower", "A")}
+    ref = O.cooling_function(h["E"], h["g"], h["upper"], h["lower"], h["A"], 1000.0)
+    log(f"  C2 W(1000 K) = {W:.6e} (oracle {ref:.6e})")
+    assert abs(W / ref - 1) <= 1e-11
 
 
 def test_c3_subset_full_size(c2):
