@@ -16,3 +16,4 @@ from .vvoigt import *  # noqa: F401,F403
 from .binned import *  # noqa: F401,F403
 from .threshold import *  # noqa: F401,F403
 from .emission import *  # noqa: F401,F403
+from .nonlte import *  # noqa: F401,F403

@@ -188,6 +188,13 @@ def make_broadening_table(seed: int, n_j: int = 51, device="cpu"):
     return gref, nexp
 
 
+def make_vibrational_labels(E: torch.Tensor, band_width: float = 2000.0) -> torch.Tensor:
+    """Vibrational (vibronic) manifold label per state, for non-LTE inputs: the synthetic
+    states carry no quantum numbers, so states are grouped into energy bands of
+    band_width cm^-1, label = floor(E / band_width) (int32)."""
+    return torch.floor(E / band_width).to(torch.int32)
+
+
 def make_linelist(cfg: WorkloadConfig, n_lines: Optional[int] = None, n_states: Optional[int] = None,
                   device="cpu", first_line: int = 0):
     """Full synthetic input for a workload (optionally truncated in size)."""

@@ -269,3 +269,46 @@ def test_heat_capacity_without_the_square_is_caught(monkeypatch):
     monkeypatch.setattr(O, "heat_capacity", bad)
     with pytest.raises(AssertionError):
         epins.test_heat_capacity_closed_forms()
+
+
+# ------------------------------------------------------------ non-LTE populations
+import oracle.nonlte as NL  # noqa: E402
+from tests import test_oracle_nonlte as npins  # noqa: E402
+
+
+def test_swapped_vibrational_and_rotational_temperatures_are_caught(monkeypatch):
+    def swapped(E, E_vib, T_vib, T_rot):
+        E = np.asarray(E, np.float64); Ev = np.asarray(E_vib, np.float64)
+        return np.exp(-O.C2 * Ev / T_rot) * np.exp(-O.C2 * (E - Ev) / T_vib)
+    monkeypatch.setattr(NL, "nlte_populations", swapped)
+    with pytest.raises(AssertionError):
+        npins.test_separable_spectrum_factorises()
+
+
+def test_manifold_energy_from_the_highest_state_is_caught(monkeypatch):
+    def highest(E, labels):
+        E = np.asarray(E, np.float64); lab = np.asarray(labels, np.int64)
+        top = {}
+        for e, l in zip(E.tolist(), lab.tolist()):
+            top[l] = max(top.get(l, e), e)
+        return np.array([top[l] for l in lab.tolist()])
+    monkeypatch.setattr(NL, "vibrational_energies", highest)
+    monkeypatch.setattr(O, "vibrational_energies", highest)
+    with pytest.raises(AssertionError):
+        npins.test_separable_spectrum_factorises()
+
+
+def test_non_lte_intensity_without_stimulated_emission_is_caught(monkeypatch):
+    def no_stim(E, g, E_vib, upper, lower, A, T_vib, T_rot, Q=None, index_base=0):
+        E = np.asarray(E, np.float64); Ev = np.asarray(E_vib, np.float64)
+        up = np.asarray(upper, np.int64) - index_base; lo = np.asarray(lower, np.int64) - index_base
+        nu = E[up] - E[lo]
+        if Q is None:
+            Q = NL.partition_function_nlte(E, g, Ev, T_vib, T_rot)
+        F_low = NL.nlte_populations(E[lo], Ev[lo], T_vib, T_rot)
+        gg = np.asarray(g, np.float64)
+        return gg[up] * np.asarray(A, np.float64) / (8 * math.pi * O.C_LIGHT_CGS * nu * nu) * F_low / Q
+    monkeypatch.setattr(NL, "intensities_nlte", no_stim)
+    monkeypatch.setattr(O, "intensities_nlte", no_stim)
+    with pytest.raises(AssertionError):
+        npins.test_two_level_vibrational_band()
