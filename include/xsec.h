@@ -16,7 +16,8 @@
  *     preserved";
  *   - emission cross sections from the emissivity (Eq. for the emissivity), radiative
  *     lifetimes, the cooling function, and the moments of the partition function with
- *     the specific heat.
+ *     the specific heat;
+ *   - two-temperature (vibrational / rotational) non-LTE populations.
  *
  * Conventions
  *   Units: wavenumbers and energies in cm^-1, T in K, P in the unit of P0 (bar by
@@ -234,6 +235,36 @@ xs_status xs_set_intensity_kind(xs_plan* plan, int32_t kind);
  * Q, dQdT: device double[n_T] or NULL. */
 xs_status xs_partition_function(xs_plan* plan, int32_t n_T, const double* T, double* Q,
                                 double* dQdT, void* stream);
+
+/* Non-LTE populations (Sec. "Treating non-local thermodynamic equilibrium"): each state's
+ * energy splits as E = E_vib + E_rot, with E_vib the energy of the lowest state of its
+ * vibrational (vibronic) manifold (the lowest-J state, which on a rotational ladder is the
+ * manifold's lowest energy), and its population per degeneracy is
+ *   F = exp(-c2 E_vib/T_vib) exp(-c2 E_rot/T_rot).
+ * labels: device int32[n_states], the manifold of each state in [0, n_labels); E_vib is the
+ * lowest energy among the states of a manifold (state energies must be >= 0).  NULL
+ * returns to LTE.  Invalidates the line set: xs_set_lines must follow (it then carries the
+ * vibrational energies of each line's states).  SYNCHRONOUS (checks the labels):
+ * XS_ERR_INDEX for a label out of range, XS_ERR_ARG for a negative energy. */
+xs_status xs_set_vibrational_labels(xs_plan* plan, int32_t n_labels, const int32_t* labels, void* stream);
+
+/* Cross sections with non-LTE populations for n_tp (T_rot, T_vib, P) points: as
+ * xs_cross_section (T_rot in the Doppler width, the broadening and the rotational
+ * populations), with the absorption intensity
+ *   I = g_up A/(8 pi c nu^2) (F_low - F_up) / Q(T_vib, T_rot),   Q = sum g F,
+ * (Eq. 1's population difference; negative for an inverted transition) or, for
+ * XS_EMISSION, the emissivity h c g_up A nu F_up/(4 pi Q).  T_rot, T_vib, P: host
+ * double[n_tp].  Needs a line set made after xs_set_vibrational_labels (XS_ERR_STATE).
+ * xs_cross_section on such a line set takes T_vib = T_rot (the LTE values); graphs and
+ * streams do the same.  xs_cross_section_adjoint returns XS_ERR_UNSUPPORTED. */
+xs_status xs_cross_section_nlte(xs_plan* plan, int32_t n_tp, const double* T_rot, const double* T_vib,
+                                const double* P, void* sigma, void* stream);
+
+/* Non-LTE partition function Q(T_vib, T_rot) = sum g F over the plan's states, in double
+ * precision (a fixed-order device sum).  T_rot, T_vib: host double[n_T]; Q: device
+ * double[n_T].  Needs xs_set_vibrational_labels (XS_ERR_STATE). */
+xs_status xs_partition_function_nlte(xs_plan* plan, int32_t n_T, const double* T_rot, const double* T_vib,
+                                     double* Q, void* stream);
 
 /* Moments of the partition function and the specific heat (Sec. "Partition function",
  * the equation for C_p), summed on the device in double precision in a fixed order over

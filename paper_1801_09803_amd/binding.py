@@ -76,6 +76,9 @@ def load_library() -> ctypes.CDLL:
         "xs_lines_kept": (i32, [P, ctypes.POINTER(i64)]),
         "xs_partition_function": (i32, [P, i32, P, P, P, P]),
         "xs_set_intensity_kind": (i32, [P, i32]),
+        "xs_set_vibrational_labels": (i32, [P, i32, P, P]),
+        "xs_cross_section_nlte": (i32, [P, i32, P, P, P, P, P]),
+        "xs_partition_function_nlte": (i32, [P, i32, P, P, P, P]),
         "xs_partition_moments": (i32, [P, i32, P, P, P, P, P, P]),
         "xs_lifetimes": (i32, [P, i64, P, P, P, P]),
         "xs_cooling_function": (i32, [P, i64, P, P, P, i32, P, P, P]),
@@ -273,6 +276,45 @@ class Plan:
         _check(self._lib.xs_cooling_function(self._h, upper.numel(), _ptr(upper), _ptr(lower), _ptr(A), len(T),
                                              _host_doubles(T), _ptr(W), self._stream()))
         return W
+
+    def set_vibrational_labels(self, labels, n_labels: Optional[int] = None):
+        """Non-LTE: per-state vibrational manifold labels (None returns to LTE); the line
+        set must be set again afterwards."""
+        torch = self._torch
+        if labels is None:
+            _check(self._lib.xs_set_vibrational_labels(self._h, 0, None, self._stream()))
+            return
+        labels = self._dev(labels, torch.int32, "labels")
+        if n_labels is None:
+            n_labels = int(labels.max().item()) + 1 if labels.numel() else 1
+        self._labels = labels
+        _check(self._lib.xs_set_vibrational_labels(self._h, int(n_labels), _ptr(labels), self._stream()))
+
+    def cross_section_nlte(self, T_rot: Sequence[float], T_vib: Sequence[float], P: Sequence[float], out=None):
+        """Cross sections with two-temperature populations at (T_rot, T_vib, P) points."""
+        torch = self._torch
+        T_rot, T_vib, P = list(T_rot), list(T_vib), list(P)
+        if not (len(T_rot) == len(T_vib) == len(P)):
+            raise ValueError("T_rot, T_vib and P differ in length")
+        if out is None:
+            out = torch.empty((len(P), self.n_points), dtype=self.dtype, device="cuda")
+        else:
+            out = self._dev(out, self.dtype, "out")
+            if out.numel() != len(P) * self.n_points:
+                raise ValueError("out has the wrong size")
+        _check(self._lib.xs_cross_section_nlte(self._h, len(P), _host_doubles(T_rot), _host_doubles(T_vib),
+                                               _host_doubles(P), _ptr(out), self._stream()))
+        return out
+
+    def partition_function_nlte(self, T_rot: Sequence[float], T_vib: Sequence[float]):
+        torch = self._torch
+        T_rot, T_vib = list(T_rot), list(T_vib)
+        if len(T_rot) != len(T_vib):
+            raise ValueError("T_rot and T_vib differ in length")
+        Q = torch.empty(len(T_rot), dtype=torch.float64, device="cuda")
+        _check(self._lib.xs_partition_function_nlte(self._h, len(T_rot), _host_doubles(T_rot), _host_doubles(T_vib),
+                                                    _ptr(Q), self._stream()))
+        return Q
 
     def set_intensity_kind(self, kind: str = "absorption"):
         """Cross sections of absorption intensities (Eq. 1) or of emissivities ("emission")."""

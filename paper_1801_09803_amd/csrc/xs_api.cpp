@@ -167,6 +167,8 @@ struct xs_plan {
     int th_mode = 0;        // intensity threshold: 0 none, 1 constant, 2 HITRAN
     double th_icrit = 0.0, th_nucrit = 0.0;
     int emission = 0;       // 1: cross sections sum emissivities instead of Eq. 1 intensities
+    bool has_vib = false;   // non-LTE: states carry vibrational energies (xs_set_vibrational_labels)
+    bool lines_vib = false; // the line set carries its states' vibrational energies
     int last_split = 0, last_block = 0;
     uint64_t generation = 1;   // bumped whenever captured graphs become invalid
     size_t total_bytes = 0;
@@ -198,6 +200,8 @@ struct xs_plan {
     // state reductions (moments, lifetimes, cooling function)
     int st_cap = 0;
     DevBuf st_T, st_part, st_sumA, st_power;
+    // non-LTE: per-state vibrational energies, manifold minima, per sorted line E_vib
+    DevBuf Ev, vmin, s_evl, s_evu;
     // batched cross-section pipeline of direct calls
     Workset ws;
     // tables
@@ -215,7 +219,7 @@ struct xs_plan {
         DevBuf* all[] = {&E, &g, &J, &tab_g, &tab_n, &p_rec, &s_nu, &s_elow, &s_cA, &s_gref, &s_nexp, &s_kc, &s_klo,
                          &s_khi, &s_orig, &k1, &v1, &k2, &v2, &hist, &hoff, &tsum, &off, &flag,
                          &T_dev, &Q, &dQ, &qpart, &tab_dev, &tile_order, &adj_pT, &adj_pP, &adj_part, &adj_rec,
-                         &adj_sums, &st_T, &st_part, &st_sumA, &st_power};
+                         &adj_sums, &st_T, &st_part, &st_sumA, &st_power, &Ev, &vmin, &s_evl, &s_evu};
         for (DevBuf* b : all) release(*b);
         ws.release();
     }
@@ -387,6 +391,7 @@ xs::TPParam make_tp(const xs_plan* p, double T, double P, int iq, double T_rm) {
     xs::TPParam tp{};
     tp.T = T;
     tp.P = P;
+    tp.Tv = T;   // LTE unless the call gives vibrational temperatures
     tp.c2_over_T = xs::kC2 / T;
     tp.beta = beta_of(o, T);
     tp.ln_T0_T = std::log(o.T0 / T);
@@ -531,6 +536,8 @@ xs::SortedLines sorted_lines(xs_plan* p) {
     L.nu = as<double>(p->s_nu); L.elow = as<double>(p->s_elow); L.cA = as<double>(p->s_cA);
     L.gref = as<float>(p->s_gref); L.nexp = as<float>(p->s_nexp); L.kc = as<int>(p->s_kc);
     L.klo = as<int>(p->s_klo); L.khi = as<int>(p->s_khi); L.orig = as<int>(p->s_orig);
+    L.evl = p->lines_vib ? as<double>(p->s_evl) : nullptr;
+    L.evu = p->lines_vib ? as<double>(p->s_evu) : nullptr;
     return L;
 }
 
@@ -628,24 +635,30 @@ xs::RecArgs rec_args(xs_plan* p, Workset& ws, int it, int row) {
 // Per-(T, P) parameters and temperatures to the device (through pinned staging), then
 // Q(T) for every temperature of the call.  With enqueue_q false the partition sum is
 // left to the caller (graph capture records it).
+// Q of the call's temperatures (ws.T: T then T_vib); non-LTE when the line set is.
+hipError_t enqueue_q_of_call(xs_plan* p, Workset& ws, int n, hipStream_t s) {
+    const double* Ev = p->lines_vib ? as<double>(p->Ev) : nullptr;
+    return xs::launch_partition(as<double>(p->E), as<int>(p->g), Ev, p->n_states, as<double>(ws.T),
+                                as<double>(ws.T) + n, n, as<double>(ws.qpart), xs_plan::kQBlocks, as<double>(ws.Q),
+                                as<double>(ws.dQ), s);
+}
+
 xs_status upload_tps(xs_plan* p, Workset& ws, const std::vector<xs::TPParam>& tps, hipStream_t s, bool enqueue_q) {
     const int n = (int)tps.size();
-    XS_TRY(ws.ensure(ws.T, n * sizeof(double), "temperatures"));
+    XS_TRY(ws.ensure(ws.T, 2 * n * sizeof(double), "temperatures"));
     XS_TRY(ws.ensure(ws.Q, n * sizeof(double), "Q(T)"));
     XS_TRY(ws.ensure(ws.dQ, n * sizeof(double), "dQ/dT"));
     XS_TRY(ws.ensure(ws.qpart, (size_t)2 * n * xs_plan::kQBlocks * sizeof(double), "Q partials"));
     XS_TRY(ws.ensure(ws.tps, n * sizeof(xs::TPParam), "(T, P) parameters"));
     void* h = nullptr;
-    XS_TRY(ws.stage.get(n * (sizeof(double) + sizeof(xs::TPParam)), &h));
+    XS_TRY(ws.stage.get(n * (2 * sizeof(double) + sizeof(xs::TPParam)), &h));
     double* hT = static_cast<double*>(h);
-    xs::TPParam* hp = reinterpret_cast<xs::TPParam*>(hT + n);
-    for (int i = 0; i < n; ++i) { hT[i] = tps[i].T; hp[i] = tps[i]; }
-    XS_HIP(hipMemcpyAsync(ws.T.p, hT, n * sizeof(double), hipMemcpyHostToDevice, s));
+    xs::TPParam* hp = reinterpret_cast<xs::TPParam*>(hT + 2 * n);
+    for (int i = 0; i < n; ++i) { hT[i] = tps[i].T; hT[n + i] = tps[i].Tv; hp[i] = tps[i]; }
+    XS_HIP(hipMemcpyAsync(ws.T.p, hT, 2 * n * sizeof(double), hipMemcpyHostToDevice, s));
     XS_HIP(hipMemcpyAsync(ws.tps.p, hp, n * sizeof(xs::TPParam), hipMemcpyHostToDevice, s));
     XS_TRY(ws.stage.record(s));
-    if (enqueue_q)
-        XS_HIP(xs::launch_partition(as<double>(p->E), as<int>(p->g), p->n_states, as<double>(ws.T), n,
-                                    as<double>(ws.qpart), xs_plan::kQBlocks, as<double>(ws.Q), as<double>(ws.dQ), s));
+    if (enqueue_q) XS_HIP(enqueue_q_of_call(p, ws, n, s));
     return XS_OK;
 }
 
@@ -859,6 +872,8 @@ xs_status xs_set_states(xs_plan* p, int64_t n, const double* E, const int32_t* g
     if (p->o.broadening == XS_BROAD_A0_JLOWER && !J) return fail(XS_ERR_ARG, "J is required for a0 broadening");
     hipStream_t s = static_cast<hipStream_t>(stream);
     p->have_lines = false;
+    p->has_vib = false;
+    p->lines_vib = false;
     p->generation++;
     xs_status st;
     if ((st = p->ensure(p->E, n * sizeof(double), "states E")) != XS_OK) return st;
@@ -922,6 +937,11 @@ xs_status xs_set_lines(xs_plan* p, int64_t n, const int32_t* upper, const int32_
     }
     if ((st = p->ensure(p->off, (size_t)(p->geo.nkeys + 1) * sizeof(int), "offsets")) != XS_OK) return st;
     if ((st = p->ensure(p->flag, sizeof(int) * 4, "flags")) != XS_OK) return st;
+    p->lines_vib = false;
+    if (p->has_vib) {
+        XS_TRY(p->ensure(p->s_evl, (size_t)std::max<int64_t>(n, 1) * sizeof(double), "line vibrational energies"));
+        XS_TRY(p->ensure(p->s_evu, (size_t)std::max<int64_t>(n, 1) * sizeof(double), "line vibrational energies"));
+    }
     XS_HIP(hipMemsetAsync(p->flag.p, 0, sizeof(int), s));
     Timer tprep(p, s, 2);
 
@@ -974,6 +994,14 @@ xs_status xs_set_lines(xs_plan* p, int64_t n, const int32_t* upper, const int32_
         XS_HIP(hipMemcpy(p->off_host.data(), p->off.p, p->off_host.size() * sizeof(int), hipMemcpyDeviceToHost));
         if ((st = build_tile_order(p)) != XS_OK) return st;
     }
+    if (p->has_vib && kept > 0) {
+        // the kept lines' vibrational energies, read through the caller's index arrays
+        // (so the call waits for them once more before returning)
+        XS_HIP(xs::launch_vib_gather(kept, as<int>(p->s_orig), n, upper, lower, p->o.index_base, as<double>(p->Ev),
+                                     p->n_states, as<double>(p->s_evl), as<double>(p->s_evu), s));
+        XS_HIP(hipStreamSynchronize(s));
+    }
+    p->lines_vib = p->has_vib;
     p->have_lines = true;
     return XS_OK;
 }
@@ -1020,8 +1048,9 @@ static xs_status run_partition(xs_plan* p, int nT, const double* T, hipStream_t 
         p->q_cap = nT;
     }
     XS_HIP(hipMemcpyAsync(p->T_dev.p, T, nT * sizeof(double), hipMemcpyHostToDevice, s));
-    XS_HIP(xs::launch_partition(as<double>(p->E), as<int>(p->g), p->n_states, as<double>(p->T_dev), nT,
-                                as<double>(p->qpart), xs_plan::kQBlocks, as<double>(p->Q), as<double>(p->dQ), s));
+    XS_HIP(xs::launch_partition(as<double>(p->E), as<int>(p->g), nullptr, p->n_states, as<double>(p->T_dev),
+                                nullptr, nT, as<double>(p->qpart), xs_plan::kQBlocks, as<double>(p->Q),
+                                as<double>(p->dQ), s));
     return XS_OK;
 }
 
@@ -1118,8 +1147,9 @@ xs_status xs_cooling_function(xs_plan* p, int64_t n_lines, const int32_t* upper,
     return XS_OK;
 }
 
-xs_status xs_cross_section(xs_plan* p, int32_t n_tp, const double* T, const double* P, void* sigma,
-                           void* stream) {
+// Cross sections of a call; Tv (vibrational temperatures of non-LTE populations) or NULL.
+static xs_status cross_section_call(xs_plan* p, int32_t n_tp, const double* T, const double* Tv, const double* P,
+                                    void* sigma, void* stream) {
     if (!p || !sigma) return fail(XS_ERR_ARG, "NULL argument");
     XS_TRY(validate_tp(n_tp, T, P));
     XS_TRY(check_vv(p, n_tp, T));
@@ -1127,7 +1157,10 @@ xs_status xs_cross_section(xs_plan* p, int32_t n_tp, const double* T, const doub
     hipStream_t s = static_cast<hipStream_t>(stream);
     Workset& ws = p->ws;
     std::vector<xs::TPParam> tps(n_tp);
-    for (int i = 0; i < n_tp; ++i) tps[i] = make_tp(p, T[i], P[i], i, T[i]);
+    for (int i = 0; i < n_tp; ++i) {
+        tps[i] = make_tp(p, T[i], P[i], i, T[i]);
+        if (Tv) tps[i].Tv = Tv[i];
+    }
     XS_TRY(build_tile_order(p));
     XS_TRY(upload_tps(p, ws, tps, s, true));
     const int B = pick_block(p, n_tp), S = pick_split(p);
@@ -1141,6 +1174,78 @@ xs_status xs_cross_section(xs_plan* p, int32_t n_tp, const double* T, const doub
         if (core_path(p) && p->n_kept > 0) XS_TRY(count_block(p, ws, tps, f, nb, s, vbase, vend));
         XS_TRY(enqueue_block(p, ws, tps, f, nb, S, false, vbase, vend, sigma, s, true));
     }
+    return XS_OK;
+}
+
+xs_status xs_cross_section(xs_plan* p, int32_t n_tp, const double* T, const double* P, void* sigma,
+                           void* stream) {
+    return cross_section_call(p, n_tp, T, nullptr, P, sigma, stream);
+}
+
+static xs_status validate_tvib(int32_t n, const double* Tv) {
+    if (!Tv) return fail(XS_ERR_ARG, "T_vib is NULL");
+    for (int i = 0; i < n; ++i)
+        if (!(Tv[i] > 0.0) || !std::isfinite(Tv[i])) return fail(XS_ERR_ARG, "T_vib must be finite and > 0");
+    return XS_OK;
+}
+
+xs_status xs_cross_section_nlte(xs_plan* p, int32_t n_tp, const double* T_rot, const double* T_vib,
+                                const double* P, void* sigma, void* stream) {
+    if (!p) return fail(XS_ERR_ARG, "plan is NULL");
+    if (n_tp > 0) XS_TRY(validate_tvib(n_tp, T_vib));
+    if (p->have_lines && !p->lines_vib)
+        return fail(XS_ERR_STATE, "the line set has no vibrational energies (xs_set_vibrational_labels, then "
+                                  "xs_set_lines)");
+    return cross_section_call(p, n_tp, T_rot, T_vib, P, sigma, stream);
+}
+
+xs_status xs_set_vibrational_labels(xs_plan* p, int32_t n_labels, const int32_t* labels, void* stream) {
+    if (!p) return fail(XS_ERR_ARG, "plan is NULL");
+    if (p->n_states <= 0) return fail(XS_ERR_STATE, "xs_set_states must come first");
+    p->have_lines = false;   // the line set must be rebuilt with (or without) E_vib
+    p->lines_vib = false;
+    p->generation++;
+    if (!labels) {
+        p->has_vib = false;
+        return XS_OK;
+    }
+    p->has_vib = false;
+    if (n_labels <= 0) return fail(XS_ERR_ARG, "n_labels must be > 0");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    XS_TRY(p->ensure(p->Ev, (size_t)p->n_states * sizeof(double), "vibrational energies"));
+    XS_TRY(p->ensure(p->vmin, (size_t)n_labels * sizeof(unsigned long long), "manifold minima"));
+    XS_TRY(p->ensure(p->flag, sizeof(int) * 4, "flags"));
+    XS_HIP(hipMemsetAsync(p->flag.p, 0, sizeof(int), s));
+    XS_HIP(xs::launch_vib_energies(as<double>(p->E), labels, p->n_states, n_labels,
+                                   as<unsigned long long>(p->vmin), as<double>(p->Ev), as<int>(p->flag), s));
+    int flag = 0;
+    XS_HIP(hipMemcpyAsync(&flag, p->flag.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    XS_HIP(hipStreamSynchronize(s));
+    if (flag & xs::kFlagIndex) return fail(XS_ERR_INDEX, "a manifold label is outside [0, n_labels)");
+    if (flag & xs::kFlagNu) return fail(XS_ERR_ARG, "non-LTE needs state energies >= 0");
+    p->has_vib = true;
+    return XS_OK;
+}
+
+xs_status xs_partition_function_nlte(xs_plan* p, int32_t nT, const double* T_rot, const double* T_vib, double* Q,
+                                     void* stream) {
+    if (!p || !T_rot || !Q) return fail(XS_ERR_ARG, "NULL argument");
+    if (nT <= 0) return fail(XS_ERR_ARG, "n_T must be > 0");
+    if (!p->has_vib) return fail(XS_ERR_STATE, "xs_set_vibrational_labels must come first");
+    XS_TRY(validate_tvib(nT, T_vib));
+    for (int i = 0; i < nT; ++i)
+        if (!(T_rot[i] > 0.0) || !std::isfinite(T_rot[i])) return fail(XS_ERR_ARG, "temperatures must be finite and > 0");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (2 * nT > p->st_cap) {
+        XS_TRY(p->ensure(p->st_T, 2 * nT * sizeof(double), "state-reduction temperatures"));
+        XS_TRY(p->ensure(p->st_part, (size_t)6 * nT * xs_plan::kQBlocks * sizeof(double), "state partial sums"));
+        p->st_cap = 2 * nT;
+    }
+    XS_HIP(hipMemcpyAsync(p->st_T.p, T_rot, nT * sizeof(double), hipMemcpyHostToDevice, s));
+    XS_HIP(hipMemcpyAsync(as<double>(p->st_T) + nT, T_vib, nT * sizeof(double), hipMemcpyHostToDevice, s));
+    XS_HIP(xs::launch_partition(as<double>(p->E), as<int>(p->g), as<double>(p->Ev), p->n_states, as<double>(p->st_T),
+                                as<double>(p->st_T) + nT, nT, as<double>(p->st_part), xs_plan::kQBlocks, Q, nullptr,
+                                s));
     return XS_OK;
 }
 
@@ -1204,8 +1309,7 @@ xs_status xs_graph_create(xs_plan* p, int32_t n_tp, const double* T, const doubl
     if (st != XS_OK) return cleanup(st);
     e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return cleanup(hip_fail(e, "hipStreamBeginCapture"));
-    e = xs::launch_partition(as<double>(p->E), as<int>(p->g), p->n_states, as<double>(ws.T), n_tp,
-                             as<double>(ws.qpart), xs_plan::kQBlocks, as<double>(ws.Q), as<double>(ws.dQ), cs);
+    e = enqueue_q_of_call(p, ws, n_tp, cs);
     if (e != hipSuccess) st = hip_fail(e, "partition function");
     for (int f = 0; f < n_tp && st == XS_OK; f += B) {
         const int nb = std::min(B, n_tp - f);
@@ -1236,11 +1340,11 @@ xs_status xs_graph_set_tp(xs_graph* g, const double* T, const double* P, void* s
     Workset& ws = g->ws;
     hipStream_t s = static_cast<hipStream_t>(stream);
     void* h = nullptr;
-    XS_TRY(ws.stage.get(n * (sizeof(double) + sizeof(xs::TPParam)), &h));
+    XS_TRY(ws.stage.get(n * (2 * sizeof(double) + sizeof(xs::TPParam)), &h));
     double* hT = static_cast<double*>(h);
-    xs::TPParam* hp = reinterpret_cast<xs::TPParam*>(hT + n);
-    for (int i = 0; i < n; ++i) { hT[i] = g->tps[i].T; hp[i] = g->tps[i]; }
-    XS_HIP(hipMemcpyAsync(ws.T.p, hT, n * sizeof(double), hipMemcpyHostToDevice, s));
+    xs::TPParam* hp = reinterpret_cast<xs::TPParam*>(hT + 2 * n);
+    for (int i = 0; i < n; ++i) { hT[i] = g->tps[i].T; hT[n + i] = g->tps[i].Tv; hp[i] = g->tps[i]; }
+    XS_HIP(hipMemcpyAsync(ws.T.p, hT, 2 * n * sizeof(double), hipMemcpyHostToDevice, s));
     XS_HIP(hipMemcpyAsync(ws.tps.p, hp, n * sizeof(xs::TPParam), hipMemcpyHostToDevice, s));
     return ws.stage.record(s);
 }
@@ -1616,6 +1720,7 @@ xs_status xs_cross_section_adjoint(xs_plan* p, double T, double P, const void* g
     if (p->o.profile != XS_VOIGT) return fail(XS_ERR_UNSUPPORTED, "the adjoint is implemented for XS_VOIGT");
     if (threshold_on(p)) return fail(XS_ERR_UNSUPPORTED, "the adjoint does not apply an intensity threshold");
     if (p->emission) return fail(XS_ERR_UNSUPPORTED, "the adjoint differentiates absorption intensities (Eq. 1)");
+    if (p->lines_vib) return fail(XS_ERR_UNSUPPORTED, "the adjoint differentiates LTE intensities");
     if ((dgref || dn) && p->o.broadening != XS_BROAD_PER_LINE)
         return fail(XS_ERR_UNSUPPORTED, "gamma_ref / n gradients need per-line broadening");
     if (!(P >= 0.0) || !std::isfinite(P)) return fail(XS_ERR_ARG, "pressure must be finite and >= 0");

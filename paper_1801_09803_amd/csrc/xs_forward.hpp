@@ -14,15 +14,29 @@ enum ProfileKind {
     kSuperLines = 9       // per-bin intensity sums (no profile)
 };
 
-// Line intensity at a (T, P) point from the stored T-independent factor
-// cA = g_up A / (8 pi c nu^2) and the lower-state energy:
+// Line intensity of sorted line g at a (T, P) point from the stored T-independent factor
+// cA = g_up A / (8 pi c nu^2), the lower-state energy and nu:
 //   absorption (Eq. 1, cm/molecule): cA exp(-c2 E_low/T) (1 - exp(-c2 nu/T)) / Q;
 //   emission (the emissivity, erg/s/sr/molecule): h c g_up A nu exp(-c2 E_up/T) / (4 pi Q),
 //   which is 2 h c^2 nu^3 cA exp(-c2 E_up/T) / Q with E_up = E_low + nu.
-__device__ __forceinline__ double line_intensity(double cA, double elow, double nu, const TPParam& tp,
-                                                 double Q) {
-    if (tp.emission)
-        return cA * ((2.0 * kH_CGS * kC_CGS * kC_CGS) * (nu * nu * nu)) * exp(-(kC2 * (elow + nu)) / tp.T) / Q;
+// With non-LTE populations (Sec. "Treating non-local thermodynamic equilibrium") the
+// Boltzmann factors become F = exp(-c2 E_vib/T_vib) exp(-c2 E_rot/T_rot): absorption
+// cA (F_low - F_up)/Q, formed as F_low (1 - F_up/F_low) through expm1 of
+// ln F_low - ln F_up = c2 [dE_vib/T_vib + dE_rot/T_rot] (negative when inverted), and
+// emission 2 h c^2 nu^3 cA F_up/Q; Q is then Q(T_vib, T_rot).
+__device__ __forceinline__ double line_intensity(const SortedLines& L, int g, double elow, double nu,
+                                                 const TPParam& tp, double Q) {
+    const double cA = L.cA[g];
+    constexpr double k2hc2 = 2.0 * kH_CGS * kC_CGS * kC_CGS;
+    if (L.evl) {
+        const double evl = L.evl[g], evu = L.evu[g];
+        const double dev = evu - evl;
+        const double ln_fl = -(kC2 * evl) / tp.Tv - (kC2 * (elow - evl)) / tp.T;
+        const double d = (kC2 * dev) / tp.Tv + (kC2 * (nu - dev)) / tp.T;
+        if (tp.emission) return cA * (k2hc2 * (nu * nu * nu)) * exp(ln_fl - d) / Q;
+        return cA * exp(ln_fl) * (-expm1(-d)) / Q;
+    }
+    if (tp.emission) return cA * (k2hc2 * (nu * nu * nu)) * exp(-(kC2 * (elow + nu)) / tp.T) / Q;
     return cA * exp(-(kC2 * elow) / tp.T) * (-expm1(-(kC2 * nu) / tp.T)) / Q;
 }
 

@@ -45,7 +45,7 @@ __device__ __forceinline__ LineSetup line_setup(const SortedLines& L, const TPPa
     LineSetup o;
     o.nu = L.nu[g];
     const double el = L.elow[g];
-    o.S = line_intensity(L.cA[g], el, o.nu, tp, Q);   // Eq. 1, or the emissivity for emission
+    o.S = line_intensity(L, g, el, o.nu, tp, Q);   // Eq. 1, or the emissivity for emission
     o.aD = o.nu * tp.beta;                                                        // Eq. 16
     o.gam = (double)L.gref[g] * exp((double)L.nexp[g] * tp.ln_T0_T) * tp.p_over_p0;  // Eq. 18
     o.kc = L.kc[g];

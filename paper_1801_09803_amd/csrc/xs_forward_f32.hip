@@ -94,7 +94,7 @@ __global__ __launch_bounds__(256) void record_kernel(const RecArgs A) {
     const double Q = A.Q[tp.iq];
     const double nu = A.L.nu[g];
     const int kc = A.L.kc[g], klo = A.L.klo[g], khi = A.L.khi[g];
-    const double S = line_intensity(A.L.cA[g], A.L.elow[g], nu, tp, Q);                      // Eq. 1
+    const double S = line_intensity(A.L, g, A.L.elow[g], nu, tp, Q);                      // Eq. 1
     const double aD = nu * tp.beta;                                                               // Eq. 16
     const double gam = (double)A.L.gref[g] * exp((double)A.L.nexp[g] * tp.ln_T0_T) * tp.p_over_p0;  // Eq. 18
     const double d = (G.nu_a + (double)kc * G.dnu) - nu;   // centre offset nu_kc - nu

@@ -343,7 +343,7 @@ __global__ __launch_bounds__(256) void superline_kernel(const FwdArgs A, int fp6
     double acc = 0.0;
     for (int l = l0; l < l1; ++l) {
         const int gs = line_of(map, l);
-        acc += line_intensity(A.L.cA[gs], A.L.elow[gs], A.L.nu[gs], tp, Q);   // Eq. 1 (or emissivity)
+        acc += line_intensity(A.L, gs, A.L.elow[gs], A.L.nu[gs], tp, Q);   // Eq. 1 (or emissivity)
     }
     const double v = acc / G.dnu;
     if (fp64) static_cast<double*>(A.sigma)[i] = v;

@@ -38,6 +38,9 @@ struct SortedLines {
     const int* klo;        // first grid index of the cut-off window (clipped)
     const int* khi;        // last grid index of the cut-off window (clipped)
     const int* orig;       // index of the line in the caller's arrays
+    // non-LTE populations: vibrational energies of the lower and upper states (NULL in LTE)
+    const double* evl;
+    const double* evu;
 };
 
 // Grid and window geometry shared by every kernel of a plan.
@@ -57,6 +60,7 @@ struct Geometry {
 // Per (T, P) scalars computed on the host (everything but Q(T), which stays on the device).
 struct TPParam {
     double T, P;
+    double Tv;            // vibrational temperature of non-LTE populations (T_rot = T)
     double c2_over_T;     // used in Eq. 1 exponents as (c2 * E) / T
     double beta;          // alpha_D / nu  (Eq. 16)
     double ln_T0_T;       // ln(T0 / T), for (T0/T)^n in Eq. 18

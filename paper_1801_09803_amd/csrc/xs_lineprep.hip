@@ -10,20 +10,28 @@
 namespace xs {
 
 // Q(T) and dQ/dT partial sums: block b of temperature blockIdx.y sums states
-// b, b + nb, ... (per thread: i = b*256 + t + k*nb*256).
+// b, b + nb, ... (per thread: i = b*256 + t + k*nb*256).  With vibrational energies Ev
+// (non-LTE, Sec. "Treating non-local thermodynamic equilibrium") the Boltzmann factor is
+// exp(-c2 Ev/T_vib) exp(-c2 (E - Ev)/T), T the rotational temperature, and the
+// derivative is taken with respect to T.
 __global__ __launch_bounds__(256) void q_partial_kernel(const double* __restrict__ E,
-                                                        const int* __restrict__ g, int64_t n,
-                                                        const double* __restrict__ T, int nb,
+                                                        const int* __restrict__ g,
+                                                        const double* __restrict__ Ev, int64_t n,
+                                                        const double* __restrict__ T,
+                                                        const double* __restrict__ Tv, int nb,
                                                         double* __restrict__ part) {
     __shared__ double lds[4];
     const double t = T[blockIdx.y];
+    const double tv = Ev ? Tv[blockIdx.y] : t;
     double q = 0.0, dq = 0.0;
     const int64_t stride = (int64_t)nb * 256;
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) {
         const double e = E[i];
-        const double bz = (double)g[i] * exp(-(kC2 * e) / t);
+        const double ev = Ev ? Ev[i] : 0.0;
+        const double er = e - ev;
+        const double bz = (double)g[i] * (Ev ? exp(-(kC2 * ev) / tv - (kC2 * er) / t) : exp(-(kC2 * e) / t));
         q += bz;
-        dq += bz * ((kC2 * e) / (t * t));
+        dq += bz * ((kC2 * er) / (t * t));
     }
     const double sq = block_sum256(q, lds);
     const double sdq = block_sum256(dq, lds);
@@ -48,9 +56,10 @@ __global__ __launch_bounds__(256) void q_final_kernel(const double* __restrict__
     }
 }
 
-hipError_t launch_partition(const double* E, const int* g, int64_t n, const double* T_dev, int nT,
-                            double* part, int nb, double* Q, double* dQ, hipStream_t s) {
-    hipLaunchKernelGGL(q_partial_kernel, dim3(nb, nT), dim3(256), 0, s, E, g, n, T_dev, nb, part);
+hipError_t launch_partition(const double* E, const int* g, const double* Ev, int64_t n, const double* T_dev,
+                            const double* Tv_dev, int nT, double* part, int nb, double* Q, double* dQ,
+                            hipStream_t s) {
+    hipLaunchKernelGGL(q_partial_kernel, dim3(nb, nT), dim3(256), 0, s, E, g, Ev, n, T_dev, Tv_dev, nb, part);
     hipLaunchKernelGGL(q_final_kernel, dim3(nT), dim3(256), 0, s, part, nb, Q, dQ);
     return hipGetLastError();
 }

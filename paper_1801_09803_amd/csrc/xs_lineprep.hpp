@@ -58,8 +58,11 @@ struct GatherArgs {
     int* orig;
 };
 
-hipError_t launch_partition(const double* E, const int* g, int64_t n, const double* T_dev, int nT,
-                            double* part, int nb, double* Q, double* dQ, hipStream_t s);
+// Q(T) and dQ/dT per temperature; with Ev (vibrational energies, or NULL for LTE) the
+// populations are non-LTE with vibrational temperatures Tv_dev[nT].
+hipError_t launch_partition(const double* E, const int* g, const double* Ev, int64_t n, const double* T_dev,
+                            const double* Tv_dev, int nT, double* part, int nb, double* Q, double* dQ,
+                            hipStream_t s);
 hipError_t launch_prep(const PrepArgs& a, hipStream_t s);
 int64_t radix_hist_len(int64_t n);
 int radix_passes(uint32_t max_key);

@@ -114,9 +114,71 @@ __global__ __launch_bounds__(256) void state_final_kernel(const double* __restri
     }
 }
 
+// Manifold minima: the bit patterns of non-negative doubles order as the values do, so
+// an unsigned 64-bit atomic minimum finds the lowest energy (order-independent).
+__global__ __launch_bounds__(256) void vib_min_kernel(const double* __restrict__ E, const int* __restrict__ lab,
+                                                      int64_t n, int n_labels, unsigned long long* vmin,
+                                                      int* flag) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const int l = lab[i];
+    const double e = E[i];
+    if (l < 0 || l >= n_labels) { atomicOr(flag, kFlagIndex); return; }
+    if (!(e >= 0.0)) { atomicOr(flag, kFlagNu); return; }
+    atomicMin(vmin + l, (unsigned long long)__double_as_longlong(e));
+}
+
+__global__ __launch_bounds__(256) void vib_assign_kernel(const int* __restrict__ lab, int64_t n, int n_labels,
+                                                         const unsigned long long* __restrict__ vmin,
+                                                         double* __restrict__ Ev) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const int l = lab[i];
+    Ev[i] = (l >= 0 && l < n_labels) ? __longlong_as_double((long long)vmin[l]) : 0.0;
+}
+
+__global__ __launch_bounds__(256) void u64_fill_kernel(unsigned long long* x, int64_t n, unsigned long long v) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) x[i] = v;
+}
+
+__global__ __launch_bounds__(256) void vib_gather_kernel(int64_t n, const int* __restrict__ orig, int64_t n_lines,
+                                                         const int* __restrict__ upper,
+                                                         const int* __restrict__ lower, int base,
+                                                         const double* __restrict__ Ev, int64_t n_states,
+                                                         double* __restrict__ evl, double* __restrict__ evu) {
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p >= n) return;
+    const int o = orig[p];
+    if (o < 0 || o >= n_lines) { evl[p] = 0.0; evu[p] = 0.0; return; }
+    const int up = upper[o] - base, lo = lower[o] - base;
+    evl[p] = (lo >= 0 && lo < n_states) ? Ev[lo] : 0.0;
+    evu[p] = (up >= 0 && up < n_states) ? Ev[up] : 0.0;
+}
+
 dim3 grid_of(int64_t n) { return dim3((unsigned)((n + 255) / 256)); }
 
 }  // namespace
+
+hipError_t launch_vib_energies(const double* E, const int* labels, int64_t n, int n_labels,
+                               unsigned long long* vmin, double* Ev, int* flag, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(u64_fill_kernel, grid_of(n_labels), dim3(256), 0, s, vmin, (int64_t)n_labels,
+                       0x7FF0000000000000ull);   // +inf
+    hipLaunchKernelGGL(vib_min_kernel, grid_of(n), dim3(256), 0, s, E, labels, n, n_labels, vmin, flag);
+    hipLaunchKernelGGL(vib_assign_kernel, grid_of(n), dim3(256), 0, s, labels, n, n_labels,
+                       (const unsigned long long*)vmin, Ev);
+    return hipGetLastError();
+}
+
+hipError_t launch_vib_gather(int64_t n, const int* orig, int64_t n_lines, const int* upper, const int* lower,
+                             int index_base, const double* Ev, int64_t n_states, double* evl, double* evu,
+                             hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(vib_gather_kernel, grid_of(n), dim3(256), 0, s, n, orig, n_lines, upper, lower, index_base,
+                       Ev, n_states, evl, evu);
+    return hipGetLastError();
+}
 
 hipError_t launch_fill(double* x, int64_t n, double v, hipStream_t s) {
     if (n <= 0) return hipSuccess;

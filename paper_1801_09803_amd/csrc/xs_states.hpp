@@ -36,4 +36,15 @@ hipError_t launch_moments(const double* E, const int* g, int64_t n, const double
 hipError_t launch_cooling(const double* E, const int* g, const double* power, int64_t n, const double* T_dev,
                           int nT, double* part, int nb, double* W, hipStream_t s);
 
+// Non-LTE (Sec. "Treating non-local thermodynamic equilibrium"): E_vib of each state is
+// the lowest energy among the states with its manifold label (labels in [0, n_labels),
+// energies >= 0; otherwise kFlagIndex / kFlagNu and E_vib = 0).  vmin: n_labels words.
+hipError_t launch_vib_energies(const double* E, const int* labels, int64_t n, int n_labels,
+                               unsigned long long* vmin, double* Ev, int* flag, hipStream_t s);
+// Per kept sorted line p < n: evl[p] / evu[p] = E_vib of its lower / upper state, through
+// the caller's index arrays (n_lines entries) at orig[p] (0 for an index out of range).
+hipError_t launch_vib_gather(int64_t n, const int* orig, int64_t n_lines, const int* upper, const int* lower,
+                             int index_base, const double* Ev, int64_t n_states, double* evl, double* evu,
+                             hipStream_t s);
+
 }  // namespace xs

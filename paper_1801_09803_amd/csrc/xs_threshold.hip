@@ -16,7 +16,7 @@ namespace {
 __device__ __forceinline__ bool keep_line(const CullArgs& A, const TPParam& tp, double Q, int g) {
     const double nu = A.L.nu[g];
     // the intensity the cross section sums: Eq. 1, or the emissivity for emission
-    const double S = line_intensity(A.L.cA[g], A.L.elow[g], nu, tp, Q);
+    const double S = line_intensity(A.L, g, A.L.elow[g], nu, tp, Q);
     double cut = A.i_crit;
     if (A.mode == 2 && nu <= A.nu_crit) cut = A.i_crit * (nu / A.nu_crit) * tanh(kC2 * nu / (2.0 * tp.T));
     return S >= cut;

@@ -113,6 +113,9 @@ def test_state_reduction_and_emission_calls_reject_null_plans_on_host():
     assert lib.xs_partition_moments(None, 1, T, None, None, None, None, None) == 1
     assert lib.xs_lifetimes(None, 0, None, None, None, None) == 1
     assert lib.xs_cooling_function(None, 0, None, None, None, 1, T, None, None) == 1
+    assert lib.xs_set_vibrational_labels(None, 1, None, None) == 1
+    assert lib.xs_cross_section_nlte(None, 1, T, T, T, None, None) == 1
+    assert lib.xs_partition_function_nlte(None, 1, T, T, None, None) == 1
 
 
 def test_binding_handles_skip_the_library_in_forked_processes():
