@@ -479,6 +479,22 @@ def emission_leg(cfg, d, temps, pressures, tile, n_kept, stream, log):
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) / reps
 
+    # non-LTE populations: manifold labels (2000 cm^-1 energy bands of the synthetic states),
+    # the line set rebuilt with its vibrational energies, then one call over both points with
+    # T_vib = 1000 K
+    plan.set_intensity_kind("absorption")
+    plan.set_vibrational_labels(synth.make_vibrational_labels(d["E"]))
+    plan.set_lines(d["upper"], d["lower"], d["A"], d["gamma_ref"], d["n_exp"])
+    t_vib = [1000.0] * len(temps)
+    plan.cross_section_nlte(temps, t_vib, pressures, out=out)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        plan.cross_section_nlte(temps, t_vib, pressures, out=out)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_nlte = e0.elapsed_time(e1) / 1e3 / reps
+    plan.set_vibrational_labels(None)
     t_tau = wall(lambda: plan.lifetimes(d["upper"], d["A"]))
     t_w = wall(lambda: plan.cooling_function(d["upper"], d["lower"], d["A"], Ts))
     t_m = wall(lambda: plan.partition_moments(Ts))
@@ -487,10 +503,12 @@ def emission_leg(cfg, d, temps, pressures, tile, n_kept, stream, log):
     # energies (24 B per transition, the energies mostly from cache)
     tau_bytes = 8.0 * n_lines + 24.0 * n_states
     del plan, out
-    log(f"emission: {t_em * 1e3:.1f} ms per call; lifetimes {t_tau * 1e3:.2f} ms, cooling (27 T) "
+    log(f"emission: {t_em * 1e3:.1f} ms per call; non-LTE {t_nlte * 1e3:.1f} ms per call; lifetimes {t_tau * 1e3:.2f} ms, cooling (27 T) "
         f"{t_w * 1e3:.2f} ms, moments (27 T) {t_m * 1e3:.3f} ms")
     return {"emission_call_ms": t_em * 1e3, "emission_line_profiles_per_s": n_kept * len(temps) / t_em,
             "emission_tile_kernel_ms_per_tp": kt["forward_ms"] / kt["forward_tp"],
+            "nlte_call_ms": t_nlte * 1e3, "nlte_line_profiles_per_s": n_kept * len(temps) / t_nlte,
+            "nlte_T_vib": t_vib,
             "lifetimes_ms": t_tau * 1e3, "lifetimes_transitions_per_s": n_lines / t_tau,
             "lifetimes_algorithmic_GBps": tau_bytes / t_tau / 1e9,
             "cooling_27T_ms": t_w * 1e3, "cooling_transitions_per_s": n_lines / t_w,
