@@ -550,6 +550,7 @@ xs::CoreArgs core_args(xs_plan* p, Workset& ws, int it, int row) {
     c.tp = as<xs::TPParam>(ws.tps) + it;
     c.Q = as<double>(ws.Q);
     c.n_lines = (int)p->n_kept;
+    c.kept_pos = threshold_on(p) ? as<unsigned>(ws.th_pos) + (int64_t)row * (n + 1) : nullptr;
     c.tab = as<xs::Tables>(p->tab_dev);
     c.rc = as<int>(ws.rc) + row * n;
     c.cnt = as<int>(ws.cnt) + row * n;
@@ -680,28 +681,34 @@ xs_status read_totals(Workset& ws, int nb, hipStream_t s, std::vector<unsigned l
 // Enqueue only: no allocation and no synchronisation (graph-capturable).
 // Per-(T, P) pre-passes of the call's point `it` into row `row`: Vectorized Voigt factors,
 // then (FP32) the Voigt core values and the line records.  Enqueue only.
+// Intensity threshold: the kept lines of (T, P) point `it` compacted into row `row`.
+xs_status enqueue_cull(xs_plan* p, Workset& ws, int it, int row, hipStream_t s) {
+    xs::CullArgs c{};
+    const int64_t n = ws.row_stride;
+    c.L = sorted_lines(p);
+    c.G = p->geo;
+    c.tp = as<xs::TPParam>(ws.tps) + it;
+    c.Q = as<double>(ws.Q);
+    c.n_lines = (int)p->n_kept;
+    c.mode = p->th_mode;
+    c.i_crit = p->th_icrit;
+    c.nu_crit = p->th_nucrit;
+    c.bsum = as<unsigned long long>(ws.th_bsum) + (int64_t)row * xs::core_blocks(n);
+    c.scan_tmp = as<unsigned long long>(ws.th_tmp) + (int64_t)row * kScanTmp;
+    c.pos = as<unsigned>(ws.th_pos) + (int64_t)row * (n + 1);
+    c.map = as<int>(ws.th_map) + (int64_t)row * n;
+    c.off = as<int>(p->off);
+    c.offs = as<int>(ws.th_offs) + (int64_t)row * ((int64_t)p->geo.nkeys + 1);
+    XS_HIP(xs::launch_cull(c, s));
+    return XS_OK;
+}
+
+// Pre-passes of (T, P) point `it` in row `row`.  count: the core counts are not computed
+// yet (graph capture); otherwise count_block has run the cull and the counts.
 xs_status enqueue_prepass(xs_plan* p, Workset& ws, int it, int row, bool count, const std::vector<long long>& vbase,
                           const std::vector<long long>& vend, hipStream_t s) {
     if (p->n_kept <= 0) return XS_OK;
-    if (threshold_on(p)) {
-        xs::CullArgs c{};
-        const int64_t n = ws.row_stride;
-        c.L = sorted_lines(p);
-        c.G = p->geo;
-        c.tp = as<xs::TPParam>(ws.tps) + it;
-        c.Q = as<double>(ws.Q);
-        c.n_lines = (int)p->n_kept;
-        c.mode = p->th_mode;
-        c.i_crit = p->th_icrit;
-        c.nu_crit = p->th_nucrit;
-        c.bsum = as<unsigned long long>(ws.th_bsum) + (int64_t)row * xs::core_blocks(n);
-        c.scan_tmp = as<unsigned long long>(ws.th_tmp) + (int64_t)row * kScanTmp;
-        c.pos = as<unsigned>(ws.th_pos) + (int64_t)row * (n + 1);
-        c.map = as<int>(ws.th_map) + (int64_t)row * n;
-        c.off = as<int>(p->off);
-        c.offs = as<int>(ws.th_offs) + (int64_t)row * ((int64_t)p->geo.nkeys + 1);
-        XS_HIP(xs::launch_cull(c, s));
-    }
+    if (threshold_on(p) && (count || !core_path(p))) XS_TRY(enqueue_cull(p, ws, it, row, s));
     if (vv_needed(p)) {
         xs::VVArgs v{};
         v.L = sorted_lines(p);
@@ -764,6 +771,7 @@ xs_status count_block(xs_plan* p, Workset& ws, const std::vector<xs::TPParam>& t
     for (int t = 0; t < nb; ++t) {
         xs::CoreArgs c = core_args(p, ws, f + t, t);
         Timer tc(p, s, 1);
+        if (threshold_on(p)) XS_TRY(enqueue_cull(p, ws, f + t, t, s));   // counts cover kept lines only
         XS_HIP(xs::launch_core_count(c, s));
         tc.stop();
     }

@@ -4,7 +4,8 @@
 // together), and stored as f32 values a * Re w(z) for the tile kernel to add.
 //
 // core_count: per sorted line, the core radius r (grid steps from kc, conservative)
-//   and the number of window points in [kc - r, kc + r]; per-256-line totals.
+//   and the number of window points in [kc - r, kc + r]; per-256-line totals.  Under an
+//   intensity threshold only kept lines count (the cull runs first).
 // (exclusive scan of the totals)
 // core_eval: per 256 lines, block-local offsets, then the block's points in passes of
 //   256, each thread finding its line by binary search over the block prefix.
@@ -65,9 +66,13 @@ __global__ __launch_bounds__(256) void core_count_kernel(const CoreArgs A) {
     const TPParam tp = *A.tp;
     unsigned long long c = 0;
     if (g < A.n_lines) {
-        const CoreLine cl = core_line(A, tp, g, A.Q[tp.iq]);
-        c = cl.hi >= cl.lo ? (unsigned long long)(cl.hi - cl.lo + 1) : 0ull;
-        A.rc[g] = cl.r;
+        if (!A.kept_pos || A.kept_pos[g + 1] > A.kept_pos[g]) {
+            const CoreLine cl = core_line(A, tp, g, A.Q[tp.iq]);
+            c = cl.hi >= cl.lo ? (unsigned long long)(cl.hi - cl.lo + 1) : 0ull;
+            A.rc[g] = cl.r;
+        } else {
+            A.rc[g] = -1;   // below the intensity threshold: no record reads its core values
+        }
         A.cnt[g] = (int)c;
     }
     unsigned long long tot;

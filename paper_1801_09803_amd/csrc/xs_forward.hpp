@@ -185,6 +185,8 @@ struct CoreArgs {
     unsigned long long* scan_tmp;    // scratch for the block-total scan (>= 4096 + 16 entries);
                                      // scan_tmp[4096] receives the total count
     const double2* vv;               // Vectorized Voigt intensity factors (.y), or NULL
+    const unsigned* kept_pos;        // intensity threshold: compacted positions [n_lines + 1] (line g
+                                     // is kept iff kept_pos[g + 1] > kept_pos[g]), or NULL
 };
 
 hipError_t launch_core_count(const CoreArgs& a, hipStream_t s);
