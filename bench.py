@@ -29,7 +29,47 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-FLOPS_PER_EVAL = 12          # far-wing rational: j add, 4 fma, rcp, accumulate fma (FMA = 2)
+# Tile-kernel flops per grid-point evaluation by the zone the point falls in, as the
+# kernel's formulas are written (FMA = 2, reciprocal = 1): one pole at |x| >= 1000 (x, den,
+# accumulate FMA + rcp) 7; 2-node rule at |z| >= 40 (x, p, den, num, accumulate FMA + rcp)
+# 11; 4-node rule at 8 <= |z| < 40 (x + two node pairs of three FMA and a rcp + two
+# accumulate FMA) 20; a core value precomputed by the FP64 pre-pass, added: 1.
+ZONE_FLOPS = {"one_pole": 7, "two_node": 11, "four_node": 20, "core": 1}
+
+
+def zone_counts(cfg, d, T, P, chunk=1 << 24):
+    """Window points of every line per zone at (T, P) (x = sqrt(ln2)(nu_k - nu)/alpha_D,
+    |z|^2 = x^2 + y^2, y = sqrt(ln2) gamma/alpha_D), counted from index ranges."""
+    import torch
+    kB, amu, c_si, ln2 = 1.380649e-23, 1.66053906660e-27, 299792458.0, math.log(2.0)
+    beta = math.sqrt(2.0 * kB * T * ln2 / (cfg.mass_amu * amu)) / c_si
+    E = d["E"]
+    tot = {k: 0 for k in ZONE_FLOPS}
+    n = d["upper"].numel()
+    for a in range(0, n, chunk):
+        b = min(n, a + chunk)
+        nu = E[d["upper"][a:b].long()] - E[d["lower"][a:b].long()]
+        gam = d["gamma_ref"][a:b].double() * torch.pow(296.0 / T, d["n_exp"][a:b].double()) * P
+        s = math.sqrt(ln2) / (beta * nu)
+        y2 = (gam * s) ** 2
+        klo = torch.clamp(torch.ceil(((nu - cfg.cutoff) - cfg.nu_a) / cfg.dnu), min=0)
+        khi = torch.clamp(torch.floor(((nu + cfg.cutoff) - cfg.nu_a) / cfg.dnu), max=cfg.n_points - 1)
+        n_all = torch.clamp(khi - klo + 1, min=0)
+
+        def inside(X):   # points of the window with |x| < X
+            R = X / s
+            lo = torch.maximum(torch.floor((nu - R - cfg.nu_a) / cfg.dnu) + 1, klo)
+            hi = torch.minimum(torch.ceil((nu + R - cfg.nu_a) / cfg.dnu) - 1, khi)
+            return torch.where(X > 0, torch.clamp(hi - lo + 1, min=0), torch.zeros_like(X))
+
+        n_x = inside(torch.full_like(nu, 1000.0))
+        n_40 = inside(torch.sqrt(torch.clamp(1600.0 - y2, min=0.0)))
+        n_8 = inside(torch.sqrt(torch.clamp(64.0 - y2, min=0.0)))
+        tot["one_pole"] += int((n_all - n_x).sum().item())
+        tot["two_node"] += int((n_x - n_40).sum().item())
+        tot["four_node"] += int((n_40 - n_8).sum().item())
+        tot["core"] += int(n_8.sum().item())
+    return tot
 
 # HBM traffic of the dominant kernel from two rocprofv3 --pmc runs of this script with
 # the tile configuration fixed (4 waves, 2 slices, 32 shares, one (T, P) per dispatch):
@@ -39,9 +79,9 @@ FLOPS_PER_EVAL = 12          # far-wing rational: j add, 4 fma, rcp, accumulate 
 # Valid only for the kernel sources they were taken with (hash below).
 TRAFFIC = {
     "kernel_sources": ['xs_forward_f32.hip', 'xs_forward_common.hpp', 'xs_voigt.hpp', 'xs_forward.hpp', 'xs_internal.hpp'],
-    "sha256": "a218233753811f491e2bd4db7d8863b2662bfc578c66192baed52de40eca91c1",
-    "fetch_kib": [32144474.2, 36812058.5],
-    "write_kib": [251283.7, 251631.7],
+    "sha256": "de797ef27da9e0176e90e9979802b1186f75145b18d38bfd6e6c1bc733833453",
+    "fetch_kib": [32054736.1, 36644856.7],
+    "write_kib": [251287.7, 251657.2],
     "fetch_scale": 2.0,
     "write_scale": 1.0,
 }
@@ -226,7 +266,13 @@ def main():
     avg_launch_s = kt["forward_ms"] / kt["forward_launches"] / 1e3
     tp_per_launch = kt["forward_tp"] / kt["forward_launches"]
     fwd_s_per_tp = kt["forward_ms"] / kt["forward_tp"] / 1e3
-    achieved = FLOPS_PER_EVAL * evals_per_tp * tp_per_launch / avg_launch_s / 1e12
+    # region-weighted algorithmic flops of the timed launches (every step covers all (T, P))
+    zones = [zone_counts(cfg, d, T, P) for T, P in zip(temps, pressures)]
+    flops_step = sum(sum(ZONE_FLOPS[k] * z[k] for k in ZONE_FLOPS) for z in zones)
+    launches_per_step = kt["forward_launches"] / args.steps
+    flops_per_launch = flops_step / launches_per_step
+    achieved = flops_per_launch / avg_launch_s / 1e12
+    flops_per_eval = flops_step / (evals_per_tp * len(temps))
     tile = plan.tile_config()
 
     result = {
@@ -265,8 +311,10 @@ def main():
             "kernel": "fwd_f32_kernel<Voigt> (tile kernel, one launch per block of (T,P))",
             "avg_launch_ms": avg_launch_s * 1e3,
             "tp_per_launch": tp_per_launch,
-            "algorithmic_flops_per_launch": FLOPS_PER_EVAL * evals_per_tp * tp_per_launch,
-            "flops_per_eval": FLOPS_PER_EVAL,
+            "algorithmic_flops_per_launch": flops_per_launch,
+            "flops_per_eval": flops_per_eval,
+            "zone_flops": ZONE_FLOPS,
+            "zone_points_per_tp": {f"T={T}": z for T, z in zip(temps, zones)},
             "frac_of_unpacked_fp32": achieved / PEAK_FP32_UNPACKED,
         },
         "step_breakdown_ms": {

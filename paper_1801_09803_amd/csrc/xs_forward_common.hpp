@@ -82,5 +82,8 @@ __device__ __forceinline__ double erf_diff64(double a, double b) {
 // double-precision core pre-pass.
 constexpr double kCoreR2 = 64.0;
 constexpr double kMidR2 = 1600.0;
+// Far-wing radius of the FP32 Voigt path: wing-only runs whose points all lie at
+// |x| >= kFarX use the one-pole form (relative error <= 1/kFarX^2 = 1e-6).
+constexpr double kFarX = 1000.0;
 
 }  // namespace xs

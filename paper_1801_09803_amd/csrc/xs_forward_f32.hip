@@ -405,6 +405,18 @@ __device__ __forceinline__ void wing_run(const float* rec, const float* sb0, flo
                 const float num = __builtin_fmaf(pp, amp, bb);
                 part[p] = __builtin_fmaf(num, __builtin_amdgcn_rcpf(den), part[p]);
             }
+        } else if constexpr (KIND == 3) {
+            // Voigt far wing, |x| >= kFarX: one pole, amp / (x^2 + y^2 - 1/2) in the scaled
+            // variables (C0 = (y^2 - 1/2) sc^2, AMP = a y sc^2 / sqrt(pi)); against
+            // Re w(z) = (y/sqrt(pi)) |z|^-2 (1 + (3x^2 - y^2)/(2|z|^4) + ...) its relative
+            // error is (x^2 - y^2)/|z|^4 + O(|z|^-4), at most 1/kFarX^2
+            const float4 q = *reinterpret_cast<const float4*>(r);
+            static_assert(L::H == 0 && L::C0 == 1 && L::AMP == 3, "layout");
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                const float x = __builtin_fmaf(jd[p], q.x, xa);
+                part[p] = __builtin_fmaf(q.w, __builtin_amdgcn_rcpf(__builtin_fmaf(x, x, q.y)), part[p]);
+            }
         } else if constexpr (KIND == 1) {
             const float4 q = *reinterpret_cast<const float4*>(r);
             const float h = q.x, amp = q.w;
@@ -429,8 +441,9 @@ __device__ __forceinline__ void wing_run(const float* rec, const float* sb0, flo
 // Voigt and Lorentz profiles one run on each side, [lo2, hi2) and [lo4, hi4); for the
 // Vectorized Voigt the runs outside R ([lo2, ha) left, [hd, hi4) right) take the
 // reference wing and the runs inside R ([hb, hi2) left, [lo4, hc) right) the 2-node rule.
-// Wing-only runs of one wavefront.  Voigt and Lorentz: [lo2, hi2) left of the wave and
-// [lo4, hi4) right of it; Vectorized Voigt: [lo2, ha) beyond R and [hb, hi2) inside R on
+// Wing-only runs of one wavefront.  Lorentz: [lo2, hi2) left of the wave and [lo4, hi4)
+// right of it; Voigt: the same runs, each split where the lines' far-wing radius kFarX
+// crosses the wave (one pole beyond it, the 2-node rule inside); Vectorized Voigt: [lo2, ha) beyond R and [hb, hi2) inside R on
 // the left, [lo4, hc) inside R and [hd, hi4) beyond R on the right.  IA: anchor word of
 // this wavefront, or -1 to rebuild anchors from (t0 - kc) + kl (left, kl = w0 - t0) or
 // + kr (right, kr = w1 - t0).
@@ -443,9 +456,16 @@ __device__ __forceinline__ void wing_runs(const float* rec, const float* sb0, fl
         wing_run<PROF, 0, P, RS, IA>(rec, sb0, kl, bs, hb, hi2, jlo_w, part);
         wing_run<PROF, 0, P, RS, IA>(rec, sb0, kr, bs, lo4, hc, jhi_w, part);
         wing_run<PROF, 2, P, RS, IA>(rec, sb0, kr, bs, hd, hi4, jhi_w, part);
+    } else if constexpr (PROF == kVoigt) {
+        // [lo2, ha) and [hd, hi4): every point of the wave at |x| >= kFarX (one pole);
+        // [hb, hi2) and [lo4, hc): the 2-node rule
+        wing_run<PROF, 3, P, RS, IA>(rec, sb0, kl, bs, lo2, ha, jlo_w, part);
+        wing_run<PROF, 0, P, RS, IA>(rec, sb0, kl, bs, hb, hi2, jlo_w, part);
+        wing_run<PROF, 0, P, RS, IA>(rec, sb0, kr, bs, lo4, hc, jhi_w, part);
+        wing_run<PROF, 3, P, RS, IA>(rec, sb0, kr, bs, hd, hi4, jhi_w, part);
     } else {
-        wing_run<PROF, PROF == kVoigt ? 0 : 1, P, RS, IA>(rec, sb0, kl, bs, lo2, hi2, jlo_w, part);
-        wing_run<PROF, PROF == kVoigt ? 0 : 1, P, RS, IA>(rec, sb0, kr, bs, lo4, hi4, jhi_w, part);
+        wing_run<PROF, 1, P, RS, IA>(rec, sb0, kl, bs, lo2, hi2, jlo_w, part);
+        wing_run<PROF, 1, P, RS, IA>(rec, sb0, kr, bs, lo4, hi4, jhi_w, part);
     }
 }
 
@@ -545,6 +565,22 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
         s3 = off_at(off, (int64_t)w1 + rm + 1, G);
         s4 = off_at(off, (int64_t)w0 + G.hmin + 1, G);
         s5 = off_at(off, (int64_t)w1 + G.hmax + 1, G);
+        if (PROF == kVoigt) { ha = hb = s1; hc = hd = s4; }   // no one-pole lines unless bounded
+        if (PROF == kVoigt && tp.rm_scale > 0.0) {
+            // wing-only runs split at the far-wing radius: every point of the wave lies at
+            // |x| >= kFarX from a line with |kc - k| > rf for all k of the wave, where
+            // rf >= kFarX alpha_D / (sqrt(ln2) dnu) + 1/2 over the wavenumbers of the lines
+            // the runs can hold (rm_scale is that radius per cm^-1 at the 2-node bound 40)
+            const double nlo = G.nu_a + ((double)w0 - G.hmax - 1) * G.dnu;
+            const double nhi = G.nu_a + ((double)w1 + G.hmax + 1) * G.dnu;
+            const double rfd = ceil(tp.rm_scale * (kFarX / 40.0) * fmax(fabs(nlo), fabs(nhi))) + 2.0;
+            const int64_t rf = rfd < 1.0e9 ? (int64_t)rfd : 1000000000;
+            const int64_t l0 = (int64_t)w1 - G.hmin, l1 = (int64_t)w0 - rm;
+            const int64_t r0 = (int64_t)w1 + rm + 1, r1 = (int64_t)w0 + G.hmin + 1;
+            auto cl = [](int64_t v, int64_t lo, int64_t hi) { return v < lo ? lo : (v > hi ? hi : v); };
+            ha = hb = off_at(off, cl((int64_t)w0 - rf, l0, l1), G);
+            hc = hd = off_at(off, cl((int64_t)w1 + rf + 1, r0, r1), G);
+        }
         if (PROF == kVVoigt) {
             // wing-only runs split where R can cross the wave: left lines with kc < w0 - rvmax
             // see only points beyond R, those with kc >= w1 - rvmin only points inside R
@@ -721,8 +757,8 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
                     {
                         const int lo2 = cs > s1 ? cs : s1, hi2 = ce < s2 ? ce : s2;
                         const int lo4 = cs > s3 ? cs : s3, hi4 = ce < s4 ? ce : s4;
-                        // Vectorized Voigt pieces: [lo2, xa) beyond R, [xb, hi2) inside R (left);
-                        // [lo4, xc) inside R, [xd, hi4) beyond R (right)
+                        // pieces: [lo2, xa) and [xd, hi4) beyond R (Vectorized Voigt) or beyond
+                        // the far-wing radius (Voigt), [xb, hi2) and [lo4, xc) inside
                         const int xa = ce < ha ? ce : ha, xb = cs > hb ? cs : hb;
                         const int xc = ce < hc ? ce : hc, xd = cs > hd ? cs : hd;
                         const float kl = (float)(wave * WW), kr = (float)(wave * WW + WW - 1);
