@@ -156,6 +156,7 @@ def main():
     ap.add_argument("--no-vv", action="store_true", help="skip the Vectorized Voigt leg")
     ap.add_argument("--no-binned", action="store_true", help="skip the binned-profile / super-line leg")
     ap.add_argument("--no-threshold", action="store_true", help="skip the intensity-threshold leg")
+    ap.add_argument("--no-c3", action="store_true", help="skip the 270-point (T, P) grid leg")
     ap.add_argument("--no-emission", action="store_true",
                     help="skip the emission cross-section and state-reduction leg")
     ap.add_argument("--stream-chunks", type=int, default=4)
@@ -376,6 +377,8 @@ def main():
         result["binned_profiles"] = binned_leg(cfg, d, temps, pressures, n_kept, stream, log)
     if not args.no_threshold:
         result["intensity_threshold"] = threshold_leg(cfg, d, temps, pressures, tile, n_kept, stream, log)
+    if not args.no_c3 and cfg.name == "C2":
+        result["c3_grid"] = c3_leg(synth.CONFIGS["C3"], d, tile, n_kept, stream, log)
     if not args.no_emission:
         result["emission_and_state_reductions"] = emission_leg(cfg, d, temps, pressures, tile, n_kept, stream,
                                                                 log)
@@ -486,6 +489,67 @@ def threshold_leg(cfg, d, temps, pressures, tile, n_kept, stream, log):
             "kept_share_per_tp": shares,
             "note": "throughput counts every line of the list (kept or dropped), as the headline does; "
                     "call = Q(T) + threshold compaction + pre-passes + tile kernel"}
+
+
+def c3_leg(cfg3, d, tile, n_kept, stream, log):
+    """The C3 grid on C2's list: all 27 x 10 (T, P) cross sections from one batched FP32
+    call (Q, pre-passes and tile kernels, in the headline's tile shape), against the plain
+    FP64 path timed on three of the points (one call each) and scaled to 270."""
+    import torch
+    from paper_1801_09803_amd import Plan
+    Ts = [T for T in cfg3.temperatures for _ in cfg3.pressures]
+    Ps = [P for _ in cfg3.temperatures for P in cfg3.pressures]
+    plan = Plan(cfg3.nu_a, cfg3.nu_b, cfg3.n_points, cfg3.mass_amu, cutoff=cfg3.cutoff, profile="voigt")
+    plan.set_states(d["E"], d["g"], d["J"])
+    plan.set_lines(d["upper"], d["lower"], d["A"], d["gamma_ref"], d["n_exp"])
+    plan.set_tile_config(tile["waves"], tile["slices"], tile["last_split"], 0)
+    out = torch.empty((len(Ts), cfg3.n_points), dtype=torch.float32, device="cuda")
+    log(f"C3: {len(Ts)} (T, P) in one call")
+    plan.cross_section(Ts[:4], Ps[:4], out=out[:4])
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    plan.set_timing(True)
+    e0.record(stream)
+    plan.cross_section(Ts, Ps, out=out)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    kt = plan.kernel_times()
+    plan.set_timing(False)
+    t = e0.elapsed_time(e1) / 1e3
+    del plan
+    # plain FP64 path: one call per (T, P) on three points of the grid
+    p64 = Plan(cfg3.nu_a, cfg3.nu_b, cfg3.n_points, cfg3.mass_amu, cutoff=cfg3.cutoff, profile="voigt",
+               precision="fp64")
+    p64.set_states(d["E"], d["g"], d["J"])
+    p64.set_lines(d["upper"], d["lower"], d["A"], d["gamma_ref"], d["n_exp"])
+    o64 = torch.empty((1, cfg3.n_points), dtype=torch.float64, device="cuda")
+    pick = [0, 135, 269]
+    p64.cross_section([Ts[0]], [Ps[0]], out=o64)
+    torch.cuda.synchronize()
+    t64, dev64 = 0.0, 0.0
+    for i in pick:
+        e0.record(stream)
+        p64.cross_section([Ts[i]], [Ps[i]], out=o64)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t64 += e0.elapsed_time(e1) / 1e3
+        ref, got = o64[0], out[i].double()
+        m = ref > 1e-6 * ref.max()
+        dev64 = max(dev64, float(((got - ref).abs()[m] / ref[m]).max().item()))
+    del p64, o64, out
+    t64_all = t64 / len(pick) * len(Ts)
+    log(f"C3: {t:.2f} s for 270 (T, P) ({n_kept * len(Ts) / t:.3e} line-profiles/s); plain FP64 "
+        f"~{t64_all:.0f} s (from 3 points)")
+    return {"n_tp": len(Ts), "call_s": t, "line_profiles_per_s": n_kept * len(Ts) / t,
+            "tile_kernel_ms_per_tp": kt["forward_ms"] / kt["forward_tp"],
+            "pre_passes_ms_per_tp": kt["core_ms"] / len(Ts),
+            "tp_block": 0,
+            "fp64_plain_s_per_tp": t64 / len(pick), "fp64_plain_s_extrapolated": t64_all,
+            "fp32_batched_vs_fp64_plain_speedup": t64_all / t,
+            "fp32_vs_fp64_max_rel_at_sampled_tp": dev64,
+            "note": "C3 = C2's 1e8 lines at 27 T (100-3000 K, log) x 10 P (1e-5-100 bar, log); one FP32 "
+                    "call over all 270 (Q, pre-passes, tile kernels; line preparation excluded); the FP64 "
+                    "plain time is 3 single-(T,P) calls scaled to 270"}
 
 
 def emission_leg(cfg, d, temps, pressures, tile, n_kept, stream, log):

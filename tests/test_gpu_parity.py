@@ -247,3 +247,23 @@ def test_gh_binned_pure_doppler_limit(precision):
     ls = oracle_lineset(h, cfg, 1000.0, 0.0)
     ref = O.cross_section(ls, cfg.nu_a, cfg.nu_b, cfg.n_points, cfg.cutoff, profile="gh_binned", workers=1)
     assert_parity(got, ref, TOL32 if precision == "fp32" else TOL64, what=f"gh_binned P=0 {precision}")
+
+
+@pytest.mark.parametrize("T", [1000.0, 3000.0])
+def test_far_wing_zone_accuracy(T):
+    # sparse lines on a fine grid: between lines the cross section is made of far wings,
+    # most of them in the one-pole zone (|x| >= 1000, relative error <= 1e-6) of the FP32
+    # path; the whole result stays within a few 1e-6 of the oracle
+    cfg = synth.WorkloadConfig("far", 77, 2000, 300, 34.0, 2100.0, 0.0, 2000.0, 200001, (T,), (1.0,))
+    d = device_linelist(cfg)
+    h = host(d)
+    got = _run(make_plan(cfg, "fp32"), d, [T], [1.0])[0]
+    ls = oracle_lineset(h, cfg, T, 1.0)
+    ref = O.cross_section(ls, cfg.nu_a, cfg.nu_b, cfg.n_points, cfg.cutoff)
+    assert_parity(got, ref, 3e-6, what=f"far-wing zone T={T}")
+    # the gaps, far below the usual floor of 1e-6 of the maximum, point by point
+    m = ref > 1e-12 * ref.max()
+    rel = np.abs(got[m] - ref[m]) / ref[m]
+    log(f"  far-wing zone T={T}: max rel {rel.max():.3e} over {m.sum()} points above 1e-12 of the maximum")
+    assert m.sum() > 100000
+    assert rel.max() <= 3e-6
