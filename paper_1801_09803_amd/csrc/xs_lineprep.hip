@@ -159,6 +159,10 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* l
     return wbase + incl - v;
 }
 
+// One pass of the LSD sort for one block of kTile items: ranks by digit in item order
+// (stable), the block's items staged in LDS in that order, then written out by
+// consecutive local positions, so each digit's run of the block lands as one contiguous,
+// coalesced range at its global offset.
 __global__ __launch_bounds__(256) void radix_scatter_kernel(const uint32_t* __restrict__ kin,
                                                             const uint32_t* __restrict__ vin, int64_t n,
                                                             int shift, int nblk,
@@ -167,9 +171,13 @@ __global__ __launch_bounds__(256) void radix_scatter_kernel(const uint32_t* __re
                                                             uint32_t* __restrict__ vout) {
     __shared__ uint32_t cnt[16 * 256];   // [digit][thread]
     __shared__ uint32_t dbase[16];
+    __shared__ uint32_t gbase[16];
     __shared__ uint32_t wsum[4];
+    __shared__ uint32_t sk[kTile], sv[kTile];
     const int t = threadIdx.x;
-    const int64_t base = (int64_t)blockIdx.x * kTile + (int64_t)t * kItems;
+    const int64_t b0 = (int64_t)blockIdx.x * kTile;
+    const int64_t base = b0 + (int64_t)t * kItems;
+    const int valid = (int)(n - b0 < kTile ? n - b0 : kTile);
     uint32_t key[kItems], val[kItems], rank[kItems];
 #pragma unroll
     for (int d = 0; d < 16; ++d) cnt[d * 256 + t] = 0;
@@ -200,17 +208,28 @@ __global__ __launch_bounds__(256) void radix_scatter_kernel(const uint32_t* __re
 #pragma unroll
     for (int k = 0; k < 16; ++k) cnt[16 * t + k] = pre + loc[k];
     __syncthreads();
-    if (t < 16) dbase[t] = cnt[t * 256];
-    __syncthreads();
+    if (t < 16) {
+        dbase[t] = cnt[t * 256];
+        gbase[t] = goff[(int64_t)t * nblk + blockIdx.x];
+    }
+    // stage in block order: local position = start of (digit, thread) + rank
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
         if (base + k < n) {
             const uint32_t d = (key[k] >> shift) & 15u;
-            const uint32_t pos = goff[(int64_t)d * nblk + blockIdx.x] + (cnt[d * 256 + t] - dbase[d]) + rank[k];
-            if ((int64_t)pos < n) {   // always true for a consistent histogram
-                kout[pos] = key[k];
-                vout[pos] = val[k];
-            }
+            const uint32_t lp = cnt[d * 256 + t] + rank[k];
+            sk[lp] = key[k];
+            sv[lp] = val[k];
+        }
+    }
+    __syncthreads();
+    for (int j = t; j < valid; j += 256) {
+        const uint32_t kk = sk[j];
+        const uint32_t d = (kk >> shift) & 15u;
+        const uint32_t pos = gbase[d] + ((uint32_t)j - dbase[d]);
+        if ((int64_t)pos < n) {   // always true for a consistent histogram
+            kout[pos] = kk;
+            vout[pos] = sv[j];
         }
     }
 }
