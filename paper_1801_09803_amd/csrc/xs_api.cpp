@@ -202,6 +202,8 @@ struct xs_plan {
     DevBuf st_T, st_part, st_sumA, st_power;
     // non-LTE: per-state vibrational energies, manifold minima, per sorted line E_vib
     DevBuf Ev, vmin, s_evl, s_evu;
+    // bucketed per-state sums: histogram, offsets, scan scratch, records
+    DevBuf st_bhist, st_bhoff, st_btsum, st_brec;
     // batched cross-section pipeline of direct calls
     Workset ws;
     // tables
@@ -219,7 +221,7 @@ struct xs_plan {
         DevBuf* all[] = {&E, &g, &J, &tab_g, &tab_n, &p_rec, &s_nu, &s_elow, &s_cA, &s_gref, &s_nexp, &s_kc, &s_klo,
                          &s_khi, &s_orig, &k1, &v1, &k2, &v2, &hist, &hoff, &tsum, &off, &flag,
                          &T_dev, &Q, &dQ, &qpart, &tab_dev, &tile_order, &adj_pT, &adj_pP, &adj_part, &adj_rec,
-                         &adj_sums, &st_T, &st_part, &st_sumA, &st_power, &Ev, &vmin, &s_evl, &s_evu};
+                         &adj_sums, &st_T, &st_part, &st_sumA, &st_power, &Ev, &vmin, &s_evl, &s_evu, &st_bhist, &st_bhoff, &st_btsum, &st_brec};
         for (DevBuf* b : all) release(*b);
         ws.release();
     }
@@ -1113,7 +1115,17 @@ static xs_status state_rates(xs_plan* p, int64_t n, const int32_t* upper, const 
     a.flag = as<int>(p->flag);
     a.sum_A = sum_A ? as<double>(p->st_sumA) : nullptr;
     a.power = power ? as<double>(p->st_power) : nullptr;
-    XS_HIP(xs::launch_rates(a, s));
+    if (xs::bucket_rates_fits(n, p->n_states)) {
+        const size_t nh = (size_t)xs::bucket_hist_len(n, p->n_states);
+        XS_TRY(p->ensure(p->st_bhist, nh * sizeof(uint32_t), "bucket histogram"));
+        XS_TRY(p->ensure(p->st_bhoff, nh * sizeof(uint32_t), "bucket offsets"));
+        XS_TRY(p->ensure(p->st_btsum, 4096 * sizeof(uint32_t), "bucket scan"));
+        XS_TRY(p->ensure(p->st_brec, (size_t)n * 16, "bucket records"));
+        XS_HIP(xs::launch_bucket_rates(a, as<uint32_t>(p->st_bhist), as<uint32_t>(p->st_bhoff),
+                                       as<uint32_t>(p->st_btsum), p->st_brec.p, s));
+    } else {
+        XS_HIP(xs::launch_rates(a, s));
+    }
     int flag = 0;
     XS_HIP(hipMemcpyAsync(&flag, p->flag.p, sizeof(int), hipMemcpyDeviceToHost, s));
     XS_HIP(hipStreamSynchronize(s));

@@ -8,6 +8,7 @@
 // per state; each temperature then costs a pass over the states only, not the lines.
 #include "xs_states.hpp"
 #include "xs_reduce.hpp"
+#include "xs_lineprep.hpp"
 
 #include <cmath>
 
@@ -158,7 +159,132 @@ __global__ __launch_bounds__(256) void vib_gather_kernel(int64_t n, const int* _
 
 dim3 grid_of(int64_t n) { return dim3((unsigned)((n + 255) / 256)); }
 
+// ------------------------------------------------------- bucketed per-state sums
+constexpr int kBItems = 16;
+constexpr int kBTile = 256 * kBItems;     // transitions per block of the count and scatter
+constexpr int kBucketStates = 1 << kBucketBits;
+
+struct BRec {
+    int local;        // upper state - bucket start
+    float araw;       // the A array's value (ln A when a_is_log)
+    double anu;       // A nu in double (when the power sum is wanted)
+};
+
+static_assert(sizeof(BRec) == 16, "bucket records are 16 B");
+
+// Upper state of transition i, or -1 (flag set) when it is out of range.  Both passes
+// place a transition by its upper state alone; the scatter checks the rest.
+__device__ __forceinline__ int checked_upper(const RateArgs& a, int64_t i) {
+    const int up = a.upper[i] - a.index_base;
+    if (up < 0 || up >= a.n_states) { atomicOr(a.flag, kFlagIndex); return -1; }
+    return up;
+}
+
+// hist[b * nblk + blk] = valid transitions of block blk whose upper state is in bucket b
+__global__ __launch_bounds__(256) void bucket_count_kernel(const RateArgs a, int nbk, int nblk,
+                                                           uint32_t* __restrict__ hist) {
+    extern __shared__ uint32_t cnt[];
+    for (int b = threadIdx.x; b < nbk; b += 256) cnt[b] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kBTile;
+    for (int k = 0; k < kBItems; ++k) {
+        const int64_t i = base + (int64_t)k * 256 + threadIdx.x;   // coalesced
+        if (i >= a.n) break;
+        const int up = checked_upper(a, i);
+        if (up >= 0) atomicAdd(&cnt[up >> kBucketBits], 1u);
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < nbk; b += 256) hist[(int64_t)b * nblk + blockIdx.x] = cnt[b];
+}
+
+// Each valid transition to rec[hoff[b * nblk + blk] + rank], rank from an LDS counter
+// (the order inside a block's bucket run is not fixed).
+__global__ __launch_bounds__(256) void bucket_scatter_kernel(const RateArgs a, int nbk, int nblk,
+                                                             const uint32_t* __restrict__ hoff,
+                                                             BRec* __restrict__ rec) {
+    extern __shared__ uint32_t cnt[];
+    for (int b = threadIdx.x; b < nbk; b += 256) cnt[b] = hoff[(int64_t)b * nblk + blockIdx.x];
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kBTile;
+    for (int k = 0; k < kBItems; ++k) {
+        const int64_t i = base + (int64_t)k * 256 + threadIdx.x;
+        if (i >= a.n) break;
+        const int up = checked_upper(a, i);
+        if (up < 0) continue;
+        const uint32_t pos = atomicAdd(&cnt[up >> kBucketBits], 1u);
+        BRec r;
+        r.local = up & (kBucketStates - 1);
+        r.araw = a.A[i];
+        r.anu = 0.0;
+        if (a.power) {
+            // a transition with a bad lower state or nu <= 0 flags the call and adds nothing
+            const int lo = a.lower[i] - a.index_base;
+            if (lo < 0 || lo >= a.n_states) {
+                atomicOr(a.flag, kFlagIndex);
+            } else {
+                const double nu = a.E[up] - a.E[lo];
+                if (!(nu > 0.0)) atomicOr(a.flag, kFlagNu);
+                else r.anu = (a.a_is_log ? exp((double)r.araw) : (double)r.araw) * nu;
+            }
+        }
+        rec[pos] = r;
+    }
+}
+
+// One workgroup per bucket: LDS sums of its records, then the bucket's states written.
+__global__ __launch_bounds__(256) void bucket_sum_kernel(const RateArgs a, int nblk, int64_t nhist,
+                                                         const uint32_t* __restrict__ hist,
+                                                         const uint32_t* __restrict__ hoff,
+                                                         const BRec* __restrict__ rec) {
+    __shared__ double sa[kBucketStates], sp[kBucketStates];
+    for (int j = threadIdx.x; j < kBucketStates; j += 256) { sa[j] = 0.0; sp[j] = 0.0; }
+    __syncthreads();
+    const int64_t h0 = (int64_t)blockIdx.x * nblk;
+    const uint32_t r0 = hoff[h0];
+    const uint32_t r1 = h0 + nblk < nhist ? hoff[h0 + nblk] : hoff[nhist - 1] + hist[nhist - 1];
+    for (uint32_t q = r0 + threadIdx.x; q < r1; q += 256) {
+        const BRec r = rec[q];
+        if (a.sum_A) atomicAdd(&sa[r.local], a.a_is_log ? exp((double)r.araw) : (double)r.araw);
+        if (a.power) atomicAdd(&sp[r.local], r.anu);
+    }
+    __syncthreads();
+    const int64_t s0 = (int64_t)blockIdx.x * kBucketStates;
+    for (int j = threadIdx.x; j < kBucketStates; j += 256) {
+        const int64_t st = s0 + j;
+        if (st >= a.n_states) break;
+        if (a.sum_A) a.sum_A[st] = sa[j];
+        if (a.power) a.power[st] = sp[j];
+    }
+}
+
 }  // namespace
+
+int64_t bucket_count_of(int64_t n_states) { return (n_states + kBucketStates - 1) >> kBucketBits; }
+
+int64_t bucket_hist_len(int64_t n, int64_t n_states) {
+    return bucket_count_of(n_states) * ((n + kBTile - 1) / kBTile);
+}
+
+bool bucket_rates_fits(int64_t n, int64_t n_states) {
+    return n > 0 && bucket_count_of(n_states) <= 8192 && bucket_hist_len(n, n_states) <= kMaxBucketHist &&
+           n < ((int64_t)1 << 32);
+}
+
+hipError_t launch_bucket_rates(const RateArgs& a, uint32_t* hist, uint32_t* hoff, uint32_t* tsum, void* rec,
+                               hipStream_t s) {
+    const int nbk = (int)bucket_count_of(a.n_states);
+    const int nblk = (int)((a.n + kBTile - 1) / kBTile);
+    const int64_t nh = (int64_t)nbk * nblk;
+    const size_t lds = (size_t)nbk * sizeof(uint32_t);
+    hipLaunchKernelGGL(bucket_count_kernel, dim3(nblk), dim3(256), lds, s, a, nbk, nblk, hist);
+    hipError_t e = launch_exclusive_scan(hist, nh, hoff, tsum, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(bucket_scatter_kernel, dim3(nblk), dim3(256), lds, s, a, nbk, nblk, (const uint32_t*)hoff,
+                       static_cast<BRec*>(rec));
+    hipLaunchKernelGGL(bucket_sum_kernel, dim3(nbk), dim3(256), 0, s, a, nblk, nh, (const uint32_t*)hist,
+                       (const uint32_t*)hoff, (const BRec*)rec);
+    return hipGetLastError();
+}
 
 hipError_t launch_vib_energies(const double* E, const int* labels, int64_t n, int n_labels,
                                unsigned long long* vmin, double* Ev, int* flag, hipStream_t s) {

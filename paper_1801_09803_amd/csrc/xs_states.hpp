@@ -26,6 +26,20 @@ struct RateArgs {
 
 hipError_t launch_fill(double* x, int64_t n, double v, hipStream_t s);
 hipError_t launch_rates(const RateArgs& a, hipStream_t s);
+
+// The same per-state sums without global atomics: the transitions are counted and
+// scattered into buckets of 2^kBucketBits consecutive upper states (a counting sort by
+// bucket: per-4096-transition-block histograms, one exclusive scan, a scatter of 16-B
+// records), then one workgroup per bucket adds its records into LDS and writes the
+// bucket's sums.  Applies while the histogram has at most kMaxBucketHist entries
+// (bucket_rates_fits); otherwise launch_rates is the path.  Workspace: hist and hoff of
+// bucket_hist_len entries, tsum of 4096 entries, rec of 16 n bytes.
+constexpr int kBucketBits = 12;
+constexpr int64_t kMaxBucketHist = (int64_t)4096 * 4096;
+bool bucket_rates_fits(int64_t n, int64_t n_states);
+int64_t bucket_hist_len(int64_t n, int64_t n_states);
+hipError_t launch_bucket_rates(const RateArgs& a, uint32_t* hist, uint32_t* hoff, uint32_t* tsum, void* rec,
+                               hipStream_t s);
 // tau_i = 1 / sum_A_i, +inf where no transition leaves state i
 hipError_t launch_lifetimes(const double* sum_A, int64_t n, double* tau, hipStream_t s);
 // Q, Q' = sum g x e^-x, Q'' = sum g x^2 e^-x (x = c2 E/T) and C_p per temperature; part:

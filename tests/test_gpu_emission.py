@@ -210,3 +210,33 @@ def test_emission_with_threshold_graph_and_stream():
                  hd["n_exp"][half:])
     assert ei.value.name == "XS_ERR_STATE"
     st.end()
+
+
+def test_lifetimes_and_cooling_beyond_the_bucketed_range():
+    # more states than the bucketed pass takes (8192 buckets of 4096): the global-atomic
+    # pass; a few transitions among 3.4e7 states
+    n_states = 8192 * 4096 + 5
+    g = torch.full((n_states,), 3, dtype=torch.int32, device="cuda")
+    E = torch.linspace(0.0, 30000.0, n_states, dtype=torch.float64, device="cuda")
+    cfg = synth.WorkloadConfig("big", 9, n_states, 1, 28.0, 300.0, 0.0, 200.0, 2001, (800.0,), (0.5,))
+    rng = np.random.default_rng(8)
+    lo = rng.integers(0, n_states - 1, 20000)
+    up = np.minimum(lo + rng.integers(1, 5000, lo.size), n_states - 1)
+    A = (10 ** rng.uniform(-3, 2, lo.size)).astype(np.float32)
+    plan = make_plan(cfg, "fp32")
+    plan.set_states(E, g)
+    tau = plan.lifetimes(torch.tensor(up, dtype=torch.int32, device="cuda"),
+                         torch.tensor(A, device="cuda")).cpu().numpy()
+    s = {}
+    for u, a in zip(up.tolist(), A.astype(np.float64).tolist()):
+        s.setdefault(u, []).append(a)
+    for u, vals in list(s.items())[:2000]:
+        assert abs(tau[u] * math.fsum(vals) - 1) <= 1e-12
+    assert np.isinf(tau[[0, n_states - 1]]).all() or (n_states - 1) in s
+    Eh = E.cpu().numpy()
+    W = plan.cooling_function(torch.tensor(up, dtype=torch.int32, device="cuda"),
+                              torch.tensor(lo, dtype=torch.int32, device="cuda"),
+                              torch.tensor(A, device="cuda"), [2000.0]).item()
+    ref = O.cooling_function(Eh, np.full(n_states, 3), up, lo, A, 2000.0)
+    log(f"  W(2000 K) over {n_states} states: {W:.6e} (oracle {ref:.6e})")
+    assert abs(W / ref - 1) <= 1e-11
