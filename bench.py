@@ -80,8 +80,8 @@ def zone_counts(cfg, d, T, P, chunk=1 << 24):
 TRAFFIC = {
     "kernel_sources": ['xs_forward_f32.hip', 'xs_forward_common.hpp', 'xs_voigt.hpp', 'xs_forward.hpp', 'xs_internal.hpp'],
     "sha256": "de797ef27da9e0176e90e9979802b1186f75145b18d38bfd6e6c1bc733833453",
-    "fetch_kib": [32054736.1, 36644856.7],
-    "write_kib": [251287.7, 251657.2],
+    "fetch_kib": [32060985.3, 36650173.4],
+    "write_kib": [251302.3, 251649.7],
     "fetch_scale": 2.0,
     "write_scale": 1.0,
 }
