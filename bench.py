@@ -698,6 +698,8 @@ def stream_run(cfg, dev, log, n_chunks, chunk):
         evals += int(torch.clamp(khi - klo + 1, min=0).sum().item())
         host.append([t.cpu().pin_memory() for t in (up, lo, A)])
         del up, lo, A, nu, klo, khi
+        if n_chunks > 4:
+            log(f"  generated chunk {c + 1}/{n_chunks}")
     plan = Plan(cfg.nu_a, cfg.nu_b, cfg.n_points, cfg.mass_amu, cutoff=cfg.cutoff, profile="voigt",
                 precision="fp32", broadening="a0_jlower")
     plan.set_broadening_table(gt.numpy(), nt.numpy())
@@ -707,8 +709,10 @@ def stream_run(cfg, dev, log, n_chunks, chunk):
     log(f"streaming {n_chunks} chunks of {chunk} lines x {len(T)} (T,P)")
     t0 = time.perf_counter()
     st = plan.stream(T, P, out=out)
-    for h in host:
+    for c, h in enumerate(host):
         st.chunk(*h)
+        if n_chunks > 4:
+            log(f"  chunk {c + 1}/{n_chunks} handed over")
     _, kept = st.end()
     dt = time.perf_counter() - t0
     n_lines = n_chunks * chunk
@@ -723,7 +727,7 @@ def stream_run(cfg, dev, log, n_chunks, chunk):
         "h2d_bytes": n_lines * 12,
         "full_list_extrapolated_s": dt * cfg.n_lines / n_lines,
         "note": "timed from stream begin to end, host-to-device copies included; the full-list time is a "
-                "linear extrapolation, not a measurement",
+                "linear extrapolation unless the chunks cover the whole list",
     }
     log(f"streaming: {dt:.2f} s, {res['line_profiles_per_s']:.3e} line-profiles/s")
     del plan, out, st, host
