@@ -164,7 +164,7 @@ def main():
     ap.add_argument("--autotune-ms", type=float, default=20000.0,
                     help="autotuner budget (0: keep the library's default tile shape)")
     ap.add_argument("--tile", default="", help="fixed tile config waves,slices,n_split,tp_block")
-    ap.add_argument("--cpu-lines-per-core", type=int, default=20000)
+    ap.add_argument("--cpu-lines-per-core", type=int, default=40000)
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run a device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
