@@ -5,7 +5,11 @@
 // leaving state i carries the same population factor g_i exp(-c2 E_i/T)/Q, so
 //     W(T) = h c / (4 pi Q(T)) sum_i g_i exp(-c2 E_i/T) P_i,   P_i = sum_f A_fi nu_fi.
 // One pass over the transitions accumulates P_i (and sum_f A_fi, the inverse lifetime)
-// per state; each temperature then costs a pass over the states only, not the lines.
+// per state (bucketed through LDS, or with global atomics beyond the bucketed range);
+// each temperature then costs a pass over the states only, not the lines.
+//
+// Also here: the per-state vibrational energies of non-LTE populations (Sec. "Treating
+// non-local thermodynamic equilibrium") and their gather onto the sorted lines.
 #include "xs_states.hpp"
 #include "xs_reduce.hpp"
 #include "xs_lineprep.hpp"
