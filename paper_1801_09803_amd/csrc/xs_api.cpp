@@ -122,6 +122,7 @@ struct Workset {
     DevBuf val;               // core values of one block of (T, P)
     DevBuf hot, cold, xscale; // FP32 line records [tp_block][n_kept] (32 or 48 + 64 + 8 B per line)
     DevBuf vv;                // Vectorized Voigt {beta, intensity factor} [tp_block][n_kept]
+    DevBuf sl;                // super-lines: per-line intensities [tp_block][n_kept]
     DevBuf th_bsum, th_tmp;   // intensity threshold: block counts, scan scratch per row
     DevBuf th_pos, th_map, th_offs;   // per row: positions [n+1], kept lines [n], offsets [nkeys+1]
     DevBuf part;              // per-part sums [tp_block][n_split][n_points] when n_split > 1
@@ -134,7 +135,7 @@ struct Workset {
     xs_status ensure(DevBuf& b, size_t n, const char* what) { return dev_ensure(b, n, what, &bytes); }
     void release() {
         DevBuf* all[] = {&T, &Q, &dQ, &qpart, &tps, &rc, &cnt, &coff, &bsum, &tmp, &val, &hot, &cold, &xscale,
-                         &vv, &th_bsum, &th_tmp, &th_pos, &th_map, &th_offs, &part, &out};
+                         &vv, &sl, &th_bsum, &th_tmp, &th_pos, &th_map, &th_offs, &part, &out};
         for (DevBuf* b : all) dev_release(*b, &bytes);
         stage.release();
         rows = 0;
@@ -509,6 +510,11 @@ xs_status ensure_rows(xs_plan* p, Workset& ws, int B, int S) {
         ws.rows = B;
         ws.row_stride = n;
     }
+    if (superlines(p)) {
+        XS_TRY(ws.ensure(ws.sl, (size_t)B * n * sizeof(double), "super-line intensities"));
+        ws.rows = B;
+        ws.row_stride = n;
+    }
     if (records_path(p)) {
         XS_TRY(ws.ensure(ws.hot, (size_t)B * n * hot_words(p) * sizeof(float), "line records"));
         XS_TRY(ws.ensure(ws.cold, (size_t)B * n * 16 * sizeof(int), "line records"));
@@ -605,6 +611,10 @@ xs::FwdArgs fwd_args(xs_plan* p, Workset& ws, const std::vector<xs::TPParam>& tp
         a.xscale = as<double>(ws.xscale) + (int64_t)row0 * ws.row_stride;
         a.rec_stride = ws.row_stride;
         a.core_val = as<float>(ws.val);
+    }
+    if (superlines(p)) {
+        a.line_S = as<double>(ws.sl) + (int64_t)row0 * ws.row_stride;
+        a.line_S_stride = ws.row_stride;
     }
     return a;
 }

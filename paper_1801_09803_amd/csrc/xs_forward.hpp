@@ -64,6 +64,9 @@ struct FwdArgs {
     const float* hot;
     const int* cold;
     const double* xscale;
+    // super-lines: per-line intensities of each (T, P) of the launch (rows of line_S_stride)
+    double* line_S;
+    int64_t line_S_stride;
     int64_t rec_stride;
     const float* core_val;          // FP32 Voigt: a * Re w at the lines' core points
     // FP64 Vectorized Voigt: per (line, T, P) {beta, intensity factor} rows of vv_stride

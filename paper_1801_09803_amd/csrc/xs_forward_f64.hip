@@ -327,7 +327,21 @@ namespace {
 
 // Sec. "Super-lines": per grid point k, the intensities (Eq. 1) of the lines whose nearest
 // grid index is k (the sorted lines of key k, in their sorted order) summed in double,
-// divided by dnu.
+// divided by dnu.  Two passes: every line's intensity (one thread per line, coalesced),
+// then per grid point the sum of its contiguous run of lines in sorted order.
+__global__ __launch_bounds__(256) void superline_S_kernel(const FwdArgs A) {
+    const Geometry G = A.G;
+    const int t = blockIdx.y;
+    const int l = blockIdx.x * 256 + threadIdx.x;
+    const int* off = A.offs ? A.offs + (int64_t)t * A.offs_stride : A.off;
+    if (l >= off[G.nkeys]) return;   // the lines of this (T, P) in sorted order
+    const int* map = A.map ? A.map + (int64_t)t * A.map_stride : nullptr;
+    const TPParam tp = A.tps[t];
+    const int gs = line_of(map, l);
+    A.line_S[(int64_t)t * A.line_S_stride + l] =
+        line_intensity(A.L, gs, A.L.elow[gs], A.L.nu[gs], tp, A.Q[tp.iq]);   // Eq. 1 (or emissivity)
+}
+
 __global__ __launch_bounds__(256) void superline_kernel(const FwdArgs A, int fp64) {
     const Geometry G = A.G;
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -335,16 +349,11 @@ __global__ __launch_bounds__(256) void superline_kernel(const FwdArgs A, int fp6
     if (i >= total) return;
     const int t = (int)(i / G.n_points);
     const int k = (int)(i - (int64_t)t * G.n_points);
-    const TPParam tp = A.tps[t];
-    const double Q = A.Q[tp.iq];
-    const int* map = A.map ? A.map + (int64_t)t * A.map_stride : nullptr;
     const int* off = A.offs ? A.offs + (int64_t)t * A.offs_stride : A.off;
     const int l0 = off_at(off, k, G), l1 = off_at(off, (int64_t)k + 1, G);
+    const double* S = A.line_S + (int64_t)t * A.line_S_stride;
     double acc = 0.0;
-    for (int l = l0; l < l1; ++l) {
-        const int gs = line_of(map, l);
-        acc += line_intensity(A.L, gs, A.L.elow[gs], A.L.nu[gs], tp, Q);   // Eq. 1 (or emissivity)
-    }
+    for (int l = l0; l < l1; ++l) acc += S[l];
     const double v = acc / G.dnu;
     if (fp64) static_cast<double*>(A.sigma)[i] = v;
     else static_cast<float*>(A.sigma)[i] = (float)v;
@@ -355,6 +364,9 @@ __global__ __launch_bounds__(256) void superline_kernel(const FwdArgs A, int fp6
 hipError_t launch_superlines(int fp64, const FwdArgs& a, hipStream_t s) {
     const int64_t total = (int64_t)a.n_tp * a.G.n_points;
     if (total == 0) return hipSuccess;
+    if (a.n_lines > 0)
+        hipLaunchKernelGGL(superline_S_kernel, dim3((unsigned)((a.n_lines + 255) / 256), (unsigned)a.n_tp), dim3(256),
+                           0, s, a);
     hipLaunchKernelGGL(superline_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, a, fp64);
     return hipGetLastError();
 }
