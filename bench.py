@@ -79,9 +79,9 @@ def zone_counts(cfg, d, T, P, chunk=1 << 24):
 # Valid only for the kernel sources they were taken with (hash below).
 TRAFFIC = {
     "kernel_sources": ['xs_forward_f32.hip', 'xs_forward_common.hpp', 'xs_voigt.hpp', 'xs_forward.hpp', 'xs_internal.hpp'],
-    "sha256": "de797ef27da9e0176e90e9979802b1186f75145b18d38bfd6e6c1bc733833453",
-    "fetch_kib": [32060985.3, 36650173.4],
-    "write_kib": [251302.3, 251649.7],
+    "sha256": "19a79d8363a950acc4bd2852e256cbdf0f8492a2e1512c1c940d72b144bbbdc8",
+    "fetch_kib": [32066342.6, 36639946.8],
+    "write_kib": [251293.3, 251648.9],
     "fetch_scale": 2.0,
     "write_scale": 1.0,
 }
