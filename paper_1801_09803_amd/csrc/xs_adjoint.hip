@@ -127,12 +127,13 @@ __global__ __launch_bounds__(256) void adjoint64_kernel(const AdjArgs A) {
 //    the line's core points [kcl, kch] (the forward core pre-pass's range: every point with
 //    |z| < 8 lies inside it) in double precision (core with w', or the 4- / 2-node rule).
 // 2. adj32_wing: one wavefront per line: the window sums over the other points with the
-//    single-precision Gauss-Hermite derivatives (2-node for |z| >= 40, 4-node inside),
-//    8-point single-precision partials folded into double.
+//    single-precision Gauss-Hermite derivatives, by index runs: the 2-node rule beyond the
+//    line's |z| = 40 radius, the 4-node rule inside it (the core excluded), 8-point
+//    single-precision partials folded into double.
 // 3. adj32_final: one thread per line: R0, R_gamma, R_alpha and the gradients.
 enum : int { J_HS = 0, J_XCS = 1, J_YS2 = 2, J_Z1S = 3, J_A2 = 4, J_B2 = 5, J_E2 = 6, J_C2 = 7,
              J_A4 = 8, J_B4 = 10, J_E4 = 12, J_C4 = 14, J_KLO = 16, J_KHI = 17, J_KC = 18, J_KCL = 19,
-             J_KCH = 20 };
+             J_KCH = 20, J_RAD = 21 };
 
 // scaling of the single-precision wing variables: x_s = x sc keeps x_s^4 in range
 __device__ __forceinline__ double wing_scale(double s, const Geometry& G) {
@@ -183,6 +184,8 @@ __global__ __launch_bounds__(256) void adj32_prep_kernel(const AdjArgs A) {
         kcl = (int)(lo > ls.klo ? lo : ls.klo);
         kch = (int)(hi < ls.khi ? hi : ls.khi);
     }
+    // points beyond rad steps from kc have |z| >= 40 (the 2-node rule's zone)
+    fi[J_RAD] = y2 < kMidR2 ? radius_steps(sqrt(kMidR2 - y2), s * G.dnu, s * d) : -1;
     fi[J_KLO] = ls.klo;
     fi[J_KHI] = ls.khi;
     fi[J_KC] = ls.kc;
@@ -218,6 +221,53 @@ __global__ __launch_bounds__(256) void adj32_prep_kernel(const AdjArgs A) {
     sm[2] = cy;
 }
 
+// Window sums over the points kA..kB of one line (lanes over consecutive points, partials
+// in single precision over 8 passes of 64 points, then folded into double).  TWO: the
+// 2-node rule (one node pair) written out, with its weight c applied per fold; otherwise
+// the 4-node rule through wing_dv_f32.
+template <bool TWO>
+__device__ __forceinline__ void adj_run(int kA, int kB, int kc, int lane, const float* __restrict__ gbar, float hs,
+                                        float xcs, float ys2, const float* a, const float* b, const float* e,
+                                        const float* c, double* s0, double* sx, double* sy) {
+    if (kB < kA) return;
+    const int niter = (kB - kA + 64) / 64;
+    const float ys2x2 = 2.0f * ys2;
+    float jf = (float)(kA + lane - kc);    // exact: |k - kc| < 2^24
+    for (int it0 = 0; it0 < niter; it0 += 8) {
+        const int ite = it0 + 8 < niter ? it0 + 8 : niter;
+        float p0 = 0.0f, px = 0.0f, py = 0.0f;
+        for (int it = it0; it < ite; ++it) {
+            const int k = kA + 64 * it + lane;
+            const float gb = k <= kB ? gbar[k] : 0.0f;
+            const float xsv = __builtin_fmaf(jf, hs, xcs);
+            jf += 64.0f;
+            if constexpr (TWO) {
+                // p = x^2 + a, q = p + b, r = 1/(p^2 + e): V ~ q r, x dV/dx ~ x^2 r (1 - 2 p q r),
+                // dV/dy ~ q r + 2 y^2 r (1 - 2 q q r)
+                const float u = xsv * xsv;
+                const float pp = u + a[0];
+                const float q = pp + b[0];
+                const float r = __builtin_amdgcn_rcpf(__builtin_fmaf(pp, pp, e[0]));
+                const float qr = q * r;
+                const float m2 = -2.0f * qr;
+                p0 = __builtin_fmaf(gb, qr, p0);
+                px = __builtin_fmaf(gb * (u * r), __builtin_fmaf(pp, m2, 1.0f), px);
+                py = __builtin_fmaf(gb, __builtin_fmaf(ys2x2, r * __builtin_fmaf(q, m2, 1.0f), qr), py);
+            } else {
+                float sv, ssx, ssy;
+                wing_dv_f32<2>(xsv, a, b, e, c, ys2, &sv, &ssx, &ssy);
+                p0 = __builtin_fmaf(gb, sv, p0);
+                px = __builtin_fmaf(gb, ssx, px);
+                py = __builtin_fmaf(gb, ssy, py);
+            }
+        }
+        const double w = TWO ? (double)c[0] : 1.0;
+        *s0 += w * (double)p0;
+        *sx += w * (double)px;
+        *sy += w * (double)py;
+    }
+}
+
 __global__ __launch_bounds__(256) void adj32_wing_kernel(const AdjArgs A) {
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -226,7 +276,7 @@ __global__ __launch_bounds__(256) void adj32_wing_kernel(const AdjArgs A) {
     for (int g = blockIdx.x * 4 + wave; g < A.n_lines; g += nwaves) {
         const float* r = A.rec + (int64_t)g * kAdjRec;
         const int* ri = reinterpret_cast<const int*>(r);
-        const float hs = r[J_HS], xcs = r[J_XCS], ys2 = r[J_YS2], z1s = r[J_Z1S];
+        const float hs = r[J_HS], xcs = r[J_XCS], ys2 = r[J_YS2];
         const float a2[1] = {r[J_A2]}, b2[1] = {r[J_B2]}, e2[1] = {r[J_E2]}, c2[1] = {r[J_C2]};
         const float a4[2] = {r[J_A4], r[J_A4 + 1]}, b4[2] = {r[J_B4], r[J_B4 + 1]};
         const float e4[2] = {r[J_E4], r[J_E4 + 1]}, c4[2] = {r[J_C4], r[J_C4 + 1]};
@@ -235,27 +285,27 @@ __global__ __launch_bounds__(256) void adj32_wing_kernel(const AdjArgs A) {
         const int kc = __builtin_amdgcn_readfirstlane(ri[J_KC]);
         const int kcl = __builtin_amdgcn_readfirstlane(ri[J_KCL]);
         const int kch = __builtin_amdgcn_readfirstlane(ri[J_KCH]);
-        const int niter = khi >= klo ? (khi - klo + 64) / 64 : 0;
+        const int rad = __builtin_amdgcn_readfirstlane(ri[J_RAD]);
         double s0 = 0.0, sxa = 0.0, sya = 0.0;
-        for (int it0 = 0; it0 < niter; it0 += 8) {
-            const int ite = it0 + 8 < niter ? it0 + 8 : niter;
-            float p0 = 0.0f, px = 0.0f, py = 0.0f;
-            for (int it = it0; it < ite; ++it) {
-                const int k = klo + 64 * it + lane;
-                const bool use = k <= khi && (k < kcl || k > kch);
-                const float gb = use ? gbar[k] : 0.0f;
-                const float xsv = __builtin_fmaf((float)(k - kc), hs, xcs);
-                const float z2s = __builtin_fmaf(xsv, xsv, ys2);
-                float sv, sx, sy;
-                if (z2s >= z1s) wing_dv_f32<1>(xsv, a2, b2, e2, c2, ys2, &sv, &sx, &sy);
-                else wing_dv_f32<2>(xsv, a4, b4, e4, c4, ys2, &sv, &sx, &sy);
-                p0 = __builtin_fmaf(gb, sv, p0);
-                px = __builtin_fmaf(gb, sx, px);
-                py = __builtin_fmaf(gb, sy, py);
+        if (rad < 0) {
+            adj_run<true>(klo, khi, kc, lane, gbar, hs, xcs, ys2, a2, b2, e2, c2, &s0, &sxa, &sya);
+        } else {
+            // [klo, kml) and (kmh, khi]: 2-node; [kml, kmh] without the core [kcl, kch]: 4-node
+            // (the core lies inside: its radius is that of |z| < 8)
+            const int64_t ml = (int64_t)kc - rad, mh = (int64_t)kc + rad;
+            const int kml = (int)(ml > klo ? ml : klo), kmh = (int)(mh < khi ? mh : khi);
+            adj_run<true>(klo, (kml - 1 < khi ? kml - 1 : khi), kc, lane, gbar, hs, xcs, ys2, a2, b2, e2, c2, &s0,
+                          &sxa, &sya);
+            if (kcl > kch) {
+                adj_run<false>(kml, kmh, kc, lane, gbar, hs, xcs, ys2, a4, b4, e4, c4, &s0, &sxa, &sya);
+            } else {
+                adj_run<false>(kml, (kcl - 1 < kmh ? kcl - 1 : kmh), kc, lane, gbar, hs, xcs, ys2, a4, b4, e4, c4,
+                               &s0, &sxa, &sya);
+                adj_run<false>((kch + 1 > kml ? kch + 1 : kml), kmh, kc, lane, gbar, hs, xcs, ys2, a4, b4, e4, c4,
+                               &s0, &sxa, &sya);
             }
-            s0 += (double)p0;
-            sxa += (double)px;
-            sya += (double)py;
+            adj_run<true>((kmh + 1 > klo ? kmh + 1 : klo), khi, kc, lane, gbar, hs, xcs, ys2, a2, b2, e2, c2, &s0,
+                          &sxa, &sya);
         }
         s0 = wave_sum64(s0);
         sxa = wave_sum64(sxa);
