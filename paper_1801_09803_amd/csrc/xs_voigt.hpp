@@ -35,21 +35,29 @@ __device__ __forceinline__ double rcp64(double d) {
 }
 
 // w(z) ~ 2 p(Z)/(L - iz)^2 + (1/sqrt(pi))/(L - iz),  Z = (L + iz)/(L - iz).
+// p has real coefficients, so p(Z) is the remainder c1 Z + c0 of p divided by
+// (t - Z)(t - conj Z) = t^2 - 2 Re Z t + |Z|^2 (synthetic division: two FMA per
+// coefficient instead of the four of a complex Horner step).
 template <int N>
 __device__ __forceinline__ cplx weideman_w(double x, double y, const WeidemanCoef& W) {
+    static_assert(N >= 3, "Weideman order");
     const double L = W.L;
     const double dr = L + y, di = -x;      // L - iz
     const double nr = L - y, ni = x;       // L + iz
-    const double inv = 1.0 / (dr * dr + di * di);
+    const double inv = rcp64(__builtin_fma(dr, dr, di * di));
     const double zr = (nr * dr + ni * di) * inv;
     const double zi = (ni * dr - nr * di) * inv;
-    double pr = W.a[N - 1], pi = 0.0;
+    const double r2 = 2.0 * zr, s2 = __builtin_fma(zr, zr, zi * zi);
+    double b2 = W.a[N - 1];
+    double b1 = __builtin_fma(r2, b2, W.a[N - 2]);
 #pragma unroll
-    for (int k = N - 2; k >= 0; --k) {
-        const double t = __builtin_fma(pr, zr, __builtin_fma(-pi, zi, W.a[k]));
-        pi = __builtin_fma(pr, zi, pi * zr);
-        pr = t;
+    for (int k = N - 3; k >= 1; --k) {
+        const double b0 = __builtin_fma(r2, b1, __builtin_fma(-s2, b2, W.a[k]));
+        b2 = b1;
+        b1 = b0;
     }
+    const double pr = __builtin_fma(zr, b1, __builtin_fma(-s2, b2, W.a[0]));
+    const double pi = zi * b1;
     const double ir = dr * inv, ii = -di * inv;            // 1/(L - iz)
     const double i2r = ir * ir - ii * ii, i2i = 2.0 * ir * ii;
     cplx w;
