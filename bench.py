@@ -79,9 +79,9 @@ def zone_counts(cfg, d, T, P, chunk=1 << 24):
 # Valid only for the kernel sources they were taken with (hash below).
 TRAFFIC = {
     "kernel_sources": ['xs_forward_f32.hip', 'xs_forward_common.hpp', 'xs_voigt.hpp', 'xs_forward.hpp', 'xs_internal.hpp'],
-    "sha256": "19a79d8363a950acc4bd2852e256cbdf0f8492a2e1512c1c940d72b144bbbdc8",
-    "fetch_kib": [32066342.6, 36639946.8],
-    "write_kib": [251293.3, 251648.9],
+    "sha256": "6ee2ddda56d79131411875dd660c12a3b87398c83abe0e33957f3a1168db9dbe",
+    "fetch_kib": [32059778.7, 36637058.1],
+    "write_kib": [251303.2, 251660.8],
     "fetch_scale": 2.0,
     "write_scale": 1.0,
 }
