@@ -176,3 +176,27 @@ def test_nlte_state_errors():
     plan.set_vibrational_labels(None)                 # back to LTE
     plan.set_lines(d["upper"], d["lower"], d["A"], d["gamma_ref"], d["n_exp"])
     plan.cross_section_adjoint(800.0, 1.0, gbar, cfg.n_lines)
+
+
+def test_nlte_line_set_streamed_in_chunks():
+    # a stream rebuilds the line set per chunk: each chunk carries its states' vibrational
+    # energies, and the streamed sums match one call over the whole list (T_vib = T_rot
+    # there, as for every stream) and the oracle's non-LTE cross section at T_vib = T_rot
+    cfg, d = _case(6, n_lines=6000)
+    h = host(d)
+    T, P = 1100.0, 0.3
+    plan = _plan(cfg, d, "fp32")
+    direct = plan.cross_section([T], [P])[0].double().cpu().numpy()
+    st = plan.stream([T], [P])
+    hd = {k: v.cpu() for k, v in d.items()}
+    for a, b in ((0, 2500), (2500, 4000), (4000, 6000)):
+        st.chunk(hd["upper"][a:b].contiguous(), hd["lower"][a:b].contiguous(), hd["A"][a:b].contiguous(),
+                 hd["gamma_ref"][a:b].contiguous(), hd["n_exp"][a:b].contiguous())
+    sig, kept = st.end()
+    got = sig[0].double().cpu().numpy()
+    assert 0 < kept <= 6000
+    m = O.error_metrics(got, direct)
+    log(f"  non-LTE stream vs one call: max rel {m['max_rel']:.2e}")
+    assert m["max_rel"] <= 2e-6 and m["area_rel"] <= 2e-6
+    ref, _ = _oracle(h, cfg, T, T, P)
+    assert_parity(got, ref, TOL32, what="non-LTE stream vs oracle")
