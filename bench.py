@@ -79,9 +79,9 @@ def zone_counts(cfg, d, T, P, chunk=1 << 24):
 # Valid only for the kernel sources they were taken with (hash below).
 TRAFFIC = {
     "kernel_sources": ['xs_forward_f32.hip', 'xs_forward_common.hpp', 'xs_voigt.hpp', 'xs_forward.hpp', 'xs_internal.hpp'],
-    "sha256": "6ee2ddda56d79131411875dd660c12a3b87398c83abe0e33957f3a1168db9dbe",
-    "fetch_kib": [32059778.7, 36637058.1],
-    "write_kib": [251303.2, 251660.8],
+    "sha256": "e073df08eb72475ba41d313539d1af2b080a22e4aa47f006c19524c113cdc828",
+    "fetch_kib": [32092223.3, 36672779.1],
+    "write_kib": [251410.6, 251684.3],
     "fetch_scale": 2.0,
     "write_scale": 1.0,
 }

@@ -794,6 +794,14 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
                         // scalar copies of the line's integer geometry
                         const int kc = __builtin_amdgcn_readfirstlane(S.kc[i]);
                         const int rad = __builtin_amdgcn_readfirstlane(S.rad[i]);
+                        if (PROF == kVoigt &&
+                            !(rad >= 0 && (int64_t)w0 <= (int64_t)kc + rad && (int64_t)w1 >= (int64_t)kc - rad)) {
+                            // the line's mid zone (|z| < 40, which holds its core) misses the wave:
+                            // every point takes the far rule, as the per-slice tests below would
+#pragma unroll
+                            for (int p = 0; p < P; ++p) part[p] += v_far<PROF>(r, jl[p] + sb0);
+                            continue;
+                        }
                         const int kcl = __builtin_amdgcn_readfirstlane(S.kcl[i]);
                         const int kch = __builtin_amdgcn_readfirstlane(S.kch[i]);
                         const float csc = S.csc[i];
