@@ -34,18 +34,38 @@ sys.path.insert(0, ROOT)
 # accumulate FMA + rcp) 7; 2-node rule at |z| >= 40 (x, p, den, num, accumulate FMA + rcp)
 # 11; 4-node rule at 8 <= |z| < 40 (x + two node pairs of three FMA and a rcp + two
 # accumulate FMA) 20; a core value precomputed by the FP64 pre-pass, added: 1.
-ZONE_FLOPS = {"one_pole": 7, "two_node": 11, "four_node": 20, "core": 1}
+ZONE_FLOPS = {"one_pole": 7, "two_node": 11, "four_node": 20, "core": 1, "far_node": 11}
+FAR_NODES = 16        # far-wing nodes per wavefront of the FP32 Voigt sweep
 
 
-def zone_counts(cfg, d, T, P, chunk=1 << 24):
+def far_reach(ww):
+    """Grid steps between a wavefront of ww points and the nearest node-sampled line centre."""
+    return (24 * (ww - 1) + FAR_NODES - 2) // (FAR_NODES - 1)
+
+
+def zone_counts(cfg, d, T, P, waves=None, slices=None, chunk=1 << 24):
     """Window points of every line per zone at (T, P) (x = sqrt(ln2)(nu_k - nu)/alpha_D,
-    |z|^2 = x^2 + y^2, y = sqrt(ln2) gamma/alpha_D), counted from index ranges."""
+    |z|^2 = x^2 + y^2, y = sqrt(ln2) gamma/alpha_D), counted from index ranges.  With the
+    tile shape (waves, slices), the points of the (line, wavefront) pairs that the far-wing
+    kernel samples at FAR_NODES nodes are counted as far_node evaluations instead (the line
+    centre at least far_reach grid steps from the wavefront of 64 * slices points, its
+    window covering it: kc in [w1 - hmin, w0 - reach) or (w1 + reach, w0 + hmin])."""
     import torch
     kB, amu, c_si, ln2 = 1.380649e-23, 1.66053906660e-27, 299792458.0, math.log(2.0)
     beta = math.sqrt(2.0 * kB * T * ln2 / (cfg.mass_amu * amu)) / c_si
     E = d["E"]
     tot = {k: 0 for k in ZONE_FLOPS}
     n = d["upper"].numel()
+    far = waves is not None
+    if far:
+        ww = 64 * slices
+        reach = far_reach(ww)
+        dnu = (cfg.nu_b - cfg.nu_a) / (cfg.n_points - 1)
+        hmin = math.floor(cfg.cutoff / dnu) - 2
+        n_waves = -(-cfg.n_points // (waves * ww)) * waves
+        # the sampled lines must lie beyond the |z| < 40 radius of every wavefront
+        rm_max = 40.0 * beta * (cfg.nu_b + cfg.cutoff) / (math.sqrt(ln2) * dnu) + 3.0
+        assert reach >= rm_max, "far-wing reach inside the |z| < 40 radius: counts would not match"
     for a in range(0, n, chunk):
         b = min(n, a + chunk)
         nu = E[d["upper"][a:b].long()] - E[d["lower"][a:b].long()]
@@ -65,6 +85,33 @@ def zone_counts(cfg, d, T, P, chunk=1 << 24):
         n_x = inside(torch.full_like(nu, 1000.0))
         n_40 = inside(torch.sqrt(torch.clamp(1600.0 - y2, min=0.0)))
         n_8 = inside(torch.sqrt(torch.clamp(64.0 - y2, min=0.0)))
+        if far:
+            kc = torch.floor((nu - cfg.nu_a) / cfg.dnu + 0.5)
+            R = 1000.0 / s   # |x| < 1000 range, as in inside()
+            xlo = torch.maximum(torch.floor((nu - R - cfg.nu_a) / cfg.dnu) + 1, klo)
+            xhi = torch.minimum(torch.ceil((nu + R - cfg.nu_a) / cfg.dnu) - 1, khi)
+            live = n_all > 0
+
+            def span(ia, ib):   # far wavefronts [ia, ib]: count, their window points, those at |x| < 1000
+                ia = torch.clamp(ia, min=0)
+                ib = torch.clamp(ib, max=n_waves - 1)
+                nw = torch.where(live, torch.clamp(ib - ia + 1, min=0), torch.zeros_like(ia))
+                a = torch.maximum(ia * ww, klo)
+                b = torch.minimum(ib * ww + ww - 1, khi)
+                pts = torch.where(nw > 0, torch.clamp(b - a + 1, min=0), torch.zeros_like(a))
+                two = torch.where(nw > 0, torch.clamp(torch.minimum(b, xhi) - torch.maximum(a, xlo) + 1, min=0),
+                                  torch.zeros_like(a))
+                return nw, pts, two
+
+            # wavefronts right of the line (left-hand runs) and left of it (right-hand runs)
+            rw = span(torch.floor((kc + reach) / ww) + 1, torch.floor((kc + hmin - ww + 1) / ww))
+            lw = span(torch.floor((kc - hmin - 1) / ww) + 1, torch.floor((kc - reach - ww) / ww))
+            n_far = rw[0] + lw[0]
+            pts_far = rw[1] + lw[1]
+            two_far = rw[2] + lw[2]
+            tot["far_node"] += FAR_NODES * int(n_far.sum().item())
+            tot["one_pole"] -= int((pts_far - two_far).sum().item())
+            tot["two_node"] -= int(two_far.sum().item())
         tot["one_pole"] += int((n_all - n_x).sum().item())
         tot["two_node"] += int((n_x - n_40).sum().item())
         tot["four_node"] += int((n_40 - n_8).sum().item())
@@ -268,13 +315,13 @@ def main():
     tp_per_launch = kt["forward_tp"] / kt["forward_launches"]
     fwd_s_per_tp = kt["forward_ms"] / kt["forward_tp"] / 1e3
     # region-weighted algorithmic flops of the timed launches (every step covers all (T, P))
-    zones = [zone_counts(cfg, d, T, P) for T, P in zip(temps, pressures)]
+    tile = plan.tile_config()
+    zones = [zone_counts(cfg, d, T, P, tile["waves"], tile["slices"]) for T, P in zip(temps, pressures)]
     flops_step = sum(sum(ZONE_FLOPS[k] * z[k] for k in ZONE_FLOPS) for z in zones)
     launches_per_step = kt["forward_launches"] / args.steps
     flops_per_launch = flops_step / launches_per_step
     achieved = flops_per_launch / avg_launch_s / 1e12
     flops_per_eval = flops_step / (evals_per_tp * len(temps))
-    tile = plan.tile_config()
 
     result = {
         "metric": "Voigt line-profiles/s at 25 cm^-1 cutoff",
@@ -309,7 +356,8 @@ def main():
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_TFLOPS,
             "traffic": traffic_bytes_per_launch(tp_per_launch),
-            "kernel": "fwd_f32_kernel<Voigt> (tile kernel, one launch per block of (T,P))",
+            "kernel": "forward launch: fwd_f32_kernel<Voigt> (tile kernel) + far_kernel (node-sampled "
+                      "far wing), one of each per block of (T,P)",
             "avg_launch_ms": avg_launch_s * 1e3,
             "tp_per_launch": tp_per_launch,
             "algorithmic_flops_per_launch": flops_per_launch,

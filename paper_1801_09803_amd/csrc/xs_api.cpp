@@ -126,6 +126,7 @@ struct Workset {
     DevBuf th_bsum, th_tmp;   // intensity threshold: block counts, scan scratch per row
     DevBuf th_pos, th_map, th_offs;   // per row: positions [n+1], kept lines [n], offsets [nkeys+1]
     DevBuf part;              // per-part sums [tp_block][n_split][n_points] when n_split > 1
+    DevBuf far;               // FP32 Voigt: node-sampled far-wing sums [tp_block][kFarShares][n_points]
     DevBuf out;               // autotuner output scratch
     size_t bytes = 0;
     Stage stage;
@@ -135,7 +136,7 @@ struct Workset {
     xs_status ensure(DevBuf& b, size_t n, const char* what) { return dev_ensure(b, n, what, &bytes); }
     void release() {
         DevBuf* all[] = {&T, &Q, &dQ, &qpart, &tps, &rc, &cnt, &coff, &bsum, &tmp, &val, &hot, &cold, &xscale,
-                         &vv, &sl, &th_bsum, &th_tmp, &th_pos, &th_map, &th_offs, &part, &out};
+                         &vv, &sl, &th_bsum, &th_tmp, &th_pos, &th_map, &th_offs, &part, &far, &out};
         for (DevBuf* b : all) dev_release(*b, &bytes);
         stage.release();
         rows = 0;
@@ -412,6 +413,11 @@ xs::TPParam make_tp(const xs_plan* p, double T, double P, int iq, double T_rm) {
 // Vectorized Voigt pre-pass needed: continuity factors or area normalisation
 bool vv_needed(const xs_plan* p) { return is_vv(p) && (p->o.vv_beta || p->o.profile == XS_VVOIGT_NORM); }
 
+// FP32 Voigt: the segmented sweep leaves lines far from a wavefront to the node-sampled
+// far-wing kernel, whose per-share sums need a buffer of at most kFarShares shares
+constexpr int kFarShares = 4;
+bool far_sampled(const xs_plan* p) { return p->o.precision == XS_FP32 && p->o.profile == XS_VOIGT; }
+
 // Profile index of the kernels (the area-normalised form differs in its intensities only)
 int kernel_profile(const xs_plan* p) {
     switch (p->o.profile) {
@@ -536,6 +542,10 @@ xs_status ensure_rows(xs_plan* p, Workset& ws, int B, int S) {
         const size_t elem = p->o.precision == XS_FP64 ? sizeof(double) : 2 * sizeof(float);
         XS_TRY(ws.ensure(ws.part, (size_t)B * S * (size_t)p->geo.n_points * elem, "split partial sums"));
     }
+    if (far_sampled(p)) {
+        XS_TRY(ws.ensure(ws.far, (size_t)B * kFarShares * (size_t)p->geo.n_points * sizeof(double),
+                         "far-wing sums"));
+    }
     return XS_OK;
 }
 
@@ -615,6 +625,12 @@ xs::FwdArgs fwd_args(xs_plan* p, Workset& ws, const std::vector<xs::TPParam>& tp
     if (superlines(p)) {
         a.line_S = as<double>(ws.sl) + (int64_t)row0 * ws.row_stride;
         a.line_S_stride = ws.row_stride;
+    }
+    if (far_sampled(p) && a.seg && records_path(p)) {
+        // enough wavefronts to fill the chip: shares of the far lines of each wavefront
+        const int64_t nw = std::max<int64_t>(1, (int64_t)a.n_tiles * p->waves * nb);
+        a.far = as<double>(ws.far);
+        a.far_share = (int)std::min<int64_t>(kFarShares, std::max<int64_t>(1, (16384 + nw - 1) / nw));
     }
     return a;
 }
@@ -767,7 +783,7 @@ xs_status enqueue_block(xs_plan* p, Workset& ws, const std::vector<xs::TPParam>&
             XS_HIP(xs::launch_forward(kernel_profile(p), fp64 ? 1 : 0, p->waves, p->P, a, s));
             tf.stop();
         }
-        if (S > 1) {
+        if (S > 1 || a.far) {
             Timer tm(p, s, 3, r1 - r0, timed);
             XS_HIP(xs::launch_combine(fp64 ? 1 : 0, a, s));
             tm.stop();
@@ -1469,7 +1485,7 @@ xs_status xs_autotune(xs_plan* p, int32_t n_tp, const double* T, const double* P
             const int nb = std::min(B, ns - f);
             const xs::FwdArgs a = fwd_args(p, ws, tps, f, nb, f, S, ws.out.p);
             XS_HIP(xs::launch_forward(kernel_profile(p), fp64 ? 1 : 0, w, sl, a, s));
-            if (S > 1) XS_HIP(xs::launch_combine(fp64 ? 1 : 0, a, s));
+            XS_HIP(xs::launch_combine(fp64 ? 1 : 0, a, s));
         }
         XS_HIP(hipEventRecord(e1, s));
         XS_HIP(hipEventSynchronize(e1));

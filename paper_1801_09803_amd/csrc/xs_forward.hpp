@@ -80,6 +80,10 @@ struct FwdArgs {
     int64_t map_stride;
     const int* offs;
     int64_t offs_stride;
+    // FP32 Voigt segmented sweep: node-sampled far-wing sums of far_kernel, FP64
+    // [n_tp][far_share][n_points], added by launch_combine; NULL: the tile kernel sums every line
+    double* far;
+    int far_share;
 };
 
 // Sorted line index of the launch's line g (through the threshold map when there is one).
@@ -161,7 +165,9 @@ hipError_t launch_forward(int profile, int fp64, int waves, int slices_per_wave,
 // Super-line histograms: sigma[t][k] = (sum of the intensities of the lines with kc == k) / dnu
 // for the launch's (T, P) block (one thread per grid point; lines of a bin in sorted order).
 hipError_t launch_superlines(int fp64, const FwdArgs& a, hipStream_t s);
-// n_split > 1: sigma[t][k] = compensated sum over parts of part[t][*][k]
+// n_split > 1: sigma[t][k] = compensated sum over parts of part[t][*][k]; with far sums,
+// sigma[t][k] (the parts' sum, or the tile kernel's value when n_split = 1) plus the sum over
+// shares of far[t][*][k].  Nothing to do otherwise.
 hipError_t launch_combine(int fp64, const FwdArgs& a, hipStream_t s);
 
 // Streaming accumulators: acc holds n (sum, compensation) pairs, float2 (FP32) or

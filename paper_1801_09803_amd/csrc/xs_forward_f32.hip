@@ -503,6 +503,47 @@ __device__ __forceinline__ Prefetch<NQ> load_batch(const FwdArgs& A, const int* 
     return f;
 }
 
+// Node-sampled Voigt far wing (segmented sweep): lines whose centre lies at least
+// far_reach(WW) grid steps from every point of a wavefront of WW points add their 2-node
+// values at kFarN equispaced nodes across it (far_kernel), interpolated to its points; the
+// tile kernel leaves them out.  Such a wing is a smooth rational function of the distance;
+// with an 8-point Lagrange stencil and 24 node spacings between the nearest centre and the
+// wavefront its interpolation error stays below 3e-8 relative.
+constexpr int kFarN = 16;
+constexpr int far_reach(int ww) { return (24 * (ww - 1) + kFarN - 2) / (kFarN - 1); }
+
+// Radius (grid steps) of the |z| < 40 zone of the lines whose centre can lie near the
+// wavefront [w0, w1]: their wavenumbers, hence Doppler widths, are bounded there.
+__device__ __forceinline__ int wave_rm(const TPParam& tp, const Geometry& G, int w0, int w1) {
+    int rm = tp.rm;
+    if (tp.rm_scale > 0.0) {
+        const double nlo = G.nu_a + ((double)w0 - rm - 1) * G.dnu;
+        const double nhi = G.nu_a + ((double)w1 + rm + 1) * G.dnu;
+        const double rw = ceil(tp.rm_scale * fmax(fabs(nlo), fabs(nhi))) + 2.0;
+        if (rw < (double)rm) rm = __builtin_amdgcn_readfirstlane((int)rw);
+    }
+    return rm;
+}
+
+// The wing-only runs of the wavefront [w0, w1] (windows covering it, centres beyond rm)
+// are [s1, s2) left and [s3, s4) right; of them, [s1, hcl) (kc < w0 - reach) and
+// [hcr, s4) (kc > w1 + reach) are node-sampled.
+struct FarRange {
+    int s1, hcl, hcr, s4;
+};
+
+__device__ __forceinline__ FarRange far_range(const int* off, const Geometry& G, int w0, int w1, int rm, int reach) {
+    const int64_t l0 = (int64_t)w1 - G.hmin, l1 = (int64_t)w0 - rm;
+    const int64_t r0 = (int64_t)w1 + rm + 1, r1 = (int64_t)w0 + G.hmin + 1;
+    auto cl = [](int64_t v, int64_t lo, int64_t hi) { return v < lo ? lo : (v > hi ? hi : v); };
+    FarRange f;
+    f.s1 = off_at(off, l0, G);
+    f.s4 = off_at(off, r1, G);
+    f.hcl = off_at(off, cl((int64_t)w0 - reach, l0, l1), G);
+    f.hcr = off_at(off, cl((int64_t)w1 + reach + 1, r0, r1), G);
+    return f;
+}
+
 template <int PROF, int WAVES, int P, bool SEG>
 __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
     constexpr int NT = 64 * WAVES;       // threads = lines per LDS batch
@@ -547,17 +588,11 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
     const int bstride = NT * A.n_split;
     const int bfirst = b0 + NT * wi.part;
     const int rm_tile = tp.rm;
-    int rm = tp.rm;
-    if (SEG && tp.rm_scale > 0.0) {
-        // the centre-near run holds lines with kc within rm of the wave, i.e. wavenumbers
-        // inside [nlo, nhi]; their Doppler widths, hence the radius, are bounded there
-        const double nlo = G.nu_a + ((double)w0 - rm - 1) * G.dnu;
-        const double nhi = G.nu_a + ((double)w1 + rm + 1) * G.dnu;
-        const double rw = ceil(tp.rm_scale * fmax(fabs(nlo), fabs(nhi))) + 2.0;
-        if (rw < (double)rm) rm = __builtin_amdgcn_readfirstlane((int)rw);
-    }
+    // the centre-near run holds lines with kc within rm of the wave
+    const int rm = SEG ? wave_rm(tp, G, w0, w1) : tp.rm;
     int s0 = 0, s1 = 0, s2 = 0, s3 = 0, s4 = 0, s5 = 0;
     int ha = 0, hb = 0, hc = 0, hd = 0;
+    int hcl = 0, hcr = 0;   // node-sampled lines (far_kernel): [s1, hcl) left, [hcr, s4) right
     if (SEG) {
         s0 = off_at(off, (int64_t)w0 - G.hmax, G);
         s1 = off_at(off, (int64_t)w1 - G.hmin, G);
@@ -592,6 +627,13 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
             hb = off_at(off, cl((int64_t)w1 - G.rvmin, l0, l1), G);
             hc = off_at(off, cl((int64_t)w0 + G.rvmin + 1, r0, r1), G);
             hd = off_at(off, cl((int64_t)w1 + G.rvmax + 1, r0, r1), G);
+        }
+        hcl = s1;
+        hcr = s4;
+        if (PROF == kVoigt && A.far) {
+            const FarRange fr = far_range(off, G, w0, w1, rm, far_reach(WW));
+            hcl = fr.hcl;
+            hcr = fr.hcr;
         }
     }
 
@@ -753,14 +795,16 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
                             }
                         }
                     }
-                    // ---- wing-only runs from the anchor, no branches
+                    // ---- wing-only runs from the anchor, no branches (without the
+                    // node-sampled lines)
                     {
-                        const int lo2 = cs > s1 ? cs : s1, hi2 = ce < s2 ? ce : s2;
-                        const int lo4 = cs > s3 ? cs : s3, hi4 = ce < s4 ? ce : s4;
+                        const int lo2 = cs > hcl ? cs : hcl, hi2 = ce < s2 ? ce : s2;
+                        const int lo4 = cs > s3 ? cs : s3, hi4 = ce < hcr ? ce : hcr;
                         // pieces: [lo2, xa) and [xd, hi4) beyond R (Vectorized Voigt) or beyond
                         // the far-wing radius (Voigt), [xb, hi2) and [lo4, xc) inside
-                        const int xa = ce < ha ? ce : ha, xb = cs > hb ? cs : hb;
-                        const int xc = ce < hc ? ce : hc, xd = cs > hd ? cs : hd;
+                        const int xa = ce < ha ? ce : ha, xb0 = cs > hb ? cs : hb;
+                        const int xc0 = ce < hc ? ce : hc, xd = cs > hd ? cs : hd;
+                        const int xb = xb0 > lo2 ? xb0 : lo2, xc = xc0 < hi4 ? xc0 : hi4;
                         const float kl = (float)(wave * WW), kr = (float)(wave * WW + WW - 1);
                         if constexpr (!ANCH) {
                             wing_runs<PROF, P, RS, -1>(rec, S.sb0, kl, kr, bs, lo2, hi2, lo4, hi4, xa, xb, xc, xd, jlo_w,
@@ -944,12 +988,102 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
     }
 }
 
+// Node-sampled Voigt far wing: one wavefront per (wavefront tile wv, (T, P), share q), the
+// share taking chunks q, q + far_share, ... of 64 lines of [s1, hcl) and [hcr, s4), one line
+// per lane, FP64 sums per lane and node; then the wavefront's node totals, interpolated to
+// its points, go to far[tp][q][k] (every point of the wavefront is written, zeros included).
+template <int P>
+__global__ __launch_bounds__(256) void far_kernel(const FwdArgs A, int n_waves) {
+    constexpr int WW = 64 * P;
+    using L = HotOf<kVoigt>;
+    __shared__ double tl[4][kFarN];
+    const int lane = threadIdx.x & 63, wl = threadIdx.x >> 6;
+    const int64_t gw = (int64_t)blockIdx.x * 4 + wl;
+    if (gw >= (int64_t)n_waves * A.n_tp * A.far_share) return;   // whole wavefronts; no block barrier
+    const int q = (int)(gw % A.far_share);
+    const int64_t rest = gw / A.far_share;
+    const int it = (int)(rest % A.n_tp);
+    const int wv = (int)(rest / A.n_tp);
+    const Geometry G = A.G;
+    const TPParam tp = A.tps[it];
+    const int w0 = wv * WW, w1 = w0 + WW - 1;
+    const int* map = A.map ? A.map + (int64_t)it * A.map_stride : nullptr;
+    const int* off = A.offs ? A.offs + (int64_t)it * A.offs_stride : A.off;
+    const float* hot = A.hot + (int64_t)it * A.rec_stride * kHot;
+    const FarRange fr = far_range(off, G, w0, w1, wave_rm(tp, G, w0, w1), far_reach(WW));
+    double acc[kFarN];
+#pragma unroll
+    for (int m = 0; m < kFarN; ++m) acc[m] = 0.0;
+    for (int side = 0; side < 2; ++side) {
+        const int lo = side ? fr.hcr : fr.s1, hi = side ? fr.s4 : fr.hcl;
+        for (int c = lo + 64 * q; c < hi; c += 64 * A.far_share) {
+            const int l = c + lane;
+            if (l < hi) {
+                const float4 h4 = *reinterpret_cast<const float4*>(hot + (int64_t)l * kHot);   // H, C0, C1, AMP
+                const float2 h2 = *reinterpret_cast<const float2*>(hot + (int64_t)l * kHot + L::B);   // B, XC
+                static_assert(L::H == 0 && L::C0 == 1 && L::C1 == 2 && L::AMP == 3 && L::XC == L::B + 1, "layout");
+                const int kc = A.L.kc[line_of(map, l)];
+                const float x0 = __builtin_fmaf((float)(w0 - kc), h4.x, h2.y);   // x at w0
+#pragma unroll
+                for (int m = 0; m < kFarN; ++m) {
+                    const float x = __builtin_fmaf((float)(m * ((double)(WW - 1) / (kFarN - 1))), h4.x, x0);
+                    const float pp = __builtin_fmaf(x, x, h4.y);
+                    const float den = __builtin_fmaf(pp, pp, h4.z);
+                    const float num = __builtin_fmaf(pp, h4.w, h2.x);
+                    // product in FP64: no single-precision rounding of tiny values
+                    acc[m] = __builtin_fma((double)num, (double)__builtin_amdgcn_rcpf(den), acc[m]);
+                }
+            }
+        }
+    }
+    // node totals over the wavefront (every lane ends with all of them), through LDS to
+    // index them by point
+#pragma unroll
+    for (int m = 0; m < kFarN; ++m) {
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) acc[m] += __shfl_xor(acc[m], o, 64);
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int m = 0; m < kFarN; ++m) tl[wl][m] = acc[m];
+    }
+    __builtin_amdgcn_wave_barrier();
+    // 8-point Lagrange weights 1 / prod_{b != a} (a - b)
+    constexpr double den8[8] = {-1.0 / 5040, 1.0 / 720, -1.0 / 240, 1.0 / 144,
+                                -1.0 / 144, 1.0 / 240, -1.0 / 720, 1.0 / 5040};
+    double* out = A.far + ((int64_t)it * A.far_share + q) * G.n_points;
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        const int o = 64 * p + lane;
+        const double u = (double)(o * (kFarN - 1)) / (double)(WW - 1);   // position in node spacings
+        int i0 = (int)floor(u) - 3;
+        i0 = i0 < 0 ? 0 : (i0 > kFarN - 8 ? kFarN - 8 : i0);
+        const double t = u - (double)i0;
+        double v = 0.0;
+#pragma unroll
+        for (int a = 0; a < 8; ++a) {
+            double w = den8[a];
+#pragma unroll
+            for (int b = 0; b < 8; ++b)
+                if (b != a) w *= t - (double)b;
+            v = __builtin_fma(w, tl[wl][i0 + a], v);
+        }
+        const int k = w0 + o;
+        if (k < G.n_points) out[k] = v;
+    }
+}
+
 template <int PROF, int WAVES, int P>
 void launch_one(const FwdArgs& a, hipStream_t s) {
     const dim3 grid((unsigned)((int64_t)a.n_tiles * a.n_tp * a.n_split)), block(64 * WAVES);
     constexpr bool CAN_SEG = PROF <= kVoigt || PROF == kVVoigt;
     if (CAN_SEG && a.seg) hipLaunchKernelGGL((fwd_f32_kernel<PROF, WAVES, P, CAN_SEG>), grid, block, 0, s, a);
     else hipLaunchKernelGGL((fwd_f32_kernel<PROF, WAVES, P, false>), grid, block, 0, s, a);
+    if (PROF == kVoigt && a.seg && a.far) {
+        const int n_waves = a.n_tiles * WAVES;
+        const int64_t total = (int64_t)n_waves * a.n_tp * a.far_share;
+        hipLaunchKernelGGL(far_kernel<P>, dim3((unsigned)((total + 3) / 4)), dim3(256), 0, s, a, n_waves);
+    }
 }
 
 template <int PROF>

@@ -278,6 +278,35 @@ __global__ __launch_bounds__(256) void combine_f32_kernel(const float2* part, fl
     sigma[i] = s + c;
 }
 
+// The same with the far-wing sums of far_kernel: (parts' compensated sum, or sigma as the
+// tile kernel wrote it when n_split = 1) + the FP64 sum over shares, rounded once.
+__global__ __launch_bounds__(256) void combine_far_kernel(const float2* part, const double* far, float* sigma,
+                                                          int n_split, int far_share, int n_points, int64_t total) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= total) return;
+    const int64_t t = i / n_points, k = i - t * n_points;
+    double base;
+    if (n_split > 1) {
+        const float2* p = part + t * n_split * (int64_t)n_points + k;
+        float s = 0.0f, c = 0.0f;
+        for (int q = 0; q < n_split; ++q) {
+            const float2 v = p[(int64_t)q * n_points];
+            const float u = s + v.x;
+            const float bp = u - s;
+            c += (s - (u - bp)) + (v.x - bp);
+            c += v.y;
+            s = u;
+        }
+        base = (double)s + (double)c;
+    } else {
+        base = (double)sigma[i];
+    }
+    const double* f = far + t * far_share * (int64_t)n_points + k;
+    double fs = 0.0;
+    for (int q = 0; q < far_share; ++q) fs += f[(int64_t)q * n_points];
+    sigma[i] = (float)(base + fs);
+}
+
 __global__ __launch_bounds__(256) void combine_f64_kernel(const double* part, double* sigma, int n_split,
                                                           int n_points, int64_t total) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -292,11 +321,15 @@ __global__ __launch_bounds__(256) void combine_f64_kernel(const double* part, do
 }  // namespace
 
 hipError_t launch_combine(int fp64, const FwdArgs& a, hipStream_t s) {
-    if (a.n_split <= 1) return hipSuccess;
+    const bool far = !fp64 && a.far && a.seg;
+    if (a.n_split <= 1 && !far) return hipSuccess;
     const int64_t total = (int64_t)a.n_tp * a.G.n_points;
     if (total == 0) return hipSuccess;
     const dim3 grid((unsigned)((total + 255) / 256)), block(256);
-    if (fp64)
+    if (far)
+        hipLaunchKernelGGL(combine_far_kernel, grid, block, 0, s, static_cast<const float2*>(a.part), a.far,
+                           static_cast<float*>(a.sigma), a.n_split, a.far_share, a.G.n_points, total);
+    else if (fp64)
         hipLaunchKernelGGL(combine_f64_kernel, grid, block, 0, s, static_cast<const double*>(a.part),
                            static_cast<double*>(a.sigma), a.n_split, a.G.n_points, total);
     else
