@@ -988,18 +988,21 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
     }
 }
 
-// Node-sampled Voigt far wing: one wavefront per (wavefront tile wv, (T, P), share q), the
-// share taking chunks q, q + far_share, ... of 64 lines of [s1, hcl) and [hcr, s4), one line
-// per lane, FP64 sums per lane and node; then the wavefront's node totals, interpolated to
-// its points, go to far[tp][q][k] (every point of the wavefront is written, zeros included).
+// Node-sampled Voigt far wing: one wavefront per (wavefront tile wv, (T, P), share q).  The
+// lines [s1, hcl) and [hcr, s4), taken as one sequence, go in chunks q, q + far_share, ...
+// of 64, one line per lane (the next chunk's line data loaded while the current one is
+// summed), with FP64 sums per lane and node; then the wavefront's node totals, interpolated
+// to its points, go to far[tp][q][k] (every point of the wavefront, zeros included).
 template <int P>
 __global__ __launch_bounds__(256) void far_kernel(const FwdArgs A, int n_waves) {
     constexpr int WW = 64 * P;
     using L = HotOf<kVoigt>;
+    static_assert(L::H == 0 && L::C0 == 1 && L::C1 == 2 && L::AMP == 3 && L::XC == L::B + 1, "layout");
     __shared__ double tl[4][kFarN];
     const int lane = threadIdx.x & 63, wl = threadIdx.x >> 6;
+    const int64_t total = (int64_t)n_waves * A.n_tp * A.far_share;
     const int64_t gw = (int64_t)blockIdx.x * 4 + wl;
-    if (gw >= (int64_t)n_waves * A.n_tp * A.far_share) return;   // whole wavefronts; no block barrier
+    if (gw >= total) return;   // whole wavefronts; no block barrier
     const int q = (int)(gw % A.far_share);
     const int64_t rest = gw / A.far_share;
     const int it = (int)(rest % A.n_tp);
@@ -1011,31 +1014,61 @@ __global__ __launch_bounds__(256) void far_kernel(const FwdArgs A, int n_waves) 
     const int* off = A.offs ? A.offs + (int64_t)it * A.offs_stride : A.off;
     const float* hot = A.hot + (int64_t)it * A.rec_stride * kHot;
     const FarRange fr = far_range(off, G, w0, w1, wave_rm(tp, G, w0, w1), far_reach(WW));
+    const int nl = fr.hcl - fr.s1, nv = nl + (fr.s4 - fr.hcr);
+    const int step = 64 * A.far_share;
+    // per lane and node: FP32 sums of up to four lines, added to FP64 sums; amplitudes
+    // scaled by 2^32 (exact) keep tiny values out of the single-precision subnormal range
+    constexpr float kUp = 4294967296.0f;
     double acc[kFarN];
+    float a32[kFarN];
 #pragma unroll
-    for (int m = 0; m < kFarN; ++m) acc[m] = 0.0;
-    for (int side = 0; side < 2; ++side) {
-        const int lo = side ? fr.hcr : fr.s1, hi = side ? fr.s4 : fr.hcl;
-        for (int c = lo + 64 * q; c < hi; c += 64 * A.far_share) {
-            const int l = c + lane;
-            if (l < hi) {
-                const float4 h4 = *reinterpret_cast<const float4*>(hot + (int64_t)l * kHot);   // H, C0, C1, AMP
-                const float2 h2 = *reinterpret_cast<const float2*>(hot + (int64_t)l * kHot + L::B);   // B, XC
-                static_assert(L::H == 0 && L::C0 == 1 && L::C1 == 2 && L::AMP == 3 && L::XC == L::B + 1, "layout");
-                const int kc = A.L.kc[line_of(map, l)];
-                const float x0 = __builtin_fmaf((float)(w0 - kc), h4.x, h2.y);   // x at w0
+    for (int m = 0; m < kFarN; ++m) {
+        acc[m] = 0.0;
+        a32[m] = 0.0f;
+    }
+    // line data of entry v of the sequence: H, C0, C1, AMP; B, XC; kc
+    float4 h4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    float2 h2 = make_float2(0.f, 0.f);
+    int kc = 0;
+    auto fetch = [&](int v) {
+        if (v < nv) {
+            const int l = v < nl ? fr.s1 + v : fr.hcr + (v - nl);
+            h4 = *reinterpret_cast<const float4*>(hot + (int64_t)l * kHot);
+            h2 = *reinterpret_cast<const float2*>(hot + (int64_t)l * kHot + L::B);
+            kc = A.L.kc[line_of(map, l)];
+        }
+    };
+    fetch(64 * q + lane);
+    int nacc = 0;
+    for (int c = 64 * q; c < nv; c += step) {
+        const bool in = c + lane < nv;
+        const float4 a4 = h4;
+        const float2 a2 = h2;
+        const int akc = kc;
+        fetch(c + step + lane);
+        if (in) {
+            const float x0 = __builtin_fmaf((float)(w0 - akc), a4.x, a2.y);   // x at w0
+            const float amp = a4.w * kUp, bb = a2.x * kUp;
 #pragma unroll
-                for (int m = 0; m < kFarN; ++m) {
-                    const float x = __builtin_fmaf((float)(m * ((double)(WW - 1) / (kFarN - 1))), h4.x, x0);
-                    const float pp = __builtin_fmaf(x, x, h4.y);
-                    const float den = __builtin_fmaf(pp, pp, h4.z);
-                    const float num = __builtin_fmaf(pp, h4.w, h2.x);
-                    // product in FP64: no single-precision rounding of tiny values
-                    acc[m] = __builtin_fma((double)num, (double)__builtin_amdgcn_rcpf(den), acc[m]);
-                }
+            for (int m = 0; m < kFarN; ++m) {
+                const float x = __builtin_fmaf((float)(m * ((double)(WW - 1) / (kFarN - 1))), a4.x, x0);
+                const float pp = __builtin_fmaf(x, x, a4.y);
+                const float den = __builtin_fmaf(pp, pp, a4.z);
+                const float num = __builtin_fmaf(pp, amp, bb);
+                a32[m] = __builtin_fmaf(num, __builtin_amdgcn_rcpf(den), a32[m]);
+            }
+        }
+        if (++nacc == 4) {
+            nacc = 0;
+#pragma unroll
+            for (int m = 0; m < kFarN; ++m) {
+                acc[m] += (double)a32[m];
+                a32[m] = 0.0f;
             }
         }
     }
+#pragma unroll
+    for (int m = 0; m < kFarN; ++m) acc[m] = (acc[m] + (double)a32[m]) * (1.0 / 4294967296.0);
     // node totals over the wavefront (every lane ends with all of them), through LDS to
     // index them by point
 #pragma unroll
