@@ -126,9 +126,9 @@ def zone_counts(cfg, d, T, P, waves=None, slices=None, chunk=1 << 24):
 # Valid only for the kernel sources they were taken with (hash below).
 TRAFFIC = {
     "kernel_sources": ['xs_forward_f32.hip', 'xs_forward_common.hpp', 'xs_voigt.hpp', 'xs_forward.hpp', 'xs_internal.hpp'],
-    "sha256": "e073df08eb72475ba41d313539d1af2b080a22e4aa47f006c19524c113cdc828",
-    "fetch_kib": [32092223.3, 36672779.1],
-    "write_kib": [251410.6, 251684.3],
+    "sha256": "3254109e4a2063aa87ee9843bbfd8f1522c2ea18c957958c1fd1e96d02ab7eec",
+    "fetch_kib": [31087471.9, 35639616.5],
+    "write_kib": [251654.8, 251664.9],
     "fetch_scale": 2.0,
     "write_scale": 1.0,
 }
@@ -313,15 +313,34 @@ def main():
     ms_step = 1e3 * elapsed / args.steps
     avg_launch_s = kt["forward_ms"] / kt["forward_launches"] / 1e3
     tp_per_launch = kt["forward_tp"] / kt["forward_launches"]
-    fwd_s_per_tp = kt["forward_ms"] / kt["forward_tp"] / 1e3
+    # forward time per (T, P): tile kernel + node-sampled far-wing kernel
+    fwd_s_per_tp = (kt["forward_ms"] + kt["far_ms"]) / kt["forward_tp"] / 1e3
     # region-weighted algorithmic flops of the timed launches (every step covers all (T, P))
     tile = plan.tile_config()
     zones = [zone_counts(cfg, d, T, P, tile["waves"], tile["slices"]) for T, P in zip(temps, pressures)]
-    flops_step = sum(sum(ZONE_FLOPS[k] * z[k] for k in ZONE_FLOPS) for z in zones)
+    # the tile kernel evaluates the window points outside the node-sampled far wing
+    tile_zones = [k for k in ZONE_FLOPS if k != "far_node"]
+    flops_step = sum(sum(ZONE_FLOPS[k] * z[k] for k in tile_zones) for z in zones)
+    tile_points_step = sum(sum(z[k] for k in tile_zones) for z in zones)
     launches_per_step = kt["forward_launches"] / args.steps
     flops_per_launch = flops_step / launches_per_step
     achieved = flops_per_launch / avg_launch_s / 1e12
-    flops_per_eval = flops_step / (evals_per_tp * len(temps))
+    flops_per_eval = flops_step / tile_points_step
+    # far-wing kernel: FAR_NODES 2-node evaluations per (line, wavefront) it samples; it
+    # reads 28 B of line data (hot record words and kc) per such pair
+    far_nodes_step = sum(z["far_node"] for z in zones)
+    far_s_step = kt["far_ms"] / 1e3 / args.steps
+    far_obj = None
+    if kt["far_launches"] > 0 and far_nodes_step > 0:
+        far_obj = {
+            "avg_launch_ms": kt["far_ms"] / kt["far_launches"],
+            "node_evaluations_per_tp": far_nodes_step / len(temps),
+            "achieved_tflops": ZONE_FLOPS["far_node"] * far_nodes_step / far_s_step / 1e12,
+            "line_data_GBps": 28.0 * far_nodes_step / FAR_NODES / far_s_step / 1e9,
+            "note": "node-sampled far wing (lines >= far_reach grid steps from a wavefront): 16 "
+                    "2-node evaluations per (line, wavefront) pair, 11 flops each, then one 8-point "
+                    "interpolation per wavefront; line data from L2/MALL",
+        }
 
     result = {
         "metric": "Voigt line-profiles/s at 25 cm^-1 cutoff",
@@ -356,8 +375,7 @@ def main():
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_TFLOPS,
             "traffic": traffic_bytes_per_launch(tp_per_launch),
-            "kernel": "forward launch: fwd_f32_kernel<Voigt> (tile kernel) + far_kernel (node-sampled "
-                      "far wing), one of each per block of (T,P)",
+            "kernel": "fwd_f32_kernel<Voigt> (tile kernel, one launch per block of (T,P))",
             "avg_launch_ms": avg_launch_s * 1e3,
             "tp_per_launch": tp_per_launch,
             "algorithmic_flops_per_launch": flops_per_launch,
@@ -366,10 +384,12 @@ def main():
             "zone_points_per_tp": {f"T={T}": z for T, z in zip(temps, zones)},
             "frac_of_unpacked_fp32": achieved / PEAK_FP32_UNPACKED,
         },
+        "far_wing_kernel": far_obj,
         "step_breakdown_ms": {
             "line_prep_and_sort": kt["prep_ms"] / args.steps,
             "voigt_core_prepass": kt["core_ms"] / args.steps,
             "tile_kernel": kt["forward_ms"] / args.steps,
+            "far_wing_kernel": kt["far_ms"] / args.steps,
             "split_combine": kt["combine_ms"] / args.steps,
         },
         "forward_line_profiles_per_s": n_kept / fwd_s_per_tp,
@@ -533,6 +553,7 @@ def threshold_leg(cfg, d, temps, pressures, tile, n_kept, stream, log):
     return {"mode": "hitran", "i_crit": 1e-29, "nu_crit": 2000.0, "call_ms": t * 1e3,
             "line_profiles_per_s_of_the_list": n_kept * len(temps) / t,
             "tile_kernel_ms_per_tp": kt["forward_ms"] / kt["forward_tp"],
+            "far_kernel_ms_per_tp": kt["far_ms"] / kt["forward_tp"],
             "pre_passes_ms_per_tp": kt["core_ms"] / (reps * len(temps)),
             "kept_share_per_tp": shares,
             "note": "throughput counts every line of the list (kept or dropped), as the headline does; "
@@ -590,6 +611,7 @@ def c3_leg(cfg3, d, tile, n_kept, stream, log):
         f"~{t64_all:.0f} s (from 3 points)")
     return {"n_tp": len(Ts), "call_s": t, "line_profiles_per_s": n_kept * len(Ts) / t,
             "tile_kernel_ms_per_tp": kt["forward_ms"] / kt["forward_tp"],
+            "far_kernel_ms_per_tp": kt["far_ms"] / kt["forward_tp"],
             "pre_passes_ms_per_tp": kt["core_ms"] / len(Ts),
             "tp_block": 0,
             "fp64_plain_s_per_tp": t64 / len(pick), "fp64_plain_s_extrapolated": t64_all,
@@ -668,6 +690,7 @@ def emission_leg(cfg, d, temps, pressures, tile, n_kept, stream, log):
         f"{t_w * 1e3:.2f} ms, moments (27 T) {t_m * 1e3:.3f} ms")
     return {"emission_call_ms": t_em * 1e3, "emission_line_profiles_per_s": n_kept * len(temps) / t_em,
             "emission_tile_kernel_ms_per_tp": kt["forward_ms"] / kt["forward_tp"],
+            "emission_far_kernel_ms_per_tp": kt["far_ms"] / kt["forward_tp"],
             "nlte_call_ms": t_nlte * 1e3, "nlte_line_profiles_per_s": n_kept * len(temps) / t_nlte,
             "nlte_T_vib": t_vib,
             "lifetimes_ms": t_tau * 1e3, "lifetimes_transitions_per_s": n_lines / t_tau,

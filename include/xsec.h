@@ -53,7 +53,7 @@
 extern "C" {
 #endif
 
-#define XS_ABI_VERSION 4
+#define XS_ABI_VERSION 5
 
 typedef struct xs_plan xs_plan;
 typedef struct xs_graph xs_graph;
@@ -421,6 +421,9 @@ typedef struct {
     double combine_ms;          /* sums of split tiles (n_split > 1)                       */
     int64_t combine_launches;
     int64_t forward_tp;         /* (T, P) results computed by the forward launches         */
+    double far_ms;              /* FP32 Voigt: node-sampled far-wing kernel (one launch per
+                                   forward launch of the segmented sweep)                  */
+    int64_t far_launches;
 } xs_timings;
 
 xs_status xs_set_timing(xs_plan* plan, int enable);

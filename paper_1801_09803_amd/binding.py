@@ -44,7 +44,8 @@ class XsKernelTimes(ctypes.Structure):
     _fields_ = [("forward_ms", ctypes.c_double), ("core_ms", ctypes.c_double), ("prep_ms", ctypes.c_double),
                 ("forward_launches", ctypes.c_int64), ("core_launches", ctypes.c_int64),
                 ("prep_launches", ctypes.c_int64), ("combine_ms", ctypes.c_double),
-                ("combine_launches", ctypes.c_int64), ("forward_tp", ctypes.c_int64)]
+                ("combine_launches", ctypes.c_int64), ("forward_tp", ctypes.c_int64),
+                ("far_ms", ctypes.c_double), ("far_launches", ctypes.c_int64)]
 
 
 _lib = None

@@ -158,8 +158,8 @@ struct xs_plan {
     xs_opts o{};
     bool timing = false;
     std::vector<TimedRange> timed;
-    double acc_ms[4] = {0, 0, 0, 0};
-    int64_t acc_n[4] = {0, 0, 0, 0};
+    double acc_ms[5] = {0, 0, 0, 0, 0};
+    int64_t acc_n[5] = {0, 0, 0, 0, 0};
     int64_t acc_tp = 0;
     xs::Geometry geo{};
     int P = 2;
@@ -782,6 +782,11 @@ xs_status enqueue_block(xs_plan* p, Workset& ws, const std::vector<xs::TPParam>&
             Timer tf(p, s, 0, r1 - r0, timed);
             XS_HIP(xs::launch_forward(kernel_profile(p), fp64 ? 1 : 0, p->waves, p->P, a, s));
             tf.stop();
+        }
+        if (a.far) {
+            Timer tw(p, s, 4, r1 - r0, timed);
+            XS_HIP(xs::launch_far(p->waves, p->P, a, s));
+            tw.stop();
         }
         if (S > 1 || a.far) {
             Timer tm(p, s, 3, r1 - r0, timed);
@@ -1485,6 +1490,7 @@ xs_status xs_autotune(xs_plan* p, int32_t n_tp, const double* T, const double* P
             const int nb = std::min(B, ns - f);
             const xs::FwdArgs a = fwd_args(p, ws, tps, f, nb, f, S, ws.out.p);
             XS_HIP(xs::launch_forward(kernel_profile(p), fp64 ? 1 : 0, w, sl, a, s));
+            if (a.far) XS_HIP(xs::launch_far(w, sl, a, s));
             XS_HIP(xs::launch_combine(fp64 ? 1 : 0, a, s));
         }
         XS_HIP(hipEventRecord(e1, s));
@@ -1814,7 +1820,7 @@ xs_status xs_set_timing(xs_plan* p, int enable) {
     if (!p) return fail(XS_ERR_ARG, "plan is NULL");
     if (enable) {
         p->drop_timed();
-        for (int k = 0; k < 4; ++k) { p->acc_ms[k] = 0; p->acc_n[k] = 0; }
+        for (int k = 0; k < 5; ++k) { p->acc_ms[k] = 0; p->acc_n[k] = 0; }
         p->acc_tp = 0;
     }
     p->timing = enable != 0;
@@ -1841,6 +1847,8 @@ xs_status xs_kernel_times(xs_plan* p, xs_timings* out) {
     out->combine_ms = p->acc_ms[3];
     out->combine_launches = p->acc_n[3];
     out->forward_tp = p->acc_tp;
+    out->far_ms = p->acc_ms[4];
+    out->far_launches = p->acc_n[4];
     return XS_OK;
 }
 

@@ -162,6 +162,9 @@ inline int tile_points(int slices_per_wave, int waves) { return 64 * waves * sli
 
 hipError_t launch_forward(int profile, int fp64, int waves, int slices_per_wave, const FwdArgs& a,
                           hipStream_t s);
+// FP32 Voigt segmented sweep (a.far set): the node-sampled far wing of the lines the tile
+// kernel leaves out, into a.far; launch after launch_forward, before launch_combine.
+hipError_t launch_far(int waves, int P, const FwdArgs& a, hipStream_t s);
 // Super-line histograms: sigma[t][k] = (sum of the intensities of the lines with kc == k) / dnu
 // for the launch's (T, P) block (one thread per grid point; lines of a bin in sorted order).
 hipError_t launch_superlines(int fp64, const FwdArgs& a, hipStream_t s);

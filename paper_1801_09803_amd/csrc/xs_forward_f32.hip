@@ -1112,11 +1112,6 @@ void launch_one(const FwdArgs& a, hipStream_t s) {
     constexpr bool CAN_SEG = PROF <= kVoigt || PROF == kVVoigt;
     if (CAN_SEG && a.seg) hipLaunchKernelGGL((fwd_f32_kernel<PROF, WAVES, P, CAN_SEG>), grid, block, 0, s, a);
     else hipLaunchKernelGGL((fwd_f32_kernel<PROF, WAVES, P, false>), grid, block, 0, s, a);
-    if (PROF == kVoigt && a.seg && a.far) {
-        const int n_waves = a.n_tiles * WAVES;
-        const int64_t total = (int64_t)n_waves * a.n_tp * a.far_share;
-        hipLaunchKernelGGL(far_kernel<P>, dim3((unsigned)((total + 3) / 4)), dim3(256), 0, s, a, n_waves);
-    }
 }
 
 template <int PROF>
@@ -1151,6 +1146,19 @@ hipError_t launch_records(int profile, const RecArgs& a, hipStream_t s) {
         case kDopplerBinned: hipLaunchKernelGGL(record_kernel<kDopplerBinned>, grid, block, 0, s, a); break;
         case kLorentzBinned: hipLaunchKernelGGL(record_kernel<kLorentzBinned>, grid, block, 0, s, a); break;
         default: hipLaunchKernelGGL(record_kernel<kVoigt>, grid, block, 0, s, a); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_far(int waves, int P, const FwdArgs& a, hipStream_t s) {
+    if (a.n_tiles <= 0 || !a.far || !a.seg) return hipSuccess;
+    const int n_waves = a.n_tiles * waves;
+    const int64_t total = (int64_t)n_waves * a.n_tp * a.far_share;
+    const dim3 grid((unsigned)((total + 3) / 4)), block(256);
+    switch (P) {
+        case 1: hipLaunchKernelGGL(far_kernel<1>, grid, block, 0, s, a, n_waves); break;
+        case 2: hipLaunchKernelGGL(far_kernel<2>, grid, block, 0, s, a, n_waves); break;
+        default: hipLaunchKernelGGL(far_kernel<4>, grid, block, 0, s, a, n_waves); break;
     }
     return hipGetLastError();
 }

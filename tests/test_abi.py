@@ -36,7 +36,7 @@ def test_library_exports_every_declared_symbol():
 def test_version_and_defaults_without_gpu():
     from paper_1801_09803_amd.binding import XsOpts, load_library
     lib = load_library()
-    assert lib.xs_version() == 4
+    assert lib.xs_version() == 5
     o = XsOpts()
     assert lib.xs_opts_default(ctypes.byref(o)) == 0
     assert o.cutoff == 25.0 and o.T0 == 296.0 and o.P0 == 1.0 and o.profile == 3
@@ -74,7 +74,8 @@ def test_struct_layouts_match_the_header():
     from paper_1801_09803_amd.binding import XsKernelTimes, XsOpts
     assert ctypes.sizeof(XsOpts) == 8 * 7 + 4 * 4 + 8 * 3 + 4 * 6 + 8
     assert XsOpts.vv_beta.offset == 116 and XsOpts.vv_radius.offset == 120
-    assert ctypes.sizeof(XsKernelTimes) == 8 * 9
+    assert ctypes.sizeof(XsKernelTimes) == 8 * 11
+    assert XsKernelTimes.far_ms.offset == 72 and XsKernelTimes.far_launches.offset == 80
 
 
 def test_graph_and_tuning_calls_reject_null_plans_on_host():
