@@ -89,6 +89,23 @@ def test_split_tiles_match_oracle(case, oracle_at, precision, split):
         _check_at(out[i], *oracle_at(T, P), TOL32 if precision == "fp32" else TOL64, f"T={T} P={P}")
 
 
+@pytest.mark.parametrize("waves,slices", [(4, 1), (4, 4), (8, 1), (8, 2), (8, 4)])
+def test_tile_shapes_match_oracle(case, oracle_at, waves, slices):
+    # every wavefront width (64, 128, 256 points) has its own far-wing node spacing and
+    # reach: the node-sampled far wings of each shape agree with the oracle
+    cfg, d, h = case
+    log(f"tile shape {waves}x{slices}")
+    plan = _plan(cfg, d, "fp32")
+    plan.set_tile_config(waves, slices, 0, 0)
+    plan.set_timing(True)
+    out = _np(plan.cross_section(TS[1:4], PS[1:4]))
+    t = plan.kernel_times()
+    plan.set_timing(False)
+    assert t["far_launches"] > 0 and t["far_ms"] > 0
+    for i, (T, P) in enumerate(zip(TS[1:4], PS[1:4])):
+        _check_at(out[i], *oracle_at(T, P), TOL32, f"{waves}x{slices} T={T} P={P}")
+
+
 def test_split_changes_only_rounding(case):
     cfg, d, h = case
     a = _np(_plan(cfg, d, "fp32", n_split=1).cross_section(TS, PS))
