@@ -8,7 +8,8 @@
 //   intensity threshold only kept lines count (the cull runs first).
 // (exclusive scan of the totals)
 // core_eval: per 256 lines, block-local offsets, then the block's points in passes of
-//   256, each thread finding its line by binary search over the block prefix.
+//   256 grouped by evaluation path, each thread finding its line by binary search over
+//   the group's block prefix.
 #include "xs_forward_common.hpp"
 #include "xs_lineprep.hpp"
 
@@ -36,7 +37,7 @@ __device__ __forceinline__ T block_exclusive_scan_t(T v, T* lds4, T* total) {
 
 struct CoreLine {
     double s, nu, y, a;
-    int lo, hi, r;
+    int lo, hi, r, kc;
 };
 
 __device__ __forceinline__ CoreLine core_line(const CoreArgs& A, const TPParam& tp, int g, double Q) {
@@ -49,6 +50,7 @@ __device__ __forceinline__ CoreLine core_line(const CoreArgs& A, const TPParam& 
     c.r = -1;
     c.lo = 0;
     c.hi = -1;
+    c.kc = ls.kc;
     const double y2 = c.y * c.y;
     if (y2 < kCoreR2) {
         const double d = (A.G.nu_a + (double)ls.kc * A.G.dnu) - ls.nu;
@@ -123,36 +125,56 @@ __global__ __launch_bounds__(256) void scan64_apply_kernel(unsigned long long* x
 
 __global__ __launch_bounds__(256) void core_eval_kernel(const CoreArgs A) {
     __shared__ unsigned long long lds4[4];
-    __shared__ unsigned long long pre[256];
+    __shared__ unsigned long long pre[256];       // exclusive prefix of the lines' points
+    __shared__ unsigned long long gpre[3][256];   // the same per evaluation group
     __shared__ double ls_s[256], ls_nu[256], ls_y[256], ls_a[256];
-    __shared__ int ls_lo[256];
+    __shared__ int ls_lo[256], ls_ia[256], ls_ib[256], ls_nl[256];
     const int t = threadIdx.x;
     const int g = blockIdx.x * 256 + t;
     const TPParam tp = *A.tp;
     const double Q = A.Q[tp.iq];
-    unsigned long long c = 0;
+    // A line's points |k - kc| <= r - 2 lie inside |z| < 8 (r = floor((X + |xc|)/h) + 1),
+    // so they take the Weideman rational (y >= 0.2, group 0) or the Taylor series (group 1);
+    // its outer points (|k - kc| >= r - 1, group 2) may fall in the wing rules.  Each group's
+    // points are evaluated together (fewer divergent paths per wavefront) and written to
+    // the same place as before: the values do not change.
+    unsigned long long c = 0, gc[3] = {0, 0, 0};
     if (g < A.n_lines) {
         c = (unsigned long long)A.cnt[g];
         if (c) {
             const CoreLine cl = core_line(A, tp, g, Q);
             ls_s[t] = cl.s; ls_nu[t] = cl.nu; ls_y[t] = cl.y; ls_lo[t] = cl.lo;
             ls_a[t] = A.vv ? cl.a * A.vv[g].y : cl.a;   // area-normalised Vectorized Voigt: I' = I x factor
+            const int64_t ia = (int64_t)cl.kc - (cl.r - 2) > cl.lo ? (int64_t)cl.kc - (cl.r - 2) : cl.lo;
+            const int64_t ib = (int64_t)cl.kc + (cl.r - 2) < cl.hi ? (int64_t)cl.kc + (cl.r - 2) : cl.hi;
+            const unsigned long long cin = ib >= ia ? (unsigned long long)(ib - ia + 1) : 0ull;
+            ls_ia[t] = (int)ia;
+            ls_ib[t] = (int)ib;
+            ls_nl[t] = cin ? (int)(ia - cl.lo) : (int)c;   // outer points left of the inner ones
+            gc[cl.y >= 0.2 ? 0 : 1] = cin;
+            gc[2] = c - cin;
         }
     }
-    unsigned long long tot;
+    unsigned long long tot, gtot[3];
     const unsigned long long ex = block_exclusive_scan_t<unsigned long long>(c, lds4, &tot);
-    const long long base = A.val_base + (long long)A.bsum[blockIdx.x];
     pre[t] = ex;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) gpre[q][t] = block_exclusive_scan_t<unsigned long long>(gc[q], lds4, &gtot[q]);
+    const long long base = A.val_base + (long long)A.bsum[blockIdx.x];
     if (g < A.n_lines) A.coff[g] = base + (long long)ex;
     __syncthreads();
     for (unsigned long long it = t; it < tot; it += 256) {
+        const int grp = it < gtot[0] ? 0 : (it < gtot[0] + gtot[1] ? 1 : 2);
+        const unsigned long long li = grp == 0 ? it : (grp == 1 ? it - gtot[0] : it - gtot[0] - gtot[1]);
+        const unsigned long long* gp = gpre[grp];
         int lo = 0, hi = 255;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
-            if (pre[mid] <= it) lo = mid; else hi = mid - 1;
+            if (gp[mid] <= li) lo = mid; else hi = mid - 1;
         }
         const int j = lo;
-        const int k = ls_lo[j] + (int)(it - pre[j]);
+        const int loc = (int)(li - gp[j]);
+        const int k = grp < 2 ? ls_ia[j] + loc : (loc < ls_nl[j] ? ls_lo[j] + loc : ls_ib[j] + 1 + (loc - ls_nl[j]));
         const double x = ls_s[j] * ((A.G.nu_a + (double)k * A.G.dnu) - ls_nu[j]);
         const double y = ls_y[j];
         const double z2 = __builtin_fma(x, x, y * y);
@@ -160,7 +182,7 @@ __global__ __launch_bounds__(256) void core_eval_kernel(const CoreArgs A) {
         if (z2 < kCoreR2) re = voigt_core_re<24, 8>(x, y, A.tab->w24);
         else if (z2 < kMidR2) re = gh_wing_re(x * x, y, A.tab->gh4);
         else re = gh_wing_re(x * x, y, A.tab->gh2);
-        const long long at = base + (long long)it;
+        const long long at = base + (long long)pre[j] + (long long)(k - ls_lo[j]);
         if (at < A.val_end) A.val[at] = (float)(ls_a[j] * re);
     }
 }
