@@ -127,8 +127,8 @@ def zone_counts(cfg, d, T, P, waves=None, slices=None, chunk=1 << 24):
 TRAFFIC = {
     "kernel_sources": ['xs_forward_f32.hip', 'xs_forward_common.hpp', 'xs_voigt.hpp', 'xs_forward.hpp', 'xs_internal.hpp'],
     "sha256": "3254109e4a2063aa87ee9843bbfd8f1522c2ea18c957958c1fd1e96d02ab7eec",
-    "fetch_kib": [31087471.9, 35639616.5],
-    "write_kib": [251654.8, 251664.9],
+    "fetch_kib": [31073428.6, 35640270.9],
+    "write_kib": [251648.6, 251677.2],
     "fetch_scale": 2.0,
     "write_scale": 1.0,
 }
