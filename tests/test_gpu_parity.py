@@ -267,3 +267,21 @@ def test_far_wing_zone_accuracy(T):
     log(f"  far-wing zone T={T}: max rel {rel.max():.3e} over {m.sum()} points above 1e-12 of the maximum")
     assert m.sum() > 100000
     assert rel.max() <= 3e-6
+
+
+def test_far_wing_clamped_to_the_mid_zone_radius():
+    # a fine grid (0.001 cm^-1) at 3000 K: Doppler widths of ~17 grid steps put the
+    # |z| < 40 radius (~800 steps) beyond the far-wing reach (204 steps for 128-point
+    # wavefronts), so the node-sampled lines start at that radius instead
+    cfg = synth.WorkloadConfig("fine", 78, 3000, 200000, 34.0, 10000.0, 4995.0, 5005.0, 10001,
+                               (3000.0,), (1.0,), cutoff=5.0)
+    d = device_linelist(cfg)
+    h = host(d)
+    plan = make_plan(cfg, "fp32")
+    plan.set_timing(True)
+    got = _run(plan, d, [3000.0], [1.0])[0]
+    t = plan.kernel_times()
+    assert t["far_launches"] > 0
+    ls = oracle_lineset(h, cfg, 3000.0, 1.0)
+    ref = O.cross_section(ls, cfg.nu_a, cfg.nu_b, cfg.n_points, cfg.cutoff)
+    assert_parity(got, ref, TOL32, what="fine grid, 3000 K")
