@@ -13,7 +13,7 @@ Paper references ("the paper" = ExoCross, arXiv:1801.09803):
   Sec. "Super-lines": per grid point the sum of the intensities of the lines falling
       into its bin (the "Bin" option).
 
-Readings (also in DESIGN.md):
+Readings of the paper:
   * The binned profiles use the same cut-off windows as the sampled ones (bins whose
     centre lies within the cut-off of the line).
   * A difference of error functions is evaluated without cancellation in the tails as a

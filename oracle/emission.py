@@ -7,7 +7,7 @@ Paper references ("the paper" = ExoCross, arXiv:1801.09803):
   lifetime", Sec. "Cooling function", and the specific heat from the moments of the
   partition function (Sec. "Partition function", Eq. for C_p).
 
-Readings (also in DESIGN.md):
+Readings of the paper:
   * Emissivity: the emitting state is the transition's upper state (the printed formula
     labels it i with A_fi), and the stated unit (erg/s/sr/molecule) needs the factor hc:
         eps = h c g_up A nu exp(-c2 E_up/T) / (4 pi Q(T)).

@@ -7,7 +7,7 @@ thermodynamic equilibrium (non-LTE)", the energy split E = E_vib + E_rot and the
 population F(T_vib, T_rot) = exp(-c2 E_vib/T_vib) exp(-c2 E_rot/T_rot) used in place of
 the Boltzmann factor in intensities and partition functions.
 
-Readings (also in DESIGN.md):
+Readings of the paper:
   * E_vib of a state is the energy of the lowest state of its vibrational (vibronic)
     manifold (the paper's J = 0 / lowest allowed J state; along a rotational ladder that
     is the manifold's lowest energy), found from a per-state manifold label;

@@ -8,7 +8,7 @@ a constant threshold in cm/molecule, or the dynamic HITRAN cut-off
     I_cut(nu) = I_crit                                     for nu >  nu_crit,
 with nu_crit = 2000 cm^-1 and I_crit = 1e-29 cm/molecule by default.
 
-Readings (also in DESIGN.md):
+Readings of the paper:
   * A line is kept when its intensity (Eq. 1 at the call's T) is >= the threshold at its
     own wavenumber; dropped lines contribute nothing.
   * The formula is used as printed (its two branches meet only to tanh(c2 nu_crit/(2T))).

@@ -11,7 +11,7 @@ Paper references ("the paper" = ExoCross, arXiv:1801.09803):
   Sec. "Binned Vectorized Voigt with the line area preserved" (VVN): the line's
       profile values are summed and the intensity divided by that sum.
 
-Readings where the paper is silent or ambiguous (each is also listed in the design doc):
+Readings where the paper is silent or ambiguous:
   * f_ref has the Doppler HWHM of Eq. 16 at nu = 1 cm^-1 (same T and mass) and the
     line's own Lorentz HWHM (the paper keeps one reference per set of broadening
     parameters; with per-line parameters every line forms its own set).  It is taken

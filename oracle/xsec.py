@@ -14,7 +14,7 @@ Paper references ("the paper" = ExoCross, arXiv:1801.09803):
   Eq. 27-29 binned Lorentzian, Eq. 30-31 Gauss-Hermite binned Voigt (Sec. "Binned Voigt profile")
   Cut-off of the line wings (25 cm^-1 default) (Sec. "Off-set")
 
-Readings where the paper is silent or garbled (each is also listed in the design doc):
+Readings where the paper is silent or garbled:
   * Voigt normalisation: Eq. 19/20 as printed carry ln2 where sqrt(ln2) belongs and
     an unscaled gamma; the text says the Voigt is the convolution of the Doppler and
     Lorentz profiles, which (both unit-area) gives
