@@ -317,8 +317,9 @@ xs_status validate_opts(const xs_opts* o) {
     if (o->slices_per_wave != 0 && o->slices_per_wave != 1 && o->slices_per_wave != 2 && o->slices_per_wave != 4)
         return fail(XS_ERR_ARG, "slices_per_wave must be 0, 1, 2 or 4");
     if (o->a_is_log != 0 && o->a_is_log != 1) return fail(XS_ERR_ARG, "a_is_log must be 0 or 1");
-    if (o->waves_per_block != 0 && o->waves_per_block != 4 && o->waves_per_block != 8)
-        return fail(XS_ERR_ARG, "waves_per_block must be 0, 4 or 8");
+    if (o->waves_per_block != 0 && o->waves_per_block != 1 && o->waves_per_block != 2 && o->waves_per_block != 4 &&
+        o->waves_per_block != 8)
+        return fail(XS_ERR_ARG, "waves_per_block must be 0, 1, 2, 4 or 8");
     if (o->n_split < 0 || o->n_split > 64) return fail(XS_ERR_ARG, "n_split must be in [0, 64]");
     if (o->tp_block < 0 || o->tp_block > 256) return fail(XS_ERR_ARG, "tp_block must be in [0, 256]");
     const double dnu = (o->nu_b - o->nu_a) / (double)(o->n_points - 1);
@@ -855,7 +856,7 @@ xs_status xs_plan_create(const xs_opts* opts, xs_plan** out) {
     if (!p) return fail(XS_ERR_OOM, "host allocation failed");
     p->o = *opts;
     p->P = opts->slices_per_wave ? opts->slices_per_wave : 2;
-    p->waves = opts->precision == XS_FP64 ? 4 : (opts->waves_per_block ? opts->waves_per_block : 4);
+    p->waves = opts->precision == XS_FP64 ? 4 : (opts->waves_per_block ? opts->waves_per_block : 2);
     p->n_split = opts->n_split;
     p->tp_block = opts->tp_block;
     if (const char* env = std::getenv("XSEC_XCD_CONTIGUOUS")) p->xcd_contiguous = std::atoi(env) ? 1 : 0;
@@ -1424,13 +1425,13 @@ size_t xs_graph_workspace_bytes(const xs_graph* g) { return g ? g->ws.bytes : 0;
 xs_status xs_set_tile_config(xs_plan* p, int32_t waves, int32_t slices, int32_t n_split, int32_t tp_block) {
     if (!p) return fail(XS_ERR_ARG, "plan is NULL");
     const bool fp64 = p->o.precision == XS_FP64;
-    if (!(waves == 0 || waves == 4 || (waves == 8 && !fp64)))
-        return fail(XS_ERR_ARG, "waves must be 0 or 4 (or 8 for XS_FP32)");
+    if (!(waves == 0 || waves == 4 || ((waves == 1 || waves == 2 || waves == 8) && !fp64)))
+        return fail(XS_ERR_ARG, "waves must be 0 or 4 (or 1, 2, 8 for XS_FP32)");
     if (!(slices == 0 || slices == 1 || slices == 2 || slices == 4)) return fail(XS_ERR_ARG, "slices must be 0, 1, 2 or 4");
     if (n_split < 0 || n_split > 64) return fail(XS_ERR_ARG, "n_split must be in [0, 64]");
     if (tp_block < 0 || tp_block > 256) return fail(XS_ERR_ARG, "tp_block must be in [0, 256]");
     XS_HIP(hipDeviceSynchronize());
-    p->waves = fp64 ? 4 : (waves ? waves : 4);
+    p->waves = fp64 ? 4 : (waves ? waves : 2);
     p->P = slices ? slices : 2;
     p->n_split = n_split;
     p->tp_block = tp_block;
@@ -1519,7 +1520,7 @@ xs_status xs_autotune(xs_plan* p, int32_t n_tp, const double* T, const double* P
     };
     // coordinate search: tile shapes at their default split, then the split of the best
     // shape, then the (T, P) block size
-    const int shapes[6][2] = {{4, 2}, {4, 4}, {8, 2}, {4, 1}, {8, 4}, {8, 1}};
+    const int shapes[9][2] = {{2, 2}, {1, 2}, {4, 2}, {2, 4}, {2, 1}, {1, 4}, {4, 4}, {8, 2}, {4, 1}};
     for (const auto& sh : shapes) {
         if (fp64 && sh[0] != 4) continue;
         p->waves = sh[0];
@@ -1527,7 +1528,7 @@ xs_status xs_autotune(xs_plan* p, int32_t n_tp, const double* T, const double* P
         p->n_split = 0;
         consider(sh[0], sh[1], pick_split(p), ns);
     }
-    const int splits[6] = {1, 2, 4, 8, 16, 32};
+    const int splits[7] = {1, 2, 4, 8, 16, 32, 64};
     const int s0 = best.S;
     for (int S : splits)
         if (S != s0) consider(best.w, best.sl, S, ns);

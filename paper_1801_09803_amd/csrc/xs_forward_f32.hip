@@ -557,7 +557,9 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
     // per-wavefront anchor words in the LDS record (segmented sweep), or anchors rebuilt
     // per line (a smaller LDS image, more resident workgroups)
     constexpr bool ANCH = SEG && anchors_in_lds(PROF);
-    constexpr int RS = ANCH ? RH + WAVES : RH;   // LDS record words
+    // LDS record words, a multiple of 4 (records are copied and read as float4)
+    constexpr int RS = ANCH ? (RH + WAVES + 3) / 4 * 4 : RH;
+    static_assert(RS % 4 == 0, "record stride");
     constexpr int NTF = SEG ? 0 : NCW * NT;
     // cold profile words in LDS
     constexpr int NM = (PROF == kGHSampled || PROF == kGHBinned) ? 5
@@ -812,9 +814,9 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
                         } else {
                             switch (wave) {
                                 case 0: wing_runs<PROF, P, RS, RH + 0>(rec, S.sb0, kl, kr, bs, lo2, hi2, lo4, hi4, xa, xb, xc, xd, jlo_w, jhi_w, part); break;
-                                case 1: wing_runs<PROF, P, RS, RH + 1>(rec, S.sb0, kl, kr, bs, lo2, hi2, lo4, hi4, xa, xb, xc, xd, jlo_w, jhi_w, part); break;
-                                case 2: wing_runs<PROF, P, RS, RH + 2>(rec, S.sb0, kl, kr, bs, lo2, hi2, lo4, hi4, xa, xb, xc, xd, jlo_w, jhi_w, part); break;
-                                case 3: wing_runs<PROF, P, RS, RH + 3>(rec, S.sb0, kl, kr, bs, lo2, hi2, lo4, hi4, xa, xb, xc, xd, jlo_w, jhi_w, part); break;
+                                case 1: wing_runs<PROF, P, RS, RH + (WAVES > 1 ? 1 : 0)>(rec, S.sb0, kl, kr, bs, lo2, hi2, lo4, hi4, xa, xb, xc, xd, jlo_w, jhi_w, part); break;
+                                case 2: wing_runs<PROF, P, RS, RH + (WAVES > 2 ? 2 : 0)>(rec, S.sb0, kl, kr, bs, lo2, hi2, lo4, hi4, xa, xb, xc, xd, jlo_w, jhi_w, part); break;
+                                case 3: wing_runs<PROF, P, RS, RH + (WAVES > 3 ? 3 : 0)>(rec, S.sb0, kl, kr, bs, lo2, hi2, lo4, hi4, xa, xb, xc, xd, jlo_w, jhi_w, part); break;
                                 case 4: wing_runs<PROF, P, RS, RH + (WAVES > 4 ? 4 : 0)>(rec, S.sb0, kl, kr, bs, lo2, hi2, lo4, hi4, xa, xb, xc, xd, jlo_w, jhi_w, part); break;
                                 case 5: wing_runs<PROF, P, RS, RH + (WAVES > 5 ? 5 : 0)>(rec, S.sb0, kl, kr, bs, lo2, hi2, lo4, hi4, xa, xb, xc, xd, jlo_w, jhi_w, part); break;
                                 case 6: wing_runs<PROF, P, RS, RH + (WAVES > 6 ? 6 : 0)>(rec, S.sb0, kl, kr, bs, lo2, hi2, lo4, hi4, xa, xb, xc, xd, jlo_w, jhi_w, part); break;
@@ -1116,7 +1118,19 @@ void launch_one(const FwdArgs& a, hipStream_t s) {
 
 template <int PROF>
 void launch_p(int waves, int P, const FwdArgs& a, hipStream_t s) {
-    if (waves == 4) {
+    if (waves == 1) {
+        switch (P) {
+            case 1: launch_one<PROF, 1, 1>(a, s); break;
+            case 2: launch_one<PROF, 1, 2>(a, s); break;
+            default: launch_one<PROF, 1, 4>(a, s); break;
+        }
+    } else if (waves == 2) {
+        switch (P) {
+            case 1: launch_one<PROF, 2, 1>(a, s); break;
+            case 2: launch_one<PROF, 2, 2>(a, s); break;
+            default: launch_one<PROF, 2, 4>(a, s); break;
+        }
+    } else if (waves == 4) {
         switch (P) {
             case 1: launch_one<PROF, 4, 1>(a, s); break;
             case 2: launch_one<PROF, 4, 2>(a, s); break;
