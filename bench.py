@@ -119,16 +119,16 @@ def zone_counts(cfg, d, T, P, waves=None, slices=None, chunk=1 << 24):
     return tot
 
 # HBM traffic of the dominant kernel from two rocprofv3 --pmc runs of this script with
-# the tile configuration fixed (4 waves, 2 slices, 32 shares, one (T, P) per dispatch):
+# the tile configuration fixed (1 wave, 4 slices, 64 shares, one (T, P) per dispatch):
 # FETCH_SIZE, then WRITE_SIZE, KiB per dispatch at T = 296 K and 2000 K, scaled by the
 # same counters on a 1 GiB device copy (FETCH_SIZE reads 0.5 GiB -> x2, WRITE_SIZE 1 GiB
 # -> x1).  Per (T, P); a launch covering several (T, P) moves that many times the bytes.
 # Valid only for the kernel sources they were taken with (hash below).
 TRAFFIC = {
     "kernel_sources": ['xs_forward_f32.hip', 'xs_forward_common.hpp', 'xs_voigt.hpp', 'xs_forward.hpp', 'xs_internal.hpp'],
-    "sha256": "3254109e4a2063aa87ee9843bbfd8f1522c2ea18c957958c1fd1e96d02ab7eec",
-    "fetch_kib": [31073428.6, 35640270.9],
-    "write_kib": [251648.6, 251677.2],
+    "sha256": "76f9640d216b506155f16f059aecf9bcb05ea2f4576b0fb8d86ab017ed93694a",
+    "fetch_kib": [57698035.0, 63831122.2],
+    "write_kib": [506985.5, 506790.2],
     "fetch_scale": 2.0,
     "write_scale": 1.0,
 }
