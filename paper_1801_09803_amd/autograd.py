@@ -5,7 +5,11 @@
 `plan` must be a Voigt Plan created with a_is_log=True and per-line broadening; T and P
 are 0-d float64 tensors.  The backward pass calls xs_cross_section_adjoint, which
 recomputes the profiles; it uses the line set of the latest forward on this plan, so
-call backward before the plan's next forward.
+call backward before the plan's next forward.  The library returns the per-line
+gradients in double precision; they are cast to the dtypes of logA, gamma_ref and n_exp
+(float32 parameters receive float32 gradients, which underflow to subnormals or zero for
+losses on cross sections of ~1e-20 cm^2: pass float64 parameters, or scale the loss, to
+keep their digits).
 """
 import torch
 

@@ -342,9 +342,11 @@ __global__ __launch_bounds__(256) void adj32_final_kernel(const AdjArgs A) {
     const double gref = (double)A.L.gref[g];
     const double nexp = (double)A.L.nexp[g];
     const int o = A.L.orig[g];
-    if (A.dlnA) static_cast<float*>(A.dlnA)[o] = (float)(S * R0);
-    if (A.dgref) static_cast<float*>(A.dgref)[o] = (float)(gref > 0.0 ? S * Rg * ls.gam / gref : 0.0);
-    if (A.dn) static_cast<float*>(A.dn)[o] = (float)(S * Rg * ls.gam * A.tp.ln_T0_T);
+    // double outputs: a loss on cross sections of ~1e-20 cm^2 has per-line gradients far
+    // below the float range (stored as float they would lose their digits as subnormals)
+    if (A.dlnA) static_cast<double*>(A.dlnA)[o] = S * R0;
+    if (A.dgref) static_cast<double*>(A.dgref)[o] = gref > 0.0 ? S * Rg * ls.gam / gref : 0.0;
+    if (A.dn) static_cast<double*>(A.dn)[o] = S * Rg * ls.gam * A.tp.ln_T0_T;
     const double x2 = (kC2 * ls.nu) / T;
     const double tau = (kC2 * A.L.elow[g]) / (T * T) - ((kC2 * ls.nu) / (T * T)) / expm1(x2) - dQ / Q;
     A.pT[g] = S * (tau * R0 + Ra * ls.aD / (2.0 * T) - Rg * nexp * ls.gam / T);
@@ -403,8 +405,7 @@ hipError_t launch_adjoint(const AdjArgs& a, int fp64, int64_t n_caller_lines, do
                           double* dP, hipStream_t s) {
     if (n_caller_lines > 0) {
         const dim3 g((unsigned)((n_caller_lines + 255) / 256));
-        if (fp64) hipLaunchKernelGGL(fill_zero_kernel<double>, g, dim3(256), 0, s, a.dlnA, a.dgref, a.dn, n_caller_lines);
-        else hipLaunchKernelGGL(fill_zero_kernel<float>, g, dim3(256), 0, s, a.dlnA, a.dgref, a.dn, n_caller_lines);
+        hipLaunchKernelGGL(fill_zero_kernel<double>, g, dim3(256), 0, s, a.dlnA, a.dgref, a.dn, n_caller_lines);
     }
     if (a.n_lines > 0) {
         const int blocks = 2048;

@@ -125,34 +125,114 @@ def test_autograd_function_wires_the_adjoint():
     (sig.double() * w).sum().backward()
     dT, dP, dlnA, dg, dn = plan.cross_section_adjoint(900.0, 0.5, w.float().contiguous(), cfg.n_lines)
     assert torch.allclose(T.grad, dT[0]) and torch.allclose(P.grad, dP[0])
-    assert torch.equal(logA.grad, dlnA) and torch.equal(gr.grad, dg) and torch.equal(ne.grad, dn)
+    assert torch.equal(logA.grad, dlnA.float()) and torch.equal(gr.grad, dg.float()) and torch.equal(ne.grad, dn.float())
 
 
-def test_c4_full_size_adjoint_sampled_lines():
+def test_c4_full_size_adjoint_random_gbar_sampled_lines():
+    # a random-sign dL/dsigma (the sums over each window cancel) on 32 seeded lines
     cfg = synth.CONFIGS["C4"]
     d = synth.make_linelist(cfg, device="cuda")
     logA = torch.log(d["A"].double()).float()
     gbar = _gbar(cfg, cfg.n_points)
-    out = {}
-    for precision in ("fp32",):
-        plan = _plan(cfg, precision)
-        plan.set_states(d["E"], d["g"], d["J"])
-        plan.set_lines(d["upper"], d["lower"], logA, d["gamma_ref"], d["n_exp"])
-        g = torch.from_numpy(gbar).to("cuda", plan.dtype)
-        out[precision] = plan.cross_section_adjoint(1500.0, 0.1, g, cfg.n_lines)
+    plan = _plan(cfg, "fp32")
+    plan.set_states(d["E"], d["g"], d["J"])
+    plan.set_lines(d["upper"], d["lower"], logA, d["gamma_ref"], d["n_exp"])
+    g = torch.from_numpy(gbar).to("cuda", plan.dtype)
+    out = plan.cross_section_adjoint(1500.0, 0.1, g)
     torch.cuda.synchronize()
-    dlnA = out["fp32"][2].cpu().numpy()
-    # 32 seeded lines among those whose window meets the grid
+    lines = _c4_lines(cfg, d, 32, seed=4)
+    h = {k: d[k].cpu().numpy() for k in ("E", "g", "upper", "lower", "gamma_ref", "n_exp")}
+    ref = _oracle_adj(cfg, h, logA.cpu().numpy(), 1500.0, 0.1, g.double().cpu().numpy(), lines=lines)
+    for name, i in (("dlnA", 2), ("dgamma_ref", 3), ("dn", 4)):
+        got = out[i].cpu().numpy()[lines]
+        rel = np.abs(got - ref[name]) / np.maximum(np.abs(ref[name]), 1e-6 * np.abs(ref[name]).max())
+        log(f"  C4 fp32 {name} on 32 lines (random dL/dsigma): max rel {rel.max():.3e}")
+        assert rel.max() <= 1e-4, (name, rel.max())
+
+
+def _c4_lines(cfg, d, n, seed):
+    """n seeded lines among those whose window meets the grid."""
     E = d["E"]
     nu = (E[d["upper"].long()] - E[d["lower"].long()]).cpu().numpy()
-    inside = np.nonzero((nu > cfg.nu_a - 25) & (nu < cfg.nu_b + 25))[0]
-    rng = np.random.default_rng(4)
-    lines = np.sort(rng.choice(inside, 32, replace=False))
+    inside = np.nonzero((nu > cfg.nu_a - cfg.cutoff) & (nu < cfg.nu_b + cfg.cutoff))[0]
+    rng = np.random.default_rng(seed)
+    return np.sort(rng.choice(inside, n, replace=False))
+
+
+@pytest.fixture(scope="module")
+def c4_retrieval():
+    """The retrieval workload: L = sum (sigma - sigma*)^2 with sigma* at the seeded
+    perturbation (T x 1.05, gamma_ref x 1.1, ln A + N(0, 0.05)); one dL/dsigma =
+    2 (sigma - sigma*) from the GPU FP64 forward feeds both precisions' adjoints."""
+    cfg = synth.CONFIGS["C4"]
+    d = synth.make_linelist(cfg, device="cuda")
+    T, P = cfg.temperatures[0], cfg.pressures[0]
+    logA = torch.log(d["A"].double()).float()
+    pert = synth.linelist.perturbation_normals(cfg.n_lines, cfg.seed).to("cuda")
+    p64 = _plan(cfg, "fp64")
+    p64.set_states(d["E"], d["g"], d["J"])
+    p64.set_lines(d["upper"], d["lower"], (logA.double() + 0.05 * pert).float(), d["gamma_ref"] * 1.1, d["n_exp"])
+    target = p64.cross_section([1.05 * T], [P])[0].clone()
+    p64.set_lines(d["upper"], d["lower"], logA, d["gamma_ref"], d["n_exp"])
+    base = p64.cross_section([T], [P])[0].clone()
+    gbar = 2.0 * (base - target)
+    p32 = _plan(cfg, "fp32")
+    p32.set_states(d["E"], d["g"], d["J"])
+    p32.set_lines(d["upper"], d["lower"], logA, d["gamma_ref"], d["n_exp"])
+    g32 = gbar.float().contiguous()
+    G64 = p64.cross_section_adjoint(T, P, gbar)
+    G32 = p32.cross_section_adjoint(T, P, g32)
+    torch.cuda.synchronize()
+    return dict(cfg=cfg, d=d, T=T, P=P, logA=logA, target=target, gbar=gbar, g32=g32, p64=p64,
+                G64=[G64[0].item(), G64[1].item()] + [t.cpu().numpy() for t in G64[2:]],
+                G32=[G32[0].item(), G32[1].item()] + [t.cpu().numpy() for t in G32[2:]])
+
+
+def test_c4_fp32_adjoint_matches_fp64_on_every_line(c4_retrieval):
+    r = c4_retrieval
+    G32, G64 = r["G32"], r["G64"]
+    for name, i in (("dlnA", 2), ("dgamma_ref", 3), ("dn", 4)):
+        a, b = G32[i], G64[i]
+        m = np.abs(b) > 1e-6 * np.abs(b).max()
+        rel = np.abs(a[m] - b[m]) / np.abs(b[m])
+        log(f"  C4 fp32 vs fp64 {name}: max rel {rel.max():.3e} over {m.sum()} lines")
+        assert rel.max() <= 1e-4, (name, rel.max())
+    for name, i in (("dT", 0), ("dP", 1)):
+        rel = abs(G32[i] - G64[i]) / abs(G64[i])
+        log(f"  C4 fp32 vs fp64 {name}: rel {rel:.3e}")
+        assert rel <= 1e-5, (name, rel)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-8), ("fp32", 1e-4)])
+def test_c4_adjoint_matches_oracle_on_sampled_lines(c4_retrieval, precision, tol):
+    r = c4_retrieval
+    cfg, d = r["cfg"], r["d"]
+    lines = _c4_lines(cfg, d, 32, seed=5)
     h = {k: d[k].cpu().numpy() for k in ("E", "g", "upper", "lower", "gamma_ref", "n_exp")}
-    h["A"] = np.exp(logA.cpu().numpy().astype(np.float64))
-    ref = _oracle_adj(cfg, h, logA.cpu().numpy(), 1500.0, 0.1,
-                      torch.from_numpy(gbar).float().double().numpy(), lines=lines)
-    got = dlnA[lines]
-    rel = np.abs(got - ref["dlnA"]) / np.maximum(np.abs(ref["dlnA"]), 1e-6 * np.abs(ref["dlnA"]).max())
-    log(f"  C4 fp32 dlnA on 32 lines: max rel {rel.max():.3e}")
-    assert rel.max() <= 1e-4
+    g = (r["gbar"] if precision == "fp64" else r["g32"]).double().cpu().numpy()
+    ref = _oracle_adj(cfg, h, r["logA"].cpu().numpy(), r["T"], r["P"], g, lines=lines)
+    G = r["G64"] if precision == "fp64" else r["G32"]
+    for name, i in (("dlnA", 2), ("dgamma_ref", 3), ("dn", 4)):
+        got = G[i][lines]
+        floor = 1e-6 * np.abs(r["G64"][i]).max()
+        rel = np.abs(got - ref[name]) / np.maximum(np.abs(ref[name]), floor)
+        log(f"  C4 {precision} {name} on 32 lines vs oracle: max rel {rel.max():.3e}")
+        assert rel.max() <= tol, (name, rel.max())
+
+
+def test_c4_fp64_adjoint_matches_central_differences(c4_retrieval):
+    # dL/dT and dL/dP against central differences of the GPU FP64 forward, h = 1e-6 relative
+    r = c4_retrieval
+    p64, T, P, target = r["p64"], r["T"], r["P"], r["target"]
+
+    def L(T_, P_):
+        s = p64.cross_section([T_], [P_])[0]
+        return float(((s - target) ** 2).sum().item())
+
+    hT, hP = 1e-6 * T, 1e-6 * P
+    fT = (L(T + hT, P) - L(T - hT, P)) / (2 * hT)
+    fP = (L(T, P + hP) - L(T, P - hP)) / (2 * hP)
+    dT, dP = r["G64"][0], r["G64"][1]
+    log(f"  C4 dT adj {dT:.9e} fd {fT:.9e}; dP adj {dP:.9e} fd {fP:.9e}")
+    assert abs(dT - fT) <= 1e-6 * abs(fT)
+    assert abs(dP - fP) <= 1e-6 * abs(fP)
