@@ -53,7 +53,7 @@
 extern "C" {
 #endif
 
-#define XS_ABI_VERSION 5
+#define XS_ABI_VERSION 6
 
 typedef struct xs_plan xs_plan;
 typedef struct xs_graph xs_graph;
@@ -67,7 +67,10 @@ typedef enum {
     XS_ERR_HIP = 4,          /* the HIP runtime reported an error                        */
     XS_ERR_OOM = 5,          /* device allocation failed                                 */
     XS_ERR_STATE = 6,        /* call out of order (e.g. no states or lines set)          */
-    XS_ERR_UNSUPPORTED = 7   /* option combination not implemented                       */
+    XS_ERR_UNSUPPORTED = 7,  /* option combination not implemented                       */
+    XS_ERR_INJECTED = 8      /* a fault injected for testing (environment variable
+                                XS_FAULT_INJECT, see xs_stream_chunk) stopped the call
+                                before any copy or device work                           */
 } xs_status;
 
 typedef enum {
@@ -155,6 +158,8 @@ typedef struct {
                                 (the paper's usual choice)                               */
     double vv_radius;        /* XS_VVOIGT(_NORM): radius R (cm^-1) of the Voigt region, > 0;
                                 0 = 4 cm^-1 (the paper's value)                          */
+    int32_t gh_nodes;        /* XS_GH_SAMPLED / XS_GH_BINNED: nodes of the Gauss-Hermite rule
+                                of Eq. 30-31, 1..64; 0 = 30 (the paper's usual N_GH)     */
 } xs_opts;
 
 /* Fill *opts with defaults: cutoff 25, T0 296 K, P0 1 bar, Voigt, FP32, per-line
@@ -375,9 +380,17 @@ xs_status xs_autotune(xs_plan* plan, int32_t n_tp, const double* T, const double
  * xs_stream_checkpoint computes any pending chunk and writes the accumulators, the
  * (T, P) points and the chunk counts to the file `path` (SYNCHRONOUS; written to
  * path.tmp, then renamed).  xs_stream_resume creates a stream from such a file for a
- * plan with the same grid and precision (states, broadening table and lines are not
- * in the file: set the states before resuming); chunks then continue the sums.
- * xs_stream_stats writes {chunks passed, transitions passed, transitions kept}. */
+ * plan with the same grid (range and points), cut-off, profile and its options, mass,
+ * broadening scheme and constants (and a0 table length), index base, A convention,
+ * precision and intensity kind; any difference returns XS_ERR_ARG naming it.  States,
+ * the broadening table's values and lines are not in the file: set the states before
+ * resuming; chunks then continue the sums.
+ * xs_stream_stats writes {chunks passed, transitions passed, transitions kept}.
+ * Fault injection (for tests of checkpoint and resume): with the environment variable
+ * XS_FAULT_INJECT=chunk:k set when xs_stream_chunk is called, the call that would pass the
+ * chunk of index k (0-based, counting every chunk of the accumulation, also those before
+ * a resume) returns XS_ERR_INJECTED after validating its arguments and before any copy
+ * or device work; the stream keeps its state and stays usable. */
 xs_status xs_stream_begin(xs_plan* plan, int32_t n_tp, const double* T, const double* P,
                           void* sigma, void* stream, xs_stream** out);
 xs_status xs_stream_chunk(xs_stream* st, int64_t n, const int32_t* upper, const int32_t* lower,
@@ -395,8 +408,9 @@ xs_status xs_stream_stats(const xs_stream* st, int64_t out[3]);
  * get 0).  Profiles are recomputed; nothing is kept from the forward call.
  * dL_dsigma: device float[n_points] (XS_FP32) or double[n_points] (XS_FP64);
  * dL_dT, dL_dP: device double[1] or NULL; dL_dlogA, dL_dgamma_ref, dL_dn: device
- * arrays of n_lines values, float (XS_FP32) or double (XS_FP64), or NULL
- * (gamma_ref / n outputs need XS_BROAD_PER_LINE).
+ * double arrays of n_lines values (n_lines of the last xs_set_lines), for both precisions
+ * (per-line gradients of a loss on cross sections of ~1e-20 cm^2 lie far below the float
+ * range), or NULL (gamma_ref / n outputs need XS_BROAD_PER_LINE).
  * Returns XS_ERR_UNSUPPORTED for other profiles. */
 xs_status xs_cross_section_adjoint(xs_plan* plan, double T, double P, const void* dL_dsigma,
                                    double* dL_dT, double* dL_dP, void* dL_dlogA,

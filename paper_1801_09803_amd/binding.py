@@ -17,7 +17,7 @@ PROFILES = {"doppler": 0, "gauss_fixed": 1, "lorentz": 2, "voigt": 3, "gh_sample
 PRECISIONS = {"fp64": 0, "fp32": 1}
 BROADENING = {"const": 0, "per_line": 1, "a0_jlower": 2}
 STATUS = {0: "XS_OK", 1: "XS_ERR_ARG", 2: "XS_ERR_INDEX", 3: "XS_ERR_NU_NONPOS", 4: "XS_ERR_HIP",
-          5: "XS_ERR_OOM", 6: "XS_ERR_STATE", 7: "XS_ERR_UNSUPPORTED"}
+          5: "XS_ERR_OOM", 6: "XS_ERR_STATE", 7: "XS_ERR_UNSUPPORTED", 8: "XS_ERR_INJECTED"}
 
 
 class XsecError(RuntimeError):
@@ -36,7 +36,7 @@ class XsOpts(ctypes.Structure):
         ("alpha_fixed", ctypes.c_double), ("gamma_const", ctypes.c_double), ("n_const", ctypes.c_double),
         ("slices_per_wave", ctypes.c_int32), ("waves_per_block", ctypes.c_int32),
         ("a_is_log", ctypes.c_int32), ("n_split", ctypes.c_int32), ("tp_block", ctypes.c_int32),
-        ("vv_beta", ctypes.c_int32), ("vv_radius", ctypes.c_double),
+        ("vv_beta", ctypes.c_int32), ("vv_radius", ctypes.c_double), ("gh_nodes", ctypes.c_int32),
     ]
 
 
@@ -132,6 +132,20 @@ def _owner(obj) -> bool:
     return getattr(obj, "_pid", None) == os.getpid()
 
 
+def _same_length(what: str, *named):
+    """Raise ValueError unless every given (name, tensor) pair has the same number of
+    elements (None entries are skipped); returns that number."""
+    n = None
+    for name, t in named:
+        if t is None:
+            continue
+        if n is None:
+            n, first = t.numel(), name
+        elif t.numel() != n:
+            raise ValueError(f"{what}: {name} has {t.numel()} values, {first} has {n}")
+    return 0 if n is None else n
+
+
 def _host_doubles(vals: Sequence[float]):
     arr = (ctypes.c_double * len(vals))(*[float(v) for v in vals])
     return arr
@@ -146,7 +160,7 @@ class Plan:
                  index_base: int = 0, alpha_fixed: float = 0.0, gamma_const: float = 0.0,
                  n_const: float = 0.0, slices_per_wave: int = 0, waves_per_block: int = 0,
                  a_is_log: bool = False, n_split: int = 0, tp_block: int = 0,
-                 vv_radius: float = 0.0, vv_beta: bool = False):
+                 vv_radius: float = 0.0, vv_beta: bool = False, gh_nodes: int = 0):
         import torch
         self._torch = torch
         lib = load_library()
@@ -166,6 +180,7 @@ class Plan:
         o.tp_block = int(tp_block)
         o.vv_radius = float(vv_radius)
         o.vv_beta = 1 if vv_beta else 0
+        o.gh_nodes = int(gh_nodes)
         h = ctypes.c_void_p()
         _check(lib.xs_plan_create(ctypes.byref(o), ctypes.byref(h)))
         self._lib = lib
@@ -210,8 +225,10 @@ class Plan:
         E = self._dev(E, torch.float64, "E")
         g = self._dev(g, torch.int32, "g")
         J = self._dev(J, torch.int32, "J")
+        n = _same_length("set_states", ("E", E), ("g", g), ("J", J))
         self._states = (E, g, J)
-        _check(self._lib.xs_set_states(self._h, E.numel(), _ptr(E), _ptr(g), _ptr(J), self._stream()))
+        self._n_lines = None   # the library drops the line set with new states
+        _check(self._lib.xs_set_states(self._h, n, _ptr(E), _ptr(g), _ptr(J), self._stream()))
 
     def set_broadening_table(self, gamma_ref, n_exp):
         import numpy as np
@@ -228,8 +245,19 @@ class Plan:
         A = self._dev(A, torch.float32, "A")
         gamma_ref = self._dev(gamma_ref, torch.float32, "gamma_ref")
         n_exp = self._dev(n_exp, torch.float32, "n_exp")
-        _check(self._lib.xs_set_lines(self._h, upper.numel(), _ptr(upper), _ptr(lower), _ptr(A),
+        n = _same_length("set_lines", ("upper", upper), ("lower", lower), ("A", A), ("gamma_ref", gamma_ref),
+                         ("n_exp", n_exp))
+        self._n_lines = None
+        _check(self._lib.xs_set_lines(self._h, n, _ptr(upper), _ptr(lower), _ptr(A),
                                       _ptr(gamma_ref), _ptr(n_exp), self._stream()))
+        self._n_lines = n
+
+    def n_lines(self) -> int:
+        """Transitions given to the last set_lines (the length of the per-line gradients)."""
+        n = getattr(self, "_n_lines", None)
+        if n is None:
+            raise ValueError("no line set: call set_lines first")
+        return n
 
     def lines_kept(self) -> int:
         n = ctypes.c_int64()
@@ -259,11 +287,12 @@ class Plan:
         torch = self._torch
         upper = self._dev(upper, torch.int32, "upper")
         A = self._dev(A, torch.float32, "A")
+        n = _same_length("lifetimes", ("upper", upper), ("A", A))
         states = getattr(self, "_states", None)
         if states is None:
             raise ValueError("set_states must come first")
         tau = torch.empty(states[0].numel(), dtype=torch.float64, device="cuda")
-        _check(self._lib.xs_lifetimes(self._h, upper.numel(), _ptr(upper), _ptr(A), _ptr(tau), self._stream()))
+        _check(self._lib.xs_lifetimes(self._h, n, _ptr(upper), _ptr(A), _ptr(tau), self._stream()))
         return tau
 
     def cooling_function(self, upper, lower, A, T: Sequence[float]):
@@ -272,9 +301,10 @@ class Plan:
         upper = self._dev(upper, torch.int32, "upper")
         lower = self._dev(lower, torch.int32, "lower")
         A = self._dev(A, torch.float32, "A")
+        n = _same_length("cooling_function", ("upper", upper), ("lower", lower), ("A", A))
         T = list(T)
         W = torch.empty(len(T), dtype=torch.float64, device="cuda")
-        _check(self._lib.xs_cooling_function(self._h, upper.numel(), _ptr(upper), _ptr(lower), _ptr(A), len(T),
+        _check(self._lib.xs_cooling_function(self._h, n, _ptr(upper), _ptr(lower), _ptr(A), len(T),
                                              _host_doubles(T), _ptr(W), self._stream()))
         return W
 
@@ -283,12 +313,19 @@ class Plan:
         set must be set again afterwards."""
         torch = self._torch
         if labels is None:
+            self._n_lines = None
             _check(self._lib.xs_set_vibrational_labels(self._h, 0, None, self._stream()))
             return
         labels = self._dev(labels, torch.int32, "labels")
+        states = getattr(self, "_states", None)
+        if states is None:
+            raise ValueError("set_states must come first")
+        if labels.numel() != states[0].numel():
+            raise ValueError(f"labels has {labels.numel()} values for {states[0].numel()} states")
         if n_labels is None:
             n_labels = int(labels.max().item()) + 1 if labels.numel() else 1
         self._labels = labels
+        self._n_lines = None   # the library drops the line set with new labels
         _check(self._lib.xs_set_vibrational_labels(self._h, int(n_labels), _ptr(labels), self._stream()))
 
     def cross_section_nlte(self, T_rot: Sequence[float], T_vib: Sequence[float], P: Sequence[float], out=None):
@@ -337,18 +374,26 @@ class Plan:
                                           self._stream()))
         return out
 
-    def cross_section_adjoint(self, T: float, P: float, grad_sigma, n_lines: int,
+    def cross_section_adjoint(self, T: float, P: float, grad_sigma, n_lines: Optional[int] = None,
                               want_broadening: bool = True):
-        """Returns (dL/dT, dL/dP, dL/dlnA, dL/dgamma_ref, dL/dn) as device tensors."""
+        """Returns (dL/dT, dL/dP, dL/dlnA, dL/dgamma_ref, dL/dn) as device tensors; the
+        per-line gradients have one value per transition of the last set_lines (n_lines, if
+        given, must equal that count)."""
         torch = self._torch
+        n_set = self.n_lines()
+        if n_lines is not None and int(n_lines) != n_set:
+            raise ValueError(f"n_lines = {n_lines}, but the line set has {n_set} transitions")
+        n_lines = n_set
         grad_sigma = self._dev(grad_sigma, self.dtype, "grad_sigma")
         if grad_sigma.numel() != self.n_points:
             raise ValueError("grad_sigma must have n_points values")
         dT = torch.empty(1, dtype=torch.float64, device="cuda")
         dP = torch.empty(1, dtype=torch.float64, device="cuda")
-        dlnA = torch.empty(n_lines, dtype=self.dtype, device="cuda")
-        dg = torch.empty(n_lines, dtype=self.dtype, device="cuda") if want_broadening else None
-        dn = torch.empty(n_lines, dtype=self.dtype, device="cuda") if want_broadening else None
+        # per-line gradients are double for both precisions (their values lie far below
+        # the float range for cross sections in cm^2/molecule)
+        dlnA = torch.empty(n_lines, dtype=torch.float64, device="cuda")
+        dg = torch.empty(n_lines, dtype=torch.float64, device="cuda") if want_broadening else None
+        dn = torch.empty(n_lines, dtype=torch.float64, device="cuda") if want_broadening else None
         _check(self._lib.xs_cross_section_adjoint(self._h, float(T), float(P), _ptr(grad_sigma), _ptr(dT),
                                                   _ptr(dP), _ptr(dlnA), _ptr(dg), _ptr(dn), self._stream()))
         return dT, dP, dlnA, dg, dn
@@ -497,7 +542,10 @@ class Stream:
         A = self._host(A, torch.float32, "A")
         gamma_ref = self._host(gamma_ref, torch.float32, "gamma_ref")
         n_exp = self._host(n_exp, torch.float32, "n_exp")
-        _check(self._lib.xs_stream_chunk(self._h, upper.numel(), _ptr(upper), _ptr(lower), _ptr(A),
+        n = _same_length("chunk", ("upper", upper), ("lower", lower), ("A", A), ("gamma_ref", gamma_ref),
+                         ("n_exp", n_exp))
+        self._plan._n_lines = None   # each chunk replaces the plan's line set
+        _check(self._lib.xs_stream_chunk(self._h, n, _ptr(upper), _ptr(lower), _ptr(A),
                                          _ptr(gamma_ref), _ptr(n_exp)))
         # the host arrays must outlive their asynchronous copy (until the next call returns)
         self._held = [upper, lower, A, gamma_ref, n_exp]

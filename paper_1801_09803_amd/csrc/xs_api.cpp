@@ -322,6 +322,7 @@ xs_status validate_opts(const xs_opts* o) {
         return fail(XS_ERR_ARG, "waves_per_block must be 0, 1, 2, 4 or 8");
     if (o->n_split < 0 || o->n_split > 64) return fail(XS_ERR_ARG, "n_split must be in [0, 64]");
     if (o->tp_block < 0 || o->tp_block > 256) return fail(XS_ERR_ARG, "tp_block must be in [0, 256]");
+    if (o->gh_nodes < 0 || o->gh_nodes > xs::kMaxGHConv) return fail(XS_ERR_ARG, "gh_nodes must be in [0, 64]");
     const double dnu = (o->nu_b - o->nu_a) / (double)(o->n_points - 1);
     if (!(dnu > 0.0)) return fail(XS_ERR_ARG, "grid step underflows");
     const double hw = o->cutoff / dnu;
@@ -883,10 +884,25 @@ xs_status xs_plan_create(const xs_opts* opts, xs_plan** out) {
     xs::make_gh_pairs(4, &p->tabs.gh4);
     xs::make_gh_pairs(6, &p->tabs.gh6);
     xs::make_gh_pairs(12, &p->tabs.gh12);
-    xs::gauss_hermite_rule(xs::kGHConv, p->tabs.tconv, p->tabs.wconv);
-    for (int j = 0; j < xs::kGHConv; ++j) {
-        p->tabs.tconvf[j] = (float)p->tabs.tconv[j];
-        p->tabs.wconvf[j] = (float)p->tabs.wconv[j];
+    {
+        // the convolution profiles' rule (Eq. 30-31): gh_nodes nodes, "usually 30"
+        xs::Tables& t = p->tabs;
+        t.nconv = opts->gh_nodes > 0 ? opts->gh_nodes : xs::kGHConvDefault;
+        xs::gauss_hermite_rule(t.nconv, t.tconv, t.wconv);
+        for (int j = 0; j < t.nconv; ++j) {
+            t.tconvf[j] = (float)t.tconv[j];
+            t.wconvf[j] = (float)t.wconv[j];
+        }
+        // pairs +-t_j from the upper half of the ascending nodes; an odd rule's middle node
+        // (t = 0) enters the pair formula twice, so it carries half its weight
+        t.npair = 0;
+        for (int j = t.nconv / 2; j < t.nconv; ++j, ++t.npair) {
+            const bool zero = (t.nconv % 2 == 1) && j == t.nconv / 2;
+            t.tpair[t.npair] = zero ? 0.0 : t.tconv[j];
+            t.wpair[t.npair] = zero ? 0.5 * t.wconv[j] : t.wconv[j];
+            t.tpairf[t.npair] = (float)t.tpair[t.npair];
+            t.wpairf[t.npair] = (float)t.wpair[t.npair];
+        }
     }
     if ((st = p->ensure(p->tab_dev, sizeof(xs::Tables), "quadrature tables")) != XS_OK) { delete p; return st; }
     {
@@ -1594,6 +1610,15 @@ xs_status stream_create(xs_plan* p, int n_tp, const double* T, const double* P, 
     return XS_OK;
 }
 
+// Chunk index at which XS_FAULT_INJECT=chunk:k asks xs_stream_chunk to fail, or -1.
+int64_t injected_chunk() {
+    const char* v = std::getenv("XS_FAULT_INJECT");
+    if (!v || std::strncmp(v, "chunk:", 6) != 0) return -1;
+    char* end = nullptr;
+    const long long k = std::strtoll(v + 6, &end, 10);
+    return (end && end != v + 6 && *end == '\0' && k >= 0) ? (int64_t)k : -1;
+}
+
 // Line preparation and cross sections of the copied chunk, added into the accumulators.
 xs_status stream_process(xs_stream* st) {
     if (!st->have_pending) return XS_OK;
@@ -1616,7 +1641,45 @@ xs_status stream_process(xs_stream* st) {
     return XS_OK;
 }
 
-constexpr uint64_t kCkptMagic = 0x31544b4343455358ull;   // "XSECCKT1"
+constexpr uint64_t kCkptMagic = 0x32544b4343455358ull;   // "XSECCKT2"
+
+// What a checkpoint's sums depend on besides the (T, P) points: the grid, the cut-off, the
+// profile and its options, the mass and the broadening scheme with its constants.  A resume
+// refuses a plan that differs in any of them (the chunks would add onto sums of another
+// geometry).
+struct CkptGeometry {
+    double nu_a, nu_b, cutoff, mass_da, T0, P0, alpha_fixed, gamma_const, n_const, vv_radius;
+    int64_t profile, broadening, index_base, a_is_log, vv_beta, n_j;
+};
+
+CkptGeometry ckpt_geometry(const xs_plan* p) {
+    const xs_opts& o = p->o;
+    CkptGeometry c{};
+    c.nu_a = o.nu_a; c.nu_b = o.nu_b; c.cutoff = o.cutoff; c.mass_da = o.mass_da; c.T0 = o.T0; c.P0 = o.P0;
+    c.alpha_fixed = o.alpha_fixed; c.gamma_const = o.gamma_const; c.n_const = o.n_const;
+    c.vv_radius = p->geo.vv_radius;
+    c.profile = o.profile; c.broadening = o.broadening; c.index_base = o.index_base; c.a_is_log = o.a_is_log;
+    c.vv_beta = o.vv_beta;
+    c.n_j = o.broadening == XS_BROAD_A0_JLOWER ? p->n_j : 0;
+    return c;
+}
+
+// first field of the two geometries that differs, or NULL
+const char* ckpt_mismatch(const CkptGeometry& a, const CkptGeometry& b) {
+    if (std::memcmp(&a.nu_a, &b.nu_a, sizeof(double)) || std::memcmp(&a.nu_b, &b.nu_b, sizeof(double)))
+        return "grid range (nu_a, nu_b)";
+    if (std::memcmp(&a.cutoff, &b.cutoff, sizeof(double))) return "cut-off";
+    if (a.profile != b.profile || std::memcmp(&a.alpha_fixed, &b.alpha_fixed, sizeof(double)) ||
+        a.vv_beta != b.vv_beta || std::memcmp(&a.vv_radius, &b.vv_radius, sizeof(double)))
+        return "profile or its options";
+    if (std::memcmp(&a.mass_da, &b.mass_da, sizeof(double))) return "molecular mass";
+    if (a.broadening != b.broadening || std::memcmp(&a.T0, &b.T0, sizeof(double)) ||
+        std::memcmp(&a.P0, &b.P0, sizeof(double)) || std::memcmp(&a.gamma_const, &b.gamma_const, sizeof(double)) ||
+        std::memcmp(&a.n_const, &b.n_const, sizeof(double)) || a.n_j != b.n_j)
+        return "broadening scheme or its constants";
+    if (a.index_base != b.index_base || a.a_is_log != b.a_is_log) return "index base or A convention";
+    return nullptr;
+}
 
 }  // namespace
 
@@ -1647,6 +1710,9 @@ xs_status xs_stream_chunk(xs_stream* st, int64_t n, const int32_t* upper, const 
     if (n > 0 && (!upper || !lower || !A)) return fail(XS_ERR_ARG, "upper, lower and A must be non-NULL");
     const bool broad = p->o.broadening == XS_BROAD_PER_LINE;
     if (broad && n > 0 && (!gamma_ref || !n_exp)) return fail(XS_ERR_ARG, "per-line broadening needs gamma_ref and n_exp");
+    if (injected_chunk() == st->chunks)
+        return fail(XS_ERR_INJECTED, "fault injected before chunk " + std::to_string(st->chunks) +
+                                         " (XS_FAULT_INJECT)");
     const int k = (int)(st->chunks & 1);
     // the slot's previous chunk was prepared (synchronously) two calls ago
     if (n > st->raw_cap[k]) {
@@ -1708,7 +1774,9 @@ xs_status xs_stream_checkpoint(xs_stream* st, const char* path) {
     if (!f) return fail(XS_ERR_ARG, std::string("cannot write ") + tmp);
     const int64_t hdr[8] = {(int64_t)kCkptMagic, XS_ABI_VERSION, st->n_tp, p->geo.n_points, ckpt_kind(st),
                             st->chunks, st->lines, st->kept};
+    const CkptGeometry geo = ckpt_geometry(p);
     bool ok = std::fwrite(hdr, sizeof(hdr), 1, f) == 1;
+    ok = ok && std::fwrite(&geo, sizeof(geo), 1, f) == 1;
     ok = ok && std::fwrite(st->T.data(), sizeof(double), st->n_tp, f) == (size_t)st->n_tp;
     ok = ok && std::fwrite(st->P.data(), sizeof(double), st->n_tp, f) == (size_t)st->n_tp;
     ok = ok && std::fwrite(host.data(), 1, bytes, f) == bytes;
@@ -1736,6 +1804,15 @@ xs_status xs_stream_resume(xs_plan* p, const char* path, void* sigma, void* stre
     if (n_tp <= 0 || hdr[3] != p->geo.n_points || hdr[4] != (p->o.precision | (p->emission << 8))) {
         std::fclose(f);
         return fail(XS_ERR_ARG, "the checkpoint's grid, precision or intensity kind differs from the plan's");
+    }
+    CkptGeometry geo{};
+    if (std::fread(&geo, sizeof(geo), 1, f) != 1) {
+        std::fclose(f);
+        return fail(XS_ERR_ARG, "truncated checkpoint");
+    }
+    if (const char* what = ckpt_mismatch(geo, ckpt_geometry(p))) {
+        std::fclose(f);
+        return fail(XS_ERR_ARG, std::string("the checkpoint's ") + what + " differs from the plan's");
     }
     std::vector<double> T(n_tp), P(n_tp);
     const size_t bytes = (size_t)n_tp * p->geo.n_points * 2 * stream_elem(p);

@@ -330,14 +330,13 @@ __device__ __forceinline__ float v_ghs(const Tables* tab, const float* r, const 
     const float g2 = m[0], ad = m[NT], g4 = m[2 * NT];
     const float D2 = __builtin_fmaf(D, D, g2);
     float acc = 0.0f;
-#pragma unroll
-    for (int q = 0; q < kGHConv / 2; ++q) {
-        const float t = tab->tconvf[kGHConv / 2 + q];
-        const float dj = ad * t;
+    const int np = tab->npair;
+    for (int q = 0; q < np; ++q) {
+        const float dj = ad * tab->tpairf[q];
         const float d2 = dj * dj;
         const float p = D2 - d2;
         const float den = __builtin_fmaf(p, p, g4 * d2);
-        acc = __builtin_fmaf(2.0f * tab->wconvf[kGHConv / 2 + q] * (D2 + d2), __builtin_amdgcn_rcpf(den), acc);
+        acc = __builtin_fmaf(2.0f * tab->wpairf[q] * (D2 + d2), __builtin_amdgcn_rcpf(den), acc);
     }
     return r[LD::AMP] * acc;
 }
@@ -348,7 +347,8 @@ __device__ __forceinline__ float v_ghb(const Tables* tab, const float* r, const 
     const float D = __builtin_fmaf(j, r[LD::H], r[LD::XC]);
     const float ad = m[NT], hg = m[3 * NT], c = m[4 * NT];
     float acc = 0.0f;
-    for (int q = 0; q < kGHConv; ++q) {
+    const int nn = tab->nconv;
+    for (int q = 0; q < nn; ++q) {
         const float e = D - ad * tab->tconvf[q];
         acc = __builtin_fmaf(tab->wconvf[q], atan2f(hg, __builtin_fmaf(e, e, c)), acc);
     }

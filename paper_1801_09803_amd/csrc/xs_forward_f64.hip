@@ -201,11 +201,11 @@ __global__ __launch_bounds__(256) void fwd_f64_kernel(const FwdArgs A) {
                     const double ad = r[D_AD], g2 = y * y;
                     const double D2 = __builtin_fma(x, x, g2);
                     double accg = 0.0;
-                    for (int q = 0; q < kGHConv / 2; ++q) {
-                        const double dj = ad * A.tab->tconv[kGHConv / 2 + q];
+                    for (int q = 0; q < A.tab->npair; ++q) {
+                        const double dj = ad * A.tab->tpair[q];
                         const double d2 = dj * dj;
                         const double pq = D2 - d2;
-                        accg = __builtin_fma(2.0 * A.tab->wconv[kGHConv / 2 + q] * (D2 + d2),
+                        accg = __builtin_fma(2.0 * A.tab->wpair[q] * (D2 + d2),
                                              rcp64(__builtin_fma(pq, pq, 4.0 * g2 * d2)), accg);
                     }
                     v = a * accg;
@@ -214,7 +214,7 @@ __global__ __launch_bounds__(256) void fwd_f64_kernel(const FwdArgs A) {
                     const double ad = r[D_AD];
                     const double hg = G.dnu * y, c = y * y - 0.25 * G.dnu * G.dnu;
                     double accg = 0.0;
-                    for (int q = 0; q < kGHConv; ++q) {
+                    for (int q = 0; q < A.tab->nconv; ++q) {
                         const double e = x - ad * A.tab->tconv[q];
                         accg = __builtin_fma(A.tab->wconv[q], atan2(hg, __builtin_fma(e, e, c)), accg);
                     }

@@ -92,13 +92,20 @@ struct WeidemanCoef {
 
 // All quadrature tables of a plan, kept in one device buffer and read by the kernels
 // through a uniform pointer (scalar loads).
-constexpr int kGHConv = 30;   // nodes of the Gauss-Hermite convolution profiles
+constexpr int kGHConvDefault = 30;   // nodes of the Gauss-Hermite convolution profiles ("usually 30")
+constexpr int kMaxGHConv = 64;       // largest rule a plan may ask for
+constexpr int kMaxGHPair = kMaxGHConv / 2 + 1;
 struct Tables {
     WeidemanCoef w24;   // FP32 path core
     WeidemanCoef w40;   // FP64 path core
     GHPairs gh2, gh4, gh6, gh12;
-    double tconv[kGHConv], wconv[kGHConv];   // full 30-node rule (nodes ascending)
-    float tconvf[kGHConv], wconvf[kGHConv];
+    // Gauss-Hermite rule of the convolution profiles (Eq. 30-31): nconv nodes ascending,
+    // and its npair node pairs +-t (the zero node of an odd rule as a pair of half weight)
+    int nconv, npair;
+    double tconv[kMaxGHConv], wconv[kMaxGHConv];
+    float tconvf[kMaxGHConv], wconvf[kMaxGHConv];
+    double tpair[kMaxGHPair], wpair[kMaxGHPair];
+    float tpairf[kMaxGHPair], wpairf[kMaxGHPair];
 };
 
 // Host helpers implemented in xs_quadrature.cpp.

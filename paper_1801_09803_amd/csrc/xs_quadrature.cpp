@@ -46,7 +46,8 @@ void gauss_hermite_rule(int n, double* nodes, double* weights) {
     for (int i = 1; i <= steps && found < n; ++i) {
         long double b = -tmax + i * dt;
         long double fb = hermite_orthonormal(n, b, nullptr);
-        if (fb == 0.0L || (fa < 0) != (fb < 0)) {
+        // a root exactly at a scan point was taken with the interval that ended there
+        if (fa != 0.0L && (fb == 0.0L || (fa < 0) != (fb < 0))) {
             long double lo = a, hi = b, flo = fa;
             for (int it = 0; it < 200; ++it) {
                 long double mid = 0.5L * (lo + hi);

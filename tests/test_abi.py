@@ -36,7 +36,7 @@ def test_library_exports_every_declared_symbol():
 def test_version_and_defaults_without_gpu():
     from paper_1801_09803_amd.binding import XsOpts, load_library
     lib = load_library()
-    assert lib.xs_version() == 5
+    assert lib.xs_version() == 6
     o = XsOpts()
     assert lib.xs_opts_default(ctypes.byref(o)) == 0
     assert o.cutoff == 25.0 and o.T0 == 296.0 and o.P0 == 1.0 and o.profile == 3
@@ -45,7 +45,8 @@ def test_version_and_defaults_without_gpu():
 @pytest.mark.parametrize("field,value", [("n_points", 1), ("cutoff", 0.0), ("mass_da", -1.0),
                                          ("profile", 11), ("index_base", 2), ("slices_per_wave", 3),
                                          ("n_split", 65), ("n_split", -1), ("tp_block", 257),
-                                         ("vv_beta", 2), ("vv_radius", -1.0), ("vv_radius", float("nan"))])
+                                         ("vv_beta", 2), ("vv_radius", -1.0), ("vv_radius", float("nan")),
+                                         ("gh_nodes", -1), ("gh_nodes", 65)])
 def test_plan_create_rejects_bad_options_on_host(field, value):
     # option validation happens before any device call
     from paper_1801_09803_amd.binding import XsOpts, load_library
@@ -68,14 +69,32 @@ def test_null_arguments_are_rejected_without_gpu():
     assert lib.xs_cross_section(None, 1, None, None, None, None) == 1
 
 
-def test_struct_layouts_match_the_header():
-    # the binding's ctypes mirrors must keep the C sizes and offsets (xs_opts keeps its
-    # size: the tile-configuration and Vectorized Voigt fields took reserved slots)
-    from paper_1801_09803_amd.binding import XsKernelTimes, XsOpts
-    assert ctypes.sizeof(XsOpts) == 8 * 7 + 4 * 4 + 8 * 3 + 4 * 6 + 8
-    assert XsOpts.vv_beta.offset == 116 and XsOpts.vv_radius.offset == 120
-    assert ctypes.sizeof(XsKernelTimes) == 8 * 11
-    assert XsKernelTimes.far_ms.offset == 72 and XsKernelTimes.far_launches.offset == 80
+def _c_layout(struct, fields, tmp_path):
+    """sizeof and offsetof of a header struct, printed by a C program compiled against it."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "layout.c"
+    body = "".join(f'  printf("%zu\\n", offsetof({struct}, {f}));\n' for f in fields)
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "xsec.h"\nint main(void) {\n'
+                   f'  printf("%zu\\n", sizeof({struct}));\n{body}  return 0;\n}}\n')
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()
+    return int(out[0]), [int(v) for v in out[1:]]
+
+
+@pytest.mark.parametrize("struct,mirror", [("xs_opts", "XsOpts"), ("xs_timings", "XsKernelTimes")])
+def test_struct_layouts_match_the_header(struct, mirror, tmp_path):
+    # the binding's ctypes mirrors keep the C sizes and every field offset
+    from paper_1801_09803_amd import binding
+    cls = getattr(binding, mirror)
+    fields = [f for f, _ in cls._fields_]
+    size, offs = _c_layout(struct, fields, tmp_path)
+    assert ctypes.sizeof(cls) == size
+    assert [getattr(cls, f).offset for f in fields] == offs
 
 
 def test_graph_and_tuning_calls_reject_null_plans_on_host():

@@ -194,7 +194,7 @@ def test_autotune_picks_a_valid_configuration(case, oracle_at):
     best = plan.autotune(TS, PS, budget_ms=4000.0)
     log(f"autotune: {best}")
     assert best["waves"] in (1, 2, 4, 8) and best["slices"] in (1, 2, 4)
-    assert 1 <= best["n_split"] <= 32 and 1 <= best["tp_block"] <= len(TS)
+    assert 1 <= best["n_split"] <= 64 and 1 <= best["tp_block"] <= len(TS)
     cfgd = plan.tile_config()
     assert (cfgd["waves"], cfgd["slices"], cfgd["n_split"], cfgd["tp_block"]) == \
         (best["waves"], best["slices"], best["n_split"], best["tp_block"])

@@ -236,6 +236,21 @@ def test_gauss_hermite_profiles(profile, precision, T, P):
     assert_parity(got, ref, TOL32 if precision == "fp32" else TOL64, what=f"{profile} {precision} T={T}")
 
 
+@pytest.mark.parametrize("profile", ["gh_sampled", "gh_binned"])
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("n_gh", [1, 2, 20, 31, 64])
+def test_gauss_hermite_rule_size(profile, precision, n_gh):
+    # gh_nodes: the Gauss-Hermite rule of Eq. 30-31 with n_gh nodes (odd rules hold a node
+    # at zero; one node is the Lorentzian itself) against the oracle's rule of that size
+    cfg, d = _small_case(11, n_lines=1200)
+    h = host(d)
+    plan = make_plan(cfg, precision, profile=profile, gh_nodes=n_gh)
+    got = _run(plan, d, [1200.0], [0.3])[0]
+    ls = oracle_lineset(h, cfg, 1200.0, 0.3)
+    ref = O.cross_section(ls, cfg.nu_a, cfg.nu_b, cfg.n_points, cfg.cutoff, profile=profile, n_gh=n_gh, workers=1)
+    assert_parity(got, ref, TOL32 if precision == "fp32" else TOL64, what=f"{profile} {precision} n_gh={n_gh}")
+
+
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
 def test_gh_binned_pure_doppler_limit(precision):
     # P = 0: each node becomes a delta function; the binned profile is a 30-point

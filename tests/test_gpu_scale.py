@@ -1,6 +1,8 @@
-"""Parity at the workloads' full sizes, in the launch configuration bench.py times,
-on sampled grid points the FP64 oracle computes one by one (every line whose window
-holds the point)."""
+"""Parity at the workloads' full sizes, on sampled grid points the FP64 oracle computes
+one by one (every line whose window holds the point).  The C2 test runs both temperatures
+in one batched call in the tile configuration the benchmark times on C2 (one wavefront x
+four 64-point slices per workgroup, 64 shares per tile, two (T, P) per launch) and at
+the autotuner's pick; the others use the library's default configuration."""
 import math
 
 import numpy as np
@@ -25,27 +27,43 @@ def _sample_points(sig, n_rand, seed, n_points):
 
 
 def _oracle_at(cfg, d, ks, T, P, margin=25.5, vv_beta=None, emission=False):
-    """Oracle sigma at grid indices ks: lines near each point are gathered on the
-    device (a generous distance filter) and evaluated on the host."""
-    E = d["E"]
-    nu = E[d["upper"].long()] - E[d["lower"].long()]
-    nu_k = torch.tensor(cfg.nu_a + ks.astype(np.float64) * cfg.dnu, device=nu.device)
-    sel = torch.zeros_like(nu, dtype=torch.bool)
-    for v in nu_k:
-        sel |= (nu - v).abs() <= margin
-    idx = torch.nonzero(sel).squeeze(1)
-    h = {k: d[k][idx].cpu().numpy() for k in ("upper", "lower", "A", "gamma_ref", "n_exp")}
-    Eh, gh = E.cpu().numpy(), d["g"].cpu().numpy()
+    """Oracle sigma at grid indices ks: for each point, the lines whose centre lies within
+    `margin` of it (a superset of those whose window holds it) are found in the
+    centre-sorted list on the device and evaluated on the host."""
+    order, nu_sorted = _sorted_centres(d)
+    Eh, gh = d["E"].cpu().numpy(), d["g"].cpu().numpy()
     Q = O.partition_function(Eh, gh, T)
-    ls = O.make_lineset(Eh, gh, h["upper"], h["lower"], h["A"], T, P, cfg.mass_amu,
-                        gamma_ref=h["gamma_ref"], n_exp=h["n_exp"], Q=Q)
-    if emission:
-        ls.I = O.emissivities(Eh, gh, h["upper"], h["lower"], h["A"], T, Q=Q)
-    log(f"  oracle: {idx.numel()} lines near {ks.size} points")
-    if vv_beta is not None:
-        return O.cross_section_vv_at(ls, ks, cfg.nu_a, cfg.nu_b, cfg.n_points, T, cfg.mass_amu, cutoff=cfg.cutoff,
-                                     radius=4.0, use_beta=vv_beta)
-    return O.cross_section_at(ls, ks, cfg.nu_a, cfg.nu_b, cfg.n_points, cfg.cutoff)
+    out = np.zeros(ks.size)
+    n_lines = 0
+    for i, k in enumerate(ks.tolist()):
+        v = cfg.nu_a + float(k) * cfg.dnu
+        lo = int(torch.searchsorted(nu_sorted, torch.tensor([v - margin], dtype=torch.float64, device="cuda")))
+        hi = int(torch.searchsorted(nu_sorted, torch.tensor([v + margin], dtype=torch.float64, device="cuda"),
+                                    right=True))
+        idx = order[lo:hi]
+        n_lines += hi - lo
+        h = {key: d[key][idx].cpu().numpy() for key in ("upper", "lower", "A", "gamma_ref", "n_exp")}
+        ls = O.make_lineset(Eh, gh, h["upper"], h["lower"], h["A"], T, P, cfg.mass_amu,
+                            gamma_ref=h["gamma_ref"], n_exp=h["n_exp"], Q=Q)
+        if emission:
+            ls.I = O.emissivities(Eh, gh, h["upper"], h["lower"], h["A"], T, Q=Q)
+        if vv_beta is not None:
+            out[i] = O.cross_section_vv_at(ls, np.array([k]), cfg.nu_a, cfg.nu_b, cfg.n_points, T, cfg.mass_amu,
+                                           cutoff=cfg.cutoff, radius=4.0, use_beta=vv_beta)[0]
+        else:
+            out[i] = O.cross_section_at(ls, np.array([k]), cfg.nu_a, cfg.nu_b, cfg.n_points, cfg.cutoff)[0]
+    log(f"  oracle: {n_lines} (line, point) pairs near {ks.size} points")
+    return out
+
+
+def _sorted_centres(d):
+    """Line centres sorted on the device (cached with the inputs)."""
+    if "_order" not in d:
+        E = d["E"]
+        nu = E[d["upper"].long()] - E[d["lower"].long()]
+        nu_sorted, order = torch.sort(nu)
+        d["_order"], d["_nu_sorted"] = order, nu_sorted
+    return d["_order"], d["_nu_sorted"]
 
 
 def _check(got, ref, tol, what):
@@ -64,17 +82,39 @@ def c2():
     return cfg, d
 
 
-@pytest.mark.parametrize("T", [296.0, 2000.0])
-def test_c2_full_size_fp32_sampled(c2, T):
+# tile configuration of the C2 benchmark step: waves, slices, n_split, tp_block
+BENCH_TILE = (1, 4, 64, 2)
+
+
+def _c2_batched_fp32(cfg, d, plan, tag):
+    Ts, Ps = [296.0, 2000.0], [1.0, 1.0]
+    out = plan.cross_section(Ts, Ps).double().cpu().numpy()
+    for i, T in enumerate(Ts):
+        ks = _sample_points(out[i], 200, int(T), cfg.n_points)
+        ref = _oracle_at(cfg, d, ks, T, 1.0)
+        _check(out[i][ks], ref, 1e-5, f"C2 fp32 T={T} {tag}")
+
+
+def test_c2_full_size_fp32_sampled_bench_tile(c2):
     cfg, d = c2
     plan = make_plan(cfg, "fp32")
     plan.set_states(d["E"], d["g"], d["J"])
     plan.set_lines(d["upper"], d["lower"], d["A"], d["gamma_ref"], d["n_exp"])
     assert plan.lines_kept() == cfg.n_lines
-    sig = plan.cross_section([T], [1.0])[0].double().cpu().numpy()
-    ks = _sample_points(sig, 24, int(T), cfg.n_points)
-    ref = _oracle_at(cfg, d, ks, T, 1.0)
-    _check(sig[ks], ref, 1e-5, f"C2 fp32 T={T}")
+    plan.set_tile_config(*BENCH_TILE)
+    _c2_batched_fp32(cfg, d, plan, "tile=%s" % (BENCH_TILE,))
+    t = plan.tile_config()
+    assert (t["waves"], t["slices"], t["last_split"], t["last_block"]) == BENCH_TILE, t
+
+
+def test_c2_full_size_fp32_sampled_autotuned(c2):
+    cfg, d = c2
+    plan = make_plan(cfg, "fp32")
+    plan.set_states(d["E"], d["g"], d["J"])
+    plan.set_lines(d["upper"], d["lower"], d["A"], d["gamma_ref"], d["n_exp"])
+    best = plan.autotune([296.0, 2000.0], [1.0, 1.0], budget_ms=6000.0)
+    log(f"  autotuned: {best}")
+    _c2_batched_fp32(cfg, d, plan, f"autotuned={best}")
 
 
 def test_c2_full_size_fp64_sampled(c2):
@@ -137,17 +177,20 @@ def test_c2_full_size_state_reductions(c2):
 
 
 def test_c3_subset_full_size(c2):
-    # C3 uses C2's list; three of its 270 (T, P) points, batched in one call
+    # C3 uses C2's list; six of its 270 (T, P) points in one batched call: the grid's
+    # corners (100 K at 1e-5 bar, 3000 K at 100 bar, ...) and two seeded interior points
     cfg3 = synth.CONFIGS["C3"]
     cfg, d = c2
-    Ts = [cfg3.temperatures[0], cfg3.temperatures[13], cfg3.temperatures[26]]
-    Ps = [cfg3.pressures[0], cfg3.pressures[5], cfg3.pressures[9]]
+    rng = np.random.default_rng(3)
+    idx = [(0, 0), (26, 9), (0, 9), (26, 0)] + [(int(rng.integers(1, 26)), int(rng.integers(1, 9))) for _ in range(2)]
+    Ts = [cfg3.temperatures[i] for i, _ in idx]
+    Ps = [cfg3.pressures[j] for _, j in idx]
     plan = make_plan(cfg3, "fp32")
     plan.set_states(d["E"], d["g"], d["J"])
     plan.set_lines(d["upper"], d["lower"], d["A"], d["gamma_ref"], d["n_exp"])
     out = plan.cross_section(Ts, Ps).double().cpu().numpy()
     for i, (T, P) in enumerate(zip(Ts, Ps)):
-        ks = _sample_points(out[i], 8, 100 + i, cfg.n_points)
+        ks = _sample_points(out[i], 200, 100 + i, cfg.n_points)
         ref = _oracle_at(cfg3, d, ks, T, P)
         keep = ref > 1e-6 * out[i].max()       # the parity floor of the full-grid metric
         _check(out[i][ks][keep], ref[keep], 1e-5, f"C3 T={T:.1f} P={P:.2e}")

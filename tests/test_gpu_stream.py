@@ -138,3 +138,56 @@ def test_stream_reports_invalid_transitions(case):
         st.chunk(chunks[1]["upper"], chunks[1]["lower"], chunks[1]["A"])    # the bad chunk computes here
     assert "XS_ERR_INDEX" in str(e.value)
     st.end()
+
+
+def test_stream_injected_fault_then_resume_is_bitwise(case, tmp_path, monkeypatch):
+    # checkpoint after two chunks, an injected fault at the third (XS_FAULT_INJECT=chunk:2:
+    # refused before any copy or device work), then a resumed stream finishes the list;
+    # its sums equal the uninterrupted run's bit for bit
+    cfg, states, table, chunks, allv = case
+    ref = _stream(_plan(cfg, states, table, "fp32"), chunks).end()[0].cpu().numpy()
+    st = _stream(_plan(cfg, states, table, "fp32"), chunks, upto=2)
+    path = str(tmp_path / "inject.ckpt")
+    st.checkpoint(path)
+    monkeypatch.setenv("XS_FAULT_INJECT", "chunk:2")
+    c = chunks[2]
+    with pytest.raises(Exception) as e:
+        st.chunk(c["upper"], c["lower"], c["A"])
+    assert "XS_ERR_INJECTED" in str(e.value)
+    assert st.stats()["chunks"] == 2                 # the refused chunk left no trace
+    st.end()                                         # the interrupted run ends here
+    monkeypatch.delenv("XS_FAULT_INJECT")
+    from paper_1801_09803_amd import Stream
+    st2 = Stream.resume(_plan(cfg, states, table, "fp32"), path, n_tp=len(TS))
+    for c in chunks[2:]:
+        st2.chunk(c["upper"], c["lower"], c["A"])
+    got = st2.end()[0].cpu().numpy()
+    assert np.array_equal(got, ref)
+
+
+def test_stream_resume_refuses_another_geometry(case, tmp_path):
+    cfg, states, table, chunks, allv = case
+    st = _stream(_plan(cfg, states, table, "fp32"), chunks, upto=1)
+    path = str(tmp_path / "geo.ckpt")
+    st.checkpoint(path)
+    st.end()
+    from paper_1801_09803_amd import Plan, Stream
+    for kw, what in ((dict(cutoff=20.0), "cut-off"), (dict(mass_da=17.0), "mass"),
+                     (dict(profile="lorentz"), "profile")):
+        args = dict(cutoff=cfg.cutoff, profile="voigt", precision="fp32", broadening="a0_jlower")
+        mass = kw.pop("mass_da", cfg.mass_amu)
+        args.update(kw)
+        plan = Plan(cfg.nu_a, cfg.nu_b, cfg.n_points, mass, **args)
+        plan.set_broadening_table(*table)
+        plan.set_states(states["E"], states["g"], states["J"])
+        with pytest.raises(Exception) as e:
+            Stream.resume(plan, path, n_tp=len(TS))
+        assert "XS_ERR_ARG" in str(e.value) and what in str(e.value), str(e.value)
+    # the same grid points over another range
+    plan = Plan(cfg.nu_a + 1.0, cfg.nu_b + 1.0, cfg.n_points, cfg.mass_amu, cutoff=cfg.cutoff, profile="voigt",
+                precision="fp32", broadening="a0_jlower")
+    plan.set_broadening_table(*table)
+    plan.set_states(states["E"], states["g"], states["J"])
+    with pytest.raises(Exception) as e:
+        Stream.resume(plan, path, n_tp=len(TS))
+    assert "grid range" in str(e.value)
