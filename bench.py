@@ -34,7 +34,7 @@ sys.path.insert(0, ROOT)
 # accumulate FMA + rcp) 7; 2-node rule at |z| >= 40 (x, p, den, num, accumulate FMA + rcp)
 # 11; 4-node rule at 8 <= |z| < 40 (x + two node pairs of three FMA and a rcp + two
 # accumulate FMA) 20; a core value precomputed by the FP64 pre-pass, added: 1.
-ZONE_FLOPS = {"one_pole": 7, "two_node": 11, "four_node": 20, "core": 1, "far_node": 11}
+ZONE_FLOPS = {"one_pole": 7, "two_node": 11, "four_node": 20, "core": 1, "far_node": 11, "far_exact": 11}
 FAR_NODES = 16        # far-wing nodes per wavefront of the FP32 Voigt sweep
 
 
@@ -45,27 +45,33 @@ def far_reach(ww):
 
 def zone_counts(cfg, d, T, P, waves=None, slices=None, chunk=1 << 24):
     """Window points of every line per zone at (T, P) (x = sqrt(ln2)(nu_k - nu)/alpha_D,
-    |z|^2 = x^2 + y^2, y = sqrt(ln2) gamma/alpha_D), counted from index ranges.  With the
-    tile shape (waves, slices), the points of the (line, wavefront) pairs that the far-wing
-    kernel samples at FAR_NODES nodes are counted as far_node evaluations instead (the line
-    centre at least far_reach grid steps from the wavefront of 64 * slices points, its
-    window covering it: kc in [w1 - hmin, w0 - reach) or (w1 + reach, w0 + hmin])."""
+    |z|^2 = x^2 + y^2, y = sqrt(ln2) gamma/alpha_D), counted from index ranges.
+
+    With the tile shape (waves, slices) of the FP32 Voigt sweep, the tile kernel evaluates
+    only the (line, wavefront) pairs whose centre lies within far_reach grid steps of the
+    wavefront of 64 * slices points; their points are counted per zone.  Every other pair
+    the window overlaps goes to the far-wing kernel: FAR_NODES node evaluations each
+    (far_node), plus, where the window starts or ends inside the wavefront, the points of
+    that end's block evaluated one by one (far_exact)."""
     import torch
     kB, amu, c_si, ln2 = 1.380649e-23, 1.66053906660e-27, 299792458.0, math.log(2.0)
     beta = math.sqrt(2.0 * kB * T * ln2 / (cfg.mass_amu * amu)) / c_si
     E = d["E"]
     tot = {k: 0 for k in ZONE_FLOPS}
+    tot["far_exact"] = 0
     n = d["upper"].numel()
     far = waves is not None
     if far:
         ww = 64 * slices
+        bw = 4 if slices == 1 else 8          # points per window-end block of the far kernel
         reach = far_reach(ww)
         dnu = (cfg.nu_b - cfg.nu_a) / (cfg.n_points - 1)
         hmin = math.floor(cfg.cutoff / dnu) - 2
-        n_waves = -(-cfg.n_points // (waves * ww)) * waves
-        # the sampled lines must lie beyond the |z| < 40 radius of every wavefront
+        # the sampled lines must lie beyond the |z| < 40 radius of every wavefront, and the
+        # window ends beyond the far reach (the library's condition for sampling them)
         rm_max = 40.0 * beta * (cfg.nu_b + cfg.cutoff) / (math.sqrt(ln2) * dnu) + 3.0
         assert reach >= rm_max, "far-wing reach inside the |z| < 40 radius: counts would not match"
+        assert hmin - ww + 2 >= reach, "window ends not node-sampled at this geometry: counts would not match"
     for a in range(0, n, chunk):
         b = min(n, a + chunk)
         nu = E[d["upper"][a:b].long()] - E[d["lower"][a:b].long()]
@@ -74,44 +80,38 @@ def zone_counts(cfg, d, T, P, waves=None, slices=None, chunk=1 << 24):
         y2 = (gam * s) ** 2
         klo = torch.clamp(torch.ceil(((nu - cfg.cutoff) - cfg.nu_a) / cfg.dnu), min=0)
         khi = torch.clamp(torch.floor(((nu + cfg.cutoff) - cfg.nu_a) / cfg.dnu), max=cfg.n_points - 1)
-        n_all = torch.clamp(khi - klo + 1, min=0)
+        live = khi >= klo
+        if far:
+            # the tile kernel's part of the window: wavefronts within reach of the centre
+            kc = torch.floor((nu - cfg.nu_a) / cfg.dnu + 0.5)
+            wl, wr = torch.floor(klo / ww), torch.floor(khi / ww)
+            na = torch.maximum(torch.ceil((kc - reach - ww + 1) / ww), wl)
+            nb = torch.minimum(torch.floor((kc + reach) / ww), wr)
+            near_w = torch.clamp(nb - na + 1, min=0)
+            lo_k = torch.maximum(klo, na * ww)
+            hi_k = torch.minimum(khi, nb * ww + ww - 1)
+            lo_k = torch.where(near_w > 0, lo_k, khi + 1)   # no near wavefront: nothing here
+            far_w = torch.where(live, (wr - wl + 1) - near_w, torch.zeros_like(wl))
+            tot["far_node"] += FAR_NODES * int(far_w.sum().item())
+            # window ends inside a far wavefront: their block's points one by one
+            left_far = live & ((wl < na) | (near_w == 0))
+            right_far = live & ((wr > nb) | (near_w == 0))
+            ex_l = torch.where(left_far, bw - torch.remainder(klo - wl * ww, bw), torch.zeros_like(klo))
+            ex_r = torch.where(right_far, torch.remainder(khi - wr * ww, bw) + 1, torch.zeros_like(khi))
+            tot["far_exact"] += int((ex_l + ex_r).sum().item())
+        else:
+            lo_k, hi_k = klo, khi
+        n_all = torch.clamp(hi_k - lo_k + 1, min=0)
 
-        def inside(X):   # points of the window with |x| < X
+        def inside(X):   # points of [lo_k, hi_k] with |x| < X
             R = X / s
-            lo = torch.maximum(torch.floor((nu - R - cfg.nu_a) / cfg.dnu) + 1, klo)
-            hi = torch.minimum(torch.ceil((nu + R - cfg.nu_a) / cfg.dnu) - 1, khi)
+            lo = torch.maximum(torch.floor((nu - R - cfg.nu_a) / cfg.dnu) + 1, lo_k)
+            hi = torch.minimum(torch.ceil((nu + R - cfg.nu_a) / cfg.dnu) - 1, hi_k)
             return torch.where(X > 0, torch.clamp(hi - lo + 1, min=0), torch.zeros_like(X))
 
         n_x = inside(torch.full_like(nu, 1000.0))
         n_40 = inside(torch.sqrt(torch.clamp(1600.0 - y2, min=0.0)))
         n_8 = inside(torch.sqrt(torch.clamp(64.0 - y2, min=0.0)))
-        if far:
-            kc = torch.floor((nu - cfg.nu_a) / cfg.dnu + 0.5)
-            R = 1000.0 / s   # |x| < 1000 range, as in inside()
-            xlo = torch.maximum(torch.floor((nu - R - cfg.nu_a) / cfg.dnu) + 1, klo)
-            xhi = torch.minimum(torch.ceil((nu + R - cfg.nu_a) / cfg.dnu) - 1, khi)
-            live = n_all > 0
-
-            def span(ia, ib):   # far wavefronts [ia, ib]: count, their window points, those at |x| < 1000
-                ia = torch.clamp(ia, min=0)
-                ib = torch.clamp(ib, max=n_waves - 1)
-                nw = torch.where(live, torch.clamp(ib - ia + 1, min=0), torch.zeros_like(ia))
-                a = torch.maximum(ia * ww, klo)
-                b = torch.minimum(ib * ww + ww - 1, khi)
-                pts = torch.where(nw > 0, torch.clamp(b - a + 1, min=0), torch.zeros_like(a))
-                two = torch.where(nw > 0, torch.clamp(torch.minimum(b, xhi) - torch.maximum(a, xlo) + 1, min=0),
-                                  torch.zeros_like(a))
-                return nw, pts, two
-
-            # wavefronts right of the line (left-hand runs) and left of it (right-hand runs)
-            rw = span(torch.floor((kc + reach) / ww) + 1, torch.floor((kc + hmin - ww + 1) / ww))
-            lw = span(torch.floor((kc - hmin - 1) / ww) + 1, torch.floor((kc - reach - ww) / ww))
-            n_far = rw[0] + lw[0]
-            pts_far = rw[1] + lw[1]
-            two_far = rw[2] + lw[2]
-            tot["far_node"] += FAR_NODES * int(n_far.sum().item())
-            tot["one_pole"] -= int((pts_far - two_far).sum().item())
-            tot["two_node"] -= int(two_far.sum().item())
         tot["one_pole"] += int((n_all - n_x).sum().item())
         tot["two_node"] += int((n_x - n_40).sum().item())
         tot["four_node"] += int((n_40 - n_8).sum().item())
@@ -319,7 +319,7 @@ def main():
     tile = plan.tile_config()
     zones = [zone_counts(cfg, d, T, P, tile["waves"], tile["slices"]) for T, P in zip(temps, pressures)]
     # the tile kernel evaluates the window points outside the node-sampled far wing
-    tile_zones = [k for k in ZONE_FLOPS if k != "far_node"]
+    tile_zones = [k for k in ZONE_FLOPS if k not in ("far_node", "far_exact")]
     flops_step = sum(sum(ZONE_FLOPS[k] * z[k] for k in tile_zones) for z in zones)
     tile_points_step = sum(sum(z[k] for k in tile_zones) for z in zones)
     launches_per_step = kt["forward_launches"] / args.steps
@@ -329,17 +329,19 @@ def main():
     # far-wing kernel: FAR_NODES 2-node evaluations per (line, wavefront) it samples; it
     # reads 28 B of line data (hot record words and kc) per such pair
     far_nodes_step = sum(z["far_node"] for z in zones)
+    far_exact_step = sum(z["far_exact"] for z in zones)
     far_s_step = kt["far_ms"] / 1e3 / args.steps
     far_obj = None
     if kt["far_launches"] > 0 and far_nodes_step > 0:
         far_obj = {
             "avg_launch_ms": kt["far_ms"] / kt["far_launches"],
             "node_evaluations_per_tp": far_nodes_step / len(temps),
-            "achieved_tflops": ZONE_FLOPS["far_node"] * far_nodes_step / far_s_step / 1e12,
+            "window_end_point_evaluations_per_tp": far_exact_step / len(temps),
+            "achieved_tflops": ZONE_FLOPS["far_node"] * (far_nodes_step + far_exact_step) / far_s_step / 1e12,
             "line_data_GBps": 28.0 * far_nodes_step / FAR_NODES / far_s_step / 1e9,
-            "note": "node-sampled far wing (lines >= far_reach grid steps from a wavefront): 16 "
-                    "2-node evaluations per (line, wavefront) pair, 11 flops each, then one 8-point "
-                    "interpolation per wavefront; line data from L2/MALL",
+            "note": "node-sampled wings (every (line, wavefront) pair whose centre lies >= far_reach grid "
+                    "steps away): 16 2-node evaluations per pair, 11 flops each, and the points of a window "
+                    "end's block one by one; one 8-point interpolation per point; line data from L2/MALL",
         }
 
     result = {

@@ -395,6 +395,15 @@ xs_status xs_stream_begin(xs_plan* plan, int32_t n_tp, const double* T, const do
                           void* sigma, void* stream, xs_stream** out);
 xs_status xs_stream_chunk(xs_stream* st, int64_t n, const int32_t* upper, const int32_t* lower,
                           const float* A, const float* gamma_ref, const float* n_exp);
+/* A chunk already in device memory (a line list kept resident in HBM, such as a list of
+ * 4e9 transitions at 12 B each): upper, lower, A (and gamma_ref, n_exp for
+ * XS_BROAD_PER_LINE) are device arrays of n transitions.  Nothing is copied: a pending
+ * host chunk is computed first, then this chunk is prepared (as xs_set_lines: synchronous,
+ * XS_ERR_INDEX / XS_ERR_NU_NONPOS at once) and its cross sections are added into the
+ * accumulators on the stream's compute stream.  The arrays are read only during the call.
+ * Counts as one chunk (fault injection included). */
+xs_status xs_stream_chunk_device(xs_stream* st, int64_t n, const int32_t* upper, const int32_t* lower,
+                                 const float* A, const float* gamma_ref, const float* n_exp);
 xs_status xs_stream_end(xs_stream* st, int64_t* lines_kept);
 xs_status xs_stream_checkpoint(xs_stream* st, const char* path);
 xs_status xs_stream_resume(xs_plan* plan, const char* path, void* sigma, void* stream,

@@ -92,6 +92,7 @@ def load_library() -> ctypes.CDLL:
         "xs_graph_workspace_bytes": (ctypes.c_size_t, [P]),
         "xs_stream_begin": (i32, [P, i32, P, P, P, P, ctypes.POINTER(P)]),
         "xs_stream_chunk": (i32, [P, i64, P, P, P, P, P]),
+        "xs_stream_chunk_device": (i32, [P, i64, P, P, P, P, P]),
         "xs_stream_end": (i32, [P, ctypes.POINTER(i64)]),
         "xs_stream_checkpoint": (i32, [P, ctypes.c_char_p]),
         "xs_stream_resume": (i32, [P, ctypes.c_char_p, P, P, ctypes.POINTER(P)]),
@@ -549,6 +550,21 @@ class Stream:
                                          _ptr(gamma_ref), _ptr(n_exp)))
         # the host arrays must outlive their asynchronous copy (until the next call returns)
         self._held = [upper, lower, A, gamma_ref, n_exp]
+
+    def chunk_device(self, upper, lower, A, gamma_ref=None, n_exp=None):
+        """A chunk whose arrays already live on the GPU (no copy; computed during the call)."""
+        plan = self._plan
+        torch = plan._torch
+        upper = plan._dev(upper, torch.int32, "upper")
+        lower = plan._dev(lower, torch.int32, "lower")
+        A = plan._dev(A, torch.float32, "A")
+        gamma_ref = plan._dev(gamma_ref, torch.float32, "gamma_ref")
+        n_exp = plan._dev(n_exp, torch.float32, "n_exp")
+        n = _same_length("chunk_device", ("upper", upper), ("lower", lower), ("A", A), ("gamma_ref", gamma_ref),
+                         ("n_exp", n_exp))
+        plan._n_lines = None   # each chunk replaces the plan's line set
+        _check(self._lib.xs_stream_chunk_device(self._h, n, _ptr(upper), _ptr(lower), _ptr(A), _ptr(gamma_ref),
+                                                _ptr(n_exp)))
 
     def checkpoint(self, path: str):
         _check(self._lib.xs_stream_checkpoint(self._h, os.fsencode(path)))

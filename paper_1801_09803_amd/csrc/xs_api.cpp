@@ -418,6 +418,9 @@ bool vv_needed(const xs_plan* p) { return is_vv(p) && (p->o.vv_beta || p->o.prof
 // FP32 Voigt: the segmented sweep leaves lines far from a wavefront to the node-sampled
 // far-wing kernel, whose per-share sums need a buffer of at most kFarShares shares
 constexpr int kFarShares = 4;
+// grid steps between a wavefront of ww points and the nearest node-sampled line centre (the
+// kernels' far_reach: 24 spacings of the 16 nodes across the wavefront)
+int far_reach_steps(int ww) { return (24 * (ww - 1) + 14) / 15; }
 bool far_sampled(const xs_plan* p) { return p->o.precision == XS_FP32 && p->o.profile == XS_VOIGT; }
 
 // Profile index of the kernels (the area-normalised form differs in its intensities only)
@@ -633,6 +636,13 @@ xs::FwdArgs fwd_args(xs_plan* p, Workset& ws, const std::vector<xs::TPParam>& tp
         const int64_t nw = std::max<int64_t>(1, (int64_t)a.n_tiles * p->waves * nb);
         a.far = as<double>(ws.far);
         a.far_share = (int)std::min<int64_t>(kFarShares, std::max<int64_t>(1, (16384 + nw - 1) / nw));
+        // the window ends go to the far kernel too when every window-end line lies beyond both
+        // the far reach and the |z| < 40 radius of any wavefront it ends in: such lines are
+        // at least hmin - WW + 2 steps from it
+        const int WW = 64 * p->P;
+        int rm = 0;
+        for (int t = f; t < f + nb; ++t) rm = std::max(rm, tps[t].rm);
+        a.far_ends = (int64_t)p->geo.hmin - WW + 2 >= (int64_t)std::max(far_reach_steps(WW), rm) ? 1 : 0;
     }
     return a;
 }
@@ -1741,6 +1751,32 @@ xs_status xs_stream_chunk(xs_stream* st, int64_t n, const int32_t* upper, const 
     st->pending_n = n;
     st->pending_broad = broad;
     st->chunks++;
+    return XS_OK;
+}
+
+xs_status xs_stream_chunk_device(xs_stream* st, int64_t n, const int32_t* upper, const int32_t* lower,
+                                 const float* A, const float* gamma_ref, const float* n_exp) {
+    if (!st) return fail(XS_ERR_ARG, "stream is NULL");
+    xs_plan* p = st->p;
+    if (n < 0 || n > ((int64_t)1 << 31) - 1) return fail(XS_ERR_ARG, "chunk size must be in [0, 2^31-1]");
+    if (n > 0 && (!upper || !lower || !A)) return fail(XS_ERR_ARG, "upper, lower and A must be non-NULL");
+    const bool broad = p->o.broadening == XS_BROAD_PER_LINE;
+    if (broad && n > 0 && (!gamma_ref || !n_exp)) return fail(XS_ERR_ARG, "per-line broadening needs gamma_ref and n_exp");
+    if (injected_chunk() == st->chunks)
+        return fail(XS_ERR_INJECTED, "fault injected before chunk " + std::to_string(st->chunks) +
+                                         " (XS_FAULT_INJECT)");
+    // a pending host chunk computes first, then this one straight from the caller's arrays
+    XS_TRY(stream_process(st));
+    st->chunks++;
+    if (p->emission != st->emission)
+        return fail(XS_ERR_STATE, "the plan's intensity kind changed while the stream was open");
+    XS_TRY(xs_set_lines(p, n, upper, lower, A, broad ? gamma_ref : nullptr, broad ? n_exp : nullptr, st->compute));
+    st->lines += n;
+    st->kept += p->n_kept;
+    if (p->n_kept == 0) return XS_OK;
+    XS_TRY(xs_cross_section(p, st->n_tp, st->T.data(), st->P.data(), st->tmp.p, st->compute));
+    XS_HIP(xs::launch_acc_add(p->o.precision == XS_FP64 ? 1 : 0, st->tmp.p, st->acc.p,
+                              (int64_t)st->n_tp * p->geo.n_points, st->compute));
     return XS_OK;
 }
 

@@ -84,6 +84,11 @@ struct FwdArgs {
     // [n_tp][far_share][n_points], added by launch_combine; NULL: the tile kernel sums every line
     double* far;
     int far_share;
+    // far: the window-end runs (windows ending or starting inside a wavefront) are
+    // node-sampled by far_kernel as well (every such line lies beyond the far reach and the
+    // |z| < 40 radius of the wavefront); the tile kernel then sweeps only the lines centred
+    // near its tile
+    int far_ends;
 };
 
 // Sorted line index of the launch's line g (through the threshold map when there is one).

@@ -584,9 +584,13 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
     const int t0 = wi.tile * W, t1 = t0 + W - 1;
     const int w0 = t0 + wave * WW, w1 = w0 + WW - 1;
 
-    // lines overlapping the tile; this workgroup takes every n_split-th batch of them
-    const int b0 = off_at(off, (int64_t)t0 - G.hmax, G);
-    const int b5 = off_at(off, (int64_t)t1 + G.hmax + 1, G);
+    // lines overlapping the tile; this workgroup takes every n_split-th batch of them.  With
+    // the window ends node-sampled too (far_ends), only lines centred within the far reach
+    // (or the centre-near radius) of the tile remain here.
+    const bool ends_far = SEG && PROF == kVoigt && A.far && A.far_ends;
+    const int64_t rnear = far_reach(WW) > tp.rm ? far_reach(WW) : tp.rm;
+    const int b0 = off_at(off, (int64_t)t0 - (ends_far ? rnear : G.hmax), G);
+    const int b5 = off_at(off, (int64_t)t1 + (ends_far ? rnear : G.hmax) + 1, G);
     const int bstride = NT * A.n_split;
     const int bfirst = b0 + NT * wi.part;
     const int rm_tile = tp.rm;
@@ -636,6 +640,10 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
             const FarRange fr = far_range(off, G, w0, w1, rm, far_reach(WW));
             hcl = fr.hcl;
             hcr = fr.hcr;
+        }
+        if (ends_far) {   // runs 1 and 5 belong to the far kernel
+            s0 = s1;
+            s5 = s4;
         }
     }
 
@@ -991,16 +999,68 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
 }
 
 // Node-sampled Voigt far wing: one wavefront per (wavefront tile wv, (T, P), share q).  The
-// lines [s1, hcl) and [hcr, s4), taken as one sequence, go in chunks q, q + far_share, ...
-// of 64, one line per lane (the next chunk's line data loaded while the current one is
-// summed), with FP64 sums per lane and node; then the wavefront's node totals, interpolated
-// to its points, go to far[tp][q][k] (every point of the wavefront, zeros included).
+// lines [s1, hcl) and [hcr, s4) (windows covering the wavefront, centres at least the far
+// reach away), taken as one sequence, go in chunks q, q + far_share, ... of 64, one line per
+// lane (the next chunk's line data loaded while the current one is summed), with FP64 sums
+// per lane and node.
+//
+// With A.far_ends the window-end lines come here too: [s0, s1) (windows ending inside the
+// wavefront) and [s4, s5) (windows starting inside it), all of them at least the far reach
+// from every point.  The wavefront is cut into NB blocks of BW points.  A left line whose
+// window ends in block b (its last point w0 + m, m clamped to the wavefront) covers blocks
+// 0..b-1 whole: its node values go to bucket b of the left side, and blocks c < b see the
+// sum of the left buckets above them (a suffix sum).  Its points in block b itself (up to
+// w0 + m) are evaluated one by one.  Right lines mirror this (prefix sums, points from the
+// window's first point).  Buckets b with b % far_share == q belong to share q.
+//
+// Each point o of the wavefront then takes the 8-point Lagrange interpolation of the node
+// values of its block, N_b = far + (left suffix) + (right prefix), plus its exact block sum,
+// into far[tp][q][k] (every point of the wavefront, zeros included).  Everything is summed
+// in a fixed order: the result does not depend on the run.
+template <int P>
+struct FarEnds {
+    static constexpr int WW = 64 * P;
+    static constexpr int BW = P == 1 ? 4 : 8;      // points per block
+    static constexpr int NB = WW / BW;             // blocks per wavefront
+    static constexpr int LPP = 64 / BW;            // lines per pass of the exact block sums
+};
+
+// wave-wide sum of v (every lane ends with the total)
+__device__ __forceinline__ double wave_total(double v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// the LDS words one lane wrote become visible to the other lanes of its wavefront
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// grid steps from w0 to node m of a wavefront of WW points: (WW - 1) m / (kFarN - 1)
+template <int WW>
+__device__ __forceinline__ float node_pos(int m) { return (float)(m * ((double)(WW - 1) / (kFarN - 1))); }
+
+// 2-node value of a line (hot record h4 = {H, C0, C1, AMP}, h2 = {B, XC}) at x, amplitudes scaled by up
+__device__ __forceinline__ float far_value(const float4& h4, const float2& h2, float x, float up) {
+    const float pp = __builtin_fmaf(x, x, h4.y);
+    const float den = __builtin_fmaf(pp, pp, h4.z);
+    const float num = __builtin_fmaf(pp, h4.w * up, h2.x * up);
+    return num * __builtin_amdgcn_rcpf(den);
+}
+
 template <int P>
 __global__ __launch_bounds__(256) void far_kernel(const FwdArgs A, int n_waves) {
     constexpr int WW = 64 * P;
+    using FE = FarEnds<P>;
+    constexpr int BW = FE::BW, NB = FE::NB, LPP = FE::LPP;
     using L = HotOf<kVoigt>;
     static_assert(L::H == 0 && L::C0 == 1 && L::C1 == 2 && L::AMP == 3 && L::XC == L::B + 1, "layout");
-    __shared__ double tl[4][kFarN];
+    __shared__ double tl[4][kFarN];           // node totals of the far lines
+    __shared__ float eb[4][2][NB][kFarN];     // window-end node sums per side and bucket (scaled by 2^32)
+    __shared__ double ex[4][WW];              // window-end block sums, point by point
     const int lane = threadIdx.x & 63, wl = threadIdx.x >> 6;
     const int64_t total = (int64_t)n_waves * A.n_tp * A.far_share;
     const int64_t gw = (int64_t)blockIdx.x * 4 + wl;
@@ -1015,12 +1075,14 @@ __global__ __launch_bounds__(256) void far_kernel(const FwdArgs A, int n_waves) 
     const int* map = A.map ? A.map + (int64_t)it * A.map_stride : nullptr;
     const int* off = A.offs ? A.offs + (int64_t)it * A.offs_stride : A.off;
     const float* hot = A.hot + (int64_t)it * A.rec_stride * kHot;
-    const FarRange fr = far_range(off, G, w0, w1, wave_rm(tp, G, w0, w1), far_reach(WW));
+    const int rm = wave_rm(tp, G, w0, w1);
+    const FarRange fr = far_range(off, G, w0, w1, rm, far_reach(WW));
     const int nl = fr.hcl - fr.s1, nv = nl + (fr.s4 - fr.hcr);
     const int step = 64 * A.far_share;
     // per lane and node: FP32 sums of up to four lines, added to FP64 sums; amplitudes
     // scaled by 2^32 (exact) keep tiny values out of the single-precision subnormal range
     constexpr float kUp = 4294967296.0f;
+    constexpr double kDown = 1.0 / 4294967296.0;
     double acc[kFarN];
     float a32[kFarN];
 #pragma unroll
@@ -1050,15 +1112,9 @@ __global__ __launch_bounds__(256) void far_kernel(const FwdArgs A, int n_waves) 
         fetch(c + step + lane);
         if (in) {
             const float x0 = __builtin_fmaf((float)(w0 - akc), a4.x, a2.y);   // x at w0
-            const float amp = a4.w * kUp, bb = a2.x * kUp;
 #pragma unroll
-            for (int m = 0; m < kFarN; ++m) {
-                const float x = __builtin_fmaf((float)(m * ((double)(WW - 1) / (kFarN - 1))), a4.x, x0);
-                const float pp = __builtin_fmaf(x, x, a4.y);
-                const float den = __builtin_fmaf(pp, pp, a4.z);
-                const float num = __builtin_fmaf(pp, amp, bb);
-                a32[m] = __builtin_fmaf(num, __builtin_amdgcn_rcpf(den), a32[m]);
-            }
+            for (int m = 0; m < kFarN; ++m)
+                a32[m] += far_value(a4, a2, __builtin_fmaf(node_pos<WW>(m), a4.x, x0), kUp);
         }
         if (++nacc == 4) {
             nacc = 0;
@@ -1070,19 +1126,137 @@ __global__ __launch_bounds__(256) void far_kernel(const FwdArgs A, int n_waves) 
         }
     }
 #pragma unroll
-    for (int m = 0; m < kFarN; ++m) acc[m] = (acc[m] + (double)a32[m]) * (1.0 / 4294967296.0);
-    // node totals over the wavefront (every lane ends with all of them), through LDS to
-    // index them by point
-#pragma unroll
-    for (int m = 0; m < kFarN; ++m) {
-#pragma unroll
-        for (int o = 32; o >= 1; o >>= 1) acc[m] += __shfl_xor(acc[m], o, 64);
-    }
+    for (int m = 0; m < kFarN; ++m) acc[m] = wave_total((acc[m] + (double)a32[m]) * kDown);
     if (lane == 0) {
 #pragma unroll
         for (int m = 0; m < kFarN; ++m) tl[wl][m] = acc[m];
     }
-    __builtin_amdgcn_wave_barrier();
+
+    const bool ends = A.far_ends != 0;
+    if (ends) {
+        for (int o = lane; o < WW; o += 64) ex[wl][o] = 0.0;
+        wave_lds_sync();
+        // left side: windows ending inside the wavefront; right side: windows starting inside
+        const int s0 = off_at(off, (int64_t)w0 - G.hmax, G), s1 = fr.s1;
+        const int s4 = fr.s4, s5 = off_at(off, (int64_t)w1 + G.hmax + 1, G);
+        for (int side = 0; side < 2; ++side) {
+            for (int b = 0; b < NB; ++b) {
+                float* bucket = eb[wl][side][b];
+                // candidate lines of bucket b (a window end can be hmin..hmax steps from kc)
+                const int64_t e0 = (int64_t)w0 + b * BW, e1 = e0 + BW - 1;
+                int r0, r1;
+                if (side == 0) {
+                    r0 = off_at(off, e0 - G.hmax, G);
+                    r1 = off_at(off, e1 - G.hmin + 1, G);
+                    r0 = r0 > s0 ? r0 : s0;
+                    r1 = r1 < s1 ? r1 : s1;
+                } else {
+                    r0 = off_at(off, e0 + G.hmin, G);
+                    r1 = off_at(off, e1 + G.hmax + 1, G);
+                    r0 = r0 > s4 ? r0 : s4;
+                    r1 = r1 < s5 ? r1 : s5;
+                }
+                if (b % A.far_share != q || r1 <= r0) {
+                    if (lane < kFarN) bucket[lane] = 0.0f;
+                    continue;
+                }
+                // block offset of a line's window end, clamped to the wavefront: left lines
+                // count up to w0 + m, right lines from w0 + m; -1 / WW: no point of the wavefront
+                auto end_of = [&](int g) {
+                    if (side == 0) {
+                        const int m = A.L.khi[g] - w0;
+                        return m < 0 ? -1 : (m > WW - 1 ? WW - 1 : m);
+                    }
+                    const int m = A.L.klo[g] - w0;
+                    return m > WW - 1 ? WW : (m < 0 ? 0 : m);
+                };
+                // node sums of the bucket's lines, one line per lane
+#pragma unroll
+                for (int m = 0; m < kFarN; ++m) {
+                    acc[m] = 0.0;
+                    a32[m] = 0.0f;
+                }
+                nacc = 0;
+                for (int c = r0; c < r1; c += 64) {
+                    const int l = c + lane;
+                    if (l < r1) {
+                        const int g = line_of(map, l);
+                        const int m = end_of(g);
+                        if (m >= 0 && m < WW && m / BW == b) {
+                            const float4 a4 = *reinterpret_cast<const float4*>(hot + (int64_t)l * kHot);
+                            const float2 a2 = *reinterpret_cast<const float2*>(hot + (int64_t)l * kHot + L::B);
+                            const float x0 = __builtin_fmaf((float)(w0 - A.L.kc[g]), a4.x, a2.y);
+#pragma unroll
+                            for (int mm = 0; mm < kFarN; ++mm)
+                                a32[mm] += far_value(a4, a2, __builtin_fmaf(node_pos<WW>(mm), a4.x, x0), kUp);
+                        }
+                    }
+                    if (++nacc == 4) {
+                        nacc = 0;
+#pragma unroll
+                        for (int mm = 0; mm < kFarN; ++mm) {
+                            acc[mm] += (double)a32[mm];
+                            a32[mm] = 0.0f;
+                        }
+                    }
+                }
+#pragma unroll
+                for (int mm = 0; mm < kFarN; ++mm) acc[mm] = wave_total(acc[mm] + (double)a32[mm]);
+                if (lane == 0) {
+#pragma unroll
+                    for (int mm = 0; mm < kFarN; ++mm) bucket[mm] = (float)acc[mm];
+                }
+                // the bucket's lines point by point within block b: lane = slot * BW + o,
+                // LPP lines per pass
+                const int slot = lane / BW, o = lane % BW;
+                const int k = w0 + b * BW + o;
+                float e32 = 0.0f;
+                double e64 = 0.0;
+                int ne = 0;
+                for (int c = r0; c < r1; c += LPP) {
+                    const int l = c + slot;
+                    if (l < r1) {
+                        const int g = line_of(map, l);
+                        const int m = end_of(g);
+                        const bool mine = m >= 0 && m < WW && m / BW == b;
+                        const bool cover = side == 0 ? (b * BW + o <= m) : (b * BW + o >= m);
+                        if (mine && cover) {
+                            const float4 a4 = *reinterpret_cast<const float4*>(hot + (int64_t)l * kHot);
+                            const float2 a2 = *reinterpret_cast<const float2*>(hot + (int64_t)l * kHot + L::B);
+                            e32 += far_value(a4, a2, __builtin_fmaf((float)(k - A.L.kc[g]), a4.x, a2.y), kUp);
+                        }
+                    }
+                    if (++ne == 4) {
+                        ne = 0;
+                        e64 += (double)e32;
+                        e32 = 0.0f;
+                    }
+                }
+                e64 += (double)e32;
+#pragma unroll
+                for (int x = BW; x < 64; x <<= 1) e64 += __shfl_xor(e64, x, 64);
+                if (slot == 0) ex[wl][b * BW + o] += e64 * kDown;
+            }
+        }
+        wave_lds_sync();
+        // left buckets become suffix sums (the lines covering blocks below them), right
+        // buckets prefix sums; one node per lane
+        if (lane < kFarN) {
+            double run = 0.0;
+            for (int b = NB - 1; b >= 0; --b) {
+                const double v = (double)eb[wl][0][b][lane];
+                eb[wl][0][b][lane] = (float)run;
+                run += v;
+            }
+            run = 0.0;
+            for (int b = 0; b < NB; ++b) {
+                const double v = (double)eb[wl][1][b][lane];
+                eb[wl][1][b][lane] = (float)run;
+                run += v;
+            }
+        }
+    }
+    wave_lds_sync();
     // 8-point Lagrange weights 1 / prod_{b != a} (a - b)
     constexpr double den8[8] = {-1.0 / 5040, 1.0 / 720, -1.0 / 240, 1.0 / 144,
                                 -1.0 / 144, 1.0 / 240, -1.0 / 720, 1.0 / 5040};
@@ -1094,15 +1268,19 @@ __global__ __launch_bounds__(256) void far_kernel(const FwdArgs A, int n_waves) 
         int i0 = (int)floor(u) - 3;
         i0 = i0 < 0 ? 0 : (i0 > kFarN - 8 ? kFarN - 8 : i0);
         const double t = u - (double)i0;
+        const int blk = o / BW;
         double v = 0.0;
 #pragma unroll
         for (int a = 0; a < 8; ++a) {
             double w = den8[a];
 #pragma unroll
-            for (int b = 0; b < 8; ++b)
-                if (b != a) w *= t - (double)b;
-            v = __builtin_fma(w, tl[wl][i0 + a], v);
+            for (int bb = 0; bb < 8; ++bb)
+                if (bb != a) w *= t - (double)bb;
+            double nodev = tl[wl][i0 + a];
+            if (ends) nodev += ((double)eb[wl][0][blk][i0 + a] + (double)eb[wl][1][blk][i0 + a]) * kDown;
+            v = __builtin_fma(w, nodev, v);
         }
+        if (ends) v += ex[wl][o];
         const int k = w0 + o;
         if (k < G.n_points) out[k] = v;
     }

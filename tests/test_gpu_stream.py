@@ -191,3 +191,20 @@ def test_stream_resume_refuses_another_geometry(case, tmp_path):
     with pytest.raises(Exception) as e:
         Stream.resume(plan, path, n_tp=len(TS))
     assert "grid range" in str(e.value)
+
+
+def test_stream_device_chunks_equal_host_chunks(case):
+    # chunks already in device memory (no copy) give the host-chunk stream's sums bit for
+    # bit, also when the two kinds alternate
+    cfg, states, table, chunks, allv = case
+    ref = _stream(_plan(cfg, states, table, "fp32"), chunks).end()
+    st = _plan(cfg, states, table, "fp32").stream(TS, PS)
+    for i, c in enumerate(chunks):
+        if i % 2 == 0:
+            st.chunk_device(c["upper"].cuda(), c["lower"].cuda(), c["A"].cuda())
+        else:
+            st.chunk(c["upper"], c["lower"], c["A"])
+    assert st.stats()["chunks"] == len(CHUNKS)
+    got = st.end()
+    assert got[1] == ref[1]
+    assert torch.equal(got[0], ref[0])
