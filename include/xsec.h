@@ -241,6 +241,20 @@ xs_status xs_set_intensity_kind(xs_plan* plan, int32_t kind);
 xs_status xs_partition_function(xs_plan* plan, int32_t n_T, const double* T, double* Q,
                                 double* dQdT, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): xs_partition_function without any
+ * allocation.  The temperatures travel to the device as a kernel argument and the partial
+ * sums live in a fixed scratch array of the library (XS_NOALLOC_MAX_T temperatures plus
+ * 2 x 256 partial sums per temperature, ~1 MiB of doubles per GPU, held until the process
+ * ends).  Results are bitwise those of xs_partition_function.  T: host double[n_T] (> 0),
+ * 1 <= n_T <= XS_NOALLOC_MAX_T (XS_ERR_ARG otherwise, before any device work); Q, dQdT:
+ * device double[n_T] or NULL.  The plan's states must be on the current device.  Every
+ * call on one GPU uses that GPU's one scratch array: calls that overlap in time on one
+ * GPU (other streams, other host threads) race and must be ordered by the caller. */
+#define XS_NOALLOC_MAX_T 256
+xs_status xs_partition_function_noalloc(xs_plan* plan, int32_t n_T, const double* T, double* Q,
+                                        double* dQdT, void* stream);
+
 /* Non-LTE populations (Sec. "Treating non-local thermodynamic equilibrium"): each state's
  * energy splits as E = E_vib + E_rot, with E_vib the energy of the lowest state of its
  * vibrational (vibronic) manifold (the lowest-J state, which on a rotational ladder is the

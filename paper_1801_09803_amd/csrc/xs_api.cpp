@@ -843,6 +843,20 @@ xs_status validate_tp(int n_tp, const double* T, const double* P) {
 
 }  // namespace
 
+namespace xs {
+
+xs_status set_error(xs_status s, const std::string& msg) { return fail(s, msg); }
+
+bool plan_states(const xs_plan* p, const double** E, const int** g, int64_t* n_states) {
+    if (!p) return false;
+    *E = static_cast<const double*>(p->E.p);
+    *g = static_cast<const int*>(p->g.p);
+    *n_states = p->n_states;
+    return true;
+}
+
+}  // namespace xs
+
 extern "C" {
 
 xs_status xs_opts_default(xs_opts* o) {

@@ -4,6 +4,9 @@
 #include <hip/hip_runtime.h>
 #include <cstdint>
 #include <cstddef>
+#include <string>
+
+#include "../../include/xsec.h"
 
 namespace xs {
 
@@ -112,5 +115,10 @@ struct Tables {
 void gauss_hermite_rule(int n, double* nodes, double* weights);
 void weideman_coefficients(int n, WeidemanCoef* out);
 void make_gh_pairs(int n, GHPairs* out);
+
+// Plan internals for entry points outside the plan's source file (xs_api.cpp):
+// the thread-local error text of xs_last_error, and the plan's states on the device.
+xs_status set_error(xs_status s, const std::string& msg);
+bool plan_states(const xs_plan* p, const double** E, const int** g, int64_t* n_states);
 
 }  // namespace xs
