@@ -1,18 +1,23 @@
 """Benchmark: Voigt line-profiles/s at a 25 cm^-1 cut-off on one MI355X.
 
-Workload (default): 1e8 synthetic transitions among 1e6 states (34 Da), T = 296 K and
-2000 K at P = 1 bar, Voigt profile sampled on 0-10000 cm^-1 at 0.01 cm^-1
-(1,000,001 points), FP32 profile arithmetic with FP64 line setup.
+Headline (default): the hot-polyatomic workload.  4e9 synthetic transitions (int32 upper,
+int32 lower, float A) among 5e7 states (16 Da) are generated on the device and kept in
+HBM (48 GB); cross sections at 9 temperatures (300-3000 K) x 4 pressures (1e-5-100 bar)
+with a0 broadening by lower-state J, Voigt profile sampled on 0-12000 cm^-1 at
+0.01 cm^-1 (1,200,001 points), FP32 profile arithmetic with FP64 line setup.  One step =
+one chunk of 2^28 transitions (15 chunks hold the list) through the whole path for all
+36 (T, P), accumulated on the device (xs_stream_chunk_device); step i takes chunk
+i mod 15, so 15 steps cover the list once.  The CPU oracle is timed on a bounded sample
+of the same list before the GPU is touched.
 
-One step = the whole hot path on device-resident inputs: line preparation and sort
-(xs_set_lines), Q(T) on the device, and both cross sections from one batched call
-(tile shape chosen by the library's autotuner before the timed steps).  The plain
-FP64 path is timed on the same workload for comparison, a captured graph of the
-batched call is replayed, the retrieval workload (1e7 lines, 1000-6000 cm^-1,
-1500 K, 0.1 bar) is timed as batched FP32 forward + adjoint against the plain FP64
-forward + adjoint, the first chunks of the 4e9-line hot-polyatomic list are streamed
-from pinned host memory through 36 (T, P), and the CPU oracle is timed on a bounded
-sample of the same list (before the GPU is touched).
+Sub-entries: the single-cross-section workload (1e8 transitions, 296 K and 2000 K at
+1 bar: timed steps of line preparation + batched call, the plain FP64 path, a graph
+replay, and the 270-point (T, P) grid on the same list); the retrieval workload (1e7
+transitions, forward + adjoint, FP32 against FP64, one shared dL/dsigma); the first
+chunks of the 4e9-transition list streamed from pinned host memory (host-to-device copies
+included); the paper's single-core timings as context.  --workload C2 makes the
+single-cross-section workload the headline; --all-legs adds the Vectorized Voigt, binned,
+threshold and emission legs.
 
 Prints one JSON line (rank 0, N = 1 only).
 """
@@ -44,8 +49,14 @@ def far_reach(ww):
 
 
 def zone_counts(cfg, d, T, P, waves=None, slices=None, chunk=1 << 24):
-    """Window points of every line per zone at (T, P) (x = sqrt(ln2)(nu_k - nu)/alpha_D,
-    |z|^2 = x^2 + y^2, y = sqrt(ln2) gamma/alpha_D), counted from index ranges.
+    """zone_counts_multi for one (T, P)."""
+    return zone_counts_multi(cfg, d, [(T, P)], waves, slices, chunk)[0]
+
+
+def zone_counts_multi(cfg, d, tps, waves=None, slices=None, chunk=1 << 24):
+    """Window points of every line per zone at each (T, P) of tps (x = sqrt(ln2)(nu_k - nu)/alpha_D,
+    |z|^2 = x^2 + y^2, y = sqrt(ln2) gamma/alpha_D), counted from index ranges.  d holds E,
+    upper, lower and the per-line gamma_ref, n_exp.
 
     With the tile shape (waves, slices) of the FP32 Voigt sweep, the tile kernel evaluates
     only the (line, wavefront) pairs whose centre lies within far_reach grid steps of the
@@ -55,10 +66,9 @@ def zone_counts(cfg, d, T, P, waves=None, slices=None, chunk=1 << 24):
     that end's block evaluated one by one (far_exact)."""
     import torch
     kB, amu, c_si, ln2 = 1.380649e-23, 1.66053906660e-27, 299792458.0, math.log(2.0)
-    beta = math.sqrt(2.0 * kB * T * ln2 / (cfg.mass_amu * amu)) / c_si
+    betas = {T: math.sqrt(2.0 * kB * T * ln2 / (cfg.mass_amu * amu)) / c_si for T, _ in tps}
     E = d["E"]
-    tot = {k: 0 for k in ZONE_FLOPS}
-    tot["far_exact"] = 0
+    tots = [dict({k: 0 for k in ZONE_FLOPS}, far_exact=0) for _ in tps]
     n = d["upper"].numel()
     far = waves is not None
     if far:
@@ -69,18 +79,17 @@ def zone_counts(cfg, d, T, P, waves=None, slices=None, chunk=1 << 24):
         hmin = math.floor(cfg.cutoff / dnu) - 2
         # the sampled lines must lie beyond the |z| < 40 radius of every wavefront, and the
         # window ends beyond the far reach (the library's condition for sampling them)
-        rm_max = 40.0 * beta * (cfg.nu_b + cfg.cutoff) / (math.sqrt(ln2) * dnu) + 3.0
+        rm_max = 40.0 * max(betas.values()) * (cfg.nu_b + cfg.cutoff) / (math.sqrt(ln2) * dnu) + 3.0
         assert reach >= rm_max, "far-wing reach inside the |z| < 40 radius: counts would not match"
         assert hmin - ww + 2 >= reach, "window ends not node-sampled at this geometry: counts would not match"
     for a in range(0, n, chunk):
         b = min(n, a + chunk)
         nu = E[d["upper"][a:b].long()] - E[d["lower"][a:b].long()]
-        gam = d["gamma_ref"][a:b].double() * torch.pow(296.0 / T, d["n_exp"][a:b].double()) * P
-        s = math.sqrt(ln2) / (beta * nu)
-        y2 = (gam * s) ** 2
+        gref, nexp = d["gamma_ref"][a:b].double(), d["n_exp"][a:b].double()
         klo = torch.clamp(torch.ceil(((nu - cfg.cutoff) - cfg.nu_a) / cfg.dnu), min=0)
         khi = torch.clamp(torch.floor(((nu + cfg.cutoff) - cfg.nu_a) / cfg.dnu), max=cfg.n_points - 1)
         live = khi >= klo
+        far_pairs, far_ex = 0, 0
         if far:
             # the tile kernel's part of the window: wavefronts within reach of the centre
             kc = torch.floor((nu - cfg.nu_a) / cfg.dnu + 0.5)
@@ -92,31 +101,41 @@ def zone_counts(cfg, d, T, P, waves=None, slices=None, chunk=1 << 24):
             hi_k = torch.minimum(khi, nb * ww + ww - 1)
             lo_k = torch.where(near_w > 0, lo_k, khi + 1)   # no near wavefront: nothing here
             far_w = torch.where(live, (wr - wl + 1) - near_w, torch.zeros_like(wl))
-            tot["far_node"] += FAR_NODES * int(far_w.sum().item())
+            far_pairs = FAR_NODES * int(far_w.sum().item())
             # window ends inside a far wavefront: their block's points one by one
             left_far = live & ((wl < na) | (near_w == 0))
             right_far = live & ((wr > nb) | (near_w == 0))
             ex_l = torch.where(left_far, bw - torch.remainder(klo - wl * ww, bw), torch.zeros_like(klo))
             ex_r = torch.where(right_far, torch.remainder(khi - wr * ww, bw) + 1, torch.zeros_like(khi))
-            tot["far_exact"] += int((ex_l + ex_r).sum().item())
+            far_ex = int((ex_l + ex_r).sum().item())
+            del kc, wl, wr, na, nb, near_w, far_w, left_far, right_far, ex_l, ex_r
         else:
             lo_k, hi_k = klo, khi
-        n_all = torch.clamp(hi_k - lo_k + 1, min=0)
+        n_all = int(torch.clamp(hi_k - lo_k + 1, min=0).sum().item())
+        cache = {}
+        for i, (T, P) in enumerate(tps):
+            s = math.sqrt(ln2) / (betas[T] * nu)
 
-        def inside(X):   # points of [lo_k, hi_k] with |x| < X
-            R = X / s
-            lo = torch.maximum(torch.floor((nu - R - cfg.nu_a) / cfg.dnu) + 1, lo_k)
-            hi = torch.minimum(torch.ceil((nu + R - cfg.nu_a) / cfg.dnu) - 1, hi_k)
-            return torch.where(X > 0, torch.clamp(hi - lo + 1, min=0), torch.zeros_like(X))
+            def inside(X):   # points of [lo_k, hi_k] with |x| < X
+                R = X / s
+                lo = torch.maximum(torch.floor((nu - R - cfg.nu_a) / cfg.dnu) + 1, lo_k)
+                hi = torch.minimum(torch.ceil((nu + R - cfg.nu_a) / cfg.dnu) - 1, hi_k)
+                return int(torch.where(X > 0, torch.clamp(hi - lo + 1, min=0), torch.zeros_like(X)).sum().item())
 
-        n_x = inside(torch.full_like(nu, 1000.0))
-        n_40 = inside(torch.sqrt(torch.clamp(1600.0 - y2, min=0.0)))
-        n_8 = inside(torch.sqrt(torch.clamp(64.0 - y2, min=0.0)))
-        tot["one_pole"] += int((n_all - n_x).sum().item())
-        tot["two_node"] += int((n_x - n_40).sum().item())
-        tot["four_node"] += int((n_40 - n_8).sum().item())
-        tot["core"] += int(n_8.sum().item())
-    return tot
+            if T not in cache:
+                cache[T] = inside(torch.full_like(nu, 1000.0))
+            n_x = cache[T]
+            y2 = (gref * torch.pow(296.0 / T, nexp) * P * s) ** 2
+            n_40 = inside(torch.sqrt(torch.clamp(1600.0 - y2, min=0.0)))
+            n_8 = inside(torch.sqrt(torch.clamp(64.0 - y2, min=0.0)))
+            t = tots[i]
+            t["one_pole"] += n_all - n_x
+            t["two_node"] += n_x - n_40
+            t["four_node"] += n_40 - n_8
+            t["core"] += n_8
+            t["far_node"] += far_pairs
+            t["far_exact"] += far_ex
+    return tots
 
 # HBM traffic of the dominant kernel from two rocprofv3 --pmc runs of this script with
 # the tile configuration fixed (1 wave, 4 slices, 64 shares, one (T, P) per dispatch):
@@ -187,59 +206,276 @@ def cpu_baseline(cfg, n_sample_lines, temps, pressures):
                        f"{dt:.1f} s wall on {cores} processes ({cpu})")
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="C2")
-    ap.add_argument("--lines", type=int, default=0, help="truncate the line list (profiling runs)")
-    ap.add_argument("--slices-per-wave", type=int, default=0)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-fp64", action="store_true")
-    ap.add_argument("--no-adjoint", action="store_true")
-    ap.add_argument("--no-graph", action="store_true")
-    ap.add_argument("--no-stream", action="store_true")
-    ap.add_argument("--no-vv", action="store_true", help="skip the Vectorized Voigt leg")
-    ap.add_argument("--no-binned", action="store_true", help="skip the binned-profile / super-line leg")
-    ap.add_argument("--no-threshold", action="store_true", help="skip the intensity-threshold leg")
-    ap.add_argument("--no-c3", action="store_true", help="skip the 270-point (T, P) grid leg")
-    ap.add_argument("--no-emission", action="store_true",
-                    help="skip the emission cross-section and state-reduction leg")
-    ap.add_argument("--stream-chunks", type=int, default=4)
-    ap.add_argument("--stream-chunk-lines", type=int, default=1 << 24)
-    ap.add_argument("--autotune-ms", type=float, default=20000.0,
-                    help="autotuner budget (0: keep the library's default tile shape)")
-    ap.add_argument("--tile", default="", help="fixed tile config waves,slices,n_split,tp_block")
-    ap.add_argument("--cpu-lines-per-core", type=int, default=40000)
-    ap.add_argument("--copy-probe", type=int, default=0,
-                    help="only run a device copy of this many MiB (HBM counter calibration)")
-    args = ap.parse_args()
+# The paper's own single-core timings of its cross-section hot path (its Table of total
+# times: BT2 water, 5e8 transitions, 0-30000 cm^-1 at 0.1 cm^-1, I/O excluded, one core of
+# an Intel Core i5-2500 at 3.30 GHz): context only, another machine, list and grid.
+PAPER_CONTEXT = {
+    "hardware": "1 core, Intel Core i5-2500 @ 3.30 GHz",
+    "workload": "BT2 H2O, 5e8 transitions, 0-30000 cm^-1 at 0.1 cm^-1, I/O excluded",
+    "humlicek_voigt_s": 2775.6,
+    "vectorized_voigt_s": 251.2,
+    "humlicek_threshold_1e-30_s": 832.6,
+    "vectorized_voigt_threshold_1e-30_s": 70.0,
+    "humlicek_line_profiles_per_s": 5e8 / 2775.6,
+    "vectorized_voigt_line_profiles_per_s": 5e8 / 251.2,
+    "note": "context, not the target: the paper prints no GPU figure",
+}
 
-    if args.copy_probe:
-        import torch
-        x = torch.ones(args.copy_probe * 2**18, dtype=torch.float32, device="cuda")
-        y = torch.empty_like(x)
-        torch.cuda.synchronize()
-        y.copy_(x)
-        torch.cuda.synchronize()
-        print(json.dumps({"copy_probe_bytes_each_way": x.numel() * 4}), flush=True)
-        return
 
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: the library has no multi-GPU path "
-              "(run with --gpus 1)", file=sys.stderr)
-        sys.exit(2)
-
+def cpu_baseline_c5(cfg, n_lines, tps):
+    """The FP64 oracle (as it stands) on the first n_lines transitions of the hot-polyatomic
+    list at the given (T, P) points (a0 broadening), full grid."""
+    import numpy as np
+    import oracle as O
     import synth
-    cfg = synth.CONFIGS[args.workload]
+    E, g, J = synth.linelist.make_states(cfg.n_states, cfg.seed, device="cpu")
+    up, lo = synth.linelist.make_transitions(E, n_lines, cfg.nu_max, cfg.seed)
+    A = synth.linelist.make_line_params(n_lines, cfg.seed)[0]
+    gt, nt = synth.make_broadening_table(cfg.seed)
+    Eh, gh, Jh = E.numpy(), g.numpy(), J.numpy()
+    cores = len(os.sched_getaffinity(0))
+    t0 = time.perf_counter()
+    profiles = 0
+    Qs = {}
+    for T, P in tps:
+        if T not in Qs:
+            Qs[T] = O.partition_function(Eh, gh, T)
+        ls = O.make_lineset(Eh, gh, up.numpy(), lo.numpy(), A.numpy(), T, P, cfg.mass_amu, J=Jh,
+                            broad_table=(gt.numpy(), nt.numpy()), Q=Qs[T])
+        O.cross_section(ls, cfg.nu_a, cfg.nu_b, cfg.n_points, cfg.cutoff, workers=cores)
+        klo, khi = O.window(ls.nu, cfg.nu_a, cfg.dnu, cfg.n_points, cfg.cutoff)
+        profiles += int(np.count_nonzero(khi >= klo))
+    dt = time.perf_counter() - t0
+    cpu = "unknown"
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                cpu = ln.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return dict(value=profiles / dt, unit="line-profiles/s", cores=cores, kind="oracle",
+                sample=f"first {n_lines} transitions of the 4e9-transition list x {len(tps)} (T,P) "
+                       f"{[(round(T, 1), P) for T, P in tps]}, full 1,200,001-point grid, Q(T) over the 5e7 "
+                       f"states included; {dt:.1f} s wall on {cores} processes ({cpu})")
+
+
+def c5_run(args):
+    """Headline: the hot-polyatomic workload.  4e9 transitions (int32 upper, int32 lower,
+    float A: 48 GB) among 5e7 states (16 Da), generated on the device and kept in HBM; 9 T
+    (300-3000 K) x 4 P (1e-5-100 bar); a0 broadening by lower-state J; FP32 Voigt on
+    0-12000 cm^-1 at 0.01 cm^-1 (1,200,001 points), cut-off 25 cm^-1.
+
+    One step = one chunk of chunk_lines transitions (2^28: 15 chunks hold the list) through
+    the whole path for all 36 (T, P): xs_stream_chunk_device (line preparation and sort,
+    Q(T), core pre-passes, tile and far-wing kernels, share combine) and the compensated
+    accumulation into the stream's sums.  Step i takes chunk i mod 15, so 15 steps cover
+    the list once.  Warm-up steps run on a stream that is discarded."""
+    import torch
+    import synth
+    from paper_1801_09803_amd import Plan
+    cfg = synth.CONFIGS["C5"]
+    dev = torch.device("cuda:0")
+    temps = [t for t in cfg.temperatures for _ in cfg.pressures]
+    press = [p for _ in cfg.temperatures for p in cfg.pressures]
+    n_tp = len(temps)
+    n_total = args.lines or cfg.n_lines
+    chunk = min(args.chunk_lines, n_total)
+    n_chunks = -(-n_total // chunk)
+
+    base = None
+    if not args.no_cpu_baseline:
+        cores = len(os.sched_getaffinity(0))
+        n_s = args.cpu_lines_per_core // 2 * cores
+        tps_s = [(temps[i], press[i]) for i in range(16, 20)]   # 1000 K at the four pressures
+        log(f"cpu baseline: oracle on {n_s} C5 lines x {len(tps_s)} (T,P), {cores} processes")
+        base = cpu_baseline_c5(cfg, n_s, tps_s)
+        log(f"cpu baseline: {base['value']:.3e} line-profiles/s")
+
+    log(f"C5: generating {cfg.n_states} states and {n_total} transitions on {torch.cuda.get_device_name(0)}")
+    t_gen = time.perf_counter()
+    E, g, J = synth.linelist.make_states(cfg.n_states, cfg.seed, device=dev)
+    gt, nt = synth.make_broadening_table(cfg.seed)
+    upper = torch.empty(n_total, dtype=torch.int32, device=dev)
+    lower = torch.empty(n_total, dtype=torch.int32, device=dev)
+    A = torch.empty(n_total, dtype=torch.float32, device=dev)
+    gen = 1 << 27
+    for a in range(0, n_total, gen):
+        b = min(n_total, a + gen)
+        up, lo = synth.linelist.make_transitions(E, b - a, cfg.nu_max, cfg.seed, first_line=a)
+        upper[a:b], lower[a:b] = up, lo
+        A[a:b] = synth.linelist.make_line_params(b - a, cfg.seed, first_line=a, device=dev)[0]
+        del up, lo
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t_gen
+    log(f"C5: list generated in {t_gen:.1f} s ({n_total * 12 / 1e9:.1f} GB resident)")
+
+    def part(i):
+        a = i * chunk
+        b = min(n_total, a + chunk)
+        return upper[a:b], lower[a:b], A[a:b]
+
+    plan = Plan(cfg.nu_a, cfg.nu_b, cfg.n_points, cfg.mass_amu, cutoff=cfg.cutoff, profile="voigt",
+                precision="fp32", broadening="a0_jlower")
+    plan.set_broadening_table(gt.numpy(), nt.numpy())
+    plan.set_states(E, g, J)
+    tune = None
+    if args.tile:
+        w, sl, sp, tb = (int(v) for v in args.tile.split(","))
+        plan.set_tile_config(w, sl, sp, tb)
+    elif args.autotune_ms > 0:
+        # tuned on the first chunk at the four pressures of 1000 K
+        plan.set_lines(*part(0))
+        t_tune = time.perf_counter()
+        chosen = plan.autotune(temps[16:20], press[16:20], budget_ms=args.autotune_ms)
+        tune = dict(chosen=chosen, wall_s=time.perf_counter() - t_tune, budget_ms=args.autotune_ms,
+                    tuned_on="chunk 0 at 1000 K and the four pressures")
+        log(f"C5 autotune: {chosen} in {tune['wall_s']:.1f} s")
+    stream = torch.cuda.current_stream()
+    if args.warmup > 0:
+        st = plan.stream(temps, press)
+        for i in range(args.warmup):
+            log(f"C5 warm-up step {i}")
+            st.chunk_device(*part(i % n_chunks))
+        st.end()
+        del st
+    out = torch.empty((n_tp, cfg.n_points), dtype=torch.float32, device=dev)
+    torch.cuda.synchronize()
+    plan.set_timing(True)
+    log(f"C5: timing {args.steps} steps of {chunk} transitions x {n_tp} (T,P)")
+    t0 = time.perf_counter()
+    st = plan.stream(temps, press, out=out)
+    for i in range(args.steps):
+        st.chunk_device(*part(i % n_chunks))
+        log(f"C5 step {i} (chunk {i % n_chunks}) handed over at {time.perf_counter() - t0:.1f} s")
+    _, kept = st.end()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    kt = plan.kernel_times()
+    plan.set_timing(False)
+    tile = plan.tile_config()
+    log(f"C5: {elapsed:.1f} s, {kept * n_tp / elapsed:.3e} line-profiles/s")
+    del st, plan
+    torch.cuda.empty_cache()
+
+    # algorithmic work of the timed steps: zone points of the tile kernel, node and
+    # window-end evaluations of the far kernel, window points (every chunk a step used,
+    # times the steps that used it)
+    log("C5: counting zone points of the timed chunks")
+    uses = [0] * n_chunks
+    for i in range(args.steps):
+        uses[i % n_chunks] += 1
+    zone_tot = {k: 0 for k in list(ZONE_FLOPS) + ["far_exact"]}
+    window_points = 0
+    jl_max = gt.numel() - 1
+    gt_d, nt_d = gt.to(dev), nt.to(dev)
+    for c in range(n_chunks):
+        if uses[c] == 0:
+            continue
+        up, lo, _ = part(c)
+        jl = torch.clamp(J[lo.long()].long(), max=jl_max)
+        dc = dict(E=E, upper=up, lower=lo, gamma_ref=gt_d[jl], n_exp=nt_d[jl])
+        zs = zone_counts_multi(cfg, dc, list(zip(temps, press)), tile["waves"], tile["slices"], chunk=1 << 27)
+        for z in zs:
+            for k, v in z.items():
+                zone_tot[k] += uses[c] * v
+        nu = E[up.long()] - E[lo.long()]
+        klo = torch.clamp(torch.ceil(((nu - cfg.cutoff) - cfg.nu_a) / cfg.dnu), min=0)
+        khi = torch.clamp(torch.floor(((nu + cfg.cutoff) - cfg.nu_a) / cfg.dnu), max=cfg.n_points - 1)
+        window_points += uses[c] * n_tp * int(torch.clamp(khi - klo + 1, min=0).sum().item())
+        del dc, jl, nu, klo, khi
+    del upper, lower, A
+    torch.cuda.empty_cache()
+
+    tile_zones = [k for k in ZONE_FLOPS if k not in ("far_node", "far_exact")]
+    flops = sum(ZONE_FLOPS[k] * zone_tot[k] for k in tile_zones)
+    tile_pts = sum(zone_tot[k] for k in tile_zones)
+    avg_launch_s = kt["forward_ms"] / kt["forward_launches"] / 1e3
+    achieved = flops / kt["forward_launches"] / avg_launch_s / 1e12
+    far_s = kt["far_ms"] / 1e3
+    value = kept * n_tp / elapsed
+    return {
+        "metric": "Voigt line-profiles/s at 25 cm^-1 cutoff",
+        "value": value,
+        "unit": "line-profiles/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"C5 hot polyatomic: {n_total} transitions (int32 upper, int32 lower, float A) resident "
+                        f"in HBM, {cfg.n_states} states, {cfg.mass_amu} Da, 9 T x 4 P = {n_tp} (T,P) "
+                        f"(T {cfg.temperatures[0]:.0f}-{cfg.temperatures[-1]:.0f} K log, P 1e-5-100 bar log), a0 "
+                        f"broadening, Voigt FP32, {cfg.nu_a}-{cfg.nu_b} cm^-1 ({cfg.n_points} points, dnu 0.01), "
+                        f"cutoff {cfg.cutoff}",
+            "step": f"one chunk of {chunk} transitions through all {n_tp} (T,P): line preparation and sort, Q(T), "
+                    f"pre-passes, tile and far-wing kernels, compensated accumulation; step i takes chunk "
+                    f"i mod {n_chunks}",
+            "chunks_in_list": n_chunks,
+            "full_list_passes_timed": args.steps / n_chunks,
+            "lines_kept_timed": kept,
+            "n_tp": n_tp,
+            "point_evaluations_timed": window_points,
+            "tile": {"waves": tile["waves"], "slices_per_wave": tile["slices"], "n_split": tile["last_split"],
+                     "tp_block": tile["last_block"]},
+            "autotune": tune,
+            "list_generation_s": t_gen,
+        },
+        "roofline": {
+            "bound": "alu",
+            "achieved": achieved,
+            "peak": PEAK_FP32_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP32_TFLOPS,
+            "traffic": traffic_bytes_per_launch(kt["forward_tp"] / kt["forward_launches"]),
+            "kernel": "fwd_f32_kernel<Voigt> (tile kernel, one launch per block of (T,P) per chunk)",
+            "avg_launch_ms": avg_launch_s * 1e3,
+            "launches": kt["forward_launches"],
+            "tp_per_launch": kt["forward_tp"] / kt["forward_launches"],
+            "algorithmic_flops_per_launch": flops / kt["forward_launches"],
+            "flops_per_eval": flops / max(tile_pts, 1),
+            "zone_flops": ZONE_FLOPS,
+            "zone_points_timed": zone_tot,
+            "frac_of_unpacked_fp32": achieved / PEAK_FP32_UNPACKED,
+        },
+        "far_wing_kernel": {
+            "avg_launch_ms": kt["far_ms"] / max(kt["far_launches"], 1),
+            "node_evaluations_timed": zone_tot["far_node"],
+            "window_end_point_evaluations_timed": zone_tot["far_exact"],
+            "achieved_tflops": ZONE_FLOPS["far_node"] * (zone_tot["far_node"] + zone_tot["far_exact"]) / far_s / 1e12
+            if far_s > 0 else None,
+        },
+        "step_breakdown_ms": {
+            "line_prep_and_sort": kt["prep_ms"] / args.steps,
+            "pre_passes": kt["core_ms"] / args.steps,
+            "tile_kernel": kt["forward_ms"] / args.steps,
+            "far_wing_kernel": kt["far_ms"] / args.steps,
+            "split_combine": kt["combine_ms"] / args.steps,
+        },
+        "point_evaluations_per_s": window_points / elapsed,
+        "cpu_baseline": base,
+    }
+
+
+def c2_run(args, workload="C2", with_baseline=False, steps=3, warmup=1):
+    """The single-cross-section workload (1e8 lines, 296 K and 2000 K at 1 bar): timed
+    steps of line preparation + Q(T) + one batched FP32 call over both (T, P), the plain
+    FP64 path, a graph replay, the 270-point (T, P) grid on the same list, and the
+    Vectorized Voigt, binned, threshold and emission legs when asked for."""
+    import synth
+    cfg = synth.CONFIGS[workload]
     n_lines = args.lines or cfg.n_lines
     temps, pressures = list(cfg.temperatures), list(cfg.pressures) * (len(cfg.temperatures) // len(cfg.pressures) or 1)
     if len(pressures) != len(temps):
         pressures = [cfg.pressures[0]] * len(temps)
 
     base = None
-    if not args.no_cpu_baseline:
+    if with_baseline:
         cores = len(os.sched_getaffinity(0))
         n_s = min(n_lines, args.cpu_lines_per_core * cores)
         log(f"cpu baseline: oracle on {n_s} lines, {cores} processes")
@@ -289,16 +525,16 @@ def main():
         ev1.record(stream)
 
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    for i in range(args.warmup):
+    for i in range(warmup):
         log(f"warmup step {i}")
         step()
     torch.cuda.synchronize()
     plan.set_timing(True)   # hipEvents around each library kernel launch, on this stream
     kern_ms = []
-    log(f"timing {args.steps} steps")
+    log(f"timing {steps} steps")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for i in range(args.steps):
+    for i in range(steps):
         step()
         torch.cuda.synchronize()
         kern_ms.append(ev0.elapsed_time(ev1))
@@ -309,8 +545,8 @@ def main():
     plan.set_timing(False)
     n_kept = plan.lines_kept()
     n_tp = len(temps)
-    value = n_kept * n_tp * args.steps / elapsed
-    ms_step = 1e3 * elapsed / args.steps
+    value = n_kept * n_tp * steps / elapsed
+    ms_step = 1e3 * elapsed / steps
     avg_launch_s = kt["forward_ms"] / kt["forward_launches"] / 1e3
     tp_per_launch = kt["forward_tp"] / kt["forward_launches"]
     # forward time per (T, P): tile kernel + node-sampled far-wing kernel
@@ -322,7 +558,7 @@ def main():
     tile_zones = [k for k in ZONE_FLOPS if k not in ("far_node", "far_exact")]
     flops_step = sum(sum(ZONE_FLOPS[k] * z[k] for k in tile_zones) for z in zones)
     tile_points_step = sum(sum(z[k] for k in tile_zones) for z in zones)
-    launches_per_step = kt["forward_launches"] / args.steps
+    launches_per_step = kt["forward_launches"] / steps
     flops_per_launch = flops_step / launches_per_step
     achieved = flops_per_launch / avg_launch_s / 1e12
     flops_per_eval = flops_step / tile_points_step
@@ -330,7 +566,7 @@ def main():
     # reads 28 B of line data (hot record words and kc) per such pair
     far_nodes_step = sum(z["far_node"] for z in zones)
     far_exact_step = sum(z["far_exact"] for z in zones)
-    far_s_step = kt["far_ms"] / 1e3 / args.steps
+    far_s_step = kt["far_ms"] / 1e3 / steps
     far_obj = None
     if kt["far_launches"] > 0 and far_nodes_step > 0:
         far_obj = {
@@ -349,8 +585,8 @@ def main():
         "value": value,
         "unit": "line-profiles/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
+        "steps": steps,
+        "warmup": warmup,
         "ms_per_step": ms_step,
         "higher_is_better": True,
         "scaling": "weak",
@@ -388,11 +624,11 @@ def main():
         },
         "far_wing_kernel": far_obj,
         "step_breakdown_ms": {
-            "line_prep_and_sort": kt["prep_ms"] / args.steps,
-            "voigt_core_prepass": kt["core_ms"] / args.steps,
-            "tile_kernel": kt["forward_ms"] / args.steps,
-            "far_wing_kernel": kt["far_ms"] / args.steps,
-            "split_combine": kt["combine_ms"] / args.steps,
+            "line_prep_and_sort": kt["prep_ms"] / steps,
+            "voigt_core_prepass": kt["core_ms"] / steps,
+            "tile_kernel": kt["forward_ms"] / steps,
+            "far_wing_kernel": kt["far_ms"] / steps,
+            "split_combine": kt["combine_ms"] / steps,
         },
         "forward_line_profiles_per_s": n_kept / fwd_s_per_tp,
         "point_evaluations_per_s": evals_per_tp / fwd_s_per_tp,
@@ -441,26 +677,91 @@ def main():
         log(f"graph replay {tg * 1e3:.1f} ms")
         graph.close()
 
-    if not args.no_vv:
+    if args.all_legs and not args.no_vv:
         result["vectorized_voigt"] = vv_leg(cfg, d, temps, pressures, tile, out, n_kept, stream, log)
-    if not args.no_binned:
+    if args.all_legs and not args.no_binned:
         result["binned_profiles"] = binned_leg(cfg, d, temps, pressures, n_kept, stream, log)
-    if not args.no_threshold:
+    if args.all_legs and not args.no_threshold:
         result["intensity_threshold"] = threshold_leg(cfg, d, temps, pressures, tile, n_kept, stream, log)
     if not args.no_c3 and cfg.name == "C2":
         result["c3_grid"] = c3_leg(synth.CONFIGS["C3"], d, tile, n_kept, stream, log)
-    if not args.no_emission:
+    if args.all_legs and not args.no_emission:
         result["emission_and_state_reductions"] = emission_leg(cfg, d, temps, pressures, tile, n_kept, stream,
                                                                 log)
 
     del plan, out, d
     torch.cuda.empty_cache()
-    if not args.no_adjoint:
-        result["fwd_adj"] = fwd_adj(synth.CONFIGS["C4"], dev, stream, log)
-    if not args.no_stream:
-        result["streaming"] = stream_run(synth.CONFIGS["C5"], dev, log, args.stream_chunks,
-                                         args.stream_chunk_lines)
+    return result
 
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=15,
+                    help="timed steps (C5: one 2^28-transition chunk through all 36 (T, P) each; 15 cover "
+                         "the 4e9-transition list once)")
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="C5", help="headline workload: C5 (default) or C2")
+    ap.add_argument("--chunk-lines", type=int, default=1 << 28, help="C5: transitions per step")
+    ap.add_argument("--no-c2", action="store_true", help="C5 headline: skip the C2 / C3 sub-entries")
+    ap.add_argument("--c2-steps", type=int, default=5, help="timed steps of the C2 sub-entry")
+    ap.add_argument("--all-legs", action="store_true",
+                    help="also run the Vectorized Voigt, binned, threshold and emission legs on C2")
+    ap.add_argument("--lines", type=int, default=0, help="truncate the line list (profiling runs)")
+    ap.add_argument("--slices-per-wave", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-stream", action="store_true")
+    ap.add_argument("--no-vv", action="store_true", help="skip the Vectorized Voigt leg")
+    ap.add_argument("--no-binned", action="store_true", help="skip the binned-profile / super-line leg")
+    ap.add_argument("--no-threshold", action="store_true", help="skip the intensity-threshold leg")
+    ap.add_argument("--no-c3", action="store_true", help="skip the 270-point (T, P) grid leg")
+    ap.add_argument("--no-emission", action="store_true",
+                    help="skip the emission cross-section and state-reduction leg")
+    ap.add_argument("--stream-chunks", type=int, default=4)
+    ap.add_argument("--stream-chunk-lines", type=int, default=1 << 24)
+    ap.add_argument("--autotune-ms", type=float, default=6000.0,
+                    help="autotuner budget (0: keep the library's default tile shape)")
+    ap.add_argument("--tile", default="", help="fixed tile config waves,slices,n_split,tp_block")
+    ap.add_argument("--cpu-lines-per-core", type=int, default=40000)
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="only run a device copy of this many MiB (HBM counter calibration)")
+    args = ap.parse_args()
+
+    if args.copy_probe:
+        import torch
+        x = torch.ones(args.copy_probe * 2**18, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_each_way": x.numel() * 4}), flush=True)
+        return
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    result = {}
+    if args.workload == "C5":
+        result = c5_run(args)
+        if not args.no_c2:
+            result["c2"] = c2_run(args, steps=args.c2_steps, warmup=1)
+    else:
+        result = c2_run(args, args.workload, with_baseline=not args.no_cpu_baseline, steps=args.steps,
+                        warmup=args.warmup)
+    import synth
+    import torch
+    torch.cuda.empty_cache()
+    if not args.no_adjoint:
+        result["fwd_adj"] = fwd_adj(synth.CONFIGS["C4"], torch.device("cuda:0"), torch.cuda.current_stream(), log)
+    if not args.no_stream:
+        result["streaming_from_host"] = stream_run(synth.CONFIGS["C5"], torch.device("cuda:0"), log,
+                                                   args.stream_chunks, args.stream_chunk_lines)
+    result["paper_cpu_context"] = PAPER_CONTEXT
     print(json.dumps(result), flush=True)
 
 

@@ -323,8 +323,10 @@ xs_status xs_cooling_function(xs_plan* plan, int64_t n_lines, const int32_t* upp
  * sigma: device array [n_tp][n_points], nu fastest; float for XS_FP32, double for
  * XS_FP64.  The result overwrites sigma.  The (T, P) points are processed in blocks
  * of tp_block, each block in one forward launch that makes one pass over the sorted
- * lines per tile.  XS_FP32 with XS_VOIGT waits on `stream` once per block (to size the
- * buffer of its double-precision core values); otherwise the call does not wait.
+ * lines per tile.  XS_FP32 with XS_VOIGT sizes the buffer of its double-precision core
+ * values from a bound kept with the line set: a call waits on `stream` once (to read the
+ * bound back) when the line set is new or its highest temperature exceeds the highest one
+ * the bound covers; otherwise, and for every other profile and precision, it does not wait.
  * The result of a (T, P) point does not depend on the other points of the call. */
 xs_status xs_cross_section(xs_plan* plan, int32_t n_tp, const double* T, const double* P,
                            void* sigma, void* stream);

@@ -126,7 +126,7 @@ struct Workset {
     DevBuf th_bsum, th_tmp;   // intensity threshold: block counts, scan scratch per row
     DevBuf th_pos, th_map, th_offs;   // per row: positions [n+1], kept lines [n], offsets [nkeys+1]
     DevBuf part;              // per-part sums [tp_block][n_split][n_points] when n_split > 1
-    DevBuf far;               // FP32 Voigt: node-sampled far-wing sums [tp_block][kFarShares][n_points]
+    DevBuf far;               // FP32 Voigt: node-sampled far-wing sums [tp_block][kFarShares + 1][n_points]
     DevBuf out;               // autotuner output scratch
     size_t bytes = 0;
     Stage stage;
@@ -173,6 +173,11 @@ struct xs_plan {
     bool lines_vib = false; // the line set carries its states' vibrational energies
     int last_split = 0, last_block = 0;
     uint64_t generation = 1;   // bumped whenever captured graphs become invalid
+    // FP32 Voigt: bound of one (T, P)'s core values over the line set (any Lorentz width,
+    // any T up to core_bound_T), valid while generation == core_bound_gen
+    long long core_bound = 0;
+    double core_bound_T = 0.0;
+    uint64_t core_bound_gen = 0;
     size_t total_bytes = 0;
 
     // states
@@ -548,7 +553,7 @@ xs_status ensure_rows(xs_plan* p, Workset& ws, int B, int S) {
         XS_TRY(ws.ensure(ws.part, (size_t)B * S * (size_t)p->geo.n_points * elem, "split partial sums"));
     }
     if (far_sampled(p)) {
-        XS_TRY(ws.ensure(ws.far, (size_t)B * kFarShares * (size_t)p->geo.n_points * sizeof(double),
+        XS_TRY(ws.ensure(ws.far, (size_t)B * (kFarShares + 1) * (size_t)p->geo.n_points * sizeof(double),
                          "far-wing sums"));
     }
     return XS_OK;
@@ -643,6 +648,7 @@ xs::FwdArgs fwd_args(xs_plan* p, Workset& ws, const std::vector<xs::TPParam>& tp
         int rm = 0;
         for (int t = f; t < f + nb; ++t) rm = std::max(rm, tps[t].rm);
         a.far_ends = (int64_t)p->geo.hmin - WW + 2 >= (int64_t)std::max(far_reach_steps(WW), rm) ? 1 : 0;
+        a.far_slots = a.far_share + a.far_ends;
     }
     return a;
 }
@@ -1260,11 +1266,34 @@ static xs_status cross_section_call(xs_plan* p, int32_t n_tp, const double* T, c
     p->last_split = S;
     XS_TRY(ensure_rows(p, ws, B, S));
     std::vector<long long> vbase(n_tp, 0), vend(n_tp, 0);
-    // (the FP32 Voigt path waits once per block of (T, P) to size its core values)
+    const bool core = core_path(p) && p->n_kept > 0;
+    if (core) {
+        // every core row of a block gets the capacity of the count bound at the call's
+        // highest temperature; the bound is kept with the line set, so only a call with a
+        // new line set or a higher temperature waits (once) to read it back
+        int imax = 0;
+        for (int i = 1; i < n_tp; ++i)
+            if (T[i] > T[imax]) imax = i;
+        if (!(p->core_bound_gen == p->generation && p->core_bound_T >= T[imax])) {
+            xs::CoreArgs c = core_args(p, ws, imax, 0);
+            XS_HIP(xs::launch_core_bound(c, s));
+            std::vector<unsigned long long> tot;
+            XS_TRY(read_totals(ws, 1, s, tot));
+            p->core_bound = (long long)tot[0];
+            p->core_bound_T = T[imax];
+            p->core_bound_gen = p->generation;
+        }
+        const long long slot = std::max<long long>(p->core_bound, 1);
+        XS_TRY(ws.ensure(ws.val, (size_t)B * (size_t)slot * sizeof(float), "core values"));
+        for (int f = 0; f < n_tp; f += B)
+            for (int t = 0; t < std::min(B, n_tp - f); ++t) {
+                vbase[f + t] = (long long)t * slot;
+                vend[f + t] = (long long)(t + 1) * slot;
+            }
+    }
     for (int f = 0; f < n_tp; f += B) {
         const int nb = std::min(B, n_tp - f);
-        if (core_path(p) && p->n_kept > 0) XS_TRY(count_block(p, ws, tps, f, nb, s, vbase, vend));
-        XS_TRY(enqueue_block(p, ws, tps, f, nb, S, false, vbase, vend, sigma, s, true));
+        XS_TRY(enqueue_block(p, ws, tps, f, nb, S, core, vbase, vend, sigma, s, true));
     }
     return XS_OK;
 }

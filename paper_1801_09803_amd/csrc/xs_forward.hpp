@@ -80,14 +80,15 @@ struct FwdArgs {
     int64_t map_stride;
     const int* offs;
     int64_t offs_stride;
-    // FP32 Voigt segmented sweep: node-sampled far-wing sums of far_kernel, FP64
-    // [n_tp][far_share][n_points], added by launch_combine; NULL: the tile kernel sums every line
+    // FP32 Voigt segmented sweep: node-sampled far-wing sums, FP64 [n_tp][far_slots][n_points]:
+    // slots 0 .. far_share-1 from far_kernel's shares, slot far_share (with far_ends) from
+    // ends_kernel; added by launch_combine.  NULL: the tile kernel sums every line
     double* far;
     int far_share;
-    // far: the window-end runs (windows ending or starting inside a wavefront) are
-    // node-sampled by far_kernel as well (every such line lies beyond the far reach and the
-    // |z| < 40 radius of the wavefront); the tile kernel then sweeps only the lines centred
-    // near its tile
+    int far_slots;
+    // with far: the window-end runs (windows ending or starting inside a wavefront) are
+    // node-sampled by ends_kernel (every such line lies beyond the far reach and the |z| < 40
+    // radius of the wavefront); the tile kernel then sweeps only the lines centred near its tile
     int far_ends;
 };
 

@@ -1002,28 +1002,8 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
 // lines [s1, hcl) and [hcr, s4) (windows covering the wavefront, centres at least the far
 // reach away), taken as one sequence, go in chunks q, q + far_share, ... of 64, one line per
 // lane (the next chunk's line data loaded while the current one is summed), with FP64 sums
-// per lane and node.
-//
-// With A.far_ends the window-end lines come here too: [s0, s1) (windows ending inside the
-// wavefront) and [s4, s5) (windows starting inside it), all of them at least the far reach
-// from every point.  The wavefront is cut into NB blocks of BW points.  A left line whose
-// window ends in block b (its last point w0 + m, m clamped to the wavefront) covers blocks
-// 0..b-1 whole: its node values go to bucket b of the left side, and blocks c < b see the
-// sum of the left buckets above them (a suffix sum).  Its points in block b itself (up to
-// w0 + m) are evaluated one by one.  Right lines mirror this (prefix sums, points from the
-// window's first point).  Buckets b with b % far_share == q belong to share q.
-//
-// Each point o of the wavefront then takes the 8-point Lagrange interpolation of the node
-// values of its block, N_b = far + (left suffix) + (right prefix), plus its exact block sum,
-// into far[tp][q][k] (every point of the wavefront, zeros included).  Everything is summed
-// in a fixed order: the result does not depend on the run.
-template <int P>
-struct FarEnds {
-    static constexpr int WW = 64 * P;
-    static constexpr int BW = P == 1 ? 4 : 8;      // points per block
-    static constexpr int NB = WW / BW;             // blocks per wavefront
-    static constexpr int LPP = 64 / BW;            // lines per pass of the exact block sums
-};
+// per lane and node; then the wavefront's node totals, interpolated to its points, go to
+// far[tp][q][k] (every point of the wavefront, zeros included).
 
 // wave-wide sum of v (every lane ends with the total)
 __device__ __forceinline__ double wave_total(double v) {
@@ -1051,16 +1031,35 @@ __device__ __forceinline__ float far_value(const float4& h4, const float2& h2, f
     return num * __builtin_amdgcn_rcpf(den);
 }
 
+// value at point o (0 .. WW-1) of a wavefront of the 8-point Lagrange interpolation of
+// node values nodes[0 .. kFarN-1] (nodes m at (WW - 1) m / (kFarN - 1)); the stencil is the
+// eight nodes around the point, clamped to the ends
+template <int WW>
+__device__ __forceinline__ void lagrange8(int o, int* i0_out, double (&w)[8]) {
+    // 1 / prod_{b != a} (a - b)
+    constexpr double den8[8] = {-1.0 / 5040, 1.0 / 720, -1.0 / 240, 1.0 / 144,
+                                -1.0 / 144, 1.0 / 240, -1.0 / 720, 1.0 / 5040};
+    const double u = (double)(o * (kFarN - 1)) / (double)(WW - 1);   // position in node spacings
+    int i0 = (int)floor(u) - 3;
+    i0 = i0 < 0 ? 0 : (i0 > kFarN - 8 ? kFarN - 8 : i0);
+    const double t = u - (double)i0;
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+        double v = den8[a];
+#pragma unroll
+        for (int b = 0; b < 8; ++b)
+            if (b != a) v *= t - (double)b;
+        w[a] = v;
+    }
+    *i0_out = i0;
+}
+
 template <int P>
 __global__ __launch_bounds__(256) void far_kernel(const FwdArgs A, int n_waves) {
     constexpr int WW = 64 * P;
-    using FE = FarEnds<P>;
-    constexpr int BW = FE::BW, NB = FE::NB, LPP = FE::LPP;
     using L = HotOf<kVoigt>;
     static_assert(L::H == 0 && L::C0 == 1 && L::C1 == 2 && L::AMP == 3 && L::XC == L::B + 1, "layout");
-    __shared__ double tl[4][kFarN];           // node totals of the far lines
-    __shared__ float eb[4][2][NB][kFarN];     // window-end node sums per side and bucket (scaled by 2^32)
-    __shared__ double ex[4][WW];              // window-end block sums, point by point
+    __shared__ double tl[4][kFarN];
     const int lane = threadIdx.x & 63, wl = threadIdx.x >> 6;
     const int64_t total = (int64_t)n_waves * A.n_tp * A.far_share;
     const int64_t gw = (int64_t)blockIdx.x * 4 + wl;
@@ -1075,14 +1074,12 @@ __global__ __launch_bounds__(256) void far_kernel(const FwdArgs A, int n_waves) 
     const int* map = A.map ? A.map + (int64_t)it * A.map_stride : nullptr;
     const int* off = A.offs ? A.offs + (int64_t)it * A.offs_stride : A.off;
     const float* hot = A.hot + (int64_t)it * A.rec_stride * kHot;
-    const int rm = wave_rm(tp, G, w0, w1);
-    const FarRange fr = far_range(off, G, w0, w1, rm, far_reach(WW));
+    const FarRange fr = far_range(off, G, w0, w1, wave_rm(tp, G, w0, w1), far_reach(WW));
     const int nl = fr.hcl - fr.s1, nv = nl + (fr.s4 - fr.hcr);
     const int step = 64 * A.far_share;
     // per lane and node: FP32 sums of up to four lines, added to FP64 sums; amplitudes
     // scaled by 2^32 (exact) keep tiny values out of the single-precision subnormal range
     constexpr float kUp = 4294967296.0f;
-    constexpr double kDown = 1.0 / 4294967296.0;
     double acc[kFarN];
     float a32[kFarN];
 #pragma unroll
@@ -1126,163 +1123,203 @@ __global__ __launch_bounds__(256) void far_kernel(const FwdArgs A, int n_waves) 
         }
     }
 #pragma unroll
-    for (int m = 0; m < kFarN; ++m) acc[m] = wave_total((acc[m] + (double)a32[m]) * kDown);
+    for (int m = 0; m < kFarN; ++m) acc[m] = wave_total((acc[m] + (double)a32[m]) * (1.0 / 4294967296.0));
     if (lane == 0) {
 #pragma unroll
         for (int m = 0; m < kFarN; ++m) tl[wl][m] = acc[m];
     }
-
-    const bool ends = A.far_ends != 0;
-    if (ends) {
-        for (int o = lane; o < WW; o += 64) ex[wl][o] = 0.0;
-        wave_lds_sync();
-        // left side: windows ending inside the wavefront; right side: windows starting inside
-        const int s0 = off_at(off, (int64_t)w0 - G.hmax, G), s1 = fr.s1;
-        const int s4 = fr.s4, s5 = off_at(off, (int64_t)w1 + G.hmax + 1, G);
-        for (int side = 0; side < 2; ++side) {
-            for (int b = 0; b < NB; ++b) {
-                float* bucket = eb[wl][side][b];
-                // candidate lines of bucket b (a window end can be hmin..hmax steps from kc)
-                const int64_t e0 = (int64_t)w0 + b * BW, e1 = e0 + BW - 1;
-                int r0, r1;
-                if (side == 0) {
-                    r0 = off_at(off, e0 - G.hmax, G);
-                    r1 = off_at(off, e1 - G.hmin + 1, G);
-                    r0 = r0 > s0 ? r0 : s0;
-                    r1 = r1 < s1 ? r1 : s1;
-                } else {
-                    r0 = off_at(off, e0 + G.hmin, G);
-                    r1 = off_at(off, e1 + G.hmax + 1, G);
-                    r0 = r0 > s4 ? r0 : s4;
-                    r1 = r1 < s5 ? r1 : s5;
-                }
-                if (b % A.far_share != q || r1 <= r0) {
-                    if (lane < kFarN) bucket[lane] = 0.0f;
-                    continue;
-                }
-                // block offset of a line's window end, clamped to the wavefront: left lines
-                // count up to w0 + m, right lines from w0 + m; -1 / WW: no point of the wavefront
-                auto end_of = [&](int g) {
-                    if (side == 0) {
-                        const int m = A.L.khi[g] - w0;
-                        return m < 0 ? -1 : (m > WW - 1 ? WW - 1 : m);
-                    }
-                    const int m = A.L.klo[g] - w0;
-                    return m > WW - 1 ? WW : (m < 0 ? 0 : m);
-                };
-                // node sums of the bucket's lines, one line per lane
-#pragma unroll
-                for (int m = 0; m < kFarN; ++m) {
-                    acc[m] = 0.0;
-                    a32[m] = 0.0f;
-                }
-                nacc = 0;
-                for (int c = r0; c < r1; c += 64) {
-                    const int l = c + lane;
-                    if (l < r1) {
-                        const int g = line_of(map, l);
-                        const int m = end_of(g);
-                        if (m >= 0 && m < WW && m / BW == b) {
-                            const float4 a4 = *reinterpret_cast<const float4*>(hot + (int64_t)l * kHot);
-                            const float2 a2 = *reinterpret_cast<const float2*>(hot + (int64_t)l * kHot + L::B);
-                            const float x0 = __builtin_fmaf((float)(w0 - A.L.kc[g]), a4.x, a2.y);
-#pragma unroll
-                            for (int mm = 0; mm < kFarN; ++mm)
-                                a32[mm] += far_value(a4, a2, __builtin_fmaf(node_pos<WW>(mm), a4.x, x0), kUp);
-                        }
-                    }
-                    if (++nacc == 4) {
-                        nacc = 0;
-#pragma unroll
-                        for (int mm = 0; mm < kFarN; ++mm) {
-                            acc[mm] += (double)a32[mm];
-                            a32[mm] = 0.0f;
-                        }
-                    }
-                }
-#pragma unroll
-                for (int mm = 0; mm < kFarN; ++mm) acc[mm] = wave_total(acc[mm] + (double)a32[mm]);
-                if (lane == 0) {
-#pragma unroll
-                    for (int mm = 0; mm < kFarN; ++mm) bucket[mm] = (float)acc[mm];
-                }
-                // the bucket's lines point by point within block b: lane = slot * BW + o,
-                // LPP lines per pass
-                const int slot = lane / BW, o = lane % BW;
-                const int k = w0 + b * BW + o;
-                float e32 = 0.0f;
-                double e64 = 0.0;
-                int ne = 0;
-                for (int c = r0; c < r1; c += LPP) {
-                    const int l = c + slot;
-                    if (l < r1) {
-                        const int g = line_of(map, l);
-                        const int m = end_of(g);
-                        const bool mine = m >= 0 && m < WW && m / BW == b;
-                        const bool cover = side == 0 ? (b * BW + o <= m) : (b * BW + o >= m);
-                        if (mine && cover) {
-                            const float4 a4 = *reinterpret_cast<const float4*>(hot + (int64_t)l * kHot);
-                            const float2 a2 = *reinterpret_cast<const float2*>(hot + (int64_t)l * kHot + L::B);
-                            e32 += far_value(a4, a2, __builtin_fmaf((float)(k - A.L.kc[g]), a4.x, a2.y), kUp);
-                        }
-                    }
-                    if (++ne == 4) {
-                        ne = 0;
-                        e64 += (double)e32;
-                        e32 = 0.0f;
-                    }
-                }
-                e64 += (double)e32;
-#pragma unroll
-                for (int x = BW; x < 64; x <<= 1) e64 += __shfl_xor(e64, x, 64);
-                if (slot == 0) ex[wl][b * BW + o] += e64 * kDown;
-            }
-        }
-        wave_lds_sync();
-        // left buckets become suffix sums (the lines covering blocks below them), right
-        // buckets prefix sums; one node per lane
-        if (lane < kFarN) {
-            double run = 0.0;
-            for (int b = NB - 1; b >= 0; --b) {
-                const double v = (double)eb[wl][0][b][lane];
-                eb[wl][0][b][lane] = (float)run;
-                run += v;
-            }
-            run = 0.0;
-            for (int b = 0; b < NB; ++b) {
-                const double v = (double)eb[wl][1][b][lane];
-                eb[wl][1][b][lane] = (float)run;
-                run += v;
-            }
-        }
-    }
     wave_lds_sync();
-    // 8-point Lagrange weights 1 / prod_{b != a} (a - b)
-    constexpr double den8[8] = {-1.0 / 5040, 1.0 / 720, -1.0 / 240, 1.0 / 144,
-                                -1.0 / 144, 1.0 / 240, -1.0 / 720, 1.0 / 5040};
-    double* out = A.far + ((int64_t)it * A.far_share + q) * G.n_points;
+    double* out = A.far + ((int64_t)it * A.far_slots + q) * G.n_points;
 #pragma unroll
     for (int p = 0; p < P; ++p) {
         const int o = 64 * p + lane;
-        const double u = (double)(o * (kFarN - 1)) / (double)(WW - 1);   // position in node spacings
-        int i0 = (int)floor(u) - 3;
-        i0 = i0 < 0 ? 0 : (i0 > kFarN - 8 ? kFarN - 8 : i0);
-        const double t = u - (double)i0;
-        const int blk = o / BW;
+        int i0;
+        double w[8];
+        lagrange8<WW>(o, &i0, w);
         double v = 0.0;
 #pragma unroll
-        for (int a = 0; a < 8; ++a) {
-            double w = den8[a];
-#pragma unroll
-            for (int bb = 0; bb < 8; ++bb)
-                if (bb != a) w *= t - (double)bb;
-            double nodev = tl[wl][i0 + a];
-            if (ends) nodev += ((double)eb[wl][0][blk][i0 + a] + (double)eb[wl][1][blk][i0 + a]) * kDown;
-            v = __builtin_fma(w, nodev, v);
-        }
-        if (ends) v += ex[wl][o];
+        for (int a = 0; a < 8; ++a) v = __builtin_fma(w[a], tl[wl][i0 + a], v);
         const int k = w0 + o;
         if (k < G.n_points) out[k] = v;
+    }
+}
+
+// Window ends of the FP32 Voigt sweep (A.far_ends): the lines [s0, s1) whose cut-off window
+// ends inside a wavefront and [s4, s5) whose window starts inside it, all at least the far
+// reach (and the |z| < 40 radius) from every point of it.  One wavefront per (wavefront
+// tile, (T, P)); its result goes to far slot far_share.
+//
+// The wavefront is cut into NB blocks of BW points.  A left line whose window ends in block
+// b (its last point w0 + m, m clamped to the wavefront) covers blocks 0..b-1 whole: its
+// values at the kFarN nodes go to bucket b of the left side, and block c sees the sum of
+// the left buckets above it (a suffix sum).  Its points in block b itself (up to w0 + m)
+// are evaluated one by one.  Right lines mirror this (windows starting at w0 + m: prefix
+// sums, points from w0 + m).  A window clipped at the grid's last point counts as ending
+// there: the left bucket holding that point takes every left line up to s1 as candidate
+// (a window clipped at the first point starts in bucket 0 of the first wavefront, whose
+// candidates already reach down to s4).
+//
+// Lane = (side, bucket, part): each lane walks its part of its bucket's candidate lines
+// (sorted by centre, a window end lies hmin..hmax steps from it), keeping the node and
+// point sums of its own lines (FP32 over four lines, then FP64), so no cross-lane sums are
+// needed.  Each point o of the wavefront then takes the 8-point interpolation of its
+// block's node values (suffix + prefix) plus its block's point sums.  Fixed order
+// throughout: the result does not depend on the run.
+template <int P>
+struct EndsShape {
+    static constexpr int WW = 64 * P;
+    static constexpr int BW = P == 1 ? 4 : 8;      // points per block
+    static constexpr int NB = WW / BW;             // blocks per wavefront (32 or 16)
+    static constexpr int H = 64 / (2 * NB);        // lanes per (side, block): 1 or 2
+};
+
+template <int P>
+__global__ __launch_bounds__(256) void ends_kernel(const FwdArgs A, int n_waves) {
+    using ES = EndsShape<P>;
+    constexpr int WW = ES::WW, BW = ES::BW, NB = ES::NB, H = ES::H;
+    using L = HotOf<kVoigt>;
+    static_assert(L::H == 0 && L::C0 == 1 && L::C1 == 2 && L::AMP == 3 && L::XC == L::B + 1, "layout");
+    __shared__ float eb[4][2][NB][H][kFarN];   // node sums per (side, block, part), scaled by 2^32
+    __shared__ float ep[4][2][NB][H][BW];      // point sums per (side, block, part), scaled by 2^32
+    const int lane = threadIdx.x & 63, wl = threadIdx.x >> 6;
+    const int64_t gw = (int64_t)blockIdx.x * 4 + wl;
+    if (gw >= (int64_t)n_waves * A.n_tp) return;   // whole wavefronts; no block barrier
+    const int it = (int)(gw % A.n_tp);
+    const int wv = (int)(gw / A.n_tp);
+    const Geometry G = A.G;
+    const int w0 = wv * WW, w1 = w0 + WW - 1;
+    const int* map = A.map ? A.map + (int64_t)it * A.map_stride : nullptr;
+    const int* off = A.offs ? A.offs + (int64_t)it * A.offs_stride : A.off;
+    const float* hot = A.hot + (int64_t)it * A.rec_stride * kHot;
+    const int side = lane / (NB * H);
+    const int b = (lane / H) % NB;
+    const int part = lane % H;
+    // candidate lines of this lane's bucket, then its part of them
+    const int64_t e0 = (int64_t)w0 + b * BW, e1 = e0 + BW - 1;
+    int r0, r1;
+    if (side == 0) {
+        const int s0 = off_at(off, (int64_t)w0 - G.hmax, G), s1 = off_at(off, (int64_t)w1 - G.hmin, G);
+        const bool last = e0 <= (int64_t)G.n_points - 1 && (int64_t)G.n_points - 1 <= e1;
+        r0 = off_at(off, e0 - G.hmax, G);
+        r1 = last ? s1 : off_at(off, e1 - G.hmin + 1, G);
+        r0 = r0 > s0 ? r0 : s0;
+        r1 = r1 < s1 ? r1 : s1;
+    } else {
+        const int s4 = off_at(off, (int64_t)w0 + G.hmin + 1, G), s5 = off_at(off, (int64_t)w1 + G.hmax + 1, G);
+        r0 = off_at(off, e0 + G.hmin, G);
+        r1 = off_at(off, e1 + G.hmax + 1, G);
+        r0 = r0 > s4 ? r0 : s4;
+        r1 = r1 < s5 ? r1 : s5;
+    }
+    if (r1 < r0) r1 = r0;
+    const int len = r1 - r0;
+    const int q0 = r0 + (int)(((int64_t)len * part) / H), q1 = r0 + (int)(((int64_t)len * (part + 1)) / H);
+    int trips = q1 - q0;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {   // the wavefront runs the longest part's trip count
+        const int t = __shfl_xor(trips, o, 64);
+        trips = t > trips ? t : trips;
+    }
+    constexpr float kUp = 4294967296.0f;
+    float n32[kFarN], p32[BW];
+    double n64[kFarN], p64[BW];
+#pragma unroll
+    for (int m = 0; m < kFarN; ++m) { n32[m] = 0.0f; n64[m] = 0.0; }
+#pragma unroll
+    for (int j = 0; j < BW; ++j) { p32[j] = 0.0f; p64[j] = 0.0; }
+    // line data of line l: H, C0, C1, AMP; B, XC; kc; window end relative to w0
+    float4 h4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    float2 h2 = make_float2(0.f, 0.f);
+    int kc = 0, m = -1;
+    auto fetch = [&](int l) {
+        m = -1;
+        if (l < q1) {
+            const int g = line_of(map, l);
+            h4 = *reinterpret_cast<const float4*>(hot + (int64_t)l * kHot);
+            h2 = *reinterpret_cast<const float2*>(hot + (int64_t)l * kHot + L::B);
+            kc = A.L.kc[g];
+            if (side == 0) {
+                const int e = A.L.khi[g] - w0;
+                m = e < 0 ? -1 : (e > WW - 1 ? WW - 1 : e);
+            } else {
+                const int e = A.L.klo[g] - w0;
+                m = e > WW - 1 ? -1 : (e < 0 ? 0 : e);
+            }
+        }
+    };
+    fetch(q0);
+    int nacc = 0;
+    for (int t = 0; t < trips; ++t) {
+        const float4 a4 = h4;
+        const float2 a2 = h2;
+        const int akc = kc, am = m;
+        fetch(q0 + t + 1);
+        if (am >= 0 && am / BW == b) {
+            // nodes (the blocks the window covers whole) and the points of its own block
+            const float x0 = __builtin_fmaf((float)(w0 - akc), a4.x, a2.y);   // x at w0
+#pragma unroll
+            for (int mm = 0; mm < kFarN; ++mm)
+                n32[mm] += far_value(a4, a2, __builtin_fmaf(node_pos<WW>(mm), a4.x, x0), kUp);
+            const int j0 = am - b * BW;   // the window's end within the block
+#pragma unroll
+            for (int j = 0; j < BW; ++j) {
+                const bool cover = side == 0 ? (j <= j0) : (j >= j0);
+                const float v = far_value(a4, a2, __builtin_fmaf((float)(b * BW + j), a4.x, x0), kUp);
+                p32[j] += cover ? v : 0.0f;
+            }
+        }
+        if (++nacc == 4) {
+            nacc = 0;
+#pragma unroll
+            for (int mm = 0; mm < kFarN; ++mm) { n64[mm] += (double)n32[mm]; n32[mm] = 0.0f; }
+#pragma unroll
+            for (int j = 0; j < BW; ++j) { p64[j] += (double)p32[j]; p32[j] = 0.0f; }
+        }
+    }
+#pragma unroll
+    for (int mm = 0; mm < kFarN; ++mm) eb[wl][side][b][part][mm] = (float)(n64[mm] + (double)n32[mm]);
+#pragma unroll
+    for (int j = 0; j < BW; ++j) ep[wl][side][b][part][j] = (float)(p64[j] + (double)p32[j]);
+    wave_lds_sync();
+    // left buckets become suffix sums (the lines covering the blocks below them), right
+    // buckets prefix sums; one node per lane, parts added in order
+    if (lane < kFarN) {
+        double run = 0.0;
+        for (int c = NB - 1; c >= 0; --c) {
+            double v = 0.0;
+#pragma unroll
+            for (int h = 0; h < H; ++h) v += (double)eb[wl][0][c][h][lane];
+            eb[wl][0][c][0][lane] = (float)run;
+            run += v;
+        }
+        run = 0.0;
+        for (int c = 0; c < NB; ++c) {
+            double v = 0.0;
+#pragma unroll
+            for (int h = 0; h < H; ++h) v += (double)eb[wl][1][c][h][lane];
+            eb[wl][1][c][0][lane] = (float)run;
+            run += v;
+        }
+    }
+    wave_lds_sync();
+    double* out = A.far + ((int64_t)it * A.far_slots + A.far_share) * G.n_points;
+    constexpr double kDown = 1.0 / 4294967296.0;
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        const int o = 64 * p + lane;
+        const int blk = o / BW, j = o % BW;
+        int i0;
+        double w[8];
+        lagrange8<WW>(o, &i0, w);
+        double v = 0.0;
+#pragma unroll
+        for (int a = 0; a < 8; ++a)
+            v = __builtin_fma(w[a], (double)eb[wl][0][blk][0][i0 + a] + (double)eb[wl][1][blk][0][i0 + a], v);
+        double e = 0.0;
+#pragma unroll
+        for (int h = 0; h < H; ++h) e += (double)ep[wl][0][blk][h][j] + (double)ep[wl][1][blk][h][j];
+        const int k = w0 + o;
+        if (k < G.n_points) out[k] = (v + e) * kDown;
     }
 }
 
@@ -1351,6 +1388,15 @@ hipError_t launch_far(int waves, int P, const FwdArgs& a, hipStream_t s) {
         case 1: hipLaunchKernelGGL(far_kernel<1>, grid, block, 0, s, a, n_waves); break;
         case 2: hipLaunchKernelGGL(far_kernel<2>, grid, block, 0, s, a, n_waves); break;
         default: hipLaunchKernelGGL(far_kernel<4>, grid, block, 0, s, a, n_waves); break;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !a.far_ends) return e;
+    const int64_t ends = (int64_t)n_waves * a.n_tp;
+    const dim3 grid_e((unsigned)((ends + 3) / 4));
+    switch (P) {
+        case 1: hipLaunchKernelGGL(ends_kernel<1>, grid_e, block, 0, s, a, n_waves); break;
+        case 2: hipLaunchKernelGGL(ends_kernel<2>, grid_e, block, 0, s, a, n_waves); break;
+        default: hipLaunchKernelGGL(ends_kernel<4>, grid_e, block, 0, s, a, n_waves); break;
     }
     return hipGetLastError();
 }

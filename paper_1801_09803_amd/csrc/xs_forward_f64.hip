@@ -278,10 +278,11 @@ __global__ __launch_bounds__(256) void combine_f32_kernel(const float2* part, fl
     sigma[i] = s + c;
 }
 
-// The same with the far-wing sums of far_kernel: (parts' compensated sum, or sigma as the
-// tile kernel wrote it when n_split = 1) + the FP64 sum over shares, rounded once.
+// The same with the node-sampled sums (far_kernel's shares and ends_kernel's slot): (parts'
+// compensated sum, or sigma as the tile kernel wrote it when n_split = 1) + the FP64 sum
+// over the slots, rounded once.
 __global__ __launch_bounds__(256) void combine_far_kernel(const float2* part, const double* far, float* sigma,
-                                                          int n_split, int far_share, int n_points, int64_t total) {
+                                                          int n_split, int far_slots, int n_points, int64_t total) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= total) return;
     const int64_t t = i / n_points, k = i - t * n_points;
@@ -301,9 +302,9 @@ __global__ __launch_bounds__(256) void combine_far_kernel(const float2* part, co
     } else {
         base = (double)sigma[i];
     }
-    const double* f = far + t * far_share * (int64_t)n_points + k;
+    const double* f = far + t * far_slots * (int64_t)n_points + k;
     double fs = 0.0;
-    for (int q = 0; q < far_share; ++q) fs += f[(int64_t)q * n_points];
+    for (int q = 0; q < far_slots; ++q) fs += f[(int64_t)q * n_points];
     sigma[i] = (float)(base + fs);
 }
 
@@ -328,7 +329,7 @@ hipError_t launch_combine(int fp64, const FwdArgs& a, hipStream_t s) {
     const dim3 grid((unsigned)((total + 255) / 256)), block(256);
     if (far)
         hipLaunchKernelGGL(combine_far_kernel, grid, block, 0, s, static_cast<const float2*>(a.part), a.far,
-                           static_cast<float*>(a.sigma), a.n_split, a.far_share, a.G.n_points, total);
+                           static_cast<float*>(a.sigma), a.n_split, a.far_slots, a.G.n_points, total);
     else if (fp64)
         hipLaunchKernelGGL(combine_f64_kernel, grid, block, 0, s, static_cast<const double*>(a.part),
                            static_cast<double*>(a.sigma), a.n_split, a.G.n_points, total);

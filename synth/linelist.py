@@ -146,8 +146,17 @@ def make_transitions(E: torch.Tensor, n_lines: int, nu_max: float, seed: int,
     2*(1024*i + r) + 1; the first accepted attempt wins.
     """
     device = E.device
-    n_states = E.numel()
     line = torch.arange(first_line, first_line + n_lines, dtype=torch.int64, device=device)
+    return make_transitions_at(E, line, nu_max, seed, max_attempts)
+
+
+def make_transitions_at(E: torch.Tensor, line: torch.Tensor, nu_max: float, seed: int, max_attempts: int = 1024):
+    """Upper/lower state indices of the lines with the given (int64) indices: the same
+    pairs make_transitions gives those lines, so any subset of a large list can be drawn."""
+    device = E.device
+    line = line.to(device=device, dtype=torch.int64)
+    n_lines = line.numel()
+    n_states = E.numel()
     upper = torch.full((n_lines,), -1, dtype=torch.int64, device=device)
     lower = torch.full((n_lines,), -1, dtype=torch.int64, device=device)
     todo = torch.arange(n_lines, dtype=torch.int64, device=device)
@@ -174,6 +183,12 @@ def make_transitions(E: torch.Tensor, n_lines: int, nu_max: float, seed: int,
 def make_line_params(n_lines: int, seed: int, first_line: int = 0, device="cpu"):
     """Einstein A (float32, s^-1), gamma_ref (float32, cm^-1/bar), n (float32)."""
     line = torch.arange(first_line, first_line + n_lines, dtype=torch.int64, device=device)
+    return make_line_params_at(line, seed)
+
+
+def make_line_params_at(line: torch.Tensor, seed: int):
+    """make_line_params for the lines with the given (int64) indices."""
+    line = line.to(torch.int64)
     A = torch.pow(10.0, -8.0 + 10.0 * uniform53(seed, STREAM_A, line)).to(torch.float32)
     gref = (0.02 + 0.08 * uniform53(seed, STREAM_BROAD, 2 * line)).to(torch.float32)
     nexp = (0.4 + 0.4 * uniform53(seed, STREAM_BROAD, 2 * line + 1)).to(torch.float32)

@@ -212,4 +212,6 @@ def test_timing_counts_blocks(case):
     log(f"  timings {t}")
     assert t["forward_tp"] == len(TS)
     assert t["forward_launches"] == 3 and t["combine_launches"] == 3
-    assert t["forward_ms"] > 0 and t["core_launches"] == 2 * len(TS)
+    # one timed pre-pass range per (T, P): core count, core evaluation and line records
+    # (the core values' capacity comes from a bound kept with the line set: no count-only pass)
+    assert t["forward_ms"] > 0 and t["core_launches"] == len(TS)

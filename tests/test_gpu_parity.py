@@ -300,3 +300,25 @@ def test_far_wing_clamped_to_the_mid_zone_radius():
     ls = oracle_lineset(h, cfg, 3000.0, 1.0)
     ref = O.cross_section(ls, cfg.nu_a, cfg.nu_b, cfg.n_points, cfg.cutoff)
     assert_parity(got, ref, TOL32, what="fine grid, 3000 K")
+
+
+@pytest.mark.parametrize("waves,slices", [(1, 4), (2, 2), (1, 1), (4, 2)])
+def test_window_ends_at_the_grid_edges(waves, slices):
+    # lines centred within 40 cm^-1 of either end of a fine grid (0.01 cm^-1, cut-off 25):
+    # their windows start or end inside wavefronts all along both edges, many clipped at the
+    # grid's first or last point, with and without a ragged last wavefront (20001 points);
+    # broad lines (30 bar) make the wings count.  The far-wing kernel node-samples these
+    # window ends; the whole grid is checked against the oracle.
+    cfg = synth.WorkloadConfig("edges", 515, 3000, 60000, 28.0, 260.0, 0.0, 200.0, 20001, (1500.0,), (30.0,))
+    d = device_linelist(cfg)
+    E = d["E"]
+    nu = E[d["upper"].long()] - E[d["lower"].long()]
+    keep = ((nu < 40.0) | ((nu > 160.0) & (nu < 240.0))).nonzero().squeeze(1)
+    d = dict(d, **{k: d[k][keep].contiguous() for k in ("upper", "lower", "A", "gamma_ref", "n_exp")})
+    h = host(d)
+    log(f"edges: {keep.numel()} lines, tile {waves} x {slices}")
+    plan = make_plan(cfg, "fp32", waves_per_block=waves, slices_per_wave=slices, n_split=4)
+    got = _run(plan, d, [1500.0], [30.0])[0]
+    ls = oracle_lineset(h, cfg, 1500.0, 30.0)
+    ref = O.cross_section(ls, cfg.nu_a, cfg.nu_b, cfg.n_points, cfg.cutoff, workers=1)
+    assert_parity(got, ref, TOL32, what=f"grid edges {waves}x{slices}")
