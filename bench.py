@@ -59,11 +59,13 @@ def zone_counts_multi(cfg, d, tps, waves=None, slices=None, chunk=1 << 24):
     upper, lower and the per-line gamma_ref, n_exp.
 
     With the tile shape (waves, slices) of the FP32 Voigt sweep, the tile kernel evaluates
-    only the (line, wavefront) pairs whose centre lies within far_reach grid steps of the
-    wavefront of 64 * slices points; their points are counted per zone.  Every other pair
-    the window overlaps goes to the far-wing kernel: FAR_NODES node evaluations each
-    (far_node), plus, where the window starts or ends inside the wavefront, the points of
-    that end's block evaluated one by one (far_exact)."""
+    only the (line, wavefront) pairs whose centre lies within R grid steps of the wavefront
+    of 64 * slices points, R = max(far reach, the wavefront's |z| < 40 radius: the Doppler
+    width at the largest wavenumber near it, capped by the grid's); their points are counted
+    per zone.  Every other pair the window overlaps goes to the node-sampled kernels:
+    FAR_NODES node evaluations each (far_node), plus, where the window starts or ends inside
+    the wavefront, the points of that end's block evaluated one by one (far_exact).  R varies
+    by at most a grid step between neighbouring wavefronts; it is taken at the centre's."""
     import torch
     kB, amu, c_si, ln2 = 1.380649e-23, 1.66053906660e-27, 299792458.0, math.log(2.0)
     betas = {T: math.sqrt(2.0 * kB * T * ln2 / (cfg.mass_amu * amu)) / c_si for T, _ in tps}
@@ -71,60 +73,75 @@ def zone_counts_multi(cfg, d, tps, waves=None, slices=None, chunk=1 << 24):
     tots = [dict({k: 0 for k in ZONE_FLOPS}, far_exact=0) for _ in tps]
     n = d["upper"].numel()
     far = waves is not None
+    dnu = (cfg.nu_b - cfg.nu_a) / (cfg.n_points - 1)
+    R_of = {}
     if far:
         ww = 64 * slices
         bw = 4 if slices == 1 else 8          # points per window-end block of the far kernel
         reach = far_reach(ww)
-        dnu = (cfg.nu_b - cfg.nu_a) / (cfg.n_points - 1)
         hmin = math.floor(cfg.cutoff / dnu) - 2
-        # the sampled lines must lie beyond the |z| < 40 radius of every wavefront, and the
-        # window ends beyond the far reach (the library's condition for sampling them)
-        rm_max = 40.0 * max(betas.values()) * (cfg.nu_b + cfg.cutoff) / (math.sqrt(ln2) * dnu) + 3.0
-        assert reach >= rm_max, "far-wing reach inside the |z| < 40 radius: counts would not match"
-        assert hmin - ww + 2 >= reach, "window ends not node-sampled at this geometry: counts would not match"
+        n_waves = -(-cfg.n_points // (waves * ww)) * waves
+        numax = max(abs(cfg.nu_a), abs(cfg.nu_b)) + cfg.cutoff
+        for T in betas:
+            # the library's per-wavefront radius of the |z| < 40 zone (the tile kernel keeps
+            # the lines centred within max(reach, it) of the wavefront)
+            rm = math.ceil(40.0 * betas[T] * numax / (math.sqrt(ln2) * dnu) + 2.0)
+            scale = 40.0 * betas[T] / (math.sqrt(ln2) * dnu)
+            w = torch.arange(n_waves, dtype=torch.float64, device=E.device)
+            nlo = cfg.nu_a + (w * ww - rm - 1) * dnu
+            nhi = cfg.nu_a + (w * ww + ww - 1 + rm + 1) * dnu
+            rw = torch.ceil(scale * torch.maximum(nlo.abs(), nhi.abs())) + 2.0
+            R_of[T] = torch.clamp(torch.minimum(rw, torch.full_like(rw, rm)), min=reach)
+            # the window ends are node-sampled only beyond both radii (the library's condition)
+            assert hmin - ww + 2 >= max(reach, rm), "window ends not node-sampled here: counts would not match"
     for a in range(0, n, chunk):
         b = min(n, a + chunk)
         nu = E[d["upper"][a:b].long()] - E[d["lower"][a:b].long()]
         gref, nexp = d["gamma_ref"][a:b].double(), d["n_exp"][a:b].double()
-        klo = torch.clamp(torch.ceil(((nu - cfg.cutoff) - cfg.nu_a) / cfg.dnu), min=0)
+        klo_raw = torch.ceil(((nu - cfg.cutoff) - cfg.nu_a) / cfg.dnu)
+        klo = torch.clamp(klo_raw, min=0)
         khi = torch.clamp(torch.floor(((nu + cfg.cutoff) - cfg.nu_a) / cfg.dnu), max=cfg.n_points - 1)
         live = khi >= klo
-        far_pairs, far_ex = 0, 0
         if far:
-            # the tile kernel's part of the window: wavefronts within reach of the centre
             kc = torch.floor((nu - cfg.nu_a) / cfg.dnu + 0.5)
             wl, wr = torch.floor(klo / ww), torch.floor(khi / ww)
-            na = torch.maximum(torch.ceil((kc - reach - ww + 1) / ww), wl)
-            nb = torch.minimum(torch.floor((kc + reach) / ww), wr)
-            near_w = torch.clamp(nb - na + 1, min=0)
-            lo_k = torch.maximum(klo, na * ww)
-            hi_k = torch.minimum(khi, nb * ww + ww - 1)
-            lo_k = torch.where(near_w > 0, lo_k, khi + 1)   # no near wavefront: nothing here
-            far_w = torch.where(live, (wr - wl + 1) - near_w, torch.zeros_like(wl))
-            far_pairs = FAR_NODES * int(far_w.sum().item())
-            # window ends inside a far wavefront: their block's points one by one
-            left_far = live & ((wl < na) | (near_w == 0))
-            right_far = live & ((wr > nb) | (near_w == 0))
-            ex_l = torch.where(left_far, bw - torch.remainder(klo - wl * ww, bw), torch.zeros_like(klo))
-            ex_r = torch.where(right_far, torch.remainder(khi - wr * ww, bw) + 1, torch.zeros_like(khi))
-            far_ex = int((ex_l + ex_r).sum().item())
-            del kc, wl, wr, na, nb, near_w, far_w, left_far, right_far, ex_l, ex_r
-        else:
-            lo_k, hi_k = klo, khi
-        n_all = int(torch.clamp(hi_k - lo_k + 1, min=0).sum().item())
+            wc = torch.clamp(torch.floor(kc / ww), 0, n_waves - 1).long()
         cache = {}
         for i, (T, P) in enumerate(tps):
             s = math.sqrt(ln2) / (betas[T] * nu)
+            if T not in cache:
+                if far:
+                    # the tile kernel's part of the window: wavefronts within R of the centre
+                    R = R_of[T][wc]
+                    na = torch.maximum(torch.ceil((kc - R - ww + 1) / ww), wl)
+                    nb = torch.minimum(torch.floor((kc + R) / ww), wr)
+                    near_w = torch.clamp(nb - na + 1, min=0)
+                    lo_k = torch.where(near_w > 0, torch.maximum(klo, na * ww), khi + 1)
+                    hi_k = torch.minimum(khi, nb * ww + ww - 1)
+                    far_w = torch.where(live, (wr - wl + 1) - near_w, torch.zeros_like(wl))
+                    # (a window cut by the grid's start has no left end on it)
+                    left_far = live & (klo_raw >= 0) & ((wl < na) | (near_w == 0))
+                    right_far = live & ((wr > nb) | (near_w == 0))
+                    ex_l = torch.where(left_far, bw - torch.remainder(klo - wl * ww, bw), torch.zeros_like(klo))
+                    ex_r = torch.where(right_far, torch.remainder(khi - wr * ww, bw) + 1, torch.zeros_like(khi))
+                    far_pairs = FAR_NODES * int(far_w.sum().item())
+                    far_ex = int((ex_l + ex_r).sum().item())
+                else:
+                    lo_k, hi_k, far_pairs, far_ex = klo, khi, 0, 0
+                n_all = int(torch.clamp(hi_k - lo_k + 1, min=0).sum().item())
+                cache[T] = (lo_k, hi_k, far_pairs, far_ex, n_all, None)
+
+            lo_k, hi_k, far_pairs, far_ex, n_all, n_x = cache[T]
 
             def inside(X):   # points of [lo_k, hi_k] with |x| < X
-                R = X / s
-                lo = torch.maximum(torch.floor((nu - R - cfg.nu_a) / cfg.dnu) + 1, lo_k)
-                hi = torch.minimum(torch.ceil((nu + R - cfg.nu_a) / cfg.dnu) - 1, hi_k)
+                R_ = X / s
+                lo = torch.maximum(torch.floor((nu - R_ - cfg.nu_a) / cfg.dnu) + 1, lo_k)
+                hi = torch.minimum(torch.ceil((nu + R_ - cfg.nu_a) / cfg.dnu) - 1, hi_k)
                 return int(torch.where(X > 0, torch.clamp(hi - lo + 1, min=0), torch.zeros_like(X)).sum().item())
 
-            if T not in cache:
-                cache[T] = inside(torch.full_like(nu, 1000.0))
-            n_x = cache[T]
+            if n_x is None:
+                n_x = inside(torch.full_like(nu, 1000.0))
+                cache[T] = (lo_k, hi_k, far_pairs, far_ex, n_all, n_x)
             y2 = (gref * torch.pow(296.0 / T, nexp) * P * s) ** 2
             n_40 = inside(torch.sqrt(torch.clamp(1600.0 - y2, min=0.0)))
             n_8 = inside(torch.sqrt(torch.clamp(64.0 - y2, min=0.0)))
@@ -135,6 +152,7 @@ def zone_counts_multi(cfg, d, tps, waves=None, slices=None, chunk=1 << 24):
             t["core"] += n_8
             t["far_node"] += far_pairs
             t["far_exact"] += far_ex
+        del cache
     return tots
 
 # HBM traffic of the dominant kernel from two rocprofv3 --pmc runs of this script with

@@ -140,7 +140,8 @@ typedef struct {
     double alpha_fixed;    /* HWHM for XS_GAUSS_FIXED                                      */
     double gamma_const;    /* gamma_ref for XS_BROAD_CONST                                 */
     double n_const;        /* temperature exponent for XS_BROAD_CONST                      */
-    int32_t slices_per_wave; /* tile shape: 64-point slices per wavefront (1, 2 or 4);
+    int32_t slices_per_wave; /* tile shape: 64-point slices per wavefront (1, 2, 4, or 8
+                                for XS_FP32 with 1 or 2 wavefronts per workgroup);
                                 0 = library default (2)                                  */
     int32_t waves_per_block; /* tile shape: wavefronts per workgroup for XS_FP32 (1, 2, 4
                                 or 8); 0 = library default (2); XS_FP64 always uses 4    */
@@ -354,7 +355,8 @@ xs_status xs_graph_destroy(xs_graph* graph);
 size_t xs_graph_workspace_bytes(const xs_graph* graph);
 
 /* Tile configuration of the forward launches: wavefronts per workgroup (4, or 1, 2, 8
- * for XS_FP32), 64-point slices per wavefront (1, 2, 4), n_split and tp_block as in
+ * for XS_FP32), 64-point slices per wavefront (1, 2, 4; 8 for XS_FP32 with 1 or 2
+ * wavefronts per workgroup), n_split and tp_block as in
  * xs_opts; 0 selects the default.  SYNCHRONOUS (waits for the device, then rebuilds
  * the tile dispatch order).  Invalidates captured graphs.
  * xs_get_tile_config writes {waves, slices, n_split, tp_block, n_split and tp_block
@@ -365,7 +367,7 @@ xs_status xs_get_tile_config(const xs_plan* plan, int32_t out[6]);
 
 /* Autotuner of the tile configuration (the batching extension).  Times the forward
  * launches (and the split combine) over the first min(n_tp, 16) (T, P) points (at
- * most one default block) in a coordinate search: nine (waves, slices) shapes at
+ * most one default block) in a coordinate search: eleven (waves, slices) shapes at
  * their default n_split, then n_split in 1, 2, 4, .. 64 for the best shape, then smaller
  * tp_block values; a candidate is timed twice when one run is under 20 ms.  It stops
  * once budget_ms of wall time is spent (the first candidate always runs) and keeps the

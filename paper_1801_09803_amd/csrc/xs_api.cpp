@@ -319,8 +319,11 @@ xs_status validate_opts(const xs_opts* o) {
         return fail(XS_ERR_ARG, "alpha_fixed must be > 0 for XS_GAUSS_FIXED");
     if (o->broadening == XS_BROAD_CONST && !(o->gamma_const >= 0.0 && std::isfinite(o->n_const)))
         return fail(XS_ERR_ARG, "gamma_const must be >= 0 and n_const finite");
-    if (o->slices_per_wave != 0 && o->slices_per_wave != 1 && o->slices_per_wave != 2 && o->slices_per_wave != 4)
-        return fail(XS_ERR_ARG, "slices_per_wave must be 0, 1, 2 or 4");
+    if (o->slices_per_wave != 0 && o->slices_per_wave != 1 && o->slices_per_wave != 2 && o->slices_per_wave != 4 &&
+        o->slices_per_wave != 8)
+        return fail(XS_ERR_ARG, "slices_per_wave must be 0, 1, 2, 4 or 8");
+    if (o->slices_per_wave == 8 && (o->precision != XS_FP32 || o->waves_per_block > 2))
+        return fail(XS_ERR_ARG, "8 slices per wavefront need XS_FP32 and 1 or 2 wavefronts per workgroup");
     if (o->a_is_log != 0 && o->a_is_log != 1) return fail(XS_ERR_ARG, "a_is_log must be 0 or 1");
     if (o->waves_per_block != 0 && o->waves_per_block != 1 && o->waves_per_block != 2 && o->waves_per_block != 4 &&
         o->waves_per_block != 8)
@@ -1496,7 +1499,10 @@ xs_status xs_set_tile_config(xs_plan* p, int32_t waves, int32_t slices, int32_t 
     const bool fp64 = p->o.precision == XS_FP64;
     if (!(waves == 0 || waves == 4 || ((waves == 1 || waves == 2 || waves == 8) && !fp64)))
         return fail(XS_ERR_ARG, "waves must be 0 or 4 (or 1, 2, 8 for XS_FP32)");
-    if (!(slices == 0 || slices == 1 || slices == 2 || slices == 4)) return fail(XS_ERR_ARG, "slices must be 0, 1, 2 or 4");
+    if (!(slices == 0 || slices == 1 || slices == 2 || slices == 4 || slices == 8))
+        return fail(XS_ERR_ARG, "slices must be 0, 1, 2, 4 or 8");
+    if (slices == 8 && (fp64 || !(waves == 1 || waves == 2)))
+        return fail(XS_ERR_ARG, "8 slices per wavefront need XS_FP32 and 1 or 2 wavefronts per workgroup");
     if (n_split < 0 || n_split > 64) return fail(XS_ERR_ARG, "n_split must be in [0, 64]");
     if (tp_block < 0 || tp_block > 256) return fail(XS_ERR_ARG, "tp_block must be in [0, 256]");
     XS_HIP(hipDeviceSynchronize());
@@ -1589,7 +1595,7 @@ xs_status xs_autotune(xs_plan* p, int32_t n_tp, const double* T, const double* P
     };
     // coordinate search: tile shapes at their default split, then the split of the best
     // shape, then the (T, P) block size
-    const int shapes[9][2] = {{2, 2}, {1, 2}, {4, 2}, {2, 4}, {2, 1}, {1, 4}, {4, 4}, {8, 2}, {4, 1}};
+    const int shapes[11][2] = {{2, 2}, {1, 2}, {4, 2}, {2, 4}, {2, 1}, {1, 4}, {4, 4}, {8, 2}, {4, 1}, {1, 8}, {2, 8}};
     for (const auto& sh : shapes) {
         if (fp64 && sh[0] != 4) continue;
         p->waves = sh[0];

@@ -902,7 +902,7 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
                     const float* r = rec + i * RS;
                     const unsigned cw =
                         __builtin_amdgcn_readfirstlane(__float_as_uint(S.tf[cword * NT + i])) >> cshift;
-                    if ((cw & ((1u << (4 * P)) - 1u)) == 0u) continue;
+                    if ((cw & (P >= 8 ? 0xffffffffu : ((1u << (4 * P)) - 1u))) == 0u) continue;
                     const float sb0 = S.sb0[i], jlo = r[L::JLO], jhi = r[L::JHI];
 #pragma unroll
                     for (int p = 0; p < P; ++p) {
@@ -1159,28 +1159,34 @@ __global__ __launch_bounds__(256) void far_kernel(const FwdArgs A, int n_waves) 
 // (a window clipped at the first point starts in bucket 0 of the first wavefront, whose
 // candidates already reach down to s4).
 //
-// Lane = (side, bucket, part): each lane walks its part of its bucket's candidate lines
-// (sorted by centre, a window end lies hmin..hmax steps from it), keeping the node and
-// point sums of its own lines (FP32 over four lines, then FP64), so no cross-lane sums are
-// needed.  Each point o of the wavefront then takes the 8-point interpolation of its
-// block's node values (suffix + prefix) plus its block's point sums.  Fixed order
-// throughout: the result does not depend on the run.
+// The buckets are walked in turn; the lanes take consecutive candidate lines of a bucket
+// (sorted by centre: a window end lies hmin..hmax steps from it, so a bucket's candidates
+// are a contiguous run), each keeping the node and point sums of its lines (FP32 over four
+// lines, then FP64), and the wavefront adds them up at the bucket's end.  Each point o
+// then takes the 8-point interpolation of its block's node values (suffix + prefix) plus
+// its block's point sums.  Fixed order throughout: the result does not depend on the run.
 template <int P>
 struct EndsShape {
     static constexpr int WW = 64 * P;
     static constexpr int BW = P == 1 ? 4 : 8;      // points per block
     static constexpr int NB = WW / BW;             // blocks per wavefront (32 or 16)
-    static constexpr int H = 64 / (2 * NB);        // lanes per (side, block): 1 or 2
 };
+
+// wave-wide sum of a float (every lane ends with the total)
+__device__ __forceinline__ float wave_total_f(float v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
 
 template <int P>
 __global__ __launch_bounds__(256) void ends_kernel(const FwdArgs A, int n_waves) {
     using ES = EndsShape<P>;
-    constexpr int WW = ES::WW, BW = ES::BW, NB = ES::NB, H = ES::H;
+    constexpr int WW = ES::WW, BW = ES::BW, NB = ES::NB;
     using L = HotOf<kVoigt>;
     static_assert(L::H == 0 && L::C0 == 1 && L::C1 == 2 && L::AMP == 3 && L::XC == L::B + 1, "layout");
-    __shared__ float eb[4][2][NB][H][kFarN];   // node sums per (side, block, part), scaled by 2^32
-    __shared__ float ep[4][2][NB][H][BW];      // point sums per (side, block, part), scaled by 2^32
+    __shared__ float eb[4][2][NB][kFarN];   // node sums per (side, block), scaled by 2^32
+    __shared__ float ep[4][WW];             // point sums of both sides, scaled by 2^32
     const int lane = threadIdx.x & 63, wl = threadIdx.x >> 6;
     const int64_t gw = (int64_t)blockIdx.x * 4 + wl;
     if (gw >= (int64_t)n_waves * A.n_tp) return;   // whole wavefronts; no block barrier
@@ -1191,113 +1197,117 @@ __global__ __launch_bounds__(256) void ends_kernel(const FwdArgs A, int n_waves)
     const int* map = A.map ? A.map + (int64_t)it * A.map_stride : nullptr;
     const int* off = A.offs ? A.offs + (int64_t)it * A.offs_stride : A.off;
     const float* hot = A.hot + (int64_t)it * A.rec_stride * kHot;
-    const int side = lane / (NB * H);
-    const int b = (lane / H) % NB;
-    const int part = lane % H;
-    // candidate lines of this lane's bucket, then its part of them
-    const int64_t e0 = (int64_t)w0 + b * BW, e1 = e0 + BW - 1;
-    int r0, r1;
-    if (side == 0) {
-        const int s0 = off_at(off, (int64_t)w0 - G.hmax, G), s1 = off_at(off, (int64_t)w1 - G.hmin, G);
-        const bool last = e0 <= (int64_t)G.n_points - 1 && (int64_t)G.n_points - 1 <= e1;
-        r0 = off_at(off, e0 - G.hmax, G);
-        r1 = last ? s1 : off_at(off, e1 - G.hmin + 1, G);
-        r0 = r0 > s0 ? r0 : s0;
-        r1 = r1 < s1 ? r1 : s1;
-    } else {
-        const int s4 = off_at(off, (int64_t)w0 + G.hmin + 1, G), s5 = off_at(off, (int64_t)w1 + G.hmax + 1, G);
-        r0 = off_at(off, e0 + G.hmin, G);
-        r1 = off_at(off, e1 + G.hmax + 1, G);
-        r0 = r0 > s4 ? r0 : s4;
-        r1 = r1 < s5 ? r1 : s5;
-    }
-    if (r1 < r0) r1 = r0;
-    const int len = r1 - r0;
-    const int q0 = r0 + (int)(((int64_t)len * part) / H), q1 = r0 + (int)(((int64_t)len * (part + 1)) / H);
-    int trips = q1 - q0;
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) {   // the wavefront runs the longest part's trip count
-        const int t = __shfl_xor(trips, o, 64);
-        trips = t > trips ? t : trips;
-    }
+    const int s0 = off_at(off, (int64_t)w0 - G.hmax, G), s1 = off_at(off, (int64_t)w1 - G.hmin, G);
+    const int s4 = off_at(off, (int64_t)w0 + G.hmin + 1, G), s5 = off_at(off, (int64_t)w1 + G.hmax + 1, G);
     constexpr float kUp = 4294967296.0f;
-    float n32[kFarN], p32[BW];
-    double n64[kFarN], p64[BW];
-#pragma unroll
-    for (int m = 0; m < kFarN; ++m) { n32[m] = 0.0f; n64[m] = 0.0; }
-#pragma unroll
-    for (int j = 0; j < BW; ++j) { p32[j] = 0.0f; p64[j] = 0.0; }
-    // line data of line l: H, C0, C1, AMP; B, XC; kc; window end relative to w0
-    float4 h4 = make_float4(0.f, 0.f, 0.f, 0.f);
-    float2 h2 = make_float2(0.f, 0.f);
-    int kc = 0, m = -1;
-    auto fetch = [&](int l) {
-        m = -1;
-        if (l < q1) {
-            const int g = line_of(map, l);
-            h4 = *reinterpret_cast<const float4*>(hot + (int64_t)l * kHot);
-            h2 = *reinterpret_cast<const float2*>(hot + (int64_t)l * kHot + L::B);
-            kc = A.L.kc[g];
+    for (int o = lane; o < WW; o += 64) ep[wl][o] = 0.0f;
+    wave_lds_sync();
+    for (int side = 0; side < 2; ++side) {
+        for (int b = 0; b < NB; ++b) {
+            // candidate lines of bucket b (uniform)
+            const int64_t e0 = (int64_t)w0 + b * BW, e1 = e0 + BW - 1;
+            int r0, r1;
             if (side == 0) {
-                const int e = A.L.khi[g] - w0;
-                m = e < 0 ? -1 : (e > WW - 1 ? WW - 1 : e);
+                const bool last = e0 <= (int64_t)G.n_points - 1 && (int64_t)G.n_points - 1 <= e1;
+                r0 = off_at(off, e0 - G.hmax, G);
+                r1 = last ? s1 : off_at(off, e1 - G.hmin + 1, G);
+                r0 = r0 > s0 ? r0 : s0;
+                r1 = r1 < s1 ? r1 : s1;
             } else {
-                const int e = A.L.klo[g] - w0;
-                m = e > WW - 1 ? -1 : (e < 0 ? 0 : e);
+                r0 = off_at(off, e0 + G.hmin, G);
+                r1 = off_at(off, e1 + G.hmax + 1, G);
+                r0 = r0 > s4 ? r0 : s4;
+                r1 = r1 < s5 ? r1 : s5;
             }
-        }
-    };
-    fetch(q0);
-    int nacc = 0;
-    for (int t = 0; t < trips; ++t) {
-        const float4 a4 = h4;
-        const float2 a2 = h2;
-        const int akc = kc, am = m;
-        fetch(q0 + t + 1);
-        if (am >= 0 && am / BW == b) {
-            // nodes (the blocks the window covers whole) and the points of its own block
-            const float x0 = __builtin_fmaf((float)(w0 - akc), a4.x, a2.y);   // x at w0
+            float n32[kFarN], p32[BW];
+            double n64[kFarN], p64[BW];
 #pragma unroll
-            for (int mm = 0; mm < kFarN; ++mm)
-                n32[mm] += far_value(a4, a2, __builtin_fmaf(node_pos<WW>(mm), a4.x, x0), kUp);
-            const int j0 = am - b * BW;   // the window's end within the block
+            for (int m = 0; m < kFarN; ++m) { n32[m] = 0.0f; n64[m] = 0.0; }
 #pragma unroll
-            for (int j = 0; j < BW; ++j) {
-                const bool cover = side == 0 ? (j <= j0) : (j >= j0);
-                const float v = far_value(a4, a2, __builtin_fmaf((float)(b * BW + j), a4.x, x0), kUp);
-                p32[j] += cover ? v : 0.0f;
+            for (int j = 0; j < BW; ++j) { p32[j] = 0.0f; p64[j] = 0.0; }
+            int nacc = 0;
+            // line data of the lane's next line (loaded while the current one is summed):
+            // H, C0, C1, AMP; B, XC; kc; window end relative to w0 (-1: none here)
+            float4 h4 = make_float4(0.f, 0.f, 0.f, 0.f);
+            float2 h2 = make_float2(0.f, 0.f);
+            int hkc = 0, hm = -1;
+            auto fetch = [&](int l) {
+                hm = -1;
+                if (l < r1) {
+                    const int g = line_of(map, l);
+                    h4 = *reinterpret_cast<const float4*>(hot + (int64_t)l * kHot);
+                    h2 = *reinterpret_cast<const float2*>(hot + (int64_t)l * kHot + L::B);
+                    hkc = A.L.kc[g];
+                    if (side == 0) {
+                        const int e = A.L.khi[g] - w0;
+                        hm = e < 0 ? -1 : (e > WW - 1 ? WW - 1 : e);
+                    } else {
+                        const int e = A.L.klo[g] - w0;
+                        hm = e > WW - 1 ? -1 : (e < 0 ? 0 : e);
+                    }
+                }
+            };
+            fetch(r0 + lane);
+            for (int c = r0; c < r1; c += 64) {
+                {
+                    const float4 a4 = h4;
+                    const float2 a2 = h2;
+                    const int akc = hkc, m = hm;
+                    fetch(c + 64 + lane);
+                    if (m >= 0 && m / BW == b) {
+                        const float x0 = __builtin_fmaf((float)(w0 - akc), a4.x, a2.y);   // x at w0
+#pragma unroll
+                        for (int mm = 0; mm < kFarN; ++mm)
+                            n32[mm] += far_value(a4, a2, __builtin_fmaf(node_pos<WW>(mm), a4.x, x0), kUp);
+                        const int j0 = m - b * BW;   // the window's end within the block
+#pragma unroll
+                        for (int j = 0; j < BW; ++j) {
+                            const bool cover = side == 0 ? (j <= j0) : (j >= j0);
+                            const float v = far_value(a4, a2, __builtin_fmaf((float)(b * BW + j), a4.x, x0), kUp);
+                            p32[j] += cover ? v : 0.0f;
+                        }
+                    }
+                }
+                if (++nacc == 4) {
+                    nacc = 0;
+#pragma unroll
+                    for (int mm = 0; mm < kFarN; ++mm) { n64[mm] += (double)n32[mm]; n32[mm] = 0.0f; }
+#pragma unroll
+                    for (int j = 0; j < BW; ++j) { p64[j] += (double)p32[j]; p32[j] = 0.0f; }
+                }
             }
-        }
-        if (++nacc == 4) {
-            nacc = 0;
+            // the bucket's totals (single-precision tree over the lanes' sums)
+            float* bucket = eb[wl][side][b];
+            if (r1 > r0) {
 #pragma unroll
-            for (int mm = 0; mm < kFarN; ++mm) { n64[mm] += (double)n32[mm]; n32[mm] = 0.0f; }
+                for (int mm = 0; mm < kFarN; ++mm) {
+                    const float t = wave_total_f((float)(n64[mm] + (double)n32[mm]));
+                    if (lane == 0) bucket[mm] = t;
+                }
 #pragma unroll
-            for (int j = 0; j < BW; ++j) { p64[j] += (double)p32[j]; p32[j] = 0.0f; }
+                for (int j = 0; j < BW; ++j) {
+                    const float t = wave_total_f((float)(p64[j] + (double)p32[j]));
+                    if (lane == j) ep[wl][b * BW + j] += t;
+                }
+            } else if (lane < kFarN) {
+                bucket[lane] = 0.0f;
+            }
         }
     }
-#pragma unroll
-    for (int mm = 0; mm < kFarN; ++mm) eb[wl][side][b][part][mm] = (float)(n64[mm] + (double)n32[mm]);
-#pragma unroll
-    for (int j = 0; j < BW; ++j) ep[wl][side][b][part][j] = (float)(p64[j] + (double)p32[j]);
     wave_lds_sync();
     // left buckets become suffix sums (the lines covering the blocks below them), right
-    // buckets prefix sums; one node per lane, parts added in order
+    // buckets prefix sums; one node per lane
     if (lane < kFarN) {
         double run = 0.0;
         for (int c = NB - 1; c >= 0; --c) {
-            double v = 0.0;
-#pragma unroll
-            for (int h = 0; h < H; ++h) v += (double)eb[wl][0][c][h][lane];
-            eb[wl][0][c][0][lane] = (float)run;
+            const double v = (double)eb[wl][0][c][lane];
+            eb[wl][0][c][lane] = (float)run;
             run += v;
         }
         run = 0.0;
         for (int c = 0; c < NB; ++c) {
-            double v = 0.0;
-#pragma unroll
-            for (int h = 0; h < H; ++h) v += (double)eb[wl][1][c][h][lane];
-            eb[wl][1][c][0][lane] = (float)run;
+            const double v = (double)eb[wl][1][c][lane];
+            eb[wl][1][c][lane] = (float)run;
             run += v;
         }
     }
@@ -1307,19 +1317,16 @@ __global__ __launch_bounds__(256) void ends_kernel(const FwdArgs A, int n_waves)
 #pragma unroll
     for (int p = 0; p < P; ++p) {
         const int o = 64 * p + lane;
-        const int blk = o / BW, j = o % BW;
+        const int blk = o / BW;
         int i0;
         double w[8];
         lagrange8<WW>(o, &i0, w);
         double v = 0.0;
 #pragma unroll
         for (int a = 0; a < 8; ++a)
-            v = __builtin_fma(w[a], (double)eb[wl][0][blk][0][i0 + a] + (double)eb[wl][1][blk][0][i0 + a], v);
-        double e = 0.0;
-#pragma unroll
-        for (int h = 0; h < H; ++h) e += (double)ep[wl][0][blk][h][j] + (double)ep[wl][1][blk][h][j];
+            v = __builtin_fma(w[a], (double)eb[wl][0][blk][i0 + a] + (double)eb[wl][1][blk][i0 + a], v);
         const int k = w0 + o;
-        if (k < G.n_points) out[k] = (v + e) * kDown;
+        if (k < G.n_points) out[k] = (v + (double)ep[wl][o]) * kDown;
     }
 }
 
@@ -1337,12 +1344,14 @@ void launch_p(int waves, int P, const FwdArgs& a, hipStream_t s) {
         switch (P) {
             case 1: launch_one<PROF, 1, 1>(a, s); break;
             case 2: launch_one<PROF, 1, 2>(a, s); break;
+            case 8: launch_one<PROF, 1, 8>(a, s); break;
             default: launch_one<PROF, 1, 4>(a, s); break;
         }
     } else if (waves == 2) {
         switch (P) {
             case 1: launch_one<PROF, 2, 1>(a, s); break;
             case 2: launch_one<PROF, 2, 2>(a, s); break;
+            case 8: launch_one<PROF, 2, 8>(a, s); break;
             default: launch_one<PROF, 2, 4>(a, s); break;
         }
     } else if (waves == 4) {
@@ -1387,6 +1396,7 @@ hipError_t launch_far(int waves, int P, const FwdArgs& a, hipStream_t s) {
     switch (P) {
         case 1: hipLaunchKernelGGL(far_kernel<1>, grid, block, 0, s, a, n_waves); break;
         case 2: hipLaunchKernelGGL(far_kernel<2>, grid, block, 0, s, a, n_waves); break;
+        case 8: hipLaunchKernelGGL(far_kernel<8>, grid, block, 0, s, a, n_waves); break;
         default: hipLaunchKernelGGL(far_kernel<4>, grid, block, 0, s, a, n_waves); break;
     }
     hipError_t e = hipGetLastError();
@@ -1396,6 +1406,7 @@ hipError_t launch_far(int waves, int P, const FwdArgs& a, hipStream_t s) {
     switch (P) {
         case 1: hipLaunchKernelGGL(ends_kernel<1>, grid_e, block, 0, s, a, n_waves); break;
         case 2: hipLaunchKernelGGL(ends_kernel<2>, grid_e, block, 0, s, a, n_waves); break;
+        case 8: hipLaunchKernelGGL(ends_kernel<8>, grid_e, block, 0, s, a, n_waves); break;
         default: hipLaunchKernelGGL(ends_kernel<4>, grid_e, block, 0, s, a, n_waves); break;
     }
     return hipGetLastError();

@@ -44,6 +44,7 @@ def test_version_and_defaults_without_gpu():
 
 @pytest.mark.parametrize("field,value", [("n_points", 1), ("cutoff", 0.0), ("mass_da", -1.0),
                                          ("profile", 11), ("index_base", 2), ("slices_per_wave", 3),
+                                         ("slices_per_wave", 16),
                                          ("n_split", 65), ("n_split", -1), ("tp_block", 257),
                                          ("vv_beta", 2), ("vv_radius", -1.0), ("vv_radius", float("nan")),
                                          ("gh_nodes", -1), ("gh_nodes", 65)])
@@ -152,3 +153,17 @@ def test_binding_handles_skip_the_library_in_forked_processes():
     f._pid = os.getpid() + 1
     assert not B._owner(f)
     assert not B._owner(Fake())
+
+
+@pytest.mark.parametrize("precision,waves", [(0, 0), (1, 4), (1, 8)])
+def test_eight_slices_need_fp32_and_narrow_workgroups(precision, waves):
+    # 512-point wavefronts exist for the FP32 kernels with 1 or 2 wavefronts per workgroup
+    from paper_1801_09803_amd.binding import XsOpts, load_library
+    lib = load_library()
+    o = XsOpts()
+    lib.xs_opts_default(ctypes.byref(o))
+    o.nu_a, o.nu_b, o.n_points, o.mass_da = 0.0, 10.0, 101, 18.0
+    o.slices_per_wave, o.precision, o.waves_per_block = 8, precision, waves
+    h = ctypes.c_void_p()
+    assert lib.xs_plan_create(ctypes.byref(o), ctypes.byref(h)) == 1 and not h.value
+    assert b"8 slices" in lib.xs_last_error()

@@ -89,7 +89,8 @@ def test_split_tiles_match_oracle(case, oracle_at, precision, split):
         _check_at(out[i], *oracle_at(T, P), TOL32 if precision == "fp32" else TOL64, f"T={T} P={P}")
 
 
-@pytest.mark.parametrize("waves,slices", [(1, 1), (1, 2), (1, 4), (2, 1), (2, 2), (2, 4), (4, 1), (4, 4), (8, 1), (8, 2), (8, 4)])
+@pytest.mark.parametrize("waves,slices", [(1, 1), (1, 2), (1, 4), (1, 8), (2, 1), (2, 2), (2, 4), (2, 8), (4, 1), (4, 4),
+                                          (8, 1), (8, 2), (8, 4)])
 def test_tile_shapes_match_oracle(case, oracle_at, waves, slices):
     # every wavefront width (64, 128, 256 points) has its own far-wing node spacing and
     # reach: the node-sampled far wings of each shape agree with the oracle
@@ -193,7 +194,7 @@ def test_autotune_picks_a_valid_configuration(case, oracle_at):
     plan = _plan(cfg, d, "fp32")
     best = plan.autotune(TS, PS, budget_ms=4000.0)
     log(f"autotune: {best}")
-    assert best["waves"] in (1, 2, 4, 8) and best["slices"] in (1, 2, 4)
+    assert best["waves"] in (1, 2, 4, 8) and best["slices"] in (1, 2, 4, 8)
     assert 1 <= best["n_split"] <= 64 and 1 <= best["tp_block"] <= len(TS)
     cfgd = plan.tile_config()
     assert (cfgd["waves"], cfgd["slices"], cfgd["n_split"], cfgd["tp_block"]) == \

@@ -142,7 +142,7 @@ def test_deterministic_bitwise():
 def test_tile_shapes_agree():
     cfg, d = _small_case(4)
     outs = []
-    for spw in (1, 2, 4):
+    for spw in (1, 2, 4, 8):
         plan = make_plan(cfg, "fp32", slices_per_wave=spw)
         outs.append(_run(plan, d, [1000.0], [1.0])[0])
     for o in outs[1:]:
@@ -302,7 +302,7 @@ def test_far_wing_clamped_to_the_mid_zone_radius():
     assert_parity(got, ref, TOL32, what="fine grid, 3000 K")
 
 
-@pytest.mark.parametrize("waves,slices", [(1, 4), (2, 2), (1, 1), (4, 2)])
+@pytest.mark.parametrize("waves,slices", [(1, 4), (2, 2), (1, 1), (4, 2), (1, 8), (2, 8)])
 def test_window_ends_at_the_grid_edges(waves, slices):
     # lines centred within 40 cm^-1 of either end of a fine grid (0.01 cm^-1, cut-off 25):
     # their windows start or end inside wavefronts all along both edges, many clipped at the
