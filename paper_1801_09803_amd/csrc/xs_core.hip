@@ -9,7 +9,8 @@
 // (exclusive scan of the totals)
 // core_eval: per 256 lines, block-local offsets, then the block's points in passes of
 //   256 grouped by evaluation path, each thread finding its line by binary search over
-//   the group's block prefix.
+//   the group's block prefix.  Near the real axis (y < 0.2) each line takes only the
+//   Taylor terms its y needs.
 #include "xs_forward_common.hpp"
 #include "xs_lineprep.hpp"
 
@@ -128,7 +129,7 @@ __global__ __launch_bounds__(256) void core_eval_kernel(const CoreArgs A) {
     __shared__ unsigned long long pre[256];       // exclusive prefix of the lines' points
     __shared__ unsigned long long gpre[3][256];   // the same per evaluation group
     __shared__ double ls_s[256], ls_nu[256], ls_y[256], ls_a[256];
-    __shared__ int ls_lo[256], ls_ia[256], ls_ib[256], ls_nl[256];
+    __shared__ int ls_lo[256], ls_ia[256], ls_ib[256], ls_nl[256], ls_k[256];
     const int t = threadIdx.x;
     const int g = blockIdx.x * 256 + t;
     const TPParam tp = *A.tp;
@@ -144,6 +145,7 @@ __global__ __launch_bounds__(256) void core_eval_kernel(const CoreArgs A) {
         if (c) {
             const CoreLine cl = core_line(A, tp, g, Q);
             ls_s[t] = cl.s; ls_nu[t] = cl.nu; ls_y[t] = cl.y; ls_lo[t] = cl.lo;
+            ls_k[t] = core_taylor_terms(cl.y);
             ls_a[t] = A.vv ? cl.a * A.vv[g].y : cl.a;   // area-normalised Vectorized Voigt: I' = I x factor
             const int64_t ia = (int64_t)cl.kc - (cl.r - 2) > cl.lo ? (int64_t)cl.kc - (cl.r - 2) : cl.lo;
             const int64_t ib = (int64_t)cl.kc + (cl.r - 2) < cl.hi ? (int64_t)cl.kc + (cl.r - 2) : cl.hi;
@@ -179,7 +181,7 @@ __global__ __launch_bounds__(256) void core_eval_kernel(const CoreArgs A) {
         const double y = ls_y[j];
         const double z2 = __builtin_fma(x, x, y * y);
         double re;
-        if (z2 < kCoreR2) re = voigt_core_re<24, 8>(x, y, A.tab->w24);
+        if (z2 < kCoreR2) re = voigt_core_re_k<24>(x, y, ls_k[j], A.tab->w24);
         else if (z2 < kMidR2) re = gh_wing_re(x * x, y, A.tab->gh4);
         else re = gh_wing_re(x * x, y, A.tab->gh2);
         const long long at = base + (long long)pre[j] + (long long)(k - ls_lo[j]);

@@ -71,7 +71,7 @@ struct HotOf<kVVoigt> {
     static constexpr int JLO = 8, JHI = 9, JVLO = 10, JVHI = 11;
 };
 // cold record words (ints unless noted; C_CBASE is int64, C_M up to 8 floats: the Voigt
-// zones use two, y^2 and the 4-node amplitude; the Gauss-Hermite profiles five)
+// zones' 4-node rule coefficients m0..m7 (struct Mid); the Gauss-Hermite profiles five)
 enum : int { C_CSC = 0, C_KC = 1, C_RAD = 2, C_KCL = 3, C_KCH = 4, C_FLAG = 5, C_CBASE = 6, C_M = 8 };
 constexpr int kHot = 8;
 constexpr int kCold = 16;
@@ -143,9 +143,21 @@ __global__ __launch_bounds__(256) void record_kernel(const RecArgs A) {
             h[L::JVHI] = (float)fmin(kvh - (double)kc, lim);
         }
         cf[C_CSC] = (float)ldexp(1.0, e);
-        // 4-node rule: node pair j has p_j = x^2 + y^2 - t_j^2 and amplitude amp w_j
-        cf[C_M + 0] = (float)y2;
-        cf[C_M + 1] = (float)(a * (y / kPI) * 2.0);
+        // 4-node rule (unscaled x): node pair j = a, b has p_j = x^2 + y^2 - t_j^2,
+        // d_j = p_j^2 + 4 t_j^2 y^2 and n_j = amp w_j (p_j + 2 t_j^2), amp = 2 a y / pi
+        {
+            const double amp = a * (y / kPI) * 2.0;
+            const double t2a = A.tab->gh4.t[0] * A.tab->gh4.t[0], t2b = A.tab->gh4.t[1] * A.tab->gh4.t[1];
+            const double ma = amp * A.tab->gh4.w[0], mb = amp * A.tab->gh4.w[1];
+            cf[C_M + 0] = (float)(y2 - t2a);
+            cf[C_M + 1] = (float)(4.0 * t2a * y2);
+            cf[C_M + 2] = (float)ma;
+            cf[C_M + 3] = (float)(ma * 2.0 * t2a);
+            cf[C_M + 4] = (float)(y2 - t2b);
+            cf[C_M + 5] = (float)(4.0 * t2b * y2);
+            cf[C_M + 6] = (float)mb;
+            cf[C_M + 7] = (float)(mb * 2.0 * t2b);
+        }
         c[C_RAD] = y2 < kMidR2 ? radius_steps(sqrt(kMidR2 - y2), s * G.dnu, s * d) : -1;
         const int rc = A.core_rc[g];
         int kcl = 0, kch = -1;
@@ -275,29 +287,12 @@ struct Mid {
     float m0, m1, m2, m3, m4, m5, m6, m7;
 };
 
-struct Gh4f {
-    float t2a, t2b, wa, wb;
-};
-
-__device__ __forceinline__ Gh4f gh4f(const Tables* tab) {
-    Gh4f g;
-    g.t2a = (float)(tab->gh4.t[0] * tab->gh4.t[0]);
-    g.t2b = (float)(tab->gh4.t[1] * tab->gh4.t[1]);
-    g.wa = (float)tab->gh4.w[0];
-    g.wb = (float)tab->gh4.w[1];
-    return g;
-}
-
-__device__ __forceinline__ Mid mid_coef(float y2, float amp, const Gh4f& g) {
+// the line's coefficients from the LDS copy of its cold words (stride NT)
+template <int NT>
+__device__ __forceinline__ Mid mid_coef(const float* m) {
     Mid c;
-    c.m0 = y2 - g.t2a;
-    c.m1 = 4.0f * g.t2a * y2;
-    c.m2 = amp * g.wa;
-    c.m3 = c.m2 * (2.0f * g.t2a);
-    c.m4 = y2 - g.t2b;
-    c.m5 = 4.0f * g.t2b * y2;
-    c.m6 = amp * g.wb;
-    c.m7 = c.m6 * (2.0f * g.t2b);
+    c.m0 = m[0]; c.m1 = m[NT]; c.m2 = m[2 * NT]; c.m3 = m[3 * NT];
+    c.m4 = m[4 * NT]; c.m5 = m[5 * NT]; c.m6 = m[6 * NT]; c.m7 = m[7 * NT];
     return c;
 }
 
@@ -562,12 +557,11 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
     static_assert(RS % 4 == 0, "record stride");
     constexpr int NTF = SEG ? 0 : NCW * NT;
     // cold profile words in LDS
-    constexpr int NM = (PROF == kGHSampled || PROF == kGHBinned) ? 5
+    constexpr int NM = is_voigt(PROF) ? 8 : (PROF == kGHSampled || PROF == kGHBinned) ? 5
                        : PROF == kDopplerBinned ? 4 : PROF == kLorentzBinned ? 6 : 2;
     __shared__ Lds<NT, RS, NTF, NM> S;
 
     const Geometry G = A.G;
-    const Gh4f g4 = gh4f(A.tab);
     // the wavefront index is uniform within a wavefront: keep it (and everything derived
     // from it: run bounds, loop counters, LDS offsets) in scalar registers
     const int tid = threadIdx.x, lane = tid & 63;
@@ -703,6 +697,8 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
                 if constexpr (NM > 3) S.m[3 * NT + tid] = __int_as_float(q2.w);
                 if constexpr (NM > 4) S.m[4 * NT + tid] = __int_as_float(q3.x);
                 if constexpr (NM > 5) S.m[5 * NT + tid] = __int_as_float(q3.y);
+                if constexpr (NM > 6) S.m[6 * NT + tid] = __int_as_float(q3.z);
+                if constexpr (NM > 7) S.m[7 * NT + tid] = __int_as_float(q3.w);
                 if constexpr (!SEG) {
                     // 4-bit code per slice: zone (0 skip, 1 far, 2 mid, 3 core) | 4 (mask)
                     // | 8 (Vectorized Voigt: points beyond R)
@@ -845,11 +841,11 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
                             for (int p = 0; p < P; ++p) part[p] += v_lor(r, jl[p] + sb0);
                             continue;
                         }
-                        // scalar copies of the line's integer geometry
+                        // scalar copies of the line's integer geometry; distances from the
+                        // centre to grid points stay inside int (grid plus halo < 2^31)
                         const int kc = __builtin_amdgcn_readfirstlane(S.kc[i]);
                         const int rad = __builtin_amdgcn_readfirstlane(S.rad[i]);
-                        if (PROF == kVoigt &&
-                            !(rad >= 0 && (int64_t)w0 <= (int64_t)kc + rad && (int64_t)w1 >= (int64_t)kc - rad)) {
+                        if (PROF == kVoigt && !(rad >= 0 && w0 - kc <= rad && kc - w1 <= rad)) {
                             // the line's mid zone (|z| < 40, which holds its core) misses the wave:
                             // every point takes the far rule, as the per-slice tests below would
 #pragma unroll
@@ -859,13 +855,12 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
                         const int kcl = __builtin_amdgcn_readfirstlane(S.kcl[i]);
                         const int kch = __builtin_amdgcn_readfirstlane(S.kch[i]);
                         const float csc = S.csc[i];
-                        const Mid mc = mid_coef(S.m[i], S.m[NT + i], g4);
+                        const Mid mc = mid_coef<NT>(S.m + i);
 #pragma unroll
                         for (int p = 0; p < P; ++p) {
                             const int kA = w0 + 64 * p, kB = kA + 63;
                             const float j = jl[p] + sb0;
-                            const bool nearz = rad >= 0 && (int64_t)kA <= (int64_t)kc + rad &&
-                                               (int64_t)kB >= (int64_t)kc - rad;
+                            const bool nearz = rad >= 0 && kA - kc <= rad && kc - kB <= rad;
                             if (is_voigt(PROF)) {
                                 float v;
                                 if (kA <= kch && kB >= kcl) {
@@ -915,7 +910,7 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
                             if (zone == 1u) {
                                 v = v_far<PROF>(r, j);
                             } else if (zone != 0u) {
-                                const float vm = v_mid<PROF>(r, mid_coef(S.m[i], S.m[NT + i], g4), S.csc[i], j);
+                                const float vm = v_mid<PROF>(r, mid_coef<NT>(S.m + i), S.csc[i], j);
                                 if (zone == 2u) {
                                     v = vm;
                                 } else {

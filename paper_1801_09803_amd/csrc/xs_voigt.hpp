@@ -91,6 +91,41 @@ __device__ __forceinline__ double voigt_core_re(double x, double y, const Weidem
     return sum;
 }
 
+// Taylor terms about the real axis that keep Re w(x + iy) within 1e-10 relative over
+// |z| < 8 for this y (the series' tail shrinks like y^(K+1); thresholds at half the y where
+// K terms first reach that accuracy).
+__device__ __forceinline__ int core_taylor_terms(double y) {
+    return y < 1.0e-6 ? 1 : y < 1.7e-5 ? 2 : y < 7.0e-4 ? 3 : y < 3.7e-3 ? 4 : y < 9.8e-3 ? 5
+         : y < 2.0e-2 ? 6 : y < 3.3e-2 ? 7 : y < 5.0e-2 ? 8 : y < 7.1e-2 ? 9 : y < 9.1e-2 ? 10 : 12;
+}
+
+// voigt_core_re with the number of Taylor terms chosen per line (K from core_taylor_terms,
+// at most 12); the factorial weights use constant reciprocals.
+template <int N>
+__device__ __forceinline__ double voigt_core_re_k(double x, double y, int K, const WeidemanCoef& W) {
+    if (y >= 0.2) return weideman_w<N>(x, y, W).re;
+    double w0r = exp(-x * x);
+    double w0i = weideman_w<N>(x, 0.0, W).im;
+    double w1r = -2.0 * x * w0r;
+    double w1i = -2.0 * x * w0i + 2.0 * kINV_SQRT_PI;
+    double sum = w0r - w1i * y;
+    double fac = y;
+    // unrolled with constant weights; lanes past their line's K are masked off
+#pragma unroll
+    for (int k = 1; k < 12; ++k) {
+        if (k < K) {
+            const double w2r = -2.0 * x * w1r - 2.0 * k * w0r;
+            const double w2i = -2.0 * x * w1i - 2.0 * k * w0i;
+            fac *= y * (1.0 / (k + 1));
+            const int m = (k + 1) & 3;
+            const double term = (m == 0) ? w2r : (m == 1) ? -w2i : (m == 2) ? -w2r : w2i;
+            sum = __builtin_fma(term, fac, sum);
+            w0r = w1r; w0i = w1i; w1r = w2r; w1i = w2i;
+        }
+    }
+    return sum;
+}
+
 // Re w from the n-point Gauss-Hermite rule (pairs + optional zero node), double.
 __device__ __forceinline__ double gh_wing_re(double u, double y, const GHPairs& G) {
     const double y2 = y * y;
