@@ -39,13 +39,16 @@ sys.path.insert(0, ROOT)
 # accumulate FMA + rcp) 7; 2-node rule at |z| >= 40 (x, p, den, num, accumulate FMA + rcp)
 # 11; 4-node rule at 8 <= |z| < 40 (x + two node pairs of three FMA and a rcp + two
 # accumulate FMA) 20; a core value precomputed by the FP64 pre-pass, added: 1.
-ZONE_FLOPS = {"one_pole": 7, "two_node": 11, "four_node": 20, "core": 1, "far_node": 11, "far_exact": 11}
+ZONE_FLOPS = {"one_pole": 7, "two_node": 11, "four_node": 20, "core": 1, "far_node": 11, "far_node4": 20,
+              "far_exact": 11}
 FAR_NODES = 16        # far-wing nodes per wavefront of the FP32 Voigt sweep
+FAR_ZONES = ("far_node", "far_node4", "far_exact")   # evaluations of the node-sampled kernels
 
 
 def far_reach(ww):
-    """Grid steps between a wavefront of ww points and the nearest node-sampled line centre."""
-    return (24 * (ww - 1) + FAR_NODES - 2) // (FAR_NODES - 1)
+    """Grid steps between a wavefront of ww points and the nearest node-sampled line centre
+    (0.57 (ww - 1), rounded up: 16 Chebyshev nodes across the wavefront)."""
+    return (57 * (ww - 1) + 99) // 100
 
 
 def zone_counts(cfg, d, T, P, waves=None, slices=None, chunk=1 << 24):
@@ -60,21 +63,23 @@ def zone_counts_multi(cfg, d, tps, waves=None, slices=None, chunk=1 << 24):
 
     With the tile shape (waves, slices) of the FP32 Voigt sweep, the tile kernel evaluates
     only the (line, wavefront) pairs whose centre lies within R grid steps of the wavefront
-    of 64 * slices points, R = max(far reach, the wavefront's |z| < 40 radius: the Doppler
-    width at the largest wavenumber near it, capped by the grid's); their points are counted
-    per zone.  Every other pair the window overlaps goes to the node-sampled kernels:
-    FAR_NODES node evaluations each (far_node), plus, where the window starts or ends inside
-    the wavefront, the points of that end's block evaluated one by one (far_exact).  R varies
-    by at most a grid step between neighbouring wavefronts; it is taken at the centre's."""
+    of 64 * slices points, R = max(far reach, the wavefront's |z| < 8 radius: the Doppler
+    width at the largest wavenumber near it); their points are counted per zone.  Every
+    other pair the window overlaps goes to the node-sampled kernels: FAR_NODES node
+    evaluations each, by the 4-node rule (far_node4) when the centre lies within the
+    wavefront's |z| < 40 radius rm, else the 2-node rule (far_node), plus, where the window
+    starts or ends inside the wavefront, the points of that end's block evaluated one by one
+    (far_exact).  R and rm vary by at most a grid step between neighbouring wavefronts; they
+    are taken at the centre's."""
     import torch
     kB, amu, c_si, ln2 = 1.380649e-23, 1.66053906660e-27, 299792458.0, math.log(2.0)
     betas = {T: math.sqrt(2.0 * kB * T * ln2 / (cfg.mass_amu * amu)) / c_si for T, _ in tps}
     E = d["E"]
-    tots = [dict({k: 0 for k in ZONE_FLOPS}, far_exact=0) for _ in tps]
+    tots = [{k: 0 for k in ZONE_FLOPS} for _ in tps]
     n = d["upper"].numel()
     far = waves is not None
     dnu = (cfg.nu_b - cfg.nu_a) / (cfg.n_points - 1)
-    R_of = {}
+    R_of, rm_of = {}, {}
     if far:
         ww = 64 * slices
         bw = 4 if slices == 1 else 8          # points per window-end block of the far kernel
@@ -83,15 +88,20 @@ def zone_counts_multi(cfg, d, tps, waves=None, slices=None, chunk=1 << 24):
         n_waves = -(-cfg.n_points // (waves * ww)) * waves
         numax = max(abs(cfg.nu_a), abs(cfg.nu_b)) + cfg.cutoff
         for T in betas:
-            # the library's per-wavefront radius of the |z| < 40 zone (the tile kernel keeps
-            # the lines centred within max(reach, it) of the wavefront)
+            # the library's per-wavefront radii: rm of the |z| < 40 zone and R (node-sampled
+            # lines beyond it) = max(reach, the |z| < 8 radius)
             rm = math.ceil(40.0 * betas[T] * numax / (math.sqrt(ln2) * dnu) + 2.0)
             scale = 40.0 * betas[T] / (math.sqrt(ln2) * dnu)
             w = torch.arange(n_waves, dtype=torch.float64, device=E.device)
             nlo = cfg.nu_a + (w * ww - rm - 1) * dnu
             nhi = cfg.nu_a + (w * ww + ww - 1 + rm + 1) * dnu
             rw = torch.ceil(scale * torch.maximum(nlo.abs(), nhi.abs())) + 2.0
-            R_of[T] = torch.clamp(torch.minimum(rw, torch.full_like(rw, rm)), min=reach)
+            rm_of[T] = torch.minimum(rw, torch.full_like(rw, rm))
+            span = max(reach, rm) + 1
+            nlo = cfg.nu_a + (w * ww - span) * dnu
+            nhi = cfg.nu_a + (w * ww + ww - 1 + span) * dnu
+            r8 = torch.ceil(0.2 * scale * torch.maximum(nlo.abs(), nhi.abs())) + 2.0
+            R_of[T] = torch.clamp(torch.minimum(r8, torch.full_like(r8, rm)), min=reach)
             # the window ends are node-sampled only beyond both radii (the library's condition)
             assert hmin - ww + 2 >= max(reach, rm), "window ends not node-sampled here: counts would not match"
     for a in range(0, n, chunk):
@@ -119,19 +129,26 @@ def zone_counts_multi(cfg, d, tps, waves=None, slices=None, chunk=1 << 24):
                     lo_k = torch.where(near_w > 0, torch.maximum(klo, na * ww), khi + 1)
                     hi_k = torch.minimum(khi, nb * ww + ww - 1)
                     far_w = torch.where(live, (wr - wl + 1) - near_w, torch.zeros_like(wl))
+                    # of the far wavefronts, those within rm of the centre take the 4-node rule
+                    rmc = rm_of[T][wc]
+                    ma = torch.maximum(torch.ceil((kc - rmc - ww + 1) / ww), wl)
+                    mb = torch.minimum(torch.floor((kc + rmc) / ww), wr)
+                    mid_w = torch.where(live, torch.clamp(torch.clamp(mb - ma + 1, min=0) - near_w, min=0),
+                                        torch.zeros_like(wl))
                     # (a window cut by the grid's start has no left end on it)
                     left_far = live & (klo_raw >= 0) & ((wl < na) | (near_w == 0))
                     right_far = live & ((wr > nb) | (near_w == 0))
                     ex_l = torch.where(left_far, bw - torch.remainder(klo - wl * ww, bw), torch.zeros_like(klo))
                     ex_r = torch.where(right_far, torch.remainder(khi - wr * ww, bw) + 1, torch.zeros_like(khi))
-                    far_pairs = FAR_NODES * int(far_w.sum().item())
+                    far4 = FAR_NODES * int(mid_w.sum().item())
+                    far_pairs = FAR_NODES * int(far_w.sum().item()) - far4
                     far_ex = int((ex_l + ex_r).sum().item())
                 else:
-                    lo_k, hi_k, far_pairs, far_ex = klo, khi, 0, 0
+                    lo_k, hi_k, far_pairs, far4, far_ex = klo, khi, 0, 0, 0
                 n_all = int(torch.clamp(hi_k - lo_k + 1, min=0).sum().item())
-                cache[T] = (lo_k, hi_k, far_pairs, far_ex, n_all, None)
+                cache[T] = (lo_k, hi_k, far_pairs, far4, far_ex, n_all, None)
 
-            lo_k, hi_k, far_pairs, far_ex, n_all, n_x = cache[T]
+            lo_k, hi_k, far_pairs, far4, far_ex, n_all, n_x = cache[T]
 
             def inside(X):   # points of [lo_k, hi_k] with |x| < X
                 R_ = X / s
@@ -141,7 +158,7 @@ def zone_counts_multi(cfg, d, tps, waves=None, slices=None, chunk=1 << 24):
 
             if n_x is None:
                 n_x = inside(torch.full_like(nu, 1000.0))
-                cache[T] = (lo_k, hi_k, far_pairs, far_ex, n_all, n_x)
+                cache[T] = (lo_k, hi_k, far_pairs, far4, far_ex, n_all, n_x)
             y2 = (gref * torch.pow(296.0 / T, nexp) * P * s) ** 2
             n_40 = inside(torch.sqrt(torch.clamp(1600.0 - y2, min=0.0)))
             n_8 = inside(torch.sqrt(torch.clamp(64.0 - y2, min=0.0)))
@@ -151,6 +168,7 @@ def zone_counts_multi(cfg, d, tps, waves=None, slices=None, chunk=1 << 24):
             t["four_node"] += n_40 - n_8
             t["core"] += n_8
             t["far_node"] += far_pairs
+            t["far_node4"] += far4
             t["far_exact"] += far_ex
         del cache
     return tots
@@ -383,7 +401,7 @@ def c5_run(args):
     uses = [0] * n_chunks
     for i in range(args.steps):
         uses[i % n_chunks] += 1
-    zone_tot = {k: 0 for k in list(ZONE_FLOPS) + ["far_exact"]}
+    zone_tot = {k: 0 for k in ZONE_FLOPS}
     window_points = 0
     jl_max = gt.numel() - 1
     gt_d, nt_d = gt.to(dev), nt.to(dev)
@@ -405,7 +423,7 @@ def c5_run(args):
     del upper, lower, A
     torch.cuda.empty_cache()
 
-    tile_zones = [k for k in ZONE_FLOPS if k not in ("far_node", "far_exact")]
+    tile_zones = [k for k in ZONE_FLOPS if k not in FAR_ZONES]
     flops = sum(ZONE_FLOPS[k] * zone_tot[k] for k in tile_zones)
     tile_pts = sum(zone_tot[k] for k in tile_zones)
     avg_launch_s = kt["forward_ms"] / kt["forward_launches"] / 1e3
@@ -463,9 +481,10 @@ def c5_run(args):
         },
         "far_wing_kernel": {
             "avg_launch_ms": kt["far_ms"] / max(kt["far_launches"], 1),
-            "node_evaluations_timed": zone_tot["far_node"],
+            "node_evaluations_timed": zone_tot["far_node"] + zone_tot["far_node4"],
+            "four_node_rule_node_evaluations_timed": zone_tot["far_node4"],
             "window_end_point_evaluations_timed": zone_tot["far_exact"],
-            "achieved_tflops": ZONE_FLOPS["far_node"] * (zone_tot["far_node"] + zone_tot["far_exact"]) / far_s / 1e12
+            "achieved_tflops": sum(ZONE_FLOPS[k] * zone_tot[k] for k in FAR_ZONES) / far_s / 1e12
             if far_s > 0 else None,
         },
         "step_breakdown_ms": {
@@ -573,17 +592,18 @@ def c2_run(args, workload="C2", with_baseline=False, steps=3, warmup=1):
     tile = plan.tile_config()
     zones = [zone_counts(cfg, d, T, P, tile["waves"], tile["slices"]) for T, P in zip(temps, pressures)]
     # the tile kernel evaluates the window points outside the node-sampled far wing
-    tile_zones = [k for k in ZONE_FLOPS if k not in ("far_node", "far_exact")]
+    tile_zones = [k for k in ZONE_FLOPS if k not in FAR_ZONES]
     flops_step = sum(sum(ZONE_FLOPS[k] * z[k] for k in tile_zones) for z in zones)
     tile_points_step = sum(sum(z[k] for k in tile_zones) for z in zones)
     launches_per_step = kt["forward_launches"] / steps
     flops_per_launch = flops_step / launches_per_step
     achieved = flops_per_launch / avg_launch_s / 1e12
     flops_per_eval = flops_step / tile_points_step
-    # far-wing kernel: FAR_NODES 2-node evaluations per (line, wavefront) it samples; it
-    # reads 28 B of line data (hot record words and kc) per such pair
-    far_nodes_step = sum(z["far_node"] for z in zones)
+    # far-wing kernel: FAR_NODES evaluations per (line, wavefront) it samples; it reads 28 B
+    # of line data (hot record words and kc) per 2-node pair
+    far_nodes_step = sum(z["far_node"] + z["far_node4"] for z in zones)
     far_exact_step = sum(z["far_exact"] for z in zones)
+    far_flops_step = sum(sum(ZONE_FLOPS[k] * z[k] for k in FAR_ZONES) for z in zones)
     far_s_step = kt["far_ms"] / 1e3 / steps
     far_obj = None
     if kt["far_launches"] > 0 and far_nodes_step > 0:
@@ -591,11 +611,13 @@ def c2_run(args, workload="C2", with_baseline=False, steps=3, warmup=1):
             "avg_launch_ms": kt["far_ms"] / kt["far_launches"],
             "node_evaluations_per_tp": far_nodes_step / len(temps),
             "window_end_point_evaluations_per_tp": far_exact_step / len(temps),
-            "achieved_tflops": ZONE_FLOPS["far_node"] * (far_nodes_step + far_exact_step) / far_s_step / 1e12,
+            "four_node_rule_node_evaluations_per_tp": sum(z["far_node4"] for z in zones) / len(temps),
+            "achieved_tflops": far_flops_step / far_s_step / 1e12,
             "line_data_GBps": 28.0 * far_nodes_step / FAR_NODES / far_s_step / 1e9,
-            "note": "node-sampled wings (every (line, wavefront) pair whose centre lies >= far_reach grid "
-                    "steps away): 16 2-node evaluations per pair, 11 flops each, and the points of a window "
-                    "end's block one by one; one 8-point interpolation per point; line data from L2/MALL",
+            "note": "node-sampled wings (every (line, wavefront) pair whose centre lies beyond max(far reach, "
+                    "|z| < 8 radius)): 16 evaluations per pair by the 2-node rule (11 flops) or, inside the "
+                    "|z| < 40 radius, the 4-node rule (20 flops), and the points of a window end's block one "
+                    "by one; one 16-node barycentric interpolation per point; line data from L2/MALL",
         }
 
     result = {

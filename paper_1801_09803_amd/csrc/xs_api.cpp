@@ -427,8 +427,8 @@ bool vv_needed(const xs_plan* p) { return is_vv(p) && (p->o.vv_beta || p->o.prof
 // far-wing kernel, whose per-share sums need a buffer of at most kFarShares shares
 constexpr int kFarShares = 4;
 // grid steps between a wavefront of ww points and the nearest node-sampled line centre (the
-// kernels' far_reach: 24 spacings of the 16 nodes across the wavefront)
-int far_reach_steps(int ww) { return (24 * (ww - 1) + 14) / 15; }
+// kernels' far_reach: 0.57 (ww - 1), rounded up, for the 16 Chebyshev nodes across it)
+int far_reach_steps(int ww) { return (57 * (ww - 1) + 99) / 100; }
 bool far_sampled(const xs_plan* p) { return p->o.precision == XS_FP32 && p->o.profile == XS_VOIGT; }
 
 // Profile index of the kernels (the area-normalised form differs in its intensities only)

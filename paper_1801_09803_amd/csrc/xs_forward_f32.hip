@@ -498,14 +498,57 @@ __device__ __forceinline__ Prefetch<NQ> load_batch(const FwdArgs& A, const int* 
     return f;
 }
 
-// Node-sampled Voigt far wing (segmented sweep): lines whose centre lies at least
-// far_reach(WW) grid steps from every point of a wavefront of WW points add their 2-node
-// values at kFarN equispaced nodes across it (far_kernel), interpolated to its points; the
-// tile kernel leaves them out.  Such a wing is a smooth rational function of the distance;
-// with an 8-point Lagrange stencil and 24 node spacings between the nearest centre and the
-// wavefront its interpolation error stays below 3e-8 relative.
+// Node-sampled Voigt far wing (segmented sweep): lines whose centre lies at least R grid
+// steps from every point of a wavefront of WW points, R = max(far_reach(WW), the |z| < 8
+// radius), add their wing values (the 2-node rule, or the 4-node rule inside the |z| < 40
+// radius) at kFarN nodes across it (far_kernel), interpolated to its points; the tile
+// kernel leaves them out.  Such a wing is a smooth rational function of the position with
+// its poles near the line centre.  The nodes are the Chebyshev points of the first kind on
+// [0, WW - 1] and the interpolant is the degree-15 polynomial through all of them
+// (barycentric form); with the nearest centre 0.57 (WW - 1) from the wavefront its error
+// stays below 2e-8 relative.
 constexpr int kFarN = 16;
-constexpr int far_reach(int ww) { return (24 * (ww - 1) + kFarN - 2) / (kFarN - 1); }
+constexpr int far_reach(int ww) { return (57 * (ww - 1) + 99) / 100; }
+
+// Grid steps from w0 to node m of a wavefront of WW points, (WW - 1)(1 - cos(pi (2m + 1)/32))/2,
+// rounded to float (the position the node values are computed at).
+template <int WW>
+__device__ __forceinline__ float node_pos(int m) {
+    constexpr double u[kFarN] = {
+        0.0024076366639015356, 0.021529832133895588, 0.059039367825822475, 0.1134947733186315,
+        0.18280335791817726,   0.2643016315870011,   0.35485766137276886,  0.45099142983521961,
+        0.54900857016478033,   0.64514233862723103,  0.73569836841299885,  0.81719664208182263,
+        0.88650522668136844,   0.94096063217417747,  0.97847016786610441,  0.99759236333609835};
+    return (float)((double)(WW - 1) * u[m]);
+}
+
+// Weights at point o (0 .. WW-1) of the polynomial through the node values: the barycentric
+// form sum_m (c_m / (o - p_m)) f_m / sum_m (c_m / (o - p_m)) with c_m = 1 / prod_{k != m}
+// (p_m - p_k) for the node positions p_m as rounded (a node hit exactly takes its value).
+template <int WW>
+__device__ __forceinline__ void far_weights(int o, double (&w)[kFarN]) {
+    double c[kFarN];
+#pragma unroll
+    for (int m = 0; m < kFarN; ++m) {
+        double pr = 1.0;
+#pragma unroll
+        for (int k = 0; k < kFarN; ++k)
+            if (k != m) pr *= (double)node_pos<WW>(m) - (double)node_pos<WW>(k);
+        c[m] = 1.0 / pr;
+    }
+    double den = 0.0;
+    int hit = -1;
+#pragma unroll
+    for (int m = 0; m < kFarN; ++m) {
+        const double d = (double)o - (double)node_pos<WW>(m);
+        if (d == 0.0) hit = m;
+        w[m] = c[m] / (d == 0.0 ? 1.0 : d);
+        den += w[m];
+    }
+    const double inv = 1.0 / den;
+#pragma unroll
+    for (int m = 0; m < kFarN; ++m) w[m] = hit < 0 ? w[m] * inv : (m == hit ? 1.0 : 0.0);
+}
 
 // Radius (grid steps) of the |z| < 40 zone of the lines whose centre can lie near the
 // wavefront [w0, w1]: their wavenumbers, hence Doppler widths, are bounded there.
@@ -520,22 +563,43 @@ __device__ __forceinline__ int wave_rm(const TPParam& tp, const Geometry& G, int
     return rm;
 }
 
-// The wing-only runs of the wavefront [w0, w1] (windows covering it, centres beyond rm)
-// are [s1, s2) left and [s3, s4) right; of them, [s1, hcl) (kc < w0 - reach) and
-// [hcr, s4) (kc > w1 + reach) are node-sampled.
+// Node-sampling radius of the wavefront [w0, w1]: the far reach, or the |z| < 8 radius of
+// the lines centred within max(reach, rm) of it where that is larger (every point of a
+// node-sampled line must lie outside its core).  At most tp.rm.
+__device__ __forceinline__ int wave_far_r(const TPParam& tp, const Geometry& G, int w0, int w1, int reach) {
+    int r8 = tp.rm;
+    if (tp.rm_scale > 0.0) {
+        const double span = (double)(reach > tp.rm ? reach : tp.rm) + 1.0;
+        const double nlo = G.nu_a + ((double)w0 - span) * G.dnu;
+        const double nhi = G.nu_a + ((double)w1 + span) * G.dnu;
+        const double rw = ceil(0.2 * tp.rm_scale * fmax(fabs(nlo), fabs(nhi))) + 2.0;
+        if (rw < (double)r8) r8 = (int)rw;
+    }
+    return __builtin_amdgcn_readfirstlane(r8 > reach ? r8 : reach);
+}
+
+// The lines whose window covers the wavefront [w0, w1] are [s1, s4) (w1 - hmin <= kc <=
+// w0 + hmin); of them, [s1, hcl) (kc < w0 - R) and [hcr, s4) (kc > w1 + R) are
+// node-sampled, R from wave_far_r, and of those [ml, hcl) and [hcr, mr) lie inside the
+// |z| < 40 radius rm (the 4-node rule).
 struct FarRange {
-    int s1, hcl, hcr, s4;
+    int s1, hcl, hcr, s4, ml, mr;
 };
 
-__device__ __forceinline__ FarRange far_range(const int* off, const Geometry& G, int w0, int w1, int rm, int reach) {
-    const int64_t l0 = (int64_t)w1 - G.hmin, l1 = (int64_t)w0 - rm;
-    const int64_t r0 = (int64_t)w1 + rm + 1, r1 = (int64_t)w0 + G.hmin + 1;
-    auto cl = [](int64_t v, int64_t lo, int64_t hi) { return v < lo ? lo : (v > hi ? hi : v); };
+__device__ __forceinline__ FarRange far_range(const int* off, const Geometry& G, int w0, int w1, int rm, int R) {
+    const int64_t l0 = (int64_t)w1 - G.hmin, r1 = (int64_t)w0 + G.hmin + 1;
+    const int64_t hl = (int64_t)w0 - R > l0 ? (int64_t)w0 - R : l0;
+    const int64_t hr = (int64_t)w1 + R + 1 < r1 ? (int64_t)w1 + R + 1 : r1;
+    int64_t ml = (int64_t)w0 - rm, mr = (int64_t)w1 + rm + 1;
+    ml = ml < l0 ? l0 : (ml > hl ? hl : ml);
+    mr = mr > r1 ? r1 : (mr < hr ? hr : mr);
     FarRange f;
     f.s1 = off_at(off, l0, G);
     f.s4 = off_at(off, r1, G);
-    f.hcl = off_at(off, cl((int64_t)w0 - reach, l0, l1), G);
-    f.hcr = off_at(off, cl((int64_t)w1 + reach + 1, r0, r1), G);
+    f.hcl = off_at(off, hl, G);
+    f.hcr = off_at(off, hr, G);
+    f.ml = off_at(off, ml, G);
+    f.mr = off_at(off, mr, G);
     return f;
 }
 
@@ -582,7 +646,7 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
     // the window ends node-sampled too (far_ends), only lines centred within the far reach
     // (or the centre-near radius) of the tile remain here.
     const bool ends_far = SEG && PROF == kVoigt && A.far && A.far_ends;
-    const int64_t rnear = far_reach(WW) > tp.rm ? far_reach(WW) : tp.rm;
+    const int64_t rnear = wave_far_r(tp, G, t0, t1, far_reach(WW));
     const int b0 = off_at(off, (int64_t)t0 - (ends_far ? rnear : G.hmax), G);
     const int b5 = off_at(off, (int64_t)t1 + (ends_far ? rnear : G.hmax) + 1, G);
     const int bstride = NT * A.n_split;
@@ -631,9 +695,12 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
         hcl = s1;
         hcr = s4;
         if (PROF == kVoigt && A.far) {
-            const FarRange fr = far_range(off, G, w0, w1, rm, far_reach(WW));
+            const FarRange fr = far_range(off, G, w0, w1, rm, wave_far_r(tp, G, w0, w1, far_reach(WW)));
             hcl = fr.hcl;
             hcr = fr.hcr;
+            // lines of the centre-near run beyond R are node-sampled too
+            s2 = s2 > hcl ? s2 : hcl;
+            s3 = s3 < hcr ? s3 : hcr;
         }
         if (ends_far) {   // runs 1 and 5 belong to the far kernel
             s0 = s1;
@@ -994,11 +1061,13 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
 }
 
 // Node-sampled Voigt far wing: one wavefront per (wavefront tile wv, (T, P), share q).  The
-// lines [s1, hcl) and [hcr, s4) (windows covering the wavefront, centres at least the far
-// reach away), taken as one sequence, go in chunks q, q + far_share, ... of 64, one line per
-// lane (the next chunk's line data loaded while the current one is summed), with FP64 sums
-// per lane and node; then the wavefront's node totals, interpolated to its points, go to
-// far[tp][q][k] (every point of the wavefront, zeros included).
+// lines [s1, hcl) and [hcr, s4) (windows covering the wavefront, centres at least R away)
+// go in chunks q, q + far_share, ... of 64, one line per lane (the next chunk's line data
+// loaded while the current one is summed), first those beyond the |z| < 40 radius (2-node
+// rule, hot record only), then those inside it (4-node rule, with the coefficients of the
+// cold record), with FP64 sums per lane and node; then the wavefront's node totals,
+// interpolated to its points, go to far[tp][q][k] (every point of the wavefront, zeros
+// included).
 
 // wave-wide sum of v (every lane ends with the total)
 __device__ __forceinline__ double wave_total(double v) {
@@ -1014,10 +1083,6 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// grid steps from w0 to node m of a wavefront of WW points: (WW - 1) m / (kFarN - 1)
-template <int WW>
-__device__ __forceinline__ float node_pos(int m) { return (float)(m * ((double)(WW - 1) / (kFarN - 1))); }
-
 // 2-node value of a line (hot record h4 = {H, C0, C1, AMP}, h2 = {B, XC}) at x, amplitudes scaled by up
 __device__ __forceinline__ float far_value(const float4& h4, const float2& h2, float x, float up) {
     const float pp = __builtin_fmaf(x, x, h4.y);
@@ -1026,27 +1091,16 @@ __device__ __forceinline__ float far_value(const float4& h4, const float2& h2, f
     return num * __builtin_amdgcn_rcpf(den);
 }
 
-// value at point o (0 .. WW-1) of a wavefront of the 8-point Lagrange interpolation of
-// node values nodes[0 .. kFarN-1] (nodes m at (WW - 1) m / (kFarN - 1)); the stencil is the
-// eight nodes around the point, clamped to the ends
-template <int WW>
-__device__ __forceinline__ void lagrange8(int o, int* i0_out, double (&w)[8]) {
-    // 1 / prod_{b != a} (a - b)
-    constexpr double den8[8] = {-1.0 / 5040, 1.0 / 720, -1.0 / 240, 1.0 / 144,
-                                -1.0 / 144, 1.0 / 240, -1.0 / 720, 1.0 / 5040};
-    const double u = (double)(o * (kFarN - 1)) / (double)(WW - 1);   // position in node spacings
-    int i0 = (int)floor(u) - 3;
-    i0 = i0 < 0 ? 0 : (i0 > kFarN - 8 ? kFarN - 8 : i0);
-    const double t = u - (double)i0;
-#pragma unroll
-    for (int a = 0; a < 8; ++a) {
-        double v = den8[a];
-#pragma unroll
-        for (int b = 0; b < 8; ++b)
-            if (b != a) v *= t - (double)b;
-        w[a] = v;
-    }
-    *i0_out = i0;
+// 4-node value at unscaled x from the coefficients m0..m7 of the cold record (amplitudes
+// m2, m3, m6, m7 already scaled)
+__device__ __forceinline__ float far_value4(const float4& ma, const float4& mb, float x) {
+    const float p1 = __builtin_fmaf(x, x, ma.x);
+    const float p2 = __builtin_fmaf(x, x, mb.x);
+    const float d1 = __builtin_fmaf(p1, p1, ma.y);
+    const float d2 = __builtin_fmaf(p2, p2, mb.y);
+    const float n1 = __builtin_fmaf(p1, ma.z, ma.w);
+    const float n2 = __builtin_fmaf(p2, mb.z, mb.w);
+    return __builtin_fmaf(n1, __builtin_amdgcn_rcpf(d1), n2 * __builtin_amdgcn_rcpf(d2));
 }
 
 template <int P>
@@ -1054,6 +1108,7 @@ __global__ __launch_bounds__(256) void far_kernel(const FwdArgs A, int n_waves) 
     constexpr int WW = 64 * P;
     using L = HotOf<kVoigt>;
     static_assert(L::H == 0 && L::C0 == 1 && L::C1 == 2 && L::AMP == 3 && L::XC == L::B + 1, "layout");
+    static_assert(C_CSC == 0 && C_M == 8 && kCold == 16, "cold layout");
     __shared__ double tl[4][kFarN];
     const int lane = threadIdx.x & 63, wl = threadIdx.x >> 6;
     const int64_t total = (int64_t)n_waves * A.n_tp * A.far_share;
@@ -1069,8 +1124,8 @@ __global__ __launch_bounds__(256) void far_kernel(const FwdArgs A, int n_waves) 
     const int* map = A.map ? A.map + (int64_t)it * A.map_stride : nullptr;
     const int* off = A.offs ? A.offs + (int64_t)it * A.offs_stride : A.off;
     const float* hot = A.hot + (int64_t)it * A.rec_stride * kHot;
-    const FarRange fr = far_range(off, G, w0, w1, wave_rm(tp, G, w0, w1), far_reach(WW));
-    const int nl = fr.hcl - fr.s1, nv = nl + (fr.s4 - fr.hcr);
+    const int* cold = A.cold + (int64_t)it * A.rec_stride * kCold;
+    const FarRange fr = far_range(off, G, w0, w1, wave_rm(tp, G, w0, w1), wave_far_r(tp, G, w0, w1, far_reach(WW)));
     const int step = 64 * A.far_share;
     // per lane and node: FP32 sums of up to four lines, added to FP64 sums; amplitudes
     // scaled by 2^32 (exact) keep tiny values out of the single-precision subnormal range
@@ -1082,32 +1137,8 @@ __global__ __launch_bounds__(256) void far_kernel(const FwdArgs A, int n_waves) 
         acc[m] = 0.0;
         a32[m] = 0.0f;
     }
-    // line data of entry v of the sequence: H, C0, C1, AMP; B, XC; kc
-    float4 h4 = make_float4(0.f, 0.f, 0.f, 0.f);
-    float2 h2 = make_float2(0.f, 0.f);
-    int kc = 0;
-    auto fetch = [&](int v) {
-        if (v < nv) {
-            const int l = v < nl ? fr.s1 + v : fr.hcr + (v - nl);
-            h4 = *reinterpret_cast<const float4*>(hot + (int64_t)l * kHot);
-            h2 = *reinterpret_cast<const float2*>(hot + (int64_t)l * kHot + L::B);
-            kc = A.L.kc[line_of(map, l)];
-        }
-    };
-    fetch(64 * q + lane);
     int nacc = 0;
-    for (int c = 64 * q; c < nv; c += step) {
-        const bool in = c + lane < nv;
-        const float4 a4 = h4;
-        const float2 a2 = h2;
-        const int akc = kc;
-        fetch(c + step + lane);
-        if (in) {
-            const float x0 = __builtin_fmaf((float)(w0 - akc), a4.x, a2.y);   // x at w0
-#pragma unroll
-            for (int m = 0; m < kFarN; ++m)
-                a32[m] += far_value(a4, a2, __builtin_fmaf(node_pos<WW>(m), a4.x, x0), kUp);
-        }
+    auto flush = [&]() {
         if (++nacc == 4) {
             nacc = 0;
 #pragma unroll
@@ -1115,6 +1146,62 @@ __global__ __launch_bounds__(256) void far_kernel(const FwdArgs A, int n_waves) 
                 acc[m] += (double)a32[m];
                 a32[m] = 0.0f;
             }
+        }
+    };
+    {
+        // 2-node lines: [s1, ml) then [mr, s4)
+        const int nl = fr.ml - fr.s1, nv = nl + (fr.s4 - fr.mr);
+        // line data of entry v of the sequence: H, C0, C1, AMP; B, XC; kc
+        float4 h4 = make_float4(0.f, 0.f, 0.f, 0.f);
+        float2 h2 = make_float2(0.f, 0.f);
+        int kc = 0;
+        auto fetch = [&](int v) {
+            if (v < nv) {
+                const int l = v < nl ? fr.s1 + v : fr.mr + (v - nl);
+                h4 = *reinterpret_cast<const float4*>(hot + (int64_t)l * kHot);
+                h2 = *reinterpret_cast<const float2*>(hot + (int64_t)l * kHot + L::B);
+                kc = A.L.kc[line_of(map, l)];
+            }
+        };
+        fetch(64 * q + lane);
+        for (int c = 64 * q; c < nv; c += step) {
+            const bool in = c + lane < nv;
+            const float4 a4 = h4;
+            const float2 a2 = h2;
+            const int akc = kc;
+            fetch(c + step + lane);
+            if (in) {
+                const float x0 = __builtin_fmaf((float)(w0 - akc), a4.x, a2.y);   // x at w0
+#pragma unroll
+                for (int m = 0; m < kFarN; ++m)
+                    a32[m] += far_value(a4, a2, __builtin_fmaf(node_pos<WW>(m), a4.x, x0), kUp);
+            }
+            flush();
+        }
+    }
+    {
+        // 4-node lines (inside the |z| < 40 radius): [ml, hcl) then [hcr, mr)
+        const int nl = fr.hcl - fr.ml, nv = nl + (fr.mr - fr.hcr);
+        for (int c = 64 * q; c < nv; c += step) {
+            const int v = c + lane;
+            if (v < nv) {
+                const int l = v < nl ? fr.ml + v : fr.hcr + (v - nl);
+                const float2 hx = *reinterpret_cast<const float2*>(hot + (int64_t)l * kHot + L::B);   // B, XC
+                const float hh = hot[(int64_t)l * kHot + L::H];
+                const int4* cw = reinterpret_cast<const int4*>(cold + (int64_t)l * kCold);
+                const float csc = __int_as_float(cw[0].x);
+                const int4 qa = cw[2], qb = cw[3];
+                const float4 ma = make_float4(__int_as_float(qa.x), __int_as_float(qa.y),
+                                              __int_as_float(qa.z) * kUp, __int_as_float(qa.w) * kUp);
+                const float4 mb = make_float4(__int_as_float(qb.x), __int_as_float(qb.y),
+                                              __int_as_float(qb.z) * kUp, __int_as_float(qb.w) * kUp);
+                const int akc = A.L.kc[line_of(map, l)];
+                const float x0 = __builtin_fmaf((float)(w0 - akc), hh, hx.y);   // scaled x at w0
+#pragma unroll
+                for (int m = 0; m < kFarN; ++m)
+                    a32[m] += far_value4(ma, mb, __builtin_fmaf(node_pos<WW>(m), hh, x0) * csc);
+            }
+            flush();
         }
     }
 #pragma unroll
@@ -1125,15 +1212,14 @@ __global__ __launch_bounds__(256) void far_kernel(const FwdArgs A, int n_waves) 
     }
     wave_lds_sync();
     double* out = A.far + ((int64_t)it * A.far_slots + q) * G.n_points;
-#pragma unroll
+#pragma unroll 1
     for (int p = 0; p < P; ++p) {
         const int o = 64 * p + lane;
-        int i0;
-        double w[8];
-        lagrange8<WW>(o, &i0, w);
+        double w[kFarN];
+        far_weights<WW>(o, w);
         double v = 0.0;
 #pragma unroll
-        for (int a = 0; a < 8; ++a) v = __builtin_fma(w[a], tl[wl][i0 + a], v);
+        for (int m = 0; m < kFarN; ++m) v = __builtin_fma(w[m], tl[wl][m], v);
         const int k = w0 + o;
         if (k < G.n_points) out[k] = v;
     }
@@ -1158,7 +1244,7 @@ __global__ __launch_bounds__(256) void far_kernel(const FwdArgs A, int n_waves) 
 // (sorted by centre: a window end lies hmin..hmax steps from it, so a bucket's candidates
 // are a contiguous run), each keeping the node and point sums of its lines (FP32 over four
 // lines, then FP64), and the wavefront adds them up at the bucket's end.  Each point o
-// then takes the 8-point interpolation of its block's node values (suffix + prefix) plus
+// then takes the interpolation of its block's node values (suffix + prefix) over all nodes plus
 // its block's point sums.  Fixed order throughout: the result does not depend on the run.
 template <int P>
 struct EndsShape {
@@ -1313,13 +1399,12 @@ __global__ __launch_bounds__(256) void ends_kernel(const FwdArgs A, int n_waves)
     for (int p = 0; p < P; ++p) {
         const int o = 64 * p + lane;
         const int blk = o / BW;
-        int i0;
-        double w[8];
-        lagrange8<WW>(o, &i0, w);
+        double w[kFarN];
+        far_weights<WW>(o, w);
         double v = 0.0;
 #pragma unroll
-        for (int a = 0; a < 8; ++a)
-            v = __builtin_fma(w[a], (double)eb[wl][0][blk][i0 + a] + (double)eb[wl][1][blk][i0 + a], v);
+        for (int m = 0; m < kFarN; ++m)
+            v = __builtin_fma(w[m], (double)eb[wl][0][blk][m] + (double)eb[wl][1][blk][m], v);
         const int k = w0 + o;
         if (k < G.n_points) out[k] = (v + (double)ep[wl][o]) * kDown;
     }

@@ -284,10 +284,12 @@ def test_far_wing_zone_accuracy(T):
     assert rel.max() <= 3e-6
 
 
-def test_far_wing_clamped_to_the_mid_zone_radius():
+def test_far_wing_inside_the_mid_zone_radius():
     # a fine grid (0.001 cm^-1) at 3000 K: Doppler widths of ~17 grid steps put the
-    # |z| < 40 radius (~800 steps) beyond the far-wing reach (204 steps for 128-point
-    # wavefronts), so the node-sampled lines start at that radius instead
+    # |z| < 40 radius (~800 steps) far beyond the far-wing reach (146 steps for 256-point
+    # wavefronts) and the |z| < 8 radius (~160 steps) beyond it too: the node-sampled
+    # lines start at the |z| < 8 radius, and those inside the |z| < 40 radius take the
+    # 4-node rule at the nodes
     cfg = synth.WorkloadConfig("fine", 78, 3000, 200000, 34.0, 10000.0, 4995.0, 5005.0, 10001,
                                (3000.0,), (1.0,), cutoff=5.0)
     d = device_linelist(cfg)
