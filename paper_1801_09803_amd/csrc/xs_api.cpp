@@ -425,7 +425,7 @@ bool vv_needed(const xs_plan* p) { return is_vv(p) && (p->o.vv_beta || p->o.prof
 
 // FP32 Voigt: the segmented sweep leaves lines far from a wavefront to the node-sampled
 // far-wing kernel, whose per-share sums need a buffer of at most kFarShares shares
-constexpr int kFarShares = 4;
+constexpr int kFarShares = 8;
 // grid steps between a wavefront of ww points and the nearest node-sampled line centre (the
 // kernels' far_reach: 0.57 (ww - 1), rounded up, for the 16 Chebyshev nodes across it)
 int far_reach_steps(int ww) { return (57 * (ww - 1) + 99) / 100; }
@@ -643,7 +643,7 @@ xs::FwdArgs fwd_args(xs_plan* p, Workset& ws, const std::vector<xs::TPParam>& tp
         // enough wavefronts to fill the chip: shares of the far lines of each wavefront
         const int64_t nw = std::max<int64_t>(1, (int64_t)a.n_tiles * p->waves * nb);
         a.far = as<double>(ws.far);
-        a.far_share = (int)std::min<int64_t>(kFarShares, std::max<int64_t>(1, (16384 + nw - 1) / nw));
+        a.far_share = (int)std::min<int64_t>(kFarShares, std::max<int64_t>(1, (32768 + nw - 1) / nw));
         // the window ends go to the far kernel too when every window-end line lies beyond both
         // the far reach and the |z| < 40 radius of any wavefront it ends in: such lines are
         // at least hmin - WW + 2 steps from it

@@ -7,9 +7,9 @@
 //   and the number of window points in [kc - r, kc + r]; per-256-line totals.  Under an
 //   intensity threshold only kept lines count (the cull runs first).
 // (exclusive scan of the totals)
-// core_eval: per 256 lines, block-local offsets, then the block's points in passes of
-//   256 grouped by evaluation path, each thread finding its line by binary search over
-//   the group's block prefix.  Near the real axis (y < 0.2) each line takes only the
+// core_eval: per 256 lines, block-local offsets, then the block's points grouped by
+//   evaluation path, each thread taking runs of 8 consecutive points (a binary search over
+//   the group's block prefix for the first, a forward step for the rest).  Near the real axis (y < 0.2) each line takes only the
 //   Taylor terms its y needs.
 #include "xs_forward_common.hpp"
 #include "xs_lineprep.hpp"
@@ -165,16 +165,28 @@ __global__ __launch_bounds__(256) void core_eval_kernel(const CoreArgs A) {
     const long long base = A.val_base + (long long)A.bsum[blockIdx.x];
     if (g < A.n_lines) A.coff[g] = base + (long long)ex;
     __syncthreads();
-    for (unsigned long long it = t; it < tot; it += 256) {
+    // each thread takes runs of kRun consecutive points: a binary search for the run's first
+    // point, then a forward step to the next line where the run crosses into it
+    constexpr unsigned long long kRun = 8;
+    for (unsigned long long it0 = (unsigned long long)t * kRun; it0 < tot; it0 += 256 * kRun) {
+    const unsigned long long itn = it0 + kRun < tot ? it0 + kRun : tot;
+    int j = 0, jg = -1;   // line of the previous point and its group
+#pragma unroll 1
+    for (unsigned long long it = it0; it < itn; ++it) {
         const int grp = it < gtot[0] ? 0 : (it < gtot[0] + gtot[1] ? 1 : 2);
         const unsigned long long li = grp == 0 ? it : (grp == 1 ? it - gtot[0] : it - gtot[0] - gtot[1]);
         const unsigned long long* gp = gpre[grp];
-        int lo = 0, hi = 255;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (gp[mid] <= li) lo = mid; else hi = mid - 1;
+        if (grp != jg) {
+            int lo = 0, hi = 255;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (gp[mid] <= li) lo = mid; else hi = mid - 1;
+            }
+            j = lo;
+            jg = grp;
+        } else {
+            while (j < 255 && gp[j + 1] <= li) ++j;
         }
-        const int j = lo;
         const int loc = (int)(li - gp[j]);
         const int k = grp < 2 ? ls_ia[j] + loc : (loc < ls_nl[j] ? ls_lo[j] + loc : ls_ib[j] + 1 + (loc - ls_nl[j]));
         const double x = ls_s[j] * ((A.G.nu_a + (double)k * A.G.dnu) - ls_nu[j]);
@@ -186,6 +198,7 @@ __global__ __launch_bounds__(256) void core_eval_kernel(const CoreArgs A) {
         else re = gh_wing_re(x * x, y, A.tab->gh2);
         const long long at = base + (long long)pre[j] + (long long)(k - ls_lo[j]);
         if (at < A.val_end) A.val[at] = (float)(ls_a[j] * re);
+    }
     }
 }
 

@@ -296,6 +296,17 @@ __device__ __forceinline__ Mid mid_coef(const float* m) {
     return c;
 }
 
+// 4-node rule at unscaled x, added to acc
+__device__ __forceinline__ float mid_rule(const Mid& c, float x, float acc) {
+    const float p1 = __builtin_fmaf(x, x, c.m0);
+    const float p2 = __builtin_fmaf(x, x, c.m4);
+    const float d1 = __builtin_fmaf(p1, p1, c.m1);
+    const float d2 = __builtin_fmaf(p2, p2, c.m5);
+    const float n1 = __builtin_fmaf(p1, c.m2, c.m3);
+    const float n2 = __builtin_fmaf(p2, c.m6, c.m7);
+    return __builtin_fmaf(n1, __builtin_amdgcn_rcpf(d1), __builtin_fmaf(n2, __builtin_amdgcn_rcpf(d2), acc));
+}
+
 // 4-node rule (unscaled x)
 template <int PROF>
 __device__ __forceinline__ float v_mid(const float* r, const Mid& c, float csc, float j) {
@@ -619,7 +630,11 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
     // LDS record words, a multiple of 4 (records are copied and read as float4)
     constexpr int RS = ANCH ? (RH + WAVES + 3) / 4 * 4 : RH;
     static_assert(RS % 4 == 0, "record stride");
-    constexpr int NTF = SEG ? 0 : NCW * NT;
+    // segmented Voigt sweep: 2-bit rule code per slice (0 the 2-node rule, 1 the 4-node
+    // rule, 2 stored core values inside the 4-node rule) of the lines centred near the tile
+    constexpr int NZW = (2 * NS + 31) / 32;
+    constexpr bool ZC = SEG && PROF == kVoigt;
+    constexpr int NTF = SEG ? (ZC ? NZW * NT : 0) : NCW * NT;
     // cold profile words in LDS
     constexpr int NM = is_voigt(PROF) ? 8 : (PROF == kGHSampled || PROF == kGHBinned) ? 5
                        : PROF == kDopplerBinned ? 4 : PROF == kLorentzBinned ? 6 : 2;
@@ -718,6 +733,8 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
     }
     const int cword = (wave * P) / 8;
     const int cshift = 4 * ((wave * P) % 8);
+    const int zword = (2 * wave * P) / 32;    // this wavefront's rule codes (2P bits)
+    const int zshift = (2 * wave * P) % 32;
 
     Prefetch<NQ> nxt = load_batch<NT, NQ>(A, map, ghot, gscale, bfirst, b5, tid);
     for (int bs = bfirst; bs < b5; bs += bstride) {
@@ -766,6 +783,21 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
                 if constexpr (NM > 5) S.m[5 * NT + tid] = __int_as_float(q3.y);
                 if constexpr (NM > 6) S.m[6 * NT + tid] = __int_as_float(q3.z);
                 if constexpr (NM > 7) S.m[7 * NT + tid] = __int_as_float(q3.w);
+                if constexpr (ZC) {
+                    const int rad = q0.z, kcl = q0.w, kch = q1.x;
+                    unsigned zw[NZW];
+#pragma unroll
+                    for (int q = 0; q < NZW; ++q) zw[q] = 0;
+#pragma unroll
+                    for (int sl = 0; sl < NS; ++sl) {
+                        const int kA = t0 + 64 * sl, kB = kA + 63;
+                        const unsigned z = (kA <= kch && kB >= kcl) ? 2u
+                                           : (rad >= 0 && kA - kc <= rad && kc - kB <= rad) ? 1u : 0u;
+                        zw[(2 * sl) / 32] |= z << ((2 * sl) % 32);
+                    }
+#pragma unroll
+                    for (int q = 0; q < NZW; ++q) S.tf[q * NT + tid] = __uint_as_float(zw[q]);
+                }
                 if constexpr (!SEG) {
                     // 4-bit code per slice: zone (0 skip, 1 far, 2 mid, 3 core) | 4 (mask)
                     // | 8 (Vectorized Voigt: points beyond R)
@@ -906,6 +938,52 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
                         if (PROF == kLorentz) {
 #pragma unroll
                             for (int p = 0; p < P; ++p) part[p] += v_lor(r, jl[p] + sb0);
+                            continue;
+                        }
+                        if constexpr (PROF == kVoigt) {
+                            // record words in registers for every slice; each slice's rule adds
+                            // straight into its sum
+                            static_assert(L::H == 0 && L::C0 == 1 && L::C1 == 2 && L::AMP == 3 &&
+                                          L::B == 4 && L::XC == 5, "layout");
+                            const float4 q = *reinterpret_cast<const float4*>(r);
+                            const float2 q2 = *reinterpret_cast<const float2*>(r + L::B);
+                            const unsigned zc = (__builtin_amdgcn_readfirstlane(__float_as_uint(S.tf[zword * NT + i])) >> zshift) &
+                                                (P >= 16 ? 0xffffffffu : ((1u << (2 * P)) - 1u));
+                            if (zc == 0u) {
+                                // the mid zone (|z| < 40, which holds the core) misses the wave
+#pragma unroll
+                                for (int p = 0; p < P; ++p) {
+                                    const float x = __builtin_fmaf(jl[p] + sb0, q.x, q2.y);
+                                    const float pp = __builtin_fmaf(x, x, q.y);
+                                    const float den = __builtin_fmaf(pp, pp, q.z);
+                                    part[p] = __builtin_fmaf(__builtin_fmaf(pp, q.w, q2.x), __builtin_amdgcn_rcpf(den), part[p]);
+                                }
+                                continue;
+                            }
+                            const int kcl = S.kcl[i], kch = S.kch[i];
+                            const float csc = S.csc[i];
+                            const Mid mc = mid_coef<NT>(S.m + i);
+#pragma unroll
+                            for (int p = 0; p < P; ++p) {
+                                const int kA = w0 + 64 * p;
+                                const unsigned z = (zc >> (2 * p)) & 3u;
+                                const float x = __builtin_fmaf(jl[p] + sb0, q.x, q2.y);
+                                if (z == 2u) {
+                                    // stored core values: loaded and consumed inside this branch
+                                    const int k = kA + lane;
+                                    const bool in = (k >= kcl && k <= kch);
+                                    float vcv = 0.0f;
+                                    if (in) vcv = A.core_val[S.cb[i] + k];
+                                    const float vm = mid_rule(mc, x * csc, 0.0f);
+                                    part[p] += in ? vcv : vm;
+                                } else if (z == 1u) {
+                                    part[p] = mid_rule(mc, x * csc, part[p]);
+                                } else {
+                                    const float pp = __builtin_fmaf(x, x, q.y);
+                                    const float den = __builtin_fmaf(pp, pp, q.z);
+                                    part[p] = __builtin_fmaf(__builtin_fmaf(pp, q.w, q2.x), __builtin_amdgcn_rcpf(den), part[p]);
+                                }
+                            }
                             continue;
                         }
                         // scalar copies of the line's integer geometry; distances from the
