@@ -180,7 +180,8 @@ def zone_counts_multi(cfg, d, tps, waves=None, slices=None, chunk=1 << 24):
 # -> x1).  Per (T, P); a launch covering several (T, P) moves that many times the bytes.
 # Valid only for the kernel sources they were taken with (hash below).
 TRAFFIC = {
-    "kernel_sources": ['xs_forward_f32.hip', 'xs_forward_common.hpp', 'xs_voigt.hpp', 'xs_forward.hpp', 'xs_internal.hpp'],
+    "kernel_sources": ['xs_forward_f32.hip', 'xs_records.hpp', 'xs_far.hpp', 'xs_forward_common.hpp', 'xs_voigt.hpp',
+                       'xs_forward.hpp', 'xs_internal.hpp'],
     "sha256": "76f9640d216b506155f16f059aecf9bcb05ea2f4576b0fb8d86ab017ed93694a",
     "fetch_kib": [57698035.0, 63831122.2],
     "write_kib": [506985.5, 506790.2],
@@ -768,7 +769,27 @@ def main():
     ap.add_argument("--cpu-lines-per-core", type=int, default=40000)
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run a device copy of this many MiB (HBM counter calibration)")
+    ap.add_argument("--valu-probe", type=int, default=0,
+                    help="only run the library's FMA-loop kernel with this many iterations per "
+                         "thread (VALU counter calibration)")
     args = ap.parse_args()
+
+    if args.valu_probe:
+        import torch
+        from paper_1801_09803_amd import binding
+        n_threads = 256 * 256 * 64     # 64 workgroups of 256 per CU
+        out = torch.empty(n_threads, dtype=torch.float32, device="cuda")
+        binding.valu_probe(out, args.valu_probe)      # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        binding.valu_probe(out, args.valu_probe)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        fma = n_threads * 16 * args.valu_probe
+        print(json.dumps({"valu_probe_threads": n_threads, "iters": args.valu_probe,
+                          "v_fma_f32_per_launch": fma, "wall_s": dt,
+                          "fp32_tflops": 2.0 * fma / dt / 1e12}), flush=True)
+        return
 
     if args.copy_probe:
         import torch

@@ -470,6 +470,15 @@ typedef struct {
 xs_status xs_set_timing(xs_plan* plan, int enable);
 xs_status xs_kernel_times(xs_plan* plan, xs_timings* out);
 
+/* Measurement aid, no part of the cross-section method: n_threads threads (a positive
+   multiple of 256) each run iters (>= 1) iterations of 16 independent FP32 FMA chains, one
+   v_fma_f32 per chain and iteration, and write one float each to out[n_threads] (device
+   memory), asynchronously on stream.  A counter run over it calibrates the VALU-issue
+   counters (SQ_INSTS_VALU, SQ_ACTIVE_INST_VALU, GRBM_GUI_ACTIVE) against a kernel that keeps
+   the vector ALUs busy, as a device copy of known size calibrates the HBM byte counters.
+   XS_ERR_ARG for a NULL out or out-of-range sizes, XS_ERR_HIP if the launch fails. */
+xs_status xs_valu_probe(float* out, int64_t n_threads, int32_t iters, void* stream);
+
 /* Bytes of device memory the plan currently holds. */
 size_t xs_workspace_bytes(const xs_plan* plan);
 

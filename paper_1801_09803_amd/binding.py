@@ -102,6 +102,7 @@ def load_library() -> ctypes.CDLL:
         "xs_autotune": (i32, [P, i32, P, P, dbl, P, ctypes.POINTER(i32)]),
         "xs_set_timing": (i32, [P, i32]),
         "xs_kernel_times": (i32, [P, ctypes.POINTER(XsKernelTimes)]),
+        "xs_valu_probe": (i32, [P, i64, i32, P]),
         "xs_workspace_bytes": (ctypes.c_size_t, [P]),
         "xs_last_error": (ctypes.c_char_p, []),
         "xs_version": (ctypes.c_int, []),
@@ -112,6 +113,16 @@ def load_library() -> ctypes.CDLL:
         fn.argtypes = args
     _lib = lib
     return lib
+
+
+def valu_probe(out, iters: int):
+    """xs_valu_probe on the float32 device tensor out (one value per thread), on torch's
+    current stream."""
+    import torch
+    if not out.is_cuda or out.dtype != torch.float32 or not out.is_contiguous():
+        raise ValueError("out must be a contiguous float32 CUDA tensor")
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    _check(load_library().xs_valu_probe(ctypes.c_void_p(out.data_ptr()), out.numel(), int(iters), stream))
 
 
 def abi_version() -> int:

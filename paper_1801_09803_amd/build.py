@@ -19,8 +19,8 @@ OBJ = os.path.join(os.path.dirname(HERE), "_build", "xsec")
 ARCH = os.environ.get("XSEC_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["xs_api.cpp", "xs_quadrature.cpp", "xs_lineprep.hip", "xs_core.hip",
-           "xs_forward_f32.hip", "xs_forward_f64.hip", "xs_adjoint.hip", "xs_stream.hip", "xs_vv.hip", "xs_threshold.hip",
-           "xs_states.hip", "xs_noalloc.hip"]
+           "xs_forward_f32.hip", "xs_far.hip", "xs_forward_f64.hip", "xs_adjoint.hip", "xs_stream.hip", "xs_vv.hip", "xs_threshold.hip",
+           "xs_states.hip", "xs_noalloc.hip", "xs_probe.hip"]
 
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",

@@ -32,6 +32,12 @@
 // (rm: radius beyond which every point of the wave is in the far zone, from the largest
 // Doppler width a line of the centre-near run can have, so it shrinks at low wavenumber)
 // Coarse grids use per-slice codes (skip / zone / mask) for every line instead.
+// FP32 Voigt: the lines centred more than R = max(far reach, |z| < 8 radius) from the wave
+// are node-sampled by the far-wing kernels (xs_far.hip) and left out here, the centre-near
+// run shrinking to [w0 - min(rm, R), w1 + min(rm, R)]; when every window-end line lies
+// beyond both radii the first and last runs go to those kernels too, and the tile stages
+// only the lines within R of it.  The centre-near run then takes per-slice rule codes
+// computed once per line at staging (2-node, 4-node, or stored core values).
 //
 // Vectorized Voigt (Sec. "Vectorized Voigt approximation"): within R of the centre the
 // Voigt zones below; beyond R the reference profile times beta, which for the reference's
@@ -49,37 +55,12 @@
 // runs as fma(k - k_anchor, h, x_anchor) from an anchor at the wavefront end nearest the
 // centre (computed in double), so its relative error stays ~1e-7 however far the point is
 // from the centre.  Partial sums are flushed every 64 lines into a compensated (TwoSum) pair.
-#include "xs_forward_common.hpp"
+#include "xs_far.hpp"
+#include "xs_records.hpp"
 
 namespace xs {
 
 namespace {
-
-// hot record words
-// hot record words: scale h, 2-node coefficients C0 C1 AMP B, centre offset XC, window
-// bounds JLO JHI relative to kc; the Vectorized Voigt adds its wing term Y and amplitude VB
-// and the R-region bounds JVLO JVHI, and puts {h, Y, VB, XC} first so that its wing loop
-// reads one float4 per line
-template <int PROF>
-struct HotOf {
-    static constexpr int H = 0, C0 = 1, C1 = 2, AMP = 3, B = 4, XC = 5, JLO = 6, JHI = 7;
-    static constexpr int VY = -1, VB = -1, JVLO = -1, JVHI = -1;
-};
-template <>
-struct HotOf<kVVoigt> {
-    static constexpr int H = 0, VY = 1, VB = 2, XC = 3, C0 = 4, C1 = 5, AMP = 6, B = 7;
-    static constexpr int JLO = 8, JHI = 9, JVLO = 10, JVHI = 11;
-};
-// cold record words (ints unless noted; C_CBASE is int64, C_M up to 8 floats: the Voigt
-// zones' 4-node rule coefficients m0..m7 (struct Mid); the Gauss-Hermite profiles five)
-enum : int { C_CSC = 0, C_KC = 1, C_RAD = 2, C_KCL = 3, C_KCH = 4, C_FLAG = 5, C_CBASE = 6, C_M = 8 };
-constexpr int kHot = 8;
-constexpr int kCold = 16;
-constexpr bool is_voigt(int prof) { return prof == kVoigt || prof == kVVoigt; }
-constexpr int hot_words(int prof) { return prof == kVVoigt ? 12 : kHot; }
-// segmented sweep: keep per-wavefront anchors in the LDS record (saves two operations per
-// line and wavefront) or rebuild them (a smaller LDS image)
-constexpr bool anchors_in_lds(int prof) { return prof != kVVoigt; }
 
 // ------------------------------------------------------------------ record kernel
 template <int PROF>
@@ -509,111 +490,6 @@ __device__ __forceinline__ Prefetch<NQ> load_batch(const FwdArgs& A, const int* 
     return f;
 }
 
-// Node-sampled Voigt far wing (segmented sweep): lines whose centre lies at least R grid
-// steps from every point of a wavefront of WW points, R = max(far_reach(WW), the |z| < 8
-// radius), add their wing values (the 2-node rule, or the 4-node rule inside the |z| < 40
-// radius) at kFarN nodes across it (far_kernel), interpolated to its points; the tile
-// kernel leaves them out.  Such a wing is a smooth rational function of the position with
-// its poles near the line centre.  The nodes are the Chebyshev points of the first kind on
-// [0, WW - 1] and the interpolant is the degree-15 polynomial through all of them
-// (barycentric form); with the nearest centre 0.57 (WW - 1) from the wavefront its error
-// stays below 2e-8 relative.
-constexpr int kFarN = 16;
-constexpr int far_reach(int ww) { return (57 * (ww - 1) + 99) / 100; }
-
-// Grid steps from w0 to node m of a wavefront of WW points, (WW - 1)(1 - cos(pi (2m + 1)/32))/2,
-// rounded to float (the position the node values are computed at).
-template <int WW>
-__device__ __forceinline__ float node_pos(int m) {
-    constexpr double u[kFarN] = {
-        0.0024076366639015356, 0.021529832133895588, 0.059039367825822475, 0.1134947733186315,
-        0.18280335791817726,   0.2643016315870011,   0.35485766137276886,  0.45099142983521961,
-        0.54900857016478033,   0.64514233862723103,  0.73569836841299885,  0.81719664208182263,
-        0.88650522668136844,   0.94096063217417747,  0.97847016786610441,  0.99759236333609835};
-    return (float)((double)(WW - 1) * u[m]);
-}
-
-// Weights at point o (0 .. WW-1) of the polynomial through the node values: the barycentric
-// form sum_m (c_m / (o - p_m)) f_m / sum_m (c_m / (o - p_m)) with c_m = 1 / prod_{k != m}
-// (p_m - p_k) for the node positions p_m as rounded (a node hit exactly takes its value).
-template <int WW>
-__device__ __forceinline__ void far_weights(int o, double (&w)[kFarN]) {
-    double c[kFarN];
-#pragma unroll
-    for (int m = 0; m < kFarN; ++m) {
-        double pr = 1.0;
-#pragma unroll
-        for (int k = 0; k < kFarN; ++k)
-            if (k != m) pr *= (double)node_pos<WW>(m) - (double)node_pos<WW>(k);
-        c[m] = 1.0 / pr;
-    }
-    double den = 0.0;
-    int hit = -1;
-#pragma unroll
-    for (int m = 0; m < kFarN; ++m) {
-        const double d = (double)o - (double)node_pos<WW>(m);
-        if (d == 0.0) hit = m;
-        w[m] = c[m] / (d == 0.0 ? 1.0 : d);
-        den += w[m];
-    }
-    const double inv = 1.0 / den;
-#pragma unroll
-    for (int m = 0; m < kFarN; ++m) w[m] = hit < 0 ? w[m] * inv : (m == hit ? 1.0 : 0.0);
-}
-
-// Radius (grid steps) of the |z| < 40 zone of the lines whose centre can lie near the
-// wavefront [w0, w1]: their wavenumbers, hence Doppler widths, are bounded there.
-__device__ __forceinline__ int wave_rm(const TPParam& tp, const Geometry& G, int w0, int w1) {
-    int rm = tp.rm;
-    if (tp.rm_scale > 0.0) {
-        const double nlo = G.nu_a + ((double)w0 - rm - 1) * G.dnu;
-        const double nhi = G.nu_a + ((double)w1 + rm + 1) * G.dnu;
-        const double rw = ceil(tp.rm_scale * fmax(fabs(nlo), fabs(nhi))) + 2.0;
-        if (rw < (double)rm) rm = __builtin_amdgcn_readfirstlane((int)rw);
-    }
-    return rm;
-}
-
-// Node-sampling radius of the wavefront [w0, w1]: the far reach, or the |z| < 8 radius of
-// the lines centred within max(reach, rm) of it where that is larger (every point of a
-// node-sampled line must lie outside its core).  At most tp.rm.
-__device__ __forceinline__ int wave_far_r(const TPParam& tp, const Geometry& G, int w0, int w1, int reach) {
-    int r8 = tp.rm;
-    if (tp.rm_scale > 0.0) {
-        const double span = (double)(reach > tp.rm ? reach : tp.rm) + 1.0;
-        const double nlo = G.nu_a + ((double)w0 - span) * G.dnu;
-        const double nhi = G.nu_a + ((double)w1 + span) * G.dnu;
-        const double rw = ceil(0.2 * tp.rm_scale * fmax(fabs(nlo), fabs(nhi))) + 2.0;
-        if (rw < (double)r8) r8 = (int)rw;
-    }
-    return __builtin_amdgcn_readfirstlane(r8 > reach ? r8 : reach);
-}
-
-// The lines whose window covers the wavefront [w0, w1] are [s1, s4) (w1 - hmin <= kc <=
-// w0 + hmin); of them, [s1, hcl) (kc < w0 - R) and [hcr, s4) (kc > w1 + R) are
-// node-sampled, R from wave_far_r, and of those [ml, hcl) and [hcr, mr) lie inside the
-// |z| < 40 radius rm (the 4-node rule).
-struct FarRange {
-    int s1, hcl, hcr, s4, ml, mr;
-};
-
-__device__ __forceinline__ FarRange far_range(const int* off, const Geometry& G, int w0, int w1, int rm, int R) {
-    const int64_t l0 = (int64_t)w1 - G.hmin, r1 = (int64_t)w0 + G.hmin + 1;
-    const int64_t hl = (int64_t)w0 - R > l0 ? (int64_t)w0 - R : l0;
-    const int64_t hr = (int64_t)w1 + R + 1 < r1 ? (int64_t)w1 + R + 1 : r1;
-    int64_t ml = (int64_t)w0 - rm, mr = (int64_t)w1 + rm + 1;
-    ml = ml < l0 ? l0 : (ml > hl ? hl : ml);
-    mr = mr > r1 ? r1 : (mr < hr ? hr : mr);
-    FarRange f;
-    f.s1 = off_at(off, l0, G);
-    f.s4 = off_at(off, r1, G);
-    f.hcl = off_at(off, hl, G);
-    f.hcr = off_at(off, hr, G);
-    f.ml = off_at(off, ml, G);
-    f.mr = off_at(off, mr, G);
-    return f;
-}
-
 template <int PROF, int WAVES, int P, bool SEG>
 __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
     constexpr int NT = 64 * WAVES;       // threads = lines per LDS batch
@@ -931,24 +807,14 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
                 // ---- run 3: centre near the wave
                 {
                     const int lo3 = cs > s2 ? cs : s2, hi3 = ce < s3 ? ce : s3;
-                    for (int l = lo3; l < hi3; ++l) {
-                        const int i = l - bs;
-                        const float* r = rec + i * RS;
-                        const float sb0 = S.sb0[i];
-                        if (PROF == kLorentz) {
-#pragma unroll
-                            for (int p = 0; p < P; ++p) part[p] += v_lor(r, jl[p] + sb0);
-                            continue;
-                        }
-                        if constexpr (PROF == kVoigt) {
-                            // record words in registers for every slice; each slice's rule adds
-                            // straight into its sum
-                            static_assert(L::H == 0 && L::C0 == 1 && L::C1 == 2 && L::AMP == 3 &&
-                                          L::B == 4 && L::XC == 5, "layout");
-                            const float4 q = *reinterpret_cast<const float4*>(r);
-                            const float2 q2 = *reinterpret_cast<const float2*>(r + L::B);
-                            const unsigned zc = (__builtin_amdgcn_readfirstlane(__float_as_uint(S.tf[zword * NT + i])) >> zshift) &
-                                                (P >= 16 ? 0xffffffffu : ((1u << (2 * P)) - 1u));
+                    if constexpr (PROF == kVoigt) {
+                        // record words in registers for every slice, two lines at a time (one
+                        // wait for both lines' LDS words); each slice's rule adds straight
+                        // into its sum
+                        static_assert(L::H == 0 && L::C0 == 1 && L::C1 == 2 && L::AMP == 3 && L::B == 4 &&
+                                      L::XC == 5, "layout");
+                        constexpr unsigned zmask = P >= 16 ? 0xffffffffu : ((1u << (2 * P)) - 1u);
+                        auto line3 = [&](int i, const float4 q, const float2 q2, float sb0, unsigned zc) {
                             if (zc == 0u) {
                                 // the mid zone (|z| < 40, which holds the core) misses the wave
 #pragma unroll
@@ -958,7 +824,7 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
                                     const float den = __builtin_fmaf(pp, pp, q.z);
                                     part[p] = __builtin_fmaf(__builtin_fmaf(pp, q.w, q2.x), __builtin_amdgcn_rcpf(den), part[p]);
                                 }
-                                continue;
+                                return;
                             }
                             const int kcl = S.kcl[i], kch = S.kch[i];
                             const float csc = S.csc[i];
@@ -984,6 +850,37 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
                                     part[p] = __builtin_fmaf(__builtin_fmaf(pp, q.w, q2.x), __builtin_amdgcn_rcpf(den), part[p]);
                                 }
                             }
+                        };
+                        auto zcode = [&](int i) {
+                            return (__builtin_amdgcn_readfirstlane(__float_as_uint(S.tf[zword * NT + i])) >> zshift) & zmask;
+                        };
+                        int l = lo3;
+                        for (; l + 1 < hi3; l += 2) {
+                            const int i = l - bs;
+                            const float* r = rec + i * RS;
+                            const float4 qa = *reinterpret_cast<const float4*>(r);
+                            const float2 qa2 = *reinterpret_cast<const float2*>(r + L::B);
+                            const float4 qb = *reinterpret_cast<const float4*>(r + RS);
+                            const float2 qb2 = *reinterpret_cast<const float2*>(r + RS + L::B);
+                            const float sa = S.sb0[i], sb = S.sb0[i + 1];
+                            const unsigned za = zcode(i), zb = zcode(i + 1);
+                            line3(i, qa, qa2, sa, za);
+                            line3(i + 1, qb, qb2, sb, zb);
+                        }
+                        if (l < hi3) {
+                            const int i = l - bs;
+                            const float* r = rec + i * RS;
+                            line3(i, *reinterpret_cast<const float4*>(r), *reinterpret_cast<const float2*>(r + L::B),
+                                  S.sb0[i], zcode(i));
+                        }
+                    } else
+                    for (int l = lo3; l < hi3; ++l) {
+                        const int i = l - bs;
+                        const float* r = rec + i * RS;
+                        const float sb0 = S.sb0[i];
+                        if (PROF == kLorentz) {
+#pragma unroll
+                            for (int p = 0; p < P; ++p) part[p] += v_lor(r, jl[p] + sb0);
                             continue;
                         }
                         // scalar copies of the line's integer geometry; distances from the
@@ -1138,356 +1035,6 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
     }
 }
 
-// Node-sampled Voigt far wing: one wavefront per (wavefront tile wv, (T, P), share q).  The
-// lines [s1, hcl) and [hcr, s4) (windows covering the wavefront, centres at least R away)
-// go in chunks q, q + far_share, ... of 64, one line per lane (the next chunk's line data
-// loaded while the current one is summed), first those beyond the |z| < 40 radius (2-node
-// rule, hot record only), then those inside it (4-node rule, with the coefficients of the
-// cold record), with FP64 sums per lane and node; then the wavefront's node totals,
-// interpolated to its points, go to far[tp][q][k] (every point of the wavefront, zeros
-// included).
-
-// wave-wide sum of v (every lane ends with the total)
-__device__ __forceinline__ double wave_total(double v) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-
-// the LDS words one lane wrote become visible to the other lanes of its wavefront
-__device__ __forceinline__ void wave_lds_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// 2-node value of a line (hot record h4 = {H, C0, C1, AMP}, h2 = {B, XC}) at x, amplitudes scaled by up
-__device__ __forceinline__ float far_value(const float4& h4, const float2& h2, float x, float up) {
-    const float pp = __builtin_fmaf(x, x, h4.y);
-    const float den = __builtin_fmaf(pp, pp, h4.z);
-    const float num = __builtin_fmaf(pp, h4.w * up, h2.x * up);
-    return num * __builtin_amdgcn_rcpf(den);
-}
-
-// 4-node value at unscaled x from the coefficients m0..m7 of the cold record (amplitudes
-// m2, m3, m6, m7 already scaled)
-__device__ __forceinline__ float far_value4(const float4& ma, const float4& mb, float x) {
-    const float p1 = __builtin_fmaf(x, x, ma.x);
-    const float p2 = __builtin_fmaf(x, x, mb.x);
-    const float d1 = __builtin_fmaf(p1, p1, ma.y);
-    const float d2 = __builtin_fmaf(p2, p2, mb.y);
-    const float n1 = __builtin_fmaf(p1, ma.z, ma.w);
-    const float n2 = __builtin_fmaf(p2, mb.z, mb.w);
-    return __builtin_fmaf(n1, __builtin_amdgcn_rcpf(d1), n2 * __builtin_amdgcn_rcpf(d2));
-}
-
-template <int P>
-__global__ __launch_bounds__(256) void far_kernel(const FwdArgs A, int n_waves) {
-    constexpr int WW = 64 * P;
-    using L = HotOf<kVoigt>;
-    static_assert(L::H == 0 && L::C0 == 1 && L::C1 == 2 && L::AMP == 3 && L::XC == L::B + 1, "layout");
-    static_assert(C_CSC == 0 && C_M == 8 && kCold == 16, "cold layout");
-    __shared__ double tl[4][kFarN];
-    const int lane = threadIdx.x & 63, wl = threadIdx.x >> 6;
-    const int64_t total = (int64_t)n_waves * A.n_tp * A.far_share;
-    const int64_t gw = (int64_t)blockIdx.x * 4 + wl;
-    if (gw >= total) return;   // whole wavefronts; no block barrier
-    const int q = (int)(gw % A.far_share);
-    const int64_t rest = gw / A.far_share;
-    const int it = (int)(rest % A.n_tp);
-    const int wv = (int)(rest / A.n_tp);
-    const Geometry G = A.G;
-    const TPParam tp = A.tps[it];
-    const int w0 = wv * WW, w1 = w0 + WW - 1;
-    const int* map = A.map ? A.map + (int64_t)it * A.map_stride : nullptr;
-    const int* off = A.offs ? A.offs + (int64_t)it * A.offs_stride : A.off;
-    const float* hot = A.hot + (int64_t)it * A.rec_stride * kHot;
-    const int* cold = A.cold + (int64_t)it * A.rec_stride * kCold;
-    const FarRange fr = far_range(off, G, w0, w1, wave_rm(tp, G, w0, w1), wave_far_r(tp, G, w0, w1, far_reach(WW)));
-    const int step = 64 * A.far_share;
-    // per lane and node: FP32 sums of up to four lines, added to FP64 sums; amplitudes
-    // scaled by 2^32 (exact) keep tiny values out of the single-precision subnormal range
-    constexpr float kUp = 4294967296.0f;
-    double acc[kFarN];
-    float a32[kFarN];
-#pragma unroll
-    for (int m = 0; m < kFarN; ++m) {
-        acc[m] = 0.0;
-        a32[m] = 0.0f;
-    }
-    int nacc = 0;
-    auto flush = [&]() {
-        if (++nacc == 4) {
-            nacc = 0;
-#pragma unroll
-            for (int m = 0; m < kFarN; ++m) {
-                acc[m] += (double)a32[m];
-                a32[m] = 0.0f;
-            }
-        }
-    };
-    {
-        // 2-node lines: [s1, ml) then [mr, s4)
-        const int nl = fr.ml - fr.s1, nv = nl + (fr.s4 - fr.mr);
-        // line data of entry v of the sequence: H, C0, C1, AMP; B, XC; kc
-        float4 h4 = make_float4(0.f, 0.f, 0.f, 0.f);
-        float2 h2 = make_float2(0.f, 0.f);
-        int kc = 0;
-        auto fetch = [&](int v) {
-            if (v < nv) {
-                const int l = v < nl ? fr.s1 + v : fr.mr + (v - nl);
-                h4 = *reinterpret_cast<const float4*>(hot + (int64_t)l * kHot);
-                h2 = *reinterpret_cast<const float2*>(hot + (int64_t)l * kHot + L::B);
-                kc = A.L.kc[line_of(map, l)];
-            }
-        };
-        fetch(64 * q + lane);
-        for (int c = 64 * q; c < nv; c += step) {
-            const bool in = c + lane < nv;
-            const float4 a4 = h4;
-            const float2 a2 = h2;
-            const int akc = kc;
-            fetch(c + step + lane);
-            if (in) {
-                const float x0 = __builtin_fmaf((float)(w0 - akc), a4.x, a2.y);   // x at w0
-#pragma unroll
-                for (int m = 0; m < kFarN; ++m)
-                    a32[m] += far_value(a4, a2, __builtin_fmaf(node_pos<WW>(m), a4.x, x0), kUp);
-            }
-            flush();
-        }
-    }
-    {
-        // 4-node lines (inside the |z| < 40 radius): [ml, hcl) then [hcr, mr)
-        const int nl = fr.hcl - fr.ml, nv = nl + (fr.mr - fr.hcr);
-        for (int c = 64 * q; c < nv; c += step) {
-            const int v = c + lane;
-            if (v < nv) {
-                const int l = v < nl ? fr.ml + v : fr.hcr + (v - nl);
-                const float2 hx = *reinterpret_cast<const float2*>(hot + (int64_t)l * kHot + L::B);   // B, XC
-                const float hh = hot[(int64_t)l * kHot + L::H];
-                const int4* cw = reinterpret_cast<const int4*>(cold + (int64_t)l * kCold);
-                const float csc = __int_as_float(cw[0].x);
-                const int4 qa = cw[2], qb = cw[3];
-                const float4 ma = make_float4(__int_as_float(qa.x), __int_as_float(qa.y),
-                                              __int_as_float(qa.z) * kUp, __int_as_float(qa.w) * kUp);
-                const float4 mb = make_float4(__int_as_float(qb.x), __int_as_float(qb.y),
-                                              __int_as_float(qb.z) * kUp, __int_as_float(qb.w) * kUp);
-                const int akc = A.L.kc[line_of(map, l)];
-                const float x0 = __builtin_fmaf((float)(w0 - akc), hh, hx.y);   // scaled x at w0
-#pragma unroll
-                for (int m = 0; m < kFarN; ++m)
-                    a32[m] += far_value4(ma, mb, __builtin_fmaf(node_pos<WW>(m), hh, x0) * csc);
-            }
-            flush();
-        }
-    }
-#pragma unroll
-    for (int m = 0; m < kFarN; ++m) acc[m] = wave_total((acc[m] + (double)a32[m]) * (1.0 / 4294967296.0));
-    if (lane == 0) {
-#pragma unroll
-        for (int m = 0; m < kFarN; ++m) tl[wl][m] = acc[m];
-    }
-    wave_lds_sync();
-    double* out = A.far + ((int64_t)it * A.far_slots + q) * G.n_points;
-#pragma unroll 1
-    for (int p = 0; p < P; ++p) {
-        const int o = 64 * p + lane;
-        double w[kFarN];
-        far_weights<WW>(o, w);
-        double v = 0.0;
-#pragma unroll
-        for (int m = 0; m < kFarN; ++m) v = __builtin_fma(w[m], tl[wl][m], v);
-        const int k = w0 + o;
-        if (k < G.n_points) out[k] = v;
-    }
-}
-
-// Window ends of the FP32 Voigt sweep (A.far_ends): the lines [s0, s1) whose cut-off window
-// ends inside a wavefront and [s4, s5) whose window starts inside it, all at least the far
-// reach (and the |z| < 40 radius) from every point of it.  One wavefront per (wavefront
-// tile, (T, P)); its result goes to far slot far_share.
-//
-// The wavefront is cut into NB blocks of BW points.  A left line whose window ends in block
-// b (its last point w0 + m, m clamped to the wavefront) covers blocks 0..b-1 whole: its
-// values at the kFarN nodes go to bucket b of the left side, and block c sees the sum of
-// the left buckets above it (a suffix sum).  Its points in block b itself (up to w0 + m)
-// are evaluated one by one.  Right lines mirror this (windows starting at w0 + m: prefix
-// sums, points from w0 + m).  A window clipped at the grid's last point counts as ending
-// there: the left bucket holding that point takes every left line up to s1 as candidate
-// (a window clipped at the first point starts in bucket 0 of the first wavefront, whose
-// candidates already reach down to s4).
-//
-// The buckets are walked in turn; the lanes take consecutive candidate lines of a bucket
-// (sorted by centre: a window end lies hmin..hmax steps from it, so a bucket's candidates
-// are a contiguous run), each keeping the node and point sums of its lines (FP32 over four
-// lines, then FP64), and the wavefront adds them up at the bucket's end.  Each point o
-// then takes the interpolation of its block's node values (suffix + prefix) over all nodes plus
-// its block's point sums.  Fixed order throughout: the result does not depend on the run.
-template <int P>
-struct EndsShape {
-    static constexpr int WW = 64 * P;
-    static constexpr int BW = P == 1 ? 4 : 8;      // points per block
-    static constexpr int NB = WW / BW;             // blocks per wavefront (32 or 16)
-};
-
-// wave-wide sum of a float (every lane ends with the total)
-__device__ __forceinline__ float wave_total_f(float v) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-
-template <int P>
-__global__ __launch_bounds__(256) void ends_kernel(const FwdArgs A, int n_waves) {
-    using ES = EndsShape<P>;
-    constexpr int WW = ES::WW, BW = ES::BW, NB = ES::NB;
-    using L = HotOf<kVoigt>;
-    static_assert(L::H == 0 && L::C0 == 1 && L::C1 == 2 && L::AMP == 3 && L::XC == L::B + 1, "layout");
-    __shared__ float eb[4][2][NB][kFarN];   // node sums per (side, block), scaled by 2^32
-    __shared__ float ep[4][WW];             // point sums of both sides, scaled by 2^32
-    const int lane = threadIdx.x & 63, wl = threadIdx.x >> 6;
-    const int64_t gw = (int64_t)blockIdx.x * 4 + wl;
-    if (gw >= (int64_t)n_waves * A.n_tp) return;   // whole wavefronts; no block barrier
-    const int it = (int)(gw % A.n_tp);
-    const int wv = (int)(gw / A.n_tp);
-    const Geometry G = A.G;
-    const int w0 = wv * WW, w1 = w0 + WW - 1;
-    const int* map = A.map ? A.map + (int64_t)it * A.map_stride : nullptr;
-    const int* off = A.offs ? A.offs + (int64_t)it * A.offs_stride : A.off;
-    const float* hot = A.hot + (int64_t)it * A.rec_stride * kHot;
-    const int s0 = off_at(off, (int64_t)w0 - G.hmax, G), s1 = off_at(off, (int64_t)w1 - G.hmin, G);
-    const int s4 = off_at(off, (int64_t)w0 + G.hmin + 1, G), s5 = off_at(off, (int64_t)w1 + G.hmax + 1, G);
-    constexpr float kUp = 4294967296.0f;
-    for (int o = lane; o < WW; o += 64) ep[wl][o] = 0.0f;
-    wave_lds_sync();
-    for (int side = 0; side < 2; ++side) {
-        for (int b = 0; b < NB; ++b) {
-            // candidate lines of bucket b (uniform)
-            const int64_t e0 = (int64_t)w0 + b * BW, e1 = e0 + BW - 1;
-            int r0, r1;
-            if (side == 0) {
-                const bool last = e0 <= (int64_t)G.n_points - 1 && (int64_t)G.n_points - 1 <= e1;
-                r0 = off_at(off, e0 - G.hmax, G);
-                r1 = last ? s1 : off_at(off, e1 - G.hmin + 1, G);
-                r0 = r0 > s0 ? r0 : s0;
-                r1 = r1 < s1 ? r1 : s1;
-            } else {
-                r0 = off_at(off, e0 + G.hmin, G);
-                r1 = off_at(off, e1 + G.hmax + 1, G);
-                r0 = r0 > s4 ? r0 : s4;
-                r1 = r1 < s5 ? r1 : s5;
-            }
-            float n32[kFarN], p32[BW];
-            double n64[kFarN], p64[BW];
-#pragma unroll
-            for (int m = 0; m < kFarN; ++m) { n32[m] = 0.0f; n64[m] = 0.0; }
-#pragma unroll
-            for (int j = 0; j < BW; ++j) { p32[j] = 0.0f; p64[j] = 0.0; }
-            int nacc = 0;
-            // line data of the lane's next line (loaded while the current one is summed):
-            // H, C0, C1, AMP; B, XC; kc; window end relative to w0 (-1: none here)
-            float4 h4 = make_float4(0.f, 0.f, 0.f, 0.f);
-            float2 h2 = make_float2(0.f, 0.f);
-            int hkc = 0, hm = -1;
-            auto fetch = [&](int l) {
-                hm = -1;
-                if (l < r1) {
-                    const int g = line_of(map, l);
-                    h4 = *reinterpret_cast<const float4*>(hot + (int64_t)l * kHot);
-                    h2 = *reinterpret_cast<const float2*>(hot + (int64_t)l * kHot + L::B);
-                    hkc = A.L.kc[g];
-                    if (side == 0) {
-                        const int e = A.L.khi[g] - w0;
-                        hm = e < 0 ? -1 : (e > WW - 1 ? WW - 1 : e);
-                    } else {
-                        const int e = A.L.klo[g] - w0;
-                        hm = e > WW - 1 ? -1 : (e < 0 ? 0 : e);
-                    }
-                }
-            };
-            fetch(r0 + lane);
-            for (int c = r0; c < r1; c += 64) {
-                {
-                    const float4 a4 = h4;
-                    const float2 a2 = h2;
-                    const int akc = hkc, m = hm;
-                    fetch(c + 64 + lane);
-                    if (m >= 0 && m / BW == b) {
-                        const float x0 = __builtin_fmaf((float)(w0 - akc), a4.x, a2.y);   // x at w0
-#pragma unroll
-                        for (int mm = 0; mm < kFarN; ++mm)
-                            n32[mm] += far_value(a4, a2, __builtin_fmaf(node_pos<WW>(mm), a4.x, x0), kUp);
-                        const int j0 = m - b * BW;   // the window's end within the block
-#pragma unroll
-                        for (int j = 0; j < BW; ++j) {
-                            const bool cover = side == 0 ? (j <= j0) : (j >= j0);
-                            const float v = far_value(a4, a2, __builtin_fmaf((float)(b * BW + j), a4.x, x0), kUp);
-                            p32[j] += cover ? v : 0.0f;
-                        }
-                    }
-                }
-                if (++nacc == 4) {
-                    nacc = 0;
-#pragma unroll
-                    for (int mm = 0; mm < kFarN; ++mm) { n64[mm] += (double)n32[mm]; n32[mm] = 0.0f; }
-#pragma unroll
-                    for (int j = 0; j < BW; ++j) { p64[j] += (double)p32[j]; p32[j] = 0.0f; }
-                }
-            }
-            // the bucket's totals (single-precision tree over the lanes' sums)
-            float* bucket = eb[wl][side][b];
-            if (r1 > r0) {
-#pragma unroll
-                for (int mm = 0; mm < kFarN; ++mm) {
-                    const float t = wave_total_f((float)(n64[mm] + (double)n32[mm]));
-                    if (lane == 0) bucket[mm] = t;
-                }
-#pragma unroll
-                for (int j = 0; j < BW; ++j) {
-                    const float t = wave_total_f((float)(p64[j] + (double)p32[j]));
-                    if (lane == j) ep[wl][b * BW + j] += t;
-                }
-            } else if (lane < kFarN) {
-                bucket[lane] = 0.0f;
-            }
-        }
-    }
-    wave_lds_sync();
-    // left buckets become suffix sums (the lines covering the blocks below them), right
-    // buckets prefix sums; one node per lane
-    if (lane < kFarN) {
-        double run = 0.0;
-        for (int c = NB - 1; c >= 0; --c) {
-            const double v = (double)eb[wl][0][c][lane];
-            eb[wl][0][c][lane] = (float)run;
-            run += v;
-        }
-        run = 0.0;
-        for (int c = 0; c < NB; ++c) {
-            const double v = (double)eb[wl][1][c][lane];
-            eb[wl][1][c][lane] = (float)run;
-            run += v;
-        }
-    }
-    wave_lds_sync();
-    double* out = A.far + ((int64_t)it * A.far_slots + A.far_share) * G.n_points;
-    constexpr double kDown = 1.0 / 4294967296.0;
-#pragma unroll
-    for (int p = 0; p < P; ++p) {
-        const int o = 64 * p + lane;
-        const int blk = o / BW;
-        double w[kFarN];
-        far_weights<WW>(o, w);
-        double v = 0.0;
-#pragma unroll
-        for (int m = 0; m < kFarN; ++m)
-            v = __builtin_fma(w[m], (double)eb[wl][0][blk][m] + (double)eb[wl][1][blk][m], v);
-        const int k = w0 + o;
-        if (k < G.n_points) out[k] = (v + (double)ep[wl][o]) * kDown;
-    }
-}
-
 template <int PROF, int WAVES, int P>
 void launch_one(const FwdArgs& a, hipStream_t s) {
     const dim3 grid((unsigned)((int64_t)a.n_tiles * a.n_tp * a.n_split)), block(64 * WAVES);
@@ -1542,30 +1089,6 @@ hipError_t launch_records(int profile, const RecArgs& a, hipStream_t s) {
         case kDopplerBinned: hipLaunchKernelGGL(record_kernel<kDopplerBinned>, grid, block, 0, s, a); break;
         case kLorentzBinned: hipLaunchKernelGGL(record_kernel<kLorentzBinned>, grid, block, 0, s, a); break;
         default: hipLaunchKernelGGL(record_kernel<kVoigt>, grid, block, 0, s, a); break;
-    }
-    return hipGetLastError();
-}
-
-hipError_t launch_far(int waves, int P, const FwdArgs& a, hipStream_t s) {
-    if (a.n_tiles <= 0 || !a.far || !a.seg) return hipSuccess;
-    const int n_waves = a.n_tiles * waves;
-    const int64_t total = (int64_t)n_waves * a.n_tp * a.far_share;
-    const dim3 grid((unsigned)((total + 3) / 4)), block(256);
-    switch (P) {
-        case 1: hipLaunchKernelGGL(far_kernel<1>, grid, block, 0, s, a, n_waves); break;
-        case 2: hipLaunchKernelGGL(far_kernel<2>, grid, block, 0, s, a, n_waves); break;
-        case 8: hipLaunchKernelGGL(far_kernel<8>, grid, block, 0, s, a, n_waves); break;
-        default: hipLaunchKernelGGL(far_kernel<4>, grid, block, 0, s, a, n_waves); break;
-    }
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess || !a.far_ends) return e;
-    const int64_t ends = (int64_t)n_waves * a.n_tp;
-    const dim3 grid_e((unsigned)((ends + 3) / 4));
-    switch (P) {
-        case 1: hipLaunchKernelGGL(ends_kernel<1>, grid_e, block, 0, s, a, n_waves); break;
-        case 2: hipLaunchKernelGGL(ends_kernel<2>, grid_e, block, 0, s, a, n_waves); break;
-        case 8: hipLaunchKernelGGL(ends_kernel<8>, grid_e, block, 0, s, a, n_waves); break;
-        default: hipLaunchKernelGGL(ends_kernel<4>, grid_e, block, 0, s, a, n_waves); break;
     }
     return hipGetLastError();
 }
