@@ -126,7 +126,8 @@ struct Workset {
     DevBuf th_bsum, th_tmp;   // intensity threshold: block counts, scan scratch per row
     DevBuf th_pos, th_map, th_offs;   // per row: positions [n+1], kept lines [n], offsets [nkeys+1]
     DevBuf part;              // per-part sums [tp_block][n_split][n_points] when n_split > 1
-    DevBuf far;               // FP32 Voigt: node-sampled far-wing sums [tp_block][kFarShares + 1][n_points]
+    DevBuf far;               // FP32 Voigt: node-sampled far-wing sums [tp_block][2][n_points]
+    DevBuf far_nodes;         // FP32 Voigt: far kernel node totals [tp_block][waves][16][kFarShares]
     DevBuf out;               // autotuner output scratch
     size_t bytes = 0;
     Stage stage;
@@ -136,7 +137,7 @@ struct Workset {
     xs_status ensure(DevBuf& b, size_t n, const char* what) { return dev_ensure(b, n, what, &bytes); }
     void release() {
         DevBuf* all[] = {&T, &Q, &dQ, &qpart, &tps, &rc, &cnt, &coff, &bsum, &tmp, &val, &hot, &cold, &xscale,
-                         &vv, &sl, &th_bsum, &th_tmp, &th_pos, &th_map, &th_offs, &part, &far, &out};
+                         &vv, &sl, &th_bsum, &th_tmp, &th_pos, &th_map, &th_offs, &part, &far, &far_nodes, &out};
         for (DevBuf* b : all) dev_release(*b, &bytes);
         stage.release();
         rows = 0;
@@ -424,8 +425,8 @@ xs::TPParam make_tp(const xs_plan* p, double T, double P, int iq, double T_rm) {
 bool vv_needed(const xs_plan* p) { return is_vv(p) && (p->o.vv_beta || p->o.profile == XS_VVOIGT_NORM); }
 
 // FP32 Voigt: the segmented sweep leaves lines far from a wavefront to the node-sampled
-// far-wing kernel, whose per-share sums need a buffer of at most kFarShares shares
-constexpr int kFarShares = 8;
+// far-wing kernel, whose per-share node totals need a buffer of at most kFarShares shares
+constexpr int kFarShares = 256;
 // grid steps between a wavefront of ww points and the nearest node-sampled line centre (the
 // kernels' far_reach: 0.57 (ww - 1), rounded up, for the 16 Chebyshev nodes across it)
 int far_reach_steps(int ww) { return (57 * (ww - 1) + 99) / 100; }
@@ -556,8 +557,10 @@ xs_status ensure_rows(xs_plan* p, Workset& ws, int B, int S) {
         XS_TRY(ws.ensure(ws.part, (size_t)B * S * (size_t)p->geo.n_points * elem, "split partial sums"));
     }
     if (far_sampled(p)) {
-        XS_TRY(ws.ensure(ws.far, (size_t)B * (kFarShares + 1) * (size_t)p->geo.n_points * sizeof(double),
-                         "far-wing sums"));
+        XS_TRY(ws.ensure(ws.far, (size_t)B * 2 * (size_t)p->geo.n_points * sizeof(double), "far-wing sums"));
+        // wavefronts of 64 points or more over the grid, a whole tile of them past its end
+        const size_t waves = (size_t)p->geo.n_points / 64 + 2 + 8;
+        XS_TRY(ws.ensure(ws.far_nodes, (size_t)B * waves * 16 * kFarShares * sizeof(double), "far-wing node sums"));
     }
     return XS_OK;
 }
@@ -640,10 +643,12 @@ xs::FwdArgs fwd_args(xs_plan* p, Workset& ws, const std::vector<xs::TPParam>& tp
         a.line_S_stride = ws.row_stride;
     }
     if (far_sampled(p) && a.seg && records_path(p)) {
-        // enough wavefronts to fill the chip: shares of the far lines of each wavefront
-        const int64_t nw = std::max<int64_t>(1, (int64_t)a.n_tiles * p->waves * nb);
+        // shares of each wavefront's far lines, about 16 lines per lane each: many short
+        // wavefronts spread the far wing evenly over the chip (at most kFarShares)
+        const double per_wave = (double)p->n_kept * (2.0 * p->geo.hmin + 64.0 * p->P) / std::max(1, p->geo.nkeys);
         a.far = as<double>(ws.far);
-        a.far_share = (int)std::min<int64_t>(kFarShares, std::max<int64_t>(1, (32768 + nw - 1) / nw));
+        a.far_nodes = as<double>(ws.far_nodes);
+        a.far_share = (int)std::min<double>(kFarShares, std::max(1.0, std::ceil(per_wave / 1024.0)));
         // the window ends go to the far kernel too when every window-end line lies beyond both
         // the far reach and the |z| < 40 radius of any wavefront it ends in: such lines are
         // at least hmin - WW + 2 steps from it
@@ -651,7 +656,7 @@ xs::FwdArgs fwd_args(xs_plan* p, Workset& ws, const std::vector<xs::TPParam>& tp
         int rm = 0;
         for (int t = f; t < f + nb; ++t) rm = std::max(rm, tps[t].rm);
         a.far_ends = (int64_t)p->geo.hmin - WW + 2 >= (int64_t)std::max(far_reach_steps(WW), rm) ? 1 : 0;
-        a.far_slots = a.far_share + a.far_ends;
+        a.far_slots = 1 + a.far_ends;
     }
     return a;
 }

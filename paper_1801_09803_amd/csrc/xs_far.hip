@@ -16,9 +16,8 @@ namespace {
 // go in chunks q, q + far_share, ... of 64, one line per lane (the next chunk's line data
 // loaded while the current one is summed), first those beyond the |z| < 40 radius (2-node
 // rule, hot record only), then those inside it (4-node rule, with the coefficients of the
-// cold record), with FP64 sums per lane and node; then the wavefront's node totals,
-// interpolated to its points, go to far[tp][q][k] (every point of the wavefront, zeros
-// included).
+// cold record), with FP64 sums per lane and node; the share's node totals go to
+// far_nodes[tp][wave][node][share], for far_finish_kernel to add up and interpolate.
 
 // wave-wide sum of v (every lane ends with the total)
 __device__ __forceinline__ double wave_total(double v) {
@@ -60,7 +59,6 @@ __global__ __launch_bounds__(256) void far_kernel(const FwdArgs A, int n_waves) 
     using L = HotOf<kVoigt>;
     static_assert(L::H == 0 && L::C0 == 1 && L::C1 == 2 && L::AMP == 3 && L::XC == L::B + 1, "layout");
     static_assert(C_CSC == 0 && C_M == 8 && kCold == 16, "cold layout");
-    __shared__ double tl[4][kFarN];
     const int lane = threadIdx.x & 63, wl = threadIdx.x >> 6;
     const int64_t total = (int64_t)n_waves * A.n_tp * A.far_share;
     const int64_t gw = (int64_t)blockIdx.x * 4 + wl;
@@ -77,7 +75,6 @@ __global__ __launch_bounds__(256) void far_kernel(const FwdArgs A, int n_waves) 
     const float* hot = A.hot + (int64_t)it * A.rec_stride * kHot;
     const int* cold = A.cold + (int64_t)it * A.rec_stride * kCold;
     const FarRange fr = far_range(off, G, w0, w1, wave_rm(tp, G, w0, w1), wave_far_r(tp, G, w0, w1, far_reach(WW)));
-    const int step = 64 * A.far_share;
     // per lane and node: FP32 sums of up to four lines, added to FP64 sums; amplitudes
     // scaled by 2^32 (exact) keep tiny values out of the single-precision subnormal range
     constexpr float kUp = 4294967296.0f;
@@ -114,6 +111,8 @@ __global__ __launch_bounds__(256) void far_kernel(const FwdArgs A, int n_waves) 
                 kc = A.L.kc[line_of(map, l)];
             }
         };
+        // this share's chunks of 64 lines: q, q + far_share, ...
+        const int step = 64 * A.far_share;
         fetch(64 * q + lane);
         for (int c = 64 * q; c < nv; c += step) {
             const bool in = c + lane < nv;
@@ -133,7 +132,7 @@ __global__ __launch_bounds__(256) void far_kernel(const FwdArgs A, int n_waves) 
     {
         // 4-node lines (inside the |z| < 40 radius): [ml, hcl) then [hcr, mr)
         const int nl = fr.hcl - fr.ml, nv = nl + (fr.mr - fr.hcr);
-        for (int c = 64 * q; c < nv; c += step) {
+        for (int c = 64 * q; c < nv; c += 64 * A.far_share) {
             const int v = c + lane;
             if (v < nv) {
                 const int l = v < nl ? fr.ml + v : fr.hcr + (v - nl);
@@ -155,14 +154,37 @@ __global__ __launch_bounds__(256) void far_kernel(const FwdArgs A, int n_waves) 
             flush();
         }
     }
+    // this share's node totals: node m from lane m
+    double mine = 0.0;
 #pragma unroll
-    for (int m = 0; m < kFarN; ++m) acc[m] = wave_total((acc[m] + (double)a32[m]) * (1.0 / 4294967296.0));
-    if (lane == 0) {
-#pragma unroll
-        for (int m = 0; m < kFarN; ++m) tl[wl][m] = acc[m];
+    for (int m = 0; m < kFarN; ++m) {
+        const double t = wave_total((acc[m] + (double)a32[m]) * (1.0 / 4294967296.0));
+        mine = lane == m ? t : mine;
+    }
+    if (lane < kFarN) A.far_nodes[(((int64_t)it * n_waves + wv) * kFarN + lane) * A.far_share + q] = mine;
+}
+
+// The far kernel's node totals of each wavefront, summed over its shares in share order,
+// interpolated to the wavefront's points into far slot 0.  One wavefront per (wavefront
+// tile, (T, P)).
+template <int P>
+__global__ __launch_bounds__(256) void far_finish_kernel(const FwdArgs A, int n_waves) {
+    constexpr int WW = 64 * P;
+    __shared__ double tl[4][kFarN];
+    const int lane = threadIdx.x & 63, wl = threadIdx.x >> 6;
+    const int64_t gw = (int64_t)blockIdx.x * 4 + wl;
+    if (gw >= (int64_t)n_waves * A.n_tp) return;   // whole wavefronts; no block barrier
+    const int it = (int)(gw % A.n_tp);
+    const int wv = (int)(gw / A.n_tp);
+    const int w0 = wv * WW;
+    if (lane < kFarN) {
+        const double* nd = A.far_nodes + (((int64_t)it * n_waves + wv) * kFarN + lane) * A.far_share;
+        double v = 0.0;
+        for (int q = 0; q < A.far_share; ++q) v += nd[q];
+        tl[wl][lane] = v;
     }
     wave_lds_sync();
-    double* out = A.far + ((int64_t)it * A.far_slots + q) * G.n_points;
+    double* out = A.far + (int64_t)it * A.far_slots * A.G.n_points;
 #pragma unroll 1
     for (int p = 0; p < P; ++p) {
         const int o = 64 * p + lane;
@@ -172,14 +194,14 @@ __global__ __launch_bounds__(256) void far_kernel(const FwdArgs A, int n_waves) 
 #pragma unroll
         for (int m = 0; m < kFarN; ++m) v = __builtin_fma(w[m], tl[wl][m], v);
         const int k = w0 + o;
-        if (k < G.n_points) out[k] = v;
+        if (k < A.G.n_points) out[k] = v;
     }
 }
 
 // Window ends of the FP32 Voigt sweep (A.far_ends): the lines [s0, s1) whose cut-off window
 // ends inside a wavefront and [s4, s5) whose window starts inside it, all at least the far
 // reach (and the |z| < 40 radius) from every point of it.  One wavefront per (wavefront
-// tile, (T, P)); its result goes to far slot far_share.
+// tile, (T, P)); its result goes to far slot 1.
 //
 // The wavefront is cut into NB blocks of BW points.  A left line whose window ends in block
 // b (its last point w0 + m, m clamped to the wavefront) covers blocks 0..b-1 whole: its
@@ -344,7 +366,7 @@ __global__ __launch_bounds__(256) void ends_kernel(const FwdArgs A, int n_waves)
         }
     }
     wave_lds_sync();
-    double* out = A.far + ((int64_t)it * A.far_slots + A.far_share) * G.n_points;
+    double* out = A.far + ((int64_t)it * A.far_slots + 1) * G.n_points;
     constexpr double kDown = 1.0 / 4294967296.0;
 #pragma unroll
     for (int p = 0; p < P; ++p) {
@@ -375,6 +397,16 @@ hipError_t launch_far(int waves, int P, const FwdArgs& a, hipStream_t s) {
         default: hipLaunchKernelGGL(far_kernel<4>, grid, block, 0, s, a, n_waves); break;
     }
     hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t fin = (int64_t)n_waves * a.n_tp;
+    const dim3 grid_f((unsigned)((fin + 3) / 4));
+    switch (P) {
+        case 1: hipLaunchKernelGGL(far_finish_kernel<1>, grid_f, block, 0, s, a, n_waves); break;
+        case 2: hipLaunchKernelGGL(far_finish_kernel<2>, grid_f, block, 0, s, a, n_waves); break;
+        case 8: hipLaunchKernelGGL(far_finish_kernel<8>, grid_f, block, 0, s, a, n_waves); break;
+        default: hipLaunchKernelGGL(far_finish_kernel<4>, grid_f, block, 0, s, a, n_waves); break;
+    }
+    e = hipGetLastError();
     if (e != hipSuccess || !a.far_ends) return e;
     const int64_t ends = (int64_t)n_waves * a.n_tp;
     const dim3 grid_e((unsigned)((ends + 3) / 4));

@@ -81,10 +81,12 @@ struct FwdArgs {
     const int* offs;
     int64_t offs_stride;
     // FP32 Voigt segmented sweep: node-sampled far-wing sums, FP64 [n_tp][far_slots][n_points]:
-    // slots 0 .. far_share-1 from far_kernel's shares, slot far_share (with far_ends) from
-    // ends_kernel; added by launch_combine.  NULL: the tile kernel sums every line
+    // slot 0 the interpolated node sums of far_kernel, slot 1 (with far_ends) ends_kernel's;
+    // added by launch_combine.  NULL: the tile kernel sums every line
     double* far;
-    int far_share;
+    // far_kernel's node totals per share, FP64 [n_tp][waves of the launch][16][far_share]
+    double* far_nodes;
+    int far_share;          // far_kernel wavefronts per tile wavefront
     int far_slots;
     // with far: the window-end runs (windows ending or starting inside a wavefront) are
     // node-sampled by ends_kernel (every such line lies beyond the far reach and the |z| < 40
