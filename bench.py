@@ -173,20 +173,20 @@ def zone_counts_multi(cfg, d, tps, waves=None, slices=None, chunk=1 << 24):
         del cache
     return tots
 
-# HBM traffic of the dominant kernel from two rocprofv3 --pmc runs of this script with
-# the tile configuration fixed (1 wave, 4 slices, 64 shares, one (T, P) per dispatch):
-# FETCH_SIZE, then WRITE_SIZE, KiB per dispatch at T = 296 K and 2000 K, scaled by the
-# same counters on a 1 GiB device copy (FETCH_SIZE reads 0.5 GiB -> x2, WRITE_SIZE 1 GiB
-# -> x1).  Per (T, P); a launch covering several (T, P) moves that many times the bytes.
-# Valid only for the kernel sources they were taken with (hash below).
+# HBM traffic of the dominant kernel (the tile kernel) from two rocprofv3 --pmc runs of this
+# script with the tile configuration fixed (1 wave, 4 slices, 32 shares): FETCH_SIZE, then
+# WRITE_SIZE, KiB per dispatch, scaled by the same counters on a 1 GiB device copy
+# (FETCH_SIZE reads 0.5 GiB -> x2, WRITE_SIZE 1 GiB -> x1).  C5: one (T, P) per dispatch,
+# averaged over the 36 of one 2^28-line chunk; C2: both (T, P) in one dispatch.  Valid only
+# for the kernel sources they were taken with (hash below).
 TRAFFIC = {
     "kernel_sources": ['xs_forward_f32.hip', 'xs_records.hpp', 'xs_far.hpp', 'xs_forward_common.hpp', 'xs_voigt.hpp',
                        'xs_forward.hpp', 'xs_internal.hpp'],
-    "sha256": "76f9640d216b506155f16f059aecf9bcb05ea2f4576b0fb8d86ab017ed93694a",
-    "fetch_kib": [57698035.0, 63831122.2],
-    "write_kib": [506985.5, 506790.2],
+    "sha256": "bced1905a96d10a4d71251d4486051aa2c19792588964d9969925d098351b11e",
     "fetch_scale": 2.0,
     "write_scale": 1.0,
+    "C5": {"fetch_kib": 45091500.0, "write_kib": 303613.0, "tp_per_dispatch": 1},
+    "C2": {"fetch_kib": 28259300.0, "write_kib": 506729.0, "tp_per_dispatch": 2},
 }
 
 
@@ -199,12 +199,17 @@ def kernel_sources_sha():
     return h.hexdigest()
 
 
-def traffic_bytes_per_launch(tp_per_launch):
-    if TRAFFIC["sha256"] is None or TRAFFIC["sha256"] != kernel_sources_sha():
+def traffic_bytes_per_launch(workload, tp_per_launch):
+    """HBM bytes per tile-kernel launch of tp_per_launch (T, P) on the workload (C5 or C2),
+    or None when the kernel sources changed since the counters were taken."""
+    if TRAFFIC["sha256"] is None or TRAFFIC["sha256"] != kernel_sources_sha() or workload not in TRAFFIC:
         return None
-    f = sum(TRAFFIC["fetch_kib"]) / len(TRAFFIC["fetch_kib"]) * TRAFFIC["fetch_scale"]
-    w = sum(TRAFFIC["write_kib"]) / len(TRAFFIC["write_kib"]) * TRAFFIC["write_scale"]
-    return (f + w) * 1024.0 * tp_per_launch
+    t = TRAFFIC[workload]
+    per_tp = (t["fetch_kib"] * TRAFFIC["fetch_scale"] + t["write_kib"] * TRAFFIC["write_scale"]) * 1024.0 \
+        / t["tp_per_dispatch"]
+    return per_tp * tp_per_launch
+
+
 PEAK_FP32_TFLOPS = 157.3     # MI355X FP32 vector peak (published, packed)
 PEAK_FP32_UNPACKED = 78.6    # 256 CU x 64 lanes x 2 flop x 2.4 GHz without packed FP32
 
@@ -469,7 +474,7 @@ def c5_run(args):
             "peak": PEAK_FP32_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_TFLOPS,
-            "traffic": traffic_bytes_per_launch(kt["forward_tp"] / kt["forward_launches"]),
+            "traffic": traffic_bytes_per_launch("C5", kt["forward_tp"] / kt["forward_launches"]),
             "kernel": "fwd_f32_kernel<Voigt> (tile kernel, one launch per block of (T,P) per chunk)",
             "avg_launch_ms": avg_launch_s * 1e3,
             "launches": kt["forward_launches"],
@@ -653,7 +658,7 @@ def c2_run(args, workload="C2", with_baseline=False, steps=3, warmup=1):
             "peak": PEAK_FP32_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_TFLOPS,
-            "traffic": traffic_bytes_per_launch(tp_per_launch),
+            "traffic": traffic_bytes_per_launch(workload, tp_per_launch),
             "kernel": "fwd_f32_kernel<Voigt> (tile kernel, one launch per block of (T,P))",
             "avg_launch_ms": avg_launch_s * 1e3,
             "tp_per_launch": tp_per_launch,
