@@ -462,8 +462,9 @@ typedef struct {
     double combine_ms;          /* sums of split tiles (n_split > 1)                       */
     int64_t combine_launches;
     int64_t forward_tp;         /* (T, P) results computed by the forward launches         */
-    double far_ms;              /* FP32 Voigt: node-sampled far-wing kernel (one launch per
-                                   forward launch of the segmented sweep)                  */
+    double far_ms;              /* FP32 Voigt: node-sampled far wing and window ends (far,
+                                   finish and ends kernels, one set per forward launch of
+                                   the segmented sweep)                                     */
     int64_t far_launches;
 } xs_timings;
 
