@@ -229,24 +229,27 @@ __global__ __launch_bounds__(256) void record_kernel(const RecArgs A) {
 // segmented sweep one anchor per wavefront, so a wing-loop line is read from one base
 // address), the grid offset, slice codes (coded sweep) and the cold fields (one array
 // per field, indexed by the line's place in the batch).
-template <int NT, int RS, int NTF, int NM>
+template <int NT, int RS, int NTF, int NM, int NKR = NT, int NCK = NT>
 struct Lds {
     float4 rec[NT * RS / 4];
     float sb0[NT];          // t0 - kc
-    float tf[NTF];          // slice-code words (coded sweep: NCW per line, stride NT)
-    float csc[NT];
-    int kc[NT], rad[NT], kcl[NT], kch[NT];
+    float tf[NTF];          // slice-code words (coded sweep: NCW per line, stride NT; Voigt
+                            // segmented sweep: 2-bit rule codes)
+    float csc[NCK];         // x scale and core range (in the record's spare words when it
+    int kcl[NCK], kch[NCK]; // has three, see CK_IN_REC)
+    int kc[NKR], rad[NKR];  // centre and mid radius (not staged where rule codes replace them)
     long long cb[NT];
     float m[NM * NT];       // cold profile words (stride NT)
 };
 // segmented sweep: no slice codes (keeps the Vectorized Voigt image at 32 KiB, five
 // workgroups per CU)
-template <int NT, int RS, int NM>
-struct Lds<NT, RS, 0, NM> {
+template <int NT, int RS, int NM, int NKR, int NCK>
+struct Lds<NT, RS, 0, NM, NKR, NCK> {
     float4 rec[NT * RS / 4];
     float sb0[NT];
-    float csc[NT];
-    int kc[NT], rad[NT], kcl[NT], kch[NT];
+    float csc[NCK];
+    int kcl[NCK], kch[NCK];
+    int kc[NKR], rad[NKR];
     long long cb[NT];
     float m[NM * NT];
 };
@@ -491,7 +494,7 @@ __device__ __forceinline__ Prefetch<NQ> load_batch(const FwdArgs& A, const int* 
 }
 
 template <int PROF, int WAVES, int P, bool SEG>
-__global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
+__global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(6))) void fwd_f32_kernel(const FwdArgs A) {
     constexpr int NT = 64 * WAVES;       // threads = lines per LDS batch
     constexpr int W = NT * P;            // grid points per tile
     constexpr int WW = 64 * P;           // grid points per wavefront
@@ -514,7 +517,11 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
     // cold profile words in LDS
     constexpr int NM = is_voigt(PROF) ? 8 : (PROF == kGHSampled || PROF == kGHBinned) ? 5
                        : PROF == kDopplerBinned ? 4 : PROF == kLorentzBinned ? 6 : 2;
-    __shared__ Lds<NT, RS, NTF, NM> S;
+    // Voigt segmented sweep whose LDS record has three spare words after the anchors: the
+    // x scale and core range go there (a smaller image, more resident workgroups)
+    constexpr bool CK_IN_REC = ZC && RS - RH - WAVES >= 3;
+    constexpr int CKW = RH + WAVES;   // first spare word
+    __shared__ Lds<NT, RS, NTF, NM, ZC ? 1 : NT, CK_IN_REC ? 1 : NT> S;
 
     const Geometry G = A.G;
     // the wavefront index is uniform within a wavefront: keep it (and everything derived
@@ -645,11 +652,20 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
             if (near) {
                 const int4* cg = gcold + (int64_t)g * (kCold / 4);
                 const int4 q0 = cg[0], q1 = cg[1], q2 = cg[2], q3 = cg[3];
-                S.csc[tid] = __int_as_float(q0.x);
-                S.kc[tid] = q0.y;
-                S.rad[tid] = q0.z;
-                S.kcl[tid] = q0.w;
-                S.kch[tid] = q1.x;
+                if constexpr (CK_IN_REC) {
+                    float* rw = reinterpret_cast<float*>(S.rec) + tid * RS + CKW;
+                    rw[0] = __int_as_float(q0.x);
+                    rw[1] = __int_as_float(q0.w);
+                    rw[2] = __int_as_float(q1.x);
+                } else {
+                    S.csc[tid] = __int_as_float(q0.x);
+                    S.kcl[tid] = q0.w;
+                    S.kch[tid] = q1.x;
+                }
+                if constexpr (!ZC) {
+                    S.kc[tid] = q0.y;
+                    S.rad[tid] = q0.z;
+                }
                 S.cb[tid] = (long long)(((unsigned long long)(unsigned)q1.w << 32) | (unsigned)q1.z);
                 S.m[0 * NT + tid] = __int_as_float(q2.x);
                 S.m[1 * NT + tid] = __int_as_float(q2.y);
@@ -826,8 +842,10 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_f32_kernel(const FwdArgs A) {
                                 }
                                 return;
                             }
-                            const int kcl = S.kcl[i], kch = S.kch[i];
-                            const float csc = S.csc[i];
+                            const float* rr = rec + i * RS;
+                            const int kcl = CK_IN_REC ? __float_as_int(rr[CKW + 1]) : S.kcl[CK_IN_REC ? 0 : i];
+                            const int kch = CK_IN_REC ? __float_as_int(rr[CKW + 2]) : S.kch[CK_IN_REC ? 0 : i];
+                            const float csc = CK_IN_REC ? rr[CKW] : S.csc[CK_IN_REC ? 0 : i];
                             const Mid mc = mid_coef<NT>(S.m + i);
 #pragma unroll
                             for (int p = 0; p < P; ++p) {
