@@ -852,20 +852,19 @@ __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(6)))
                                 const int kA = w0 + 64 * p;
                                 const unsigned z = (zc >> (2 * p)) & 3u;
                                 const float x = __builtin_fmaf(jl[p] + sb0, q.x, q2.y);
-                                if (z == 2u) {
-                                    // stored core values: loaded and consumed inside this branch
-                                    const int k = kA + lane;
-                                    const bool in = (k >= kcl && k <= kch);
-                                    float vcv = 0.0f;
-                                    if (in) vcv = A.core_val[S.cb[i] + k];
-                                    const float vm = mid_rule(mc, x * csc, 0.0f);
-                                    part[p] += in ? vcv : vm;
-                                } else if (z == 1u) {
-                                    part[p] = mid_rule(mc, x * csc, part[p]);
-                                } else {
+                                if (z == 0u) {
                                     const float pp = __builtin_fmaf(x, x, q.y);
                                     const float den = __builtin_fmaf(pp, pp, q.z);
                                     part[p] = __builtin_fmaf(__builtin_fmaf(pp, q.w, q2.x), __builtin_amdgcn_rcpf(den), part[p]);
+                                } else if (z == 1u) {
+                                    part[p] = mid_rule(mc, x * csc, part[p]);
+                                } else {
+                                    const int k = kA + lane;
+                                    const bool in = (k >= kcl && k <= kch);
+                                    const int kk = k < kcl ? kcl : (k > kch ? kch : k);
+                                    const float vcv = A.core_val[S.cb[i] + kk];
+                                    const float vm = mid_rule(mc, x * csc, 0.0f);
+                                    part[p] += in ? vcv : vm;
                                 }
                             }
                         };
