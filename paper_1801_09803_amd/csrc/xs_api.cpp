@@ -918,6 +918,7 @@ xs_status xs_plan_create(const xs_opts* opts, xs_plan** out) {
     }
     xs::weideman_coefficients(24, &p->tabs.w24);
     xs::weideman_coefficients(40, &p->tabs.w40);
+    xs::dawson_table(p->tabs.dawson);
     xs::make_gh_pairs(2, &p->tabs.gh2);
     xs::make_gh_pairs(4, &p->tabs.gh4);
     xs::make_gh_pairs(6, &p->tabs.gh6);

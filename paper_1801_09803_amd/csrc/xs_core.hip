@@ -130,6 +130,7 @@ __global__ __launch_bounds__(256) void core_eval_kernel(const CoreArgs A) {
     __shared__ unsigned long long gpre[3][256];   // the same per evaluation group
     __shared__ double ls_s[256], ls_nu[256], ls_y[256], ls_a[256];
     __shared__ int ls_lo[256], ls_ia[256], ls_ib[256], ls_nl[256], ls_k[256];
+    __shared__ double ls_daw[kDawsonIv * kDawsonNc];   // Dawson table (real-axis Im w)
     const int t = threadIdx.x;
     const int g = blockIdx.x * 256 + t;
     const TPParam tp = *A.tp;
@@ -162,6 +163,7 @@ __global__ __launch_bounds__(256) void core_eval_kernel(const CoreArgs A) {
     pre[t] = ex;
 #pragma unroll
     for (int q = 0; q < 3; ++q) gpre[q][t] = block_exclusive_scan_t<unsigned long long>(gc[q], lds4, &gtot[q]);
+    for (int i = t; i < kDawsonIv * kDawsonNc; i += 256) ls_daw[i] = A.tab->dawson[i];
     const long long base = A.val_base + (long long)A.bsum[blockIdx.x];
     if (g < A.n_lines) A.coff[g] = base + (long long)ex;
     __syncthreads();
@@ -193,7 +195,7 @@ __global__ __launch_bounds__(256) void core_eval_kernel(const CoreArgs A) {
         const double y = ls_y[j];
         const double z2 = __builtin_fma(x, x, y * y);
         double re;
-        if (z2 < kCoreR2) re = voigt_core_re_k<24>(x, y, ls_k[j], A.tab->w24);
+        if (z2 < kCoreR2) re = voigt_core_re_k<24>(x, y, ls_k[j], A.tab->w24, ls_daw);
         else if (z2 < kMidR2) re = gh_wing_re(x * x, y, A.tab->gh4);
         else re = gh_wing_re(x * x, y, A.tab->gh2);
         const long long at = base + (long long)pre[j] + (long long)(k - ls_lo[j]);

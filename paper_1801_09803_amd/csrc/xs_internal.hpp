@@ -93,6 +93,12 @@ struct WeidemanCoef {
     double a[kMaxWeideman];       // a[n-1] is the leading coefficient in Horner order
 };
 
+// Dawson's function D(x) on [0, kDawsonIv / 2): one polynomial of degree kDawsonNc - 1 per
+// interval [i/2, (i+1)/2), in u = 4 (x - (i/2 + 1/4)) in [-1, 1], coefficients ascending;
+// relative error below 1e-13 (Chebyshev interpolation of a reference sum)
+constexpr int kDawsonIv = 17;
+constexpr int kDawsonNc = 13;
+
 // All quadrature tables of a plan, kept in one device buffer and read by the kernels
 // through a uniform pointer (scalar loads).
 constexpr int kGHConvDefault = 30;   // nodes of the Gauss-Hermite convolution profiles ("usually 30")
@@ -101,6 +107,7 @@ constexpr int kMaxGHPair = kMaxGHConv / 2 + 1;
 struct Tables {
     WeidemanCoef w24;   // FP32 path core
     WeidemanCoef w40;   // FP64 path core
+    double dawson[kDawsonIv * kDawsonNc];   // FP32 path core: D(x) on the real axis
     GHPairs gh2, gh4, gh6, gh12;
     // Gauss-Hermite rule of the convolution profiles (Eq. 30-31): nconv nodes ascending,
     // and its npair node pairs +-t (the zero node of an odd rule as a pair of half weight)
@@ -114,6 +121,7 @@ struct Tables {
 // Host helpers implemented in xs_quadrature.cpp.
 void gauss_hermite_rule(int n, double* nodes, double* weights);
 void weideman_coefficients(int n, WeidemanCoef* out);
+void dawson_table(double* out);
 void make_gh_pairs(int n, GHPairs* out);
 
 // Plan internals for entry points outside the plan's source file (xs_api.cpp):

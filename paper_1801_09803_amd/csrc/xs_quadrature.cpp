@@ -87,6 +87,54 @@ void make_gh_pairs(int n, GHPairs* out) {
     }
 }
 
+// Dawson's function D(x) = exp(-x^2) int_0^x exp(t^2) dt by Rybicki's sum (G. B. Rybicki,
+// Computers in Physics 3, 85 (1989)): D(x) = lim_{h->0} pi^-1/2 sum_{n odd} exp(-(x - n h)^2)/n,
+// whose error at step h falls like exp(-(pi / 2h)^2) (below 1e-26 at h = 0.2); terms more
+// than 20 from x are below exp(-400) and left out.
+static long double dawson_ref(long double x) {
+    const long double pi = 3.141592653589793238462643383279502884L;
+    const long double h = 0.2L;
+    const int n0 = (int)std::floor(x / h);
+    long double s = 0.0L;
+    for (int n = n0 - 101; n <= n0 + 101; ++n) {
+        if (n % 2 == 0) continue;
+        const long double d = x - n * h;
+        s += std::exp(-d * d) / n;
+    }
+    return s / std::sqrt(pi);
+}
+
+void dawson_table(double* out) {
+    // per interval: Chebyshev interpolation at kDawsonNc points of the first kind, its
+    // Chebyshev series turned into powers of u (T_0 = 1, T_1 = u, T_{j+1} = 2u T_j - T_{j-1})
+    const long double pi = 3.141592653589793238462643383279502884L;
+    constexpr int M = kDawsonNc;
+    for (int iv = 0; iv < kDawsonIv; ++iv) {
+        const long double c = 0.5L * iv + 0.25L;
+        long double f[M];
+        for (int k = 0; k < M; ++k) f[k] = dawson_ref(c + 0.25L * std::cos(pi * (k + 0.5L) / M));
+        long double cheb[M];
+        for (int j = 0; j < M; ++j) {
+            long double acc = 0.0L;
+            for (int k = 0; k < M; ++k) acc += f[k] * std::cos(pi * j * (k + 0.5L) / M);
+            cheb[j] = acc * (j == 0 ? 1.0L : 2.0L) / M;
+        }
+        long double poly[M] = {}, tm[M] = {}, t0[M] = {}, t1[M] = {};
+        t0[0] = 1.0L;   // T_0
+        t1[1] = 1.0L;   // T_1
+        for (int i = 0; i < M; ++i) poly[i] += cheb[0] * t0[i] + (M > 1 ? cheb[1] * t1[i] : 0.0L);
+        for (int j = 2; j < M; ++j) {
+            for (int i = 0; i < M; ++i) tm[i] = -t0[i] + (i > 0 ? 2.0L * t1[i - 1] : 0.0L);
+            for (int i = 0; i < M; ++i) {
+                poly[i] += cheb[j] * tm[i];
+                t0[i] = t1[i];
+                t1[i] = tm[i];
+            }
+        }
+        for (int i = 0; i < M; ++i) out[iv * M + i] = (double)poly[i];
+    }
+}
+
 void weideman_coefficients(int n, WeidemanCoef* out) {
     const long double pi = 3.141592653589793238462643383279502884L;
     const int M = 2 * n;

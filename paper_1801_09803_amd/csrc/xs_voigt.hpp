@@ -99,13 +99,29 @@ __device__ __forceinline__ int core_taylor_terms(double y) {
          : y < 2.0e-2 ? 6 : y < 3.3e-2 ? 7 : y < 5.0e-2 ? 8 : y < 7.1e-2 ? 9 : y < 9.1e-2 ? 10 : 12;
 }
 
+// Im w(x) on the real axis, (2/sqrt(pi)) D(x) with Dawson's function D odd, from the
+// piecewise polynomials of the table dt (|x| < kDawsonIv / 2; Horner in u)
+__device__ __forceinline__ double im_w_real(double x, const double* dt) {
+    const double ax = fabs(x);
+    int iv = (int)(ax * 2.0);
+    iv = iv < kDawsonIv - 1 ? iv : kDawsonIv - 1;
+    const double u = (ax - (0.5 * iv + 0.25)) * 4.0;
+    const double* c = dt + iv * kDawsonNc;
+    double p = c[kDawsonNc - 1];
+#pragma unroll
+    for (int j = kDawsonNc - 2; j >= 0; --j) p = __builtin_fma(p, u, c[j]);
+    return copysign(2.0 * kINV_SQRT_PI * p, x);
+}
+
 // voigt_core_re with the number of Taylor terms chosen per line (K from core_taylor_terms,
-// at most 12); the factorial weights use constant reciprocals.
+// at most 12) and the real-axis Im w from the Dawson table dt; the factorial weights use
+// constant reciprocals.
 template <int N>
-__device__ __forceinline__ double voigt_core_re_k(double x, double y, int K, const WeidemanCoef& W) {
+__device__ __forceinline__ double voigt_core_re_k(double x, double y, int K, const WeidemanCoef& W,
+                                                  const double* dt) {
     if (y >= 0.2) return weideman_w<N>(x, y, W).re;
     double w0r = exp(-x * x);
-    double w0i = weideman_w<N>(x, 0.0, W).im;
+    double w0i = im_w_real(x, dt);
     double w1r = -2.0 * x * w0r;
     double w1i = -2.0 * x * w0i + 2.0 * kINV_SQRT_PI;
     double sum = w0r - w1i * y;
