@@ -200,8 +200,8 @@ __global__ __launch_bounds__(256) void far_finish_kernel(const FwdArgs A, int n_
 
 // Window ends of the FP32 Voigt sweep (A.far_ends): the lines [s0, s1) whose cut-off window
 // ends inside a wavefront and [s4, s5) whose window starts inside it, all at least the far
-// reach (and the |z| < 40 radius) from every point of it.  One wavefront per (wavefront
-// tile, (T, P)); its result goes to far slot 1.
+// reach (and the |z| < 40 radius) from every point of it.  One workgroup of four
+// wavefronts per (wavefront tile, (T, P)); its result goes to far slot 1.
 //
 // The wavefront is cut into NB blocks of BW points.  A left line whose window ends in block
 // b (its last point w0 + m, m clamped to the wavefront) covers blocks 0..b-1 whole: its
@@ -213,12 +213,14 @@ __global__ __launch_bounds__(256) void far_finish_kernel(const FwdArgs A, int n_
 // (a window clipped at the first point starts in bucket 0 of the first wavefront, whose
 // candidates already reach down to s4).
 //
-// The buckets are walked in turn; the lanes take consecutive candidate lines of a bucket
-// (sorted by centre: a window end lies hmin..hmax steps from it, so a bucket's candidates
-// are a contiguous run), each keeping the node and point sums of its lines (FP32 over four
-// lines, then FP64), and the wavefront adds them up at the bucket's end.  Each point o
-// then takes the interpolation of its block's node values (suffix + prefix) over all nodes plus
-// its block's point sums.  Fixed order throughout: the result does not depend on the run.
+// Each wavefront of the workgroup walks the buckets of one side in turn, every other one
+// (side = wavefront & 1, buckets (wavefront >> 1) + 2i); the lanes take consecutive
+// candidate lines of a bucket (sorted by centre: a window end lies hmin..hmax steps from
+// it, so a bucket's candidates are a contiguous run), each keeping the node and point sums
+// of its lines (FP32 over four lines, then FP64), and the wavefront adds them up at the
+// bucket's end.  Each point o then takes the interpolation of its block's node values
+// (suffix + prefix) over all nodes plus its block's point sums of both sides.  Fixed order
+// throughout: the result does not depend on the run.
 template <int P>
 struct EndsShape {
     static constexpr int WW = 64 * P;
@@ -239,13 +241,14 @@ __global__ __launch_bounds__(256) void ends_kernel(const FwdArgs A, int n_waves)
     constexpr int WW = ES::WW, BW = ES::BW, NB = ES::NB;
     using L = HotOf<kVoigt>;
     static_assert(L::H == 0 && L::C0 == 1 && L::C1 == 2 && L::AMP == 3 && L::XC == L::B + 1, "layout");
-    __shared__ float eb[4][2][NB][kFarN];   // node sums per (side, block), scaled by 2^32
-    __shared__ float ep[4][WW];             // point sums of both sides, scaled by 2^32
+    static_assert(NB % 2 == 0, "buckets split over two wavefronts per side");
+    __shared__ float eb[2][NB][kFarN];   // node sums per (side, block), scaled by 2^32
+    __shared__ float ep[2][WW];          // point sums per side, scaled by 2^32
     const int lane = threadIdx.x & 63, wl = threadIdx.x >> 6;
-    const int64_t gw = (int64_t)blockIdx.x * 4 + wl;
-    if (gw >= (int64_t)n_waves * A.n_tp) return;   // whole wavefronts; no block barrier
-    const int it = (int)(gw % A.n_tp);
-    const int wv = (int)(gw / A.n_tp);
+    const int64_t gb = blockIdx.x;
+    if (gb >= (int64_t)n_waves * A.n_tp) return;   // the whole workgroup
+    const int it = (int)(gb % A.n_tp);
+    const int wv = (int)(gb / A.n_tp);
     const Geometry G = A.G;
     const int w0 = wv * WW, w1 = w0 + WW - 1;
     const int* map = A.map ? A.map + (int64_t)it * A.map_stride : nullptr;
@@ -254,132 +257,131 @@ __global__ __launch_bounds__(256) void ends_kernel(const FwdArgs A, int n_waves)
     const int s0 = off_at(off, (int64_t)w0 - G.hmax, G), s1 = off_at(off, (int64_t)w1 - G.hmin, G);
     const int s4 = off_at(off, (int64_t)w0 + G.hmin + 1, G), s5 = off_at(off, (int64_t)w1 + G.hmax + 1, G);
     constexpr float kUp = 4294967296.0f;
-    for (int o = lane; o < WW; o += 64) ep[wl][o] = 0.0f;
-    wave_lds_sync();
-    for (int side = 0; side < 2; ++side) {
-        for (int b = 0; b < NB; ++b) {
-            // candidate lines of bucket b (uniform)
-            const int64_t e0 = (int64_t)w0 + b * BW, e1 = e0 + BW - 1;
-            int r0, r1;
-            if (side == 0) {
-                const bool last = e0 <= (int64_t)G.n_points - 1 && (int64_t)G.n_points - 1 <= e1;
-                r0 = off_at(off, e0 - G.hmax, G);
-                r1 = last ? s1 : off_at(off, e1 - G.hmin + 1, G);
-                r0 = r0 > s0 ? r0 : s0;
-                r1 = r1 < s1 ? r1 : s1;
-            } else {
-                r0 = off_at(off, e0 + G.hmin, G);
-                r1 = off_at(off, e1 + G.hmax + 1, G);
-                r0 = r0 > s4 ? r0 : s4;
-                r1 = r1 < s5 ? r1 : s5;
-            }
-            float n32[kFarN], p32[BW];
-            double n64[kFarN], p64[BW];
+    for (int o = threadIdx.x; o < 2 * WW; o += 256) (&ep[0][0])[o] = 0.0f;
+    __syncthreads();
+    const int side = wl & 1;
+    for (int b = wl >> 1; b < NB; b += 2) {
+        // candidate lines of bucket b (uniform)
+        const int64_t e0 = (int64_t)w0 + b * BW, e1 = e0 + BW - 1;
+        int r0, r1;
+        if (side == 0) {
+            const bool last = e0 <= (int64_t)G.n_points - 1 && (int64_t)G.n_points - 1 <= e1;
+            r0 = off_at(off, e0 - G.hmax, G);
+            r1 = last ? s1 : off_at(off, e1 - G.hmin + 1, G);
+            r0 = r0 > s0 ? r0 : s0;
+            r1 = r1 < s1 ? r1 : s1;
+        } else {
+            r0 = off_at(off, e0 + G.hmin, G);
+            r1 = off_at(off, e1 + G.hmax + 1, G);
+            r0 = r0 > s4 ? r0 : s4;
+            r1 = r1 < s5 ? r1 : s5;
+        }
+        float n32[kFarN], p32[BW];
+        double n64[kFarN], p64[BW];
 #pragma unroll
-            for (int m = 0; m < kFarN; ++m) { n32[m] = 0.0f; n64[m] = 0.0; }
+        for (int m = 0; m < kFarN; ++m) { n32[m] = 0.0f; n64[m] = 0.0; }
 #pragma unroll
-            for (int j = 0; j < BW; ++j) { p32[j] = 0.0f; p64[j] = 0.0; }
-            int nacc = 0;
-            // line data of the lane's next line (loaded while the current one is summed):
-            // H, C0, C1, AMP; B, XC; kc; window end relative to w0 (-1: none here)
-            float4 h4 = make_float4(0.f, 0.f, 0.f, 0.f);
-            float2 h2 = make_float2(0.f, 0.f);
-            int hkc = 0, hm = -1;
-            auto fetch = [&](int l) {
-                hm = -1;
-                if (l < r1) {
-                    const int g = line_of(map, l);
-                    h4 = *reinterpret_cast<const float4*>(hot + (int64_t)l * kHot);
-                    h2 = *reinterpret_cast<const float2*>(hot + (int64_t)l * kHot + L::B);
-                    hkc = A.L.kc[g];
-                    if (side == 0) {
-                        const int e = A.L.khi[g] - w0;
-                        hm = e < 0 ? -1 : (e > WW - 1 ? WW - 1 : e);
-                    } else {
-                        const int e = A.L.klo[g] - w0;
-                        hm = e > WW - 1 ? -1 : (e < 0 ? 0 : e);
-                    }
-                }
-            };
-            fetch(r0 + lane);
-            for (int c = r0; c < r1; c += 64) {
-                {
-                    const float4 a4 = h4;
-                    const float2 a2 = h2;
-                    const int akc = hkc, m = hm;
-                    fetch(c + 64 + lane);
-                    if (m >= 0 && m / BW == b) {
-                        const float x0 = __builtin_fmaf((float)(w0 - akc), a4.x, a2.y);   // x at w0
-#pragma unroll
-                        for (int mm = 0; mm < kFarN; ++mm)
-                            n32[mm] += far_value(a4, a2, __builtin_fmaf(node_pos<WW>(mm), a4.x, x0), kUp);
-                        const int j0 = m - b * BW;   // the window's end within the block
-#pragma unroll
-                        for (int j = 0; j < BW; ++j) {
-                            const bool cover = side == 0 ? (j <= j0) : (j >= j0);
-                            const float v = far_value(a4, a2, __builtin_fmaf((float)(b * BW + j), a4.x, x0), kUp);
-                            p32[j] += cover ? v : 0.0f;
-                        }
-                    }
-                }
-                if (++nacc == 4) {
-                    nacc = 0;
-#pragma unroll
-                    for (int mm = 0; mm < kFarN; ++mm) { n64[mm] += (double)n32[mm]; n32[mm] = 0.0f; }
-#pragma unroll
-                    for (int j = 0; j < BW; ++j) { p64[j] += (double)p32[j]; p32[j] = 0.0f; }
+        for (int j = 0; j < BW; ++j) { p32[j] = 0.0f; p64[j] = 0.0; }
+        int nacc = 0;
+        // line data of the lane's next line (loaded while the current one is summed):
+        // H, C0, C1, AMP; B, XC; kc; window end relative to w0 (-1: none here)
+        float4 h4 = make_float4(0.f, 0.f, 0.f, 0.f);
+        float2 h2 = make_float2(0.f, 0.f);
+        int hkc = 0, hm = -1;
+        auto fetch = [&](int l) {
+            hm = -1;
+            if (l < r1) {
+                const int g = line_of(map, l);
+                h4 = *reinterpret_cast<const float4*>(hot + (int64_t)l * kHot);
+                h2 = *reinterpret_cast<const float2*>(hot + (int64_t)l * kHot + L::B);
+                hkc = A.L.kc[g];
+                if (side == 0) {
+                    const int e = A.L.khi[g] - w0;
+                    hm = e < 0 ? -1 : (e > WW - 1 ? WW - 1 : e);
+                } else {
+                    const int e = A.L.klo[g] - w0;
+                    hm = e > WW - 1 ? -1 : (e < 0 ? 0 : e);
                 }
             }
-            // the bucket's totals (single-precision tree over the lanes' sums)
-            float* bucket = eb[wl][side][b];
-            if (r1 > r0) {
+        };
+        fetch(r0 + lane);
+        for (int c = r0; c < r1; c += 64) {
+            {
+                const float4 a4 = h4;
+                const float2 a2 = h2;
+                const int akc = hkc, m = hm;
+                fetch(c + 64 + lane);
+                if (m >= 0 && m / BW == b) {
+                    const float x0 = __builtin_fmaf((float)(w0 - akc), a4.x, a2.y);   // x at w0
 #pragma unroll
-                for (int mm = 0; mm < kFarN; ++mm) {
-                    const float t = wave_total_f((float)(n64[mm] + (double)n32[mm]));
-                    if (lane == 0) bucket[mm] = t;
-                }
+                    for (int mm = 0; mm < kFarN; ++mm)
+                        n32[mm] += far_value(a4, a2, __builtin_fmaf(node_pos<WW>(mm), a4.x, x0), kUp);
+                    const int j0 = m - b * BW;   // the window's end within the block
 #pragma unroll
-                for (int j = 0; j < BW; ++j) {
-                    const float t = wave_total_f((float)(p64[j] + (double)p32[j]));
-                    if (lane == j) ep[wl][b * BW + j] += t;
+                    for (int j = 0; j < BW; ++j) {
+                        const bool cover = side == 0 ? (j <= j0) : (j >= j0);
+                        const float v = far_value(a4, a2, __builtin_fmaf((float)(b * BW + j), a4.x, x0), kUp);
+                        p32[j] += cover ? v : 0.0f;
+                    }
                 }
-            } else if (lane < kFarN) {
-                bucket[lane] = 0.0f;
+            }
+            if (++nacc == 4) {
+                nacc = 0;
+#pragma unroll
+                for (int mm = 0; mm < kFarN; ++mm) { n64[mm] += (double)n32[mm]; n32[mm] = 0.0f; }
+#pragma unroll
+                for (int j = 0; j < BW; ++j) { p64[j] += (double)p32[j]; p32[j] = 0.0f; }
             }
         }
+        // the bucket's totals (single-precision tree over the lanes' sums)
+        float* bucket = eb[side][b];
+        if (r1 > r0) {
+#pragma unroll
+            for (int mm = 0; mm < kFarN; ++mm) {
+                const float t = wave_total_f((float)(n64[mm] + (double)n32[mm]));
+                if (lane == 0) bucket[mm] = t;
+            }
+#pragma unroll
+            for (int j = 0; j < BW; ++j) {
+                const float t = wave_total_f((float)(p64[j] + (double)p32[j]));
+                if (lane == j) ep[side][b * BW + j] = t;
+            }
+        } else if (lane < kFarN) {
+            bucket[lane] = 0.0f;
+        }
     }
-    wave_lds_sync();
+    __syncthreads();
     // left buckets become suffix sums (the lines covering the blocks below them), right
-    // buckets prefix sums; one node per lane
-    if (lane < kFarN) {
+    // buckets prefix sums; one node per lane of wavefront 0 (left) and 1 (right)
+    if (wl < 2 && lane < kFarN) {
         double run = 0.0;
-        for (int c = NB - 1; c >= 0; --c) {
-            const double v = (double)eb[wl][0][c][lane];
-            eb[wl][0][c][lane] = (float)run;
-            run += v;
-        }
-        run = 0.0;
-        for (int c = 0; c < NB; ++c) {
-            const double v = (double)eb[wl][1][c][lane];
-            eb[wl][1][c][lane] = (float)run;
-            run += v;
+        if (wl == 0) {
+            for (int c = NB - 1; c >= 0; --c) {
+                const double v = (double)eb[0][c][lane];
+                eb[0][c][lane] = (float)run;
+                run += v;
+            }
+        } else {
+            for (int c = 0; c < NB; ++c) {
+                const double v = (double)eb[1][c][lane];
+                eb[1][c][lane] = (float)run;
+                run += v;
+            }
         }
     }
-    wave_lds_sync();
+    __syncthreads();
     double* out = A.far + ((int64_t)it * A.far_slots + 1) * G.n_points;
     constexpr double kDown = 1.0 / 4294967296.0;
-#pragma unroll
-    for (int p = 0; p < P; ++p) {
-        const int o = 64 * p + lane;
+    for (int o = threadIdx.x; o < WW; o += 256) {
         const int blk = o / BW;
         double w[kFarN];
         far_weights<WW>(o, w);
         double v = 0.0;
 #pragma unroll
         for (int m = 0; m < kFarN; ++m)
-            v = __builtin_fma(w[m], (double)eb[wl][0][blk][m] + (double)eb[wl][1][blk][m], v);
+            v = __builtin_fma(w[m], (double)eb[0][blk][m] + (double)eb[1][blk][m], v);
         const int k = w0 + o;
-        if (k < G.n_points) out[k] = (v + (double)ep[wl][o]) * kDown;
+        if (k < G.n_points) out[k] = (v + ((double)ep[0][o] + (double)ep[1][o])) * kDown;
     }
 }
 
@@ -408,8 +410,8 @@ hipError_t launch_far(int waves, int P, const FwdArgs& a, hipStream_t s) {
     }
     e = hipGetLastError();
     if (e != hipSuccess || !a.far_ends) return e;
-    const int64_t ends = (int64_t)n_waves * a.n_tp;
-    const dim3 grid_e((unsigned)((ends + 3) / 4));
+    const int64_t ends = (int64_t)n_waves * a.n_tp;   // one workgroup each
+    const dim3 grid_e((unsigned)ends);
     switch (P) {
         case 1: hipLaunchKernelGGL(ends_kernel<1>, grid_e, block, 0, s, a, n_waves); break;
         case 2: hipLaunchKernelGGL(ends_kernel<2>, grid_e, block, 0, s, a, n_waves); break;
