@@ -510,7 +510,9 @@ __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(6)))
     constexpr int RS = ANCH ? (RH + WAVES + 3) / 4 * 4 : RH;
     static_assert(RS % 4 == 0, "record stride");
     // segmented Voigt sweep: 2-bit rule code per slice (0 the 2-node rule, 1 the 4-node
-    // rule, 2 stored core values inside the 4-node rule) of the lines centred near the tile
+    // rule, 2 stored core values inside the 4-node rule: only for a non-empty core range, so
+    // the values a code-2 slice loads at indices clamped into the range exist) of the lines
+    // centred near the tile
     constexpr int NZW = (2 * NS + 31) / 32;
     constexpr bool ZC = SEG && PROF == kVoigt;
     constexpr int NTF = SEG ? (ZC ? NZW * NT : 0) : NCW * NT;
@@ -683,7 +685,7 @@ __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(6)))
 #pragma unroll
                     for (int sl = 0; sl < NS; ++sl) {
                         const int kA = t0 + 64 * sl, kB = kA + 63;
-                        const unsigned z = (kA <= kch && kB >= kcl) ? 2u
+                        const unsigned z = (kcl <= kch && kA <= kch && kB >= kcl) ? 2u
                                            : (rad >= 0 && kA - kc <= rad && kc - kB <= rad) ? 1u : 0u;
                         zw[(2 * sl) / 32] |= z << ((2 * sl) % 32);
                     }
@@ -830,7 +832,24 @@ __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(6)))
                         static_assert(L::H == 0 && L::C0 == 1 && L::C1 == 2 && L::AMP == 3 && L::B == 4 &&
                                       L::XC == 5, "layout");
                         constexpr unsigned zmask = P >= 16 ? 0xffffffffu : ((1u << (2 * P)) - 1u);
-                        auto line3 = [&](int i, const float4 q, const float2 q2, float sb0, unsigned zc) {
+                        // a line's first slice with stored core values (P: none) and its values
+                        // there (lanes clamped into the core range): requested for both lines
+                        // of a pair before either is evaluated, so the two requests overlap
+                        auto core_first = [&](int i, unsigned zc, int& pc) {
+                            const unsigned cm = (zc >> 1) & 0x55555555u;   // bit 2p: z = 2
+                            pc = cm ? (int)(__builtin_ctz(cm) >> 1) : P;
+                            float v = 0.0f;
+                            if (cm) {
+                                const float* rr = rec + i * RS;
+                                const int kcl = CK_IN_REC ? __float_as_int(rr[CKW + 1]) : S.kcl[CK_IN_REC ? 0 : i];
+                                const int kch = CK_IN_REC ? __float_as_int(rr[CKW + 2]) : S.kch[CK_IN_REC ? 0 : i];
+                                const int k = w0 + 64 * pc + lane;
+                                v = A.core_val[S.cb[i] + (k < kcl ? kcl : (k > kch ? kch : k))];
+                            }
+                            return v;
+                        };
+                        auto line3 = [&](int i, const float4 q, const float2 q2, float sb0, unsigned zc, float cpre,
+                                         int pc) {
                             if (zc == 0u) {
                                 // the mid zone (|z| < 40, which holds the core) misses the wave
 #pragma unroll
@@ -861,8 +880,13 @@ __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(6)))
                                 } else {
                                     const int k = kA + lane;
                                     const bool in = (k >= kcl && k <= kch);
-                                    const int kk = k < kcl ? kcl : (k > kch ? kch : k);
-                                    const float vcv = A.core_val[S.cb[i] + kk];
+                                    float vcv;
+                                    if (p == pc) {
+                                        vcv = cpre;
+                                    } else {
+                                        const int kk = k < kcl ? kcl : (k > kch ? kch : k);
+                                        vcv = A.core_val[S.cb[i] + kk];
+                                    }
                                     const float vm = mid_rule(mc, x * csc, 0.0f);
                                     part[p] += in ? vcv : vm;
                                 }
@@ -881,14 +905,19 @@ __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(6)))
                             const float2 qb2 = *reinterpret_cast<const float2*>(r + RS + L::B);
                             const float sa = S.sb0[i], sb = S.sb0[i + 1];
                             const unsigned za = zcode(i), zb = zcode(i + 1);
-                            line3(i, qa, qa2, sa, za);
-                            line3(i + 1, qb, qb2, sb, zb);
+                            int pa, pb;
+                            const float ca = core_first(i, za, pa), cb = core_first(i + 1, zb, pb);
+                            line3(i, qa, qa2, sa, za, ca, pa);
+                            line3(i + 1, qb, qb2, sb, zb, cb, pb);
                         }
                         if (l < hi3) {
                             const int i = l - bs;
                             const float* r = rec + i * RS;
+                            const unsigned z1 = zcode(i);
+                            int p1;
+                            const float c1 = core_first(i, z1, p1);
                             line3(i, *reinterpret_cast<const float4*>(r), *reinterpret_cast<const float2*>(r + L::B),
-                                  S.sb0[i], zcode(i));
+                                  S.sb0[i], z1, c1, p1);
                         }
                     } else
                     for (int l = lo3; l < hi3; ++l) {
