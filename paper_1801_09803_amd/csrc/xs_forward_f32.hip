@@ -239,7 +239,8 @@ struct Lds {
     int kcl[NCK], kch[NCK]; // has three, see CK_IN_REC)
     int kc[NKR], rad[NKR];  // centre and mid radius (not staged where rule codes replace them)
     long long cb[NT];
-    float m[NM * NT];       // cold profile words (stride NT)
+    alignas(16) float m[NM * NT];   // cold profile words (stride NT; Voigt segmented
+                                    // sweep: the line's eight words together)
 };
 // segmented sweep: no slice codes (keeps the Vectorized Voigt image at 32 KiB, five
 // workgroups per CU)
@@ -251,7 +252,7 @@ struct Lds<NT, RS, 0, NM, NKR, NCK> {
     int kcl[NCK], kch[NCK];
     int kc[NKR], rad[NKR];
     long long cb[NT];
-    float m[NM * NT];
+    alignas(16) float m[NM * NT];
 };
 
 // wing formula (2-node rule, scaled variables)
@@ -277,6 +278,15 @@ __device__ __forceinline__ Mid mid_coef(const float* m) {
     Mid c;
     c.m0 = m[0]; c.m1 = m[NT]; c.m2 = m[2 * NT]; c.m3 = m[3 * NT];
     c.m4 = m[4 * NT]; c.m5 = m[5 * NT]; c.m6 = m[6 * NT]; c.m7 = m[7 * NT];
+    return c;
+}
+
+// the same from the line's eight consecutive words (two LDS reads)
+__device__ __forceinline__ Mid mid_coef8(const float* m) {
+    const float4 a = *reinterpret_cast<const float4*>(m), b = *reinterpret_cast<const float4*>(m + 4);
+    Mid c;
+    c.m0 = a.x; c.m1 = a.y; c.m2 = a.z; c.m3 = a.w;
+    c.m4 = b.x; c.m5 = b.y; c.m6 = b.z; c.m7 = b.w;
     return c;
 }
 
@@ -669,14 +679,23 @@ __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(6)))
                     S.rad[tid] = q0.z;
                 }
                 S.cb[tid] = (long long)(((unsigned long long)(unsigned)q1.w << 32) | (unsigned)q1.z);
-                S.m[0 * NT + tid] = __int_as_float(q2.x);
-                S.m[1 * NT + tid] = __int_as_float(q2.y);
-                if constexpr (NM > 2) S.m[2 * NT + tid] = __int_as_float(q2.z);
-                if constexpr (NM > 3) S.m[3 * NT + tid] = __int_as_float(q2.w);
-                if constexpr (NM > 4) S.m[4 * NT + tid] = __int_as_float(q3.x);
-                if constexpr (NM > 5) S.m[5 * NT + tid] = __int_as_float(q3.y);
-                if constexpr (NM > 6) S.m[6 * NT + tid] = __int_as_float(q3.z);
-                if constexpr (NM > 7) S.m[7 * NT + tid] = __int_as_float(q3.w);
+                if constexpr (ZC) {
+                    static_assert(NM == 8, "Voigt cold words");
+                    float4* m4 = reinterpret_cast<float4*>(S.m) + 2 * tid;
+                    m4[0] = make_float4(__int_as_float(q2.x), __int_as_float(q2.y), __int_as_float(q2.z),
+                                        __int_as_float(q2.w));
+                    m4[1] = make_float4(__int_as_float(q3.x), __int_as_float(q3.y), __int_as_float(q3.z),
+                                        __int_as_float(q3.w));
+                } else {
+                    S.m[0 * NT + tid] = __int_as_float(q2.x);
+                    S.m[1 * NT + tid] = __int_as_float(q2.y);
+                    if constexpr (NM > 2) S.m[2 * NT + tid] = __int_as_float(q2.z);
+                    if constexpr (NM > 3) S.m[3 * NT + tid] = __int_as_float(q2.w);
+                    if constexpr (NM > 4) S.m[4 * NT + tid] = __int_as_float(q3.x);
+                    if constexpr (NM > 5) S.m[5 * NT + tid] = __int_as_float(q3.y);
+                    if constexpr (NM > 6) S.m[6 * NT + tid] = __int_as_float(q3.z);
+                    if constexpr (NM > 7) S.m[7 * NT + tid] = __int_as_float(q3.w);
+                }
                 if constexpr (ZC) {
                     const int rad = q0.z, kcl = q0.w, kch = q1.x;
                     unsigned zw[NZW];
@@ -865,7 +884,7 @@ __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(6)))
                             const int kcl = CK_IN_REC ? __float_as_int(rr[CKW + 1]) : S.kcl[CK_IN_REC ? 0 : i];
                             const int kch = CK_IN_REC ? __float_as_int(rr[CKW + 2]) : S.kch[CK_IN_REC ? 0 : i];
                             const float csc = CK_IN_REC ? rr[CKW] : S.csc[CK_IN_REC ? 0 : i];
-                            const Mid mc = mid_coef<NT>(S.m + i);
+                            const Mid mc = mid_coef8(S.m + 8 * i);
 #pragma unroll
                             for (int p = 0; p < P; ++p) {
                                 const int kA = w0 + 64 * p;
@@ -896,6 +915,27 @@ __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(6)))
                             return (__builtin_amdgcn_readfirstlane(__float_as_uint(S.tf[zword * NT + i])) >> zshift) & zmask;
                         };
                         int l = lo3;
+                        // four lines per pass: the four lines' core requests first, then the
+                        // lines two at a time
+                        for (; l + 3 < hi3; l += 4) {
+                            const int i = l - bs;
+                            const unsigned z0 = zcode(i), z1 = zcode(i + 1), z2 = zcode(i + 2), z3 = zcode(i + 3);
+                            int p0, p1, p2, p3;
+                            const float c0 = core_first(i, z0, p0), c1 = core_first(i + 1, z1, p1);
+                            const float c2 = core_first(i + 2, z2, p2), c3 = core_first(i + 3, z3, p3);
+#pragma unroll
+                            for (int h = 0; h < 2; ++h) {
+                                const int ih = i + 2 * h;
+                                const float* r = rec + ih * RS;
+                                const float4 qa = *reinterpret_cast<const float4*>(r);
+                                const float2 qa2 = *reinterpret_cast<const float2*>(r + L::B);
+                                const float4 qb = *reinterpret_cast<const float4*>(r + RS);
+                                const float2 qb2 = *reinterpret_cast<const float2*>(r + RS + L::B);
+                                const float sa = S.sb0[ih], sb = S.sb0[ih + 1];
+                                line3(ih, qa, qa2, sa, h ? z2 : z0, h ? c2 : c0, h ? p2 : p0);
+                                line3(ih + 1, qb, qb2, sb, h ? z3 : z1, h ? c3 : c1, h ? p3 : p1);
+                            }
+                        }
                         for (; l + 1 < hi3; l += 2) {
                             const int i = l - bs;
                             const float* r = rec + i * RS;
