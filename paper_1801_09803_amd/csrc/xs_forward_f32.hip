@@ -469,20 +469,22 @@ __device__ __forceinline__ void wing_runs(const float* rec, const float* sb0, fl
     }
 }
 
-// The next batch's global data of one thread: NQ float4 chunks of the hot records
-// (chunks tid, NT + tid, ... of the batch; chunk c is quarter c % NQ of line c / NQ)
-// and its own line's offset data.
+// A batch's global data of one thread: NQ float4 chunks of the hot records (chunks tid,
+// NT + tid, ... of the batch; chunk c is quarter c % NQ of line c / NQ) and its own line's
+// offset data.  Loaded when the batch is staged: holding the next batch's data in registers
+// through the sweep (a prefetch) made the compiler spill them, which waits for the loads
+// at once and cost more than it hid.
 template <int NQ>
-struct Prefetch {
+struct BatchLoad {
     float4 h[NQ];
     int kc;
     double nu, scale;
 };
 
 template <int NT, int NQ>
-__device__ __forceinline__ Prefetch<NQ> load_batch(const FwdArgs& A, const int* map, const float4* ghot,
+__device__ __forceinline__ BatchLoad<NQ> load_batch(const FwdArgs& A, const int* map, const float4* ghot,
                                                    const double* gscale, int bs, int b5, int tid) {
-    Prefetch<NQ> f;
+    BatchLoad<NQ> f;
     const int64_t cend = NQ * (int64_t)b5;
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
@@ -631,24 +633,24 @@ __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(6)))
     const int zword = (2 * wave * P) / 32;    // this wavefront's rule codes (2P bits)
     const int zshift = (2 * wave * P) % 32;
 
-    Prefetch<NQ> nxt = load_batch<NT, NQ>(A, map, ghot, gscale, bfirst, b5, tid);
     for (int bs = bfirst; bs < b5; bs += bstride) {
+        const BatchLoad<NQ> bl = load_batch<NT, NQ>(A, map, ghot, gscale, bs, b5, tid);
         const int g = bs + tid;
         // ---- batch set-up: hot records (coalesced loads; chunk c is quarter c % NQ of
         // line c / NQ), then this thread's line
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
             const int c = q * NT + tid;
-            if (NQ * (int64_t)bs + c < NQ * (int64_t)b5) S.rec[(c / NQ) * (RS / 4) + (c % NQ)] = nxt.h[q];
+            if (NQ * (int64_t)bs + c < NQ * (int64_t)b5) S.rec[(c / NQ) * (RS / 4) + (c % NQ)] = bl.h[q];
         }
         if (g < b5) {
-            const int kc = nxt.kc;
+            const int kc = bl.kc;
             S.sb0[tid] = (float)(t0 - kc);
             if constexpr (ANCH) {
                 // x at the end of each wavefront's range nearest the centre: wing points are
                 // then x = anchor + (k - k_anchor) h with both terms of one sign
-                const double d = (G.nu_a + (double)kc * G.dnu) - nxt.nu;
-                const double hd = nxt.scale * G.dnu, xd = nxt.scale * d;
+                const double d = (G.nu_a + (double)kc * G.dnu) - bl.nu;
+                const double hd = bl.scale * G.dnu, xd = bl.scale * d;
 #pragma unroll
                 for (int wv = 0; wv < WAVES; ++wv) {
                     const int wa = t0 + WW * wv;
@@ -758,7 +760,6 @@ __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(6)))
             }
         }
         __syncthreads();
-        if (bs + bstride < b5) nxt = load_batch<NT, NQ>(A, map, ghot, gscale, bs + bstride, b5, tid);   // overlaps the sweep
         const float* rec = reinterpret_cast<const float*>(S.rec);
         const int be = bs + NT < b5 ? bs + NT : b5;
         for (int cs = bs; cs < be; cs += 64) {
