@@ -182,11 +182,11 @@ def zone_counts_multi(cfg, d, tps, waves=None, slices=None, chunk=1 << 24):
 TRAFFIC = {
     "kernel_sources": ['xs_forward_f32.hip', 'xs_records.hpp', 'xs_far.hpp', 'xs_forward_common.hpp', 'xs_voigt.hpp',
                        'xs_forward.hpp', 'xs_internal.hpp'],
-    "sha256": "c68a4f613688656bc7b33dc1c1725b74b44476c8e65beced77fedf2e9387ca35",
+    "sha256": "00e6b1bab174e9b48b2752d142ef5a2b8916a6be597d8248c1d5243543c395a5",
     "fetch_scale": 2.0,
     "write_scale": 1.0,
-    "C5": {"fetch_kib": 50646000.0, "write_kib": 4356440.0, "tp_per_dispatch": 1},
-    "C2": {"fetch_kib": 32113300.0, "write_kib": 3592610.0, "tp_per_dispatch": 2},
+    "C5": {"fetch_kib": 45091000.0, "write_kib": 303684.0, "tp_per_dispatch": 1},
+    "C2": {"fetch_kib": 28368300.0, "write_kib": 506574.0, "tp_per_dispatch": 2},
 }
 
 

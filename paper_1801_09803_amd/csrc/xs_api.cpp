@@ -1586,17 +1586,15 @@ xs_status xs_autotune(xs_plan* p, int32_t n_tp, const double* T, const double* P
     Cand best{save_w, save_p, 1, ns, 1e300};
     xs_status st = XS_OK;
     int tried = 0;
-    // one timing, repeated when short (the first launch of a kernel includes its load)
+    // the faster of two timings (the first launch of a kernel includes its load, and close
+    // candidates differ by a few per cent, about the spread of a single timing)
     auto consider = [&](int w, int sl, int S, int B) {
         if (st != XS_OK || (tried > 0 && elapsed() > budget_ms)) return;
         ++tried;
-        double a = 0.0;
+        double a = 0.0, b = 0.0;
         st = run(w, sl, S, B, &a);
-        if (st == XS_OK && a * ns < 20.0) {
-            double b = 0.0;
-            st = run(w, sl, S, B, &b);
-            a = std::min(a, b);
-        }
+        if (st == XS_OK) st = run(w, sl, S, B, &b);
+        a = std::min(a, b);
         if (st == XS_OK && a < best.ms) best = Cand{w, sl, S, B, a};
     };
     // coordinate search: tile shapes at their default split, then the split of the best
