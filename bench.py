@@ -182,7 +182,7 @@ def zone_counts_multi(cfg, d, tps, waves=None, slices=None, chunk=1 << 24):
 TRAFFIC = {
     "kernel_sources": ['xs_forward_f32.hip', 'xs_records.hpp', 'xs_far.hpp', 'xs_forward_common.hpp', 'xs_voigt.hpp',
                        'xs_forward.hpp', 'xs_internal.hpp'],
-    "sha256": "00e6b1bab174e9b48b2752d142ef5a2b8916a6be597d8248c1d5243543c395a5",
+    "sha256": "d44acbe103e9b61d1793dc26b3e34a83ad80b7aecb5633f54a1bb62f53eba594",
     "fetch_scale": 2.0,
     "write_scale": 1.0,
     "C5": {"fetch_kib": 45091000.0, "write_kib": 303684.0, "tp_per_dispatch": 1},

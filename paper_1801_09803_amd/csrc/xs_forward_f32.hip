@@ -506,7 +506,7 @@ __device__ __forceinline__ BatchLoad<NQ> load_batch(const FwdArgs& A, const int*
 }
 
 template <int PROF, int WAVES, int P, bool SEG>
-__global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(6))) void fwd_f32_kernel(const FwdArgs A) {
+__global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(WAVES == 1 ? 6 : 1))) void fwd_f32_kernel(const FwdArgs A) {
     constexpr int NT = 64 * WAVES;       // threads = lines per LDS batch
     constexpr int W = NT * P;            // grid points per tile
     constexpr int WW = 64 * P;           // grid points per wavefront
