@@ -324,3 +324,27 @@ def test_window_ends_at_the_grid_edges(waves, slices):
     ls = oracle_lineset(h, cfg, 1500.0, 30.0)
     ref = O.cross_section(ls, cfg.nu_a, cfg.nu_b, cfg.n_points, cfg.cutoff, workers=1)
     assert_parity(got, ref, TOL32, what=f"grid edges {waves}x{slices}")
+
+
+@pytest.mark.parametrize("waves,slices", [(1, 4), (2, 2)])
+def test_narrow_lines_centred_past_the_grid_end(waves, slices):
+    # Doppler-narrow lines (300 K, 1e-3 bar: cores of a few grid steps) centred up to 40
+    # cm^-1 beyond the last point of a grid whose last wavefront is ragged (20001 points):
+    # their core ranges, clipped to the grid, are empty, while the last 64-point slice runs
+    # past the grid's end over their centres; such lines must take the 4-node rule there,
+    # never stored core values.  The whole grid is checked against the oracle.
+    cfg = synth.WorkloadConfig("past_end", 516, 3000, 60000, 28.0, 260.0, 0.0, 200.0, 20001, (300.0,), (1e-3,))
+    d = device_linelist(cfg)
+    E = d["E"]
+    nu = E[d["upper"].long()] - E[d["lower"].long()]
+    keep = ((nu > 150.0) & (nu < 240.0)).nonzero().squeeze(1)
+    d = dict(d, **{k: d[k][keep].contiguous() for k in ("upper", "lower", "A", "gamma_ref", "n_exp")})
+    h = host(d)
+    n_past = int((nu[keep] > 200.0).sum().item())
+    log(f"past end: {keep.numel()} lines ({n_past} centred past the grid), tile {waves} x {slices}")
+    assert n_past > 100
+    plan = make_plan(cfg, "fp32", waves_per_block=waves, slices_per_wave=slices, n_split=4)
+    got = _run(plan, d, [300.0], [1e-3])[0]
+    ls = oracle_lineset(h, cfg, 300.0, 1e-3)
+    ref = O.cross_section(ls, cfg.nu_a, cfg.nu_b, cfg.n_points, cfg.cutoff, workers=1)
+    assert_parity(got, ref, TOL32, what=f"past grid end {waves}x{slices}")
