@@ -182,7 +182,7 @@ def zone_counts_multi(cfg, d, tps, waves=None, slices=None, chunk=1 << 24):
 TRAFFIC = {
     "kernel_sources": ['xs_forward_f32.hip', 'xs_records.hpp', 'xs_far.hpp', 'xs_forward_common.hpp', 'xs_voigt.hpp',
                        'xs_forward.hpp', 'xs_internal.hpp'],
-    "sha256": "d44acbe103e9b61d1793dc26b3e34a83ad80b7aecb5633f54a1bb62f53eba594",
+    "sha256": "5c941ce5a466ee94070b079239c3b9e0db55ec004b1c81805f7d07279a7158ae",
     "fetch_scale": 2.0,
     "write_scale": 1.0,
     "C5": {"fetch_kib": 45091000.0, "write_kib": 303684.0, "tp_per_dispatch": 1},

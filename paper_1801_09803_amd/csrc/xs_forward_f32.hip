@@ -847,14 +847,16 @@ __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(WAVE
                     const int lo3 = cs > s2 ? cs : s2, hi3 = ce < s3 ? ce : s3;
                     if constexpr (PROF == kVoigt) {
                         // record words in registers for every slice, two lines at a time (one
-                        // wait for both lines' LDS words); each slice's rule adds straight
-                        // into its sum
+                        // wait for both lines' LDS words), in passes of four lines whose
+                        // core-value requests are issued first; each slice's rule adds
+                        // straight into its sum
                         static_assert(L::H == 0 && L::C0 == 1 && L::C1 == 2 && L::AMP == 3 && L::B == 4 &&
                                       L::XC == 5, "layout");
                         constexpr unsigned zmask = P >= 16 ? 0xffffffffu : ((1u << (2 * P)) - 1u);
                         // a line's first slice with stored core values (P: none) and its values
-                        // there (lanes clamped into the core range): requested for both lines
-                        // of a pair before either is evaluated, so the two requests overlap
+                        // there (lanes clamped into the core range): requested for all lines of
+                        // a pass before any is evaluated, so the requests overlap; a further
+                        // core slice (cores wider than one slice) loads its own
                         auto core_first = [&](int i, unsigned zc, int& pc) {
                             const unsigned cm = (zc >> 1) & 0x55555555u;   // bit 2p: z = 2
                             pc = cm ? (int)(__builtin_ctz(cm) >> 1) : P;
