@@ -182,11 +182,11 @@ def zone_counts_multi(cfg, d, tps, waves=None, slices=None, chunk=1 << 24):
 TRAFFIC = {
     "kernel_sources": ['xs_forward_f32.hip', 'xs_records.hpp', 'xs_far.hpp', 'xs_forward_common.hpp', 'xs_voigt.hpp',
                        'xs_forward.hpp', 'xs_internal.hpp'],
-    "sha256": "5c941ce5a466ee94070b079239c3b9e0db55ec004b1c81805f7d07279a7158ae",
+    "sha256": "71c569f83680a7e63e072f716b3b2a1f49e26d82b60895c8d3fc7d750bf250d6",
     "fetch_scale": 2.0,
     "write_scale": 1.0,
-    "C5": {"fetch_kib": 45091000.0, "write_kib": 303684.0, "tp_per_dispatch": 1},
-    "C2": {"fetch_kib": 28368300.0, "write_kib": 506574.0, "tp_per_dispatch": 2},
+    "C5": {"fetch_kib": 38084300.0, "write_kib": 378624.0, "tp_per_dispatch": 1},
+    "C2": {"fetch_kib": 24000800.0, "write_kib": 631665.0, "tp_per_dispatch": 2},
 }
 
 

@@ -682,7 +682,8 @@ xs::RecArgs rec_args(xs_plan* p, Workset& ws, int it, int row) {
         r.count = as<unsigned long long>(ws.th_tmp) + (int64_t)row * kScanTmp + 4096;
     }
     r.hot = as<float>(ws.hot) + row * n * hot_words(p);
-    r.cold = as<int>(ws.cold) + row * n * 16;
+    r.cold = as<int>(ws.cold) + row * n * 16;   // a row: words 0-7 of its n records, then words 8-15
+    r.cold_b = r.cold + n * 8;
     r.xscale = as<double>(ws.xscale) + row * n;
     return r;
 }

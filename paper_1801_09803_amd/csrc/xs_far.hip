@@ -15,8 +15,8 @@ namespace {
 // lines [s1, hcl) and [hcr, s4) (windows covering the wavefront, centres at least R away)
 // go in chunks q, q + far_share, ... of 64, one line per lane (the next chunk's line data
 // loaded while the current one is summed), first those beyond the |z| < 40 radius (2-node
-// rule, hot record only), then those inside it (4-node rule, with the coefficients of the
-// cold record), with FP64 sums per lane and node; the share's node totals go to
+// rule, hot record only), then those inside it (4-node rule, its coefficients rebuilt from
+// the hot record and the x scale), with FP64 sums per lane and node; the share's node totals go to
 // far_nodes[tp][wave][node][share], for far_finish_kernel to add up and interpolate.
 
 // wave-wide sum of v (every lane ends with the total)
@@ -41,8 +41,8 @@ __device__ __forceinline__ float far_value(const float4& h4, const float2& h2, f
     return num * __builtin_amdgcn_rcpf(den);
 }
 
-// 4-node value at unscaled x from the coefficients m0..m7 of the cold record (amplitudes
-// m2, m3, m6, m7 already scaled)
+// 4-node value at unscaled x from the coefficients m0..m7 (amplitudes m2, m3, m6, m7
+// already scaled)
 __device__ __forceinline__ float far_value4(const float4& ma, const float4& mb, float x) {
     const float p1 = __builtin_fmaf(x, x, ma.x);
     const float p2 = __builtin_fmaf(x, x, mb.x);
@@ -73,7 +73,8 @@ __global__ __launch_bounds__(256) void far_kernel(const FwdArgs A, int n_waves) 
     const int* map = A.map ? A.map + (int64_t)it * A.map_stride : nullptr;
     const int* off = A.offs ? A.offs + (int64_t)it * A.offs_stride : A.off;
     const float* hot = A.hot + (int64_t)it * A.rec_stride * kHot;
-    const int* cold = A.cold + (int64_t)it * A.rec_stride * kCold;
+    const int* cold = A.cold + (int64_t)it * A.rec_stride * kCold;   // words 0-7 plane of the row
+    const MidNodes mnodes = mid_nodes(A.tab);
     const FarRange fr = far_range(off, G, w0, w1, wave_rm(tp, G, w0, w1), wave_far_r(tp, G, w0, w1, far_reach(WW)));
     // per lane and node: FP32 sums of up to four lines, added to FP64 sums; amplitudes
     // scaled by 2^32 (exact) keep tiny values out of the single-precision subnormal range
@@ -137,14 +138,13 @@ __global__ __launch_bounds__(256) void far_kernel(const FwdArgs A, int n_waves) 
             if (v < nv) {
                 const int l = v < nl ? fr.ml + v : fr.hcr + (v - nl);
                 const float2 hx = *reinterpret_cast<const float2*>(hot + (int64_t)l * kHot + L::B);   // B, XC
-                const float hh = hot[(int64_t)l * kHot + L::H];
-                const int4* cw = reinterpret_cast<const int4*>(cold + (int64_t)l * kCold);
-                const float csc = __int_as_float(cw[0].x);
-                const int4 qa = cw[2], qb = cw[3];
-                const float4 ma = make_float4(__int_as_float(qa.x), __int_as_float(qa.y),
-                                              __int_as_float(qa.z) * kUp, __int_as_float(qa.w) * kUp);
-                const float4 mb = make_float4(__int_as_float(qb.x), __int_as_float(qb.y),
-                                              __int_as_float(qb.z) * kUp, __int_as_float(qb.w) * kUp);
+                const float4 h4 = *reinterpret_cast<const float4*>(hot + (int64_t)l * kHot);     // H, C0, C1, AMP
+                const float hh = h4.x;
+                const float csc = __int_as_float(cold[(int64_t)l * 8 + C_CSC]);   // first cold plane
+                float mm[8];
+                mid_from_hot(h4.z, h4.w, csc, mnodes, mm);
+                const float4 ma = make_float4(mm[0], mm[1], mm[2] * kUp, mm[3] * kUp);
+                const float4 mb = make_float4(mm[4], mm[5], mm[6] * kUp, mm[7] * kUp);
                 const int akc = A.L.kc[line_of(map, l)];
                 const float x0 = __builtin_fmaf((float)(w0 - akc), hh, hx.y);   // scaled x at w0
 #pragma unroll

@@ -113,7 +113,9 @@ struct RecArgs {
     const unsigned long long* count;   // number of kept lines (device), with map
     float* hot;                     // [n_lines][8] ([n_lines][12] for the Vectorized Voigt), in
                                     // the order of map when there is one
-    int* cold;                      // [n_lines][16]
+    int* cold;                      // words 0-7 of the cold records, [n_lines][8]
+    int* cold_b;                    // words 8-15, [n_lines][8] (not written for Voigt: the
+                                    // kernels rebuild its 4-node coefficients from the hot record)
     double* xscale;                 // [n_lines]
 };
 

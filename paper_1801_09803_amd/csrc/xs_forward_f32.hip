@@ -126,7 +126,8 @@ __global__ __launch_bounds__(256) void record_kernel(const RecArgs A) {
         cf[C_CSC] = (float)ldexp(1.0, e);
         // 4-node rule (unscaled x): node pair j = a, b has p_j = x^2 + y^2 - t_j^2,
         // d_j = p_j^2 + 4 t_j^2 y^2 and n_j = amp w_j (p_j + 2 t_j^2), amp = 2 a y / pi
-        {
+        // (Voigt: rebuilt by the kernels from C1, AMP and the x scale, see mid_from_hot)
+        if (PROF == kVVoigt) {
             const double amp = a * (y / kPI) * 2.0;
             const double t2a = A.tab->gh4.t[0] * A.tab->gh4.t[0], t2b = A.tab->gh4.t[1] * A.tab->gh4.t[1];
             const double ma = amp * A.tab->gh4.w[0], mb = amp * A.tab->gh4.w[1];
@@ -218,9 +219,15 @@ __global__ __launch_bounds__(256) void record_kernel(const RecArgs A) {
     float4* ho = reinterpret_cast<float4*>(A.hot + (int64_t)ci * NH);
 #pragma unroll
     for (int q = 0; q < NH / 4; ++q) ho[q] = make_float4(h[4 * q], h[4 * q + 1], h[4 * q + 2], h[4 * q + 3]);
-    int4* co = reinterpret_cast<int4*>(A.cold + (int64_t)ci * kCold);
-#pragma unroll
-    for (int q = 0; q < 4; ++q) co[q] = make_int4(c[4 * q], c[4 * q + 1], c[4 * q + 2], c[4 * q + 3]);
+    // cold words 0-7 and 8-15 in their two planes (the second not needed for Voigt)
+    int4* co = reinterpret_cast<int4*>(A.cold + (int64_t)ci * 8);
+    co[0] = make_int4(c[0], c[1], c[2], c[3]);
+    co[1] = make_int4(c[4], c[5], c[6], c[7]);
+    if (PROF != kVoigt) {
+        int4* cb = reinterpret_cast<int4*>(A.cold_b + (int64_t)ci * 8);
+        cb[0] = make_int4(c[8], c[9], c[10], c[11]);
+        cb[1] = make_int4(c[12], c[13], c[14], c[15]);
+    }
     A.xscale[ci] = scale;
 }
 
@@ -546,7 +553,10 @@ __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(WAVE
     const TPParam tp = A.tps[wi.tp];
     const int64_t row = (int64_t)wi.tp * A.rec_stride;
     const float4* ghot = reinterpret_cast<const float4*>(A.hot + row * RH);
+    // cold records: words 0-7 of the row's lines, then words 8-15 (second plane)
     const int4* gcold = reinterpret_cast<const int4*>(A.cold + row * kCold);
+    const int4* gcoldb = reinterpret_cast<const int4*>(A.cold + row * kCold + A.rec_stride * 8);
+    const MidNodes mnodes = mid_nodes(A.tab);
     const double* gscale = A.xscale + row;
     // intensity threshold: this (T, P)'s kept lines and offsets table
     const int* map = A.map ? A.map + (int64_t)wi.tp * A.map_stride : nullptr;
@@ -664,8 +674,24 @@ __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(WAVE
             const bool near = !SEG || (PROF != kLorentz && (int64_t)kc >= (int64_t)t0 - rm_tile &&
                                        (int64_t)kc <= (int64_t)t1 + rm_tile);
             if (near) {
-                const int4* cg = gcold + (int64_t)g * (kCold / 4);
-                const int4 q0 = cg[0], q1 = cg[1], q2 = cg[2], q3 = cg[3];
+                const int4* cg = gcold + (int64_t)g * 2;
+                const int4 q0 = cg[0], q1 = cg[1];
+                int4 q2, q3;
+                if constexpr (PROF == kVoigt) {
+                    // the 4-node coefficients from the hot words C1, AMP and the x scale
+                    const float2 ca = *reinterpret_cast<const float2*>(A.hot + (row + g) * RH + L::C1);
+                    static_assert(L::AMP == L::C1 + 1, "layout");
+                    float mm[8];
+                    mid_from_hot(ca.x, ca.y, __int_as_float(q0.x), mnodes, mm);
+                    q2 = make_int4(__float_as_int(mm[0]), __float_as_int(mm[1]), __float_as_int(mm[2]),
+                                   __float_as_int(mm[3]));
+                    q3 = make_int4(__float_as_int(mm[4]), __float_as_int(mm[5]), __float_as_int(mm[6]),
+                                   __float_as_int(mm[7]));
+                } else {
+                    const int4* cb = gcoldb + (int64_t)g * 2;
+                    q2 = cb[0];
+                    q3 = cb[1];
+                }
                 if constexpr (CK_IN_REC) {
                     float* rw = reinterpret_cast<float*>(S.rec) + tid * RS + CKW;
                     rw[0] = __int_as_float(q0.x);
