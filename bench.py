@@ -182,7 +182,7 @@ def zone_counts_multi(cfg, d, tps, waves=None, slices=None, chunk=1 << 24):
 TRAFFIC = {
     "kernel_sources": ['xs_forward_f32.hip', 'xs_records.hpp', 'xs_far.hpp', 'xs_forward_common.hpp', 'xs_voigt.hpp',
                        'xs_forward.hpp', 'xs_internal.hpp'],
-    "sha256": "71c569f83680a7e63e072f716b3b2a1f49e26d82b60895c8d3fc7d750bf250d6",
+    "sha256": "cd5f2811b759394ae8df0630c8dd02bf45741bacc90008f83895f041a61f2f66",
     "fetch_scale": 2.0,
     "write_scale": 1.0,
     "C5": {"fetch_kib": 38084300.0, "write_kib": 378624.0, "tp_per_dispatch": 1},

@@ -95,7 +95,8 @@ struct WeidemanCoef {
 
 // Dawson's function D(x) on [0, kDawsonIv / 2): one polynomial of degree kDawsonNc - 1 per
 // interval [i/2, (i+1)/2), in u = 4 (x - (i/2 + 1/4)) in [-1, 1], coefficients ascending;
-// relative error below 1e-13 (Chebyshev interpolation of a reference sum)
+// Chebyshev interpolation of a reference sum, absolute error below 2e-15 (relative 1e-13
+// above x = 0.5, where D grows past 0.4)
 constexpr int kDawsonIv = 17;
 constexpr int kDawsonNc = 13;
 
